@@ -1,0 +1,231 @@
+/*
+ * mw.h -- C ABI of the MI355X microwave-tomography solve library.
+ *
+ * Solves, for many antenna right-hand sides at once, the lowest-order
+ * Nedelec edge-element discretisation of the time-harmonic Maxwell problem
+ *
+ *     curl curl E - k0^2 eps_r E = 0 in Omega,   E x n = 0 on metal walls,
+ *     (curl E) x n + i beta n x (E x n) = g     on ports / impedance faces
+ *
+ * (paper: Section 2, problem (pbdirect), variational form (pbdirectvarf),
+ * linear systems (linsys) with one matrix A for every antenna), by GMRES
+ * right-preconditioned with the one-level Optimized Restricted Additive
+ * Schwarz preconditioner  M^-1 = sum_i R_i^T D_i B_i^-1 R_i  (Section 3,
+ * equations (algebPartUnity), (chi), (ORAS)), stopped on the unpreconditioned
+ * relative residual (Section 6).  It also forms the scattering matrix
+ * (Section 4, equation (sij)), the misfit J (equation (defJ)) and its adjoint
+ * gradient with respect to a per-tetrahedron permittivity (Section 5,
+ * problems (pblin), (pbadj)).
+ *
+ * Conventions
+ *  - time factor e^{+i omega t}: lossy media have Im eps_r < 0;
+ *  - complex numbers are two doubles (re, im), layout-compatible with
+ *    C99 double _Complex, std::complex<double> and torch.complex128;
+ *  - unknowns are the circulations along the oriented mesh edges
+ *    (lo -> hi global vertex id), edges numbered in lexicographic (lo, hi)
+ *    order; the edges lying on a PEC face are eliminated and the remaining
+ *    ("free") edges, in ascending edge order, are the n unknowns;
+ *  - multi-vectors (B, X, U, ...) are n x nrhs, row-major, the right-hand-
+ *    side index contiguous (an n x nrhs contiguous torch tensor);
+ *  - every call returns mw_status; MW_OK is 0, errors are negative; the
+ *    message of the last error of the calling thread is mw_last_error().
+ *    Nothing throws across the ABI.
+ *
+ * Ownership: the caller owns every buffer it passes; "host" arrays are read
+ * during the call only (copied where kept), "device" pointers must be device
+ * memory of the context's device, valid for the duration of the call.  The
+ * library owns the factors, Krylov bases and workspaces it allocates; they
+ * are released by mw_destroy_problem / mw_destroy.  Work is issued on the
+ * context's stream (mw_set_stream) and every call returns after that stream
+ * has finished the call's work.
+ */
+#ifndef MW_H
+#define MW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MW_OK = 0,
+  MW_EINVAL = -1,     /* bad argument: NULL, size, index or shape */
+  MW_ENOMEM = -2,     /* request exceeds the context's HBM budget; nothing allocated */
+  MW_ESINGULAR = -3,  /* zero pivot in a subdomain factorisation (message names it) */
+  MW_ENOCONV = -4,    /* GMRES reached maxit; X holds the last iterate, info filled */
+  MW_ENUMERIC = -5,   /* NaN or Inf in a residual */
+  MW_EDEVICE = -6     /* HIP runtime error (message holds its string) */
+} mw_status;
+
+typedef enum { MW_C128 = 0, MW_C64 = 1 } mw_precision;
+
+#define MW_TAG_PEC (-1)
+#define MW_TAG_IMPEDANCE 0
+/* btag >= 1 : aperture of port (btag - 1) */
+
+typedef struct { double re, im; } mw_complex;
+
+typedef struct mw_ctx mw_ctx;
+typedef struct mw_problem mw_problem;
+
+/* Tetrahedral mesh (host arrays).  Tetrahedra and faces may list their
+ * vertices in any order.  bface/btag label every boundary face that carries
+ * a condition: PEC (E x n = 0, equation (eqmetal)), impedance with the
+ * problem's beta_imp (the chamber top, the first-order absorbing condition
+ * of equation (eqwgi)), or a port aperture (equations (eqwgj), (eqwgi)). */
+typedef struct {
+  int32_t nv;
+  const double *xyz;     /* [nv*3] */
+  int32_t nt;
+  const int32_t *tet;    /* [nt*4] */
+  int32_t nbf;
+  const int32_t *bface;  /* [nbf*3] */
+  const int32_t *btag;   /* [nbf]  */
+} mw_mesh;
+
+/* Port k (faces with btag == k+1): propagation constant beta of its
+ * fundamental mode and that mode's tangential profile on the aperture,
+ *   E0(x) = pol * cos(pi * s / width),  s = radius * wrap(atan2(y,x) - theta),
+ * wrap() to (-pi, pi].  Section 2: g = (curl E0) x n + i beta n x (E0 x n),
+ * which for the incoming mode is 2 i beta E0_t. */
+typedef struct {
+  mw_complex beta;
+  double radius, theta, width;
+  double pol[3];
+} mw_port;
+
+typedef struct {
+  double tol;        /* stop when ||b - A x||_2 / ||b||_2 <= tol, per column (Section 6) */
+  int32_t restart;   /* GMRES restart length m (>= 1) */
+  int32_t maxit;     /* max total iterations per column */
+  int32_t use_x0;    /* 1: X holds the initial guess on entry; 0: x0 = 0 */
+} mw_solve_opts;
+
+typedef struct {
+  int32_t *iters;    /* host [nrhs] or NULL: iterations per column */
+  double *relres;    /* host [nrhs] or NULL: final true relative residual */
+  int32_t max_iters; /* out */
+  int32_t cycles;    /* out: restart cycles of the slowest chunk */
+  int32_t chunks;    /* out: column chunks the solve was split into (memory) */
+  double t_solve;    /* out: seconds */
+} mw_solve_info;
+
+typedef struct {
+  int64_t n;        /* free unknowns */
+  int64_t nnz;      /* nonzeros of A */
+  int64_t n_edges;  /* all mesh edges */
+  int32_t nt, nports;
+  int32_t n_sub;    /* 0 until mw_factor_subdomains */
+  int64_t sum_ni;   /* sum of local sizes n_i */
+  int32_t max_ni;   /* largest n_i */
+  int32_t precision;
+  int64_t factor_bytes;
+  double t_assemble, t_decompose, t_factor; /* seconds of the last calls */
+} mw_problem_info;
+
+/* ---- context -------------------------------------------------------- */
+/* device: HIP device ordinal.  hbm_budget_bytes: upper bound on what the
+ * library may hold on the device (<= 0: 95 % of the device's memory). */
+mw_status mw_create(mw_ctx **out, int device, int64_t hbm_budget_bytes);
+/* stream: a hipStream_t of the context's device (NULL = null stream). */
+mw_status mw_set_stream(mw_ctx *ctx, void *stream);
+mw_status mw_destroy(mw_ctx *ctx);
+const char *mw_last_error(void);
+
+/* ---- assembly (Section 2, (pbdirectvarf); Section 2.1) --------------- */
+/* Builds the edge topology, eliminates PEC edges and assembles
+ *   A = sum_t (K_t - k0^2 eps_t M_t) + sum_F i beta_F M_F
+ * on the device (K_t curl-curl, M_t mass of the Whitney functions, M_F the
+ * tangential face mass).  eps_r: host [nt] relative permittivity per
+ * tetrahedron.  beta_imp: coefficient of MW_TAG_IMPEDANCE faces. */
+mw_status mw_assemble(mw_ctx *ctx, const mw_mesh *mesh, const mw_complex *eps_r, double k0,
+                      mw_complex beta_imp, const mw_port *ports, int32_t nports,
+                      mw_problem **out);
+/* Replaces eps (device [nt] complex) and re-assembles A.  Factors become
+ * stale: call mw_factor_subdomains again before mw_solve. */
+mw_status mw_update_eps(mw_problem *p, const void *eps_dev);
+mw_status mw_problem_get_info(mw_problem *p, mw_problem_info *info);
+/* host [n]: edge id of every unknown; host [n_edges*2]: edge end vertices. */
+mw_status mw_dof_edges(mw_problem *p, int32_t *edge_of_dof, int32_t *edge_vertices);
+mw_status mw_destroy_problem(mw_problem *p);
+
+/* Copies A in CSR (device buffers: row_ptr int64 [n+1], col int32 [nnz],
+ * val complex [nnz]); any pointer may be NULL. */
+mw_status mw_get_matrix(mw_problem *p, void *row_ptr, void *col, void *val);
+
+/* ---- right-hand sides ------------------------------------------------ */
+/* B (device, n x ntx): column j = 2 i beta_k p_k, k = tx[j] (host), with
+ * p_k[e] = int_{Gamma_k} E0_k . N_e by the edge-midpoint rule on each face. */
+mw_status mw_rhs_ports(mw_problem *p, int32_t ntx, const int32_t *tx, void *B);
+/* B (device, n x np): column j = dir_j . N_e(x_j) (unit point dipole);
+ * xyz, dir: host [np*3]; the point lies in the lowest-index tetrahedron
+ * whose barycentric coordinates are all >= -1e-12 (MW_EINVAL if none). */
+mw_status mw_rhs_dipoles(mw_problem *p, int32_t np, const double *xyz, const double *dir,
+                         void *B);
+
+/* ---- preconditioner (Section 3) -------------------------------------- */
+/* tet_part: host [nt] subdomain of every tetrahedron, values in [0, n_sub)
+ * (the non-overlapping partition T_i; every part non-empty).  overlap: delta
+ * >= 1 layers of vertex-adjacent tetrahedra.  Builds R_i, the partition of
+ * unity D_i (P1 chi_i at edge midpoints), the local matrices B_i with
+ * impedance transmission conditions i k (E x n).(v x n) on the interfaces,
+ * k = k0 sqrt(Re eps_r) of the owning tetrahedron, and factors every B_i by
+ * dense LU with partial pivoting in `prec` (MW_C64: complex FP32 factors
+ * and triangular solves; MW_C128: complex FP64). */
+mw_status mw_factor_subdomains(mw_problem *p, int32_t n_sub, int32_t overlap,
+                               mw_precision prec, const int32_t *tet_part);
+/* Z = M^-1 V for nrhs columns (device n x nrhs). */
+mw_status mw_apply_preconditioner(mw_problem *p, int32_t nrhs, const void *V, void *Z);
+
+/* ---- solve ----------------------------------------------------------- */
+/* X = A^-1 B for nrhs columns (device n x nrhs each) by ORAS right-
+ * preconditioned pseudo-block GMRES(m): each column keeps its own Krylov
+ * space, GMRES arithmetic in FP64, true residual recomputed at every
+ * restart.  Returns MW_ENOCONV (X = last iterate) if a column misses tol
+ * within maxit.  info may be NULL. */
+mw_status mw_solve(mw_problem *p, int32_t nrhs, const void *B, void *X, const mw_solve_opts *o,
+                   mw_solve_info *info);
+
+/* ---- scattering matrix, misfit and gradient (Sections 4-5) ----------- */
+/* S (device nrx x ntx) = conj(p_{rx_i}^T U[:, j]) / nu_{rx_i}; U device n x ntx. */
+mw_status mw_s_matrix(mw_problem *p, int32_t nrx, const int32_t *rx, int32_t ntx, const void *U,
+                      void *S);
+/* nu (host [nports]) = int_{Gamma_k} |E0_k|^2. */
+mw_status mw_port_norms(mw_problem *p, double *nu);
+/* Reverse mode of eps -> U -> S.  gS (device nrx x ntx): dL/dRe S + i dL/dIm S
+ * for a real loss L; U (device n x ntx): forward fields of ports tx.
+ * Solves A F = Lambda, Lambda_j = sum_i gS_ij p_{rx_i} / nu_{rx_i}, with the
+ * current factors, then grad_eps (device [nt]) = conj(k0^2 sum_j f_j^T M_t u_j),
+ * i.e. dL/dRe eps + i dL/dIm eps. */
+mw_status mw_adjoint_gradient(mw_problem *p, int32_t ntx, const int32_t *tx, int32_t nrx,
+                              const int32_t *rx, const void *U, const void *gS, void *grad_eps,
+                              const mw_solve_opts *o, mw_solve_info *info);
+/* Forward solve of ports tx, S_sim (device nrx x ntx), J = 1/2 sum |S - S_meas|^2
+ * (host double), and grad_eps (device [nt]) by one adjoint solve with the
+ * same factors.  S_meas: device nrx x ntx. */
+mw_status mw_misfit_gradient(mw_problem *p, int32_t ntx, const int32_t *tx, int32_t nrx,
+                             const int32_t *rx, const void *S_meas, double *J, void *S_sim,
+                             void *grad_eps, const mw_solve_opts *o);
+
+
+/* ---- host-only inspection (no device needed) ------------------------- */
+/* Topology the library builds for `mesh` (Section 2.1): number of unknowns,
+ * nonzeros of A's pattern, edges; optional host outputs (pass NULL to skip):
+ * edge_of_dof [n], row_ptr [n+1], col [nnz]. */
+mw_status mw_host_topology(const mw_mesh *mesh, int64_t *n, int64_t *nnz, int64_t *n_edges,
+                           int32_t *edge_of_dof, int64_t *row_ptr, int32_t *col);
+/* Overlapping decomposition (Section 3) for tet_part: n_loc [n_sub] local
+ * sizes, n_faces [n_sub] faces carrying a boundary or transmission term
+ * (NULL to skip), and concatenated over subdomains (NULL to skip): sub_dof
+ * [sum n_loc] global unknown of each local one (R_i), D [sum n_loc] the
+ * partition-of-unity weights. */
+mw_status mw_host_decomposition(const mw_mesh *mesh, const int32_t *tet_part, int32_t n_sub,
+                                int32_t overlap, int32_t *n_loc, int64_t *n_faces, int32_t *sub_dof,
+                                double *D);
+const char *mw_host_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MW_H */

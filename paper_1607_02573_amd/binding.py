@@ -1,0 +1,167 @@
+"""ctypes binding of libmw.so (include/mw.h): argument marshalling only.
+
+Every step of the solve path runs inside the library's HIP kernels; this
+module checks tensor shapes/dtypes/devices, passes raw pointers and turns
+non-zero status codes into exceptions.  There is no CPU fallback: a missing
+library raises ``MwLibraryMissing``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmw.so")
+
+MW_OK, MW_EINVAL, MW_ENOMEM, MW_ESINGULAR, MW_ENOCONV, MW_ENUMERIC, MW_EDEVICE = 0, -1, -2, -3, -4, -5, -6
+MW_C128, MW_C64 = 0, 1
+STATUS_NAMES = {0: "MW_OK", -1: "MW_EINVAL", -2: "MW_ENOMEM", -3: "MW_ESINGULAR", -4: "MW_ENOCONV",
+                -5: "MW_ENUMERIC", -6: "MW_EDEVICE"}
+
+
+class MwLibraryMissing(RuntimeError):
+    pass
+
+
+class MwError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class mw_complex(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class mw_mesh(C.Structure):
+    _fields_ = [("nv", C.c_int32), ("xyz", C.c_void_p), ("nt", C.c_int32), ("tet", C.c_void_p),
+                ("nbf", C.c_int32), ("bface", C.c_void_p), ("btag", C.c_void_p)]
+
+
+class mw_port(C.Structure):
+    _fields_ = [("beta", mw_complex), ("radius", C.c_double), ("theta", C.c_double), ("width", C.c_double),
+                ("pol", C.c_double * 3)]
+
+
+class mw_solve_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("maxit", C.c_int32), ("use_x0", C.c_int32)]
+
+
+class mw_solve_info(C.Structure):
+    _fields_ = [("iters", C.c_void_p), ("relres", C.c_void_p), ("max_iters", C.c_int32), ("cycles", C.c_int32),
+                ("chunks", C.c_int32), ("t_solve", C.c_double)]
+
+
+class mw_problem_info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("n_edges", C.c_int64), ("nt", C.c_int32),
+                ("nports", C.c_int32), ("n_sub", C.c_int32), ("sum_ni", C.c_int64), ("max_ni", C.c_int32),
+                ("precision", C.c_int32), ("factor_bytes", C.c_int64), ("t_assemble", C.c_double),
+                ("t_decompose", C.c_double), ("t_factor", C.c_double)]
+
+
+_P = C.c_void_p
+_I = C.c_int32
+_SIGS = {
+    "mw_create": [C.POINTER(_P), C.c_int, C.c_int64],
+    "mw_set_stream": [_P, _P],
+    "mw_destroy": [_P],
+    "mw_assemble": [_P, C.POINTER(mw_mesh), _P, C.c_double, mw_complex, _P, _I, C.POINTER(_P)],
+    "mw_update_eps": [_P, _P],
+    "mw_problem_get_info": [_P, C.POINTER(mw_problem_info)],
+    "mw_dof_edges": [_P, _P, _P],
+    "mw_destroy_problem": [_P],
+    "mw_get_matrix": [_P, _P, _P, _P],
+    "mw_rhs_ports": [_P, _I, _P, _P],
+    "mw_rhs_dipoles": [_P, _I, _P, _P, _P],
+    "mw_factor_subdomains": [_P, _I, _I, C.c_int, _P],
+    "mw_apply_preconditioner": [_P, _I, _P, _P],
+    "mw_solve": [_P, _I, _P, _P, C.POINTER(mw_solve_opts), C.POINTER(mw_solve_info)],
+    "mw_s_matrix": [_P, _I, _P, _I, _P, _P],
+    "mw_port_norms": [_P, _P],
+    "mw_adjoint_gradient": [_P, _I, _P, _I, _P, _P, _P, _P, C.POINTER(mw_solve_opts), C.POINTER(mw_solve_info)],
+    "mw_misfit_gradient": [_P, _I, _P, _I, _P, _P, _P, _P, _P, C.POINTER(mw_solve_opts)],
+    "mw_host_topology": [C.POINTER(mw_mesh), _P, _P, _P, _P, _P, _P],
+    "mw_host_decomposition": [C.POINTER(mw_mesh), _P, _I, _I, _P, _P, _P, _P],
+}
+EXPORTED = list(_SIGS) + ["mw_last_error", "mw_host_last_error"]
+
+_lib = None
+
+
+def lib():
+    """Load libmw.so (built in-tree); raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise MwLibraryMissing(f"{LIB_PATH} not found: build it with `python -m paper_1607_02573_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    for name, args in _SIGS.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    L.mw_last_error.restype = C.c_char_p
+    L.mw_last_error.argtypes = []
+    L.mw_host_last_error.restype = C.c_char_p
+    L.mw_host_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def check(code: int, host: bool = False):
+    if code != MW_OK:
+        L = lib()
+        msg = (L.mw_host_last_error() if host else L.mw_last_error()).decode(errors="replace")
+        raise MwError(code, msg)
+
+
+def ptr(a) -> int:
+    """Raw address of a contiguous numpy array or torch tensor."""
+    if isinstance(a, np.ndarray):
+        assert a.flags["C_CONTIGUOUS"]
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def make_mesh(xyz: np.ndarray, tet: np.ndarray, bface: np.ndarray, btag: np.ndarray):
+    """mw_mesh over host arrays (the arrays are returned to keep them alive)."""
+    keep = (np.ascontiguousarray(xyz, dtype=np.float64), np.ascontiguousarray(tet, dtype=np.int32),
+            np.ascontiguousarray(bface, dtype=np.int32), np.ascontiguousarray(btag, dtype=np.int32))
+    m = mw_mesh(nv=keep[0].shape[0], xyz=ptr(keep[0]), nt=keep[1].shape[0], tet=ptr(keep[1]),
+                nbf=keep[2].shape[0], bface=ptr(keep[2]) if keep[2].size else None,
+                btag=ptr(keep[3]) if keep[3].size else None)
+    return m, keep
+
+
+def host_topology(xyz, tet, bface, btag):
+    """Edge numbering and CSR pattern from the library's host code (no GPU)."""
+    L = lib()
+    m, keep = make_mesh(xyz, tet, bface, btag)
+    n, nnz, ne = C.c_int64(), C.c_int64(), C.c_int64()
+    check(L.mw_host_topology(C.byref(m), C.addressof(n), C.addressof(nnz), C.addressof(ne), None, None, None), True)
+    eod = np.empty(n.value, dtype=np.int32)
+    rp = np.empty(n.value + 1, dtype=np.int64)
+    col = np.empty(nnz.value, dtype=np.int32)
+    check(L.mw_host_topology(C.byref(m), C.addressof(n), C.addressof(nnz), C.addressof(ne), ptr(eod), ptr(rp),
+                             ptr(col)), True)
+    return {"n": n.value, "nnz": nnz.value, "n_edges": ne.value, "edge_of_dof": eod, "row_ptr": rp, "col": col}
+
+
+def host_decomposition(xyz, tet, bface, btag, part, n_sub: int, overlap: int = 1):
+    """Local unknowns and partition-of-unity weights from the library's host code."""
+    L = lib()
+    m, keep = make_mesh(xyz, tet, bface, btag)
+    part = np.ascontiguousarray(part, dtype=np.int32)
+    n_loc = np.zeros(n_sub, dtype=np.int32)
+    nf = np.zeros(n_sub, dtype=np.int64)
+    check(L.mw_host_decomposition(C.byref(m), ptr(part), n_sub, overlap, ptr(n_loc), ptr(nf), None, None), True)
+    tot = int(n_loc.sum())
+    sub_dof = np.empty(tot, dtype=np.int32)
+    D = np.empty(tot)
+    check(L.mw_host_decomposition(C.byref(m), ptr(part), n_sub, overlap, ptr(n_loc), ptr(nf), ptr(sub_dof),
+                                  ptr(D)), True)
+    off = np.r_[0, np.cumsum(n_loc)]
+    return {"n_loc": n_loc, "n_faces": nf, "sub_dof": [sub_dof[off[i]:off[i + 1]] for i in range(n_sub)],
+            "D": [D[off[i]:off[i + 1]] for i in range(n_sub)]}

@@ -1,0 +1,824 @@
+// C ABI of the library (include/mw.h): context and problem objects, the
+// byte budget, and the host drivers of assembly, subdomain factorisation and
+// the preconditioned pseudo-block GMRES.  All arithmetic runs in the HIP
+// kernels; the host only orders launches, moves index lists and reads back
+// per-column convergence flags.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <numeric>
+
+#include "kernels.hpp"
+
+using namespace mw;
+
+static thread_local std::string g_last_error;
+
+struct mw_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t budget = 0;
+  int64_t used = 0;
+};
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct DeviceGuard {
+  int prev = 0;
+  explicit DeviceGuard(int dev) {
+    MW_HIP(hipGetDevice(&prev));
+    if (prev != dev) MW_HIP(hipSetDevice(dev));
+  }
+  ~DeviceGuard() { (void)hipSetDevice(prev); }
+};
+
+DevBuf dalloc(mw_ctx* c, int64_t bytes) {
+  DevBuf b;
+  if (bytes <= 0) return b;
+  if (c->used + bytes > c->budget)
+    fail(MW_ENOMEM, "HBM budget exceeded: need " + std::to_string(bytes) + " more bytes, " +
+                        std::to_string(c->budget - c->used) + " of " + std::to_string(c->budget) + " left");
+  hipError_t e = hipMalloc(&b.p, (size_t)bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(MW_ENOMEM, std::string("hipMalloc of ") + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+  }
+  b.bytes = (size_t)bytes;
+  b.ledger = &c->used;
+  c->used += bytes;
+  return b;
+}
+
+template <class T>
+DevBuf upload(mw_ctx* c, const std::vector<T>& v) {
+  DevBuf b = dalloc(c, (int64_t)(v.size() * sizeof(T)));
+  if (!v.empty()) MW_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  return b;
+}
+
+void sync(mw_ctx* c) { MW_HIP(hipStreamSynchronize(c->stream)); }
+
+// A resizable device workspace (grown on demand, never shrunk).
+struct Work {
+  DevBuf b;
+  void* get(mw_ctx* c, int64_t bytes) {
+    if ((int64_t)b.bytes < bytes) {
+      b.release();
+      b = dalloc(c, bytes);
+    }
+    return b.p;
+  }
+};
+
+}  // namespace
+
+struct mw_problem {
+  mw_ctx* ctx = nullptr;
+  Topology T;
+  double k0 = 0;
+  mw_complex beta_imp{0, 0};
+  std::vector<mw_port> ports;
+  // mesh and operator
+  DevBuf xyz, tet, t2e, dof, bface, bf2e, fbeta, row_ptr, col, rt_ptr, rt, rf_ptr, rf;
+  DevBuf eps, E, val;
+  DeviceMesh dm;
+  // ports
+  DevBuf port_dev, port_ptr, ent_dof, ent_port, ent_ptr, ent_fq, pf_ptr, pf, pval, nu;
+  DevicePorts dp;
+  // decomposition and factors
+  bool has_dec = false;
+  uint64_t dec_key = 0;
+  Decomposition D;
+  DevBuf d_fac_off, d_loc_off, d_n_loc, d_n_pad, d_lt_off, d_lt_tet, d_lt_loc, d_lf_off, d_lf_vert, d_lf_owner,
+      d_lf_kind, d_lf_loc, d_rtl_ptr, d_rtl, d_rfl_ptr, d_rfl, d_sub_dof, d_D, d_cp_ptr, d_cp_row, d_ipiv, d_ridx,
+      d_info;
+  DeviceDecomp dd;
+  DevBuf F;
+  int prec = -1;
+  bool factors_valid = false;
+  // solve workspaces
+  Work w_V, w_X, w_B, w_Z, w_Y, w_H, w_cs, w_sn, w_g, w_y, w_h1, w_h2, w_part, w_npart, w_vec, w_int, w_tmp;
+  double t_assemble = 0, t_decompose = 0, t_factor = 0;
+};
+
+namespace {
+
+mw_status guard(const std::function<void()>& f) {
+  try {
+    f();
+    return MW_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host out of memory";
+    return MW_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return MW_EINVAL;
+  }
+}
+
+void check_prob(mw_problem* p) { MW_CHECK(p != nullptr && p->ctx != nullptr, MW_EINVAL, "problem is NULL"); }
+
+// ------------------------------------------------------------------ ports
+void setup_ports(mw_problem* p) {
+  mw_ctx* c = p->ctx;
+  const Topology& T = p->T;
+  int np = (int)p->ports.size();
+  std::vector<PortDev> pd(np);
+  for (int k = 0; k < np; ++k) {
+    const mw_port& q = p->ports[k];
+    pd[k].beta = make_double2(q.beta.re, q.beta.im);
+    pd[k].radius = q.radius;
+    pd[k].theta = q.theta;
+    pd[k].width = q.width;
+    for (int a = 0; a < 3; ++a) pd[k].pol[a] = q.pol[a];
+  }
+  // faces of every port, ascending face id
+  std::vector<int64_t> pf_ptr(np + 1, 0);
+  for (int32_t f = 0; f < T.nbf; ++f)
+    if (T.btag[f] >= 1) pf_ptr[T.btag[f]]++;
+  for (int k = 0; k < np; ++k) pf_ptr[k + 1] += pf_ptr[k];
+  std::vector<int32_t> pf(pf_ptr[np]);
+  {
+    std::vector<int64_t> fill(pf_ptr.begin(), pf_ptr.end() - 1);
+    for (int32_t f = 0; f < T.nbf; ++f)
+      if (T.btag[f] >= 1) pf[fill[T.btag[f] - 1]++] = f;
+  }
+  // distinct unknowns of each port with their (face, local edge) contributions
+  std::vector<int64_t> port_ptr(np + 1, 0), ent_ptr(1, 0);
+  std::vector<int32_t> ent_dof, ent_port, ent_fq;
+  for (int k = 0; k < np; ++k) {
+    std::vector<std::pair<int32_t, int32_t>> dq;  // (dof, face*3+q)
+    for (int64_t j = pf_ptr[k]; j < pf_ptr[k + 1]; ++j) {
+      int32_t f = pf[j];
+      for (int q = 0; q < 3; ++q) {
+        int32_t d = T.dof[T.bf2e[(size_t)f * 3 + q]];
+        if (d >= 0) dq.push_back({d, f * 3 + q});
+      }
+    }
+    std::stable_sort(dq.begin(), dq.end(), [](auto& a, auto& b) { return a.first < b.first; });
+    for (size_t a = 0; a < dq.size();) {
+      size_t b = a;
+      while (b < dq.size() && dq[b].first == dq[a].first) { ent_fq.push_back(dq[b].second); ++b; }
+      ent_dof.push_back(dq[a].first);
+      ent_port.push_back(k);
+      ent_ptr.push_back((int64_t)ent_fq.size());
+      a = b;
+    }
+    port_ptr[k + 1] = (int64_t)ent_dof.size();
+  }
+  p->port_dev = dalloc(c, (int64_t)std::max<size_t>(1, pd.size()) * sizeof(PortDev));
+  if (np) MW_HIP(hipMemcpyAsync(p->port_dev.p, pd.data(), pd.size() * sizeof(PortDev), hipMemcpyHostToDevice, c->stream));
+  p->port_ptr = upload(c, port_ptr);
+  p->ent_dof = upload(c, ent_dof);
+  p->ent_port = upload(c, ent_port);
+  p->ent_ptr = upload(c, ent_ptr);
+  p->ent_fq = upload(c, ent_fq);
+  p->pf_ptr = upload(c, pf_ptr);
+  p->pf = upload(c, pf);
+  p->pval = dalloc(c, (int64_t)std::max<size_t>(1, ent_dof.size()) * 8);
+  p->nu = dalloc(c, (int64_t)std::max(1, np) * 8);
+  DevicePorts& P = p->dp;
+  P.nports = np;
+  P.nent = (int64_t)ent_dof.size();
+  P.ports = p->port_dev.as<PortDev>();
+  P.port_ptr = p->port_ptr.as<int64_t>();
+  P.ent_dof = p->ent_dof.as<int32_t>();
+  P.ent_port = p->ent_port.as<int32_t>();
+  P.ent_ptr = p->ent_ptr.as<int64_t>();
+  P.ent_fq = p->ent_fq.as<int32_t>();
+  P.pf_ptr = p->pf_ptr.as<int64_t>();
+  P.pf = p->pf.as<int32_t>();
+  P.pval = p->pval.as<double>();
+  P.nu = p->nu.as<double>();
+  launch_port_setup(p->dm, P, c->stream);
+}
+
+void assemble_values(mw_problem* p) {
+  launch_element_matrices(p->dm, p->eps.as<double2>(), p->k0, p->E.as<double2>(), p->ctx->stream);
+  launch_gather_csr(p->dm, p->E.as<double2>(), p->val.as<double2>(), p->ctx->stream);
+}
+
+uint64_t hash_part(const int32_t* part, int32_t nt, int32_t nsub, int32_t delta) {
+  uint64_t h = 1469598103934665603ull ^ (uint64_t)nsub * 1099511628211ull ^ ((uint64_t)delta << 32);
+  for (int32_t t = 0; t < nt; ++t) h = (h ^ (uint64_t)(uint32_t)part[t]) * 1099511628211ull;
+  return h;
+}
+
+void upload_decomp(mw_problem* p) {
+  mw_ctx* c = p->ctx;
+  const Decomposition& D = p->D;
+  p->d_fac_off = upload(c, D.fac_off);
+  p->d_loc_off = upload(c, D.loc_off);
+  p->d_n_loc = upload(c, D.n_loc);
+  p->d_n_pad = upload(c, D.n_pad);
+  p->d_lt_off = upload(c, D.lt_off);
+  p->d_lt_tet = upload(c, D.lt_tet);
+  p->d_lt_loc = upload(c, D.lt_loc);
+  p->d_lf_off = upload(c, D.lf_off);
+  p->d_lf_vert = upload(c, D.lf_vert);
+  p->d_lf_owner = upload(c, D.lf_owner);
+  p->d_lf_kind = upload(c, D.lf_kind);
+  p->d_lf_loc = upload(c, D.lf_loc);
+  p->d_rtl_ptr = upload(c, D.rtl_ptr);
+  p->d_rtl = upload(c, D.rtl);
+  p->d_rfl_ptr = upload(c, D.rfl_ptr);
+  p->d_rfl = upload(c, D.rfl);
+  p->d_sub_dof = upload(c, D.sub_dof);
+  p->d_D = upload(c, D.D);
+  p->d_cp_ptr = upload(c, D.cp_ptr);
+  p->d_cp_row = upload(c, D.cp_row);
+  p->d_ipiv = dalloc(c, D.sum_pad() * 4);
+  p->d_ridx = dalloc(c, D.sum_pad() * 4);
+  p->d_info = dalloc(c, (int64_t)D.nsub * 4);
+  DeviceDecomp& d = p->dd;
+  d.nsub = D.nsub;
+  d.max_pad = *std::max_element(D.n_pad.begin(), D.n_pad.end());
+  d.sum_pad = D.sum_pad();
+  d.fac_off = p->d_fac_off.as<int64_t>();
+  d.loc_off = p->d_loc_off.as<int64_t>();
+  d.n_loc = p->d_n_loc.as<int32_t>();
+  d.n_pad = p->d_n_pad.as<int32_t>();
+  d.lt_off = p->d_lt_off.as<int64_t>();
+  d.lt_tet = p->d_lt_tet.as<int32_t>();
+  d.lt_loc = p->d_lt_loc.as<int32_t>();
+  d.lf_off = p->d_lf_off.as<int64_t>();
+  d.lf_vert = p->d_lf_vert.as<int32_t>();
+  d.lf_owner = p->d_lf_owner.as<int32_t>();
+  d.lf_kind = p->d_lf_kind.as<int32_t>();
+  d.lf_loc = p->d_lf_loc.as<int32_t>();
+  d.rtl_ptr = p->d_rtl_ptr.as<int64_t>();
+  d.rtl = p->d_rtl.as<int32_t>();
+  d.rfl_ptr = p->d_rfl_ptr.as<int64_t>();
+  d.rfl = p->d_rfl.as<int32_t>();
+  d.sub_dof = p->d_sub_dof.as<int32_t>();
+  d.D = p->d_D.as<double>();
+  d.cp_ptr = p->d_cp_ptr.as<int64_t>();
+  d.cp_row = p->d_cp_row.as<int64_t>();
+  d.ipiv = p->d_ipiv.as<int32_t>();
+  d.ridx = p->d_ridx.as<int32_t>();
+  d.info = p->d_info.as<int32_t>();
+}
+
+// Z = M^-1 V (n x nc, leading dimension ld), local workspace Y
+void apply_prec(mw_problem* p, const double2* V, double2* Z, int nc, int64_t ld) {
+  mw_ctx* c = p->ctx;
+  MW_CHECK(p->factors_valid, MW_EINVAL, "no valid subdomain factors: call mw_factor_subdomains");
+  int64_t n = p->T.n();
+  if (p->prec == MW_C64) {
+    float2* Y = (float2*)p->w_Y.get(c, p->dd.sum_pad * nc * 8);
+    launch_restrict<float2>(p->dd, V, ld, nc, Y, nc, c->stream);
+    lu_solve_batched<float2>(p->dd, p->F.as<float2>(), Y, nc, nc, c->stream);
+    launch_prolong<float2>(p->dd, n, Y, nc, nc, Z, ld, c->stream);
+  } else {
+    double2* Y = (double2*)p->w_Y.get(c, p->dd.sum_pad * nc * 16);
+    launch_restrict<double2>(p->dd, V, ld, nc, Y, nc, c->stream);
+    lu_solve_batched<double2>(p->dd, p->F.as<double2>(), Y, nc, nc, c->stream);
+    launch_prolong<double2>(p->dd, n, Y, nc, nc, Z, ld, c->stream);
+  }
+}
+
+// column 2-norms squared of an n x nc block (device out), deterministic
+void colnorm2(mw_problem* p, const double2* V, int64_t ld, int nc, double* out) {
+  mw_ctx* c = p->ctx;
+  int64_t n = p->T.n();
+  int64_t nch = reduce_chunks(n);
+  double* part = (double*)p->w_npart.get(c, nch * nc * 8);
+  launch_colnorm2_partial(V, n, ld, nc, part, c->stream);
+  launch_sum_chunks(part, nch, nc, out, c->stream);
+}
+
+struct ChunkResult {
+  int max_iters = 0, cycles = 0;
+  bool numeric = false;
+};
+
+// GMRES(m) right-preconditioned with ORAS, pseudo-block over nc columns
+// (Section 6), true residual recomputed at every restart.
+ChunkResult gmres_chunk(mw_problem* p, const double2* Bsrc, int64_t ldb_src, double2* Xdst, int64_t ldx_dst, int nc,
+                        const mw_solve_opts& o, int32_t* iters_out, double* relres_out) {
+  mw_ctx* c = p->ctx;
+  hipStream_t st = c->stream;
+  const int64_t n = p->T.n();
+  const int m = o.restart;
+  const int64_t ld = nc;
+  const int64_t vstride = n * ld;
+  double2* V = (double2*)p->w_V.get(c, (int64_t)(m + 1) * vstride * 16);
+  double2* X = (double2*)p->w_X.get(c, vstride * 16);
+  double2* B = (double2*)p->w_B.get(c, vstride * 16);
+  double2* Z = (double2*)p->w_Z.get(c, vstride * 16);
+  double2* H = (double2*)p->w_H.get(c, (int64_t)(m + 1) * m * nc * 16);
+  double* cs = (double*)p->w_cs.get(c, (int64_t)m * nc * 8);
+  double2* sn = (double2*)p->w_sn.get(c, (int64_t)m * nc * 16);
+  double2* g = (double2*)p->w_g.get(c, (int64_t)(m + 1) * nc * 16);
+  double2* y = (double2*)p->w_y.get(c, (int64_t)(m + 1) * nc * 16);
+  double2* h1 = (double2*)p->w_h1.get(c, (int64_t)(m + 1) * nc * 16);
+  double2* h2 = (double2*)p->w_h2.get(c, (int64_t)(m + 1) * nc * 16);
+  int64_t nch = reduce_chunks(n);
+  double2* part = (double2*)p->w_part.get(c, nch * (m + 1) * nc * 16);
+  double* vec = (double*)p->w_vec.get(c, (int64_t)4 * nc * 8);
+  double* bnorm = vec;        // ||b||
+  double* rn2 = vec + nc;     // ||r||^2
+  double* hn2 = vec + 2 * nc; // ||w||^2
+  double* resid = vec + 3 * nc;
+  int32_t* ivec = (int32_t*)p->w_int.get(c, (int64_t)2 * nc * 4);
+  int32_t* act = ivec;
+  int32_t* kdim = ivec + nc;
+
+  launch_copy_cols(Bsrc, ldb_src, B, ld, n, nc, st);
+  if (o.use_x0) launch_copy_cols(Xdst, ldx_dst, X, ld, n, nc, st);
+  else launch_zero(X, vstride, st);
+  std::vector<double> hb(nc), hr(nc), hb2(nc);
+  colnorm2(p, B, ld, nc, rn2);
+  MW_HIP(hipMemcpyAsync(hb2.data(), rn2, nc * 8, hipMemcpyDeviceToHost, st));
+  sync(c);
+  for (int k = 0; k < nc; ++k) hb[k] = std::sqrt(hb2[k]);
+  MW_HIP(hipMemcpyAsync(bnorm, hb.data(), nc * 8, hipMemcpyHostToDevice, st));
+
+  ChunkResult res;
+  std::vector<int32_t> iters(nc, 0), hact(nc, 0), hact_prev(nc, 0);
+  std::vector<double> relres(nc, 0.0);
+  std::vector<double2> g0((size_t)nc);
+  for (;;) {
+    // true residual r = b - A x (iterative refinement point)
+    launch_spmm(p->dm, p->val.as<double2>(), X, ld, Z, ld, nc, B, ld, st);
+    colnorm2(p, Z, ld, nc, rn2);
+    MW_HIP(hipMemcpyAsync(hr.data(), rn2, nc * 8, hipMemcpyDeviceToHost, st));
+    sync(c);
+    int nact = 0;
+    for (int k = 0; k < nc; ++k) {
+      double r = std::sqrt(hr[k]);
+      if (!std::isfinite(r)) res.numeric = true;
+      relres[k] = hb[k] > 0 ? r / hb[k] : 0.0;
+      hact[k] = (hb[k] > 0 && relres[k] > o.tol && iters[k] < o.maxit && std::isfinite(r)) ? 1 : 0;
+      nact += hact[k];
+      g0[k] = make_double2(r, 0.0);
+    }
+    if (res.numeric || nact == 0) break;
+    res.cycles++;
+    MW_HIP(hipMemcpyAsync(act, hact.data(), nc * 4, hipMemcpyHostToDevice, st));
+    launch_zero_bytes(kdim, nc * 4, st);
+    launch_zero(g, (int64_t)(m + 1) * nc, st);
+    MW_HIP(hipMemcpyAsync(g, g0.data(), nc * 16, hipMemcpyHostToDevice, st));
+    launch_start_cycle(Z, V, n, ld, nc, rn2, act, st);
+    for (int j = 0; j < m; ++j) {
+      double2* Vj = V + (int64_t)j * vstride;
+      double2* W = V + (int64_t)(j + 1) * vstride;
+      apply_prec(p, Vj, Z, nc, ld);
+      launch_spmm(p->dm, p->val.as<double2>(), Z, ld, W, ld, nc, nullptr, 0, st);
+      // classical Gram-Schmidt, twice
+      launch_dots_partial(V, vstride, j + 1, W, n, ld, nc, act, part, st);
+      launch_sum_chunks_c(part, nch, (int64_t)(j + 1) * nc, h1, st);
+      launch_cgs_update(V, vstride, j + 1, h1, W, n, ld, nc, act, nullptr, st);
+      launch_dots_partial(V, vstride, j + 1, W, n, ld, nc, act, part, st);
+      launch_sum_chunks_c(part, nch, (int64_t)(j + 1) * nc, h2, st);
+      double* npart = (double*)p->w_npart.get(c, nch * nc * 8);
+      launch_cgs_update(V, vstride, j + 1, h2, W, n, ld, nc, act, npart, st);
+      launch_sum_chunks(npart, nch, nc, hn2, st);
+      launch_scale_cols(W, n, ld, nc, hn2, act, st);
+      launch_givens(j, m, nc, h1, h2, hn2, H, cs, sn, g, kdim, act, resid, bnorm, o.tol, st);
+      hact_prev = hact;
+      MW_HIP(hipMemcpyAsync(hact.data(), act, nc * 4, hipMemcpyDeviceToHost, st));
+      sync(c);
+      bool changed = false;
+      nact = 0;
+      for (int k = 0; k < nc; ++k) {
+        if (hact_prev[k]) iters[k]++;
+        if (hact[k] && iters[k] >= o.maxit) { hact[k] = 0; changed = true; }
+        nact += hact[k];
+      }
+      if (nact == 0) break;
+      if (changed) MW_HIP(hipMemcpyAsync(act, hact.data(), nc * 4, hipMemcpyHostToDevice, st));
+    }
+    // x += M^-1 (V y)
+    launch_backsolve(m, nc, H, g, kdim, y, st);
+    launch_combine(V, vstride, m, y, kdim, Z, n, ld, nc, st);
+    double2* U = (double2*)p->w_tmp.get(c, vstride * 16);
+    apply_prec(p, Z, U, nc, ld);
+    launch_axpy_cols(X, U, n, ld, nc, st);
+  }
+  launch_copy_cols(X, ld, Xdst, ldx_dst, n, nc, st);
+  sync(c);
+  for (int k = 0; k < nc; ++k) {
+    if (iters_out) iters_out[k] = iters[k];
+    if (relres_out) relres_out[k] = relres[k];
+    res.max_iters = std::max(res.max_iters, iters[k]);
+  }
+  return res;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char* mw_last_error(void) { return g_last_error.c_str(); }
+
+mw_status mw_create(mw_ctx** out, int device, int64_t hbm_budget_bytes) {
+  return guard([&] {
+    MW_CHECK(out != nullptr, MW_EINVAL, "out is NULL");
+    int ndev = 0;
+    MW_HIP(hipGetDeviceCount(&ndev));
+    MW_CHECK(device >= 0 && device < ndev, MW_EINVAL, "device ordinal out of range");
+    DeviceGuard dg(device);
+    size_t fr = 0, tot = 0;
+    MW_HIP(hipMemGetInfo(&fr, &tot));
+    auto* c = new mw_ctx();
+    c->device = device;
+    c->budget = hbm_budget_bytes > 0 ? hbm_budget_bytes : (int64_t)(0.95 * (double)tot);
+    *out = c;
+  });
+}
+
+mw_status mw_set_stream(mw_ctx* ctx, void* stream) {
+  return guard([&] {
+    MW_CHECK(ctx != nullptr, MW_EINVAL, "ctx is NULL");
+    ctx->stream = (hipStream_t)stream;
+  });
+}
+
+mw_status mw_destroy(mw_ctx* ctx) {
+  return guard([&] {
+    if (!ctx) return;
+    MW_CHECK(ctx->used == 0, MW_EINVAL, "destroy every problem of the context first");
+    delete ctx;
+  });
+}
+
+mw_status mw_assemble(mw_ctx* ctx, const mw_mesh* mesh, const mw_complex* eps_r, double k0, mw_complex beta_imp,
+                      const mw_port* ports, int32_t nports, mw_problem** out) {
+  return guard([&] {
+    MW_CHECK(ctx && mesh && eps_r && out, MW_EINVAL, "NULL argument");
+    MW_CHECK(nports >= 0 && (nports == 0 || ports), MW_EINVAL, "ports");
+    MW_CHECK(std::isfinite(k0) && k0 > 0, MW_EINVAL, "k0 must be positive");
+    DeviceGuard dg(ctx->device);
+    double t0 = now_s();
+    auto p = std::make_unique<mw_problem>();
+    p->ctx = ctx;
+    p->k0 = k0;
+    p->beta_imp = beta_imp;
+    p->ports.assign(ports, ports + nports);
+    build_topology(*mesh, p->T);
+    Topology& T = p->T;
+    for (int32_t f = 0; f < T.nbf; ++f)
+      MW_CHECK(T.btag[f] <= nports, MW_EINVAL, "face tag refers to a port beyond nports");
+    std::vector<double2> fb(std::max(1, T.nbf), make_double2(0, 0));
+    for (int32_t f = 0; f < T.nbf; ++f) {
+      if (T.btag[f] == MW_TAG_IMPEDANCE) fb[f] = make_double2(beta_imp.re, beta_imp.im);
+      else if (T.btag[f] >= 1) fb[f] = make_double2(ports[T.btag[f] - 1].beta.re, ports[T.btag[f] - 1].beta.im);
+    }
+    std::vector<double2> e(T.nt);
+    for (int32_t t = 0; t < T.nt; ++t) e[t] = make_double2(eps_r[t].re, eps_r[t].im);
+    p->xyz = upload(ctx, T.xyz);
+    p->tet = upload(ctx, T.tet);
+    p->t2e = upload(ctx, T.t2e);
+    p->dof = upload(ctx, T.dof);
+    p->bface = upload(ctx, T.bface);
+    p->bf2e = upload(ctx, T.bf2e);
+    p->fbeta = upload(ctx, fb);
+    p->row_ptr = upload(ctx, T.row_ptr);
+    p->col = upload(ctx, T.col);
+    p->rt_ptr = upload(ctx, T.rt_ptr);
+    p->rt = upload(ctx, T.rt);
+    p->rf_ptr = upload(ctx, T.rf_ptr);
+    p->rf = upload(ctx, T.rf);
+    p->eps = upload(ctx, e);
+    p->E = dalloc(ctx, (int64_t)T.nt * 21 * 16);
+    p->val = dalloc(ctx, (int64_t)T.col.size() * 16);
+    DeviceMesh& m = p->dm;
+    m.nv = T.nv; m.nt = T.nt; m.n = T.n(); m.nbf = T.nbf; m.nnz = (int64_t)T.col.size();
+    m.xyz = p->xyz.as<double>(); m.tet = p->tet.as<int32_t>(); m.t2e = p->t2e.as<int32_t>();
+    m.dof = p->dof.as<int32_t>(); m.bface = p->bface.as<int32_t>(); m.bf2e = p->bf2e.as<int32_t>();
+    m.fbeta = p->fbeta.as<double2>(); m.row_ptr = p->row_ptr.as<int64_t>(); m.col = p->col.as<int32_t>();
+    m.rt_ptr = p->rt_ptr.as<int64_t>(); m.rt = p->rt.as<int32_t>(); m.rf_ptr = p->rf_ptr.as<int64_t>();
+    m.rf = p->rf.as<int32_t>();
+    assemble_values(p.get());
+    setup_ports(p.get());
+    sync(ctx);
+    p->t_assemble = now_s() - t0;
+    *out = p.release();
+  });
+}
+
+mw_status mw_update_eps(mw_problem* p, const void* eps_dev) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(eps_dev != nullptr, MW_EINVAL, "eps is NULL");
+    DeviceGuard dg(p->ctx->device);
+    double t0 = now_s();
+    MW_HIP(hipMemcpyAsync(p->eps.p, eps_dev, (size_t)p->T.nt * 16, hipMemcpyDeviceToDevice, p->ctx->stream));
+    assemble_values(p);
+    p->factors_valid = false;
+    sync(p->ctx);
+    p->t_assemble = now_s() - t0;
+  });
+}
+
+mw_status mw_problem_get_info(mw_problem* p, mw_problem_info* info) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(info != nullptr, MW_EINVAL, "info is NULL");
+    std::memset(info, 0, sizeof(*info));
+    info->n = p->T.n();
+    info->nnz = (int64_t)p->T.col.size();
+    info->n_edges = p->T.ne();
+    info->nt = p->T.nt;
+    info->nports = (int32_t)p->ports.size();
+    if (p->has_dec) {
+      info->n_sub = p->D.nsub;
+      info->sum_ni = std::accumulate(p->D.n_loc.begin(), p->D.n_loc.end(), (int64_t)0);
+      info->max_ni = *std::max_element(p->D.n_loc.begin(), p->D.n_loc.end());
+    }
+    info->precision = p->prec;
+    info->factor_bytes = (int64_t)p->F.bytes;
+    info->t_assemble = p->t_assemble;
+    info->t_decompose = p->t_decompose;
+    info->t_factor = p->t_factor;
+  });
+}
+
+mw_status mw_dof_edges(mw_problem* p, int32_t* edge_of_dof, int32_t* edge_vertices) {
+  return guard([&] {
+    check_prob(p);
+    if (edge_of_dof) std::copy(p->T.free_edge.begin(), p->T.free_edge.end(), edge_of_dof);
+    if (edge_vertices)
+      for (size_t k = 0; k < p->T.edges.size(); ++k) edge_vertices[k] = (int32_t)p->T.edges[k];
+  });
+}
+
+mw_status mw_get_matrix(mw_problem* p, void* row_ptr, void* col, void* val) {
+  return guard([&] {
+    check_prob(p);
+    DeviceGuard dg(p->ctx->device);
+    hipStream_t st = p->ctx->stream;
+    if (row_ptr) MW_HIP(hipMemcpyAsync(row_ptr, p->row_ptr.p, p->row_ptr.bytes, hipMemcpyDeviceToDevice, st));
+    if (col) MW_HIP(hipMemcpyAsync(col, p->col.p, p->col.bytes, hipMemcpyDeviceToDevice, st));
+    if (val) MW_HIP(hipMemcpyAsync(val, p->val.p, p->val.bytes, hipMemcpyDeviceToDevice, st));
+    sync(p->ctx);
+  });
+}
+
+mw_status mw_destroy_problem(mw_problem* p) {
+  return guard([&] {
+    if (!p) return;
+    if (p->ctx) { DeviceGuard dg(p->ctx->device); (void)hipStreamSynchronize(p->ctx->stream); delete p; }
+    else delete p;
+  });
+}
+
+mw_status mw_rhs_ports(mw_problem* p, int32_t ntx, const int32_t* tx, void* B) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(ntx >= 0 && (ntx == 0 || (tx && B)), MW_EINVAL, "NULL argument");
+    for (int j = 0; j < ntx; ++j) MW_CHECK(tx[j] >= 0 && tx[j] < (int)p->ports.size(), MW_EINVAL, "port index out of range");
+    if (ntx == 0) return;
+    DeviceGuard dg(p->ctx->device);
+    hipStream_t st = p->ctx->stream;
+    std::vector<int32_t> h(tx, tx + ntx);
+    int32_t* d = (int32_t*)p->w_tmp.get(p->ctx, ntx * 4);
+    MW_HIP(hipMemcpyAsync(d, h.data(), ntx * 4, hipMemcpyHostToDevice, st));
+    launch_zero((double2*)B, p->T.n() * ntx, st);
+    launch_rhs_ports(p->dp, ntx, d, (double2*)B, ntx, st);
+    sync(p->ctx);
+  });
+}
+
+mw_status mw_rhs_dipoles(mw_problem* p, int32_t np, const double* xyz, const double* dir, void* B) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(np >= 0 && (np == 0 || (xyz && dir && B)), MW_EINVAL, "NULL argument");
+    if (np == 0) return;
+    DeviceGuard dg(p->ctx->device);
+    hipStream_t st = p->ctx->stream;
+    char* w = (char*)p->w_tmp.get(p->ctx, (int64_t)np * (48 + 4));
+    double* pts = (double*)w;
+    double* dirs = pts + 3 * np;
+    int* found = (int*)(dirs + 3 * np);
+    std::vector<int> init(np, 0x7fffffff);
+    MW_HIP(hipMemcpyAsync(pts, xyz, np * 24, hipMemcpyHostToDevice, st));
+    MW_HIP(hipMemcpyAsync(dirs, dir, np * 24, hipMemcpyHostToDevice, st));
+    MW_HIP(hipMemcpyAsync(found, init.data(), np * 4, hipMemcpyHostToDevice, st));
+    launch_locate(p->dm, pts, np, found, st);
+    std::vector<int> hf(np);
+    MW_HIP(hipMemcpyAsync(hf.data(), found, np * 4, hipMemcpyDeviceToHost, st));
+    sync(p->ctx);
+    for (int j = 0; j < np; ++j) MW_CHECK(hf[j] != 0x7fffffff, MW_EINVAL, "dipole point outside the mesh");
+    launch_zero((double2*)B, p->T.n() * np, st);
+    launch_rhs_dipoles(p->dm, pts, dirs, found, np, (double2*)B, np, st);
+    sync(p->ctx);
+  });
+}
+
+mw_status mw_factor_subdomains(mw_problem* p, int32_t n_sub, int32_t overlap, mw_precision prec,
+                               const int32_t* tet_part) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(prec == MW_C64 || prec == MW_C128, MW_EINVAL, "precision must be MW_C64 or MW_C128");
+    MW_CHECK(tet_part != nullptr, MW_EINVAL, "tet_part is NULL");
+    mw_ctx* c = p->ctx;
+    DeviceGuard dg(c->device);
+    double t0 = now_s();
+    uint64_t key = hash_part(tet_part, p->T.nt, n_sub, overlap);
+    if (!p->has_dec || key != p->dec_key) {
+      p->has_dec = false;
+      p->factors_valid = false;
+      p->F.release();
+      Decomposition D;
+      build_decomposition(p->T, tet_part, n_sub, overlap, 64, D);
+      p->D = std::move(D);
+      upload_decomp(p);
+      p->has_dec = true;
+      p->dec_key = key;
+    }
+    double t1 = now_s();
+    p->t_decompose = t1 - t0;
+    int64_t esz = prec == MW_C64 ? 8 : 16;
+    int64_t need = p->D.fac_off.back() * esz;
+    if ((int64_t)p->F.bytes != need) {
+      p->F.release();
+      p->factors_valid = false;
+      p->F = dalloc(c, need);
+    }
+    p->prec = prec;
+    hipStream_t st = c->stream;
+    launch_zero_bytes(p->dd.info, (int64_t)p->dd.nsub * 4, st);
+    if (prec == MW_C64) {
+      launch_fill_local<float2>(p->dm, p->dd, p->E.as<double2>(), p->eps.as<double2>(), p->k0, p->F.as<float2>(), st);
+      lu_factor_batched<float2>(p->dd, p->F.as<float2>(), st);
+    } else {
+      launch_fill_local<double2>(p->dm, p->dd, p->E.as<double2>(), p->eps.as<double2>(), p->k0, p->F.as<double2>(), st);
+      lu_factor_batched<double2>(p->dd, p->F.as<double2>(), st);
+    }
+    std::vector<int32_t> info(p->dd.nsub);
+    MW_HIP(hipMemcpyAsync(info.data(), p->dd.info, info.size() * 4, hipMemcpyDeviceToHost, st));
+    sync(c);
+    p->t_factor = now_s() - t1;
+    for (int i = 0; i < p->dd.nsub; ++i)
+      MW_CHECK(info[i] == 0, MW_ESINGULAR,
+               "zero pivot in subdomain " + std::to_string(i) + " at column " + std::to_string(info[i] - 1));
+    p->factors_valid = true;
+  });
+}
+
+mw_status mw_apply_preconditioner(mw_problem* p, int32_t nrhs, const void* V, void* Z) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(nrhs >= 0 && (nrhs == 0 || (V && Z)), MW_EINVAL, "NULL argument");
+    if (nrhs == 0) return;
+    DeviceGuard dg(p->ctx->device);
+    apply_prec(p, (const double2*)V, (double2*)Z, nrhs, nrhs);
+    sync(p->ctx);
+  });
+}
+
+static int solve_chunk_cols(mw_problem* p, int nrhs, int m) {
+  mw_ctx* c = p->ctx;
+  const int64_t n = p->T.n();
+  int64_t esz = p->prec == MW_C64 ? 8 : 16;
+  // bytes per column: basis (m+1), X, B, Z, tmp, local vectors, small arrays
+  int64_t per = (int64_t)(m + 5) * n * 16 + p->dd.sum_pad * esz + reduce_chunks(n) * (m + 2) * 16 + 4096;
+  int64_t held = (int64_t)(p->w_V.b.bytes + p->w_X.b.bytes + p->w_B.b.bytes + p->w_Z.b.bytes + p->w_tmp.b.bytes +
+                           p->w_Y.b.bytes + p->w_part.b.bytes);
+  int64_t avail = c->budget - c->used + held;
+  int64_t cols = avail / std::max<int64_t>(per, 1);
+  return (int)std::min<int64_t>(nrhs, std::max<int64_t>(cols, 0));
+}
+
+mw_status mw_solve(mw_problem* p, int32_t nrhs, const void* B, void* X, const mw_solve_opts* o, mw_solve_info* info) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(nrhs >= 0 && (nrhs == 0 || (B && X)), MW_EINVAL, "NULL argument");
+    mw_solve_opts op{1e-8, 30, 1000, 0};
+    if (o) op = *o;
+    MW_CHECK(op.restart >= 1 && op.maxit >= 1 && op.tol > 0, MW_EINVAL, "invalid solve options");
+    MW_CHECK(p->factors_valid, MW_EINVAL, "no valid subdomain factors: call mw_factor_subdomains");
+    if (info) { info->max_iters = 0; info->cycles = 0; info->chunks = 0; info->t_solve = 0; }
+    if (nrhs == 0) return;
+    DeviceGuard dg(p->ctx->device);
+    double t0 = now_s();
+    int cols = solve_chunk_cols(p, nrhs, op.restart);
+    MW_CHECK(cols >= 1, MW_ENOMEM, "HBM budget leaves no room for the Krylov basis of one column");
+    bool numeric = false, noconv = false;
+    int chunks = 0;
+    for (int c0 = 0; c0 < nrhs; c0 += cols) {
+      int nc = std::min(cols, nrhs - c0);
+      std::vector<int32_t> it(nc);
+      std::vector<double> rr(nc);
+      ChunkResult r = gmres_chunk(p, (const double2*)B + c0, nrhs, (double2*)X + c0, nrhs, nc, op, it.data(), rr.data());
+      chunks++;
+      numeric |= r.numeric;
+      for (int k = 0; k < nc; ++k) {
+        if (info && info->iters) info->iters[c0 + k] = it[k];
+        if (info && info->relres) info->relres[c0 + k] = rr[k];
+        if (!(rr[k] <= op.tol)) noconv = true;
+      }
+      if (info) { info->max_iters = std::max(info->max_iters, r.max_iters); info->cycles = std::max(info->cycles, r.cycles); }
+    }
+    if (info) { info->chunks = chunks; info->t_solve = now_s() - t0; }
+    MW_CHECK(!numeric, MW_ENUMERIC, "NaN or Inf in a GMRES residual");
+    MW_CHECK(!noconv, MW_ENOCONV, "GMRES did not reach the tolerance within maxit");
+  });
+}
+
+mw_status mw_s_matrix(mw_problem* p, int32_t nrx, const int32_t* rx, int32_t ntx, const void* U, void* S) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(nrx >= 0 && ntx >= 0, MW_EINVAL, "sizes");
+    if (nrx == 0 || ntx == 0) return;
+    MW_CHECK(rx && U && S, MW_EINVAL, "NULL argument");
+    for (int i = 0; i < nrx; ++i) MW_CHECK(rx[i] >= 0 && rx[i] < (int)p->ports.size(), MW_EINVAL, "port index out of range");
+    DeviceGuard dg(p->ctx->device);
+    hipStream_t st = p->ctx->stream;
+    int32_t* d = (int32_t*)p->w_int.get(p->ctx, (int64_t)std::max(nrx, 1) * 4 + 16);
+    MW_HIP(hipMemcpyAsync(d, rx, nrx * 4, hipMemcpyHostToDevice, st));
+    launch_s_matrix(p->dp, nrx, d, ntx, (const double2*)U, ntx, (double2*)S, st);
+    sync(p->ctx);
+  });
+}
+
+mw_status mw_port_norms(mw_problem* p, double* nu) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(nu != nullptr, MW_EINVAL, "nu is NULL");
+    if (p->ports.empty()) return;
+    DeviceGuard dg(p->ctx->device);
+    MW_HIP(hipMemcpyAsync(nu, p->dp.nu, p->ports.size() * 8, hipMemcpyDeviceToHost, p->ctx->stream));
+    sync(p->ctx);
+  });
+}
+
+mw_status mw_adjoint_gradient(mw_problem* p, int32_t ntx, const int32_t* tx, int32_t nrx, const int32_t* rx,
+                              const void* U, const void* gS, void* grad_eps, const mw_solve_opts* o,
+                              mw_solve_info* info) {
+  (void)tx;
+  mw_status s = guard([&] {
+    check_prob(p);
+    MW_CHECK(ntx >= 1 && nrx >= 1 && rx && U && gS && grad_eps, MW_EINVAL, "NULL argument or empty port set");
+    for (int i = 0; i < nrx; ++i) MW_CHECK(rx[i] >= 0 && rx[i] < (int)p->ports.size(), MW_EINVAL, "port index out of range");
+  });
+  if (s != MW_OK) return s;
+  mw_ctx* c = p->ctx;
+  const int64_t n = p->T.n();
+  DevBuf lam, F, drx;
+  s = guard([&] {
+    DeviceGuard dg(c->device);
+    hipStream_t st = c->stream;
+    lam = dalloc(c, n * ntx * 16);
+    F = dalloc(c, n * ntx * 16);
+    drx = dalloc(c, (int64_t)nrx * 4);
+    MW_HIP(hipMemcpyAsync(drx.p, rx, nrx * 4, hipMemcpyHostToDevice, st));
+    launch_zero(lam.as<double2>(), n * ntx, st);
+    launch_adjoint_rhs(p->dp, nrx, drx.as<int32_t>(), ntx, (const double2*)gS, lam.as<double2>(), ntx, st);
+    sync(c);
+  });
+  if (s != MW_OK) return s;
+  s = mw_solve(p, ntx, lam.p, F.p, o, info);
+  if (s != MW_OK) return s;
+  return guard([&] {
+    DeviceGuard dg(c->device);
+    launch_gradient(p->dm, (const double2*)U, F.as<double2>(), ntx, ntx, p->k0, (double2*)grad_eps, c->stream);
+    sync(c);
+  });
+}
+
+mw_status mw_misfit_gradient(mw_problem* p, int32_t ntx, const int32_t* tx, int32_t nrx, const int32_t* rx,
+                             const void* S_meas, double* J, void* S_sim, void* grad_eps, const mw_solve_opts* o) {
+  mw_status s = guard([&] {
+    check_prob(p);
+    MW_CHECK(ntx >= 1 && nrx >= 1 && tx && rx && S_meas && J && S_sim && grad_eps, MW_EINVAL, "NULL argument");
+  });
+  if (s != MW_OK) return s;
+  mw_ctx* c = p->ctx;
+  const int64_t n = p->T.n();
+  DevBuf Bb, Ub, gS, dJ;
+  s = guard([&] {
+    Bb = dalloc(c, n * ntx * 16);
+    Ub = dalloc(c, n * ntx * 16);
+    gS = dalloc(c, (int64_t)nrx * ntx * 16);
+    dJ = dalloc(c, 8);
+  });
+  if (s != MW_OK) return s;
+  if ((s = mw_rhs_ports(p, ntx, tx, Bb.p)) != MW_OK) return s;
+  if ((s = mw_solve(p, ntx, Bb.p, Ub.p, o, nullptr)) != MW_OK) return s;
+  if ((s = mw_s_matrix(p, nrx, rx, ntx, Ub.p, S_sim)) != MW_OK) return s;
+  s = guard([&] {
+    DeviceGuard dg(c->device);
+    launch_misfit((const double2*)S_sim, (const double2*)S_meas, (int64_t)nrx * ntx, gS.as<double2>(), dJ.as<double>(),
+                  c->stream);
+    MW_HIP(hipMemcpyAsync(J, dJ.p, 8, hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+  });
+  if (s != MW_OK) return s;
+  return mw_adjoint_gradient(p, ntx, tx, nrx, rx, Ub.p, gS.p, grad_eps, o, nullptr);
+}
+
+}  // extern "C"

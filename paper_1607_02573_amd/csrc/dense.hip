@@ -1,0 +1,499 @@
+// Batched dense complex LU with partial pivoting and triangular solves of the
+// ORAS subdomain matrices B_i (paper Section 3: M^-1 = sum R_i^T D_i B_i^-1 R_i,
+// each B_i factored once; applying B_i^-1 to many vectors is one forward
+// elimination and one backward substitution).
+//
+// Layout: B_i is row-major n_pad x n_pad (n_pad a multiple of 64) at
+// F + fac_off[i]; every kernel is batched over the subdomains (grid.y or
+// grid.x = subdomain) and skips the parts beyond each subdomain's size.
+//
+// LU (right-looking, LAPACK-style row interchanges on the whole row):
+//   for each 64-wide panel k:
+//     for each 8-wide sub-panel c of it:
+//       k_lu_panel: pivot search (max |re|+|im|, lowest row on ties), row
+//         swap across the 64-wide panel, scaling, rank-1 updates inside the
+//         sub-panel, unit-lower solve of the sub-panel's U rows for the rest
+//         of the 64-wide panel;
+//       GEMM: trailing rows x rest of the 64-wide panel -= L * U  (K = 8)
+//     k_laswp: the panel's interchanges on the columns outside it
+//     leaf TRSM: U12 = L11^-1 A12
+//     GEMM: A22 -= L21 U12 (K = 64)
+// P_i B_i = L_i U_i; P_i is folded into the restriction gather index, so
+// the solves need no interchanges.
+//
+// Complex GEMM on MFMA: with A stored as interleaved (re, im) along K, a real
+// 16x16x4 MFMA over two complex K entries gives Re(C) when B's fragment is
+// (Re b, -Im b) and Im(C) when it is (Im b, Re b); two MFMAs per 2 complex K,
+// no wasted work.  FP32 path: v_mfma_f32_16x16x4f32; FP64: v_mfma_f64_16x16x4f64.
+#include "kernels.hpp"
+
+namespace mw {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <class R> struct Mf;
+template <> struct Mf<float> {
+  using acc = floatx4;
+  static __device__ inline acc mfma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // output element r of lane l sits at row 4*(l/16) + r, column l%16
+  static __device__ inline int out_row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+template <> struct Mf<double> {
+  using acc = doublex4;
+  static __device__ inline acc mfma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // output element r of lane l sits at row (l/16) + 4*r, column l%16
+  static __device__ inline int out_row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+
+constexpr int TB = 64;    // output tile (complex) per workgroup: TB x TB
+constexpr int BK = 16;    // complex K per LDS stage
+constexpr int NB = 64;    // LU panel width and TRSM leaf size
+constexpr int W0 = 8;     // LU sub-panel width
+
+// C[M x N] (ldc) = (OVERWRITE ? 0 : C) - A[M x K] (lda) * B[K x N] (ldb), for the
+// output tile (tm, tn); 256 threads = 4 waves, each a 32 x 32 complex quadrant.
+template <class R, bool OVERWRITE>
+__device__ inline void gemm_tile(const typename cplx<R>::t* __restrict__ A, int64_t lda,
+                                 const typename cplx<R>::t* __restrict__ B, int64_t ldb,
+                                 typename cplx<R>::t* __restrict__ Cm, int64_t ldc, int M, int N, int K,
+                                 int tm, int tn) {
+  using C = typename cplx<R>::t;
+  using acc_t = typename Mf<R>::acc;
+  __shared__ R As[TB][2 * BK + 1];
+  __shared__ C Bs[BK][TB + 1];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, kq = lane >> 4;
+  const int row0 = tm * TB, col0 = tn * TB;
+  acc_t accr[2][2], acci[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int r = 0; r < 4; ++r) { accr[a][b][r] = 0; acci[a][b][r] = 0; }
+
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    // A tile: TB rows x BK complex; consecutive threads -> consecutive k in a row
+    for (int e = 0; e < 4; ++e) {
+      int idx = tid + e * 256;
+      int r = idx >> 4, kc = idx & 15;
+      int gr = row0 + r, gk = k0 + kc;
+      C v;
+      v.x = 0; v.y = 0;
+      if (gr < M && gk < K) v = A[(int64_t)gr * lda + gk];
+      As[r][2 * kc] = v.x;
+      As[r][2 * kc + 1] = v.y;
+    }
+    // B tile: BK rows x TB complex; consecutive threads -> consecutive columns
+    for (int e = 0; e < 4; ++e) {
+      int idx = tid + e * 256;
+      int r = idx >> 6, c = idx & 63;
+      int gk = k0 + r, gc = col0 + c;
+      C v;
+      v.x = 0; v.y = 0;
+      if (gk < K && gc < N) v = B[(int64_t)gk * ldb + gc];
+      Bs[r][c] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 2) {
+      R a[2], br[2], bi[2];
+#pragma unroll
+      for (int bi_ = 0; bi_ < 2; ++bi_) a[bi_] = As[wm * 32 + bi_ * 16 + li][2 * kk + kq];
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        C b = Bs[kk + (kq >> 1)][wn * 32 + bj * 16 + li];
+        bool odd = kq & 1;
+        br[bj] = odd ? -b.y : b.x;
+        bi[bj] = odd ? b.x : b.y;
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          accr[x][y] = Mf<R>::mfma(a[x], br[y], accr[x][y]);
+          acci[x][y] = Mf<R>::mfma(a[x], bi[y], acci[x][y]);
+        }
+    }
+    __syncthreads();
+  }
+  // epilogue
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int gr = row0 + wm * 32 + x * 16 + Mf<R>::out_row(lane, r);
+        int gc = col0 + wn * 32 + y * 16 + li;
+        if (gr < M && gc < N) {
+          C* p = Cm + (int64_t)gr * ldc + gc;
+          C o;
+          if (OVERWRITE) { o.x = -accr[x][y][r]; o.y = -acci[x][y][r]; }
+          else { o = *p; o.x -= accr[x][y][r]; o.y -= acci[x][y][r]; }
+          *p = o;
+        }
+      }
+}
+
+// LU-internal update of subdomain blockIdx.y:
+// F[r0:np, c0:min(c1,np)] -= F[r0:np, k0:k1] * F[k0:k1, c0:min(c1,np)]
+template <class R>
+__global__ void __launch_bounds__(256) k_gemm_lu(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
+                                                 const int32_t* __restrict__ n_pad, int r0, int k0, int k1,
+                                                 int c0, int c1) {
+  using C = typename cplx<R>::t;
+  int i = blockIdx.y;
+  int np = n_pad[i];
+  int M = np - r0;
+  int N = min(c1, np) - c0;
+  if (M <= 0 || N <= 0 || k1 > np) return;
+  int tiles_n = (N + TB - 1) / TB;
+  int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  if (tm * TB >= M) return;
+  C* Fi = F + fac_off[i];
+  gemm_tile<R, false>(Fi + (int64_t)r0 * np + k0, np, Fi + (int64_t)k0 * np + c0, np,
+                      Fi + (int64_t)r0 * np + c0, np, M, N, k1 - k0, tm, tn);
+}
+
+// Triangular-solve update on the local multi-vector of subdomain blockIdx.y:
+// Y[r0:min(r1,np)] -= F[r0:min(r1,np), k0:min(k1,np)] * Y[k0:min(k1,np)]
+template <class R>
+__global__ void __launch_bounds__(256) k_gemm_x(const typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
+                                                const int32_t* __restrict__ n_pad,
+                                                const int64_t* __restrict__ loc_off, typename cplx<R>::t* Y,
+                                                int64_t ld, int ncols, int r0, int r1, int k0, int k1) {
+  using C = typename cplx<R>::t;
+  int i = blockIdx.y;
+  int np = n_pad[i];
+  int M = min(r1, np) - r0;
+  int K = min(k1, np) - k0;
+  if (M <= 0 || K <= 0) return;
+  int tiles_n = (ncols + TB - 1) / TB;
+  int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  if (tm * TB >= M) return;
+  const C* Fi = F + fac_off[i];
+  C* Yi = Y + loc_off[i] * ld;
+  gemm_tile<R, false>(Fi + (int64_t)r0 * np + k0, np, Yi + (int64_t)k0 * ld, ld, Yi + (int64_t)r0 * ld, ld, M,
+                      ncols, K, tm, tn);
+}
+
+// ---------------------------------------------------------------- pivot reduction
+struct Piv { double v; int idx; };
+__device__ inline Piv piv_max(Piv a, Piv b) {
+  if (b.v > a.v || (b.v == a.v && b.idx < a.idx)) return b;
+  return a;
+}
+
+// One workgroup per subdomain: factor columns [c, c+W0) of rows [c, np),
+// row interchanges across the 64-wide panel [k, k+NB), then the unit-lower
+// solve of rows [c, c+W0) for the panel columns [c+W0, k+NB).
+template <class R>
+__global__ void __launch_bounds__(256) k_lu_panel(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
+                                                  const int32_t* __restrict__ n_pad,
+                                                  const int64_t* __restrict__ loc_off, int32_t* ipiv,
+                                                  int32_t* info, int c, int k) {
+  using C = typename cplx<R>::t;
+  __shared__ Piv red[4];
+  __shared__ C prow[W0];
+  int i = blockIdx.x;
+  int np = n_pad[i];
+  if (c >= np) return;
+  int kend = min(k + NB, np);
+  C* Fi = F + fac_off[i];
+  int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int j = 0; j < W0; ++j) {
+    int col = c + j;
+    Piv best{-1.0, 0x7fffffff};
+    for (int r = col + tid; r < np; r += 256) {
+      C v = Fi[(int64_t)r * np + col];
+      double a = fabs((double)v.x) + fabs((double)v.y);
+      if (a > best.v) { best.v = a; best.idx = r; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      Piv o;
+      o.v = __shfl_xor(best.v, off);
+      o.idx = __shfl_xor(best.idx, off);
+      best = piv_max(best, o);
+    }
+    if (lane == 0) red[wave] = best;
+    __syncthreads();
+    best = piv_max(piv_max(red[0], red[1]), piv_max(red[2], red[3]));
+    int p = best.idx;
+    bool zero = !(best.v > 0.0);
+    if (zero) p = col;
+    if (tid == 0) {
+      ipiv[loc_off[i] + col] = p;
+      if (zero && info[i] == 0) info[i] = col + 1;
+    }
+    if (p != col)
+      for (int cc = k + tid; cc < kend; cc += 256) {
+        C t0 = Fi[(int64_t)col * np + cc];
+        Fi[(int64_t)col * np + cc] = Fi[(int64_t)p * np + cc];
+        Fi[(int64_t)p * np + cc] = t0;
+      }
+    __syncthreads();
+    if (tid < W0) prow[tid] = Fi[(int64_t)col * np + c + tid];
+    __syncthreads();
+    C pv = prow[j];
+    C inv;
+    inv.x = 0;
+    inv.y = 0;
+    if (!zero) inv = cinv(pv);
+    for (int r = col + 1 + tid; r < np; r += 256) {
+      C* rowp = Fi + (int64_t)r * np;
+      C l = cmul(rowp[col], inv);
+      rowp[col] = l;
+      for (int cc = j + 1; cc < W0; ++cc) rowp[c + cc] = csub(rowp[c + cc], cmul(l, prow[cc]));
+    }
+    __syncthreads();
+  }
+  // U rows of the sub-panel for the remaining panel columns (unit lower solve)
+  for (int cc = c + W0 + tid; cc < kend; cc += 256) {
+    C x[W0];
+    for (int r = 0; r < W0; ++r) x[r] = Fi[(int64_t)(c + r) * np + cc];
+    for (int r = 1; r < W0; ++r)
+      for (int s = 0; s < r; ++s) x[r] = csub(x[r], cmul(Fi[(int64_t)(c + r) * np + c + s], x[s]));
+    for (int r = 1; r < W0; ++r) Fi[(int64_t)(c + r) * np + cc] = x[r];
+  }
+}
+
+// interchanges of the panel [k, k+NB) on the columns outside it
+template <class R>
+__global__ void k_laswp(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
+                        const int32_t* __restrict__ n_pad, const int64_t* __restrict__ loc_off,
+                        const int32_t* __restrict__ ipiv, int k) {
+  using C = typename cplx<R>::t;
+  int i = blockIdx.y;
+  int np = n_pad[i];
+  if (k >= np) return;
+  int kend = min(k + NB, np);
+  int ncol = np - (kend - k);
+  int cc = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cc >= ncol) return;
+  if (cc >= k) cc += kend - k;
+  C* Fi = F + fac_off[i];
+  const int32_t* pv = ipiv + loc_off[i];
+  for (int j = k; j < kend; ++j) {
+    int p = pv[j];
+    if (p != j) {
+      C t0 = Fi[(int64_t)j * np + cc];
+      Fi[(int64_t)j * np + cc] = Fi[(int64_t)p * np + cc];
+      Fi[(int64_t)p * np + cc] = t0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- leaf TRSM
+// Solve T X = X in place for the NB x NB triangle T (unit lower, or upper with
+// its diagonal) and an NB-row block X with `ncols` columns.  Each 16-lane
+// group owns one column and holds 4 of its rows in registers; the solution
+// entries are broadcast by lane shuffles, the triangle sits in LDS (packed).
+template <class R, bool UPPER>
+__device__ inline void trsm_leaf(const typename cplx<R>::t* __restrict__ T, int64_t ldt,
+                                 typename cplx<R>::t* __restrict__ X, int64_t ldx, int ncols, int col0) {
+  using C = typename cplx<R>::t;
+  __shared__ C tri[NB * (NB + 1) / 2];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < NB * NB; e += 256) {
+    int r = e / NB, s = e % NB;
+    if (UPPER ? (s >= r) : (s <= r)) {
+      int idx = UPPER ? (s * (s + 1) / 2 + r) : (r * (r + 1) / 2 + s);
+      tri[idx] = T[(int64_t)r * ldt + s];
+    }
+  }
+  __syncthreads();
+  const int q = tid & 15;
+  const int colx = col0 + (tid >> 4);
+  const bool live = colx < ncols;
+  C v[4];
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl) {
+    v[sl].x = 0; v[sl].y = 0;
+    if (live) v[sl] = X[(int64_t)(q + 16 * sl) * ldx + colx];
+  }
+  if (!UPPER) {
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      const int owner = r & 15, slot = r >> 4;
+      C xr;
+      xr.x = __shfl(v[slot].x, owner, 16);
+      xr.y = __shfl(v[slot].y, owner, 16);
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl) {
+        int s = q + 16 * sl;
+        if (s > r) v[sl] = csub(v[sl], cmul(tri[s * (s + 1) / 2 + r], xr));
+      }
+    }
+  } else {
+#pragma unroll
+    for (int r = NB - 1; r >= 0; --r) {
+      const int owner = r & 15, slot = r >> 4;
+      C xr;
+      xr.x = __shfl(v[slot].x, owner, 16);
+      xr.y = __shfl(v[slot].y, owner, 16);
+      xr = cmul(xr, cinv(tri[r * (r + 1) / 2 + r]));
+      if (q == owner) v[slot] = xr;
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl) {
+        int s = q + 16 * sl;
+        if (s < r) v[sl] = csub(v[sl], cmul(tri[r * (r + 1) / 2 + s], xr));
+      }
+    }
+  }
+  if (live) {
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl) X[(int64_t)(q + 16 * sl) * ldx + colx] = v[sl];
+  }
+}
+
+// LU: U12 = L11^-1 A12 for the panel k (rows [k, k+NB), columns [k+NB, np))
+template <class R>
+__global__ void __launch_bounds__(256) k_trsm_panel(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
+                                                    const int32_t* __restrict__ n_pad, int k) {
+  int i = blockIdx.y;
+  int np = n_pad[i];
+  int c0 = k + NB;
+  if (c0 >= np) return;
+  int ncols = np - c0;
+  int col0 = blockIdx.x * 16;
+  if (col0 >= ncols) return;
+  auto* Fi = F + fac_off[i];
+  trsm_leaf<R, false>(Fi + (int64_t)k * np + k, np, Fi + (int64_t)k * np + c0, np, ncols, col0);
+}
+
+// solve: leaf block b of L (UPPER = false) or U (UPPER = true) on Y
+template <class R, bool UPPER>
+__global__ void __launch_bounds__(256) k_trsm_x(const typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
+                                                const int32_t* __restrict__ n_pad,
+                                                const int64_t* __restrict__ loc_off, typename cplx<R>::t* Y,
+                                                int64_t ld, int ncols, int r0) {
+  int i = blockIdx.y;
+  int np = n_pad[i];
+  if (r0 >= np) return;
+  int col0 = blockIdx.x * 16;
+  if (col0 >= ncols) return;
+  const auto* Fi = F + fac_off[i];
+  trsm_leaf<R, UPPER>(Fi + (int64_t)r0 * np + r0, np, Y + (loc_off[i] + r0) * ld, ld, ncols, col0);
+}
+
+// restriction gather index with the row interchanges folded in:
+// ridx[l] = sub_dof[perm[l]], perm = interchanges applied to the identity
+__global__ void __launch_bounds__(256) k_build_perm(const int32_t* __restrict__ n_pad,
+                                                    const int64_t* __restrict__ loc_off,
+                                                    const int32_t* __restrict__ ipiv,
+                                                    const int32_t* __restrict__ sub_dof, int32_t* ridx) {
+  __shared__ int32_t perm[8192];
+  int i = blockIdx.x;
+  int np = n_pad[i];
+  int64_t o = loc_off[i];
+  for (int l = threadIdx.x; l < np; l += blockDim.x) perm[l] = l;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int j = 0; j < np; ++j) {
+      int p = ipiv[o + j];
+      int t = perm[j];
+      perm[j] = perm[p];
+      perm[p] = t;
+    }
+  __syncthreads();
+  for (int l = threadIdx.x; l < np; l += blockDim.x) ridx[o + l] = sub_dof[o + perm[l]];
+}
+
+template <class C> struct RealOf;
+template <> struct RealOf<float2> { using t = float; };
+template <> struct RealOf<double2> { using t = double; };
+
+template <class C>
+void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st) {
+  using R = typename RealOf<C>::t;
+  MW_CHECK(d.max_pad <= 8192, MW_EINVAL, "subdomain too large for the dense factorisation (n_i > 8192)");
+  const int maxp = d.max_pad;
+  for (int k = 0; k < maxp; k += NB) {
+    for (int c = k; c < k + NB; c += W0) {
+      k_lu_panel<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, c, k);
+      MW_LAUNCH_CHECK();
+      int r0 = c + W0, c1 = k + NB;
+      if (r0 < c1) {
+        int M = maxp - r0, N = c1 - r0;
+        unsigned tiles = (unsigned)(ceil_div(M, TB) * ceil_div(N, TB));
+        k_gemm_lu<R><<<dim3(tiles, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, r0, c, c + W0, r0, c1);
+        MW_LAUNCH_CHECK();
+      }
+    }
+    int ncol = maxp;  // upper bound of columns outside the panel
+    k_laswp<R><<<dim3((unsigned)ceil_div(ncol, 256), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off,
+                                                                             d.ipiv, k);
+    MW_LAUNCH_CHECK();
+    int c0 = k + NB;
+    if (c0 < maxp) {
+      k_trsm_panel<R><<<dim3((unsigned)ceil_div(maxp - c0, 16), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, k);
+      MW_LAUNCH_CHECK();
+      int M = maxp - c0;
+      unsigned tiles = (unsigned)(ceil_div(M, TB) * ceil_div(M, TB));
+      k_gemm_lu<R><<<dim3(tiles, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, c0, k, k + NB, c0, maxp);
+      MW_LAUNCH_CHECK();
+    }
+  }
+  k_build_perm<<<d.nsub, 256, 0, st>>>(d.n_pad, d.loc_off, d.ipiv, d.sub_dof, d.ridx);
+  MW_LAUNCH_CHECK();
+}
+
+template <class R>
+static void fwd_rec(const DeviceDecomp& d, const typename cplx<R>::t* F, typename cplx<R>::t* Y, int ncols,
+                    int64_t ld, int b0, int b1, hipStream_t st) {
+  if (b1 - b0 == 1) {
+    k_trsm_x<R, false><<<dim3((unsigned)ceil_div(ncols, 16), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad,
+                                                                                      d.loc_off, Y, ld, ncols,
+                                                                                      b0 * NB);
+    MW_LAUNCH_CHECK();
+    return;
+  }
+  int mid = b0 + (b1 - b0) / 2;
+  fwd_rec<R>(d, F, Y, ncols, ld, b0, mid, st);
+  int M = (b1 - mid) * NB;
+  unsigned tiles = (unsigned)(ceil_div(M, TB) * ceil_div(ncols, TB));
+  k_gemm_x<R><<<dim3(tiles, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, Y, ld, ncols, mid * NB,
+                                                   b1 * NB, b0 * NB, mid * NB);
+  MW_LAUNCH_CHECK();
+  fwd_rec<R>(d, F, Y, ncols, ld, mid, b1, st);
+}
+
+template <class R>
+static void bwd_rec(const DeviceDecomp& d, const typename cplx<R>::t* F, typename cplx<R>::t* Y, int ncols,
+                    int64_t ld, int b0, int b1, hipStream_t st) {
+  if (b1 - b0 == 1) {
+    k_trsm_x<R, true><<<dim3((unsigned)ceil_div(ncols, 16), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad,
+                                                                                     d.loc_off, Y, ld, ncols,
+                                                                                     b0 * NB);
+    MW_LAUNCH_CHECK();
+    return;
+  }
+  int mid = b0 + (b1 - b0) / 2;
+  bwd_rec<R>(d, F, Y, ncols, ld, mid, b1, st);
+  int M = (mid - b0) * NB;
+  unsigned tiles = (unsigned)(ceil_div(M, TB) * ceil_div(ncols, TB));
+  k_gemm_x<R><<<dim3(tiles, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, Y, ld, ncols, b0 * NB,
+                                                   mid * NB, mid * NB, b1 * NB);
+  MW_LAUNCH_CHECK();
+  bwd_rec<R>(d, F, Y, ncols, ld, b0, mid, st);
+}
+
+template <class C>
+void lu_solve_batched(const DeviceDecomp& d, const C* F, C* Y, int ncols, int64_t ld, hipStream_t st) {
+  using R = typename RealOf<C>::t;
+  int nblk = d.max_pad / NB;
+  fwd_rec<R>(d, F, Y, ncols, ld, 0, nblk, st);
+  bwd_rec<R>(d, F, Y, ncols, ld, 0, nblk, st);
+}
+
+template void lu_factor_batched<float2>(const DeviceDecomp&, float2*, hipStream_t);
+template void lu_factor_batched<double2>(const DeviceDecomp&, double2*, hipStream_t);
+template void lu_solve_batched<float2>(const DeviceDecomp&, const float2*, float2*, int, int64_t, hipStream_t);
+template void lu_solve_batched<double2>(const DeviceDecomp&, const double2*, double2*, int, int64_t, hipStream_t);
+
+}  // namespace mw

@@ -1,0 +1,68 @@
+// Host-only inspection of the edge topology and the overlapping
+// decomposition (no device needed): lets the host logic be checked against
+// an independent implementation on machines without a GPU.
+#include <cstring>
+#include <numeric>
+
+#include "common.hpp"
+
+using namespace mw;
+
+#include <functional>
+
+static thread_local std::string g_host_err;
+
+static mw_status hguard(const std::function<void()>& f) {
+  try {
+    f();
+    return MW_OK;
+  } catch (const Error& e) {
+    g_host_err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    g_host_err = e.what();
+    return MW_EINVAL;
+  }
+}
+
+extern "C" {
+
+const char* mw_host_last_error(void) { return g_host_err.c_str(); }
+
+mw_status mw_host_topology(const mw_mesh* mesh, int64_t* n, int64_t* nnz, int64_t* n_edges, int32_t* edge_of_dof,
+                           int64_t* row_ptr, int32_t* col) {
+  return hguard([&] {
+    MW_CHECK(mesh && n && nnz && n_edges, MW_EINVAL, "NULL argument");
+    Topology T;
+    build_topology(*mesh, T);
+    *n = T.n();
+    *nnz = (int64_t)T.col.size();
+    *n_edges = T.ne();
+    if (edge_of_dof) std::copy(T.free_edge.begin(), T.free_edge.end(), edge_of_dof);
+    if (row_ptr) std::copy(T.row_ptr.begin(), T.row_ptr.end(), row_ptr);
+    if (col) std::copy(T.col.begin(), T.col.end(), col);
+  });
+}
+
+mw_status mw_host_decomposition(const mw_mesh* mesh, const int32_t* tet_part, int32_t n_sub, int32_t overlap,
+                                int32_t* n_loc, int64_t* n_faces, int32_t* sub_dof, double* D) {
+  return hguard([&] {
+    MW_CHECK(mesh && tet_part && n_loc, MW_EINVAL, "NULL argument");
+    Topology T;
+    build_topology(*mesh, T);
+    Decomposition Dc;
+    build_decomposition(T, tet_part, n_sub, overlap, 64, Dc);
+    int64_t w = 0;
+    for (int32_t i = 0; i < n_sub; ++i) {
+      n_loc[i] = Dc.n_loc[i];
+      if (n_faces) n_faces[i] = Dc.lf_off[i + 1] - Dc.lf_off[i];
+      for (int32_t l = 0; l < Dc.n_loc[i]; ++l) {
+        if (sub_dof) sub_dof[w] = Dc.sub_dof[Dc.loc_off[i] + l];
+        if (D) D[w] = Dc.D[Dc.loc_off[i] + l];
+        ++w;
+      }
+    }
+  });
+}
+
+}  // extern "C"

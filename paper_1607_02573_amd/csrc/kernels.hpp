@@ -1,0 +1,144 @@
+// Device data views and kernel launchers of the library (all HIP, gfx950).
+#pragma once
+
+#include "common.hpp"
+
+namespace mw {
+
+// Mesh, operator pattern and per-row assembly lists on the device.
+struct DeviceMesh {
+  int64_t nv = 0, nt = 0, n = 0, nbf = 0, nnz = 0;
+  const double* xyz = nullptr;
+  const int32_t* tet = nullptr;
+  const int32_t* t2e = nullptr;
+  const int32_t* dof = nullptr;
+  const int32_t* bface = nullptr;
+  const int32_t* bf2e = nullptr;
+  const double2* fbeta = nullptr;   // i*beta coefficient source per boundary face (beta)
+  const int64_t* row_ptr = nullptr;
+  const int32_t* col = nullptr;
+  const int64_t* rt_ptr = nullptr;
+  const int32_t* rt = nullptr;
+  const int64_t* rf_ptr = nullptr;
+  const int32_t* rf = nullptr;
+};
+
+struct PortDev {
+  double2 beta;
+  double radius, theta, width;
+  double pol[3];
+};
+
+// Sparse port projections: for port k, entries [port_ptr[k], port_ptr[k+1])
+// hold distinct unknowns ent_dof[] with values pval[]; each entry sums the
+// (face, local edge) contributions ent_fq[ent_ptr[e] .. ent_ptr[e+1]).
+struct DevicePorts {
+  int nports = 0;
+  int64_t nent = 0;
+  const PortDev* ports = nullptr;
+  const int64_t* port_ptr = nullptr;
+  const int32_t* ent_dof = nullptr;
+  const int32_t* ent_port = nullptr;
+  const int64_t* ent_ptr = nullptr;
+  const int32_t* ent_fq = nullptr;
+  const int64_t* pf_ptr = nullptr;   // faces of each port
+  const int32_t* pf = nullptr;
+  double* pval = nullptr;
+  double* nu = nullptr;
+};
+
+struct DeviceDecomp {
+  int nsub = 0;
+  int max_pad = 0;
+  int64_t sum_pad = 0;
+  const int64_t* fac_off = nullptr;
+  const int64_t* loc_off = nullptr;
+  const int32_t* n_loc = nullptr;
+  const int32_t* n_pad = nullptr;
+  const int64_t* lt_off = nullptr;
+  const int32_t* lt_tet = nullptr;
+  const int32_t* lt_loc = nullptr;
+  const int64_t* lf_off = nullptr;
+  const int32_t* lf_vert = nullptr;
+  const int32_t* lf_owner = nullptr;
+  const int32_t* lf_kind = nullptr;
+  const int32_t* lf_loc = nullptr;
+  const int64_t* rtl_ptr = nullptr;
+  const int32_t* rtl = nullptr;
+  const int64_t* rfl_ptr = nullptr;
+  const int32_t* rfl = nullptr;
+  const int32_t* sub_dof = nullptr;
+  const double* D = nullptr;
+  const int64_t* cp_ptr = nullptr;
+  const int64_t* cp_row = nullptr;
+  int32_t* ipiv = nullptr;      // [sum_pad] pivot row of each column (subdomain-relative)
+  int32_t* ridx = nullptr;      // [sum_pad] restriction gather index after pivoting (-1 padding)
+  int32_t* info = nullptr;      // [nsub] first zero-pivot column + 1, 0 if none
+};
+
+// ---- assembly (assemble.hip)
+void launch_element_matrices(const DeviceMesh& m, const double2* eps, double k0, double2* E, hipStream_t st);
+void launch_gather_csr(const DeviceMesh& m, const double2* E, double2* val, hipStream_t st);
+template <class C>
+void launch_fill_local(const DeviceMesh& m, const DeviceDecomp& d, const double2* E, const double2* eps,
+                       double k0, C* F, hipStream_t st);
+void launch_port_setup(const DeviceMesh& m, const DevicePorts& P, hipStream_t st);
+void launch_rhs_ports(const DevicePorts& P, int ntx, const int32_t* tx_dev, double2* B, int64_t ldb,
+                      hipStream_t st);
+void launch_locate(const DeviceMesh& m, const double* pts, int np, int* found, hipStream_t st);
+void launch_rhs_dipoles(const DeviceMesh& m, const double* pts, const double* dirs, const int* found, int np,
+                        double2* B, int64_t ldb, hipStream_t st);
+void launch_s_matrix(const DevicePorts& P, int nrx, const int32_t* rx_dev, int ntx, const double2* U,
+                     int64_t ldu, double2* S, hipStream_t st);
+void launch_adjoint_rhs(const DevicePorts& P, int nrx, const int32_t* rx_dev, int ntx, const double2* gS,
+                        double2* L, int64_t ldl, hipStream_t st);
+void launch_gradient(const DeviceMesh& m, const double2* U, const double2* F, int64_t ld, int ncol, double k0,
+                     double2* grad, hipStream_t st);
+
+// ---- dense subdomain algebra (dense.hip)
+// Factor every B_i in place: P_i B_i = L_i U_i (partial pivoting, unit L),
+// then build the pivoted restriction index.  C = float2 or double2.
+template <class C>
+void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st);
+// Y_i = U_i^-1 L_i^-1 Y_i in place on the local multi-vector (rows
+// loc_off[i] .. +n_pad[i], ncols columns, leading dimension ld).
+template <class C>
+void lu_solve_batched(const DeviceDecomp& d, const C* F, C* Y, int ncols, int64_t ld, hipStream_t st);
+
+// ---- Krylov and vector kernels (krylov.hip)
+void launch_spmm(const DeviceMesh& m, const double2* val, const double2* X, int64_t ldx, double2* Y,
+                 int64_t ldy, int ncols, const double2* Bsub, int64_t ldb, hipStream_t st);
+template <class C>
+void launch_restrict(const DeviceDecomp& d, const double2* V, int64_t ldv, int ncols, C* Y, int64_t ldy,
+                     hipStream_t st);
+template <class C>
+void launch_prolong(const DeviceDecomp& d, int64_t n, const C* Y, int64_t ldy, int ncols, double2* Z,
+                    int64_t ldz, hipStream_t st);
+// column sums over rows in fixed-size row chunks, then in chunk order
+int64_t reduce_chunks(int64_t n);
+void launch_colnorm2_partial(const double2* V, int64_t n, int64_t ld, int ncols, double* part, hipStream_t st);
+void launch_sum_chunks(const double* part, int64_t nchunk, int64_t width, double* out, hipStream_t st);
+void launch_dots_partial(const double2* V, int64_t vstride, int kcount, const double2* w, int64_t n, int64_t ld,
+                         int ncols, const int32_t* act, double2* part, hipStream_t st);
+void launch_sum_chunks_c(const double2* part, int64_t nchunk, int64_t width, double2* out, hipStream_t st);
+void launch_cgs_update(const double2* V, int64_t vstride, int kcount, const double2* h, double2* w, int64_t n,
+                       int64_t ld, int ncols, const int32_t* act, double* norm_part, hipStream_t st);
+void launch_scale_cols(double2* w, int64_t n, int64_t ld, int ncols, const double* nrm, const int32_t* act,
+                       hipStream_t st);
+void launch_givens(int j, int m, int ncols, const double2* h1, const double2* h2, const double* hn2,
+                   double2* H, double* cs, double2* sn, double2* g, int32_t* kdim, int32_t* act,
+                   double* resid, const double* bnorm, double tol, hipStream_t st);
+void launch_backsolve(int m, int ncols, const double2* H, const double2* g, const int32_t* kdim, double2* y,
+                      hipStream_t st);
+void launch_combine(const double2* V, int64_t vstride, int m, const double2* y, const int32_t* kdim,
+                    double2* u, int64_t n, int64_t ld, int ncols, hipStream_t st);
+void launch_axpy_cols(double2* x, const double2* z, int64_t n, int64_t ld, int ncols, hipStream_t st);
+void launch_start_cycle(const double2* r, double2* v0, int64_t n, int64_t ld, int ncols, const double* rn2,
+                        const int32_t* act, hipStream_t st);
+void launch_copy_cols(const double2* src, int64_t lds, double2* dst, int64_t ldd, int64_t n, int ncols,
+                      hipStream_t st);
+void launch_zero(double2* p, int64_t count, hipStream_t st);
+void launch_zero_bytes(void* p, int64_t bytes, hipStream_t st);
+void launch_misfit(const double2* S, const double2* Sm, int64_t count, double2* gS, double* J, hipStream_t st);
+
+}  // namespace mw

@@ -1,0 +1,453 @@
+// Vector kernels of the preconditioned pseudo-block GMRES (paper Section 6:
+// right-preconditioned GMRES, stopped on the unpreconditioned residual; the
+// right-hand sides keep their own Krylov spaces and only their arithmetic is
+// fused).  All multi-vectors are n x ncols row-major (column index
+// contiguous).  Every reduction sums fixed row chunks in a fixed order, so a
+// column's result does not depend on how many other columns are present
+// (a column solved alone or in a batch gives bitwise the same numbers).
+#include "kernels.hpp"
+
+namespace mw {
+
+constexpr int RCHUNK = 2048;   // rows per reduction chunk
+
+int64_t reduce_chunks(int64_t n) { return ceil_div(n, RCHUNK); }
+
+// ---------------------------------------------------------------- K1 / K12
+// Y = A X  (Bsub == nullptr)  or  Y = Bsub - A X, CSR complex128.
+// TPR threads per row; each lane walks columns lane, lane+TPR, ...
+template <int TPR>
+__global__ void __launch_bounds__(256) k_spmm(int64_t n, const int64_t* __restrict__ row_ptr,
+                                              const int32_t* __restrict__ col, const double2* __restrict__ val,
+                                              const double2* __restrict__ X, int64_t ldx, double2* __restrict__ Y,
+                                              int64_t ldy, int ncols, const double2* __restrict__ Bs, int64_t ldb) {
+  int64_t r = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / TPR;
+  int lane = threadIdx.x % TPR;
+  if (r >= n) return;
+  int64_t b = row_ptr[r], e = row_ptr[r + 1];
+  for (int c0 = 0; c0 < ncols; c0 += TPR) {
+    int c = c0 + lane;
+    if (c >= ncols) break;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int64_t k = b; k < e; ++k) {
+      double2 a = val[k];
+      double2 x = X[(int64_t)col[k] * ldx + c];
+      acc.x += a.x * x.x - a.y * x.y;
+      acc.y += a.x * x.y + a.y * x.x;
+    }
+    if (Bs) {
+      double2 bb = Bs[r * ldb + c];
+      acc = make_double2(bb.x - acc.x, bb.y - acc.y);
+    }
+    Y[r * ldy + c] = acc;
+  }
+}
+
+void launch_spmm(const DeviceMesh& m, const double2* val, const double2* X, int64_t ldx, double2* Y, int64_t ldy,
+                 int ncols, const double2* Bsub, int64_t ldb, hipStream_t st) {
+  int64_t n = m.n;
+#define MW_SPMM(T)                                                                                      \
+  k_spmm<T><<<(unsigned)ceil_div(n * T, 256), 256, 0, st>>>(n, m.row_ptr, m.col, val, X, ldx, Y, ldy, \
+                                                            ncols, Bsub, ldb)
+  if (ncols <= 1) MW_SPMM(1);
+  else if (ncols <= 2) MW_SPMM(2);
+  else if (ncols <= 4) MW_SPMM(4);
+  else if (ncols <= 8) MW_SPMM(8);
+  else if (ncols <= 16) MW_SPMM(16);
+  else if (ncols <= 32) MW_SPMM(32);
+  else MW_SPMM(64);
+#undef MW_SPMM
+  MW_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- K4 / K5
+// restriction: Y[l][c] = V[ridx[l]][c] (cast), zero on padding rows
+template <class C>
+__global__ void k_restrict(int64_t nloc, const int32_t* __restrict__ ridx, const double2* __restrict__ V,
+                           int64_t ldv, int ncols, C* __restrict__ Y, int64_t ldy) {
+  int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t l = id / ncols;
+  int c = (int)(id % ncols);
+  if (l >= nloc) return;
+  int32_t g = ridx[l];
+  C y;
+  y.x = 0; y.y = 0;
+  if (g >= 0) {
+    double2 v = V[(int64_t)g * ldv + c];
+    y.x = v.x; y.y = v.y;
+  }
+  Y[l * ldy + c] = y;
+}
+
+template <class C>
+void launch_restrict(const DeviceDecomp& d, const double2* V, int64_t ldv, int ncols, C* Y, int64_t ldy,
+                     hipStream_t st) {
+  int64_t tot = d.sum_pad * ncols;
+  k_restrict<C><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(d.sum_pad, d.ridx, V, ldv, ncols, Y, ldy);
+  MW_LAUNCH_CHECK();
+}
+
+// weighted prolongation: Z[g][c] = sum over the copies of g of D * Y (FP64 sum,
+// ascending subdomain order)
+template <class C>
+__global__ void k_prolong(int64_t n, const int64_t* __restrict__ cp_ptr, const int64_t* __restrict__ cp_row,
+                          const double* __restrict__ D, const C* __restrict__ Y, int64_t ldy, int ncols,
+                          double2* __restrict__ Z, int64_t ldz) {
+  int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t g = id / ncols;
+  int c = (int)(id % ncols);
+  if (g >= n) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t k = cp_ptr[g]; k < cp_ptr[g + 1]; ++k) {
+    int64_t r = cp_row[k];
+    C y = Y[r * ldy + c];
+    double w = D[r];
+    acc.x += w * (double)y.x;
+    acc.y += w * (double)y.y;
+  }
+  Z[g * ldz + c] = acc;
+}
+
+template <class C>
+void launch_prolong(const DeviceDecomp& d, int64_t n, const C* Y, int64_t ldy, int ncols, double2* Z, int64_t ldz,
+                    hipStream_t st) {
+  int64_t tot = n * ncols;
+  k_prolong<C><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(n, d.cp_ptr, d.cp_row, d.D, Y, ldy, ncols, Z, ldz);
+  MW_LAUNCH_CHECK();
+}
+
+template void launch_restrict<float2>(const DeviceDecomp&, const double2*, int64_t, int, float2*, int64_t,
+                                      hipStream_t);
+template void launch_restrict<double2>(const DeviceDecomp&, const double2*, int64_t, int, double2*, int64_t,
+                                       hipStream_t);
+template void launch_prolong<float2>(const DeviceDecomp&, int64_t, const float2*, int64_t, int, double2*, int64_t,
+                                     hipStream_t);
+template void launch_prolong<double2>(const DeviceDecomp&, int64_t, const double2*, int64_t, int, double2*,
+                                      int64_t, hipStream_t);
+
+// ---------------------------------------------------------------- reductions
+// Workgroup (chunk, column tile of 64): thread (column lane, row lane of 4)
+// accumulates rows rl, rl+4, ... of the chunk; the 4 row lanes are combined
+// in LDS in a fixed order.
+__global__ void __launch_bounds__(256) k_colnorm2_partial(const double2* __restrict__ V, int64_t n, int64_t ld,
+                                                          int ncols, double* __restrict__ part) {
+  __shared__ double red[4][64];
+  int chunk = blockIdx.x;
+  int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  int c = blockIdx.y * 64 + cl;
+  int64_t r0 = (int64_t)chunk * RCHUNK, r1 = min(n, r0 + RCHUNK);
+  double acc = 0.0;
+  if (c < ncols)
+    for (int64_t r = r0 + rl; r < r1; r += 4) {
+      double2 v = V[r * ld + c];
+      acc += v.x * v.x + v.y * v.y;
+    }
+  red[rl][cl] = acc;
+  __syncthreads();
+  if (rl == 0 && c < ncols) part[(int64_t)chunk * ncols + c] = ((red[0][cl] + red[1][cl]) + red[2][cl]) + red[3][cl];
+}
+
+void launch_colnorm2_partial(const double2* V, int64_t n, int64_t ld, int ncols, double* part, hipStream_t st) {
+  dim3 g((unsigned)reduce_chunks(n), (unsigned)ceil_div(ncols, 64));
+  k_colnorm2_partial<<<g, 256, 0, st>>>(V, n, ld, ncols, part);
+  MW_LAUNCH_CHECK();
+}
+
+__global__ void k_sum_chunks(const double* __restrict__ part, int64_t nchunk, int64_t width, double* __restrict__ out) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= width) return;
+  double acc = 0.0;
+  for (int64_t k = 0; k < nchunk; ++k) acc += part[k * width + c];
+  out[c] = acc;
+}
+void launch_sum_chunks(const double* part, int64_t nchunk, int64_t width, double* out, hipStream_t st) {
+  k_sum_chunks<<<(unsigned)ceil_div(width, 128), 128, 0, st>>>(part, nchunk, width, out);
+  MW_LAUNCH_CHECK();
+}
+__global__ void k_sum_chunks_c(const double2* __restrict__ part, int64_t nchunk, int64_t width,
+                               double2* __restrict__ out) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= width) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t k = 0; k < nchunk; ++k) acc = cadd(acc, part[k * width + c]);
+  out[c] = acc;
+}
+void launch_sum_chunks_c(const double2* part, int64_t nchunk, int64_t width, double2* out, hipStream_t st) {
+  k_sum_chunks_c<<<(unsigned)ceil_div(width, 128), 128, 0, st>>>(part, nchunk, width, out);
+  MW_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- K6 (CGS2)
+// part[chunk][k][c] = sum_{rows of chunk} conj(V_k[r][c]) w[r][c], k < kcount
+__global__ void __launch_bounds__(256) k_dots_partial(const double2* __restrict__ V, int64_t vstride, int kcount,
+                                                      const double2* __restrict__ w, int64_t n, int64_t ld,
+                                                      int ncols, const int32_t* __restrict__ act,
+                                                      double2* __restrict__ part) {
+  __shared__ double2 red[4][64];
+  int k = blockIdx.x;
+  int chunk = blockIdx.y;
+  int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  int c = blockIdx.z * 64 + cl;
+  int64_t r0 = (int64_t)chunk * RCHUNK, r1 = min(n, r0 + RCHUNK);
+  double2 acc = make_double2(0.0, 0.0);
+  const double2* Vk = V + (int64_t)k * vstride;
+  if (c < ncols && act[c])
+    for (int64_t r = r0 + rl; r < r1; r += 4) {
+      double2 v = Vk[r * ld + c], x = w[r * ld + c];
+      acc.x += v.x * x.x + v.y * x.y;
+      acc.y += v.x * x.y - v.y * x.x;
+    }
+  red[rl][cl] = acc;
+  __syncthreads();
+  if (rl == 0 && c < ncols)
+    part[((int64_t)chunk * kcount + k) * ncols + c] =
+        cadd(cadd(cadd(red[0][cl], red[1][cl]), red[2][cl]), red[3][cl]);
+}
+
+void launch_dots_partial(const double2* V, int64_t vstride, int kcount, const double2* w, int64_t n, int64_t ld,
+                         int ncols, const int32_t* act, double2* part, hipStream_t st) {
+  dim3 g(kcount, (unsigned)reduce_chunks(n), (unsigned)ceil_div(ncols, 64));
+  k_dots_partial<<<g, 256, 0, st>>>(V, vstride, kcount, w, n, ld, ncols, act, part);
+  MW_LAUNCH_CHECK();
+}
+
+// w[r][c] -= sum_k V_k[r][c] h[k][c]; optionally |w|^2 chunk partials
+__global__ void __launch_bounds__(256) k_cgs_update(const double2* __restrict__ V, int64_t vstride, int kcount,
+                                                    const double2* __restrict__ h, double2* __restrict__ w, int64_t n,
+                                                    int64_t ld, int ncols, const int32_t* __restrict__ act,
+                                                    double* __restrict__ norm_part) {
+  __shared__ double red[4][64];
+  int chunk = blockIdx.x;
+  int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  int c = blockIdx.y * 64 + cl;
+  int64_t r0 = (int64_t)chunk * RCHUNK, r1 = min(n, r0 + RCHUNK);
+  double acc = 0.0;
+  if (c < ncols && act[c]) {
+    for (int64_t r = r0 + rl; r < r1; r += 4) {
+      double2 x = w[r * ld + c];
+      for (int k = 0; k < kcount; ++k) {
+        double2 v = V[(int64_t)k * vstride + r * ld + c];
+        double2 hk = h[(int64_t)k * ncols + c];
+        x.x -= v.x * hk.x - v.y * hk.y;
+        x.y -= v.x * hk.y + v.y * hk.x;
+      }
+      w[r * ld + c] = x;
+      acc += x.x * x.x + x.y * x.y;
+    }
+  }
+  if (norm_part) {
+    red[rl][cl] = acc;
+    __syncthreads();
+    if (rl == 0 && c < ncols)
+      norm_part[(int64_t)chunk * ncols + c] = ((red[0][cl] + red[1][cl]) + red[2][cl]) + red[3][cl];
+  }
+}
+
+void launch_cgs_update(const double2* V, int64_t vstride, int kcount, const double2* h, double2* w, int64_t n,
+                       int64_t ld, int ncols, const int32_t* act, double* norm_part, hipStream_t st) {
+  dim3 g((unsigned)reduce_chunks(n), (unsigned)ceil_div(ncols, 64));
+  k_cgs_update<<<g, 256, 0, st>>>(V, vstride, kcount, h, w, n, ld, ncols, act, norm_part);
+  MW_LAUNCH_CHECK();
+}
+
+// w[:, c] /= sqrt(nrm2[c]) for active columns with a nonzero norm
+__global__ void k_scale_cols(double2* __restrict__ w, int64_t n, int64_t ld, int ncols, const double* __restrict__ nrm2,
+                             const int32_t* __restrict__ act) {
+  int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t r = id / ncols;
+  int c = (int)(id % ncols);
+  if (r >= n || !act[c]) return;
+  double s = sqrt(nrm2[c]);
+  if (s > 0.0) {
+    double2 v = w[r * ld + c];
+    w[r * ld + c] = make_double2(v.x / s, v.y / s);
+  }
+}
+void launch_scale_cols(double2* w, int64_t n, int64_t ld, int ncols, const double* nrm, const int32_t* act,
+                       hipStream_t st) {
+  k_scale_cols<<<(unsigned)ceil_div(n * ncols, 256), 256, 0, st>>>(w, n, ld, ncols, nrm, act);
+  MW_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- K7
+// Column j of the Hessenberg matrix of every active column: h = h1 + h2
+// (the two Gram-Schmidt passes), h_{j+1,j} = ||w||; previous Givens
+// rotations, a new one, the residual estimate |g_{j+1}|, and deactivation
+// when it reaches tol * ||b|| or the Krylov space is exhausted.
+// H[i][jj][c] at (i*m + jj)*ncols + c, g[i][c] at i*ncols + c.
+__global__ void k_givens(int j, int m, int ncols, const double2* __restrict__ h1, const double2* __restrict__ h2,
+                         const double* __restrict__ hn2, double2* __restrict__ H, double* __restrict__ cs,
+                         double2* __restrict__ sn, double2* __restrict__ g, int32_t* __restrict__ kdim,
+                         int32_t* __restrict__ act, double* __restrict__ resid, const double* __restrict__ bnorm,
+                         double tol) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols || !act[c]) return;
+  for (int i = 0; i <= j; ++i) H[((int64_t)i * m + j) * ncols + c] = cadd(h1[(int64_t)i * ncols + c], h2[(int64_t)i * ncols + c]);
+  double hn = sqrt(hn2[c]);
+  for (int i = 0; i < j; ++i) {
+    double ci = cs[(int64_t)i * ncols + c];
+    double2 si = sn[(int64_t)i * ncols + c];
+    double2 a = H[((int64_t)i * m + j) * ncols + c];
+    double2 b = H[((int64_t)(i + 1) * m + j) * ncols + c];
+    double2 t = cadd(cscale(a, ci), cmul(si, b));
+    double2 u = csub(cscale(b, ci), cmulc(a, si));   // -conj(s) a + c b
+    H[((int64_t)i * m + j) * ncols + c] = t;
+    H[((int64_t)(i + 1) * m + j) * ncols + c] = u;
+  }
+  double2 a = H[((int64_t)j * m + j) * ncols + c];
+  double aa = hypot(a.x, a.y);
+  double rho = hypot(aa, hn);
+  double ci;
+  double2 si, r;
+  if (rho == 0.0) { ci = 1.0; si = make_double2(0.0, 0.0); r = make_double2(0.0, 0.0); }
+  else if (aa == 0.0) { ci = 0.0; si = make_double2(1.0, 0.0); r = make_double2(hn, 0.0); }
+  else {
+    double2 ph = make_double2(a.x / aa, a.y / aa);
+    ci = aa / rho;
+    si = cscale(ph, hn / rho);
+    r = cscale(ph, rho);
+  }
+  cs[(int64_t)j * ncols + c] = ci;
+  sn[(int64_t)j * ncols + c] = si;
+  H[((int64_t)j * m + j) * ncols + c] = r;
+  double2 gj = g[(int64_t)j * ncols + c];
+  double2 gj1 = make_double2(-(si.x * gj.x + si.y * gj.y), -(si.x * gj.y - si.y * gj.x));   // -conj(s) g_j
+  g[(int64_t)(j + 1) * ncols + c] = gj1;
+  g[(int64_t)j * ncols + c] = cscale(gj, ci);
+  kdim[c] = j + 1;
+  double res = hypot(gj1.x, gj1.y);
+  resid[c] = res;
+  if (!(res > tol * bnorm[c]) || !(hn > 0.0)) act[c] = 0;
+}
+
+void launch_givens(int j, int m, int ncols, const double2* h1, const double2* h2, const double* hn2, double2* H,
+                   double* cs, double2* sn, double2* g, int32_t* kdim, int32_t* act, double* resid,
+                   const double* bnorm, double tol, hipStream_t st) {
+  k_givens<<<(unsigned)ceil_div(ncols, 64), 64, 0, st>>>(j, m, ncols, h1, h2, hn2, H, cs, sn, g, kdim, act, resid,
+                                                        bnorm, tol);
+  MW_LAUNCH_CHECK();
+}
+
+// y = R^-1 g on the Krylov dimension of each column (back substitution)
+__global__ void k_backsolve(int m, int ncols, const double2* __restrict__ H, const double2* __restrict__ g,
+                            const int32_t* __restrict__ kdim, double2* __restrict__ y) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  int kk = kdim[c];
+  for (int i = kk - 1; i >= 0; --i) {
+    double2 s = g[(int64_t)i * ncols + c];
+    for (int t = i + 1; t < kk; ++t) s = csub(s, cmul(H[((int64_t)i * m + t) * ncols + c], y[(int64_t)t * ncols + c]));
+    y[(int64_t)i * ncols + c] = cmul(s, cinv(H[((int64_t)i * m + i) * ncols + c]));
+  }
+}
+void launch_backsolve(int m, int ncols, const double2* H, const double2* g, const int32_t* kdim, double2* y,
+                      hipStream_t st) {
+  k_backsolve<<<(unsigned)ceil_div(ncols, 64), 64, 0, st>>>(m, ncols, H, g, kdim, y);
+  MW_LAUNCH_CHECK();
+}
+
+// u[r][c] = sum_{k < kdim[c]} V_k[r][c] y[k][c]
+__global__ void k_combine(const double2* __restrict__ V, int64_t vstride, const double2* __restrict__ y,
+                          const int32_t* __restrict__ kdim, double2* __restrict__ u, int64_t n, int64_t ld,
+                          int ncols) {
+  int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t r = id / ncols;
+  int c = (int)(id % ncols);
+  if (r >= n) return;
+  double2 acc = make_double2(0.0, 0.0);
+  int kk = kdim[c];
+  for (int k = 0; k < kk; ++k) acc = cadd(acc, cmul(V[(int64_t)k * vstride + r * ld + c], y[(int64_t)k * ncols + c]));
+  u[r * ld + c] = acc;
+}
+void launch_combine(const double2* V, int64_t vstride, int m, const double2* y, const int32_t* kdim, double2* u,
+                    int64_t n, int64_t ld, int ncols, hipStream_t st) {
+  (void)m;
+  k_combine<<<(unsigned)ceil_div(n * ncols, 256), 256, 0, st>>>(V, vstride, y, kdim, u, n, ld, ncols);
+  MW_LAUNCH_CHECK();
+}
+
+__global__ void k_axpy_cols(double2* __restrict__ x, const double2* __restrict__ z, int64_t total) {
+  int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (id < total) x[id] = cadd(x[id], z[id]);
+}
+void launch_axpy_cols(double2* x, const double2* z, int64_t n, int64_t ld, int ncols, hipStream_t st) {
+  (void)ncols;
+  int64_t tot = n * ld;
+  k_axpy_cols<<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(x, z, tot);
+  MW_LAUNCH_CHECK();
+}
+
+// v0 = r / ||r|| for active columns, 0 elsewhere
+__global__ void k_start_cycle(const double2* __restrict__ r, double2* __restrict__ v0, int64_t n, int64_t ld,
+                              int ncols, const double* __restrict__ rn2, const int32_t* __restrict__ act) {
+  int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t row = id / ncols;
+  int c = (int)(id % ncols);
+  if (row >= n) return;
+  double2 v = make_double2(0.0, 0.0);
+  if (act[c]) {
+    double s = sqrt(rn2[c]);
+    double2 x = r[row * ld + c];
+    v = make_double2(x.x / s, x.y / s);
+  }
+  v0[row * ld + c] = v;
+}
+void launch_start_cycle(const double2* r, double2* v0, int64_t n, int64_t ld, int ncols, const double* rn2,
+                        const int32_t* act, hipStream_t st) {
+  k_start_cycle<<<(unsigned)ceil_div(n * ncols, 256), 256, 0, st>>>(r, v0, n, ld, ncols, rn2, act);
+  MW_LAUNCH_CHECK();
+}
+
+__global__ void k_copy_cols(const double2* __restrict__ src, int64_t lds, double2* __restrict__ dst, int64_t ldd,
+                            int64_t n, int ncols) {
+  int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t r = id / ncols;
+  int c = (int)(id % ncols);
+  if (r >= n) return;
+  dst[r * ldd + c] = src[r * lds + c];
+}
+void launch_copy_cols(const double2* src, int64_t lds, double2* dst, int64_t ldd, int64_t n, int ncols,
+                      hipStream_t st) {
+  if (n * ncols == 0) return;
+  k_copy_cols<<<(unsigned)ceil_div(n * ncols, 256), 256, 0, st>>>(src, lds, dst, ldd, n, ncols);
+  MW_LAUNCH_CHECK();
+}
+
+__global__ void k_zero_bytes(uint32_t* __restrict__ p, int64_t words) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+void launch_zero_bytes(void* p, int64_t bytes, hipStream_t st) {
+  if (bytes <= 0) return;
+  MW_CHECK(bytes % 4 == 0, MW_EINVAL, "zero fill of a non-word size");
+  int64_t words = bytes / 4;
+  unsigned grid = (unsigned)std::min<int64_t>(ceil_div(words, 256), 65536);
+  k_zero_bytes<<<grid, 256, 0, st>>>(reinterpret_cast<uint32_t*>(p), words);
+  MW_LAUNCH_CHECK();
+}
+void launch_zero(double2* p, int64_t count, hipStream_t st) { launch_zero_bytes(p, count * 16, st); }
+
+// gS = S - Smes and J = 1/2 sum |gS|^2 (one workgroup, fixed summation order)
+__global__ void __launch_bounds__(256) k_misfit(const double2* __restrict__ S, const double2* __restrict__ Sm,
+                                                int64_t count, double2* __restrict__ gS, double* __restrict__ J) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t k = threadIdx.x; k < count; k += 256) {
+    double2 d = csub(S[k], Sm[k]);
+    gS[k] = d;
+    acc += d.x * d.x + d.y * d.y;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) J[0] = 0.5 * red[0];
+}
+void launch_misfit(const double2* S, const double2* Sm, int64_t count, double2* gS, double* J, hipStream_t st) {
+  k_misfit<<<1, 256, 0, st>>>(S, Sm, count, gS, J);
+  MW_LAUNCH_CHECK();
+}
+
+}  // namespace mw

@@ -1,0 +1,197 @@
+"""Torch-facing wrappers of the C ABI: device tensors in, device tensors out.
+
+PyTorch provides device memory and the stream; every computation is a call
+into libmw.so.  Multi-vectors are (n, nrhs) contiguous complex128 tensors on
+the context's device.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import binding as B
+from .binding import check, lib, ptr
+
+
+@dataclass
+class SolveInfo:
+    iters: np.ndarray
+    relres: np.ndarray
+    max_iters: int
+    cycles: int
+    chunks: int
+    t_solve: float
+
+
+def _opts(tol, restart, maxit, use_x0):
+    return B.mw_solve_opts(tol=float(tol), restart=int(restart), maxit=int(maxit), use_x0=int(use_x0))
+
+
+def _dev_tensor(t: torch.Tensor, dtype, device, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or t.device != device or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor on {device}")
+    return t
+
+
+class Context:
+    """A device, its stream and an HBM byte budget for the library."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0, stream: torch.cuda.Stream | None = None):
+        L = lib()
+        self.device = torch.device("cuda", device)
+        h = C.c_void_p()
+        check(L.mw_create(C.byref(h), device, int(budget_bytes)))
+        self.h = h
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        check(L.mw_set_stream(self.h, C.c_void_p(self.stream.cuda_stream)))
+
+    def close(self):
+        if self.h:
+            check(lib().mw_destroy(self.h))
+            self.h = None
+
+
+class Problem:
+    """One mesh + permittivity + boundary data, its operator and factors."""
+
+    def __init__(self, ctx: Context, xyz, tet, bface, btag, eps, k0: float, beta_imp: complex, ports=()):
+        self.ctx = ctx
+        L = lib()
+        m, self._mesh_keep = B.make_mesh(xyz, tet, bface, btag)
+        eps = np.ascontiguousarray(np.asarray(eps, dtype=np.complex128))
+        assert eps.shape == (m.nt,)
+        nports = len(ports)
+        parr = (B.mw_port * max(nports, 1))()
+        for k, pt in enumerate(ports):
+            b = complex(pt.beta)
+            parr[k].beta = B.mw_complex(b.real, b.imag)
+            parr[k].radius, parr[k].theta, parr[k].width = pt.radius, pt.theta, pt.width
+            for a in range(3):
+                parr[k].pol[a] = float(pt.pol[a])
+        h = C.c_void_p()
+        b = complex(beta_imp)
+        check(L.mw_assemble(ctx.h, C.byref(m), ptr(eps), float(k0), B.mw_complex(b.real, b.imag),
+                            C.addressof(parr), nports, C.byref(h)))
+        self.h = h
+        self.k0 = float(k0)
+        self.nports = nports
+        inf = self.info()
+        self.n, self.nnz, self.nt = inf.n, inf.nnz, inf.nt
+
+    # ------------------------------------------------------------------ info
+    def info(self) -> B.mw_problem_info:
+        i = B.mw_problem_info()
+        check(lib().mw_problem_get_info(self.h, C.byref(i)))
+        return i
+
+    def dof_edges(self):
+        i = self.info()
+        eod = np.empty(i.n, dtype=np.int32)
+        ev = np.empty(i.n_edges * 2, dtype=np.int32)
+        check(lib().mw_dof_edges(self.h, ptr(eod), ptr(ev)))
+        return eod, ev.reshape(-1, 2)
+
+    def matrix(self):
+        dev = self.ctx.device
+        rp = torch.empty(self.n + 1, dtype=torch.int64, device=dev)
+        col = torch.empty(self.nnz, dtype=torch.int32, device=dev)
+        val = torch.empty(self.nnz, dtype=torch.complex128, device=dev)
+        check(lib().mw_get_matrix(self.h, ptr(rp), ptr(col), ptr(val)))
+        return rp, col, val
+
+    def close(self):
+        if self.h:
+            check(lib().mw_destroy_problem(self.h))
+            self.h = None
+
+    # ------------------------------------------------------------------ data
+    def update_eps(self, eps: torch.Tensor):
+        _dev_tensor(eps, torch.complex128, self.ctx.device, "eps")
+        check(lib().mw_update_eps(self.h, ptr(eps)))
+
+    def rhs_ports(self, tx) -> torch.Tensor:
+        tx = np.ascontiguousarray(tx, dtype=np.int32)
+        Bm = torch.empty((self.n, tx.size), dtype=torch.complex128, device=self.ctx.device)
+        check(lib().mw_rhs_ports(self.h, tx.size, ptr(tx), ptr(Bm)))
+        return Bm
+
+    def rhs_dipoles(self, points, dirs=None) -> torch.Tensor:
+        pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+        if dirs is None:
+            dirs = np.tile([0.0, 0.0, 1.0], (pts.shape[0], 1))
+        dirs = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+        Bm = torch.empty((self.n, pts.shape[0]), dtype=torch.complex128, device=self.ctx.device)
+        check(lib().mw_rhs_dipoles(self.h, pts.shape[0], ptr(pts), ptr(dirs), ptr(Bm)))
+        return Bm
+
+    def port_norms(self) -> np.ndarray:
+        nu = np.empty(max(self.nports, 1))
+        check(lib().mw_port_norms(self.h, ptr(nu)))
+        return nu[: self.nports]
+
+    # ------------------------------------------------------------------ preconditioner
+    def factor(self, part, n_sub: int, overlap: int = 1, precision: str = "c128"):
+        part = np.ascontiguousarray(part, dtype=np.int32)
+        prec = {"c128": B.MW_C128, "c64": B.MW_C64}[precision]
+        check(lib().mw_factor_subdomains(self.h, int(n_sub), int(overlap), prec, ptr(part)))
+
+    def apply_preconditioner(self, V: torch.Tensor) -> torch.Tensor:
+        _dev_tensor(V, torch.complex128, self.ctx.device, "V")
+        Z = torch.empty_like(V)
+        check(lib().mw_apply_preconditioner(self.h, V.shape[1], ptr(V), ptr(Z)))
+        return Z
+
+    # ------------------------------------------------------------------ solve
+    def solve(self, Bm: torch.Tensor, tol=1e-8, restart=30, maxit=1000, x0: torch.Tensor | None = None,
+              raise_noconv: bool = True):
+        _dev_tensor(Bm, torch.complex128, self.ctx.device, "B")
+        nrhs = Bm.shape[1]
+        X = x0.clone() if x0 is not None else torch.empty_like(Bm)
+        it = np.zeros(nrhs, dtype=np.int32)
+        rr = np.zeros(nrhs)
+        info = B.mw_solve_info(iters=ptr(it) if nrhs else None, relres=ptr(rr) if nrhs else None)
+        o = _opts(tol, restart, maxit, x0 is not None)
+        code = lib().mw_solve(self.h, nrhs, ptr(Bm), ptr(X), C.byref(o), C.byref(info))
+        if code != B.MW_OK and not (code == B.MW_ENOCONV and not raise_noconv):
+            check(code)
+        return X, SolveInfo(it, rr, info.max_iters, info.cycles, info.chunks, info.t_solve)
+
+    # ------------------------------------------------------------------ S, J, gradient
+    def s_matrix(self, U: torch.Tensor, rx) -> torch.Tensor:
+        rx = np.ascontiguousarray(rx, dtype=np.int32)
+        _dev_tensor(U, torch.complex128, self.ctx.device, "U")
+        S = torch.empty((rx.size, U.shape[1]), dtype=torch.complex128, device=self.ctx.device)
+        check(lib().mw_s_matrix(self.h, rx.size, ptr(rx), U.shape[1], ptr(U), ptr(S)))
+        return S
+
+    def adjoint_gradient(self, U: torch.Tensor, gS: torch.Tensor, tx, rx, tol=1e-8, restart=30, maxit=1000):
+        tx = np.ascontiguousarray(tx, dtype=np.int32)
+        rx = np.ascontiguousarray(rx, dtype=np.int32)
+        _dev_tensor(U, torch.complex128, self.ctx.device, "U")
+        _dev_tensor(gS, torch.complex128, self.ctx.device, "gS")
+        g = torch.empty(self.nt, dtype=torch.complex128, device=self.ctx.device)
+        o = _opts(tol, restart, maxit, 0)
+        check(lib().mw_adjoint_gradient(self.h, tx.size, ptr(tx), rx.size, ptr(rx), ptr(U), ptr(gS), ptr(g),
+                                        C.byref(o), None))
+        return g
+
+    def misfit_gradient(self, tx, rx, S_meas: torch.Tensor, tol=1e-8, restart=30, maxit=1000):
+        tx = np.ascontiguousarray(tx, dtype=np.int32)
+        rx = np.ascontiguousarray(rx, dtype=np.int32)
+        _dev_tensor(S_meas, torch.complex128, self.ctx.device, "S_meas")
+        S = torch.empty((rx.size, tx.size), dtype=torch.complex128, device=self.ctx.device)
+        g = torch.empty(self.nt, dtype=torch.complex128, device=self.ctx.device)
+        J = C.c_double()
+        o = _opts(tol, restart, maxit, 0)
+        check(lib().mw_misfit_gradient(self.h, tx.size, ptr(tx), rx.size, ptr(rx), ptr(S_meas), C.addressof(J),
+                                       ptr(S), ptr(g), C.byref(o)))
+        return J.value, S, g
+
+
+def problem_from_workload(ctx: Context, w) -> Problem:
+    """Problem for a seeded synthetic workload (see mw_inputs.configs)."""
+    m = w.mesh
+    return Problem(ctx, m.xyz, m.tet, m.bface, m.btag, w.eps, w.k0, w.beta_imp, w.ports)
