@@ -98,7 +98,7 @@ struct mw_problem {
   Decomposition D;
   DevBuf d_fac_off, d_loc_off, d_n_loc, d_n_pad, d_lt_off, d_lt_tet, d_lt_loc, d_lf_off, d_lf_vert, d_lf_owner,
       d_lf_kind, d_lf_loc, d_rtl_ptr, d_rtl, d_rfl_ptr, d_rfl, d_sub_dof, d_D, d_cp_ptr, d_cp_row, d_ipiv, d_ridx,
-      d_info;
+      d_info, d_amax;
   DeviceDecomp dd;
   DevBuf F;
   int prec = -1;
@@ -240,6 +240,7 @@ void upload_decomp(mw_problem* p) {
   p->d_ipiv = dalloc(c, D.sum_pad() * 4);
   p->d_ridx = dalloc(c, D.sum_pad() * 4);
   p->d_info = dalloc(c, (int64_t)D.nsub * 4);
+  p->d_amax = dalloc(c, (int64_t)D.nsub * 8);
   DeviceDecomp& d = p->dd;
   d.nsub = D.nsub;
   d.max_pad = *std::max_element(D.n_pad.begin(), D.n_pad.end());
@@ -267,6 +268,7 @@ void upload_decomp(mw_problem* p) {
   d.ipiv = p->d_ipiv.as<int32_t>();
   d.ridx = p->d_ridx.as<int32_t>();
   d.info = p->d_info.as<int32_t>();
+  d.amax = p->d_amax.as<double>();
 }
 
 // Z = M^-1 V (n x nc, leading dimension ld), local workspace Y
@@ -664,7 +666,7 @@ mw_status mw_factor_subdomains(mw_problem* p, int32_t n_sub, int32_t overlap, mw
     p->t_factor = now_s() - t1;
     for (int i = 0; i < p->dd.nsub; ++i)
       MW_CHECK(info[i] == 0, MW_ESINGULAR,
-               "zero pivot in subdomain " + std::to_string(i) + " at column " + std::to_string(info[i] - 1));
+               "(near-)zero pivot in subdomain " + std::to_string(i) + " at column " + std::to_string(info[i] - 1));
     p->factors_valid = true;
   });
 }

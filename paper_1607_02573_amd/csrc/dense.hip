@@ -189,6 +189,30 @@ __device__ inline Piv piv_max(Piv a, Piv b) {
   return a;
 }
 
+// largest |re|+|im| of every B_i (scale of the singular-pivot test)
+template <class R>
+__global__ void __launch_bounds__(256) k_amax(const typename cplx<R>::t* __restrict__ F,
+                                              const int64_t* __restrict__ fac_off, const int32_t* __restrict__ n_pad,
+                                              double* __restrict__ amax) {
+  __shared__ double red[4];
+  int i = blockIdx.x;
+  int64_t tot = (int64_t)n_pad[i] * n_pad[i];
+  const auto* Fi = F + fac_off[i];
+  double m = 0.0;
+  for (int64_t k = threadIdx.x; k < tot; k += 256) {
+    auto v = Fi[k];
+    double a = fabs((double)v.x) + fabs((double)v.y);
+    m = a > m ? a : m;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    double o = __shfl_xor(m, off);
+    m = o > m ? o : m;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) amax[i] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
 // One workgroup per subdomain: factor columns [c, c+W0) of rows [c, np),
 // row interchanges across the 64-wide panel [k, k+NB), then the unit-lower
 // solve of rows [c, c+W0) for the panel columns [c+W0, k+NB).
@@ -196,7 +220,8 @@ template <class R>
 __global__ void __launch_bounds__(256) k_lu_panel(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
                                                   const int32_t* __restrict__ n_pad,
                                                   const int64_t* __restrict__ loc_off, int32_t* ipiv,
-                                                  int32_t* info, int c, int k) {
+                                                  int32_t* info, const double* __restrict__ amax, double rtol,
+                                                  int c, int k) {
   using C = typename cplx<R>::t;
   __shared__ Piv red[4];
   __shared__ C prow[W0];
@@ -224,11 +249,14 @@ __global__ void __launch_bounds__(256) k_lu_panel(typename cplx<R>::t* F, const 
     __syncthreads();
     best = piv_max(piv_max(red[0], red[1]), piv_max(red[2], red[3]));
     int p = best.idx;
+    // a pivot below rtol * max|B_i| marks B_i numerically singular; an exact
+    // zero (or NaN) column is skipped without division
     bool zero = !(best.v > 0.0);
+    bool tiny = !(best.v > rtol * amax[i]);
     if (zero) p = col;
     if (tid == 0) {
       ipiv[loc_off[i] + col] = p;
-      if (zero && info[i] == 0) info[i] = col + 1;
+      if (tiny && info[i] == 0) info[i] = col + 1;
     }
     if (p != col)
       for (int cc = k + tid; cc < kend; cc += 256) {
@@ -413,9 +441,12 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st) {
   using R = typename RealOf<C>::t;
   MW_CHECK(d.max_pad <= 8192, MW_EINVAL, "subdomain too large for the dense factorisation (n_i > 8192)");
   const int maxp = d.max_pad;
+  k_amax<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.amax);
+  MW_LAUNCH_CHECK();
+  const double rtol = sizeof(R) == 4 ? 1e-6 : 1e-14;
   for (int k = 0; k < maxp; k += NB) {
     for (int c = k; c < k + NB; c += W0) {
-      k_lu_panel<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, c, k);
+      k_lu_panel<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, d.amax, rtol, c, k);
       MW_LAUNCH_CHECK();
       int r0 = c + W0, c1 = k + NB;
       if (r0 < c1) {

@@ -73,7 +73,8 @@ struct DeviceDecomp {
   const int64_t* cp_row = nullptr;
   int32_t* ipiv = nullptr;      // [sum_pad] pivot row of each column (subdomain-relative)
   int32_t* ridx = nullptr;      // [sum_pad] restriction gather index after pivoting (-1 padding)
-  int32_t* info = nullptr;      // [nsub] first zero-pivot column + 1, 0 if none
+  int32_t* info = nullptr;      // [nsub] first (near-)zero-pivot column + 1, 0 if none
+  double* amax = nullptr;       // [nsub] max |re|+|im| of B_i
 };
 
 // ---- assembly (assemble.hip)
