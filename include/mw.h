@@ -225,6 +225,18 @@ mw_status mw_host_decomposition(const mw_mesh *mesh, const int32_t *tet_part, in
                                 double *D);
 const char *mw_host_last_error(void);
 
+/* ---- kernel timing (measurement) --------------------------------------- */
+/* When enabled, HIP events are recorded on the launch stream around every
+ * launch of each kernel family, with the algorithmic flops and HBM bytes of
+ * the launch (from the true, unpadded subdomain sizes).  Families are
+ * numbered 0 .. mw_timer_families()-1, named by mw_timer_name(). */
+int32_t mw_timer_families(void);
+const char *mw_timer_name(int32_t family);
+void mw_timer_enable(int32_t on);
+void mw_timer_reset(void);
+/* launches, total milliseconds, flops and bytes since the last reset. */
+mw_status mw_timer_read(int32_t family, int64_t *launches, double *ms, double *flops, double *bytes);
+
 #ifdef __cplusplus
 }
 #endif

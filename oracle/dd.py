@@ -55,7 +55,8 @@ def _all_faces(tet: np.ndarray):
     return f, own
 
 
-def decompose(fp: fem.FEProblem, part: np.ndarray, delta: int = 1, factor: bool = True):
+def decompose(fp: fem.FEProblem, part: np.ndarray, delta: int = 1, factor: bool = True, subset=None):
+    """All subdomains, or only those listed in ``subset``."""
     nsub = int(part.max()) + 1
     nv = fp.nv
     # number of subdomains whose T_j^0 holds each node: denominator of (chi)
@@ -69,7 +70,7 @@ def decompose(fp: fem.FEProblem, part: np.ndarray, delta: int = 1, factor: bool 
     order_b = np.argsort(key_b)
     k0sq = fp.k0 * fp.k0
     subs = []
-    for i in range(nsub):
+    for i in (range(nsub) if subset is None else subset):
         t0 = part == i
         td = grow(fp.tet, nv, t0, delta)
         tets = np.nonzero(td)[0]

@@ -85,7 +85,8 @@ _SIGS = {
     "mw_host_topology": [C.POINTER(mw_mesh), _P, _P, _P, _P, _P, _P],
     "mw_host_decomposition": [C.POINTER(mw_mesh), _P, _I, _I, _P, _P, _P, _P],
 }
-EXPORTED = list(_SIGS) + ["mw_last_error", "mw_host_last_error"]
+EXPORTED = list(_SIGS) + ["mw_last_error", "mw_host_last_error", "mw_timer_families", "mw_timer_name",
+                          "mw_timer_enable", "mw_timer_reset"]
 
 _lib = None
 
@@ -106,6 +107,16 @@ def lib():
     L.mw_last_error.argtypes = []
     L.mw_host_last_error.restype = C.c_char_p
     L.mw_host_last_error.argtypes = []
+    L.mw_timer_families.restype = C.c_int32
+    L.mw_timer_families.argtypes = []
+    L.mw_timer_name.restype = C.c_char_p
+    L.mw_timer_name.argtypes = [C.c_int32]
+    L.mw_timer_enable.restype = None
+    L.mw_timer_enable.argtypes = [C.c_int32]
+    L.mw_timer_reset.restype = None
+    L.mw_timer_reset.argtypes = []
+    L.mw_timer_read.restype = C.c_int
+    L.mw_timer_read.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     _lib = L
     return L
 
@@ -165,3 +176,22 @@ def host_decomposition(xyz, tet, bface, btag, part, n_sub: int, overlap: int = 1
     off = np.r_[0, np.cumsum(n_loc)]
     return {"n_loc": n_loc, "n_faces": nf, "sub_dof": [sub_dof[off[i]:off[i + 1]] for i in range(n_sub)],
             "D": [D[off[i]:off[i + 1]] for i in range(n_sub)]}
+
+
+def timer_enable(on: bool = True):
+    lib().mw_timer_enable(1 if on else 0)
+
+
+def timer_reset():
+    lib().mw_timer_reset()
+
+
+def timer_read() -> dict:
+    """{family: {launches, ms, flops, bytes}} since the last reset."""
+    L = lib()
+    out = {}
+    for f in range(L.mw_timer_families()):
+        n, ms, fl, by = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+        check(L.mw_timer_read(f, C.addressof(n), C.addressof(ms), C.addressof(fl), C.addressof(by)))
+        out[L.mw_timer_name(f).decode()] = {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
+    return out

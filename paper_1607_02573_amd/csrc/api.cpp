@@ -269,6 +269,7 @@ void upload_decomp(mw_problem* p) {
   d.ridx = p->d_ridx.as<int32_t>();
   d.info = p->d_info.as<int32_t>();
   d.amax = p->d_amax.as<double>();
+  d.h_n_loc = p->D.n_loc.data();
 }
 
 // Z = M^-1 V (n x nc, leading dimension ld), local workspace Y
@@ -380,8 +381,10 @@ ChunkResult gmres_chunk(mw_problem* p, const double2* Bsrc, int64_t ldb_src, dou
       // classical Gram-Schmidt, twice
       launch_dots_partial(V, vstride, j + 1, W, n, ld, nc, act, part, st);
       launch_sum_chunks_c(part, nch, (int64_t)(j + 1) * nc, h1, st);
-      launch_cgs_update(V, vstride, j + 1, h1, W, n, ld, nc, act, nullptr, st);
-      launch_dots_partial(V, vstride, j + 1, W, n, ld, nc, act, part, st);
+      if (!launch_cgs_update_dots(V, vstride, j + 1, h1, W, n, ld, nc, act, part, st)) {
+        launch_cgs_update(V, vstride, j + 1, h1, W, n, ld, nc, act, nullptr, st);
+        launch_dots_partial(V, vstride, j + 1, W, n, ld, nc, act, part, st);
+      }
       launch_sum_chunks_c(part, nch, (int64_t)(j + 1) * nc, h2, st);
       double* npart = (double*)p->w_npart.get(c, nch * nc * 8);
       launch_cgs_update(V, vstride, j + 1, h2, W, n, ld, nc, act, npart, st);
@@ -648,6 +651,10 @@ mw_status mw_factor_subdomains(mw_problem* p, int32_t n_sub, int32_t overlap, mw
     if ((int64_t)p->F.bytes != need) {
       p->F.release();
       p->factors_valid = false;
+      // solve workspaces are re-created on demand; give their memory to the factors
+      for (Work* w : {&p->w_V, &p->w_X, &p->w_B, &p->w_Z, &p->w_Y, &p->w_H, &p->w_cs, &p->w_sn, &p->w_g, &p->w_y,
+                      &p->w_h1, &p->w_h2, &p->w_part, &p->w_npart, &p->w_vec, &p->w_int, &p->w_tmp})
+        w->b.release();
       p->F = dalloc(c, need);
     }
     p->prec = prec;

@@ -160,26 +160,159 @@ __global__ void __launch_bounds__(256) k_gemm_lu(typename cplx<R>::t* F, const i
                       Fi + (int64_t)r0 * np + c0, np, M, N, k1 - k0, tm, tn);
 }
 
-// Triangular-solve update on the local multi-vector of subdomain blockIdx.y:
-// Y[r0:min(r1,np)] -= F[r0:min(r1,np), k0:min(k1,np)] * Y[k0:min(k1,np)]
-template <class R>
+// Wide tile for the triangular-solve updates: C[64 rows x NCB*16 columns] -= A * B
+// with every right-hand-side column of the tile in one workgroup, so each
+// factor block (A) is read once per launch.  Wave w owns rows 16w..16w+15 of
+// the tile and all its column blocks; the next K stage is fetched into
+// registers while the current one is multiplied out of LDS.
+constexpr int WBK = 16;   // complex K per stage
+// AMODE 0: A as stored; 1: unit lower triangle of A (strict part stored,
+// implicit ones); 2: upper triangle of A with its diagonal.  OVERWRITE:
+// C = A B instead of C -= A B (B may alias C: every B row of the tile is
+// read before the epilogue writes).
+template <class R, int NCB, int AMODE = 0, bool OVERWRITE = false>
+__device__ inline void gemm_wide(const typename cplx<R>::t* __restrict__ A, int64_t lda,
+                                 const typename cplx<R>::t* B, int64_t ldb,
+                                 typename cplx<R>::t* Cm, int64_t ldc, int M, int N, int K) {
+  using C = typename cplx<R>::t;
+  using acc_t = typename Mf<R>::acc;
+  constexpr int TN = NCB * 16;
+  constexpr int AREG = 64 * WBK / 256;          // complex A values per thread per stage
+  constexpr int BREG = (WBK * TN + 255) / 256;  // complex B values per thread per stage
+  __shared__ R As[64][2 * WBK + 1];
+  __shared__ C Bs[WBK][TN + 1];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, kq = lane >> 4;
+  acc_t accr[NCB], acci[NCB];
+#pragma unroll
+  for (int b = 0; b < NCB; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) { accr[b][r] = 0; acci[b][r] = 0; }
+  C ra[AREG], rb[BREG];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < AREG; ++e) {
+      int idx = tid + e * 256;
+      int r = idx / WBK, kc = idx % WBK;
+      C v;
+      v.x = 0; v.y = 0;
+      const int kk = k0 + kc;
+      if (r < M && kk < K) {
+        if (AMODE == 0 || (AMODE == 1 && kk < r) || (AMODE == 2 && kk >= r)) v = A[(int64_t)r * lda + kk];
+        else if (AMODE == 1 && kk == r) v.x = 1;
+      }
+      ra[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < BREG; ++e) {
+      int idx = tid + e * 256;
+      int r = idx / TN, c = idx % TN;
+      C v;
+      v.x = 0; v.y = 0;
+      if (idx < WBK * TN && k0 + r < K && c < N) v = B[(int64_t)(k0 + r) * ldb + c];
+      rb[e] = v;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += WBK) {
+#pragma unroll
+    for (int e = 0; e < AREG; ++e) {
+      int idx = tid + e * 256;
+      int r = idx / WBK, kc = idx % WBK;
+      As[r][2 * kc] = ra[e].x;
+      As[r][2 * kc + 1] = ra[e].y;
+    }
+#pragma unroll
+    for (int e = 0; e < BREG; ++e) {
+      int idx = tid + e * 256;
+      if (idx < WBK * TN) Bs[idx / TN][idx % TN] = rb[e];
+    }
+    __syncthreads();
+    if (k0 + WBK < K) fetch(k0 + WBK);
+#pragma unroll
+    for (int kk = 0; kk < WBK; kk += 2) {
+      R a = As[wave * 16 + li][2 * kk + kq];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        C b = Bs[kk + (kq >> 1)][cb * 16 + li];
+        bool odd = kq & 1;
+        R br = odd ? -b.y : b.x;
+        R bi = odd ? b.x : b.y;
+        accr[cb] = Mf<R>::mfma(a, br, accr[cb]);
+        acci[cb] = Mf<R>::mfma(a, bi, acci[cb]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int gr = wave * 16 + Mf<R>::out_row(lane, r);
+      int gc = cb * 16 + li;
+      if (gr < M && gc < N) {
+        C* p = Cm + (int64_t)gr * ldc + gc;
+        C o;
+        if (OVERWRITE) { o.x = accr[cb][r]; o.y = acci[cb][r]; }
+        else { o = *p; o.x -= accr[cb][r]; o.y -= acci[cb][r]; }
+        *p = o;
+      }
+    }
+}
+
+// Triangular-solve update on the local multi-vector of every subdomain:
+// Y[r0:min(r1,np)] -= F[r0:min(r1,np), k0:min(k1,np)] * Y[k0:min(k1,np)].
+// 1-D grid of nsub * tiles_per_sub (padded to a multiple of 8) workgroups;
+// the linear id is remapped so that the tiles of one subdomain run on one XCD
+// (workgroups are dealt to the 8 XCDs round-robin) and share its L2.
+template <class R, int NCB>
 __global__ void __launch_bounds__(256) k_gemm_x(const typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
                                                 const int32_t* __restrict__ n_pad,
                                                 const int64_t* __restrict__ loc_off, typename cplx<R>::t* Y,
-                                                int64_t ld, int ncols, int r0, int r1, int k0, int k1) {
+                                                int64_t ld, int ncols, int r0, int r1, int k0, int k1,
+                                                int tiles_m, int tiles_n, int nsub) {
   using C = typename cplx<R>::t;
-  int i = blockIdx.y;
-  int np = n_pad[i];
-  int M = min(r1, np) - r0;
-  int K = min(k1, np) - k0;
+  const int per_sub = tiles_m * tiles_n;
+  const int G = gridDim.x;
+  const int logical = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  const int i = logical / per_sub;
+  if (i >= nsub) return;
+  const int t = logical % per_sub;
+  const int tm = t / tiles_n, tn = t % tiles_n;
+  const int np = n_pad[i];
+  const int M = min(r1, np) - r0 - tm * 64;
+  const int K = min(k1, np) - k0;
   if (M <= 0 || K <= 0) return;
-  int tiles_n = (ncols + TB - 1) / TB;
-  int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
-  if (tm * TB >= M) return;
+  const int TN = NCB * 16;
+  const int N = min(ncols - tn * TN, TN);
   const C* Fi = F + fac_off[i];
   C* Yi = Y + loc_off[i] * ld;
-  gemm_tile<R, false>(Fi + (int64_t)r0 * np + k0, np, Yi + (int64_t)k0 * ld, ld, Yi + (int64_t)r0 * ld, ld, M,
-                      ncols, K, tm, tn);
+  const int row = r0 + tm * 64;
+  gemm_wide<R, NCB>(Fi + (int64_t)row * np + k0, np, Yi + (int64_t)k0 * ld + tn * TN, ld,
+                    Yi + (int64_t)row * ld + tn * TN, ld, M, N, K);
+}
+
+// Leaf of the blocked triangular solves: Y[r0:r0+64] = T^-1 Y[r0:r0+64] with the
+// inverted diagonal block (AMODE 1: L^-1, 2: U^-1), in place, all columns.
+template <class R, int NCB, int AMODE>
+__global__ void __launch_bounds__(256) k_leaf_x(const typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
+                                                const int32_t* __restrict__ n_pad,
+                                                const int64_t* __restrict__ loc_off, typename cplx<R>::t* Y,
+                                                int64_t ld, int ncols, int r0, int tiles_n, int nsub) {
+  using C = typename cplx<R>::t;
+  const int G = gridDim.x;
+  const int logical = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  const int i = logical / tiles_n;
+  if (i >= nsub) return;
+  const int tn = logical % tiles_n;
+  const int np = n_pad[i];
+  if (r0 >= np) return;
+  const int TN = NCB * 16;
+  const int N = min(ncols - tn * TN, TN);
+  const C* blk = F + fac_off[i] + (int64_t)r0 * np + r0;
+  C* Yb = Y + (loc_off[i] + r0) * ld + tn * TN;
+  gemm_wide<R, NCB, AMODE, true>(blk, np, Yb, ld, Yb, ld, NB, N, NB);
 }
 
 // ---------------------------------------------------------------- pivot reduction
@@ -318,66 +451,96 @@ __global__ void k_laswp(typename cplx<R>::t* F, const int64_t* __restrict__ fac_
 
 // ---------------------------------------------------------------- leaf TRSM
 // Solve T X = X in place for the NB x NB triangle T (unit lower, or upper with
-// its diagonal) and an NB-row block X with `ncols` columns.  Each 16-lane
-// group owns one column and holds 4 of its rows in registers; the solution
-// entries are broadcast by lane shuffles, the triangle sits in LDS (packed).
-template <class R, bool UPPER>
-__device__ inline void trsm_leaf(const typename cplx<R>::t* __restrict__ T, int64_t ldt,
-                                 typename cplx<R>::t* __restrict__ X, int64_t ldx, int ncols, int col0) {
+// its diagonal) and an NB-row block X, columns [c_begin, c_end).  Each
+// 16-lane group owns one column at a time and keeps its 64 rows in 4
+// registers per lane (row q + 16*sl); solution entries are broadcast by lane
+// shuffles.  The triangle is staged in LDS as four 16-row bands, band sl
+// holding rows q + 16*sl with a per-band stride, so that every LDS access is
+// a per-band base plus a compile-time offset (the loops are fully unrolled).
+//   lower band sl: T[q+16sl][r], r in [0, 16sl+16),  stride 16sl+17
+//   upper band sl: T[q+16sl][r], r in [16sl, 64),     stride 65-16sl
+constexpr int BAND_TOTAL = 16 * (17 + 33 + 49 + 65);
+__host__ __device__ constexpr int band_off(int sl, bool upper) {
+  return upper ? (sl == 0 ? 0 : sl == 1 ? 16 * 65 : sl == 2 ? 16 * (65 + 49) : 16 * (65 + 49 + 33))
+               : (sl == 0 ? 0 : sl == 1 ? 16 * 17 : sl == 2 ? 16 * (17 + 33) : 16 * (17 + 33 + 49));
+}
+__host__ __device__ constexpr int band_stride(int sl, bool upper) { return upper ? 65 - 16 * sl : 16 * sl + 17; }
+
+template <class C>
+__device__ inline C pick4(const C v[4], int sl) {
+  C a = sl == 1 ? v[1] : v[0];
+  C b = sl == 3 ? v[3] : v[2];
+  return sl >= 2 ? b : a;
+}
+
+// IDENT: the block X starts as the identity (its old contents are not read);
+// WMASK: 0 write every row, 1 only rows below the column (strict lower),
+// 2 only rows on or above it (upper with diagonal).
+template <class R, bool UPPER, bool IDENT = false, int WMASK = 0>
+__device__ inline void trsm_leaf(const typename cplx<R>::t* __restrict__ T, int64_t ldt, typename cplx<R>::t* X,
+                                 int64_t ldx, int c_begin, int c_end, typename cplx<R>::t* tri) {
   using C = typename cplx<R>::t;
-  __shared__ C tri[NB * (NB + 1) / 2];
   const int tid = threadIdx.x;
-  for (int e = tid; e < NB * NB; e += 256) {
-    int r = e / NB, s = e % NB;
-    if (UPPER ? (s >= r) : (s <= r)) {
-      int idx = UPPER ? (s * (s + 1) / 2 + r) : (r * (r + 1) / 2 + s);
-      tri[idx] = T[(int64_t)r * ldt + s];
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl) {
+    const int w = UPPER ? 64 - 16 * sl : 16 * sl + 16;    // stored columns per band row
+    for (int e = tid; e < 16 * w; e += 256) {
+      int q = e / w, j = e % w;
+      int r = UPPER ? 16 * sl + j : j;
+      tri[band_off(sl, UPPER) + q * band_stride(sl, UPPER) + j] = T[(int64_t)(q + 16 * sl) * ldt + r];
     }
   }
   __syncthreads();
   const int q = tid & 15;
-  const int colx = col0 + (tid >> 4);
-  const bool live = colx < ncols;
-  C v[4];
+  const C* band[4];
 #pragma unroll
-  for (int sl = 0; sl < 4; ++sl) {
-    v[sl].x = 0; v[sl].y = 0;
-    if (live) v[sl] = X[(int64_t)(q + 16 * sl) * ldx + colx];
-  }
-  if (!UPPER) {
+  for (int sl = 0; sl < 4; ++sl) band[sl] = tri + band_off(sl, UPPER) + q * band_stride(sl, UPPER);
+  for (int colx = c_begin + (tid >> 4); colx < c_end; colx += 16) {
+    C v[4];
 #pragma unroll
-    for (int r = 0; r < NB; ++r) {
-      const int owner = r & 15, slot = r >> 4;
-      C xr;
-      xr.x = __shfl(v[slot].x, owner, 16);
-      xr.y = __shfl(v[slot].y, owner, 16);
+    for (int sl = 0; sl < 4; ++sl) {
+      if (IDENT) { v[sl].x = (q + 16 * sl == colx) ? 1 : 0; v[sl].y = 0; }
+      else v[sl] = X[(int64_t)(q + 16 * sl) * ldx + colx];
+    }
+    if (!UPPER) {
+      for (int r = 0; r < NB; ++r) {
+        const int owner = r & 15, slot = r >> 4;
+        C mine = pick4(v, slot);
+        C xr;
+        xr.x = __shfl(mine.x, owner, 16);
+        xr.y = __shfl(mine.y, owner, 16);
 #pragma unroll
-      for (int sl = 0; sl < 4; ++sl) {
-        int s = q + 16 * sl;
-        if (s > r) v[sl] = csub(v[sl], cmul(tri[s * (s + 1) / 2 + r], xr));
+        for (int sl = 0; sl < 4; ++sl)
+          if (q + 16 * sl > r) v[sl] = csub(v[sl], cmul(band[sl][r], xr));
+      }
+    } else {
+      for (int r = NB - 1; r >= 0; --r) {
+        const int owner = r & 15, slot = r >> 4;
+        C mine = pick4(v, slot);
+        C xr;
+        xr.x = __shfl(mine.x, owner, 16);
+        xr.y = __shfl(mine.y, owner, 16);
+        // diagonal U[r][r]: band `slot`, row `owner`, column r
+        C dg = tri[band_off(slot, true) + owner * band_stride(slot, true) + (r - 16 * slot)];
+        xr = cmul(xr, cinv(dg));
+#pragma unroll
+        for (int sl = 0; sl < 4; ++sl) {
+          const int srow = q + 16 * sl;
+          if (srow == r) v[sl] = xr;
+          else if (srow < r) v[sl] = csub(v[sl], cmul(band[sl][r - 16 * sl], xr));
+        }
       }
     }
-  } else {
 #pragma unroll
-    for (int r = NB - 1; r >= 0; --r) {
-      const int owner = r & 15, slot = r >> 4;
-      C xr;
-      xr.x = __shfl(v[slot].x, owner, 16);
-      xr.y = __shfl(v[slot].y, owner, 16);
-      xr = cmul(xr, cinv(tri[r * (r + 1) / 2 + r]));
-      if (q == owner) v[slot] = xr;
-#pragma unroll
-      for (int sl = 0; sl < 4; ++sl) {
-        int s = q + 16 * sl;
-        if (s < r) v[sl] = csub(v[sl], cmul(tri[r * (r + 1) / 2 + s], xr));
-      }
+    for (int sl = 0; sl < 4; ++sl) {
+      const int srow = q + 16 * sl;
+      if (WMASK == 0 || (WMASK == 1 && srow > colx) || (WMASK == 2 && srow <= colx))
+        X[(int64_t)srow * ldx + colx] = v[sl];
     }
-  }
-  if (live) {
-#pragma unroll
-    for (int sl = 0; sl < 4; ++sl) X[(int64_t)(q + 16 * sl) * ldx + colx] = v[sl];
   }
 }
+
+constexpr int PANEL_COLS = 256;   // columns per workgroup of the LU panel solve
 
 // LU: U12 = L11^-1 A12 for the panel k (rows [k, k+NB), columns [k+NB, np))
 template <class R>
@@ -386,27 +549,29 @@ __global__ void __launch_bounds__(256) k_trsm_panel(typename cplx<R>::t* F, cons
   int i = blockIdx.y;
   int np = n_pad[i];
   int c0 = k + NB;
-  if (c0 >= np) return;
-  int ncols = np - c0;
-  int col0 = blockIdx.x * 16;
-  if (col0 >= ncols) return;
+  int cb = c0 + blockIdx.x * PANEL_COLS;
+  if (cb >= np) return;
   auto* Fi = F + fac_off[i];
-  trsm_leaf<R, false>(Fi + (int64_t)k * np + k, np, Fi + (int64_t)k * np + c0, np, ncols, col0);
+  __shared__ typename cplx<R>::t tri[BAND_TOTAL];
+  trsm_leaf<R, false>(Fi + (int64_t)k * np + k, np, Fi + (int64_t)k * np, np, cb, min(np, cb + PANEL_COLS), tri);
 }
 
-// solve: leaf block b of L (UPPER = false) or U (UPPER = true) on Y
-template <class R, bool UPPER>
-__global__ void __launch_bounds__(256) k_trsm_x(const typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
-                                                const int32_t* __restrict__ n_pad,
-                                                const int64_t* __restrict__ loc_off, typename cplx<R>::t* Y,
-                                                int64_t ld, int ncols, int r0) {
-  int i = blockIdx.y;
+// Every 64 x 64 diagonal block of a factored B_i is replaced by the inverses of
+// its two triangles: L_bb^-1 (unit lower, strict part stored) and U_bb^-1
+// (upper with diagonal) share the block, so the leaf triangular solves become
+// small dense products.  U_bb is staged in LDS before any of its entries is
+// overwritten; the L_bb^-1 writes touch only the strict lower part.
+template <class R>
+__global__ void __launch_bounds__(256) k_invert_diag(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
+                                                     const int32_t* __restrict__ n_pad) {
+  int b = blockIdx.x, i = blockIdx.y;
   int np = n_pad[i];
-  if (r0 >= np) return;
-  int col0 = blockIdx.x * 16;
-  if (col0 >= ncols) return;
-  const auto* Fi = F + fac_off[i];
-  trsm_leaf<R, UPPER>(Fi + (int64_t)r0 * np + r0, np, Y + (loc_off[i] + r0) * ld, ld, ncols, col0);
+  if (b * NB >= np) return;
+  auto* blk = F + fac_off[i] + (int64_t)b * NB * np + b * NB;
+  __shared__ typename cplx<R>::t tri[BAND_TOTAL];
+  trsm_leaf<R, false, true, 1>(blk, np, blk, np, 0, NB, tri);
+  __syncthreads();
+  trsm_leaf<R, true, true, 2>(blk, np, blk, np, 0, NB, tri);
 }
 
 // restriction gather index with the row interchanges folded in:
@@ -436,6 +601,22 @@ template <class C> struct RealOf;
 template <> struct RealOf<float2> { using t = float; };
 template <> struct RealOf<double2> { using t = double; };
 
+// ---------------------------------------------------------------- launch accounting
+// algorithmic flops / bytes of one batched launch from the true sizes n_i
+template <class F>
+static void kt_account(const DeviceDecomp& d, int fam, hipStream_t st, F&& per_sub, int esz) {
+  if (!kt_enabled()) return;
+  double fl = 0, by = 0;
+  for (int i = 0; i < d.nsub; ++i) {
+    double a = 0, b = 0;
+    per_sub(d.h_n_loc[i], a, b);
+    fl += a;
+    by += b * esz;
+  }
+  kt_end(fam, st, fl, by);
+}
+static inline double clampd(double v) { return v > 0 ? v : 0; }
+
 template <class C>
 void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st) {
   using R = typename RealOf<C>::t;
@@ -446,71 +627,147 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st) {
   const double rtol = sizeof(R) == 4 ? 1e-6 : 1e-14;
   for (int k = 0; k < maxp; k += NB) {
     for (int c = k; c < k + NB; c += W0) {
+      kt_begin(KF_LU_PANEL, st);
       k_lu_panel<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, d.amax, rtol, c, k);
       MW_LAUNCH_CHECK();
+      kt_account(d, KF_LU_PANEL, st, [&](int n, double& f, double& b) {
+        double rows = clampd(n - c);
+        f = 8.0 * rows * W0 * W0 / 2;
+        b = 2.0 * rows * W0;
+      }, (int)sizeof(C));
       int r0 = c + W0, c1 = k + NB;
       if (r0 < c1) {
         int M = maxp - r0, N = c1 - r0;
         unsigned tiles = (unsigned)(ceil_div(M, TB) * ceil_div(N, TB));
+        kt_begin(KF_LU_GEMM, st);
         k_gemm_lu<R><<<dim3(tiles, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, r0, c, c + W0, r0, c1);
         MW_LAUNCH_CHECK();
+        kt_account(d, KF_LU_GEMM, st, [&](int n, double& f, double& b) {
+          double M = clampd(n - r0), N = clampd(std::min(c1, n) - r0), K = clampd(std::min(c + W0, n) - c);
+          f = 8.0 * M * N * K;
+          b = M * K + K * N + 2 * M * N;
+        }, (int)sizeof(C));
       }
     }
     int ncol = maxp;  // upper bound of columns outside the panel
+    kt_begin(KF_LU_OTHER, st);
     k_laswp<R><<<dim3((unsigned)ceil_div(ncol, 256), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off,
                                                                              d.ipiv, k);
     MW_LAUNCH_CHECK();
+    kt_account(d, KF_LU_OTHER, st, [&](int n, double& f, double& b) { f = 0; b = n > k ? 2.0 * NB * n : 0; },
+               (int)sizeof(C));
     int c0 = k + NB;
     if (c0 < maxp) {
-      k_trsm_panel<R><<<dim3((unsigned)ceil_div(maxp - c0, 16), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, k);
+      kt_begin(KF_LU_OTHER, st);
+      k_trsm_panel<R><<<dim3((unsigned)ceil_div(maxp - c0, PANEL_COLS), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, k);
       MW_LAUNCH_CHECK();
+      kt_account(d, KF_LU_OTHER, st, [&](int n, double& f, double& b) {
+        double N = clampd(n - c0);
+        f = 4.0 * NB * NB * N;
+        b = NB * NB / 2.0 + 2.0 * NB * N;
+      }, (int)sizeof(C));
       int M = maxp - c0;
       unsigned tiles = (unsigned)(ceil_div(M, TB) * ceil_div(M, TB));
+      kt_begin(KF_LU_GEMM, st);
       k_gemm_lu<R><<<dim3(tiles, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, c0, k, k + NB, c0, maxp);
       MW_LAUNCH_CHECK();
+      kt_account(d, KF_LU_GEMM, st, [&](int n, double& f, double& b) {
+        double M2 = clampd(n - c0), K = clampd(std::min(k + NB, n) - k);
+        f = 8.0 * M2 * M2 * K;
+        b = 2 * M2 * K + 2 * M2 * M2;
+      }, (int)sizeof(C));
     }
   }
+  kt_begin(KF_LU_OTHER, st);
+  k_invert_diag<R><<<dim3((unsigned)(maxp / NB), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad);
+  MW_LAUNCH_CHECK();
+  kt_account(d, KF_LU_OTHER, st, [&](int n, double& f, double& b) {
+    double nb = std::ceil(n / (double)NB);
+    f = nb * 8.0 * NB * NB * NB / 3.0;
+    b = nb * 2.0 * NB * NB;
+  }, (int)sizeof(C));
   k_build_perm<<<d.nsub, 256, 0, st>>>(d.n_pad, d.loc_off, d.ipiv, d.sub_dof, d.ridx);
+  MW_LAUNCH_CHECK();
+}
+
+// Y[r0:r1] -= F[r0:r1, k0:k1] Y[k0:k1] on every subdomain (wide tiles: 160
+// columns per tile in FP32, 80 in FP64)
+template <class R>
+static void launch_gemm_x(const DeviceDecomp& d, const typename cplx<R>::t* F, typename cplx<R>::t* Y, int64_t ld,
+                          int ncols, int r0, int r1, int k0, int k1, hipStream_t st) {
+  constexpr int NCB = sizeof(R) == 4 ? 10 : 5;
+  int tiles_m = (int)ceil_div(r1 - r0, 64);
+  int tiles_n = (int)ceil_div(ncols, NCB * 16);
+  int64_t G = round_up((int64_t)d.nsub * tiles_m * tiles_n, 8);
+  k_gemm_x<R, NCB><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, Y, ld, ncols, r0, r1, k0, k1,
+                                                tiles_m, tiles_n, d.nsub);
+  MW_LAUNCH_CHECK();
+}
+
+template <class R, int AMODE>
+static void launch_leaf_x(const DeviceDecomp& d, const typename cplx<R>::t* F, typename cplx<R>::t* Y, int64_t ld,
+                          int ncols, int r0, hipStream_t st) {
+  constexpr int NCB = sizeof(R) == 4 ? 10 : 5;
+  int tiles_n = (int)ceil_div(ncols, NCB * 16);
+  int64_t G = round_up((int64_t)d.nsub * tiles_n, 8);
+  k_leaf_x<R, NCB, AMODE><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, Y, ld, ncols, r0, tiles_n,
+                                                      d.nsub);
   MW_LAUNCH_CHECK();
 }
 
 template <class R>
 static void fwd_rec(const DeviceDecomp& d, const typename cplx<R>::t* F, typename cplx<R>::t* Y, int ncols,
                     int64_t ld, int b0, int b1, hipStream_t st) {
+  const int esz = (int)sizeof(typename cplx<R>::t);
   if (b1 - b0 == 1) {
-    k_trsm_x<R, false><<<dim3((unsigned)ceil_div(ncols, 16), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad,
-                                                                                      d.loc_off, Y, ld, ncols,
-                                                                                      b0 * NB);
+    kt_begin(KF_TRSM_LEAF, st);
+    launch_leaf_x<R, 1>(d, F, Y, ld, ncols, b0 * NB, st);
     MW_LAUNCH_CHECK();
+    kt_account(d, KF_TRSM_LEAF, st, [&](int n, double& f, double& b) {
+      double m = clampd(std::min((b0 + 1) * NB, n) - b0 * NB);
+      f = 4.0 * m * m * ncols;
+      b = m * m / 2 + 2 * m * ncols;
+    }, esz);
     return;
   }
   int mid = b0 + (b1 - b0) / 2;
   fwd_rec<R>(d, F, Y, ncols, ld, b0, mid, st);
-  int M = (b1 - mid) * NB;
-  unsigned tiles = (unsigned)(ceil_div(M, TB) * ceil_div(ncols, TB));
-  k_gemm_x<R><<<dim3(tiles, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, Y, ld, ncols, mid * NB,
-                                                   b1 * NB, b0 * NB, mid * NB);
+  kt_begin(KF_TRSM_GEMM, st);
+  launch_gemm_x<R>(d, F, Y, ld, ncols, mid * NB, b1 * NB, b0 * NB, mid * NB, st);
   MW_LAUNCH_CHECK();
+  kt_account(d, KF_TRSM_GEMM, st, [&](int n, double& f, double& b) {
+    double Mi = clampd(std::min(b1 * NB, n) - mid * NB), Ki = clampd(std::min(mid * NB, n) - b0 * NB);
+    f = 8.0 * Mi * Ki * ncols;
+    b = Mi * Ki + Ki * ncols + 2 * Mi * ncols;
+  }, esz);
   fwd_rec<R>(d, F, Y, ncols, ld, mid, b1, st);
 }
 
 template <class R>
 static void bwd_rec(const DeviceDecomp& d, const typename cplx<R>::t* F, typename cplx<R>::t* Y, int ncols,
                     int64_t ld, int b0, int b1, hipStream_t st) {
+  const int esz = (int)sizeof(typename cplx<R>::t);
   if (b1 - b0 == 1) {
-    k_trsm_x<R, true><<<dim3((unsigned)ceil_div(ncols, 16), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad,
-                                                                                     d.loc_off, Y, ld, ncols,
-                                                                                     b0 * NB);
+    kt_begin(KF_TRSM_LEAF, st);
+    launch_leaf_x<R, 2>(d, F, Y, ld, ncols, b0 * NB, st);
     MW_LAUNCH_CHECK();
+    kt_account(d, KF_TRSM_LEAF, st, [&](int n, double& f, double& b) {
+      double m = clampd(std::min((b0 + 1) * NB, n) - b0 * NB);
+      f = 4.0 * m * m * ncols;
+      b = m * m / 2 + 2 * m * ncols;
+    }, esz);
     return;
   }
   int mid = b0 + (b1 - b0) / 2;
   bwd_rec<R>(d, F, Y, ncols, ld, mid, b1, st);
-  int M = (mid - b0) * NB;
-  unsigned tiles = (unsigned)(ceil_div(M, TB) * ceil_div(ncols, TB));
-  k_gemm_x<R><<<dim3(tiles, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, Y, ld, ncols, b0 * NB,
-                                                   mid * NB, mid * NB, b1 * NB);
+  kt_begin(KF_TRSM_GEMM, st);
+  launch_gemm_x<R>(d, F, Y, ld, ncols, b0 * NB, mid * NB, mid * NB, b1 * NB, st);
   MW_LAUNCH_CHECK();
+  kt_account(d, KF_TRSM_GEMM, st, [&](int n, double& f, double& b) {
+    double Mi = clampd(std::min(mid * NB, n) - b0 * NB), Ki = clampd(std::min(b1 * NB, n) - mid * NB);
+    f = 8.0 * Mi * Ki * ncols;
+    b = Mi * Ki + Ki * ncols + 2 * Mi * ncols;
+  }, esz);
   bwd_rec<R>(d, F, Y, ncols, ld, b0, mid, st);
 }
 

@@ -5,6 +5,13 @@
 
 namespace mw {
 
+// kernel families timed by ktimer.cpp
+enum KFamily { KF_TRSM_GEMM, KF_TRSM_LEAF, KF_LU_GEMM, KF_LU_PANEL, KF_LU_OTHER, KF_SPMM, KF_CGS_DOTS,
+               KF_CGS_UPDATE, KF_RESTRICT, KF_PROLONG, KF_VECTOR, KF_COUNT };
+bool kt_enabled();
+void kt_begin(int family, hipStream_t st);
+void kt_end(int family, hipStream_t st, double flops, double bytes);
+
 // Mesh, operator pattern and per-row assembly lists on the device.
 struct DeviceMesh {
   int64_t nv = 0, nt = 0, n = 0, nbf = 0, nnz = 0;
@@ -75,6 +82,7 @@ struct DeviceDecomp {
   int32_t* ridx = nullptr;      // [sum_pad] restriction gather index after pivoting (-1 padding)
   int32_t* info = nullptr;      // [nsub] first (near-)zero-pivot column + 1, 0 if none
   double* amax = nullptr;       // [nsub] max |re|+|im| of B_i
+  const int32_t* h_n_loc = nullptr;  // host copy of n_loc (launch accounting)
 };
 
 // ---- assembly (assemble.hip)
@@ -124,6 +132,9 @@ void launch_dots_partial(const double2* V, int64_t vstride, int kcount, const do
 void launch_sum_chunks_c(const double2* part, int64_t nchunk, int64_t width, double2* out, hipStream_t st);
 void launch_cgs_update(const double2* V, int64_t vstride, int kcount, const double2* h, double2* w, int64_t n,
                        int64_t ld, int ncols, const int32_t* act, double* norm_part, hipStream_t st);
+// fused w -= V h and dot products with the updated w; false (nothing launched) if kcount > 8
+bool launch_cgs_update_dots(const double2* V, int64_t vstride, int kcount, const double2* h, double2* w, int64_t n,
+                            int64_t ld, int ncols, const int32_t* act, double2* part, hipStream_t st);
 void launch_scale_cols(double2* w, int64_t n, int64_t ld, int ncols, const double* nrm, const int32_t* act,
                        hipStream_t st);
 void launch_givens(int j, int m, int ncols, const double2* h1, const double2* h2, const double* hn2,

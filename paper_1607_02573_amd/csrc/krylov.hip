@@ -46,6 +46,7 @@ __global__ void __launch_bounds__(256) k_spmm(int64_t n, const int64_t* __restri
 void launch_spmm(const DeviceMesh& m, const double2* val, const double2* X, int64_t ldx, double2* Y, int64_t ldy,
                  int ncols, const double2* Bsub, int64_t ldb, hipStream_t st) {
   int64_t n = m.n;
+  kt_begin(KF_SPMM, st);
 #define MW_SPMM(T)                                                                                      \
   k_spmm<T><<<(unsigned)ceil_div(n * T, 256), 256, 0, st>>>(n, m.row_ptr, m.col, val, X, ldx, Y, ldy, \
                                                             ncols, Bsub, ldb)
@@ -58,6 +59,9 @@ void launch_spmm(const DeviceMesh& m, const double2* val, const double2* X, int6
   else MW_SPMM(64);
 #undef MW_SPMM
   MW_LAUNCH_CHECK();
+  if (kt_enabled())
+    kt_end(KF_SPMM, st, 8.0 * m.nnz * ncols,
+           (double)m.nnz * 20 + (n + 1) * 8.0 + n * (double)ncols * 16 * (Bsub ? 3 : 2));
 }
 
 // ---------------------------------------------------------------- K4 / K5
@@ -83,8 +87,14 @@ template <class C>
 void launch_restrict(const DeviceDecomp& d, const double2* V, int64_t ldv, int ncols, C* Y, int64_t ldy,
                      hipStream_t st) {
   int64_t tot = d.sum_pad * ncols;
+  kt_begin(KF_RESTRICT, st);
   k_restrict<C><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(d.sum_pad, d.ridx, V, ldv, ncols, Y, ldy);
   MW_LAUNCH_CHECK();
+  if (kt_enabled()) {
+    double sl = 0;
+    for (int i = 0; i < d.nsub; ++i) sl += d.h_n_loc[i];
+    kt_end(KF_RESTRICT, st, 0.0, sl * 4 + sl * ncols * (16.0 + sizeof(C)));
+  }
 }
 
 // weighted prolongation: Z[g][c] = sum over the copies of g of D * Y (FP64 sum,
@@ -112,8 +122,14 @@ template <class C>
 void launch_prolong(const DeviceDecomp& d, int64_t n, const C* Y, int64_t ldy, int ncols, double2* Z, int64_t ldz,
                     hipStream_t st) {
   int64_t tot = n * ncols;
+  kt_begin(KF_PROLONG, st);
   k_prolong<C><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(n, d.cp_ptr, d.cp_row, d.D, Y, ldy, ncols, Z, ldz);
   MW_LAUNCH_CHECK();
+  if (kt_enabled()) {
+    double sl = 0;
+    for (int i = 0; i < d.nsub; ++i) sl += d.h_n_loc[i];
+    kt_end(KF_PROLONG, st, 4.0 * sl * ncols, sl * (16.0 + ncols * sizeof(C)) + (n + 1) * 8.0 + n * ncols * 16.0);
+  }
 }
 
 template void launch_restrict<float2>(const DeviceDecomp&, const double2*, int64_t, int, float2*, int64_t,
@@ -207,8 +223,10 @@ __global__ void __launch_bounds__(256) k_dots_partial(const double2* __restrict_
 void launch_dots_partial(const double2* V, int64_t vstride, int kcount, const double2* w, int64_t n, int64_t ld,
                          int ncols, const int32_t* act, double2* part, hipStream_t st) {
   dim3 g(kcount, (unsigned)reduce_chunks(n), (unsigned)ceil_div(ncols, 64));
+  kt_begin(KF_CGS_DOTS, st);
   k_dots_partial<<<g, 256, 0, st>>>(V, vstride, kcount, w, n, ld, ncols, act, part);
   MW_LAUNCH_CHECK();
+  if (kt_enabled()) kt_end(KF_CGS_DOTS, st, 8.0 * kcount * n * ncols, (kcount + 1.0) * n * ncols * 16);
 }
 
 // w[r][c] -= sum_k V_k[r][c] h[k][c]; optionally |w|^2 chunk partials
@@ -246,8 +264,81 @@ __global__ void __launch_bounds__(256) k_cgs_update(const double2* __restrict__ 
 void launch_cgs_update(const double2* V, int64_t vstride, int kcount, const double2* h, double2* w, int64_t n,
                        int64_t ld, int ncols, const int32_t* act, double* norm_part, hipStream_t st) {
   dim3 g((unsigned)reduce_chunks(n), (unsigned)ceil_div(ncols, 64));
+  kt_begin(KF_CGS_UPDATE, st);
   k_cgs_update<<<g, 256, 0, st>>>(V, vstride, kcount, h, w, n, ld, ncols, act, norm_part);
   MW_LAUNCH_CHECK();
+  if (kt_enabled()) kt_end(KF_CGS_UPDATE, st, 8.0 * kcount * n * ncols, (kcount + 2.0) * n * ncols * 16);
+}
+
+// Second Gram-Schmidt sweep fused with the first update:
+//   w' = w - sum_k V_k h1_k   and   part[chunk][k][c] = sum_rows conj(V_k) w'
+// for k < kcount <= KMAX; every row is finished before its products are
+// accumulated, so one pass over V replaces two.  Per-thread accumulators are
+// indexed by unrolled constants (registers, no scratch).
+template <int KMAX>
+__global__ void __launch_bounds__(256) k_cgs_update_dots(const double2* __restrict__ V, int64_t vstride, int kcount,
+                                                         const double2* __restrict__ h, double2* __restrict__ w,
+                                                         int64_t n, int64_t ld, int ncols,
+                                                         const int32_t* __restrict__ act, double2* __restrict__ part) {
+  __shared__ double2 red[4][64];
+  __shared__ double2 hs[KMAX][64];
+  int chunk = blockIdx.x;
+  int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  int c = blockIdx.y * 64 + cl;
+  int64_t r0 = (int64_t)chunk * RCHUNK, r1 = min(n, r0 + RCHUNK);
+  for (int k = rl; k < KMAX; k += 4)
+    hs[k][cl] = (c < ncols && k < kcount) ? h[(int64_t)k * ncols + c] : make_double2(0.0, 0.0);
+  __syncthreads();
+  double2 acc[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) acc[k] = make_double2(0.0, 0.0);
+  const bool live = c < ncols && act[c];
+  if (live) {
+    for (int64_t r = r0 + rl; r < r1; r += 4) {
+      const int64_t o = r * ld + c;
+      double2 x = w[o];
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k)
+        if (k < kcount) {
+          double2 v = V[(int64_t)k * vstride + o];
+          double2 hk = hs[k][cl];
+          x.x -= v.x * hk.x - v.y * hk.y;
+          x.y -= v.x * hk.y + v.y * hk.x;
+        }
+      w[o] = x;
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k)
+        if (k < kcount) {
+          double2 v = V[(int64_t)k * vstride + o];
+          acc[k].x += v.x * x.x + v.y * x.y;
+          acc[k].y += v.x * x.y - v.y * x.x;
+        }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    if (k < kcount) {
+      red[rl][cl] = acc[k];
+      __syncthreads();
+      if (rl == 0 && c < ncols)
+        part[((int64_t)chunk * kcount + k) * ncols + c] =
+            cadd(cadd(cadd(red[0][cl], red[1][cl]), red[2][cl]), red[3][cl]);
+      __syncthreads();
+    }
+  }
+}
+
+bool launch_cgs_update_dots(const double2* V, int64_t vstride, int kcount, const double2* h, double2* w, int64_t n,
+                            int64_t ld, int ncols, const int32_t* act, double2* part, hipStream_t st) {
+  dim3 g((unsigned)reduce_chunks(n), (unsigned)ceil_div(ncols, 64));
+  // the per-thread accumulators stay in registers (no spill, occupancy >= 5)
+  // only up to 8 basis vectors; beyond that the two separate sweeps are faster
+  if (kcount > 8) return false;
+  kt_begin(KF_CGS_UPDATE, st);
+  k_cgs_update_dots<8><<<g, 256, 0, st>>>(V, vstride, kcount, h, w, n, ld, ncols, act, part);
+  MW_LAUNCH_CHECK();
+  if (kt_enabled()) kt_end(KF_CGS_UPDATE, st, 16.0 * kcount * n * ncols, (kcount + 2.0) * n * ncols * 16);
+  return true;
 }
 
 // w[:, c] /= sqrt(nrm2[c]) for active columns with a nonzero norm
