@@ -213,11 +213,15 @@ def main():
         del Xm, Sm
         torch.cuda.empty_cache()
         log(f"[bench] FP64 steps x{args.fp64_steps}")
+        binding.timer_enable(True)
+        binding.timer_reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st64, (X64, S64) = run_steps(P, w, eps_dev, "c128", args.fp64_steps, tol, args.restart, args.maxit, tx, rx)
         torch.cuda.synchronize()
         T64 = time.perf_counter() - t0
+        fam64 = binding.timer_read()
+        binding.timer_enable(False)
         ok64 = int(sum((s["relres"] <= tol).sum() for s in st64))
         it64 = np.concatenate([s["iters"] for s in st64])
         x64 = X64[:, : Xm_host.shape[1]].cpu()
@@ -226,7 +230,11 @@ def main():
         fp64 = {"value": ok64 / T64, "ms_per_step": 1e3 * T64 / args.fp64_steps, "iters_mean": float(it64.mean()),
                 "chunks": st64[-1]["chunks"], "solve_rhs_per_s": sum(len(s["relres"]) for s in st64)
                 / sum(s["t_solve"] for s in st64), "setup_s": st64[-1]["t_setup"],
-                "mixed_vs_fp64_field_relL2_max": dx, "mixed_vs_fp64_S_rel_max": dS}
+                "mixed_vs_fp64_field_relL2_max": dx, "mixed_vs_fp64_S_rel_max": dS,
+                "kernels": {k: {"ms": round(v["ms"], 2), "launches": v["launches"],
+                                "TFLOPs": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 2),
+                                "GBs": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)}
+                            for k, v in fam64.items() if v["launches"] > 0}}
         log(f"[bench] FP64: {T64 / args.fp64_steps:.2f} s/step, {fp64['value']:.2f} RHS/s; mixed-vs-fp64 field {dx:.2e}")
 
     out = {

@@ -98,7 +98,8 @@ struct mw_problem {
   Decomposition D;
   DevBuf d_fac_off, d_loc_off, d_n_loc, d_n_pad, d_lt_off, d_lt_tet, d_lt_loc, d_lf_off, d_lf_vert, d_lf_owner,
       d_lf_kind, d_lf_loc, d_rtl_ptr, d_rtl, d_rfl_ptr, d_rfl, d_sub_dof, d_D, d_cp_ptr, d_cp_row, d_ipiv, d_ridx,
-      d_info, d_amax;
+      d_info, d_amax, d_row_lo;
+  std::vector<int32_t> h_row_lo;
   DeviceDecomp dd;
   DevBuf F;
   int prec = -1;
@@ -241,6 +242,9 @@ void upload_decomp(mw_problem* p) {
   p->d_ridx = dalloc(c, D.sum_pad() * 4);
   p->d_info = dalloc(c, (int64_t)D.nsub * 4);
   p->d_amax = dalloc(c, (int64_t)D.nsub * 8);
+  p->h_row_lo.resize(D.nsub);
+  for (int32_t i = 0; i < D.nsub; ++i) p->h_row_lo[i] = (D.n_lead[i] / 64) * 64;
+  p->d_row_lo = upload(c, p->h_row_lo);
   DeviceDecomp& d = p->dd;
   d.nsub = D.nsub;
   d.max_pad = *std::max_element(D.n_pad.begin(), D.n_pad.end());
@@ -270,6 +274,8 @@ void upload_decomp(mw_problem* p) {
   d.info = p->d_info.as<int32_t>();
   d.amax = p->d_amax.as<double>();
   d.h_n_loc = p->D.n_loc.data();
+  d.row_lo = p->d_row_lo.as<int32_t>();
+  d.h_row_lo = p->h_row_lo.data();
 }
 
 // Z = M^-1 V (n x nc, leading dimension ld), local workspace Y

@@ -143,9 +143,11 @@ struct Decomposition {
   int32_t nsub = 0, delta = 1;
   std::vector<int32_t> n_loc;       // [nsub] n_i
   std::vector<int32_t> n_pad;       // [nsub] n_i rounded up to the block size
+  std::vector<int32_t> n_lead;      // [nsub] leading local unknowns with D = 0
   std::vector<int64_t> loc_off;     // [nsub+1] row offset of subdomain i in local vectors
   std::vector<int64_t> fac_off;     // [nsub+1] element offset of subdomain i's dense matrix
-  std::vector<int32_t> sub_dof;     // [sum n_pad] global dof of each local row (-1 padding)
+  std::vector<int32_t> sub_dof;     // [sum n_pad] global dof of each local row (-1 padding);
+                                    // zero-weight unknowns first, each group ascending
   std::vector<double> D;            // [sum n_pad] partition-of-unity weight (0 padding)
   // prolongation: copies of every global dof (CSR over dofs, deterministic order)
   std::vector<int64_t> cp_ptr;      // [n+1]

@@ -3,7 +3,8 @@
 //  * T_i^delta: T_i^{delta-1} plus every tetrahedron sharing a vertex with it
 //    ("adjacent" read as vertex adjacency: the only reading under which the
 //    support of the P1 function chi~_i stays inside T_i^delta);
-//  * R_i: restriction to the non-PEC edges of T_i^delta, in ascending order;
+//  * R_i: restriction to the non-PEC edges of T_i^delta; locally numbered with
+//    the zero-weight unknowns first (ascending), then the others (ascending);
 //  * partition of unity, equations (algebPartUnity) and (chi):
 //    chi~_i = 1 on the nodes of T_i^0, 0 on the other nodes of T_i^delta,
 //    chi_i = chi~_i / sum_j chi~_j, and D_i[e] is chi_i at the midpoint of e
@@ -28,6 +29,7 @@ static const int kFaceEdge[4][3] = {{0, 1, 3}, {0, 2, 4}, {1, 2, 5}, {3, 4, 5}};
 
 namespace {
 struct SubTmp {
+  int32_t n_lead = 0;
   std::vector<int32_t> tets, edges, lt_loc, lf_vert, lf_owner, lf_kind, lf_loc;
   std::vector<double> D;
   std::vector<int64_t> rtl_ptr, rfl_ptr;
@@ -150,15 +152,29 @@ void build_decomposition(const Topology& T, const int32_t* part, int32_t nsub, i
       }
     std::sort(o.edges.begin(), o.edges.end());
     const int32_t ni = (int32_t)o.edges.size();
-    for (int32_t l = 0; l < ni; ++l) s.eloc[o.edges[l]] = l;
-    o.D.resize(ni);
+    // weights, then the local numbering: unknowns with D = 0 first (they are
+    // discarded after the local solve, so the backward substitution can stop
+    // at the first block holding a weighted unknown), each group ascending
+    std::vector<double> Dg(ni);
     for (int32_t l = 0; l < ni; ++l) {
       int64_t e = o.edges[l];
       int32_t a = (int32_t)T.edges[e * 2], b = (int32_t)T.edges[e * 2 + 1];
       double ca = s.node0[a] == stamp ? 1.0 / cnt[a] : 0.0;
       double cb = s.node0[b] == stamp ? 1.0 / cnt[b] : 0.0;
-      o.D[l] = 0.5 * (ca + cb);
+      Dg[l] = 0.5 * (ca + cb);
     }
+    {
+      std::vector<int32_t> ord(ni);
+      int32_t z = 0;
+      for (int32_t l = 0; l < ni; ++l) if (Dg[l] == 0.0) ord[z++] = l;
+      o.n_lead = z;
+      for (int32_t l = 0; l < ni; ++l) if (Dg[l] != 0.0) ord[z++] = l;
+      std::vector<int32_t> e2(ni);
+      o.D.resize(ni);
+      for (int32_t l = 0; l < ni; ++l) { e2[l] = o.edges[ord[l]]; o.D[l] = Dg[ord[l]]; }
+      o.edges.swap(e2);
+    }
+    for (int32_t l = 0; l < ni; ++l) s.eloc[o.edges[l]] = l;
     auto lidx = [&](int32_t e) -> int32_t { return T.pec[e] ? -1 : s.eloc[e]; };
     o.lt_loc.resize(o.tets.size() * 6);
     for (size_t k = 0; k < o.tets.size(); ++k) {
@@ -209,11 +225,12 @@ void build_decomposition(const Topology& T, const int32_t* part, int32_t nsub, i
   Decomposition& D = out;
   D = Decomposition();
   D.nsub = nsub; D.delta = delta;
-  D.n_loc.resize(nsub); D.n_pad.resize(nsub);
+  D.n_loc.resize(nsub); D.n_pad.resize(nsub); D.n_lead.resize(nsub);
   D.loc_off.assign(nsub + 1, 0); D.fac_off.assign(nsub + 1, 0);
   D.lt_off.assign(nsub + 1, 0); D.lf_off.assign(nsub + 1, 0);
   for (int32_t i = 0; i < nsub; ++i) {
     D.n_loc[i] = (int32_t)sub[i].edges.size();
+    D.n_lead[i] = sub[i].n_lead;
     D.n_pad[i] = (int32_t)round_up(std::max(D.n_loc[i], 1), block);
     D.loc_off[i + 1] = D.loc_off[i] + D.n_pad[i];
     D.fac_off[i + 1] = D.fac_off[i] + (int64_t)D.n_pad[i] * D.n_pad[i];
@@ -255,16 +272,19 @@ void build_decomposition(const Topology& T, const int32_t* part, int32_t nsub, i
     }
   }
   // prolongation copies of every dof, ascending subdomain order
+  // (copies with a zero weight contribute nothing and are left out)
   D.cp_ptr.assign(n + 1, 0);
-  for (int64_t r = 0; r < sp; ++r) if (D.sub_dof[r] >= 0) D.cp_ptr[D.sub_dof[r] + 1]++;
+  for (int64_t r = 0; r < sp; ++r) if (D.sub_dof[r] >= 0 && D.D[r] != 0.0) D.cp_ptr[D.sub_dof[r] + 1]++;
   for (int64_t g = 0; g < n; ++g) {
     MW_CHECK(D.cp_ptr[g + 1] > 0, MW_EINVAL, "decomposition leaves an unknown uncovered");
     D.cp_ptr[g + 1] += D.cp_ptr[g];
   }
   D.cp_row.resize(D.cp_ptr[n]);
   {
+    // ascending subdomain order for every unknown
     std::vector<int64_t> fill(D.cp_ptr.begin(), D.cp_ptr.end() - 1);
-    for (int64_t r = 0; r < sp; ++r) if (D.sub_dof[r] >= 0) D.cp_row[fill[D.sub_dof[r]]++] = r;
+    for (int64_t r = 0; r < sp; ++r)
+      if (D.sub_dof[r] >= 0 && D.D[r] != 0.0) D.cp_row[fill[D.sub_dof[r]]++] = r;
   }
 }
 

@@ -160,44 +160,49 @@ __global__ void __launch_bounds__(256) k_gemm_lu(typename cplx<R>::t* F, const i
                       Fi + (int64_t)r0 * np + c0, np, M, N, k1 - k0, tm, tn);
 }
 
-// Wide tile for the triangular-solve updates: C[64 rows x NCB*16 columns] -= A * B
-// with every right-hand-side column of the tile in one workgroup, so each
-// factor block (A) is read once per launch.  Wave w owns rows 16w..16w+15 of
-// the tile and all its column blocks; the next K stage is fetched into
-// registers while the current one is multiplied out of LDS.
-constexpr int WBK = 16;   // complex K per stage
+// Wide tile for the triangular-solve updates: C[64 x 32*WC] -= A[64 x K] B[K x 32*WC]
+// (or C = A B).  Four waves in a 2 x 2 arrangement, each owning 32 rows x
+// 16*WC columns (2 x WC MFMA blocks); every right-hand-side column of the
+// tile is in one workgroup, so each factor block (A) is read once per
+// launch.  K advances by WBK complex per stage through double-buffered LDS:
+// the next stage is fetched into registers while the current one is
+// multiplied, then written to the other buffer (one barrier per stage).
 // AMODE 0: A as stored; 1: unit lower triangle of A (strict part stored,
 // implicit ones); 2: upper triangle of A with its diagonal.  OVERWRITE:
-// C = A B instead of C -= A B (B may alias C: every B row of the tile is
-// read before the epilogue writes).
-template <class R, int NCB, int AMODE = 0, bool OVERWRITE = false>
-__device__ inline void gemm_wide(const typename cplx<R>::t* __restrict__ A, int64_t lda,
+// C = A B (B may alias C: all B rows of the tile are read before the
+// epilogue writes).
+constexpr int WBK = 8;    // complex K per stage
+template <class R, int WC, int AMODE = 0, bool OVERWRITE = false>
+__device__ __attribute__((always_inline)) inline void gemm_wide(const typename cplx<R>::t* __restrict__ A, int64_t lda,
                                  const typename cplx<R>::t* B, int64_t ldb,
                                  typename cplx<R>::t* Cm, int64_t ldc, int M, int N, int K) {
   using C = typename cplx<R>::t;
   using acc_t = typename Mf<R>::acc;
-  constexpr int TN = NCB * 16;
-  constexpr int AREG = 64 * WBK / 256;          // complex A values per thread per stage
-  constexpr int BREG = (WBK * TN + 255) / 256;  // complex B values per thread per stage
-  __shared__ R As[64][2 * WBK + 1];
-  __shared__ C Bs[WBK][TN + 1];
+  constexpr int TM = 64, TN = 32 * WC;
+  constexpr int AREG = TM * WBK / 256;
+  constexpr int BREG = (WBK * TN + 255) / 256;
+  __shared__ R As[2][TM][2 * WBK + 1];
+  __shared__ C Bs[2][WBK][TN + 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
   const int li = lane & 15, kq = lane >> 4;
-  acc_t accr[NCB], acci[NCB];
+  acc_t accr[2][WC], acci[2][WC];
 #pragma unroll
-  for (int b = 0; b < NCB; ++b)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) { accr[b][r] = 0; acci[b][r] = 0; }
+    for (int y = 0; y < WC; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) { accr[x][y][r] = 0; acci[x][y][r] = 0; }
   C ra[AREG], rb[BREG];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < AREG; ++e) {
       int idx = tid + e * 256;
       int r = idx / WBK, kc = idx % WBK;
+      const int kk = k0 + kc;
       C v;
       v.x = 0; v.y = 0;
-      const int kk = k0 + kc;
       if (r < M && kk < K) {
         if (AMODE == 0 || (AMODE == 1 && kk < r) || (AMODE == 2 && kk >= r)) v = A[(int64_t)r * lda + kk];
         else if (AMODE == 1 && kk == r) v.x = 1;
@@ -214,51 +219,67 @@ __device__ inline void gemm_wide(const typename cplx<R>::t* __restrict__ A, int6
       rb[e] = v;
     }
   };
-  fetch(0);
-  for (int k0 = 0; k0 < K; k0 += WBK) {
+  auto store = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < AREG; ++e) {
       int idx = tid + e * 256;
       int r = idx / WBK, kc = idx % WBK;
-      As[r][2 * kc] = ra[e].x;
-      As[r][2 * kc + 1] = ra[e].y;
+      As[buf][r][2 * kc] = ra[e].x;
+      As[buf][r][2 * kc + 1] = ra[e].y;
     }
 #pragma unroll
     for (int e = 0; e < BREG; ++e) {
       int idx = tid + e * 256;
-      if (idx < WBK * TN) Bs[idx / TN][idx % TN] = rb[e];
+      if (idx < WBK * TN) Bs[buf][idx / TN][idx % TN] = rb[e];
     }
-    __syncthreads();
-    if (k0 + WBK < K) fetch(k0 + WBK);
+  };
+  fetch(0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < K; k0 += WBK) {
+    const bool more = k0 + WBK < K;
+    if (more) fetch(k0 + WBK);
 #pragma unroll
     for (int kk = 0; kk < WBK; kk += 2) {
-      R a = As[wave * 16 + li][2 * kk + kq];
+      R a[2], br[WC], bi[WC];
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) {
-        C b = Bs[kk + (kq >> 1)][cb * 16 + li];
+      for (int x = 0; x < 2; ++x) a[x] = As[buf][wm * 32 + x * 16 + li][2 * kk + kq];
+#pragma unroll
+      for (int y = 0; y < WC; ++y) {
+        C b = Bs[buf][kk + (kq >> 1)][wn * 16 * WC + y * 16 + li];
         bool odd = kq & 1;
-        R br = odd ? -b.y : b.x;
-        R bi = odd ? b.x : b.y;
-        accr[cb] = Mf<R>::mfma(a, br, accr[cb]);
-        acci[cb] = Mf<R>::mfma(a, bi, acci[cb]);
+        br[y] = odd ? -b.y : b.x;
+        bi[y] = odd ? b.x : b.y;
       }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < WC; ++y) {
+          accr[x][y] = Mf<R>::mfma(a[x], br[y], accr[x][y]);
+          acci[x][y] = Mf<R>::mfma(a[x], bi[y], acci[x][y]);
+        }
     }
+    if (more) store(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
-  for (int cb = 0; cb < NCB; ++cb)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int gr = wave * 16 + Mf<R>::out_row(lane, r);
-      int gc = cb * 16 + li;
-      if (gr < M && gc < N) {
-        C* p = Cm + (int64_t)gr * ldc + gc;
-        C o;
-        if (OVERWRITE) { o.x = accr[cb][r]; o.y = acci[cb][r]; }
-        else { o = *p; o.x -= accr[cb][r]; o.y -= acci[cb][r]; }
-        *p = o;
+    for (int y = 0; y < WC; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int gr = wm * 32 + x * 16 + Mf<R>::out_row(lane, r);
+        int gc = wn * 16 * WC + y * 16 + li;
+        if (gr < M && gc < N) {
+          C* p = Cm + (int64_t)gr * ldc + gc;
+          C o;
+          if (OVERWRITE) { o.x = accr[x][y][r]; o.y = acci[x][y][r]; }
+          else { o = *p; o.x -= accr[x][y][r]; o.y -= acci[x][y][r]; }
+          *p = o;
+        }
       }
-    }
 }
 
 // Triangular-solve update on the local multi-vector of every subdomain:
@@ -266,12 +287,13 @@ __device__ inline void gemm_wide(const typename cplx<R>::t* __restrict__ A, int6
 // 1-D grid of nsub * tiles_per_sub (padded to a multiple of 8) workgroups;
 // the linear id is remapped so that the tiles of one subdomain run on one XCD
 // (workgroups are dealt to the 8 XCDs round-robin) and share its L2.
-template <class R, int NCB>
+template <class R, int WC>
 __global__ void __launch_bounds__(256) k_gemm_x(const typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
                                                 const int32_t* __restrict__ n_pad,
                                                 const int64_t* __restrict__ loc_off, typename cplx<R>::t* Y,
                                                 int64_t ld, int ncols, int r0, int r1, int k0, int k1,
-                                                int tiles_m, int tiles_n, int nsub) {
+                                                int tiles_m, int tiles_n, int nsub,
+                                                const int32_t* __restrict__ row_lo) {
   using C = typename cplx<R>::t;
   const int per_sub = tiles_m * tiles_n;
   const int G = gridDim.x;
@@ -284,22 +306,24 @@ __global__ void __launch_bounds__(256) k_gemm_x(const typename cplx<R>::t* F, co
   const int M = min(r1, np) - r0 - tm * 64;
   const int K = min(k1, np) - k0;
   if (M <= 0 || K <= 0) return;
-  const int TN = NCB * 16;
+  const int TN = WC * 32;
   const int N = min(ncols - tn * TN, TN);
   const C* Fi = F + fac_off[i];
   C* Yi = Y + loc_off[i] * ld;
   const int row = r0 + tm * 64;
-  gemm_wide<R, NCB>(Fi + (int64_t)row * np + k0, np, Yi + (int64_t)k0 * ld + tn * TN, ld,
+  if (row_lo && row + 64 <= row_lo[i]) return;   // rows discarded by the weights
+  gemm_wide<R, WC>(Fi + (int64_t)row * np + k0, np, Yi + (int64_t)k0 * ld + tn * TN, ld,
                     Yi + (int64_t)row * ld + tn * TN, ld, M, N, K);
 }
 
 // Leaf of the blocked triangular solves: Y[r0:r0+64] = T^-1 Y[r0:r0+64] with the
 // inverted diagonal block (AMODE 1: L^-1, 2: U^-1), in place, all columns.
-template <class R, int NCB, int AMODE>
+template <class R, int WC, int AMODE>
 __global__ void __launch_bounds__(256) k_leaf_x(const typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
                                                 const int32_t* __restrict__ n_pad,
                                                 const int64_t* __restrict__ loc_off, typename cplx<R>::t* Y,
-                                                int64_t ld, int ncols, int r0, int tiles_n, int nsub) {
+                                                int64_t ld, int ncols, int r0, int tiles_n, int nsub,
+                                                const int32_t* __restrict__ row_lo) {
   using C = typename cplx<R>::t;
   const int G = gridDim.x;
   const int logical = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
@@ -307,12 +331,48 @@ __global__ void __launch_bounds__(256) k_leaf_x(const typename cplx<R>::t* F, co
   if (i >= nsub) return;
   const int tn = logical % tiles_n;
   const int np = n_pad[i];
-  if (r0 >= np) return;
-  const int TN = NCB * 16;
+  if (r0 >= np || (row_lo && r0 < row_lo[i])) return;
+  const int TN = WC * 32;
   const int N = min(ncols - tn * TN, TN);
   const C* blk = F + fac_off[i] + (int64_t)r0 * np + r0;
   C* Yb = Y + (loc_off[i] + r0) * ld + tn * TN;
-  gemm_wide<R, NCB, AMODE, true>(blk, np, Yb, ld, Yb, ld, NB, N, NB);
+  gemm_wide<R, WC, AMODE, true>(blk, np, Yb, ld, Yb, ld, NB, N, NB);
+}
+
+// LU update with wide tiles: F[r0:np, c0:min(c1,np)] -= F[r0:np, k0:k1] F[k0:k1, c0:min(c1,np)]
+// on every subdomain; 1-D XCD-aware grid of nsub * tiles_m * tiles_n.
+template <class R, int WC>
+__global__ void __launch_bounds__(256) k_gemm_luw(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
+                                                  const int32_t* __restrict__ n_pad, int r0, int k0, int k1, int c0,
+                                                  int c1, int tiles_m, int tiles_n, int nsub) {
+  using C = typename cplx<R>::t;
+  const int per_sub = tiles_m * tiles_n;
+  const int G = gridDim.x;
+  const int logical = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  const int i = logical / per_sub;
+  if (i >= nsub) return;
+  const int t = logical % per_sub;
+  const int tm = t / tiles_n, tn = t % tiles_n;
+  const int np = n_pad[i];
+  const int M = np - r0 - tm * 64;
+  const int N = min(c1, np) - c0 - tn * 32 * WC;
+  if (M <= 0 || N <= 0 || k1 > np) return;
+  C* Fi = F + fac_off[i];
+  const int row = r0 + tm * 64, col = c0 + tn * 32 * WC;
+  gemm_wide<R, WC>(Fi + (int64_t)row * np + k0, np, Fi + (int64_t)k0 * np + col, np, Fi + (int64_t)row * np + col,
+                   np, M, min(N, 32 * WC), k1 - k0);
+}
+
+template <class R, int WC>
+static void launch_gemm_lu(const DeviceDecomp& d, typename cplx<R>::t* F, int r0, int k0, int k1, int c0, int c1,
+                           int maxp, hipStream_t st) {
+  int tiles_m = (int)ceil_div(maxp - r0, 64);
+  int tiles_n = (int)ceil_div(std::min(c1, maxp) - c0, 32 * WC);
+  if (tiles_m <= 0 || tiles_n <= 0) return;
+  int64_t G = round_up((int64_t)d.nsub * tiles_m * tiles_n, 8);
+  k_gemm_luw<R, WC><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, r0, k0, k1, c0, c1, tiles_m, tiles_n,
+                                                 d.nsub);
+  MW_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------- pivot reduction
@@ -637,11 +697,8 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st) {
       }, (int)sizeof(C));
       int r0 = c + W0, c1 = k + NB;
       if (r0 < c1) {
-        int M = maxp - r0, N = c1 - r0;
-        unsigned tiles = (unsigned)(ceil_div(M, TB) * ceil_div(N, TB));
         kt_begin(KF_LU_GEMM, st);
-        k_gemm_lu<R><<<dim3(tiles, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, r0, c, c + W0, r0, c1);
-        MW_LAUNCH_CHECK();
+        launch_gemm_lu<R, 2>(d, F, r0, c, c + W0, r0, c1, maxp, st);
         kt_account(d, KF_LU_GEMM, st, [&](int n, double& f, double& b) {
           double M = clampd(n - r0), N = clampd(std::min(c1, n) - r0), K = clampd(std::min(c + W0, n) - c);
           f = 8.0 * M * N * K;
@@ -690,29 +747,59 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st) {
   MW_LAUNCH_CHECK();
 }
 
-// Y[r0:r1] -= F[r0:r1, k0:k1] Y[k0:k1] on every subdomain (wide tiles: 160
-// columns per tile in FP32, 80 in FP64)
+// Tile width (columns) for a multi-vector of ncols columns: the narrowest of
+// 32, 64, ... that holds it, up to 160 (FP32) or 64 (FP64) per tile (wider
+// FP64 tiles drop to one wave per SIMD).
 template <class R>
-static void launch_gemm_x(const DeviceDecomp& d, const typename cplx<R>::t* F, typename cplx<R>::t* Y, int64_t ld,
-                          int ncols, int r0, int r1, int k0, int k1, hipStream_t st) {
-  constexpr int NCB = sizeof(R) == 4 ? 10 : 5;
-  int tiles_m = (int)ceil_div(r1 - r0, 64);
-  int tiles_n = (int)ceil_div(ncols, NCB * 16);
-  int64_t G = round_up((int64_t)d.nsub * tiles_m * tiles_n, 8);
-  k_gemm_x<R, NCB><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, Y, ld, ncols, r0, r1, k0, k1,
-                                                tiles_m, tiles_n, d.nsub);
-  MW_LAUNCH_CHECK();
+static int pick_wc(int ncols) {
+  const int maxwc = sizeof(R) == 4 ? 5 : 2;
+  int wc = (int)ceil_div(ncols, 32);
+  return wc > maxwc ? maxwc : (wc < 1 ? 1 : wc);
 }
 
+// Y[r0:r1] -= F[r0:r1, k0:k1] Y[k0:k1] on every subdomain
+template <class R, int WC>
+static void launch_gemm_x_wc(const DeviceDecomp& d, const typename cplx<R>::t* F, typename cplx<R>::t* Y,
+                             int64_t ld, int ncols, int r0, int r1, int k0, int k1, const int32_t* row_lo,
+                             hipStream_t st) {
+  int tiles_m = (int)ceil_div(r1 - r0, 64);
+  int tiles_n = (int)ceil_div(ncols, WC * 32);
+  int64_t G = round_up((int64_t)d.nsub * tiles_m * tiles_n, 8);
+  k_gemm_x<R, WC><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, Y, ld, ncols, r0, r1, k0, k1,
+                                               tiles_m, tiles_n, d.nsub, row_lo);
+  MW_LAUNCH_CHECK();
+}
+template <class R>
+static void launch_gemm_x(const DeviceDecomp& d, const typename cplx<R>::t* F, typename cplx<R>::t* Y, int64_t ld,
+                          int ncols, int r0, int r1, int k0, int k1, const int32_t* row_lo, hipStream_t st) {
+  switch (pick_wc<R>(ncols)) {
+    case 1: launch_gemm_x_wc<R, 1>(d, F, Y, ld, ncols, r0, r1, k0, k1, row_lo, st); break;
+    case 2: launch_gemm_x_wc<R, 2>(d, F, Y, ld, ncols, r0, r1, k0, k1, row_lo, st); break;
+    case 3: launch_gemm_x_wc<R, sizeof(R) == 4 ? 3 : 2>(d, F, Y, ld, ncols, r0, r1, k0, k1, row_lo, st); break;
+    case 4: launch_gemm_x_wc<R, sizeof(R) == 4 ? 4 : 2>(d, F, Y, ld, ncols, r0, r1, k0, k1, row_lo, st); break;
+    default: launch_gemm_x_wc<R, sizeof(R) == 4 ? 5 : 2>(d, F, Y, ld, ncols, r0, r1, k0, k1, row_lo, st); break;
+  }
+}
+
+template <class R, int WC, int AMODE>
+static void launch_leaf_x_wc(const DeviceDecomp& d, const typename cplx<R>::t* F, typename cplx<R>::t* Y,
+                             int64_t ld, int ncols, int r0, const int32_t* row_lo, hipStream_t st) {
+  int tiles_n = (int)ceil_div(ncols, WC * 32);
+  int64_t G = round_up((int64_t)d.nsub * tiles_n, 8);
+  k_leaf_x<R, WC, AMODE><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, Y, ld, ncols, r0, tiles_n,
+                                                     d.nsub, row_lo);
+  MW_LAUNCH_CHECK();
+}
 template <class R, int AMODE>
 static void launch_leaf_x(const DeviceDecomp& d, const typename cplx<R>::t* F, typename cplx<R>::t* Y, int64_t ld,
-                          int ncols, int r0, hipStream_t st) {
-  constexpr int NCB = sizeof(R) == 4 ? 10 : 5;
-  int tiles_n = (int)ceil_div(ncols, NCB * 16);
-  int64_t G = round_up((int64_t)d.nsub * tiles_n, 8);
-  k_leaf_x<R, NCB, AMODE><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, Y, ld, ncols, r0, tiles_n,
-                                                      d.nsub);
-  MW_LAUNCH_CHECK();
+                          int ncols, int r0, const int32_t* row_lo, hipStream_t st) {
+  switch (pick_wc<R>(ncols)) {
+    case 1: launch_leaf_x_wc<R, 1, AMODE>(d, F, Y, ld, ncols, r0, row_lo, st); break;
+    case 2: launch_leaf_x_wc<R, 2, AMODE>(d, F, Y, ld, ncols, r0, row_lo, st); break;
+    case 3: launch_leaf_x_wc<R, sizeof(R) == 4 ? 3 : 2, AMODE>(d, F, Y, ld, ncols, r0, row_lo, st); break;
+    case 4: launch_leaf_x_wc<R, sizeof(R) == 4 ? 4 : 2, AMODE>(d, F, Y, ld, ncols, r0, row_lo, st); break;
+    default: launch_leaf_x_wc<R, sizeof(R) == 4 ? 5 : 2, AMODE>(d, F, Y, ld, ncols, r0, row_lo, st); break;
+  }
 }
 
 template <class R>
@@ -721,7 +808,7 @@ static void fwd_rec(const DeviceDecomp& d, const typename cplx<R>::t* F, typenam
   const int esz = (int)sizeof(typename cplx<R>::t);
   if (b1 - b0 == 1) {
     kt_begin(KF_TRSM_LEAF, st);
-    launch_leaf_x<R, 1>(d, F, Y, ld, ncols, b0 * NB, st);
+    launch_leaf_x<R, 1>(d, F, Y, ld, ncols, b0 * NB, nullptr, st);
     MW_LAUNCH_CHECK();
     kt_account(d, KF_TRSM_LEAF, st, [&](int n, double& f, double& b) {
       double m = clampd(std::min((b0 + 1) * NB, n) - b0 * NB);
@@ -733,7 +820,7 @@ static void fwd_rec(const DeviceDecomp& d, const typename cplx<R>::t* F, typenam
   int mid = b0 + (b1 - b0) / 2;
   fwd_rec<R>(d, F, Y, ncols, ld, b0, mid, st);
   kt_begin(KF_TRSM_GEMM, st);
-  launch_gemm_x<R>(d, F, Y, ld, ncols, mid * NB, b1 * NB, b0 * NB, mid * NB, st);
+  launch_gemm_x<R>(d, F, Y, ld, ncols, mid * NB, b1 * NB, b0 * NB, mid * NB, nullptr, st);
   MW_LAUNCH_CHECK();
   kt_account(d, KF_TRSM_GEMM, st, [&](int n, double& f, double& b) {
     double Mi = clampd(std::min(b1 * NB, n) - mid * NB), Ki = clampd(std::min(mid * NB, n) - b0 * NB);
@@ -749,10 +836,12 @@ static void bwd_rec(const DeviceDecomp& d, const typename cplx<R>::t* F, typenam
   const int esz = (int)sizeof(typename cplx<R>::t);
   if (b1 - b0 == 1) {
     kt_begin(KF_TRSM_LEAF, st);
-    launch_leaf_x<R, 2>(d, F, Y, ld, ncols, b0 * NB, st);
+    launch_leaf_x<R, 2>(d, F, Y, ld, ncols, b0 * NB, d.row_lo, st);
     MW_LAUNCH_CHECK();
+    int sub = 0;
     kt_account(d, KF_TRSM_LEAF, st, [&](int n, double& f, double& b) {
-      double m = clampd(std::min((b0 + 1) * NB, n) - b0 * NB);
+      const int lo = d.h_row_lo[sub++];
+      double m = b0 * NB < lo ? 0.0 : clampd(std::min((b0 + 1) * NB, n) - b0 * NB);
       f = 4.0 * m * m * ncols;
       b = m * m / 2 + 2 * m * ncols;
     }, esz);
@@ -761,13 +850,17 @@ static void bwd_rec(const DeviceDecomp& d, const typename cplx<R>::t* F, typenam
   int mid = b0 + (b1 - b0) / 2;
   bwd_rec<R>(d, F, Y, ncols, ld, mid, b1, st);
   kt_begin(KF_TRSM_GEMM, st);
-  launch_gemm_x<R>(d, F, Y, ld, ncols, b0 * NB, mid * NB, mid * NB, b1 * NB, st);
+  launch_gemm_x<R>(d, F, Y, ld, ncols, b0 * NB, mid * NB, mid * NB, b1 * NB, d.row_lo, st);
   MW_LAUNCH_CHECK();
-  kt_account(d, KF_TRSM_GEMM, st, [&](int n, double& f, double& b) {
-    double Mi = clampd(std::min(mid * NB, n) - b0 * NB), Ki = clampd(std::min(b1 * NB, n) - mid * NB);
-    f = 8.0 * Mi * Ki * ncols;
-    b = Mi * Ki + Ki * ncols + 2 * Mi * ncols;
-  }, esz);
+  {
+    int sub = 0;
+    kt_account(d, KF_TRSM_GEMM, st, [&](int n, double& f, double& b) {
+      const int lo = d.h_row_lo[sub++];
+      double Mi = clampd(std::min(mid * NB, n) - std::max(b0 * NB, lo)), Ki = clampd(std::min(b1 * NB, n) - mid * NB);
+      f = 8.0 * Mi * Ki * ncols;
+      b = Mi * Ki + Ki * ncols + 2 * Mi * ncols;
+    }, esz);
+  }
   bwd_rec<R>(d, F, Y, ncols, ld, b0, mid, st);
 }
 

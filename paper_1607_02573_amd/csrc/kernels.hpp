@@ -83,6 +83,8 @@ struct DeviceDecomp {
   int32_t* info = nullptr;      // [nsub] first (near-)zero-pivot column + 1, 0 if none
   double* amax = nullptr;       // [nsub] max |re|+|im| of B_i
   const int32_t* h_n_loc = nullptr;  // host copy of n_loc (launch accounting)
+  const int32_t* row_lo = nullptr;   // [nsub] first row (multiple of 64) the backward solve must produce
+  const int32_t* h_row_lo = nullptr; // host copy
 };
 
 // ---- assembly (assemble.hip)

@@ -248,3 +248,20 @@ def test_error_paths(ctx):
         P3.solve(P3.rhs_dipoles(w.dipoles), tol=1e-12, maxit=3)
     assert e.value.code == binding.MW_ENOCONV
     P3.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-11), ("c64", 1e-5)])
+def test_preconditioner_column_counts(chamber_small, prec, tol):
+    """Every tile width of the batched triangular solves (1 .. >160 columns)."""
+    w, fp, P = chamber_small
+    P.factor(w.part, w.n_sub, 1, prec)
+    subs = dd.decompose(fp, w.part, 1)
+    rng = np.random.default_rng(5)
+    for nc in (1, 3, 33, 65, 97, 130, 170):
+        V = rng.normal(size=(P.n, nc)) + 1j * rng.normal(size=(P.n, nc))
+        Zg = P.apply_preconditioner(torch.from_numpy(V).cuda()).cpu().numpy()
+        Zo = dd.oras_apply(subs, V)
+        assert _rel(Zg, Zo) <= tol, nc
+        # each column is independent of the others (bitwise)
+        Z1 = P.apply_preconditioner(torch.from_numpy(np.ascontiguousarray(V[:, :1])).cuda()).cpu().numpy()
+        assert np.array_equal(Z1[:, 0], Zg[:, 0]), nc
