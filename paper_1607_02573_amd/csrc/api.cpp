@@ -705,6 +705,9 @@ static int solve_chunk_cols(mw_problem* p, int nrhs, int m) {
                            p->w_Y.b.bytes + p->w_part.b.bytes);
   int64_t avail = c->budget - c->used + held;
   int64_t cols = avail / std::max<int64_t>(per, 1);
+  // when the columns must be split, use multiples of 32 (the width granule of
+  // the triangular-solve tiles) so that no tile runs half empty
+  if (cols < nrhs && cols >= 32) cols = (cols / 32) * 32;
   return (int)std::min<int64_t>(nrhs, std::max<int64_t>(cols, 0));
 }
 

@@ -282,6 +282,114 @@ __device__ __attribute__((always_inline)) inline void gemm_wide(const typename c
       }
 }
 
+// Complex FP32 product by the 3M (Gauss) form: with P1 = Ar Br, P2 = Ai Bi and
+// P3 = (Ar + Ai)(Br + Bi) (three real 16x16x4 MFMA products, K = 4 complex per
+// instruction), Re = P1 - P2 and Im = P3 - P1 - P2: 3/4 of the real MFMA work of
+// the 4M form.  Used for the FP32 preconditioner updates only (its rounding is
+// slightly larger in the imaginary part; the FP64 path keeps 4M).
+// Tile: 32 rows x 32*WC columns, waves 2 x 2 (16 rows x 16*WC columns each),
+// C -= A B, double-buffered LDS stages of G3K complex.
+constexpr int G3K = 8;
+template <int WC>
+__device__ __attribute__((always_inline)) inline void gemm3m(const float2* __restrict__ A, int64_t lda,
+                                                             const float2* B, int64_t ldb, float2* Cm,
+                                                             int64_t ldc, int M, int N, int K) {
+  using acc_t = typename Mf<float>::acc;
+  constexpr int TM = 32, TN = 32 * WC;
+  constexpr int AREG = TM * G3K / 256;
+  constexpr int BREG = (G3K * TN + 255) / 256;
+  __shared__ float As[2][3][TM][G3K + 1];
+  __shared__ float Bs[2][3][G3K][TN + 1];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, kq = lane >> 4;
+  acc_t p1[WC], p2[WC], p3[WC];
+#pragma unroll
+  for (int y = 0; y < WC; ++y)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) { p1[y][r] = 0; p2[y][r] = 0; p3[y][r] = 0; }
+  float2 ra[AREG], rb[BREG];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < AREG; ++e) {
+      int idx = tid + e * 256;
+      int r = idx / G3K, kc = idx % G3K;
+      float2 v = make_float2(0.f, 0.f);
+      if (r < M && k0 + kc < K) v = A[(int64_t)r * lda + k0 + kc];
+      ra[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < BREG; ++e) {
+      int idx = tid + e * 256;
+      int r = idx / TN, c = idx % TN;
+      float2 v = make_float2(0.f, 0.f);
+      if (idx < G3K * TN && k0 + r < K && c < N) v = B[(int64_t)(k0 + r) * ldb + c];
+      rb[e] = v;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < AREG; ++e) {
+      int idx = tid + e * 256;
+      int r = idx / G3K, kc = idx % G3K;
+      As[buf][0][r][kc] = ra[e].x;
+      As[buf][1][r][kc] = ra[e].y;
+      As[buf][2][r][kc] = ra[e].x + ra[e].y;
+    }
+#pragma unroll
+    for (int e = 0; e < BREG; ++e) {
+      int idx = tid + e * 256;
+      if (idx < G3K * TN) {
+        int r = idx / TN, c = idx % TN;
+        Bs[buf][0][r][c] = rb[e].x;
+        Bs[buf][1][r][c] = rb[e].y;
+        Bs[buf][2][r][c] = rb[e].x + rb[e].y;
+      }
+    }
+  };
+  fetch(0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < K; k0 += G3K) {
+    const bool more = k0 + G3K < K;
+    if (more) fetch(k0 + G3K);
+#pragma unroll
+    for (int kk = 0; kk < G3K; kk += 4) {
+      const int row = wm * 16 + li;
+      float a1 = As[buf][0][row][kk + kq], a2 = As[buf][1][row][kk + kq], a3 = As[buf][2][row][kk + kq];
+#pragma unroll
+      for (int y = 0; y < WC; ++y) {
+        const int col = wn * 16 * WC + y * 16 + li;
+        p1[y] = Mf<float>::mfma(a1, Bs[buf][0][kk + kq][col], p1[y]);
+        p2[y] = Mf<float>::mfma(a2, Bs[buf][1][kk + kq][col], p2[y]);
+        p3[y] = Mf<float>::mfma(a3, Bs[buf][2][kk + kq][col], p3[y]);
+      }
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int y = 0; y < WC; ++y)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int gr = wm * 16 + Mf<float>::out_row(lane, r);
+      int gc = wn * 16 * WC + y * 16 + li;
+      if (gr < M && gc < N) {
+        float2* p = Cm + (int64_t)gr * ldc + gc;
+        float2 o = *p;
+        o.x -= p1[y][r] - p2[y][r];
+        o.y -= p3[y][r] - p1[y][r] - p2[y][r];
+        *p = o;
+      }
+    }
+}
+
+// rows per tile of the triangular-solve updates: 32 (3M, FP32) or 64 (4M, FP64)
+template <class R> struct XTile { static constexpr int TM = sizeof(R) == 4 ? 32 : 64; };
+
 // Triangular-solve update on the local multi-vector of every subdomain:
 // Y[r0:min(r1,np)] -= F[r0:min(r1,np), k0:min(k1,np)] * Y[k0:min(k1,np)].
 // 1-D grid of nsub * tiles_per_sub (padded to a multiple of 8) workgroups;
@@ -303,17 +411,22 @@ __global__ void __launch_bounds__(256) k_gemm_x(const typename cplx<R>::t* F, co
   const int t = logical % per_sub;
   const int tm = t / tiles_n, tn = t % tiles_n;
   const int np = n_pad[i];
-  const int M = min(r1, np) - r0 - tm * 64;
+  const int M = min(r1, np) - r0 - tm * XTile<R>::TM;
   const int K = min(k1, np) - k0;
   if (M <= 0 || K <= 0) return;
+  constexpr int TM = XTile<R>::TM;
   const int TN = WC * 32;
   const int N = min(ncols - tn * TN, TN);
   const C* Fi = F + fac_off[i];
   C* Yi = Y + loc_off[i] * ld;
-  const int row = r0 + tm * 64;
-  if (row_lo && row + 64 <= row_lo[i]) return;   // rows discarded by the weights
-  gemm_wide<R, WC>(Fi + (int64_t)row * np + k0, np, Yi + (int64_t)k0 * ld + tn * TN, ld,
-                    Yi + (int64_t)row * ld + tn * TN, ld, M, N, K);
+  const int row = r0 + tm * TM;
+  if (row_lo && row + TM <= row_lo[i]) return;   // rows discarded by the weights
+  if constexpr (sizeof(R) == 4)
+    gemm3m<WC>(Fi + (int64_t)row * np + k0, np, Yi + (int64_t)k0 * ld + tn * TN, ld,
+               Yi + (int64_t)row * ld + tn * TN, ld, M, N, K);
+  else
+    gemm_wide<R, WC>(Fi + (int64_t)row * np + k0, np, Yi + (int64_t)k0 * ld + tn * TN, ld,
+                     Yi + (int64_t)row * ld + tn * TN, ld, M, N, K);
 }
 
 // Leaf of the blocked triangular solves: Y[r0:r0+64] = T^-1 Y[r0:r0+64] with the
@@ -762,7 +875,7 @@ template <class R, int WC>
 static void launch_gemm_x_wc(const DeviceDecomp& d, const typename cplx<R>::t* F, typename cplx<R>::t* Y,
                              int64_t ld, int ncols, int r0, int r1, int k0, int k1, const int32_t* row_lo,
                              hipStream_t st) {
-  int tiles_m = (int)ceil_div(r1 - r0, 64);
+  int tiles_m = (int)ceil_div(r1 - r0, XTile<R>::TM);
   int tiles_n = (int)ceil_div(ncols, WC * 32);
   int64_t G = round_up((int64_t)d.nsub * tiles_m * tiles_n, 8);
   k_gemm_x<R, WC><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, Y, ld, ncols, r0, r1, k0, k1,
