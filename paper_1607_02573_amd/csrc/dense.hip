@@ -467,11 +467,12 @@ __global__ void __launch_bounds__(256) k_gemm_luw(typename cplx<R>::t* F, const 
   const int t = logical % per_sub;
   const int tm = t / tiles_n, tn = t % tiles_n;
   const int np = n_pad[i];
-  const int M = np - r0 - tm * 64;
+  constexpr int TM = 64;
+  const int M = np - r0 - tm * TM;
   const int N = min(c1, np) - c0 - tn * 32 * WC;
   if (M <= 0 || N <= 0 || k1 > np) return;
   C* Fi = F + fac_off[i];
-  const int row = r0 + tm * 64, col = c0 + tn * 32 * WC;
+  const int row = r0 + tm * TM, col = c0 + tn * 32 * WC;
   gemm_wide<R, WC>(Fi + (int64_t)row * np + k0, np, Fi + (int64_t)k0 * np + col, np, Fi + (int64_t)row * np + col,
                    np, M, min(N, 32 * WC), k1 - k0);
 }
@@ -593,6 +594,150 @@ __global__ void __launch_bounds__(256) k_lu_panel(typename cplx<R>::t* F, const 
     for (int r = 1; r < W0; ++r)
       for (int s = 0; s < r; ++s) x[r] = csub(x[r], cmul(Fi[(int64_t)(c + r) * np + c + s], x[s]));
     for (int r = 1; r < W0; ++r) Fi[(int64_t)(c + r) * np + cc] = x[r];
+  }
+}
+
+// Register-resident form of k_lu_panel (FP32): 1024 threads hold rows
+// [c, np) of the sub-panel columns [c, c+W0) in registers (row c + t + 1024 s
+// in slot s of thread t, np - c <= 1024 * RPT), so every row is read and
+// written once per sub-panel instead of once per column.  Pivot search,
+// interchange and rank-1 updates follow k_lu_panel exactly (same pivot rule,
+// same order of operations per entry).  One column step per instantiation of
+// panel_reg_col, so that every register index is a compile-time constant.
+struct PanelRegArgs {
+  float2* Fi;
+  Piv* red;
+  float2 (*prow)[W0];
+  int np, c, k, kend, tid;
+  int32_t* ipiv_i;   // ipiv + loc_off[i]
+  int32_t* info_i;   // info + i
+  double thr;        // rtol * max|B_i|
+};
+
+template <int J, int RPT>
+__device__ __forceinline__ void panel_reg_col(float2 (&v)[RPT][W0], const PanelRegArgs& g) {
+  const int col = g.c + J, tid = g.tid;
+  Piv best{-1.0, 0x7fffffff};
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) {
+    const int row = g.c + tid + 1024 * s;
+    if (row >= col && row < g.np) {
+      const double a = fabs((double)v[s][J].x) + fabs((double)v[s][J].y);
+      if (a > best.v) { best.v = a; best.idx = row; }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    Piv o;
+    o.v = __shfl_xor(best.v, off);
+    o.idx = __shfl_xor(best.idx, off);
+    best = piv_max(best, o);
+  }
+  if ((tid & 63) == 0) g.red[tid >> 6] = best;
+  __syncthreads();
+  best = g.red[0];
+  for (int w = 1; w < 16; ++w) best = piv_max(best, g.red[w]);
+  int p = best.idx;
+  const bool zero = !(best.v > 0.0);
+  const bool tiny = !(best.v > g.thr);
+  if (zero) p = col;
+  if (tid == 0) {
+    g.ipiv_i[col] = p;
+    if (tiny && *g.info_i == 0) *g.info_i = col + 1;
+  }
+  // rows col (thread J, slot 0) and p (thread tp, slot sp) exchange through
+  // LDS; prow[0] ends as the pivot row
+  const int tp = (p - g.c) & 1023, sp = (p - g.c) >> 10;
+#pragma unroll
+  for (int s = 0; s < RPT; ++s)
+    if (tid == tp && s == sp)
+#pragma unroll
+      for (int q = 0; q < W0; ++q) g.prow[0][q] = v[s][q];
+  if (tid == J && p != col)
+#pragma unroll
+    for (int q = 0; q < W0; ++q) g.prow[1][q] = v[0][q];
+  if (p != col) {
+    const int nout = (g.kend - g.k) - W0;   // panel columns outside [c, c+W0)
+    for (int e = tid; e < nout; e += 1024) {
+      int cc = g.k + e;
+      if (cc >= g.c) cc += W0;
+      const float2 t0 = g.Fi[(int64_t)col * g.np + cc];
+      g.Fi[(int64_t)col * g.np + cc] = g.Fi[(int64_t)p * g.np + cc];
+      g.Fi[(int64_t)p * g.np + cc] = t0;
+    }
+  }
+  __syncthreads();
+  if (p != col) {
+    if (tid == J)
+#pragma unroll
+      for (int q = 0; q < W0; ++q) v[0][q] = g.prow[0][q];
+#pragma unroll
+    for (int s = 0; s < RPT; ++s)
+      if (tid == tp && s == sp)
+#pragma unroll
+        for (int q = 0; q < W0; ++q) v[s][q] = g.prow[1][q];
+  }
+  float2 inv = make_float2(0.f, 0.f);
+  if (!zero) inv = cinv(g.prow[0][J]);
+  float2 u[W0];
+#pragma unroll
+  for (int q = J + 1; q < W0; ++q) u[q] = g.prow[0][q];
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) {
+    const int row = g.c + tid + 1024 * s;
+    if (row > col && row < g.np) {
+      const float2 l = cmul(v[s][J], inv);
+      v[s][J] = l;
+#pragma unroll
+      for (int q = J + 1; q < W0; ++q) v[s][q] = csub(v[s][q], cmul(l, u[q]));
+    }
+  }
+  __syncthreads();
+}
+
+template <int RPT>
+__global__ void __launch_bounds__(1024) k_lu_panel_reg(float2* F, const int64_t* __restrict__ fac_off,
+                                                       const int32_t* __restrict__ n_pad,
+                                                       const int64_t* __restrict__ loc_off, int32_t* ipiv,
+                                                       int32_t* info, const double* __restrict__ amax, double rtol,
+                                                       int c, int k) {
+  static_assert(W0 == 8, "column steps are spelled out for W0 = 8");
+  __shared__ Piv red[16];
+  __shared__ float2 prow[2][W0];
+  const int i = blockIdx.x;
+  const int np = n_pad[i];
+  if (c >= np) return;
+  PanelRegArgs g{F + fac_off[i], red, prow, np, c, k, min(k + NB, np), (int)threadIdx.x,
+                 ipiv + loc_off[i], info + i, rtol * amax[i]};
+  float2 v[RPT][W0];
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) {
+    const int row = c + g.tid + 1024 * s;
+#pragma unroll
+    for (int q = 0; q < W0; ++q) v[s][q] = row < np ? g.Fi[(int64_t)row * np + c + q] : make_float2(0.f, 0.f);
+  }
+  panel_reg_col<0, RPT>(v, g);
+  panel_reg_col<1, RPT>(v, g);
+  panel_reg_col<2, RPT>(v, g);
+  panel_reg_col<3, RPT>(v, g);
+  panel_reg_col<4, RPT>(v, g);
+  panel_reg_col<5, RPT>(v, g);
+  panel_reg_col<6, RPT>(v, g);
+  panel_reg_col<7, RPT>(v, g);
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) {
+    const int row = c + g.tid + 1024 * s;
+    if (row < np)
+#pragma unroll
+      for (int q = 0; q < W0; ++q) g.Fi[(int64_t)row * np + c + q] = v[s][q];
+  }
+  __syncthreads();
+  // U rows of the sub-panel for the remaining panel columns (unit lower solve)
+  for (int cc = c + W0 + g.tid; cc < g.kend; cc += 1024) {
+    float2 x[W0];
+    for (int r = 0; r < W0; ++r) x[r] = g.Fi[(int64_t)(c + r) * np + cc];
+    for (int r = 1; r < W0; ++r)
+      for (int q = 0; q < r; ++q) x[r] = csub(x[r], cmul(g.Fi[(int64_t)(c + r) * np + c + q], x[q]));
+    for (int r = 1; r < W0; ++r) g.Fi[(int64_t)(c + r) * np + cc] = x[r];
   }
 }
 
@@ -801,7 +946,16 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st) {
   for (int k = 0; k < maxp; k += NB) {
     for (int c = k; c < k + NB; c += W0) {
       kt_begin(KF_LU_PANEL, st);
-      k_lu_panel<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, d.amax, rtol, c, k);
+      if constexpr (sizeof(R) == 4) {
+        if (maxp - c <= 4096) {
+          k_lu_panel_reg<4><<<d.nsub, 1024, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, d.amax, rtol,
+                                                    c, k);
+        } else {
+          k_lu_panel<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, d.amax, rtol, c, k);
+        }
+      } else {
+        k_lu_panel<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, d.amax, rtol, c, k);
+      }
       MW_LAUNCH_CHECK();
       kt_account(d, KF_LU_PANEL, st, [&](int n, double& f, double& b) {
         double rows = clampd(n - c);
@@ -836,11 +990,13 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st) {
         f = 4.0 * NB * NB * N;
         b = NB * NB / 2.0 + 2.0 * NB * N;
       }, (int)sizeof(C));
-      int M = maxp - c0;
-      unsigned tiles = (unsigned)(ceil_div(M, TB) * ceil_div(M, TB));
       kt_begin(KF_LU_GEMM, st);
-      k_gemm_lu<R><<<dim3(tiles, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, c0, k, k + NB, c0, maxp);
-      MW_LAUNCH_CHECK();
+      {
+        int M = maxp - c0;
+        unsigned tiles = (unsigned)(ceil_div(M, TB) * ceil_div(M, TB));
+        k_gemm_lu<R><<<dim3(tiles, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, c0, k, k + NB, c0, maxp);
+        MW_LAUNCH_CHECK();
+      }
       kt_account(d, KF_LU_GEMM, st, [&](int n, double& f, double& b) {
         double M2 = clampd(n - c0), K = clampd(std::min(k + NB, n) - k);
         f = 8.0 * M2 * M2 * K;
