@@ -140,6 +140,47 @@ def cpu_baseline(w, iters_mean: float, nrhs: int, budget_s: float):
                        f"{iters_mean:.1f} iterations x (apply+SpMV+CGS2); single thread")}
 
 
+def serve_main(args):
+    """Continuous-batching service over a menu of problems: Poisson arrivals,
+    admission by bytes, factor cache with LRU eviction, one stream per problem."""
+    import torch
+
+    import mw_inputs as mi
+    from paper_1607_02573_amd import serve, solver
+    log("[serve] generating the menu (4 chamber meshes, 2 permittivity versions each)")
+    t0 = time.perf_counter()
+    menu = mi.serving.serving_menu()
+    log(f"[serve] menu ready in {time.perf_counter() - t0:.1f} s: " +
+        ", ".join(f"{e.name} {e.n_edges} edges / {e.workload.n_sub} subdomains" for e in menu))
+    reqs = mi.serving.serving_requests(n_req=args.serve_requests, rate=args.serve_rate)
+    total = torch.cuda.mem_get_info()[1]
+    ctx = solver.Context(0, budget_bytes=int(total - (32 << 30)))
+    srv = serve.Server(ctx, menu, tol=args.tol, restart=args.restart, maxit=args.maxit, log=log)
+    log(f"[serve] {len(srv.slots)} problems set up in {srv.t_setup:.1f} s; serving {len(reqs)} requests "
+        f"at {args.serve_rate}/s")
+    t0 = time.perf_counter()
+    out = srv.run(reqs)
+    t_wall = time.perf_counter() - t0
+    summ = serve.summarize(out, t_wall)
+    facts = {f"{menu[k[0]].name}/v{k[1]}": s.factorisations for k, s in srv.slots.items()}
+    line = {
+        "metric": "serving request latency p50 (p99 beside it), mixed precision, rel-res tol",
+        "value": summ["p50_s"], "unit": "s", "higher_is_better": False, "n_gpus": 1,
+        "p99_s": summ["p99_s"], "mean_s": summ["mean_s"], "by_kind": summ["by_kind"],
+        "rhs_columns": summ["rhs_columns"], "rhs_per_s": summ["rhs_per_s"], "makespan_s": t_wall,
+        "failed": summ["failed"], "max_relres": summ["max_relres"],
+        "factorisations": facts, "evictions": srv.evictions, "setup_s": srv.t_setup,
+        "dtype": "c64 factors/TRSM (FP32 MFMA) + f64 GMRES", "data": "synthetic",
+        "config": {"workload": "chamber serving menu: 0.3125/0.5/0.75/1 GHz meshes x 2 permittivity versions, "
+                               "160 ports, ceil(edges/1000) subdomains; Poisson arrivals",
+                   "requests": len(reqs), "rate_per_s": args.serve_rate, "tol": args.tol,
+                   "restart": args.restart, "budget_bytes": srv.adm.budget},
+    }
+    print(json.dumps(line), flush=True)
+    srv.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,6 +196,11 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain elementwise copy (torch.neg) of this many MiB, the known-size "
                          "kernel that calibrates rocprofv3's FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--serve", action="store_true",
+                    help="serve the seeded request stream over the 4-mesh x 2-permittivity chamber menu and print "
+                         "its latency line instead of the batch benchmark")
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-rate", type=float, default=4.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build solves all subdomains "
@@ -167,6 +213,9 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
     binding.lib()   # fails loudly if the HIP library is not built
+    if args.serve:
+        serve_main(args)
+        return
     if args.copy_probe_mib:
         src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -35,9 +35,10 @@
  * during the call only (copied where kept), "device" pointers must be device
  * memory of the context's device, valid for the duration of the call.  The
  * library owns the factors, Krylov bases and workspaces it allocates; they
- * are released by mw_destroy_problem / mw_destroy.  Work is issued on the
- * context's stream (mw_set_stream) and every call returns after that stream
- * has finished the call's work.
+ * are released by mw_destroy_problem / mw_destroy.  A problem issues its
+ * work on its own stream (the context's stream, mw_set_stream, when it was
+ * assembled; mw_problem_set_stream to change it) and every call returns after
+ * that stream has finished the call's work.
  */
 #ifndef MW_H
 #define MW_H
@@ -128,7 +129,8 @@ typedef struct {
 /* device: HIP device ordinal.  hbm_budget_bytes: upper bound on what the
  * library may hold on the device (<= 0: 95 % of the device's memory). */
 mw_status mw_create(mw_ctx **out, int device, int64_t hbm_budget_bytes);
-/* stream: a hipStream_t of the context's device (NULL = null stream). */
+/* stream: a hipStream_t of the context's device (NULL = null stream), taken
+ * by the problems assembled after this call. */
 mw_status mw_set_stream(mw_ctx *ctx, void *stream);
 mw_status mw_destroy(mw_ctx *ctx);
 const char *mw_last_error(void);
@@ -148,6 +150,7 @@ mw_status mw_update_eps(mw_problem *p, const void *eps_dev);
 mw_status mw_problem_get_info(mw_problem *p, mw_problem_info *info);
 /* host [n]: edge id of every unknown; host [n_edges*2]: edge end vertices. */
 mw_status mw_dof_edges(mw_problem *p, int32_t *edge_of_dof, int32_t *edge_vertices);
+/* MW_EINVAL while batches of the problem exist. */
 mw_status mw_destroy_problem(mw_problem *p);
 
 /* Copies A in CSR (device buffers: row_ptr int64 [n+1], col int32 [nnz],
@@ -208,6 +211,77 @@ mw_status mw_misfit_gradient(mw_problem *p, int32_t ntx, const int32_t *tx, int3
                              const int32_t *rx, const void *S_meas, double *J, void *S_sim,
                              void *grad_eps, const mw_solve_opts *o);
 
+
+/* Pieces of mw_adjoint_gradient, for callers that run the adjoint solve
+ * themselves (e.g. through a batch):
+ *  mw_adjoint_rhs: Lambda (device n x ntx) with column j
+ *    sum_i gS_ij p_{rx_i} / nu_{rx_i}  (gS device nrx x ntx; rx host [nrx]);
+ *  mw_gradient: grad_eps (device [nt]) = conj(k0^2 sum_j f_j^T M_t u_j) from the
+ *    forward fields U and adjoint fields F (device n x ntx each), overwritten;
+ *  mw_misfit: gS = S_sim - S_meas and J = 1/2 sum |gS|^2 over count entries
+ *    (device arrays; J host), the misfit of Section 4 (equation (defJ)). */
+mw_status mw_adjoint_rhs(mw_problem *p, int32_t nrx, const int32_t *rx, int32_t ntx, const void *gS,
+                         void *Lambda);
+mw_status mw_gradient(mw_problem *p, int32_t ntx, const void *U, const void *F, void *grad_eps);
+mw_status mw_misfit(mw_problem *p, int64_t count, const void *S_sim, const void *S_meas, void *gS,
+                    double *J);
+
+/* ---- serving: memory, streams, factor cache, continuous batching ------ */
+/* Budget and bytes currently held by the context (either pointer may be NULL). */
+mw_status mw_ctx_get_info(mw_ctx *ctx, int64_t *budget, int64_t *used);
+/* Issue this problem's work on `stream` (a hipStream_t of the context's
+ * device) from now on; waits for the problem's previous stream first.
+ * Different problems may be driven concurrently from different host threads,
+ * each on its own stream; calls on one problem (and its batches) must not
+ * overlap. */
+mw_status mw_problem_set_stream(mw_problem *p, void *stream);
+/* Frees the subdomain factors and solve workspaces (the decomposition is
+ * kept, so mw_factor_subdomains with the same partition only refills and
+ * refactors).  Batches stay valid but cannot cycle until the factors are
+ * rebuilt. */
+mw_status mw_release_factors(mw_problem *p);
+/* Bytes mw_factor_subdomains holds for the factors of this partition in
+ * `prec` (the decomposition must have been built once). */
+mw_status mw_factor_bytes(mw_problem *p, int32_t n_sub, int32_t overlap, mw_precision prec,
+                          const int32_t *tet_part, int64_t *bytes);
+
+/* A batch runs the pseudo-block GMRES(m) of mw_solve over a changing set of
+ * columns: requests join between restart cycles and leave at the restart
+ * where all their columns have met the tolerance (or maxit).  Every column
+ * follows exactly the iteration it would follow alone: x0 = 0, restart m,
+ * true FP64 residual at each restart (Section 6).  The batch holds B and X of
+ * max_cols column slots (device, 2 x 16 n bytes per slot) and, while columns
+ * are active, the Krylov workspaces of the active width (mw_batch_info
+ * bytes_per_col each; released when the batch idles). */
+typedef struct mw_batch mw_batch;
+typedef struct {
+  int32_t max_cols, free_cols, active_cols;
+  int32_t requests;     /* joined and not yet taken */
+  int32_t finished;     /* finished, waiting for mw_batch_take */
+  int64_t cycles;       /* restart cycles run so far */
+  int64_t slot_bytes;   /* device bytes of the column slots */
+  int64_t work_bytes;   /* device bytes of the workspaces held now */
+  int64_t bytes_per_col;/* workspace bytes per active column */
+} mw_batch_info;
+/* o: tol, restart, maxit (use_x0 must be 0); NULL = defaults of mw_solve. */
+mw_status mw_batch_create(mw_problem *p, int32_t max_cols, const mw_solve_opts *o, mw_batch **out);
+/* Copies B (device n x ncols) into free slots under `tag` (>= 0, unique among
+ * the batch's requests); the columns start at the next mw_batch_cycle.
+ * MW_ENOMEM if fewer than ncols slots are free (nothing changes). */
+mw_status mw_batch_join(mw_batch *b, int64_t tag, int32_t ncols, const void *B);
+/* One restart cycle (at most m Arnoldi steps) of every active column, then
+ * the true residual of each; requests whose columns have all stopped become
+ * finished.  n_active: columns that ran; n_finished: requests finished by
+ * this cycle (either may be NULL). */
+mw_status mw_batch_cycle(mw_batch *b, int32_t *n_active, int32_t *n_finished);
+/* Oldest finished request not yet taken: *tag = -1 if none. */
+mw_status mw_batch_poll(mw_batch *b, int64_t *tag, int32_t *ncols);
+/* Copies a finished request's solution into X (device n x ncols) and frees
+ * its slots; iters, relres: host [ncols] or NULL.  MW_ENOCONV / MW_ENUMERIC
+ * (X still written) if a column missed the tolerance or hit NaN/Inf. */
+mw_status mw_batch_take(mw_batch *b, int64_t tag, void *X, int32_t *iters, double *relres);
+mw_status mw_batch_get_info(mw_batch *b, mw_batch_info *info);
+mw_status mw_batch_destroy(mw_batch *b);
 
 /* ---- host-only inspection (no device needed) ------------------------- */
 /* Topology the library builds for `mesh` (Section 2.1): number of unknowns,

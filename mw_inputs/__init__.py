@@ -3,5 +3,5 @@
 Geometry, labels, permittivity maps, source points, port descriptions and the
 non-overlapping partition.  Holds none of the method's arithmetic.
 """
-from . import configs, fields, mesh, partition  # noqa: F401
+from . import configs, fields, mesh, partition, serving  # noqa: F401
 from .mesh import TAG_IMPEDANCE, TAG_PEC, Mesh, PortSpec  # noqa: F401

@@ -61,6 +61,12 @@ class mw_problem_info(C.Structure):
                 ("t_decompose", C.c_double), ("t_factor", C.c_double)]
 
 
+class mw_batch_info(C.Structure):
+    _fields_ = [("max_cols", C.c_int32), ("free_cols", C.c_int32), ("active_cols", C.c_int32),
+                ("requests", C.c_int32), ("finished", C.c_int32), ("cycles", C.c_int64), ("slot_bytes", C.c_int64),
+                ("work_bytes", C.c_int64), ("bytes_per_col", C.c_int64)]
+
+
 _P = C.c_void_p
 _I = C.c_int32
 _SIGS = {
@@ -82,6 +88,20 @@ _SIGS = {
     "mw_port_norms": [_P, _P],
     "mw_adjoint_gradient": [_P, _I, _P, _I, _P, _P, _P, _P, C.POINTER(mw_solve_opts), C.POINTER(mw_solve_info)],
     "mw_misfit_gradient": [_P, _I, _P, _I, _P, _P, _P, _P, _P, C.POINTER(mw_solve_opts)],
+    "mw_adjoint_rhs": [_P, _I, _P, _I, _P, _P],
+    "mw_gradient": [_P, _I, _P, _P, _P],
+    "mw_misfit": [_P, C.c_int64, _P, _P, _P, _P],
+    "mw_ctx_get_info": [_P, _P, _P],
+    "mw_problem_set_stream": [_P, _P],
+    "mw_release_factors": [_P],
+    "mw_factor_bytes": [_P, _I, _I, C.c_int, _P, _P],
+    "mw_batch_create": [_P, _I, C.POINTER(mw_solve_opts), C.POINTER(_P)],
+    "mw_batch_join": [_P, C.c_int64, _I, _P],
+    "mw_batch_cycle": [_P, _P, _P],
+    "mw_batch_poll": [_P, _P, _P],
+    "mw_batch_take": [_P, C.c_int64, _P, _P, _P],
+    "mw_batch_get_info": [_P, C.POINTER(mw_batch_info)],
+    "mw_batch_destroy": [_P],
     "mw_host_topology": [C.POINTER(mw_mesh), _P, _P, _P, _P, _P, _P],
     "mw_host_decomposition": [C.POINTER(mw_mesh), _P, _I, _I, _P, _P, _P, _P],
 }

@@ -4,10 +4,14 @@
 // kernels; the host only orders launches, moves index lists and reads back
 // per-column convergence flags.
 #include <algorithm>
+#include <array>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <functional>
+#include <map>
 #include <memory>
 #include <numeric>
 
@@ -19,9 +23,9 @@ static thread_local std::string g_last_error;
 
 struct mw_ctx {
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;     // default stream of problems created on this context
   int64_t budget = 0;
-  int64_t used = 0;
+  std::atomic<int64_t> used{0};     // bytes held; problems may be driven from several threads
 };
 
 namespace {
@@ -42,28 +46,29 @@ struct DeviceGuard {
 DevBuf dalloc(mw_ctx* c, int64_t bytes) {
   DevBuf b;
   if (bytes <= 0) return b;
-  if (c->used + bytes > c->budget)
-    fail(MW_ENOMEM, "HBM budget exceeded: need " + std::to_string(bytes) + " more bytes, " +
-                        std::to_string(c->budget - c->used) + " of " + std::to_string(c->budget) + " left");
+  int64_t cur = c->used.load();
+  do {
+    if (cur + bytes > c->budget)
+      fail(MW_ENOMEM, "HBM budget exceeded: need " + std::to_string(bytes) + " more bytes, " +
+                          std::to_string(c->budget - cur) + " of " + std::to_string(c->budget) + " left");
+  } while (!c->used.compare_exchange_weak(cur, cur + bytes));
   hipError_t e = hipMalloc(&b.p, (size_t)bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
+    c->used.fetch_sub(bytes);
     fail(MW_ENOMEM, std::string("hipMalloc of ") + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
   }
   b.bytes = (size_t)bytes;
   b.ledger = &c->used;
-  c->used += bytes;
   return b;
 }
 
 template <class T>
-DevBuf upload(mw_ctx* c, const std::vector<T>& v) {
+DevBuf upload(mw_ctx* c, hipStream_t st, const std::vector<T>& v) {
   DevBuf b = dalloc(c, (int64_t)(v.size() * sizeof(T)));
-  if (!v.empty()) MW_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  if (!v.empty()) MW_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
   return b;
 }
-
-void sync(mw_ctx* c) { MW_HIP(hipStreamSynchronize(c->stream)); }
 
 // A resizable device workspace (grown on demand, never shrunk).
 struct Work {
@@ -74,6 +79,23 @@ struct Work {
       b = dalloc(c, bytes);
     }
     return b.p;
+  }
+};
+
+// Device workspaces of one pseudo-block GMRES driver (mw_solve, or one
+// batch), grown on demand.
+struct GmresWork {
+  Work V, X, B, Z, Y, H, cs, sn, g, y, h1, h2, part, npart, vec, ints, tmp;
+  std::array<Work*, 17> all() {
+    return {&V, &X, &B, &Z, &Y, &H, &cs, &sn, &g, &y, &h1, &h2, &part, &npart, &vec, &ints, &tmp};
+  }
+  void release() {
+    for (Work* w : all()) w->b.release();
+  }
+  int64_t held() {
+    int64_t s = 0;
+    for (Work* w : all()) s += (int64_t)w->b.bytes;
+    return s;
   }
 };
 
@@ -104,8 +126,11 @@ struct mw_problem {
   DevBuf F;
   int prec = -1;
   bool factors_valid = false;
-  // solve workspaces
-  Work w_V, w_X, w_B, w_Z, w_Y, w_H, w_cs, w_sn, w_g, w_y, w_h1, w_h2, w_part, w_npart, w_vec, w_int, w_tmp;
+  // workspaces of mw_solve / mw_apply_preconditioner, and of small index lists
+  GmresWork ws;
+  Work w_small;
+  hipStream_t stream = nullptr;   // every launch and copy of this problem
+  int live_batches = 0;
   double t_assemble = 0, t_decompose = 0, t_factor = 0;
 };
 
@@ -128,6 +153,8 @@ mw_status guard(const std::function<void()>& f) {
 }
 
 void check_prob(mw_problem* p) { MW_CHECK(p != nullptr && p->ctx != nullptr, MW_EINVAL, "problem is NULL"); }
+
+void psync(mw_problem* p) { MW_HIP(hipStreamSynchronize(p->stream)); }
 
 // ------------------------------------------------------------------ ports
 void setup_ports(mw_problem* p) {
@@ -178,14 +205,14 @@ void setup_ports(mw_problem* p) {
     port_ptr[k + 1] = (int64_t)ent_dof.size();
   }
   p->port_dev = dalloc(c, (int64_t)std::max<size_t>(1, pd.size()) * sizeof(PortDev));
-  if (np) MW_HIP(hipMemcpyAsync(p->port_dev.p, pd.data(), pd.size() * sizeof(PortDev), hipMemcpyHostToDevice, c->stream));
-  p->port_ptr = upload(c, port_ptr);
-  p->ent_dof = upload(c, ent_dof);
-  p->ent_port = upload(c, ent_port);
-  p->ent_ptr = upload(c, ent_ptr);
-  p->ent_fq = upload(c, ent_fq);
-  p->pf_ptr = upload(c, pf_ptr);
-  p->pf = upload(c, pf);
+  if (np) MW_HIP(hipMemcpyAsync(p->port_dev.p, pd.data(), pd.size() * sizeof(PortDev), hipMemcpyHostToDevice, p->stream));
+  p->port_ptr = upload(c, p->stream, port_ptr);
+  p->ent_dof = upload(c, p->stream, ent_dof);
+  p->ent_port = upload(c, p->stream, ent_port);
+  p->ent_ptr = upload(c, p->stream, ent_ptr);
+  p->ent_fq = upload(c, p->stream, ent_fq);
+  p->pf_ptr = upload(c, p->stream, pf_ptr);
+  p->pf = upload(c, p->stream, pf);
   p->pval = dalloc(c, (int64_t)std::max<size_t>(1, ent_dof.size()) * 8);
   p->nu = dalloc(c, (int64_t)std::max(1, np) * 8);
   DevicePorts& P = p->dp;
@@ -201,12 +228,12 @@ void setup_ports(mw_problem* p) {
   P.pf = p->pf.as<int32_t>();
   P.pval = p->pval.as<double>();
   P.nu = p->nu.as<double>();
-  launch_port_setup(p->dm, P, c->stream);
+  launch_port_setup(p->dm, P, p->stream);
 }
 
 void assemble_values(mw_problem* p) {
-  launch_element_matrices(p->dm, p->eps.as<double2>(), p->k0, p->E.as<double2>(), p->ctx->stream);
-  launch_gather_csr(p->dm, p->E.as<double2>(), p->val.as<double2>(), p->ctx->stream);
+  launch_element_matrices(p->dm, p->eps.as<double2>(), p->k0, p->E.as<double2>(), p->stream);
+  launch_gather_csr(p->dm, p->E.as<double2>(), p->val.as<double2>(), p->stream);
 }
 
 uint64_t hash_part(const int32_t* part, int32_t nt, int32_t nsub, int32_t delta) {
@@ -218,33 +245,33 @@ uint64_t hash_part(const int32_t* part, int32_t nt, int32_t nsub, int32_t delta)
 void upload_decomp(mw_problem* p) {
   mw_ctx* c = p->ctx;
   const Decomposition& D = p->D;
-  p->d_fac_off = upload(c, D.fac_off);
-  p->d_loc_off = upload(c, D.loc_off);
-  p->d_n_loc = upload(c, D.n_loc);
-  p->d_n_pad = upload(c, D.n_pad);
-  p->d_lt_off = upload(c, D.lt_off);
-  p->d_lt_tet = upload(c, D.lt_tet);
-  p->d_lt_loc = upload(c, D.lt_loc);
-  p->d_lf_off = upload(c, D.lf_off);
-  p->d_lf_vert = upload(c, D.lf_vert);
-  p->d_lf_owner = upload(c, D.lf_owner);
-  p->d_lf_kind = upload(c, D.lf_kind);
-  p->d_lf_loc = upload(c, D.lf_loc);
-  p->d_rtl_ptr = upload(c, D.rtl_ptr);
-  p->d_rtl = upload(c, D.rtl);
-  p->d_rfl_ptr = upload(c, D.rfl_ptr);
-  p->d_rfl = upload(c, D.rfl);
-  p->d_sub_dof = upload(c, D.sub_dof);
-  p->d_D = upload(c, D.D);
-  p->d_cp_ptr = upload(c, D.cp_ptr);
-  p->d_cp_row = upload(c, D.cp_row);
+  p->d_fac_off = upload(c, p->stream, D.fac_off);
+  p->d_loc_off = upload(c, p->stream, D.loc_off);
+  p->d_n_loc = upload(c, p->stream, D.n_loc);
+  p->d_n_pad = upload(c, p->stream, D.n_pad);
+  p->d_lt_off = upload(c, p->stream, D.lt_off);
+  p->d_lt_tet = upload(c, p->stream, D.lt_tet);
+  p->d_lt_loc = upload(c, p->stream, D.lt_loc);
+  p->d_lf_off = upload(c, p->stream, D.lf_off);
+  p->d_lf_vert = upload(c, p->stream, D.lf_vert);
+  p->d_lf_owner = upload(c, p->stream, D.lf_owner);
+  p->d_lf_kind = upload(c, p->stream, D.lf_kind);
+  p->d_lf_loc = upload(c, p->stream, D.lf_loc);
+  p->d_rtl_ptr = upload(c, p->stream, D.rtl_ptr);
+  p->d_rtl = upload(c, p->stream, D.rtl);
+  p->d_rfl_ptr = upload(c, p->stream, D.rfl_ptr);
+  p->d_rfl = upload(c, p->stream, D.rfl);
+  p->d_sub_dof = upload(c, p->stream, D.sub_dof);
+  p->d_D = upload(c, p->stream, D.D);
+  p->d_cp_ptr = upload(c, p->stream, D.cp_ptr);
+  p->d_cp_row = upload(c, p->stream, D.cp_row);
   p->d_ipiv = dalloc(c, D.sum_pad() * 4);
   p->d_ridx = dalloc(c, D.sum_pad() * 4);
   p->d_info = dalloc(c, (int64_t)D.nsub * 4);
   p->d_amax = dalloc(c, (int64_t)D.nsub * 8);
   p->h_row_lo.resize(D.nsub);
   for (int32_t i = 0; i < D.nsub; ++i) p->h_row_lo[i] = (D.n_lead[i] / 64) * 64;
-  p->d_row_lo = upload(c, p->h_row_lo);
+  p->d_row_lo = upload(c, p->stream, p->h_row_lo);
   DeviceDecomp& d = p->dd;
   d.nsub = D.nsub;
   d.max_pad = *std::max_element(D.n_pad.begin(), D.n_pad.end());
@@ -278,32 +305,141 @@ void upload_decomp(mw_problem* p) {
   d.h_row_lo = p->h_row_lo.data();
 }
 
-// Z = M^-1 V (n x nc, leading dimension ld), local workspace Y
-void apply_prec(mw_problem* p, const double2* V, double2* Z, int nc, int64_t ld) {
+// Z = M^-1 V (n x nc, leading dimension ld), local workspace W.Y
+void apply_prec(mw_problem* p, GmresWork& W, const double2* V, double2* Z, int nc, int64_t ld) {
   mw_ctx* c = p->ctx;
   MW_CHECK(p->factors_valid, MW_EINVAL, "no valid subdomain factors: call mw_factor_subdomains");
   int64_t n = p->T.n();
   if (p->prec == MW_C64) {
-    float2* Y = (float2*)p->w_Y.get(c, p->dd.sum_pad * nc * 8);
-    launch_restrict<float2>(p->dd, V, ld, nc, Y, nc, c->stream);
-    lu_solve_batched<float2>(p->dd, p->F.as<float2>(), Y, nc, nc, c->stream);
-    launch_prolong<float2>(p->dd, n, Y, nc, nc, Z, ld, c->stream);
+    float2* Y = (float2*)W.Y.get(c, p->dd.sum_pad * nc * 8);
+    launch_restrict<float2>(p->dd, V, ld, nc, Y, nc, p->stream);
+    lu_solve_batched<float2>(p->dd, p->F.as<float2>(), Y, nc, nc, p->stream);
+    launch_prolong<float2>(p->dd, n, Y, nc, nc, Z, ld, p->stream);
   } else {
-    double2* Y = (double2*)p->w_Y.get(c, p->dd.sum_pad * nc * 16);
-    launch_restrict<double2>(p->dd, V, ld, nc, Y, nc, c->stream);
-    lu_solve_batched<double2>(p->dd, p->F.as<double2>(), Y, nc, nc, c->stream);
-    launch_prolong<double2>(p->dd, n, Y, nc, nc, Z, ld, c->stream);
+    double2* Y = (double2*)W.Y.get(c, p->dd.sum_pad * nc * 16);
+    launch_restrict<double2>(p->dd, V, ld, nc, Y, nc, p->stream);
+    lu_solve_batched<double2>(p->dd, p->F.as<double2>(), Y, nc, nc, p->stream);
+    launch_prolong<double2>(p->dd, n, Y, nc, nc, Z, ld, p->stream);
   }
 }
 
 // column 2-norms squared of an n x nc block (device out), deterministic
-void colnorm2(mw_problem* p, const double2* V, int64_t ld, int nc, double* out) {
-  mw_ctx* c = p->ctx;
+void colnorm2(mw_problem* p, GmresWork& W, const double2* V, int64_t ld, int nc, double* out) {
   int64_t n = p->T.n();
   int64_t nch = reduce_chunks(n);
-  double* part = (double*)p->w_npart.get(c, nch * nc * 8);
-  launch_colnorm2_partial(V, n, ld, nc, part, c->stream);
-  launch_sum_chunks(part, nch, nc, out, c->stream);
+  double* part = (double*)W.npart.get(p->ctx, nch * nc * 8);
+  launch_colnorm2_partial(V, n, ld, nc, part, p->stream);
+  launch_sum_chunks(part, nch, nc, out, p->stream);
+}
+
+// device bytes one more right-hand side column costs a GMRES(m) driver:
+// basis (m+1), X, B, Z, update, local vectors, reduction partials
+int64_t gmres_bytes_per_col(mw_problem* p, int m) {
+  int64_t esz = p->prec == MW_C64 ? 8 : 16;
+  int64_t big = (int64_t)(m + 5) * p->T.n() * 16 + p->dd.sum_pad * esz + reduce_chunks(p->T.n()) * (m + 2) * 16;
+  // Hessenberg, rotations, g, y, h1, h2, norms, flags
+  int64_t small = (int64_t)(m + 1) * m * 16 + (int64_t)m * 24 + 4 * (int64_t)(m + 1) * 16 + 4 * 8 + 2 * 4;
+  return big + small + 256;
+}
+
+// Z = B - A X (n x nc, ld nc); squared column norms into rn2 (device) and hr2 (host)
+void true_residual(mw_problem* p, GmresWork& W, const double2* B, const double2* X, double2* Z, int nc, double* rn2,
+                   std::vector<double>& hr2) {
+  launch_spmm(p->dm, p->val.as<double2>(), X, nc, Z, nc, nc, B, nc, p->stream);
+  colnorm2(p, W, Z, nc, nc, rn2);
+  hr2.resize(nc);
+  MW_HIP(hipMemcpyAsync(hr2.data(), rn2, nc * 8, hipMemcpyDeviceToHost, p->stream));
+  psync(p);
+}
+
+// One restart cycle of GMRES(m) right-preconditioned with ORAS (Section 6),
+// pseudo-block over the nc columns of X (ld nc).  On entry Z holds the true
+// residual r = b - A x and vec = [||b|| | ||r||^2 | scratch x2] (device, nc
+// each), rnorm = ||r|| on the host.  Columns with hact[k] = 0 are carried
+// along untouched.  A column stops when its Givens residual estimate reaches
+// tol (relative to ||b||) or its iteration count reaches maxit; the cycle
+// ends when every column has stopped or after m steps, then x += M^-1 V y.
+// iters[k] counts the Arnoldi steps of column k.
+void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, const mw_solve_opts& o, double* vec,
+                 const std::vector<double>& rnorm, std::vector<int32_t>& hact, std::vector<int32_t>& iters) {
+  mw_ctx* c = p->ctx;
+  hipStream_t st = p->stream;
+  const int64_t n = p->T.n();
+  const int m = o.restart;
+  const int64_t ld = nc;
+  const int64_t vstride = n * ld;
+  double2* V = (double2*)W.V.get(c, (int64_t)(m + 1) * vstride * 16);
+  double2* H = (double2*)W.H.get(c, (int64_t)(m + 1) * m * nc * 16);
+  double* cs = (double*)W.cs.get(c, (int64_t)m * nc * 8);
+  double2* sn = (double2*)W.sn.get(c, (int64_t)m * nc * 16);
+  double2* g = (double2*)W.g.get(c, (int64_t)(m + 1) * nc * 16);
+  double2* y = (double2*)W.y.get(c, (int64_t)(m + 1) * nc * 16);
+  double2* h1 = (double2*)W.h1.get(c, (int64_t)(m + 1) * nc * 16);
+  double2* h2 = (double2*)W.h2.get(c, (int64_t)(m + 1) * nc * 16);
+  int64_t nch = reduce_chunks(n);
+  double2* part = (double2*)W.part.get(c, nch * (m + 1) * nc * 16);
+  double* npart = (double*)W.npart.get(c, nch * nc * 8);
+  double* bnorm = vec;        // ||b||
+  double* rn2 = vec + nc;     // ||r||^2
+  double* hn2 = vec + 2 * nc; // ||w||^2
+  double* resid = vec + 3 * nc;
+  int32_t* ivec = (int32_t*)W.ints.get(c, (int64_t)2 * nc * 4);
+  int32_t* act = ivec;
+  int32_t* kdim = ivec + nc;
+  std::vector<double2> g0((size_t)nc);
+  int nact = 0;
+  for (int k = 0; k < nc; ++k) {
+    g0[k] = make_double2(rnorm[k], 0.0);
+    nact += hact[k];
+  }
+  if (nact == 0) return;
+  MW_HIP(hipMemcpyAsync(act, hact.data(), nc * 4, hipMemcpyHostToDevice, st));
+  launch_zero_bytes(kdim, nc * 4, st);
+  launch_zero(g, (int64_t)(m + 1) * nc, st);
+  MW_HIP(hipMemcpyAsync(g, g0.data(), nc * 16, hipMemcpyHostToDevice, st));
+  launch_start_cycle(Z, V, n, ld, nc, rn2, act, st);
+  std::vector<int32_t> hact_prev(nc);
+  for (int j = 0; j < m; ++j) {
+    double2* Vj = V + (int64_t)j * vstride;
+    double2* Wj = V + (int64_t)(j + 1) * vstride;
+    apply_prec(p, W, Vj, Z, nc, ld);
+    launch_spmm(p->dm, p->val.as<double2>(), Z, ld, Wj, ld, nc, nullptr, 0, st);
+    // classical Gram-Schmidt, twice
+    launch_dots_partial(V, vstride, j + 1, Wj, n, ld, nc, act, part, st);
+    launch_sum_chunks_c(part, nch, (int64_t)(j + 1) * nc, h1, st);
+    if (!launch_cgs_update_dots(V, vstride, j + 1, h1, Wj, n, ld, nc, act, part, st)) {
+      launch_cgs_update(V, vstride, j + 1, h1, Wj, n, ld, nc, act, nullptr, st);
+      launch_dots_partial(V, vstride, j + 1, Wj, n, ld, nc, act, part, st);
+    }
+    launch_sum_chunks_c(part, nch, (int64_t)(j + 1) * nc, h2, st);
+    launch_cgs_update(V, vstride, j + 1, h2, Wj, n, ld, nc, act, npart, st);
+    launch_sum_chunks(npart, nch, nc, hn2, st);
+    launch_scale_cols(Wj, n, ld, nc, hn2, act, st);
+    launch_givens(j, m, nc, h1, h2, hn2, H, cs, sn, g, kdim, act, resid, bnorm, o.tol, st);
+    hact_prev = hact;
+    MW_HIP(hipMemcpyAsync(hact.data(), act, nc * 4, hipMemcpyDeviceToHost, st));
+    psync(p);
+    bool changed = false;
+    nact = 0;
+    for (int k = 0; k < nc; ++k) {
+      if (hact_prev[k]) iters[k]++;
+      if (hact[k] && iters[k] >= o.maxit) { hact[k] = 0; changed = true; }
+      nact += hact[k];
+    }
+    if (nact == 0) break;
+    if (changed) MW_HIP(hipMemcpyAsync(act, hact.data(), nc * 4, hipMemcpyHostToDevice, st));
+  }
+  // x += M^-1 (V y)
+  launch_backsolve(m, nc, H, g, kdim, y, st);
+  launch_combine(V, vstride, m, y, kdim, Z, n, ld, nc, st);
+  double2* U = (double2*)W.tmp.get(c, vstride * 16);
+  apply_prec(p, W, Z, U, nc, ld);
+  launch_axpy_cols(X, U, n, ld, nc, st);
+}
+
+// whether column k needs another cycle, from its true residual
+inline bool column_continues(double bnorm, double relres, int32_t iters, double r, const mw_solve_opts& o) {
+  return bnorm > 0 && relres > o.tol && iters < o.maxit && std::isfinite(r);
 }
 
 struct ChunkResult {
@@ -311,114 +447,54 @@ struct ChunkResult {
   bool numeric = false;
 };
 
-// GMRES(m) right-preconditioned with ORAS, pseudo-block over nc columns
-// (Section 6), true residual recomputed at every restart.
+// Pseudo-block GMRES(m) to convergence on nc columns (one memory chunk of
+// mw_solve), true residual recomputed at every restart.
 ChunkResult gmres_chunk(mw_problem* p, const double2* Bsrc, int64_t ldb_src, double2* Xdst, int64_t ldx_dst, int nc,
                         const mw_solve_opts& o, int32_t* iters_out, double* relres_out) {
   mw_ctx* c = p->ctx;
-  hipStream_t st = c->stream;
+  hipStream_t st = p->stream;
+  GmresWork& W = p->ws;
   const int64_t n = p->T.n();
-  const int m = o.restart;
   const int64_t ld = nc;
   const int64_t vstride = n * ld;
-  double2* V = (double2*)p->w_V.get(c, (int64_t)(m + 1) * vstride * 16);
-  double2* X = (double2*)p->w_X.get(c, vstride * 16);
-  double2* B = (double2*)p->w_B.get(c, vstride * 16);
-  double2* Z = (double2*)p->w_Z.get(c, vstride * 16);
-  double2* H = (double2*)p->w_H.get(c, (int64_t)(m + 1) * m * nc * 16);
-  double* cs = (double*)p->w_cs.get(c, (int64_t)m * nc * 8);
-  double2* sn = (double2*)p->w_sn.get(c, (int64_t)m * nc * 16);
-  double2* g = (double2*)p->w_g.get(c, (int64_t)(m + 1) * nc * 16);
-  double2* y = (double2*)p->w_y.get(c, (int64_t)(m + 1) * nc * 16);
-  double2* h1 = (double2*)p->w_h1.get(c, (int64_t)(m + 1) * nc * 16);
-  double2* h2 = (double2*)p->w_h2.get(c, (int64_t)(m + 1) * nc * 16);
-  int64_t nch = reduce_chunks(n);
-  double2* part = (double2*)p->w_part.get(c, nch * (m + 1) * nc * 16);
-  double* vec = (double*)p->w_vec.get(c, (int64_t)4 * nc * 8);
-  double* bnorm = vec;        // ||b||
-  double* rn2 = vec + nc;     // ||r||^2
-  double* hn2 = vec + 2 * nc; // ||w||^2
-  double* resid = vec + 3 * nc;
-  int32_t* ivec = (int32_t*)p->w_int.get(c, (int64_t)2 * nc * 4);
-  int32_t* act = ivec;
-  int32_t* kdim = ivec + nc;
+  double2* X = (double2*)W.X.get(c, vstride * 16);
+  double2* B = (double2*)W.B.get(c, vstride * 16);
+  double2* Z = (double2*)W.Z.get(c, vstride * 16);
+  double* vec = (double*)W.vec.get(c, (int64_t)4 * nc * 8);
+  double* bnorm = vec;
+  double* rn2 = vec + nc;
 
   launch_copy_cols(Bsrc, ldb_src, B, ld, n, nc, st);
   if (o.use_x0) launch_copy_cols(Xdst, ldx_dst, X, ld, n, nc, st);
   else launch_zero(X, vstride, st);
-  std::vector<double> hb(nc), hr(nc), hb2(nc);
-  colnorm2(p, B, ld, nc, rn2);
+  std::vector<double> hb(nc), hr, hb2(nc);
+  colnorm2(p, W, B, ld, nc, rn2);
   MW_HIP(hipMemcpyAsync(hb2.data(), rn2, nc * 8, hipMemcpyDeviceToHost, st));
-  sync(c);
+  psync(p);
   for (int k = 0; k < nc; ++k) hb[k] = std::sqrt(hb2[k]);
   MW_HIP(hipMemcpyAsync(bnorm, hb.data(), nc * 8, hipMemcpyHostToDevice, st));
 
   ChunkResult res;
-  std::vector<int32_t> iters(nc, 0), hact(nc, 0), hact_prev(nc, 0);
-  std::vector<double> relres(nc, 0.0);
-  std::vector<double2> g0((size_t)nc);
+  std::vector<int32_t> iters(nc, 0), hact(nc, 0);
+  std::vector<double> relres(nc, 0.0), rnorm(nc);
   for (;;) {
     // true residual r = b - A x (iterative refinement point)
-    launch_spmm(p->dm, p->val.as<double2>(), X, ld, Z, ld, nc, B, ld, st);
-    colnorm2(p, Z, ld, nc, rn2);
-    MW_HIP(hipMemcpyAsync(hr.data(), rn2, nc * 8, hipMemcpyDeviceToHost, st));
-    sync(c);
+    true_residual(p, W, B, X, Z, nc, rn2, hr);
     int nact = 0;
     for (int k = 0; k < nc; ++k) {
       double r = std::sqrt(hr[k]);
       if (!std::isfinite(r)) res.numeric = true;
       relres[k] = hb[k] > 0 ? r / hb[k] : 0.0;
-      hact[k] = (hb[k] > 0 && relres[k] > o.tol && iters[k] < o.maxit && std::isfinite(r)) ? 1 : 0;
+      hact[k] = column_continues(hb[k], relres[k], iters[k], r, o) ? 1 : 0;
       nact += hact[k];
-      g0[k] = make_double2(r, 0.0);
+      rnorm[k] = r;
     }
     if (res.numeric || nact == 0) break;
     res.cycles++;
-    MW_HIP(hipMemcpyAsync(act, hact.data(), nc * 4, hipMemcpyHostToDevice, st));
-    launch_zero_bytes(kdim, nc * 4, st);
-    launch_zero(g, (int64_t)(m + 1) * nc, st);
-    MW_HIP(hipMemcpyAsync(g, g0.data(), nc * 16, hipMemcpyHostToDevice, st));
-    launch_start_cycle(Z, V, n, ld, nc, rn2, act, st);
-    for (int j = 0; j < m; ++j) {
-      double2* Vj = V + (int64_t)j * vstride;
-      double2* W = V + (int64_t)(j + 1) * vstride;
-      apply_prec(p, Vj, Z, nc, ld);
-      launch_spmm(p->dm, p->val.as<double2>(), Z, ld, W, ld, nc, nullptr, 0, st);
-      // classical Gram-Schmidt, twice
-      launch_dots_partial(V, vstride, j + 1, W, n, ld, nc, act, part, st);
-      launch_sum_chunks_c(part, nch, (int64_t)(j + 1) * nc, h1, st);
-      if (!launch_cgs_update_dots(V, vstride, j + 1, h1, W, n, ld, nc, act, part, st)) {
-        launch_cgs_update(V, vstride, j + 1, h1, W, n, ld, nc, act, nullptr, st);
-        launch_dots_partial(V, vstride, j + 1, W, n, ld, nc, act, part, st);
-      }
-      launch_sum_chunks_c(part, nch, (int64_t)(j + 1) * nc, h2, st);
-      double* npart = (double*)p->w_npart.get(c, nch * nc * 8);
-      launch_cgs_update(V, vstride, j + 1, h2, W, n, ld, nc, act, npart, st);
-      launch_sum_chunks(npart, nch, nc, hn2, st);
-      launch_scale_cols(W, n, ld, nc, hn2, act, st);
-      launch_givens(j, m, nc, h1, h2, hn2, H, cs, sn, g, kdim, act, resid, bnorm, o.tol, st);
-      hact_prev = hact;
-      MW_HIP(hipMemcpyAsync(hact.data(), act, nc * 4, hipMemcpyDeviceToHost, st));
-      sync(c);
-      bool changed = false;
-      nact = 0;
-      for (int k = 0; k < nc; ++k) {
-        if (hact_prev[k]) iters[k]++;
-        if (hact[k] && iters[k] >= o.maxit) { hact[k] = 0; changed = true; }
-        nact += hact[k];
-      }
-      if (nact == 0) break;
-      if (changed) MW_HIP(hipMemcpyAsync(act, hact.data(), nc * 4, hipMemcpyHostToDevice, st));
-    }
-    // x += M^-1 (V y)
-    launch_backsolve(m, nc, H, g, kdim, y, st);
-    launch_combine(V, vstride, m, y, kdim, Z, n, ld, nc, st);
-    double2* U = (double2*)p->w_tmp.get(c, vstride * 16);
-    apply_prec(p, Z, U, nc, ld);
-    launch_axpy_cols(X, U, n, ld, nc, st);
+    gmres_cycle(p, W, X, Z, nc, o, vec, rnorm, hact, iters);
   }
   launch_copy_cols(X, ld, Xdst, ldx_dst, n, nc, st);
-  sync(c);
+  psync(p);
   for (int k = 0; k < nc; ++k) {
     if (iters_out) iters_out[k] = iters[k];
     if (relres_out) relres_out[k] = relres[k];
@@ -460,7 +536,7 @@ mw_status mw_set_stream(mw_ctx* ctx, void* stream) {
 mw_status mw_destroy(mw_ctx* ctx) {
   return guard([&] {
     if (!ctx) return;
-    MW_CHECK(ctx->used == 0, MW_EINVAL, "destroy every problem of the context first");
+    MW_CHECK(ctx->used.load() == 0, MW_EINVAL, "destroy every problem of the context first");
     delete ctx;
   });
 }
@@ -475,6 +551,7 @@ mw_status mw_assemble(mw_ctx* ctx, const mw_mesh* mesh, const mw_complex* eps_r,
     double t0 = now_s();
     auto p = std::make_unique<mw_problem>();
     p->ctx = ctx;
+    p->stream = ctx->stream;
     p->k0 = k0;
     p->beta_imp = beta_imp;
     p->ports.assign(ports, ports + nports);
@@ -489,20 +566,20 @@ mw_status mw_assemble(mw_ctx* ctx, const mw_mesh* mesh, const mw_complex* eps_r,
     }
     std::vector<double2> e(T.nt);
     for (int32_t t = 0; t < T.nt; ++t) e[t] = make_double2(eps_r[t].re, eps_r[t].im);
-    p->xyz = upload(ctx, T.xyz);
-    p->tet = upload(ctx, T.tet);
-    p->t2e = upload(ctx, T.t2e);
-    p->dof = upload(ctx, T.dof);
-    p->bface = upload(ctx, T.bface);
-    p->bf2e = upload(ctx, T.bf2e);
-    p->fbeta = upload(ctx, fb);
-    p->row_ptr = upload(ctx, T.row_ptr);
-    p->col = upload(ctx, T.col);
-    p->rt_ptr = upload(ctx, T.rt_ptr);
-    p->rt = upload(ctx, T.rt);
-    p->rf_ptr = upload(ctx, T.rf_ptr);
-    p->rf = upload(ctx, T.rf);
-    p->eps = upload(ctx, e);
+    p->xyz = upload(ctx, p->stream, T.xyz);
+    p->tet = upload(ctx, p->stream, T.tet);
+    p->t2e = upload(ctx, p->stream, T.t2e);
+    p->dof = upload(ctx, p->stream, T.dof);
+    p->bface = upload(ctx, p->stream, T.bface);
+    p->bf2e = upload(ctx, p->stream, T.bf2e);
+    p->fbeta = upload(ctx, p->stream, fb);
+    p->row_ptr = upload(ctx, p->stream, T.row_ptr);
+    p->col = upload(ctx, p->stream, T.col);
+    p->rt_ptr = upload(ctx, p->stream, T.rt_ptr);
+    p->rt = upload(ctx, p->stream, T.rt);
+    p->rf_ptr = upload(ctx, p->stream, T.rf_ptr);
+    p->rf = upload(ctx, p->stream, T.rf);
+    p->eps = upload(ctx, p->stream, e);
     p->E = dalloc(ctx, (int64_t)T.nt * 21 * 16);
     p->val = dalloc(ctx, (int64_t)T.col.size() * 16);
     DeviceMesh& m = p->dm;
@@ -514,7 +591,7 @@ mw_status mw_assemble(mw_ctx* ctx, const mw_mesh* mesh, const mw_complex* eps_r,
     m.rf = p->rf.as<int32_t>();
     assemble_values(p.get());
     setup_ports(p.get());
-    sync(ctx);
+    psync(p.get());
     p->t_assemble = now_s() - t0;
     *out = p.release();
   });
@@ -526,10 +603,10 @@ mw_status mw_update_eps(mw_problem* p, const void* eps_dev) {
     MW_CHECK(eps_dev != nullptr, MW_EINVAL, "eps is NULL");
     DeviceGuard dg(p->ctx->device);
     double t0 = now_s();
-    MW_HIP(hipMemcpyAsync(p->eps.p, eps_dev, (size_t)p->T.nt * 16, hipMemcpyDeviceToDevice, p->ctx->stream));
+    MW_HIP(hipMemcpyAsync(p->eps.p, eps_dev, (size_t)p->T.nt * 16, hipMemcpyDeviceToDevice, p->stream));
     assemble_values(p);
     p->factors_valid = false;
-    sync(p->ctx);
+    psync(p);
     p->t_assemble = now_s() - t0;
   });
 }
@@ -570,18 +647,19 @@ mw_status mw_get_matrix(mw_problem* p, void* row_ptr, void* col, void* val) {
   return guard([&] {
     check_prob(p);
     DeviceGuard dg(p->ctx->device);
-    hipStream_t st = p->ctx->stream;
+    hipStream_t st = p->stream;
     if (row_ptr) MW_HIP(hipMemcpyAsync(row_ptr, p->row_ptr.p, p->row_ptr.bytes, hipMemcpyDeviceToDevice, st));
     if (col) MW_HIP(hipMemcpyAsync(col, p->col.p, p->col.bytes, hipMemcpyDeviceToDevice, st));
     if (val) MW_HIP(hipMemcpyAsync(val, p->val.p, p->val.bytes, hipMemcpyDeviceToDevice, st));
-    sync(p->ctx);
+    psync(p);
   });
 }
 
 mw_status mw_destroy_problem(mw_problem* p) {
   return guard([&] {
     if (!p) return;
-    if (p->ctx) { DeviceGuard dg(p->ctx->device); (void)hipStreamSynchronize(p->ctx->stream); delete p; }
+    MW_CHECK(p->live_batches == 0, MW_EINVAL, "destroy the problem's batches first");
+    if (p->ctx) { DeviceGuard dg(p->ctx->device); (void)hipStreamSynchronize(p->stream); delete p; }
     else delete p;
   });
 }
@@ -593,13 +671,13 @@ mw_status mw_rhs_ports(mw_problem* p, int32_t ntx, const int32_t* tx, void* B) {
     for (int j = 0; j < ntx; ++j) MW_CHECK(tx[j] >= 0 && tx[j] < (int)p->ports.size(), MW_EINVAL, "port index out of range");
     if (ntx == 0) return;
     DeviceGuard dg(p->ctx->device);
-    hipStream_t st = p->ctx->stream;
+    hipStream_t st = p->stream;
     std::vector<int32_t> h(tx, tx + ntx);
-    int32_t* d = (int32_t*)p->w_tmp.get(p->ctx, ntx * 4);
+    int32_t* d = (int32_t*)p->w_small.get(p->ctx, ntx * 4);
     MW_HIP(hipMemcpyAsync(d, h.data(), ntx * 4, hipMemcpyHostToDevice, st));
     launch_zero((double2*)B, p->T.n() * ntx, st);
     launch_rhs_ports(p->dp, ntx, d, (double2*)B, ntx, st);
-    sync(p->ctx);
+    psync(p);
   });
 }
 
@@ -609,8 +687,8 @@ mw_status mw_rhs_dipoles(mw_problem* p, int32_t np, const double* xyz, const dou
     MW_CHECK(np >= 0 && (np == 0 || (xyz && dir && B)), MW_EINVAL, "NULL argument");
     if (np == 0) return;
     DeviceGuard dg(p->ctx->device);
-    hipStream_t st = p->ctx->stream;
-    char* w = (char*)p->w_tmp.get(p->ctx, (int64_t)np * (48 + 4));
+    hipStream_t st = p->stream;
+    char* w = (char*)p->w_small.get(p->ctx, (int64_t)np * (48 + 4));
     double* pts = (double*)w;
     double* dirs = pts + 3 * np;
     int* found = (int*)(dirs + 3 * np);
@@ -621,11 +699,11 @@ mw_status mw_rhs_dipoles(mw_problem* p, int32_t np, const double* xyz, const dou
     launch_locate(p->dm, pts, np, found, st);
     std::vector<int> hf(np);
     MW_HIP(hipMemcpyAsync(hf.data(), found, np * 4, hipMemcpyDeviceToHost, st));
-    sync(p->ctx);
+    psync(p);
     for (int j = 0; j < np; ++j) MW_CHECK(hf[j] != 0x7fffffff, MW_EINVAL, "dipole point outside the mesh");
     launch_zero((double2*)B, p->T.n() * np, st);
     launch_rhs_dipoles(p->dm, pts, dirs, found, np, (double2*)B, np, st);
-    sync(p->ctx);
+    psync(p);
   });
 }
 
@@ -658,13 +736,11 @@ mw_status mw_factor_subdomains(mw_problem* p, int32_t n_sub, int32_t overlap, mw
       p->F.release();
       p->factors_valid = false;
       // solve workspaces are re-created on demand; give their memory to the factors
-      for (Work* w : {&p->w_V, &p->w_X, &p->w_B, &p->w_Z, &p->w_Y, &p->w_H, &p->w_cs, &p->w_sn, &p->w_g, &p->w_y,
-                      &p->w_h1, &p->w_h2, &p->w_part, &p->w_npart, &p->w_vec, &p->w_int, &p->w_tmp})
-        w->b.release();
+      p->ws.release();
       p->F = dalloc(c, need);
     }
     p->prec = prec;
-    hipStream_t st = c->stream;
+    hipStream_t st = p->stream;
     launch_zero_bytes(p->dd.info, (int64_t)p->dd.nsub * 4, st);
     if (prec == MW_C64) {
       launch_fill_local<float2>(p->dm, p->dd, p->E.as<double2>(), p->eps.as<double2>(), p->k0, p->F.as<float2>(), st);
@@ -675,7 +751,7 @@ mw_status mw_factor_subdomains(mw_problem* p, int32_t n_sub, int32_t overlap, mw
     }
     std::vector<int32_t> info(p->dd.nsub);
     MW_HIP(hipMemcpyAsync(info.data(), p->dd.info, info.size() * 4, hipMemcpyDeviceToHost, st));
-    sync(c);
+    psync(p);
     p->t_factor = now_s() - t1;
     for (int i = 0; i < p->dd.nsub; ++i)
       MW_CHECK(info[i] == 0, MW_ESINGULAR,
@@ -690,20 +766,16 @@ mw_status mw_apply_preconditioner(mw_problem* p, int32_t nrhs, const void* V, vo
     MW_CHECK(nrhs >= 0 && (nrhs == 0 || (V && Z)), MW_EINVAL, "NULL argument");
     if (nrhs == 0) return;
     DeviceGuard dg(p->ctx->device);
-    apply_prec(p, (const double2*)V, (double2*)Z, nrhs, nrhs);
-    sync(p->ctx);
+    apply_prec(p, p->ws, (const double2*)V, (double2*)Z, nrhs, nrhs);
+    psync(p);
   });
 }
 
 static int solve_chunk_cols(mw_problem* p, int nrhs, int m) {
   mw_ctx* c = p->ctx;
-  const int64_t n = p->T.n();
-  int64_t esz = p->prec == MW_C64 ? 8 : 16;
-  // bytes per column: basis (m+1), X, B, Z, tmp, local vectors, small arrays
-  int64_t per = (int64_t)(m + 5) * n * 16 + p->dd.sum_pad * esz + reduce_chunks(n) * (m + 2) * 16 + 4096;
-  int64_t held = (int64_t)(p->w_V.b.bytes + p->w_X.b.bytes + p->w_B.b.bytes + p->w_Z.b.bytes + p->w_tmp.b.bytes +
-                           p->w_Y.b.bytes + p->w_part.b.bytes);
-  int64_t avail = c->budget - c->used + held;
+  int64_t per = gmres_bytes_per_col(p, m);
+  int64_t held = p->ws.held();
+  int64_t avail = c->budget - c->used.load() + held;
   int64_t cols = avail / std::max<int64_t>(per, 1);
   // when the columns must be split, use multiples of 32 (the width granule of
   // the triangular-solve tiles) so that no tile runs half empty
@@ -755,11 +827,11 @@ mw_status mw_s_matrix(mw_problem* p, int32_t nrx, const int32_t* rx, int32_t ntx
     MW_CHECK(rx && U && S, MW_EINVAL, "NULL argument");
     for (int i = 0; i < nrx; ++i) MW_CHECK(rx[i] >= 0 && rx[i] < (int)p->ports.size(), MW_EINVAL, "port index out of range");
     DeviceGuard dg(p->ctx->device);
-    hipStream_t st = p->ctx->stream;
-    int32_t* d = (int32_t*)p->w_int.get(p->ctx, (int64_t)std::max(nrx, 1) * 4 + 16);
+    hipStream_t st = p->stream;
+    int32_t* d = (int32_t*)p->w_small.get(p->ctx, (int64_t)std::max(nrx, 1) * 4 + 16);
     MW_HIP(hipMemcpyAsync(d, rx, nrx * 4, hipMemcpyHostToDevice, st));
     launch_s_matrix(p->dp, nrx, d, ntx, (const double2*)U, ntx, (double2*)S, st);
-    sync(p->ctx);
+    psync(p);
   });
 }
 
@@ -769,8 +841,45 @@ mw_status mw_port_norms(mw_problem* p, double* nu) {
     MW_CHECK(nu != nullptr, MW_EINVAL, "nu is NULL");
     if (p->ports.empty()) return;
     DeviceGuard dg(p->ctx->device);
-    MW_HIP(hipMemcpyAsync(nu, p->dp.nu, p->ports.size() * 8, hipMemcpyDeviceToHost, p->ctx->stream));
-    sync(p->ctx);
+    MW_HIP(hipMemcpyAsync(nu, p->dp.nu, p->ports.size() * 8, hipMemcpyDeviceToHost, p->stream));
+    psync(p);
+  });
+}
+
+mw_status mw_adjoint_rhs(mw_problem* p, int32_t nrx, const int32_t* rx, int32_t ntx, const void* gS, void* Lambda) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(nrx >= 1 && ntx >= 1 && rx && gS && Lambda, MW_EINVAL, "NULL argument or empty port set");
+    for (int i = 0; i < nrx; ++i) MW_CHECK(rx[i] >= 0 && rx[i] < (int)p->ports.size(), MW_EINVAL, "port index out of range");
+    DeviceGuard dg(p->ctx->device);
+    hipStream_t st = p->stream;
+    int32_t* d = (int32_t*)p->w_small.get(p->ctx, (int64_t)nrx * 4 + 16);
+    MW_HIP(hipMemcpyAsync(d, rx, nrx * 4, hipMemcpyHostToDevice, st));
+    launch_zero((double2*)Lambda, p->T.n() * ntx, st);
+    launch_adjoint_rhs(p->dp, nrx, d, ntx, (const double2*)gS, (double2*)Lambda, ntx, st);
+    psync(p);
+  });
+}
+
+mw_status mw_gradient(mw_problem* p, int32_t ntx, const void* U, const void* F, void* grad_eps) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(ntx >= 1 && U && F && grad_eps, MW_EINVAL, "NULL argument");
+    DeviceGuard dg(p->ctx->device);
+    launch_gradient(p->dm, (const double2*)U, (const double2*)F, ntx, ntx, p->k0, (double2*)grad_eps, p->stream);
+    psync(p);
+  });
+}
+
+mw_status mw_misfit(mw_problem* p, int64_t count, const void* S_sim, const void* S_meas, void* gS, double* J) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(count >= 1 && S_sim && S_meas && gS && J, MW_EINVAL, "NULL argument");
+    DeviceGuard dg(p->ctx->device);
+    double* dJ = (double*)p->w_small.get(p->ctx, 16);
+    launch_misfit((const double2*)S_sim, (const double2*)S_meas, count, (double2*)gS, dJ, p->stream);
+    MW_HIP(hipMemcpyAsync(J, dJ, 8, hipMemcpyDeviceToHost, p->stream));
+    psync(p);
   });
 }
 
@@ -781,31 +890,20 @@ mw_status mw_adjoint_gradient(mw_problem* p, int32_t ntx, const int32_t* tx, int
   mw_status s = guard([&] {
     check_prob(p);
     MW_CHECK(ntx >= 1 && nrx >= 1 && rx && U && gS && grad_eps, MW_EINVAL, "NULL argument or empty port set");
-    for (int i = 0; i < nrx; ++i) MW_CHECK(rx[i] >= 0 && rx[i] < (int)p->ports.size(), MW_EINVAL, "port index out of range");
   });
   if (s != MW_OK) return s;
   mw_ctx* c = p->ctx;
   const int64_t n = p->T.n();
-  DevBuf lam, F, drx;
+  DevBuf lam, F;
   s = guard([&] {
     DeviceGuard dg(c->device);
-    hipStream_t st = c->stream;
     lam = dalloc(c, n * ntx * 16);
     F = dalloc(c, n * ntx * 16);
-    drx = dalloc(c, (int64_t)nrx * 4);
-    MW_HIP(hipMemcpyAsync(drx.p, rx, nrx * 4, hipMemcpyHostToDevice, st));
-    launch_zero(lam.as<double2>(), n * ntx, st);
-    launch_adjoint_rhs(p->dp, nrx, drx.as<int32_t>(), ntx, (const double2*)gS, lam.as<double2>(), ntx, st);
-    sync(c);
   });
   if (s != MW_OK) return s;
-  s = mw_solve(p, ntx, lam.p, F.p, o, info);
-  if (s != MW_OK) return s;
-  return guard([&] {
-    DeviceGuard dg(c->device);
-    launch_gradient(p->dm, (const double2*)U, F.as<double2>(), ntx, ntx, p->k0, (double2*)grad_eps, c->stream);
-    sync(c);
-  });
+  if ((s = mw_adjoint_rhs(p, nrx, rx, ntx, gS, lam.p)) != MW_OK) return s;
+  if ((s = mw_solve(p, ntx, lam.p, F.p, o, info)) != MW_OK) return s;
+  return mw_gradient(p, ntx, U, F.p, grad_eps);
 }
 
 mw_status mw_misfit_gradient(mw_problem* p, int32_t ntx, const int32_t* tx, int32_t nrx, const int32_t* rx,
@@ -817,26 +915,320 @@ mw_status mw_misfit_gradient(mw_problem* p, int32_t ntx, const int32_t* tx, int3
   if (s != MW_OK) return s;
   mw_ctx* c = p->ctx;
   const int64_t n = p->T.n();
-  DevBuf Bb, Ub, gS, dJ;
+  DevBuf Bb, Ub, gS;
   s = guard([&] {
+    DeviceGuard dg(c->device);
     Bb = dalloc(c, n * ntx * 16);
     Ub = dalloc(c, n * ntx * 16);
     gS = dalloc(c, (int64_t)nrx * ntx * 16);
-    dJ = dalloc(c, 8);
   });
   if (s != MW_OK) return s;
   if ((s = mw_rhs_ports(p, ntx, tx, Bb.p)) != MW_OK) return s;
   if ((s = mw_solve(p, ntx, Bb.p, Ub.p, o, nullptr)) != MW_OK) return s;
   if ((s = mw_s_matrix(p, nrx, rx, ntx, Ub.p, S_sim)) != MW_OK) return s;
-  s = guard([&] {
-    DeviceGuard dg(c->device);
-    launch_misfit((const double2*)S_sim, (const double2*)S_meas, (int64_t)nrx * ntx, gS.as<double2>(), dJ.as<double>(),
-                  c->stream);
-    MW_HIP(hipMemcpyAsync(J, dJ.p, 8, hipMemcpyDeviceToHost, c->stream));
-    sync(c);
+  if ((s = mw_misfit(p, (int64_t)nrx * ntx, S_sim, S_meas, gS.p, J)) != MW_OK) return s;
+  return mw_adjoint_gradient(p, ntx, tx, nrx, rx, Ub.p, gS.p, grad_eps, o, nullptr);
+}
+
+// ---------------------------------------------------------------- serving support
+mw_status mw_ctx_get_info(mw_ctx* ctx, int64_t* budget, int64_t* used) {
+  return guard([&] {
+    MW_CHECK(ctx != nullptr, MW_EINVAL, "ctx is NULL");
+    if (budget) *budget = ctx->budget;
+    if (used) *used = ctx->used.load();
+  });
+}
+
+mw_status mw_problem_set_stream(mw_problem* p, void* stream) {
+  return guard([&] {
+    check_prob(p);
+    DeviceGuard dg(p->ctx->device);
+    psync(p);
+    p->stream = (hipStream_t)stream;
+  });
+}
+
+mw_status mw_release_factors(mw_problem* p) {
+  return guard([&] {
+    check_prob(p);
+    DeviceGuard dg(p->ctx->device);
+    psync(p);
+    p->F.release();
+    p->ws.release();
+    p->factors_valid = false;
+  });
+}
+
+mw_status mw_factor_bytes(mw_problem* p, int32_t n_sub, int32_t overlap, mw_precision prec, const int32_t* tet_part,
+                          int64_t* bytes) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(bytes && tet_part, MW_EINVAL, "NULL argument");
+    MW_CHECK(prec == MW_C64 || prec == MW_C128, MW_EINVAL, "precision must be MW_C64 or MW_C128");
+    int64_t esz = prec == MW_C64 ? 8 : 16;
+    uint64_t key = hash_part(tet_part, p->T.nt, n_sub, overlap);
+    MW_CHECK(p->has_dec && key == p->dec_key, MW_EINVAL,
+             "no decomposition for this partition yet: call mw_factor_subdomains once");
+    *bytes = p->D.fac_off.back() * esz;
+  });
+}
+
+}  // extern "C"
+
+// Continuous batching of pseudo-block GMRES columns over one problem.  Each
+// request owns some column slots of the batch; its columns join the Krylov
+// iteration at the next restart cycle and leave it at the restart where
+// their true residual meets the tolerance.  Pseudo-block columns never mix,
+// so a column's iterates do not depend on its batch-mates.
+struct mw_batch {
+  mw_problem* p = nullptr;
+  mw_solve_opts o{};
+  int max_cols = 0;
+  DevBuf Bs, Xs, idx;   // slot storage n x max_cols (ld max_cols); device index list [max_cols]
+  GmresWork W;          // compact per-cycle workspaces, released when the batch idles
+  enum { FREE = 0, ACTIVE = 1, DONE = 2 };
+  struct Slot {
+    int64_t tag = -1;
+    int state = FREE;
+    int32_t iters = 0;
+    double bnorm = 0, relres = 0;
+    bool numeric = false;
+  };
+  std::vector<Slot> slots;
+  struct Req {
+    std::vector<int32_t> slots;
+    int left = 0;
+  };
+  std::map<int64_t, Req> reqs;
+  std::deque<int64_t> done;
+  int64_t cycles = 0;
+};
+
+namespace {
+
+void check_batch(mw_batch* b) {
+  MW_CHECK(b != nullptr && b->p != nullptr, MW_EINVAL, "batch is NULL");
+}
+
+void batch_retire_if_done(mw_batch* b, int slot, int& finished) {
+  auto it = b->reqs.find(b->slots[slot].tag);
+  if (--it->second.left == 0) {
+    b->done.push_back(it->first);
+    ++finished;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+mw_status mw_batch_create(mw_problem* p, int32_t max_cols, const mw_solve_opts* o, mw_batch** out) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(out != nullptr && max_cols >= 1, MW_EINVAL, "out is NULL or max_cols < 1");
+    mw_solve_opts op{1e-8, 30, 1000, 0};
+    if (o) op = *o;
+    MW_CHECK(op.restart >= 1 && op.maxit >= 1 && op.tol > 0, MW_EINVAL, "invalid solve options");
+    MW_CHECK(!op.use_x0, MW_EINVAL, "batched columns start from x0 = 0");
+    DeviceGuard dg(p->ctx->device);
+    auto b = std::make_unique<mw_batch>();
+    b->p = p;
+    b->o = op;
+    b->max_cols = max_cols;
+    const int64_t n = p->T.n();
+    b->Bs = dalloc(p->ctx, n * max_cols * 16);
+    b->Xs = dalloc(p->ctx, n * max_cols * 16);
+    b->idx = dalloc(p->ctx, (int64_t)max_cols * 4);
+    b->slots.resize(max_cols);
+    p->live_batches++;
+    *out = b.release();
+  });
+}
+
+mw_status mw_batch_join(mw_batch* b, int64_t tag, int32_t ncols, const void* B) {
+  return guard([&] {
+    check_batch(b);
+    MW_CHECK(tag >= 0 && ncols >= 1 && B, MW_EINVAL, "tag < 0, ncols < 1 or B NULL");
+    MW_CHECK(b->reqs.find(tag) == b->reqs.end(), MW_EINVAL, "tag already in use in this batch");
+    mw_problem* p = b->p;
+    std::vector<int32_t> sl;
+    for (int k = 0; k < b->max_cols && (int)sl.size() < ncols; ++k)
+      if (b->slots[k].state == mw_batch::FREE) sl.push_back(k);
+    MW_CHECK((int)sl.size() == ncols, MW_ENOMEM,
+             "batch has " + std::to_string(sl.size()) + " free column slots, request needs " + std::to_string(ncols));
+    DeviceGuard dg(p->ctx->device);
+    hipStream_t st = p->stream;
+    const int64_t n = p->T.n();
+    MW_HIP(hipMemcpyAsync(b->idx.p, sl.data(), ncols * 4, hipMemcpyHostToDevice, st));
+    launch_scatter_cols((const double2*)B, ncols, b->idx.as<int32_t>(), b->Bs.as<double2>(), b->max_cols, n, ncols, st);
+    launch_scatter_cols(nullptr, 0, b->idx.as<int32_t>(), b->Xs.as<double2>(), b->max_cols, n, ncols, st);
+    double* nb = (double*)b->W.vec.get(p->ctx, (int64_t)4 * b->max_cols * 8);
+    colnorm2(p, b->W, (const double2*)B, ncols, ncols, nb);
+    std::vector<double> h(ncols);
+    MW_HIP(hipMemcpyAsync(h.data(), nb, ncols * 8, hipMemcpyDeviceToHost, st));
+    psync(p);
+    mw_batch::Req r;
+    r.slots = sl;
+    r.left = ncols;
+    b->reqs[tag] = r;
+    int finished = 0;
+    for (int k = 0; k < ncols; ++k) {
+      mw_batch::Slot& s = b->slots[sl[k]];
+      s.tag = tag;
+      s.iters = 0;
+      s.bnorm = std::sqrt(h[k]);
+      s.relres = 0.0;
+      s.numeric = !std::isfinite(s.bnorm);
+      s.state = mw_batch::ACTIVE;
+      if (!(s.bnorm > 0) || s.numeric) {   // b = 0: x = 0 is exact
+        s.state = mw_batch::DONE;
+        batch_retire_if_done(b, sl[k], finished);
+      }
+    }
+  });
+}
+
+mw_status mw_batch_cycle(mw_batch* b, int32_t* n_active, int32_t* n_finished) {
+  return guard([&] {
+    check_batch(b);
+    mw_problem* p = b->p;
+    MW_CHECK(p->factors_valid, MW_EINVAL, "no valid subdomain factors: call mw_factor_subdomains");
+    if (n_active) *n_active = 0;
+    if (n_finished) *n_finished = 0;
+    std::vector<int32_t> act;
+    for (int k = 0; k < b->max_cols; ++k)
+      if (b->slots[k].state == mw_batch::ACTIVE) act.push_back(k);
+    const int na = (int)act.size();
+    DeviceGuard dg(p->ctx->device);
+    if (na == 0) {
+      b->W.release();
+      return;
+    }
+    if (n_active) *n_active = na;
+    mw_ctx* c = p->ctx;
+    hipStream_t st = p->stream;
+    const int64_t n = p->T.n();
+    GmresWork& W = b->W;
+    double2* X = (double2*)W.X.get(c, n * na * 16);
+    double2* Bc = (double2*)W.B.get(c, n * na * 16);
+    double2* Z = (double2*)W.Z.get(c, n * na * 16);
+    double* vec = (double*)W.vec.get(c, (int64_t)4 * b->max_cols * 8);
+    std::vector<double> hb(na), hr, rnorm(na), relres(na);
+    std::vector<int32_t> iters(na), hact(na);
+    for (int k = 0; k < na; ++k) {
+      hb[k] = b->slots[act[k]].bnorm;
+      iters[k] = b->slots[act[k]].iters;
+    }
+    MW_HIP(hipMemcpyAsync(b->idx.p, act.data(), na * 4, hipMemcpyHostToDevice, st));
+    MW_HIP(hipMemcpyAsync(vec, hb.data(), na * 8, hipMemcpyHostToDevice, st));
+    launch_gather_cols(b->Bs.as<double2>(), b->max_cols, b->idx.as<int32_t>(), Bc, na, n, na, st);
+    launch_gather_cols(b->Xs.as<double2>(), b->max_cols, b->idx.as<int32_t>(), X, na, n, na, st);
+    // residual at the start of the cycle (x of the previous restart, or 0)
+    true_residual(p, W, Bc, X, Z, na, vec + na, hr);
+    for (int k = 0; k < na; ++k) {
+      double r = std::sqrt(hr[k]);
+      relres[k] = r / hb[k];
+      rnorm[k] = r;
+      hact[k] = column_continues(hb[k], relres[k], iters[k], r, b->o) ? 1 : 0;
+    }
+    gmres_cycle(p, W, X, Z, na, b->o, vec, rnorm, hact, iters);
+    b->cycles++;
+    // restart point: the true residual decides which columns leave
+    true_residual(p, W, Bc, X, Z, na, vec + na, hr);
+    launch_scatter_cols(X, na, b->idx.as<int32_t>(), b->Xs.as<double2>(), b->max_cols, n, na, st);
+    psync(p);
+    int finished = 0, still = 0;
+    for (int k = 0; k < na; ++k) {
+      mw_batch::Slot& s = b->slots[act[k]];
+      double r = std::sqrt(hr[k]);
+      s.iters = iters[k];
+      s.relres = r / s.bnorm;
+      s.numeric = !std::isfinite(r);
+      if (column_continues(s.bnorm, s.relres, s.iters, r, b->o)) {
+        ++still;
+      } else {
+        s.state = mw_batch::DONE;
+        batch_retire_if_done(b, act[k], finished);
+      }
+    }
+    if (still == 0) W.release();
+    if (n_finished) *n_finished = finished;
+  });
+}
+
+mw_status mw_batch_poll(mw_batch* b, int64_t* tag, int32_t* ncols) {
+  return guard([&] {
+    check_batch(b);
+    MW_CHECK(tag != nullptr, MW_EINVAL, "tag is NULL");
+    *tag = -1;
+    if (ncols) *ncols = 0;
+    if (b->done.empty()) return;
+    *tag = b->done.front();
+    if (ncols) *ncols = (int32_t)b->reqs[*tag].slots.size();
+  });
+}
+
+mw_status mw_batch_take(mw_batch* b, int64_t tag, void* X, int32_t* iters, double* relres) {
+  bool noconv = false, numeric = false;
+  mw_status s = guard([&] {
+    check_batch(b);
+    MW_CHECK(X != nullptr, MW_EINVAL, "X is NULL");
+    auto it = b->reqs.find(tag);
+    MW_CHECK(it != b->reqs.end() && it->second.left == 0, MW_EINVAL, "request is unknown or not finished");
+    mw_problem* p = b->p;
+    DeviceGuard dg(p->ctx->device);
+    const std::vector<int32_t>& sl = it->second.slots;
+    const int nc = (int)sl.size();
+    MW_HIP(hipMemcpyAsync(b->idx.p, sl.data(), nc * 4, hipMemcpyHostToDevice, p->stream));
+    launch_gather_cols(b->Xs.as<double2>(), b->max_cols, b->idx.as<int32_t>(), (double2*)X, nc, p->T.n(), nc,
+                       p->stream);
+    psync(p);
+    for (int k = 0; k < nc; ++k) {
+      mw_batch::Slot& q = b->slots[sl[k]];
+      if (iters) iters[k] = q.iters;
+      if (relres) relres[k] = q.relres;
+      noconv |= !(q.relres <= b->o.tol);
+      numeric |= q.numeric;
+      q = mw_batch::Slot();
+    }
+    b->reqs.erase(it);
+    b->done.erase(std::find(b->done.begin(), b->done.end(), tag));
   });
   if (s != MW_OK) return s;
-  return mw_adjoint_gradient(p, ntx, tx, nrx, rx, Ub.p, gS.p, grad_eps, o, nullptr);
+  if (numeric) { g_last_error = "NaN or Inf in a GMRES residual"; return MW_ENUMERIC; }
+  if (noconv) { g_last_error = "GMRES did not reach the tolerance within maxit"; return MW_ENOCONV; }
+  return MW_OK;
+}
+
+mw_status mw_batch_get_info(mw_batch* b, mw_batch_info* info) {
+  return guard([&] {
+    check_batch(b);
+    MW_CHECK(info != nullptr, MW_EINVAL, "info is NULL");
+    std::memset(info, 0, sizeof(*info));
+    info->max_cols = b->max_cols;
+    for (const auto& s : b->slots) {
+      if (s.state == mw_batch::FREE) info->free_cols++;
+      if (s.state == mw_batch::ACTIVE) info->active_cols++;
+    }
+    info->requests = (int32_t)b->reqs.size();
+    info->finished = (int32_t)b->done.size();
+    info->cycles = b->cycles;
+    info->slot_bytes = (int64_t)(b->Bs.bytes + b->Xs.bytes + b->idx.bytes);
+    info->work_bytes = b->W.held();
+    info->bytes_per_col = gmres_bytes_per_col(b->p, b->o.restart);
+  });
+}
+
+mw_status mw_batch_destroy(mw_batch* b) {
+  return guard([&] {
+    if (!b) return;
+    if (b->p) {
+      DeviceGuard dg(b->p->ctx->device);
+      (void)hipStreamSynchronize(b->p->stream);
+      b->p->live_batches--;
+    }
+    delete b;
+  });
 }
 
 }  // extern "C"

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <stdexcept>
@@ -42,7 +43,7 @@ struct Error : std::runtime_error {
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
-  int64_t* ledger = nullptr;  // running total of the owning context
+  std::atomic<int64_t>* ledger = nullptr;  // running total of the owning context
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
@@ -59,7 +60,7 @@ struct DevBuf {
   void release() {
     if (p) {
       (void)hipFree(p);
-      if (ledger) *ledger -= (int64_t)bytes;
+      if (ledger) ledger->fetch_sub((int64_t)bytes);
     }
     p = nullptr;
     bytes = 0;

@@ -152,6 +152,13 @@ void launch_start_cycle(const double2* r, double2* v0, int64_t n, int64_t ld, in
 void launch_copy_cols(const double2* src, int64_t lds, double2* dst, int64_t ldd, int64_t n, int ncols,
                       hipStream_t st);
 void launch_zero(double2* p, int64_t count, hipStream_t st);
+// column moves by an index list idx (device [ncols]) over n rows:
+// gather dst[:, k] = src[:, idx[k]]; scatter dst[:, idx[k]] = src[:, k];
+// scatter of zeros when src is NULL
+void launch_gather_cols(const double2* src, int64_t lds, const int32_t* idx, double2* dst, int64_t ldd, int64_t n,
+                        int ncols, hipStream_t st);
+void launch_scatter_cols(const double2* src, int64_t lds, const int32_t* idx, double2* dst, int64_t ldd, int64_t n,
+                         int ncols, hipStream_t st);
 void launch_zero_bytes(void* p, int64_t bytes, hipStream_t st);
 void launch_misfit(const double2* S, const double2* Sm, int64_t count, double2* gS, double* J, hipStream_t st);
 

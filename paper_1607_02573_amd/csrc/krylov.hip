@@ -504,6 +504,28 @@ void launch_copy_cols(const double2* src, int64_t lds, double2* dst, int64_t ldd
   MW_LAUNCH_CHECK();
 }
 
+__global__ void k_move_cols(const double2* __restrict__ src, int64_t lds, const int32_t* __restrict__ idx,
+                            double2* __restrict__ dst, int64_t ldd, int64_t n, int ncols, int scatter) {
+  int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t r = id / ncols;
+  int k = (int)(id % ncols);
+  if (r >= n) return;
+  if (scatter) dst[r * ldd + idx[k]] = src ? src[r * lds + k] : make_double2(0.0, 0.0);
+  else dst[r * ldd + k] = src[r * lds + idx[k]];
+}
+void launch_gather_cols(const double2* src, int64_t lds, const int32_t* idx, double2* dst, int64_t ldd, int64_t n,
+                        int ncols, hipStream_t st) {
+  if (n * ncols == 0) return;
+  k_move_cols<<<(unsigned)ceil_div(n * ncols, 256), 256, 0, st>>>(src, lds, idx, dst, ldd, n, ncols, 0);
+  MW_LAUNCH_CHECK();
+}
+void launch_scatter_cols(const double2* src, int64_t lds, const int32_t* idx, double2* dst, int64_t ldd, int64_t n,
+                         int ncols, hipStream_t st) {
+  if (n * ncols == 0) return;
+  k_move_cols<<<(unsigned)ceil_div(n * ncols, 256), 256, 0, st>>>(src, lds, idx, dst, ldd, n, ncols, 1);
+  MW_LAUNCH_CHECK();
+}
+
 __global__ void k_zero_bytes(uint32_t* __restrict__ p, int64_t words) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0u;

@@ -48,6 +48,12 @@ class Context:
         self.stream = stream or torch.cuda.current_stream(self.device)
         check(L.mw_set_stream(self.h, C.c_void_p(self.stream.cuda_stream)))
 
+    def info(self) -> tuple[int, int]:
+        """(budget, bytes held) of the context."""
+        b, u = C.c_int64(), C.c_int64()
+        check(lib().mw_ctx_get_info(self.h, C.addressof(b), C.addressof(u)))
+        return b.value, u.value
+
     def close(self):
         if self.h:
             check(lib().mw_destroy(self.h))
@@ -138,6 +144,21 @@ class Problem:
         prec = {"c128": B.MW_C128, "c64": B.MW_C64}[precision]
         check(lib().mw_factor_subdomains(self.h, int(n_sub), int(overlap), prec, ptr(part)))
 
+    def factor_bytes(self, part, n_sub: int, overlap: int = 1, precision: str = "c64") -> int:
+        """Device bytes of the factors of this partition (decomposition built once before)."""
+        part = np.ascontiguousarray(part, dtype=np.int32)
+        prec = {"c128": B.MW_C128, "c64": B.MW_C64}[precision]
+        out = C.c_int64()
+        check(lib().mw_factor_bytes(self.h, int(n_sub), int(overlap), prec, ptr(part), C.addressof(out)))
+        return out.value
+
+    def release_factors(self):
+        check(lib().mw_release_factors(self.h))
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        self.stream = stream
+        check(lib().mw_problem_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
+
     def apply_preconditioner(self, V: torch.Tensor) -> torch.Tensor:
         _dev_tensor(V, torch.complex128, self.ctx.device, "V")
         Z = torch.empty_like(V)
@@ -189,6 +210,78 @@ class Problem:
         check(lib().mw_misfit_gradient(self.h, tx.size, ptr(tx), rx.size, ptr(rx), ptr(S_meas), C.addressof(J),
                                        ptr(S), ptr(g), C.byref(o)))
         return J.value, S, g
+
+
+    def adjoint_rhs(self, gS: torch.Tensor, rx) -> torch.Tensor:
+        rx = np.ascontiguousarray(rx, dtype=np.int32)
+        _dev_tensor(gS, torch.complex128, self.ctx.device, "gS")
+        lam = torch.empty((self.n, gS.shape[1]), dtype=torch.complex128, device=self.ctx.device)
+        check(lib().mw_adjoint_rhs(self.h, rx.size, ptr(rx), gS.shape[1], ptr(gS), ptr(lam)))
+        return lam
+
+    def gradient(self, U: torch.Tensor, F: torch.Tensor) -> torch.Tensor:
+        _dev_tensor(U, torch.complex128, self.ctx.device, "U")
+        _dev_tensor(F, torch.complex128, self.ctx.device, "F")
+        assert U.shape == F.shape
+        g = torch.empty(self.nt, dtype=torch.complex128, device=self.ctx.device)
+        check(lib().mw_gradient(self.h, U.shape[1], ptr(U), ptr(F), ptr(g)))
+        return g
+
+    def misfit(self, S: torch.Tensor, S_meas: torch.Tensor):
+        _dev_tensor(S, torch.complex128, self.ctx.device, "S")
+        _dev_tensor(S_meas, torch.complex128, self.ctx.device, "S_meas")
+        assert S.shape == S_meas.shape
+        gS = torch.empty_like(S)
+        J = C.c_double()
+        check(lib().mw_misfit(self.h, S.numel(), ptr(S), ptr(S_meas), ptr(gS), C.addressof(J)))
+        return J.value, gS
+
+
+class Batch:
+    """Continuous batching of GMRES columns over one problem's factors: requests
+    join between restart cycles and leave when all their columns converged."""
+
+    def __init__(self, problem: Problem, max_cols: int, tol=1e-8, restart=30, maxit=1000):
+        self.problem = problem
+        h = C.c_void_p()
+        o = _opts(tol, restart, maxit, 0)
+        check(lib().mw_batch_create(problem.h, int(max_cols), C.byref(o), C.byref(h)))
+        self.h = h
+
+    def join(self, tag: int, Bm: torch.Tensor):
+        _dev_tensor(Bm, torch.complex128, self.problem.ctx.device, "B")
+        check(lib().mw_batch_join(self.h, int(tag), Bm.shape[1], ptr(Bm)))
+
+    def cycle(self) -> tuple[int, int]:
+        """One restart cycle; returns (columns that ran, requests finished)."""
+        na, nf = C.c_int32(), C.c_int32()
+        check(lib().mw_batch_cycle(self.h, C.addressof(na), C.addressof(nf)))
+        return na.value, nf.value
+
+    def poll(self) -> tuple[int, int]:
+        """(tag, ncols) of the oldest finished request, or (-1, 0)."""
+        t, nc = C.c_int64(), C.c_int32()
+        check(lib().mw_batch_poll(self.h, C.addressof(t), C.addressof(nc)))
+        return t.value, nc.value
+
+    def take(self, tag: int, ncols: int, raise_noconv: bool = True):
+        X = torch.empty((self.problem.n, ncols), dtype=torch.complex128, device=self.problem.ctx.device)
+        it = np.zeros(ncols, dtype=np.int32)
+        rr = np.zeros(ncols)
+        code = lib().mw_batch_take(self.h, int(tag), ptr(X), ptr(it), ptr(rr))
+        if code != B.MW_OK and not (code == B.MW_ENOCONV and not raise_noconv):
+            check(code)
+        return X, it, rr
+
+    def info(self) -> B.mw_batch_info:
+        i = B.mw_batch_info()
+        check(lib().mw_batch_get_info(self.h, C.byref(i)))
+        return i
+
+    def close(self):
+        if self.h:
+            check(lib().mw_batch_destroy(self.h))
+            self.h = None
 
 
 def problem_from_workload(ctx: Context, w) -> Problem:
