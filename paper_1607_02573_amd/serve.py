@@ -30,7 +30,7 @@ import torch
 from .solver import Batch, Context, Problem
 
 
-@dataclass
+@dataclass(eq=False)
 class Group:
     """Columns of one request admitted together."""
     req: object
@@ -331,20 +331,23 @@ class Server:
         evict idle factors (lock held)."""
         blocked = False
         busy = {key for key, s in self.slots.items() if s.inbox or s.tags}
-        for g in list(pending):
+        waiting = list(pending)
+        pending.clear()
+        for g in waiting:
             key = (g.req.mesh, g.req.version)
             nc = len(g.cols)
             s = self.slots[key]
             if self.adm.fits(key, nc) and not s.evict:
                 self.adm.admit(key, nc, now)
-                pending.remove(g)
                 out = self.outcomes[g.req.rid]
                 if out.t_admit < 0:
                     out.t_admit = now
                 s.inbox.append(g)
                 busy.add(key)
                 self.cond.notify_all()
-            elif not blocked:
+                continue
+            pending.append(g)
+            if not blocked:
                 blocked = True
                 q = self.adm.p[key]
                 if q["open"] + nc > q["max_cols"]:

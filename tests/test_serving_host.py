@@ -55,3 +55,50 @@ def test_admission_bookkeeping():
     a.evicted("A")
     assert a.total() == 100 and a.fits("B", 8)
     assert a.group_cols("B") == min(16, (1000 - 100 - 430) // 20)
+
+
+def test_dispatch_first_fit_then_eviction():
+    """The dispatcher admits in arrival order what fits, and lets the oldest
+    blocked group evict idle factors (no GPU: slots are stand-ins)."""
+    import threading
+    from collections import deque
+
+    from paper_1607_02573_amd.serve import Admission, Group, Outcome, Server
+
+    class Slot:
+        def __init__(self):
+            self.inbox, self.tags, self.evict = deque(), {}, False
+
+    srv = object.__new__(Server)
+    srv.cond = threading.Condition()
+    srv.adm = Admission(budget=1000, base=100)
+    srv.adm.add_problem((0, 0), 300, 20, 10, 16)
+    srv.adm.add_problem((1, 0), 400, 30, 20, 16)
+    srv.slots = {(0, 0): Slot(), (1, 0): Slot()}
+    mk = mi.serving.Request
+    reqs = [mk(0, 0.0, 0, 0, "solve", np.arange(6, dtype=np.int32), np.arange(8, dtype=np.int32)),
+            mk(1, 0.1, 1, 0, "solve", np.arange(8, dtype=np.int32), np.arange(8, dtype=np.int32)),
+            mk(2, 0.2, 0, 0, "solve", np.arange(3, dtype=np.int32), np.arange(8, dtype=np.int32))]
+    srv.outcomes = {r.rid: Outcome(r.rid, r.kind, r.mesh, r.version, r.ncols, r.t_arrive) for r in reqs}
+    groups = [Group(r, np.arange(r.ncols)) for r in reqs]
+    pending = deque(groups)
+    with srv.cond:
+        srv._admit(pending, 1.0)
+    # request 0 and 2 (problem (0,0)) fit; request 1 needs 430 + 160 more bytes
+    assert list(pending) == [groups[1]]
+    assert list(srv.slots[(0, 0)].inbox) == [groups[0], groups[2]]
+    assert srv.outcomes[0].t_admit == 1.0 and srv.outcomes[1].t_admit < 0
+    assert not srv.slots[(0, 0)].evict          # (0,0) is busy: no victim yet
+    # both finish; (0,0) idles with its factors resident
+    srv.slots[(0, 0)].inbox.clear()
+    srv.adm.finish((0, 0), 6)
+    srv.adm.finish((0, 0), 3)
+    with srv.cond:
+        srv._admit(pending, 2.0)
+    assert list(pending) == [groups[1]] and srv.slots[(0, 0)].evict
+    srv.adm.evicted((0, 0))
+    srv.slots[(0, 0)].evict = False
+    with srv.cond:
+        srv._admit(pending, 3.0)
+    assert not pending and list(srv.slots[(1, 0)].inbox) == [groups[1]]
+    assert srv.adm.total() == 100 + 430 + 160
