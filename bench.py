@@ -154,8 +154,11 @@ def serve_main(args):
         ", ".join(f"{e.name} {e.n_edges} edges / {e.workload.n_sub} subdomains" for e in menu))
     reqs = mi.serving.serving_requests(n_req=args.serve_requests, rate=args.serve_rate)
     total = torch.cuda.mem_get_info()[1]
-    ctx = solver.Context(0, budget_bytes=int(total - (32 << 30)))
-    srv = serve.Server(ctx, menu, tol=args.tol, restart=args.restart, maxit=args.maxit, log=log)
+    # library hard cap 8 GiB below the device; admission (library + PyTorch
+    # temporaries) 20 GiB below it
+    ctx = solver.Context(0, budget_bytes=int(total - (8 << 30)))
+    srv = serve.Server(ctx, menu, tol=args.tol, restart=args.restart, maxit=args.maxit, log=log,
+                       budget_bytes=int(total - (20 << 30)))
     log(f"[serve] {len(srv.slots)} problems set up in {srv.t_setup:.1f} s; serving {len(reqs)} requests "
         f"at {args.serve_rate}/s")
     t0 = time.perf_counter()

@@ -15,7 +15,11 @@ Admission counts, per problem: its factors and column slots while they are
 resident, plus the GMRES workspace of the widest set of open columns since
 the batch last idled (the library frees that workspace when a batch idles).
 A request wider than what fits beside its factors is split into column
-groups that are admitted separately.
+groups that are admitted separately.  The PyTorch tensors a group passes
+through (sources, fields, adjoint sources: at most four n-vectors per
+column at a time) are counted per column too, and each worker returns its
+stream's cached blocks to the device when a group finishes, so that the
+library's own allocations, which fail rather than wait, always find room.
 """
 from __future__ import annotations
 
@@ -148,7 +152,10 @@ class Server:
     """menu: list of mw_inputs.serving.MenuEntry.  Builds every (mesh, version)
     problem, its decomposition and its byte figures before serving."""
 
-    def __init__(self, ctx: Context, menu, tol=1e-8, restart=30, maxit=1000, max_cols=160, log=print):
+    TORCH_VECTORS_PER_COL = 4
+
+    def __init__(self, ctx: Context, menu, tol=1e-8, restart=30, maxit=1000, max_cols=160, log=print,
+                 budget_bytes: int | None = None):
         self.ctx, self.tol, self.restart, self.maxit, self.log = ctx, tol, restart, maxit, log
         self.cond = threading.Condition()
         self.slots = {}
@@ -172,11 +179,12 @@ class Server:
                     P.release_factors()
                 key = (mi, v)
                 self.slots[key] = _Slot(key, P, w.part, w.n_sub, stream)
-                figures[key] = (fb, inf.slot_bytes, inf.bytes_per_col, max_cols)
+                figures[key] = (fb, inf.slot_bytes, inf.bytes_per_col + self.TORCH_VECTORS_PER_COL * P.n * 16,
+                                max_cols)
                 self.log(f"[serve] problem {entry.name} v{v}: n={P.n}, {w.n_sub} subdomains, factors "
                          f"{fb / 2**30:.1f} GiB, {inf.bytes_per_col / 2**20:.0f} MiB per column")
         budget, used = ctx.info()
-        self.adm = Admission(budget, used)
+        self.adm = Admission(min(budget, budget_bytes) if budget_bytes else budget, used)
         for key, f in figures.items():
             self.adm.add_problem(key, *f)
         self.t_setup = time.perf_counter() - t0
@@ -249,6 +257,8 @@ class Server:
             r = g.req
             if r.kind == "solve":
                 out.S[int(g.cols[0])] = P.s_matrix(X, r.rx).cpu()
+                del X
+                torch.cuda.empty_cache()
                 with self.cond:
                     self._finish(s, g)
             elif g.phase == 0:
@@ -263,6 +273,8 @@ class Server:
             else:
                 out.grad = P.gradient(g.U, X)
                 g.U = None
+                del X
+                torch.cuda.empty_cache()
                 with self.cond:
                     self._finish(s, g)
 
