@@ -54,6 +54,7 @@ constexpr int TB = 64;    // output tile (complex) per workgroup: TB x TB
 constexpr int BK = 16;    // complex K per LDS stage
 constexpr int NB = 64;    // LU panel width and TRSM leaf size
 constexpr int W0 = 8;     // LU sub-panel width
+constexpr int NB2 = 256;  // LU outer block: the trailing update runs once per NB2 columns (K = NB2)
 
 // C[M x N] (ldc) = (OVERWRITE ? 0 : C) - A[M x K] (lda) * B[K x N] (ldb), for the
 // output tile (tm, tn); 256 threads = 4 waves, each a 32 x 32 complex quadrant.
@@ -298,8 +299,10 @@ __device__ __attribute__((always_inline)) inline void gemm3m(const float2* __res
   constexpr int TM = 32, TN = 32 * WC;
   constexpr int AREG = TM * G3K / 256;
   constexpr int BREG = (G3K * TN + 255) / 256;
+  // B rows padded by 16 floats: the four K rows a wave reads at once start in
+  // different halves of the 32 LDS banks
   __shared__ float As[2][3][TM][G3K + 1];
-  __shared__ float Bs[2][3][G3K][TN + 1];
+  __shared__ float Bs[2][3][G3K][TN + 16];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -452,12 +455,17 @@ __global__ void __launch_bounds__(256) k_leaf_x(const typename cplx<R>::t* F, co
   gemm_wide<R, WC, AMODE, true>(blk, np, Yb, ld, Yb, ld, NB, N, NB);
 }
 
-// LU update with wide tiles: F[r0:np, c0:min(c1,np)] -= F[r0:np, k0:k1] F[k0:k1, c0:min(c1,np)]
-// on every subdomain; 1-D XCD-aware grid of nsub * tiles_m * tiles_n.
-template <class R, int WC>
+// LU update with wide tiles:
+//   F[r0:min(r1,np), c0:min(c1,np)] -= F[r0:min(r1,np), k0:k1] F[k0:k1, c0:min(c1,np)]
+// on every subdomain; 1-D XCD-aware grid of nsub * tiles_m * tiles_n.  G3
+// selects the three-product complex form (FP32, 32-row tiles).
+template <class R, int WC, bool G3>
+struct LuwTile { static constexpr int TM = (G3 && sizeof(R) == 4) ? 32 : 64; };
+
+template <class R, int WC, bool G3>
 __global__ void __launch_bounds__(256) k_gemm_luw(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
-                                                  const int32_t* __restrict__ n_pad, int r0, int k0, int k1, int c0,
-                                                  int c1, int tiles_m, int tiles_n, int nsub) {
+                                                  const int32_t* __restrict__ n_pad, int r0, int r1, int k0, int k1,
+                                                  int c0, int c1, int tiles_m, int tiles_n, int nsub) {
   using C = typename cplx<R>::t;
   const int per_sub = tiles_m * tiles_n;
   const int G = gridDim.x;
@@ -467,25 +475,29 @@ __global__ void __launch_bounds__(256) k_gemm_luw(typename cplx<R>::t* F, const 
   const int t = logical % per_sub;
   const int tm = t / tiles_n, tn = t % tiles_n;
   const int np = n_pad[i];
-  constexpr int TM = 64;
-  const int M = np - r0 - tm * TM;
+  constexpr int TM = LuwTile<R, WC, G3>::TM;
+  const int M = min(r1, np) - r0 - tm * TM;
   const int N = min(c1, np) - c0 - tn * 32 * WC;
   if (M <= 0 || N <= 0 || k1 > np) return;
   C* Fi = F + fac_off[i];
   const int row = r0 + tm * TM, col = c0 + tn * 32 * WC;
-  gemm_wide<R, WC>(Fi + (int64_t)row * np + k0, np, Fi + (int64_t)k0 * np + col, np, Fi + (int64_t)row * np + col,
-                   np, M, min(N, 32 * WC), k1 - k0);
+  if constexpr (G3 && sizeof(R) == 4)
+    gemm3m<WC>(Fi + (int64_t)row * np + k0, np, Fi + (int64_t)k0 * np + col, np, Fi + (int64_t)row * np + col, np,
+               M, min(N, 32 * WC), k1 - k0);
+  else
+    gemm_wide<R, WC>(Fi + (int64_t)row * np + k0, np, Fi + (int64_t)k0 * np + col, np,
+                     Fi + (int64_t)row * np + col, np, M, min(N, 32 * WC), k1 - k0);
 }
 
-template <class R, int WC>
-static void launch_gemm_lu(const DeviceDecomp& d, typename cplx<R>::t* F, int r0, int k0, int k1, int c0, int c1,
-                           int maxp, hipStream_t st) {
-  int tiles_m = (int)ceil_div(maxp - r0, 64);
+template <class R, int WC, bool G3 = false>
+static void launch_gemm_lu(const DeviceDecomp& d, typename cplx<R>::t* F, int r0, int r1, int k0, int k1, int c0,
+                           int c1, int maxp, hipStream_t st) {
+  int tiles_m = (int)ceil_div(std::min(r1, maxp) - r0, LuwTile<R, WC, G3>::TM);
   int tiles_n = (int)ceil_div(std::min(c1, maxp) - c0, 32 * WC);
-  if (tiles_m <= 0 || tiles_n <= 0) return;
+  if (tiles_m <= 0 || tiles_n <= 0 || k1 <= k0) return;
   int64_t G = round_up((int64_t)d.nsub * tiles_m * tiles_n, 8);
-  k_gemm_luw<R, WC><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, r0, k0, k1, c0, c1, tiles_m, tiles_n,
-                                                 d.nsub);
+  k_gemm_luw<R, WC, G3><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, r0, r1, k0, k1, c0, c1, tiles_m,
+                                                     tiles_n, d.nsub);
   MW_LAUNCH_CHECK();
 }
 
@@ -943,45 +955,65 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st) {
   k_amax<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.amax);
   MW_LAUNCH_CHECK();
   const double rtol = sizeof(R) == 4 ? 1e-6 : 1e-14;
-  for (int k = 0; k < maxp; k += NB) {
-    for (int c = k; c < k + NB; c += W0) {
-      kt_begin(KF_LU_PANEL, st);
-      if constexpr (sizeof(R) == 4) {
-        if (maxp - c <= 4096) {
-          k_lu_panel_reg<4><<<d.nsub, 1024, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, d.amax, rtol,
-                                                    c, k);
+  // Right-looking blocked LU in two levels: 64-column panels (8-column
+  // sub-panels inside) are factored and applied within an outer block of
+  // NB2 columns; the rows of a panel beyond the outer block receive the
+  // block's earlier panels just before their triangular solve; the trailing
+  // matrix is updated once per outer block with K = NB2.
+  constexpr int WCL = sizeof(R) == 4 ? 5 : 2;
+  for (int K0 = 0; K0 < maxp; K0 += NB2) {
+    const int Kend = std::min(K0 + NB2, maxp);
+    for (int k = K0; k < Kend; k += NB) {
+      for (int c = k; c < k + NB; c += W0) {
+        kt_begin(KF_LU_PANEL, st);
+        if constexpr (sizeof(R) == 4) {
+          if (maxp - c <= 4096) {
+            k_lu_panel_reg<4><<<d.nsub, 1024, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, d.amax,
+                                                      rtol, c, k);
+          } else {
+            k_lu_panel<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, d.amax, rtol, c,
+                                                  k);
+          }
         } else {
           k_lu_panel<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, d.amax, rtol, c, k);
         }
-      } else {
-        k_lu_panel<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, d.amax, rtol, c, k);
+        MW_LAUNCH_CHECK();
+        kt_account(d, KF_LU_PANEL, st, [&](int n, double& f, double& b) {
+          double rows = clampd(n - c);
+          f = 8.0 * rows * W0 * W0 / 2;
+          b = 2.0 * rows * W0;
+        }, (int)sizeof(C));
+        int r0 = c + W0, c1 = k + NB;
+        if (r0 < c1) {
+          kt_begin(KF_LU_GEMM, st);
+          launch_gemm_lu<R, 2>(d, F, r0, maxp, c, c + W0, r0, c1, maxp, st);
+          kt_account(d, KF_LU_GEMM, st, [&](int n, double& f, double& b) {
+            double M = clampd(n - r0), N = clampd(std::min(c1, n) - r0), K = clampd(std::min(c + W0, n) - c);
+            f = 8.0 * M * N * K;
+            b = M * K + K * N + 2 * M * N;
+          }, (int)sizeof(C));
+        }
       }
+      int ncol = maxp;  // upper bound of columns outside the panel
+      kt_begin(KF_LU_OTHER, st);
+      k_laswp<R><<<dim3((unsigned)ceil_div(ncol, 256), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off,
+                                                                               d.ipiv, k);
       MW_LAUNCH_CHECK();
-      kt_account(d, KF_LU_PANEL, st, [&](int n, double& f, double& b) {
-        double rows = clampd(n - c);
-        f = 8.0 * rows * W0 * W0 / 2;
-        b = 2.0 * rows * W0;
-      }, (int)sizeof(C));
-      int r0 = c + W0, c1 = k + NB;
-      if (r0 < c1) {
+      kt_account(d, KF_LU_OTHER, st, [&](int n, double& f, double& b) { f = 0; b = n > k ? 2.0 * NB * n : 0; },
+                 (int)sizeof(C));
+      const int c0 = k + NB;
+      if (c0 >= maxp) continue;
+      if (k > K0 && Kend < maxp) {
+        // rows [k, k+NB) beyond the outer block: the block's panels [K0, k)
         kt_begin(KF_LU_GEMM, st);
-        launch_gemm_lu<R, 2>(d, F, r0, c, c + W0, r0, c1, maxp, st);
+        launch_gemm_lu<R, WCL, true>(d, F, k, k + NB, K0, k, Kend, maxp, maxp, st);
         kt_account(d, KF_LU_GEMM, st, [&](int n, double& f, double& b) {
-          double M = clampd(n - r0), N = clampd(std::min(c1, n) - r0), K = clampd(std::min(c + W0, n) - c);
+          double M = clampd(std::min(k + NB, n) - k), N = clampd(n - Kend), K = clampd(std::min(k, n) - K0);
+          if (M <= 0) N = 0;
           f = 8.0 * M * N * K;
           b = M * K + K * N + 2 * M * N;
         }, (int)sizeof(C));
       }
-    }
-    int ncol = maxp;  // upper bound of columns outside the panel
-    kt_begin(KF_LU_OTHER, st);
-    k_laswp<R><<<dim3((unsigned)ceil_div(ncol, 256), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off,
-                                                                             d.ipiv, k);
-    MW_LAUNCH_CHECK();
-    kt_account(d, KF_LU_OTHER, st, [&](int n, double& f, double& b) { f = 0; b = n > k ? 2.0 * NB * n : 0; },
-               (int)sizeof(C));
-    int c0 = k + NB;
-    if (c0 < maxp) {
       kt_begin(KF_LU_OTHER, st);
       k_trsm_panel<R><<<dim3((unsigned)ceil_div(maxp - c0, PANEL_COLS), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, k);
       MW_LAUNCH_CHECK();
@@ -990,17 +1022,28 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st) {
         f = 4.0 * NB * NB * N;
         b = NB * NB / 2.0 + 2.0 * NB * N;
       }, (int)sizeof(C));
-      kt_begin(KF_LU_GEMM, st);
-      {
-        int M = maxp - c0;
-        unsigned tiles = (unsigned)(ceil_div(M, TB) * ceil_div(M, TB));
-        k_gemm_lu<R><<<dim3(tiles, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, c0, k, k + NB, c0, maxp);
+      if (c0 < Kend) {
+        // inside the outer block: rows [c0, np), columns [c0, Kend)
+        kt_begin(KF_LU_GEMM, st);
+        int M = maxp - c0, N = Kend - c0;
+        unsigned tiles = (unsigned)(ceil_div(M, TB) * ceil_div(N, TB));
+        k_gemm_lu<R><<<dim3(tiles, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, c0, k, k + NB, c0, Kend);
         MW_LAUNCH_CHECK();
+        kt_account(d, KF_LU_GEMM, st, [&](int n, double& f, double& b) {
+          double M2 = clampd(n - c0), N2 = clampd(std::min(Kend, n) - c0), K = clampd(std::min(k + NB, n) - k);
+          f = 8.0 * M2 * N2 * K;
+          b = M2 * K + K * N2 + 2 * M2 * N2;
+        }, (int)sizeof(C));
       }
+    }
+    if (Kend < maxp) {
+      // trailing matrix: rows and columns [Kend, np), K = [K0, Kend)
+      kt_begin(KF_LU_GEMM, st);
+      launch_gemm_lu<R, WCL, true>(d, F, Kend, maxp, K0, Kend, Kend, maxp, maxp, st);
       kt_account(d, KF_LU_GEMM, st, [&](int n, double& f, double& b) {
-        double M2 = clampd(n - c0), K = clampd(std::min(k + NB, n) - k);
+        double M2 = clampd(n - Kend), K = clampd(std::min(Kend, n) - K0);
         f = 8.0 * M2 * M2 * K;
-        b = 2 * M2 * K + 2 * M2 * M2;
+        b = M2 * K + K * M2 + 2 * M2 * M2;
       }, (int)sizeof(C));
     }
   }

@@ -194,58 +194,84 @@ void launch_sum_chunks_c(const double2* part, int64_t nchunk, int64_t width, dou
 }
 
 // ---------------------------------------------------------------- K6 (CGS2)
-// part[chunk][k][c] = sum_{rows of chunk} conj(V_k[r][c]) w[r][c], k < kcount
+// part[chunk][k][c] = sum_{rows of chunk} conj(V_k[r][c]) w[r][c], k < kcount.
+// A workgroup takes KG basis vectors of one row chunk and 64 columns, so w is
+// read once per KG vectors; every (k, c) sum runs over the chunk's rows in the
+// same order whatever KG and the other columns are.
+constexpr int DOTS_KG = 8;
 __global__ void __launch_bounds__(256) k_dots_partial(const double2* __restrict__ V, int64_t vstride, int kcount,
                                                       const double2* __restrict__ w, int64_t n, int64_t ld,
                                                       int ncols, const int32_t* __restrict__ act,
                                                       double2* __restrict__ part) {
   __shared__ double2 red[4][64];
-  int k = blockIdx.x;
-  int chunk = blockIdx.y;
-  int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
-  int c = blockIdx.z * 64 + cl;
-  int64_t r0 = (int64_t)chunk * RCHUNK, r1 = min(n, r0 + RCHUNK);
-  double2 acc = make_double2(0.0, 0.0);
-  const double2* Vk = V + (int64_t)k * vstride;
-  if (c < ncols && act[c])
+  const int kb = blockIdx.x * DOTS_KG;
+  const int chunk = blockIdx.y;
+  const int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  const int c = blockIdx.z * 64 + cl;
+  const int64_t r0 = (int64_t)chunk * RCHUNK, r1 = min(n, r0 + RCHUNK);
+  double2 acc[DOTS_KG];
+#pragma unroll
+  for (int q = 0; q < DOTS_KG; ++q) acc[q] = make_double2(0.0, 0.0);
+  if (c < ncols && act[c]) {
+    const double2* Vb = V + (int64_t)kb * vstride;
     for (int64_t r = r0 + rl; r < r1; r += 4) {
-      double2 v = Vk[r * ld + c], x = w[r * ld + c];
-      acc.x += v.x * x.x + v.y * x.y;
-      acc.y += v.x * x.y - v.y * x.x;
+      const double2 x = w[r * ld + c];
+#pragma unroll
+      for (int q = 0; q < DOTS_KG; ++q)
+        if (kb + q < kcount) {
+          const double2 v = Vb[(int64_t)q * vstride + r * ld + c];
+          acc[q].x += v.x * x.x + v.y * x.y;
+          acc[q].y += v.x * x.y - v.y * x.x;
+        }
     }
-  red[rl][cl] = acc;
-  __syncthreads();
-  if (rl == 0 && c < ncols)
-    part[((int64_t)chunk * kcount + k) * ncols + c] =
-        cadd(cadd(cadd(red[0][cl], red[1][cl]), red[2][cl]), red[3][cl]);
+  }
+#pragma unroll
+  for (int q = 0; q < DOTS_KG; ++q) {
+    if (kb + q < kcount) {
+      red[rl][cl] = acc[q];
+      __syncthreads();
+      if (rl == 0 && c < ncols)
+        part[((int64_t)chunk * kcount + kb + q) * ncols + c] =
+            cadd(cadd(cadd(red[0][cl], red[1][cl]), red[2][cl]), red[3][cl]);
+      __syncthreads();
+    }
+  }
 }
 
 void launch_dots_partial(const double2* V, int64_t vstride, int kcount, const double2* w, int64_t n, int64_t ld,
                          int ncols, const int32_t* act, double2* part, hipStream_t st) {
-  dim3 g(kcount, (unsigned)reduce_chunks(n), (unsigned)ceil_div(ncols, 64));
+  dim3 g((unsigned)ceil_div(kcount, DOTS_KG), (unsigned)reduce_chunks(n), (unsigned)ceil_div(ncols, 64));
   kt_begin(KF_CGS_DOTS, st);
   k_dots_partial<<<g, 256, 0, st>>>(V, vstride, kcount, w, n, ld, ncols, act, part);
   MW_LAUNCH_CHECK();
   if (kt_enabled()) kt_end(KF_CGS_DOTS, st, 8.0 * kcount * n * ncols, (kcount + 1.0) * n * ncols * 16);
 }
 
-// w[r][c] -= sum_k V_k[r][c] h[k][c]; optionally |w|^2 chunk partials
+// w[r][c] -= sum_k V_k[r][c] h[k][c]; optionally |w|^2 chunk partials.
+// The coefficients sit in LDS when kcount <= CGS_HK.
+constexpr int CGS_HK = 32;
 __global__ void __launch_bounds__(256) k_cgs_update(const double2* __restrict__ V, int64_t vstride, int kcount,
                                                     const double2* __restrict__ h, double2* __restrict__ w, int64_t n,
                                                     int64_t ld, int ncols, const int32_t* __restrict__ act,
                                                     double* __restrict__ norm_part) {
   __shared__ double red[4][64];
+  extern __shared__ double2 hs[];   // [kcount][64] when kcount <= CGS_HK
   int chunk = blockIdx.x;
   int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
   int c = blockIdx.y * 64 + cl;
   int64_t r0 = (int64_t)chunk * RCHUNK, r1 = min(n, r0 + RCHUNK);
+  const bool in_lds = kcount <= CGS_HK;
+  if (in_lds) {
+    for (int k = rl; k < kcount; k += 4) hs[k * 64 + cl] = c < ncols ? h[(int64_t)k * ncols + c] : make_double2(0.0, 0.0);
+    __syncthreads();
+  }
   double acc = 0.0;
   if (c < ncols && act[c]) {
     for (int64_t r = r0 + rl; r < r1; r += 4) {
       double2 x = w[r * ld + c];
       for (int k = 0; k < kcount; ++k) {
         double2 v = V[(int64_t)k * vstride + r * ld + c];
-        double2 hk = h[(int64_t)k * ncols + c];
+        double2 hk = in_lds ? hs[k * 64 + cl] : h[(int64_t)k * ncols + c];
         x.x -= v.x * hk.x - v.y * hk.y;
         x.y -= v.x * hk.y + v.y * hk.x;
       }
@@ -265,7 +291,8 @@ void launch_cgs_update(const double2* V, int64_t vstride, int kcount, const doub
                        int64_t ld, int ncols, const int32_t* act, double* norm_part, hipStream_t st) {
   dim3 g((unsigned)reduce_chunks(n), (unsigned)ceil_div(ncols, 64));
   kt_begin(KF_CGS_UPDATE, st);
-  k_cgs_update<<<g, 256, 0, st>>>(V, vstride, kcount, h, w, n, ld, ncols, act, norm_part);
+  size_t lds = kcount <= CGS_HK ? (size_t)kcount * 64 * sizeof(double2) : 0;
+  k_cgs_update<<<g, 256, lds, st>>>(V, vstride, kcount, h, w, n, ld, ncols, act, norm_part);
   MW_LAUNCH_CHECK();
   if (kt_enabled()) kt_end(KF_CGS_UPDATE, st, 8.0 * kcount * n * ncols, (kcount + 2.0) * n * ncols * 16);
 }
