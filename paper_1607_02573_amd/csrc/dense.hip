@@ -288,15 +288,17 @@ __device__ __attribute__((always_inline)) inline void gemm_wide(const typename c
 // instruction), Re = P1 - P2 and Im = P3 - P1 - P2: 3/4 of the real MFMA work of
 // the 4M form.  Used for the FP32 preconditioner updates only (its rounding is
 // slightly larger in the imaginary part; the FP64 path keeps 4M).
-// Tile: 32 rows x 32*WC columns, waves 2 x 2 (16 rows x 16*WC columns each),
-// C -= A B, double-buffered LDS stages of G3K complex.
+// Tile: 32*RB rows x 32*WC columns, waves 2 x 2 (16*RB rows x 16*WC columns
+// each), C -= A B, double-buffered LDS stages of G3K complex.  RB = 2 halves
+// the B reads per product at the cost of occupancy (long K pays for it).
+// FULL: M, N, K are known to be multiples of the tile (no bounds tests).
 constexpr int G3K = 8;
-template <int WC>
+template <int WC, int RB = 1, bool FULL = false>
 __device__ __attribute__((always_inline)) inline void gemm3m(const float2* __restrict__ A, int64_t lda,
                                                              const float2* B, int64_t ldb, float2* Cm,
                                                              int64_t ldc, int M, int N, int K) {
   using acc_t = typename Mf<float>::acc;
-  constexpr int TM = 32, TN = 32 * WC;
+  constexpr int TM = 32 * RB, TN = 32 * WC;
   constexpr int AREG = TM * G3K / 256;
   constexpr int BREG = (G3K * TN + 255) / 256;
   // B rows padded by 16 floats: the four K rows a wave reads at once start in
@@ -307,11 +309,13 @@ __device__ __attribute__((always_inline)) inline void gemm3m(const float2* __res
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int li = lane & 15, kq = lane >> 4;
-  acc_t p1[WC], p2[WC], p3[WC];
+  acc_t p1[RB][WC], p2[RB][WC], p3[RB][WC];
 #pragma unroll
-  for (int y = 0; y < WC; ++y)
+  for (int x = 0; x < RB; ++x)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) { p1[y][r] = 0; p2[y][r] = 0; p3[y][r] = 0; }
+    for (int y = 0; y < WC; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) { p1[x][y][r] = 0; p2[x][y][r] = 0; p3[x][y][r] = 0; }
   float2 ra[AREG], rb[BREG];
   auto fetch = [&](int k0) {
 #pragma unroll
@@ -319,7 +323,7 @@ __device__ __attribute__((always_inline)) inline void gemm3m(const float2* __res
       int idx = tid + e * 256;
       int r = idx / G3K, kc = idx % G3K;
       float2 v = make_float2(0.f, 0.f);
-      if (r < M && k0 + kc < K) v = A[(int64_t)r * lda + k0 + kc];
+      if (FULL || (r < M && k0 + kc < K)) v = A[(int64_t)r * lda + k0 + kc];
       ra[e] = v;
     }
 #pragma unroll
@@ -327,7 +331,7 @@ __device__ __attribute__((always_inline)) inline void gemm3m(const float2* __res
       int idx = tid + e * 256;
       int r = idx / TN, c = idx % TN;
       float2 v = make_float2(0.f, 0.f);
-      if (idx < G3K * TN && k0 + r < K && c < N) v = B[(int64_t)(k0 + r) * ldb + c];
+      if (idx < G3K * TN && (FULL || (k0 + r < K && c < N))) v = B[(int64_t)(k0 + r) * ldb + c];
       rb[e] = v;
     }
   };
@@ -360,14 +364,24 @@ __device__ __attribute__((always_inline)) inline void gemm3m(const float2* __res
     if (more) fetch(k0 + G3K);
 #pragma unroll
     for (int kk = 0; kk < G3K; kk += 4) {
-      const int row = wm * 16 + li;
-      float a1 = As[buf][0][row][kk + kq], a2 = As[buf][1][row][kk + kq], a3 = As[buf][2][row][kk + kq];
+      float a1[RB], a2[RB], a3[RB];
+#pragma unroll
+      for (int x = 0; x < RB; ++x) {
+        const int row = wm * 16 * RB + x * 16 + li;
+        a1[x] = As[buf][0][row][kk + kq];
+        a2[x] = As[buf][1][row][kk + kq];
+        a3[x] = As[buf][2][row][kk + kq];
+      }
 #pragma unroll
       for (int y = 0; y < WC; ++y) {
         const int col = wn * 16 * WC + y * 16 + li;
-        p1[y] = Mf<float>::mfma(a1, Bs[buf][0][kk + kq][col], p1[y]);
-        p2[y] = Mf<float>::mfma(a2, Bs[buf][1][kk + kq][col], p2[y]);
-        p3[y] = Mf<float>::mfma(a3, Bs[buf][2][kk + kq][col], p3[y]);
+        const float b1 = Bs[buf][0][kk + kq][col], b2 = Bs[buf][1][kk + kq][col], b3 = Bs[buf][2][kk + kq][col];
+#pragma unroll
+        for (int x = 0; x < RB; ++x) {
+          p1[x][y] = Mf<float>::mfma(a1[x], b1, p1[x][y]);
+          p2[x][y] = Mf<float>::mfma(a2[x], b2, p2[x][y]);
+          p3[x][y] = Mf<float>::mfma(a3[x], b3, p3[x][y]);
+        }
       }
     }
     if (more) store(buf ^ 1);
@@ -375,31 +389,33 @@ __device__ __attribute__((always_inline)) inline void gemm3m(const float2* __res
     buf ^= 1;
   }
 #pragma unroll
-  for (int y = 0; y < WC; ++y)
+  for (int x = 0; x < RB; ++x)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int gr = wm * 16 + Mf<float>::out_row(lane, r);
-      int gc = wn * 16 * WC + y * 16 + li;
-      if (gr < M && gc < N) {
-        float2* p = Cm + (int64_t)gr * ldc + gc;
-        float2 o = *p;
-        o.x -= p1[y][r] - p2[y][r];
-        o.y -= p3[y][r] - p1[y][r] - p2[y][r];
-        *p = o;
+    for (int y = 0; y < WC; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int gr = wm * 16 * RB + x * 16 + Mf<float>::out_row(lane, r);
+        int gc = wn * 16 * WC + y * 16 + li;
+        if (FULL || (gr < M && gc < N)) {
+          float2* p = Cm + (int64_t)gr * ldc + gc;
+          float2 o = *p;
+          o.x -= p1[x][y][r] - p2[x][y][r];
+          o.y -= p3[x][y][r] - p1[x][y][r] - p2[x][y][r];
+          *p = o;
+        }
       }
-    }
 }
 
-// rows per tile of the triangular-solve updates: 32 (3M, FP32) or 64 (4M, FP64)
-template <class R> struct XTile { static constexpr int TM = sizeof(R) == 4 ? 32 : 64; };
+// rows per tile of the triangular-solve updates: 32*RB (3M, FP32) or 64 (4M, FP64)
+template <class R, int RB = 1> struct XTile { static constexpr int TM = sizeof(R) == 4 ? 32 * RB : 64; };
 
 // Triangular-solve update on the local multi-vector of every subdomain:
 // Y[r0:min(r1,np)] -= F[r0:min(r1,np), k0:min(k1,np)] * Y[k0:min(k1,np)].
 // 1-D grid of nsub * tiles_per_sub (padded to a multiple of 8) workgroups;
 // the linear id is remapped so that the tiles of one subdomain run on one XCD
 // (workgroups are dealt to the 8 XCDs round-robin) and share its L2.
-template <class R, int WC>
-__global__ void __launch_bounds__(256) k_gemm_x(const typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
+template <class R, int WC, int RB, bool FULL = false>
+__global__ void __launch_bounds__(256, RB) k_gemm_x(const typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
                                                 const int32_t* __restrict__ n_pad,
                                                 const int64_t* __restrict__ loc_off, typename cplx<R>::t* Y,
                                                 int64_t ld, int ncols, int r0, int r1, int k0, int k1,
@@ -414,10 +430,10 @@ __global__ void __launch_bounds__(256) k_gemm_x(const typename cplx<R>::t* F, co
   const int t = logical % per_sub;
   const int tm = t / tiles_n, tn = t % tiles_n;
   const int np = n_pad[i];
-  const int M = min(r1, np) - r0 - tm * XTile<R>::TM;
+  const int M = min(r1, np) - r0 - tm * XTile<R, RB>::TM;
   const int K = min(k1, np) - k0;
   if (M <= 0 || K <= 0) return;
-  constexpr int TM = XTile<R>::TM;
+  constexpr int TM = XTile<R, RB>::TM;
   const int TN = WC * 32;
   const int N = min(ncols - tn * TN, TN);
   const C* Fi = F + fac_off[i];
@@ -425,7 +441,7 @@ __global__ void __launch_bounds__(256) k_gemm_x(const typename cplx<R>::t* F, co
   const int row = r0 + tm * TM;
   if (row_lo && row + TM <= row_lo[i]) return;   // rows discarded by the weights
   if constexpr (sizeof(R) == 4)
-    gemm3m<WC>(Fi + (int64_t)row * np + k0, np, Yi + (int64_t)k0 * ld + tn * TN, ld,
+    gemm3m<WC, RB, FULL>(Fi + (int64_t)row * np + k0, np, Yi + (int64_t)k0 * ld + tn * TN, ld,
                Yi + (int64_t)row * ld + tn * TN, ld, M, N, K);
   else
     gemm_wide<R, WC>(Fi + (int64_t)row * np + k0, np, Yi + (int64_t)k0 * ld + tn * TN, ld,
@@ -458,12 +474,13 @@ __global__ void __launch_bounds__(256) k_leaf_x(const typename cplx<R>::t* F, co
 // LU update with wide tiles:
 //   F[r0:min(r1,np), c0:min(c1,np)] -= F[r0:min(r1,np), k0:k1] F[k0:k1, c0:min(c1,np)]
 // on every subdomain; 1-D XCD-aware grid of nsub * tiles_m * tiles_n.  G3
-// selects the three-product complex form (FP32, 32-row tiles).
+// selects the three-product complex form (FP32; 64-row tiles of two row blocks
+// per wave).
 template <class R, int WC, bool G3>
-struct LuwTile { static constexpr int TM = (G3 && sizeof(R) == 4) ? 32 : 64; };
+struct LuwTile { static constexpr int TM = 64; };
 
 template <class R, int WC, bool G3>
-__global__ void __launch_bounds__(256) k_gemm_luw(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
+__global__ void __launch_bounds__(256, (G3 && sizeof(R) == 4) ? 2 : 1) k_gemm_luw(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
                                                   const int32_t* __restrict__ n_pad, int r0, int r1, int k0, int k1,
                                                   int c0, int c1, int tiles_m, int tiles_n, int nsub) {
   using C = typename cplx<R>::t;
@@ -482,8 +499,8 @@ __global__ void __launch_bounds__(256) k_gemm_luw(typename cplx<R>::t* F, const 
   C* Fi = F + fac_off[i];
   const int row = r0 + tm * TM, col = c0 + tn * 32 * WC;
   if constexpr (G3 && sizeof(R) == 4)
-    gemm3m<WC>(Fi + (int64_t)row * np + k0, np, Fi + (int64_t)k0 * np + col, np, Fi + (int64_t)row * np + col, np,
-               M, min(N, 32 * WC), k1 - k0);
+    gemm3m<WC, 2>(Fi + (int64_t)row * np + k0, np, Fi + (int64_t)k0 * np + col, np, Fi + (int64_t)row * np + col,
+                  np, M, min(N, 32 * WC), k1 - k0);
   else
     gemm_wide<R, WC>(Fi + (int64_t)row * np + k0, np, Fi + (int64_t)k0 * np + col, np,
                      Fi + (int64_t)row * np + col, np, M, min(N, 32 * WC), k1 - k0);
@@ -1070,17 +1087,20 @@ static int pick_wc(int ncols) {
 }
 
 // Y[r0:r1] -= F[r0:r1, k0:k1] Y[k0:k1] on every subdomain
-template <class R, int WC>
+template <class R, int WC, int RB = 1, bool FULL = false>
 static void launch_gemm_x_wc(const DeviceDecomp& d, const typename cplx<R>::t* F, typename cplx<R>::t* Y,
                              int64_t ld, int ncols, int r0, int r1, int k0, int k1, const int32_t* row_lo,
                              hipStream_t st) {
-  int tiles_m = (int)ceil_div(r1 - r0, XTile<R>::TM);
+  int tiles_m = (int)ceil_div(r1 - r0, XTile<R, RB>::TM);
   int tiles_n = (int)ceil_div(ncols, WC * 32);
   int64_t G = round_up((int64_t)d.nsub * tiles_m * tiles_n, 8);
-  k_gemm_x<R, WC><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, Y, ld, ncols, r0, r1, k0, k1,
-                                               tiles_m, tiles_n, d.nsub, row_lo);
+  k_gemm_x<R, WC, RB, FULL><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, Y, ld, ncols, r0, r1, k0, k1,
+                                                   tiles_m, tiles_n, d.nsub, row_lo);
   MW_LAUNCH_CHECK();
 }
+// FP32 updates with a long inner dimension take 64-row tiles (two row blocks
+// per wave: half the B reads per product, lower occupancy).
+constexpr int RB2_MIN_K = 256;
 template <class R>
 static void launch_gemm_x(const DeviceDecomp& d, const typename cplx<R>::t* F, typename cplx<R>::t* Y, int64_t ld,
                           int ncols, int r0, int r1, int k0, int k1, const int32_t* row_lo, hipStream_t st) {
@@ -1089,10 +1109,16 @@ static void launch_gemm_x(const DeviceDecomp& d, const typename cplx<R>::t* F, t
     case 2: launch_gemm_x_wc<R, 2>(d, F, Y, ld, ncols, r0, r1, k0, k1, row_lo, st); break;
     case 3: launch_gemm_x_wc<R, sizeof(R) == 4 ? 3 : 2>(d, F, Y, ld, ncols, r0, r1, k0, k1, row_lo, st); break;
     case 4: launch_gemm_x_wc<R, sizeof(R) == 4 ? 4 : 2>(d, F, Y, ld, ncols, r0, r1, k0, k1, row_lo, st); break;
-    default: launch_gemm_x_wc<R, sizeof(R) == 4 ? 5 : 2>(d, F, Y, ld, ncols, r0, r1, k0, k1, row_lo, st); break;
+    default:
+      // full tiles: every row and K range is a multiple of 64, so only the
+      // column count decides
+      if (sizeof(R) == 4 && k1 - k0 >= RB2_MIN_K && ncols % 160 == 0)
+        launch_gemm_x_wc<R, sizeof(R) == 4 ? 5 : 2, 2, true>(d, F, Y, ld, ncols, r0, r1, k0, k1, row_lo, st);
+      else
+        launch_gemm_x_wc<R, sizeof(R) == 4 ? 5 : 2>(d, F, Y, ld, ncols, r0, r1, k0, k1, row_lo, st);
+      break;
   }
 }
-
 template <class R, int WC, int AMODE>
 static void launch_leaf_x_wc(const DeviceDecomp& d, const typename cplx<R>::t* F, typename cplx<R>::t* Y,
                              int64_t ld, int ncols, int r0, const int32_t* row_lo, hipStream_t st) {

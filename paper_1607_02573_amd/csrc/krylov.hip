@@ -43,6 +43,75 @@ __global__ void __launch_bounds__(256) k_spmm(int64_t n, const int64_t* __restri
   }
 }
 
+// Wide form for many columns: one wave per row; the row's (column, value)
+// pairs are loaded once, 64 at a time (one per lane), and broadcast with
+// readlane, so the inner loop issues only the X loads of CPL column groups
+// per nonzero.  Per (row, column) the products are summed in the order of
+// the row's nonzeros, as in k_spmm.
+__device__ inline double bcast(double v, int t) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(v), t);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(v), t);
+  return __hiloint2double(hi, lo);
+}
+
+template <int CPL>
+__global__ void __launch_bounds__(256) k_spmm_w(int64_t n, const int64_t* __restrict__ row_ptr,
+                                                const int32_t* __restrict__ col, const double2* __restrict__ val,
+                                                const double2* __restrict__ X, int64_t ldx, double2* __restrict__ Y,
+                                                int64_t ldy, int ncols, const double2* __restrict__ Bs, int64_t ldb) {
+  // workgroups are dealt to the 8 XCDs round-robin: remap so that each XCD
+  // takes one contiguous eighth of the rows, whose X rows overlap in its L2
+  const int64_t G = gridDim.x;
+  const int64_t blk = (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  const int64_t r = (blk * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (r >= n) return;
+  const int64_t b = row_ptr[r], e = row_ptr[r + 1];
+  for (int c0 = 0; c0 < ncols; c0 += 64 * CPL) {
+    double2 acc[CPL];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) acc[q] = make_double2(0.0, 0.0);
+    for (int64_t kb = b; kb < e; kb += 64) {
+      const int cnt = (int)min((int64_t)64, e - kb);
+      int mycol = 0;
+      double2 myval = make_double2(0.0, 0.0);
+      if (lane < cnt) {
+        mycol = col[kb + lane];
+        myval = val[kb + lane];
+      }
+#pragma unroll 4
+      for (int t = 0; t < cnt; ++t) {
+        const int64_t cc = __builtin_amdgcn_readlane(mycol, t);
+        double2 a;
+        a.x = bcast(myval.x, t);
+        a.y = bcast(myval.y, t);
+        const double2* xr = X + cc * ldx;
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+          const int c = c0 + lane + 64 * q;
+          if (c < ncols) {
+            double2 x = xr[c];
+            acc[q].x += a.x * x.x - a.y * x.y;
+            acc[q].y += a.x * x.y + a.y * x.x;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const int c = c0 + lane + 64 * q;
+      if (c < ncols) {
+        double2 o = acc[q];
+        if (Bs) {
+          double2 bb = Bs[r * ldb + c];
+          o = make_double2(bb.x - o.x, bb.y - o.y);
+        }
+        Y[r * ldy + c] = o;
+      }
+    }
+  }
+}
+
 void launch_spmm(const DeviceMesh& m, const double2* val, const double2* X, int64_t ldx, double2* Y, int64_t ldy,
                  int ncols, const double2* Bsub, int64_t ldb, hipStream_t st) {
   int64_t n = m.n;
@@ -50,14 +119,20 @@ void launch_spmm(const DeviceMesh& m, const double2* val, const double2* X, int6
 #define MW_SPMM(T)                                                                                      \
   k_spmm<T><<<(unsigned)ceil_div(n * T, 256), 256, 0, st>>>(n, m.row_ptr, m.col, val, X, ldx, Y, ldy, \
                                                             ncols, Bsub, ldb)
+#define MW_SPMM_W(Q)                                                                                  \
+  k_spmm_w<Q><<<(unsigned)round_up(ceil_div(n * 64, 256), 8), 256, 0, st>>>(n, m.row_ptr, m.col, val, X, \
+                                                                           ldx, Y, ldy, ncols, Bsub, ldb)
   if (ncols <= 1) MW_SPMM(1);
   else if (ncols <= 2) MW_SPMM(2);
   else if (ncols <= 4) MW_SPMM(4);
   else if (ncols <= 8) MW_SPMM(8);
   else if (ncols <= 16) MW_SPMM(16);
   else if (ncols <= 32) MW_SPMM(32);
-  else MW_SPMM(64);
+  else if (ncols <= 64) MW_SPMM_W(1);
+  else if (ncols <= 128) MW_SPMM_W(2);
+  else MW_SPMM_W(3);
 #undef MW_SPMM
+#undef MW_SPMM_W
   MW_LAUNCH_CHECK();
   if (kt_enabled())
     kt_end(KF_SPMM, st, 8.0 * m.nnz * ncols,
