@@ -433,8 +433,8 @@ __global__ void __launch_bounds__(256) k_cgs_update_dots(const double2* __restri
 bool launch_cgs_update_dots(const double2* V, int64_t vstride, int kcount, const double2* h, double2* w, int64_t n,
                             int64_t ld, int ncols, const int32_t* act, double2* part, hipStream_t st) {
   dim3 g((unsigned)reduce_chunks(n), (unsigned)ceil_div(ncols, 64));
-  // the per-thread accumulators stay in registers (no spill, occupancy >= 5)
-  // only up to 8 basis vectors; beyond that the two separate sweeps are faster
+  // the per-thread dot accumulators stay in registers (occupancy 5) only up
+  // to 8 basis vectors; beyond that the two separate sweeps are faster
   if (kcount > 8) return false;
   kt_begin(KF_CGS_UPDATE, st);
   k_cgs_update_dots<8><<<g, 256, 0, st>>>(V, vstride, kcount, h, w, n, ld, ncols, act, part);
