@@ -86,6 +86,7 @@ struct Work {
 // batch), grown on demand.
 struct GmresWork {
   Work V, X, B, Z, Y, H, cs, sn, g, y, h1, h2, part, npart, vec, ints, tmp;
+  hipStream_t st = nullptr;   // the stream this driver's work runs on
   std::array<Work*, 17> all() {
     return {&V, &X, &B, &Z, &Y, &H, &cs, &sn, &g, &y, &h1, &h2, &part, &npart, &vec, &ints, &tmp};
   }
@@ -129,7 +130,7 @@ struct mw_problem {
   // workspaces of mw_solve / mw_apply_preconditioner, and of small index lists
   GmresWork ws;
   Work w_small;
-  hipStream_t stream = nullptr;   // every launch and copy of this problem
+  hipStream_t stream = nullptr;    // every launch and copy of this problem
   int live_batches = 0;
   double t_assemble = 0, t_decompose = 0, t_factor = 0;
 };
@@ -312,14 +313,14 @@ void apply_prec(mw_problem* p, GmresWork& W, const double2* V, double2* Z, int n
   int64_t n = p->T.n();
   if (p->prec == MW_C64) {
     float2* Y = (float2*)W.Y.get(c, p->dd.sum_pad * nc * 8);
-    launch_restrict<float2>(p->dd, V, ld, nc, Y, nc, p->stream);
-    lu_solve_batched<float2>(p->dd, p->F.as<float2>(), Y, nc, nc, p->stream);
-    launch_prolong<float2>(p->dd, n, Y, nc, nc, Z, ld, p->stream);
+    launch_restrict<float2>(p->dd, V, ld, nc, Y, nc, W.st);
+    lu_solve_batched<float2>(p->dd, p->F.as<float2>(), Y, nc, nc, W.st);
+    launch_prolong<float2>(p->dd, n, Y, nc, nc, Z, ld, W.st);
   } else {
     double2* Y = (double2*)W.Y.get(c, p->dd.sum_pad * nc * 16);
-    launch_restrict<double2>(p->dd, V, ld, nc, Y, nc, p->stream);
-    lu_solve_batched<double2>(p->dd, p->F.as<double2>(), Y, nc, nc, p->stream);
-    launch_prolong<double2>(p->dd, n, Y, nc, nc, Z, ld, p->stream);
+    launch_restrict<double2>(p->dd, V, ld, nc, Y, nc, W.st);
+    lu_solve_batched<double2>(p->dd, p->F.as<double2>(), Y, nc, nc, W.st);
+    launch_prolong<double2>(p->dd, n, Y, nc, nc, Z, ld, W.st);
   }
 }
 
@@ -328,8 +329,8 @@ void colnorm2(mw_problem* p, GmresWork& W, const double2* V, int64_t ld, int nc,
   int64_t n = p->T.n();
   int64_t nch = reduce_chunks(n);
   double* part = (double*)W.npart.get(p->ctx, nch * nc * 8);
-  launch_colnorm2_partial(V, n, ld, nc, part, p->stream);
-  launch_sum_chunks(part, nch, nc, out, p->stream);
+  launch_colnorm2_partial(V, n, ld, nc, part, W.st);
+  launch_sum_chunks(part, nch, nc, out, W.st);
 }
 
 // device bytes one more right-hand side column costs a GMRES(m) driver:
@@ -345,11 +346,11 @@ int64_t gmres_bytes_per_col(mw_problem* p, int m) {
 // Z = B - A X (n x nc, ld nc); squared column norms into rn2 (device) and hr2 (host)
 void true_residual(mw_problem* p, GmresWork& W, const double2* B, const double2* X, double2* Z, int nc, double* rn2,
                    std::vector<double>& hr2) {
-  launch_spmm(p->dm, p->val.as<double2>(), X, nc, Z, nc, nc, B, nc, p->stream);
+  launch_spmm(p->dm, p->val.as<double2>(), X, nc, Z, nc, nc, B, nc, W.st);
   colnorm2(p, W, Z, nc, nc, rn2);
   hr2.resize(nc);
-  MW_HIP(hipMemcpyAsync(hr2.data(), rn2, nc * 8, hipMemcpyDeviceToHost, p->stream));
-  psync(p);
+  MW_HIP(hipMemcpyAsync(hr2.data(), rn2, nc * 8, hipMemcpyDeviceToHost, W.st));
+  MW_HIP(hipStreamSynchronize(W.st));
 }
 
 // One restart cycle of GMRES(m) right-preconditioned with ORAS (Section 6),
@@ -363,7 +364,7 @@ void true_residual(mw_problem* p, GmresWork& W, const double2* B, const double2*
 void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, const mw_solve_opts& o, double* vec,
                  const std::vector<double>& rnorm, std::vector<int32_t>& hact, std::vector<int32_t>& iters) {
   mw_ctx* c = p->ctx;
-  hipStream_t st = p->stream;
+  hipStream_t st = W.st;
   const int64_t n = p->T.n();
   const int m = o.restart;
   const int64_t ld = nc;
@@ -418,7 +419,7 @@ void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, co
     launch_givens(j, m, nc, h1, h2, hn2, H, cs, sn, g, kdim, act, resid, bnorm, o.tol, st);
     hact_prev = hact;
     MW_HIP(hipMemcpyAsync(hact.data(), act, nc * 4, hipMemcpyDeviceToHost, st));
-    psync(p);
+    MW_HIP(hipStreamSynchronize(st));
     bool changed = false;
     nact = 0;
     for (int k = 0; k < nc; ++k) {
@@ -449,11 +450,10 @@ struct ChunkResult {
 
 // Pseudo-block GMRES(m) to convergence on nc columns (one memory chunk of
 // mw_solve), true residual recomputed at every restart.
-ChunkResult gmres_chunk(mw_problem* p, const double2* Bsrc, int64_t ldb_src, double2* Xdst, int64_t ldx_dst, int nc,
-                        const mw_solve_opts& o, int32_t* iters_out, double* relres_out) {
+ChunkResult gmres_chunk(mw_problem* p, GmresWork& W, const double2* Bsrc, int64_t ldb_src, double2* Xdst,
+                        int64_t ldx_dst, int nc, const mw_solve_opts& o, int32_t* iters_out, double* relres_out) {
   mw_ctx* c = p->ctx;
-  hipStream_t st = p->stream;
-  GmresWork& W = p->ws;
+  hipStream_t st = W.st;
   const int64_t n = p->T.n();
   const int64_t ld = nc;
   const int64_t vstride = n * ld;
@@ -470,7 +470,7 @@ ChunkResult gmres_chunk(mw_problem* p, const double2* Bsrc, int64_t ldb_src, dou
   std::vector<double> hb(nc), hr, hb2(nc);
   colnorm2(p, W, B, ld, nc, rn2);
   MW_HIP(hipMemcpyAsync(hb2.data(), rn2, nc * 8, hipMemcpyDeviceToHost, st));
-  psync(p);
+  MW_HIP(hipStreamSynchronize(st));
   for (int k = 0; k < nc; ++k) hb[k] = std::sqrt(hb2[k]);
   MW_HIP(hipMemcpyAsync(bnorm, hb.data(), nc * 8, hipMemcpyHostToDevice, st));
 
@@ -494,7 +494,7 @@ ChunkResult gmres_chunk(mw_problem* p, const double2* Bsrc, int64_t ldb_src, dou
     gmres_cycle(p, W, X, Z, nc, o, vec, rnorm, hact, iters);
   }
   launch_copy_cols(X, ld, Xdst, ldx_dst, n, nc, st);
-  psync(p);
+  MW_HIP(hipStreamSynchronize(st));
   for (int k = 0; k < nc; ++k) {
     if (iters_out) iters_out[k] = iters[k];
     if (relres_out) relres_out[k] = relres[k];
@@ -766,6 +766,7 @@ mw_status mw_apply_preconditioner(mw_problem* p, int32_t nrhs, const void* V, vo
     MW_CHECK(nrhs >= 0 && (nrhs == 0 || (V && Z)), MW_EINVAL, "NULL argument");
     if (nrhs == 0) return;
     DeviceGuard dg(p->ctx->device);
+    p->ws.st = p->stream;
     apply_prec(p, p->ws, (const double2*)V, (double2*)Z, nrhs, nrhs);
     psync(p);
   });
@@ -803,7 +804,9 @@ mw_status mw_solve(mw_problem* p, int32_t nrhs, const void* B, void* X, const mw
       int nc = std::min(cols, nrhs - c0);
       std::vector<int32_t> it(nc);
       std::vector<double> rr(nc);
-      ChunkResult r = gmres_chunk(p, (const double2*)B + c0, nrhs, (double2*)X + c0, nrhs, nc, op, it.data(), rr.data());
+      p->ws.st = p->stream;
+      ChunkResult r =
+          gmres_chunk(p, p->ws, (const double2*)B + c0, nrhs, (double2*)X + c0, nrhs, nc, op, it.data(), rr.data());
       chunks++;
       numeric |= r.numeric;
       for (int k = 0; k < nc; ++k) {
@@ -1062,6 +1065,7 @@ mw_status mw_batch_join(mw_batch* b, int64_t tag, int32_t ncols, const void* B) 
     MW_HIP(hipMemcpyAsync(b->idx.p, sl.data(), ncols * 4, hipMemcpyHostToDevice, st));
     launch_scatter_cols((const double2*)B, ncols, b->idx.as<int32_t>(), b->Bs.as<double2>(), b->max_cols, n, ncols, st);
     launch_scatter_cols(nullptr, 0, b->idx.as<int32_t>(), b->Xs.as<double2>(), b->max_cols, n, ncols, st);
+    b->W.st = p->stream;
     double* nb = (double*)b->W.vec.get(p->ctx, (int64_t)4 * b->max_cols * 8);
     colnorm2(p, b->W, (const double2*)B, ncols, ncols, nb);
     std::vector<double> h(ncols);
@@ -1109,6 +1113,7 @@ mw_status mw_batch_cycle(mw_batch* b, int32_t* n_active, int32_t* n_finished) {
     hipStream_t st = p->stream;
     const int64_t n = p->T.n();
     GmresWork& W = b->W;
+    W.st = st;
     double2* X = (double2*)W.X.get(c, n * na * 16);
     double2* Bc = (double2*)W.B.get(c, n * na * 16);
     double2* Z = (double2*)W.Z.get(c, n * na * 16);

@@ -2,7 +2,9 @@
 // stream around every launch of a family, plus the algorithmic flops and
 // HBM bytes of each launch (counted from the true subdomain sizes, not the
 // padded ones).  Off by default; enabled through mw_timer_enable.
+#include <map>
 #include <mutex>
+#include <utility>
 
 #include "kernels.hpp"
 
@@ -20,7 +22,7 @@ struct Timer {
   bool on = false;
   Fam fam[KF_COUNT];
   std::vector<hipEvent_t> pool;
-  hipEvent_t pending[KF_COUNT] = {};
+  std::map<std::pair<int, hipStream_t>, hipEvent_t> pending;   // open launch per (family, stream)
   std::mutex mu;
   hipEvent_t get() {
     if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
@@ -38,7 +40,7 @@ void kt_begin(int f, hipStream_t st) {
   std::lock_guard<std::mutex> g(g_t.mu);
   hipEvent_t e = g_t.get();
   MW_HIP(hipEventRecord(e, st));
-  g_t.pending[f] = e;
+  g_t.pending[{f, st}] = e;
 }
 
 void kt_end(int f, hipStream_t st, double flops, double bytes) {
@@ -46,7 +48,13 @@ void kt_end(int f, hipStream_t st, double flops, double bytes) {
   std::lock_guard<std::mutex> g(g_t.mu);
   hipEvent_t e = g_t.get();
   MW_HIP(hipEventRecord(e, st));
-  g_t.fam[f].ev.push_back({g_t.pending[f], e});
+  auto it = g_t.pending.find({f, st});
+  if (it == g_t.pending.end()) {   // kt_begin was not called while the timer was on
+    g_t.pool.push_back(e);
+    return;
+  }
+  g_t.fam[f].ev.push_back({it->second, e});
+  g_t.pending.erase(it);
   g_t.fam[f].flops += flops;
   g_t.fam[f].bytes += bytes;
   g_t.fam[f].launches++;
