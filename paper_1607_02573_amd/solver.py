@@ -170,7 +170,13 @@ class Problem:
               raise_noconv: bool = True):
         _dev_tensor(Bm, torch.complex128, self.ctx.device, "B")
         nrhs = Bm.shape[1]
-        X = x0.clone() if x0 is not None else torch.empty_like(Bm)
+        if x0 is not None:
+            if (not isinstance(x0, torch.Tensor) or x0.dtype != torch.complex128 or x0.device != self.ctx.device
+                    or x0.shape != Bm.shape):
+                raise ValueError(f"x0 must be a complex128 tensor of shape {tuple(Bm.shape)} on {self.ctx.device}")
+            X = x0.clone(memory_format=torch.contiguous_format)
+        else:
+            X = torch.empty_like(Bm)
         it = np.zeros(nrhs, dtype=np.int32)
         rr = np.zeros(nrhs)
         info = B.mw_solve_info(iters=ptr(it) if nrhs else None, relres=ptr(rr) if nrhs else None)

@@ -1,0 +1,79 @@
+"""Degenerate and edge cases of the solve path on the GPU (through the C ABI):
+empty right-hand-side sets, zero columns, an exact initial guess, a single
+subdomain (the preconditioner is then A^-1: one GMRES iteration), and inputs
+the library must refuse."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import mw_inputs as mi
+from oracle import fem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cube():
+    from paper_1607_02573_amd import solver
+    ctx = solver.Context(0)
+    w = mi.configs.cube8()
+    P = solver.problem_from_workload(ctx, w)
+    yield ctx, w, P
+    P.close()
+
+
+def test_empty_and_zero_columns(cube):
+    ctx, w, P = cube
+    P.factor(w.part, w.n_sub, 1, "c128")
+    X, info = P.solve(torch.empty((P.n, 0), dtype=torch.complex128, device="cuda"))
+    assert X.shape == (P.n, 0) and info.max_iters == 0
+    B = P.rhs_dipoles(w.dipoles)
+    B[:, 1] = 0
+    X, info = P.solve(B.contiguous(), tol=1e-10)
+    assert float(X[:, 1].abs().max()) == 0.0 and info.iters[1] == 0 and info.relres[1] == 0.0
+    X0, _ = P.solve(B[:, 0:1].contiguous(), tol=1e-10)
+    assert torch.equal(X0[:, 0], X[:, 0])
+
+
+def test_exact_initial_guess_takes_no_iteration(cube):
+    ctx, w, P = cube
+    P.factor(w.part, w.n_sub, 1, "c128")
+    fp = fem.build(w.mesh, w.eps, w.k0, w.beta_imp, w.ports)
+    Bo = fem.rhs_dipoles(fp, w.dipoles)
+    U = spla.splu(fp.A.tocsc()).solve(Bo)
+    X, info = P.solve(torch.from_numpy(Bo).cuda(), tol=1e-10, x0=torch.from_numpy(U).cuda())
+    assert (info.iters == 0).all() and (info.relres <= 1e-10).all()
+    assert np.abs(X.cpu().numpy() - U).max() <= 1e-12 * np.abs(U).max()
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_single_subdomain_is_a_direct_solve(cube, prec):
+    """N_S = 1: B_1 = A and D_1 = I, so M^-1 = A^-1 up to the factor
+    precision; FP64 factors converge in one iteration."""
+    ctx, w, P = cube
+    P.factor(np.zeros(w.mesh.nt, dtype=np.int32), 1, 1, prec)
+    X, info = P.solve(P.rhs_dipoles(w.dipoles), tol=1e-10)
+    if prec == "c128":
+        assert (info.iters == 1).all(), info.iters
+    else:
+        assert (info.iters <= 3).all(), info.iters
+    assert (info.relres <= 1e-10).all()
+
+
+def test_refused_inputs(cube):
+    from paper_1607_02573_amd import binding
+    ctx, w, P = cube
+    with pytest.raises(binding.MwError) as e:
+        P.rhs_dipoles(np.array([[2.0, 0.5, 0.5]]))        # outside the unit cube
+    assert e.value.code == binding.MW_EINVAL
+    with pytest.raises(binding.MwError) as e:
+        P.rhs_ports([0])                                    # the cube has no ports
+    assert e.value.code == binding.MW_EINVAL
+    P.factor(w.part, w.n_sub, 1, "c128")
+    with pytest.raises(binding.MwError) as e:
+        P.solve(P.rhs_dipoles(w.dipoles), tol=-1.0)         # invalid options
+    assert e.value.code == binding.MW_EINVAL
+    with pytest.raises(ValueError):
+        P.solve(P.rhs_dipoles(w.dipoles).to(torch.complex64))   # wrong dtype never reaches the library
