@@ -75,13 +75,21 @@ void build_decomposition(const Topology& T, const int32_t* part, int32_t nsub, i
   // number of subdomains whose T_j^0 holds each node (denominator of (chi))
   std::vector<float> cnt(nv, 0.f);
   parallel_for(nv, [&](int64_t v) {
-    int32_t seen[64];
+    // distinct parts among the tetrahedra around v (at most their number)
+    int32_t small[64];
+    std::vector<int32_t> big;
+    const int64_t deg = vt_ptr[v + 1] - vt_ptr[v];
+    int32_t* seen = small;
+    if (deg > 64) {
+      big.resize(deg);
+      seen = big.data();
+    }
     int ns = 0;
     for (int64_t q = vt_ptr[v]; q < vt_ptr[v + 1]; ++q) {
       int32_t p = part[vt[q]];
       bool dup = false;
       for (int k = 0; k < ns; ++k) dup |= seen[k] == p;
-      if (!dup && ns < 64) seen[ns++] = p;
+      if (!dup) seen[ns++] = p;
     }
     cnt[v] = (float)ns;
   });
