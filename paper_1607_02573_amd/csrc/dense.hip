@@ -283,28 +283,32 @@ __device__ __attribute__((always_inline)) inline void gemm_wide(const typename c
       }
 }
 
-// Complex FP32 product by the 3M (Gauss) form: with P1 = Ar Br, P2 = Ai Bi and
+// Complex product by the 3M (Gauss) form: with P1 = Ar Br, P2 = Ai Bi and
 // P3 = (Ar + Ai)(Br + Bi) (three real 16x16x4 MFMA products, K = 4 complex per
 // instruction), Re = P1 - P2 and Im = P3 - P1 - P2: 3/4 of the real MFMA work of
-// the 4M form.  Used for the FP32 preconditioner updates only (its rounding is
-// slightly larger in the imaginary part; the FP64 path keeps 4M).
+// the 4M form.  Its rounding error in the imaginary part is bounded by the
+// working precision times (|Ar| + |Ai|)(|Br| + |Bi|) instead of |A||B|.  Used
+// for the triangular-solve updates (FP32 and FP64) and the FP32 LU trailing
+// update; the LU panels keep 4M.
 // Tile: 32*RB rows x 32*WC columns, waves 2 x 2 (16*RB rows x 16*WC columns
 // each), C -= A B, double-buffered LDS stages of G3K complex.  RB = 2 halves
 // the B reads per product at the cost of occupancy (long K pays for it).
 // FULL: M, N, K are known to be multiples of the tile (no bounds tests).
 constexpr int G3K = 8;
-template <int WC, int RB = 1, bool FULL = false>
-__device__ __attribute__((always_inline)) inline void gemm3m(const float2* __restrict__ A, int64_t lda,
-                                                             const float2* B, int64_t ldb, float2* Cm,
-                                                             int64_t ldc, int M, int N, int K) {
-  using acc_t = typename Mf<float>::acc;
+template <class R, int WC, int RB = 1, bool FULL = false>
+__device__ __attribute__((always_inline)) inline void gemm3m(const typename cplx<R>::t* __restrict__ A, int64_t lda,
+                                                             const typename cplx<R>::t* B, int64_t ldb,
+                                                             typename cplx<R>::t* Cm, int64_t ldc, int M, int N,
+                                                             int K) {
+  using C = typename cplx<R>::t;
+  using acc_t = typename Mf<R>::acc;
   constexpr int TM = 32 * RB, TN = 32 * WC;
   constexpr int AREG = TM * G3K / 256;
   constexpr int BREG = (G3K * TN + 255) / 256;
-  // B rows padded by 16 floats: the four K rows a wave reads at once start in
-  // different halves of the 32 LDS banks
-  __shared__ float As[2][3][TM][G3K + 1];
-  __shared__ float Bs[2][3][G3K][TN + 16];
+  // B rows padded by 16 elements: the four K rows a wave reads at once start
+  // in different halves of the LDS banks
+  __shared__ R As[2][3][TM][G3K + 1];
+  __shared__ R Bs[2][3][G3K][TN + 16];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -316,13 +320,15 @@ __device__ __attribute__((always_inline)) inline void gemm3m(const float2* __res
     for (int y = 0; y < WC; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) { p1[x][y][r] = 0; p2[x][y][r] = 0; p3[x][y][r] = 0; }
-  float2 ra[AREG], rb[BREG];
+  C ra[AREG], rb[BREG];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < AREG; ++e) {
       int idx = tid + e * 256;
       int r = idx / G3K, kc = idx % G3K;
-      float2 v = make_float2(0.f, 0.f);
+      C v;
+      v.x = 0;
+      v.y = 0;
       if (FULL || (r < M && k0 + kc < K)) v = A[(int64_t)r * lda + k0 + kc];
       ra[e] = v;
     }
@@ -330,7 +336,9 @@ __device__ __attribute__((always_inline)) inline void gemm3m(const float2* __res
     for (int e = 0; e < BREG; ++e) {
       int idx = tid + e * 256;
       int r = idx / TN, c = idx % TN;
-      float2 v = make_float2(0.f, 0.f);
+      C v;
+      v.x = 0;
+      v.y = 0;
       if (idx < G3K * TN && (FULL || (k0 + r < K && c < N))) v = B[(int64_t)(k0 + r) * ldb + c];
       rb[e] = v;
     }
@@ -364,7 +372,7 @@ __device__ __attribute__((always_inline)) inline void gemm3m(const float2* __res
     if (more) fetch(k0 + G3K);
 #pragma unroll
     for (int kk = 0; kk < G3K; kk += 4) {
-      float a1[RB], a2[RB], a3[RB];
+      R a1[RB], a2[RB], a3[RB];
 #pragma unroll
       for (int x = 0; x < RB; ++x) {
         const int row = wm * 16 * RB + x * 16 + li;
@@ -375,12 +383,12 @@ __device__ __attribute__((always_inline)) inline void gemm3m(const float2* __res
 #pragma unroll
       for (int y = 0; y < WC; ++y) {
         const int col = wn * 16 * WC + y * 16 + li;
-        const float b1 = Bs[buf][0][kk + kq][col], b2 = Bs[buf][1][kk + kq][col], b3 = Bs[buf][2][kk + kq][col];
+        const R b1 = Bs[buf][0][kk + kq][col], b2 = Bs[buf][1][kk + kq][col], b3 = Bs[buf][2][kk + kq][col];
 #pragma unroll
         for (int x = 0; x < RB; ++x) {
-          p1[x][y] = Mf<float>::mfma(a1[x], b1, p1[x][y]);
-          p2[x][y] = Mf<float>::mfma(a2[x], b2, p2[x][y]);
-          p3[x][y] = Mf<float>::mfma(a3[x], b3, p3[x][y]);
+          p1[x][y] = Mf<R>::mfma(a1[x], b1, p1[x][y]);
+          p2[x][y] = Mf<R>::mfma(a2[x], b2, p2[x][y]);
+          p3[x][y] = Mf<R>::mfma(a3[x], b3, p3[x][y]);
         }
       }
     }
@@ -394,11 +402,11 @@ __device__ __attribute__((always_inline)) inline void gemm3m(const float2* __res
     for (int y = 0; y < WC; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int gr = wm * 16 * RB + x * 16 + Mf<float>::out_row(lane, r);
+        int gr = wm * 16 * RB + x * 16 + Mf<R>::out_row(lane, r);
         int gc = wn * 16 * WC + y * 16 + li;
         if (FULL || (gr < M && gc < N)) {
-          float2* p = Cm + (int64_t)gr * ldc + gc;
-          float2 o = *p;
+          C* p = Cm + (int64_t)gr * ldc + gc;
+          C o = *p;
           o.x -= p1[x][y][r] - p2[x][y][r];
           o.y -= p3[x][y][r] - p1[x][y][r] - p2[x][y][r];
           *p = o;
@@ -415,7 +423,7 @@ template <class R, int RB = 1> struct XTile { static constexpr int TM = sizeof(R
 // the linear id is remapped so that the tiles of one subdomain run on one XCD
 // (workgroups are dealt to the 8 XCDs round-robin) and share its L2.
 template <class R, int WC, int RB, bool FULL = false>
-__global__ void __launch_bounds__(256, RB) k_gemm_x(const typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
+__global__ void __launch_bounds__(256, (sizeof(R) == 8 && WC >= 2) ? 2 : RB) k_gemm_x(const typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
                                                 const int32_t* __restrict__ n_pad,
                                                 const int64_t* __restrict__ loc_off, typename cplx<R>::t* Y,
                                                 int64_t ld, int ncols, int r0, int r1, int k0, int k1,
@@ -440,12 +448,9 @@ __global__ void __launch_bounds__(256, RB) k_gemm_x(const typename cplx<R>::t* F
   C* Yi = Y + loc_off[i] * ld;
   const int row = r0 + tm * TM;
   if (row_lo && row + TM <= row_lo[i]) return;   // rows discarded by the weights
-  if constexpr (sizeof(R) == 4)
-    gemm3m<WC, RB, FULL>(Fi + (int64_t)row * np + k0, np, Yi + (int64_t)k0 * ld + tn * TN, ld,
-               Yi + (int64_t)row * ld + tn * TN, ld, M, N, K);
-  else
-    gemm_wide<R, WC>(Fi + (int64_t)row * np + k0, np, Yi + (int64_t)k0 * ld + tn * TN, ld,
-                     Yi + (int64_t)row * ld + tn * TN, ld, M, N, K);
+  // FP32: 32*RB-row tiles; FP64: 64-row tiles (two row blocks per wave)
+  gemm3m<R, WC, sizeof(R) == 4 ? RB : 2, FULL>(Fi + (int64_t)row * np + k0, np, Yi + (int64_t)k0 * ld + tn * TN, ld,
+                                               Yi + (int64_t)row * ld + tn * TN, ld, M, N, K);
 }
 
 // Leaf of the blocked triangular solves: Y[r0:r0+64] = T^-1 Y[r0:r0+64] with the
@@ -474,13 +479,13 @@ __global__ void __launch_bounds__(256) k_leaf_x(const typename cplx<R>::t* F, co
 // LU update with wide tiles:
 //   F[r0:min(r1,np), c0:min(c1,np)] -= F[r0:min(r1,np), k0:k1] F[k0:k1, c0:min(c1,np)]
 // on every subdomain; 1-D XCD-aware grid of nsub * tiles_m * tiles_n.  G3
-// selects the three-product complex form (FP32; 64-row tiles of two row blocks
-// per wave).
+// selects the three-product complex form (64-row tiles of two row blocks per
+// wave).
 template <class R, int WC, bool G3>
 struct LuwTile { static constexpr int TM = 64; };
 
 template <class R, int WC, bool G3>
-__global__ void __launch_bounds__(256, (G3 && sizeof(R) == 4) ? 2 : 1) k_gemm_luw(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
+__global__ void __launch_bounds__(256, G3 ? 2 : 1) k_gemm_luw(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
                                                   const int32_t* __restrict__ n_pad, int r0, int r1, int k0, int k1,
                                                   int c0, int c1, int tiles_m, int tiles_n, int nsub) {
   using C = typename cplx<R>::t;
@@ -498,8 +503,8 @@ __global__ void __launch_bounds__(256, (G3 && sizeof(R) == 4) ? 2 : 1) k_gemm_lu
   if (M <= 0 || N <= 0 || k1 > np) return;
   C* Fi = F + fac_off[i];
   const int row = r0 + tm * TM, col = c0 + tn * 32 * WC;
-  if constexpr (G3 && sizeof(R) == 4)
-    gemm3m<WC, 2>(Fi + (int64_t)row * np + k0, np, Fi + (int64_t)k0 * np + col, np, Fi + (int64_t)row * np + col,
+  if constexpr (G3)
+    gemm3m<R, WC, 2>(Fi + (int64_t)row * np + k0, np, Fi + (int64_t)k0 * np + col, np, Fi + (int64_t)row * np + col,
                   np, M, min(N, 32 * WC), k1 - k0);
   else
     gemm_wide<R, WC>(Fi + (int64_t)row * np + k0, np, Fi + (int64_t)k0 * np + col, np,
