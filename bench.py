@@ -91,6 +91,26 @@ def run_steps(P, w, eps_dev, prec, nsteps, tol, restart, maxit, tx, rx):
     return stats, last
 
 
+def family_table(fam: dict, mfma_peak_tflops: float, wall_s: float):
+    """Per kernel family: time, rates, the roofline that bounds it and the
+    fraction of it reached.  The roofline time of a family is the larger of
+    its algorithmic flops at the compute peak (MFMA at `mfma_peak_tflops` for
+    the dense factor/solve families, FP64 vector for the Krylov kernels) and
+    its algorithmic bytes at 8 TB/s.  Also the whole run's roofline time (the
+    sum over families) over its wall time."""
+    out, roof_s = {}, 0.0
+    for k, v in fam.items():
+        s = max(v["ms"], 1e-9) * 1e-3
+        dense = k in MFMA_FAMILIES or k in ("trsm_leaf", "lu_panel", "lu_other")
+        t_flop = v["flops"] / ((mfma_peak_tflops if dense else PEAK["fp64_TFLOPs"]) * 1e12)
+        t_byte = v["bytes"] / (PEAK["hbm_GBs"] * 1e9)
+        t_roof, bound = (t_flop, "mfma" if dense else "alu") if t_flop >= t_byte else (t_byte, "hbm")
+        roof_s += t_roof
+        out[k] = {"ms": round(v["ms"], 2), "launches": v["launches"], "TFLOPs": round(v["flops"] / s / 1e12, 2),
+                  "GBs": round(v["bytes"] / s / 1e9, 1), "bound": bound, "frac": round(t_roof / s, 3)}
+    return out, {"roofline_s": roof_s, "wall_s": wall_s, "frac": roof_s / wall_s if wall_s > 0 else None}
+
+
 def cpu_baseline(w, iters_mean: float, nrhs: int, budget_s: float):
     """The oracle (FP64 numpy/scipy, sparse direct subdomain solves), single
     thread, on a bounded sample of the same workload, scaled to RHS/s:
@@ -283,9 +303,7 @@ def main():
     roof["kernel"] = dom
     roof["launches"] = d["launches"]
     roof["avg_launch_us"] = d["ms"] * 1e3 / d["launches"]
-    kernel_table = {k: {"ms": round(v["ms"], 2), "launches": v["launches"],
-                        "TFLOPs": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 2),
-                        "GBs": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for k, v in famt.items()}
+    kernel_table, solve_roof = family_table(famt, PEAK["fp32_TFLOPs"], T)
 
     # ---------------- FP64 path, same workload
     fp64 = None
@@ -316,10 +334,8 @@ def main():
                 "chunks": st64[-1]["chunks"], "solve_rhs_per_s": sum(len(s["relres"]) for s in st64)
                 / sum(s["t_solve"] for s in st64), "setup_s": st64[-1]["t_setup"],
                 "mixed_vs_fp64_field_relL2_max": dx, "mixed_vs_fp64_S_rel_max": dS,
-                "kernels": {k: {"ms": round(v["ms"], 2), "launches": v["launches"],
-                                "TFLOPs": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 2),
-                                "GBs": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)}
-                            for k, v in fam64.items() if v["launches"] > 0}}
+                "kernels": family_table({k: v for k, v in fam64.items() if v["launches"] > 0},
+                                        PEAK["fp64_TFLOPs"], T64)[0]}
         log(f"[bench] FP64: {T64 / args.fp64_steps:.2f} s/step, {fp64['value']:.2f} RHS/s; mixed-vs-fp64 field {dx:.2e}")
 
     out = {
@@ -347,6 +363,7 @@ def main():
         "speedup_mixed_vs_fp64": (value / fp64["value"]) if fp64 else None,
         "roofline": roof,
         "kernels": kernel_table,
+        "whole_run_roofline": solve_roof,
     }
     if not args.no_cpu:
         log("[bench] cpu_baseline (oracle sample)")
