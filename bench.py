@@ -226,7 +226,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=4.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build solves all subdomains "
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this library solves all subdomains "
               "of a problem on a single MI355X and has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
