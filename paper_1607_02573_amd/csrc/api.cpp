@@ -85,10 +85,11 @@ struct Work {
 // Device workspaces of one pseudo-block GMRES driver (mw_solve, or one
 // batch), grown on demand.
 struct GmresWork {
-  Work V, X, B, Z, Y, H, cs, sn, g, y, h1, h2, part, npart, vec, ints, tmp;
+  Work V, X, B, Z, Y, H, Hr, cs, sn, g, y, h1, h2, hp, cf, nu, ee, part, npart, vec, ints, tmp;
   hipStream_t st = nullptr;   // the stream this driver's work runs on
-  std::array<Work*, 17> all() {
-    return {&V, &X, &B, &Z, &Y, &H, &cs, &sn, &g, &y, &h1, &h2, &part, &npart, &vec, &ints, &tmp};
+  std::array<Work*, 22> all() {
+    return {&V, &X, &B, &Z, &Y, &H, &Hr, &cs, &sn, &g, &y, &h1, &h2, &hp, &cf, &nu, &ee, &part, &npart, &vec, &ints,
+            &tmp};
   }
   void release() {
     for (Work* w : all()) w->b.release();
@@ -337,9 +338,11 @@ void colnorm2(mw_problem* p, GmresWork& W, const double2* V, int64_t ld, int nc,
 // basis (m+1), X, B, Z, update, local vectors, reduction partials
 int64_t gmres_bytes_per_col(mw_problem* p, int m) {
   int64_t esz = p->prec == MW_C64 ? 8 : 16;
-  int64_t big = (int64_t)(m + 5) * p->T.n() * 16 + p->dd.sum_pad * esz + reduce_chunks(p->T.n()) * (m + 2) * 16;
-  // Hessenberg, rotations, g, y, h1, h2, norms, flags
-  int64_t small = (int64_t)(m + 1) * m * 16 + (int64_t)m * 24 + 4 * (int64_t)(m + 1) * 16 + 4 * 8 + 2 * 4;
+  int64_t big = (int64_t)(m + 5) * p->T.n() * 16 + p->dd.sum_pad * esz + reduce_chunks(p->T.n()) * (2 * m + 3) * 16;
+  // Hessenberg (raw and rotated), rotations, g, y, dot sums, provisional
+  // column, coefficients, norms, flags
+  int64_t small = 2 * (int64_t)(m + 1) * m * 16 + (int64_t)m * 24 + 5 * (int64_t)(m + 1) * 16 + 2 * (int64_t)m * 16 +
+                  6 * 8 + 2 * 4;
   return big + small + 256;
 }
 
@@ -357,7 +360,13 @@ void true_residual(mw_problem* p, GmresWork& W, const double2* B, const double2*
 // pseudo-block over the nc columns of X (ld nc).  On entry Z holds the true
 // residual r = b - A x and vec = [||b|| | ||r||^2 | scratch x2] (device, nc
 // each), rnorm = ||r|| on the host.  Columns with hact[k] = 0 are carried
-// along untouched.  A column stops when its Givens residual estimate reaches
+// along untouched.  The Arnoldi basis is orthogonalised by classical
+// Gram-Schmidt applied twice, with the second pass of each new vector
+// delayed to the next step so that one sweep of dot products and one sweep of
+// updates over the basis serve both passes (k_dgs_step, k_dgs_update): step
+// j applies the operator to the once-orthogonalised candidate, finishes its
+// second pass and column j-1 of the Hessenberg matrix, then projects the
+// operator image.  A column stops when its Givens residual estimate reaches
 // tol (relative to ||b||) or its iteration count reaches maxit; the cycle
 // ends when every column has stopped or after m steps, then x += M^-1 V y.
 // iters[k] counts the Arnoldi steps of column k.
@@ -370,23 +379,31 @@ void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, co
   const int64_t ld = nc;
   const int64_t vstride = n * ld;
   double2* V = (double2*)W.V.get(c, (int64_t)(m + 1) * vstride * 16);
+  double2* T = (double2*)W.tmp.get(c, vstride * 16);
   double2* H = (double2*)W.H.get(c, (int64_t)(m + 1) * m * nc * 16);
+  double2* Hraw = (double2*)W.Hr.get(c, (int64_t)(m + 1) * m * nc * 16);
   double* cs = (double*)W.cs.get(c, (int64_t)m * nc * 8);
   double2* sn = (double2*)W.sn.get(c, (int64_t)m * nc * 16);
   double2* g = (double2*)W.g.get(c, (int64_t)(m + 1) * nc * 16);
   double2* y = (double2*)W.y.get(c, (int64_t)(m + 1) * nc * 16);
-  double2* h1 = (double2*)W.h1.get(c, (int64_t)(m + 1) * nc * 16);
-  double2* h2 = (double2*)W.h2.get(c, (int64_t)(m + 1) * nc * 16);
-  int64_t nch = reduce_chunks(n);
-  double2* part = (double2*)W.part.get(c, nch * (m + 1) * nc * 16);
+  double2* P1 = (double2*)W.h1.get(c, (int64_t)(m + 1) * nc * 16);
+  double2* P2 = (double2*)W.h2.get(c, (int64_t)(m + 1) * nc * 16);
+  double2* hprov = (double2*)W.hp.get(c, (int64_t)(m + 1) * nc * 16);
+  double2* coef = (double2*)W.cf.get(c, (int64_t)2 * m * nc * 16 + 16);
+  double* nu = (double*)W.nu.get(c, (int64_t)nc * 8);
+  double2* ee = (double2*)W.ee.get(c, (int64_t)nc * 16);
+  const int64_t nch = reduce_chunks(n);
+  double2* part1 = (double2*)W.part.get(c, nch * 2 * (m + 1) * nc * 16);
+  double2* part2 = part1 + nch * (m + 1) * nc;
   double* npart = (double*)W.npart.get(c, nch * nc * 8);
   double* bnorm = vec;        // ||b||
   double* rn2 = vec + nc;     // ||r||^2
-  double* hn2 = vec + 2 * nc; // ||w||^2
+  double* hn2 = vec + 2 * nc; // ||u||^2 of the current candidate
   double* resid = vec + 3 * nc;
-  int32_t* ivec = (int32_t*)W.ints.get(c, (int64_t)2 * nc * 4);
+  int32_t* ivec = (int32_t*)W.ints.get(c, (int64_t)3 * nc * 4);
   int32_t* act = ivec;
   int32_t* kdim = ivec + nc;
+  int32_t* done = ivec + 2 * nc;
   std::vector<double2> g0((size_t)nc);
   int nact = 0;
   for (int k = 0; k < nc; ++k) {
@@ -397,43 +414,63 @@ void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, co
   MW_HIP(hipMemcpyAsync(act, hact.data(), nc * 4, hipMemcpyHostToDevice, st));
   launch_zero_bytes(kdim, nc * 4, st);
   launch_zero(g, (int64_t)(m + 1) * nc, st);
+  launch_zero(Hraw, (int64_t)(m + 1) * m * nc, st);
   MW_HIP(hipMemcpyAsync(g, g0.data(), nc * 16, hipMemcpyHostToDevice, st));
   launch_start_cycle(Z, V, n, ld, nc, rn2, act, st);
-  std::vector<int32_t> hact_prev(nc);
-  for (int j = 0; j < m; ++j) {
+  std::vector<int32_t> hact_prev(nc), hdone(nc);
+  // The step after the one whose trial estimates say every active column is
+  // done only finishes the last column (no operator application); if a
+  // column then turns out to need more, the step is repeated with the
+  // operator, the column already finished.
+  bool finish_only = false;
+  for (int j = 0; j <= m; ++j) {
     double2* Vj = V + (int64_t)j * vstride;
-    double2* Wj = V + (int64_t)(j + 1) * vstride;
-    apply_prec(p, W, Vj, Z, nc, ld);
-    launch_spmm(p->dm, p->val.as<double2>(), Z, ld, Wj, ld, nc, nullptr, 0, st);
-    // classical Gram-Schmidt, twice
-    launch_dots_partial(V, vstride, j + 1, Wj, n, ld, nc, act, part, st);
-    launch_sum_chunks_c(part, nch, (int64_t)(j + 1) * nc, h1, st);
-    if (!launch_cgs_update_dots(V, vstride, j + 1, h1, Wj, n, ld, nc, act, part, st)) {
-      launch_cgs_update(V, vstride, j + 1, h1, Wj, n, ld, nc, act, nullptr, st);
-      launch_dots_partial(V, vstride, j + 1, Wj, n, ld, nc, act, part, st);
+    bool more = j < m && !finish_only;   // step m only finishes column m-1
+    for (int pass = 0; pass < 2; ++pass) {
+      if (more) {
+        apply_prec(p, W, Vj, Z, nc, ld);
+        launch_spmm(p->dm, p->val.as<double2>(), Z, ld, T, ld, nc, nullptr, 0, st);
+      }
+      launch_dots_partial(V, vstride, j + 1, Vj, more ? T : nullptr, n, ld, nc, act, part1, part2, st);
+      launch_sum_chunks_c(part1, nch, (int64_t)(j + 1) * nc, P1, st);
+      if (more) launch_sum_chunks_c(part2, nch, (int64_t)(j + 1) * nc, P2, st);
+      launch_dgs_step(j, m, pass == 0, nc, P1, more ? P2 : nullptr, hn2, Hraw, H, cs, sn, g, hprov, coef, nu, ee,
+                      kdim, act, resid, bnorm, o.tol, st);
+      if (j > 0 && pass == 0) {
+        // column j-1 is final: one Arnoldi step for every column active before
+        hact_prev = hact;
+        MW_HIP(hipMemcpyAsync(hact.data(), act, nc * 4, hipMemcpyDeviceToHost, st));
+        MW_HIP(hipStreamSynchronize(st));
+        bool changed = false;
+        nact = 0;
+        for (int k = 0; k < nc; ++k) {
+          if (hact_prev[k]) iters[k]++;
+          if (hact[k] && iters[k] >= o.maxit) { hact[k] = 0; changed = true; }
+          nact += hact[k];
+        }
+        if (changed) MW_HIP(hipMemcpyAsync(act, hact.data(), nc * 4, hipMemcpyHostToDevice, st));
+      }
+      if (more || nact == 0 || j == m) break;
+      more = true;   // a column continues although its trial estimate said done
     }
-    launch_sum_chunks_c(part, nch, (int64_t)(j + 1) * nc, h2, st);
-    launch_cgs_update(V, vstride, j + 1, h2, Wj, n, ld, nc, act, npart, st);
+    if (nact == 0 || j == m) break;
+    launch_dgs_update(V, vstride, j, coef, nu, ee, T, n, ld, nc, act, npart, st);
     launch_sum_chunks(npart, nch, nc, hn2, st);
-    launch_scale_cols(Wj, n, ld, nc, hn2, act, st);
-    launch_givens(j, m, nc, h1, h2, hn2, H, cs, sn, g, kdim, act, resid, bnorm, o.tol, st);
-    hact_prev = hact;
-    MW_HIP(hipMemcpyAsync(hact.data(), act, nc * 4, hipMemcpyDeviceToHost, st));
-    MW_HIP(hipStreamSynchronize(st));
-    bool changed = false;
-    nact = 0;
-    for (int k = 0; k < nc; ++k) {
-      if (hact_prev[k]) iters[k]++;
-      if (hact[k] && iters[k] >= o.maxit) { hact[k] = 0; changed = true; }
-      nact += hact[k];
+    launch_scale_cols(V + (int64_t)(j + 1) * vstride, n, ld, nc, hn2, act, st);
+    finish_only = false;
+    if (j + 1 < m) {
+      launch_dgs_trial(j, m, nc, hprov, hn2, cs, sn, g, act, bnorm, o.tol, done, st);
+      MW_HIP(hipMemcpyAsync(hdone.data(), done, nc * 4, hipMemcpyDeviceToHost, st));
+      MW_HIP(hipStreamSynchronize(st));
+      finish_only = true;
+      for (int k = 0; k < nc; ++k)
+        if (hact[k] && !hdone[k] && iters[k] + 1 < o.maxit) finish_only = false;
     }
-    if (nact == 0) break;
-    if (changed) MW_HIP(hipMemcpyAsync(act, hact.data(), nc * 4, hipMemcpyHostToDevice, st));
   }
   // x += M^-1 (V y)
   launch_backsolve(m, nc, H, g, kdim, y, st);
   launch_combine(V, vstride, m, y, kdim, Z, n, ld, nc, st);
-  double2* U = (double2*)W.tmp.get(c, vstride * 16);
+  double2* U = T;
   apply_prec(p, W, Z, U, nc, ld);
   launch_axpy_cols(X, U, n, ld, nc, st);
 }

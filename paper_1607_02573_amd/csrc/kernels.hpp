@@ -129,19 +129,22 @@ void launch_prolong(const DeviceDecomp& d, int64_t n, const C* Y, int64_t ldy, i
 int64_t reduce_chunks(int64_t n);
 void launch_colnorm2_partial(const double2* V, int64_t n, int64_t ld, int ncols, double* part, hipStream_t st);
 void launch_sum_chunks(const double* part, int64_t nchunk, int64_t width, double* out, hipStream_t st);
-void launch_dots_partial(const double2* V, int64_t vstride, int kcount, const double2* w, int64_t n, int64_t ld,
-                         int ncols, const int32_t* act, double2* part, hipStream_t st);
+void launch_dots_partial(const double2* V, int64_t vstride, int kcount, const double2* w1, const double2* w2,
+                         int64_t n, int64_t ld, int ncols, const int32_t* act, double2* part1, double2* part2,
+                         hipStream_t st);
 void launch_sum_chunks_c(const double2* part, int64_t nchunk, int64_t width, double2* out, hipStream_t st);
-void launch_cgs_update(const double2* V, int64_t vstride, int kcount, const double2* h, double2* w, int64_t n,
-                       int64_t ld, int ncols, const int32_t* act, double* norm_part, hipStream_t st);
-// fused w -= V h and dot products with the updated w; false (nothing launched) if kcount > 8
-bool launch_cgs_update_dots(const double2* V, int64_t vstride, int kcount, const double2* h, double2* w, int64_t n,
-                            int64_t ld, int ncols, const int32_t* act, double2* part, hipStream_t st);
+void launch_dgs_step(int j, int m, bool fin, int ncols, const double2* P1, const double2* P2, const double* beta2,
+                     double2* Hraw, double2* H, double* cs, double2* sn, double2* g, double2* hprov, double2* coef,
+                     double* nu, double2* e, int32_t* kdim, int32_t* act, double* resid, const double* bnorm,
+                     double tol, hipStream_t st);
+void launch_dgs_trial(int j, int m, int ncols, const double2* hprov, const double* beta2, const double* cs,
+                      const double2* sn, const double2* g, const int32_t* act, const double* bnorm, double tol,
+                      int32_t* done, hipStream_t st);
+void launch_dgs_update(double2* V, int64_t vstride, int j, const double2* coef, const double* nu, const double2* e,
+                       const double2* T, int64_t n, int64_t ld, int ncols, const int32_t* act, double* norm_part,
+                       hipStream_t st);
 void launch_scale_cols(double2* w, int64_t n, int64_t ld, int ncols, const double* nrm, const int32_t* act,
                        hipStream_t st);
-void launch_givens(int j, int m, int ncols, const double2* h1, const double2* h2, const double* hn2,
-                   double2* H, double* cs, double2* sn, double2* g, int32_t* kdim, int32_t* act,
-                   double* resid, const double* bnorm, double tol, hipStream_t st);
 void launch_backsolve(int m, int ncols, const double2* H, const double2* g, const int32_t* kdim, double2* y,
                       hipStream_t st);
 void launch_combine(const double2* V, int64_t vstride, int m, const double2* y, const int32_t* kdim,

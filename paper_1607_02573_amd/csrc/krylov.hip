@@ -269,178 +269,281 @@ void launch_sum_chunks_c(const double2* part, int64_t nchunk, int64_t width, dou
 }
 
 // ---------------------------------------------------------------- K6 (CGS2)
-// part[chunk][k][c] = sum_{rows of chunk} conj(V_k[r][c]) w[r][c], k < kcount.
-// A workgroup takes KG basis vectors of one row chunk and 64 columns, so w is
-// read once per KG vectors; every (k, c) sum runs over the chunk's rows in the
-// same order whatever KG and the other columns are.
+// part1[chunk][k][c] = sum_{rows of chunk} conj(V_k[r][c]) w1[r][c] and, if
+// w2 is given, part2 likewise with w2, for k < kcount.  A workgroup takes KG
+// basis vectors of one row chunk and 64 columns, so w1 and w2 are read once
+// per KG vectors; every (k, c) sum runs over the chunk's rows in the same
+// order whatever KG and the other columns are.
 constexpr int DOTS_KG = 8;
+constexpr int CGS_HK = 32;   // coefficients held in LDS up to this many (complex) per column
 __global__ void __launch_bounds__(256) k_dots_partial(const double2* __restrict__ V, int64_t vstride, int kcount,
-                                                      const double2* __restrict__ w, int64_t n, int64_t ld,
-                                                      int ncols, const int32_t* __restrict__ act,
-                                                      double2* __restrict__ part) {
+                                                      const double2* __restrict__ w1, const double2* __restrict__ w2,
+                                                      int64_t n, int64_t ld, int ncols,
+                                                      const int32_t* __restrict__ act, double2* __restrict__ part1,
+                                                      double2* __restrict__ part2) {
   __shared__ double2 red[4][64];
   const int kb = blockIdx.x * DOTS_KG;
   const int chunk = blockIdx.y;
   const int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
   const int c = blockIdx.z * 64 + cl;
   const int64_t r0 = (int64_t)chunk * RCHUNK, r1 = min(n, r0 + RCHUNK);
-  double2 acc[DOTS_KG];
+  double2 acc1[DOTS_KG], acc2[DOTS_KG];
 #pragma unroll
-  for (int q = 0; q < DOTS_KG; ++q) acc[q] = make_double2(0.0, 0.0);
+  for (int q = 0; q < DOTS_KG; ++q) acc1[q] = acc2[q] = make_double2(0.0, 0.0);
   if (c < ncols && act[c]) {
     const double2* Vb = V + (int64_t)kb * vstride;
     for (int64_t r = r0 + rl; r < r1; r += 4) {
-      const double2 x = w[r * ld + c];
+      const double2 x = w1[r * ld + c];
+      const double2 y = w2 ? w2[r * ld + c] : make_double2(0.0, 0.0);
 #pragma unroll
       for (int q = 0; q < DOTS_KG; ++q)
         if (kb + q < kcount) {
           const double2 v = Vb[(int64_t)q * vstride + r * ld + c];
-          acc[q].x += v.x * x.x + v.y * x.y;
-          acc[q].y += v.x * x.y - v.y * x.x;
+          acc1[q].x += v.x * x.x + v.y * x.y;
+          acc1[q].y += v.x * x.y - v.y * x.x;
+          acc2[q].x += v.x * y.x + v.y * y.y;
+          acc2[q].y += v.x * y.y - v.y * y.x;
         }
     }
   }
 #pragma unroll
   for (int q = 0; q < DOTS_KG; ++q) {
     if (kb + q < kcount) {
-      red[rl][cl] = acc[q];
+      red[rl][cl] = acc1[q];
       __syncthreads();
       if (rl == 0 && c < ncols)
-        part[((int64_t)chunk * kcount + kb + q) * ncols + c] =
+        part1[((int64_t)chunk * kcount + kb + q) * ncols + c] =
             cadd(cadd(cadd(red[0][cl], red[1][cl]), red[2][cl]), red[3][cl]);
       __syncthreads();
+      if (part2) {
+        red[rl][cl] = acc2[q];
+        __syncthreads();
+        if (rl == 0 && c < ncols)
+          part2[((int64_t)chunk * kcount + kb + q) * ncols + c] =
+              cadd(cadd(cadd(red[0][cl], red[1][cl]), red[2][cl]), red[3][cl]);
+        __syncthreads();
+      }
     }
   }
 }
 
-void launch_dots_partial(const double2* V, int64_t vstride, int kcount, const double2* w, int64_t n, int64_t ld,
-                         int ncols, const int32_t* act, double2* part, hipStream_t st) {
+void launch_dots_partial(const double2* V, int64_t vstride, int kcount, const double2* w1, const double2* w2,
+                         int64_t n, int64_t ld, int ncols, const int32_t* act, double2* part1, double2* part2,
+                         hipStream_t st) {
   dim3 g((unsigned)ceil_div(kcount, DOTS_KG), (unsigned)reduce_chunks(n), (unsigned)ceil_div(ncols, 64));
   kt_begin(KF_CGS_DOTS, st);
-  k_dots_partial<<<g, 256, 0, st>>>(V, vstride, kcount, w, n, ld, ncols, act, part);
+  k_dots_partial<<<g, 256, 0, st>>>(V, vstride, kcount, w1, w2, n, ld, ncols, act, part1, w2 ? part2 : nullptr);
   MW_LAUNCH_CHECK();
-  if (kt_enabled()) kt_end(KF_CGS_DOTS, st, 8.0 * kcount * n * ncols, (kcount + 1.0) * n * ncols * 16);
+  if (kt_enabled())
+    kt_end(KF_CGS_DOTS, st, (w2 ? 16.0 : 8.0) * kcount * n * ncols, (kcount + (w2 ? 2.0 : 1.0)) * n * ncols * 16);
 }
 
-// w[r][c] -= sum_k V_k[r][c] h[k][c]; optionally |w|^2 chunk partials.
-// The coefficients sit in LDS when kcount <= CGS_HK.
-constexpr int CGS_HK = 32;
-__global__ void __launch_bounds__(256) k_cgs_update(const double2* __restrict__ V, int64_t vstride, int kcount,
-                                                    const double2* __restrict__ h, double2* __restrict__ w, int64_t n,
-                                                    int64_t ld, int ncols, const int32_t* __restrict__ act,
+// ---------------------------------------------------------------- K6/K7 with delayed reorthogonalisation
+// Arnoldi step j of every active column, scalar part (one thread per column).
+// Slot j of the basis holds the candidate y (the previous new vector after
+// one Gram-Schmidt pass, normalised: its norm before scaling was beta);
+// T = A M^-1 y.  From the dot products P1 = [V_0..V_{j-1}, y]^H y and
+// P2 = [V_0..V_{j-1}, y]^H T (a = P1[<j], alpha = P1[j], b = P2[<j],
+// gamma = P2[j]):
+//  * the second pass of y: v_j = (y - V a) / nu, nu = sqrt(alpha - |a|^2)
+//    (nu = 1 for j = 0, where y = r0 / |r0| is final);
+//  * column j-1 of the Hessenberg matrix becomes final:
+//    Hraw[<j][j-1] = hprov + beta a, Hraw[j][j-1] = beta nu; it is rotated
+//    by the previous Givens rotations and a new one into H, giving the
+//    residual estimate |g_j| and Krylov dimension j (deactivation when
+//    |g_j| <= tol |b| or the Krylov space is exhausted);
+//  * the first pass of the next vector: with e = (gamma - a^H b) / nu,
+//    A M^-1 v_j = (T - [V, v_j] Hraw a) / nu, whose projection on [V, v_j]
+//    is hprov = ([b; e] - Hraw[0..j][0..j-1] a) / nu and whose remainder is
+//    (T - V b - v_j e) / nu (formed by k_dgs_update).
+// Equal in exact arithmetic to classical Gram-Schmidt applied twice; each
+// basis vector is read twice per step instead of four times.
+__global__ void k_dgs_step(int j, int m, int fin, int ncols, const double2* __restrict__ P1,
+                           const double2* __restrict__ P2,
+                           const double* __restrict__ beta2, double2* __restrict__ Hraw, double2* __restrict__ H,
+                           double* __restrict__ cs, double2* __restrict__ sn, double2* __restrict__ g,
+                           double2* __restrict__ hprov, double2* __restrict__ coef, double* __restrict__ nu_out,
+                           double2* __restrict__ e_out, int32_t* __restrict__ kdim, int32_t* __restrict__ act,
+                           double* __restrict__ resid, const double* __restrict__ bnorm, double tol) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols || !act[c]) return;
+  auto at = [&](const double2* X, int i) { return X[(int64_t)i * ncols + c]; };
+  auto hr = [&](int i, int k) -> double2& { return Hraw[((int64_t)i * m + k) * ncols + c]; };
+  const double alpha = at(P1, j).x;
+  double a2 = 0.0;
+  for (int k = 0; k < j; ++k) { double2 a = at(P1, k); a2 += a.x * a.x + a.y * a.y; }
+  const double nu = j == 0 ? 1.0 : sqrt(fmax(alpha - a2, 0.0));
+  if (j > 0 && fin) {
+    const double beta = sqrt(beta2[c]);
+    const double hn = beta * nu;
+    for (int i = 0; i < j; ++i) {
+      double2 a = at(P1, i);
+      double2 h = at(hprov, i);
+      hr(i, j - 1) = make_double2(h.x + beta * a.x, h.y + beta * a.y);
+    }
+    hr(j, j - 1) = make_double2(hn, 0.0);
+    // rotate column j-1 into H
+    for (int i = 0; i < j; ++i) H[((int64_t)i * m + j - 1) * ncols + c] = hr(i, j - 1);
+    for (int i = 0; i + 1 < j; ++i) {
+      double ci = cs[(int64_t)i * ncols + c];
+      double2 si = sn[(int64_t)i * ncols + c];
+      double2 x = H[((int64_t)i * m + j - 1) * ncols + c];
+      double2 y = H[((int64_t)(i + 1) * m + j - 1) * ncols + c];
+      H[((int64_t)i * m + j - 1) * ncols + c] = cadd(cscale(x, ci), cmul(si, y));
+      H[((int64_t)(i + 1) * m + j - 1) * ncols + c] = csub(cscale(y, ci), cmulc(x, si));
+    }
+    double2 x = H[((int64_t)(j - 1) * m + j - 1) * ncols + c];
+    double xa = hypot(x.x, x.y);
+    double rho = hypot(xa, hn);
+    double ci;
+    double2 si, r;
+    if (rho == 0.0) { ci = 1.0; si = make_double2(0.0, 0.0); r = make_double2(0.0, 0.0); }
+    else if (xa == 0.0) { ci = 0.0; si = make_double2(1.0, 0.0); r = make_double2(hn, 0.0); }
+    else {
+      double2 ph = make_double2(x.x / xa, x.y / xa);
+      ci = xa / rho;
+      si = cscale(ph, hn / rho);
+      r = cscale(ph, rho);
+    }
+    cs[(int64_t)(j - 1) * ncols + c] = ci;
+    sn[(int64_t)(j - 1) * ncols + c] = si;
+    H[((int64_t)(j - 1) * m + j - 1) * ncols + c] = r;
+    double2 gj = g[(int64_t)(j - 1) * ncols + c];
+    double2 gj1 = make_double2(-(si.x * gj.x + si.y * gj.y), -(si.x * gj.y - si.y * gj.x));   // -conj(s) g
+    g[(int64_t)j * ncols + c] = gj1;
+    g[(int64_t)(j - 1) * ncols + c] = cscale(gj, ci);
+    kdim[c] = j;
+    double res = hypot(gj1.x, gj1.y);
+    resid[c] = res;
+    if (!(res > tol * bnorm[c]) || !(hn > 0.0)) { act[c] = 0; return; }
+  }
+  if (j >= m || !P2) return;
+  // first pass of the next vector
+  double2 e = at(P2, j);
+  for (int k = 0; k < j; ++k) {
+    double2 a = at(P1, k), b = at(P2, k);
+    e.x -= a.x * b.x + a.y * b.y;   // conj(a) b
+    e.y -= a.x * b.y - a.y * b.x;
+  }
+  e = make_double2(e.x / nu, e.y / nu);
+  for (int i = 0; i <= j; ++i) {
+    double2 d = i < j ? at(P2, i) : e;
+    for (int k = 0; k < j; ++k) d = csub(d, cmul(hr(i, k), at(P1, k)));
+    hprov[(int64_t)i * ncols + c] = make_double2(d.x / nu, d.y / nu);
+  }
+  for (int k = 0; k < j; ++k) {
+    coef[(int64_t)(2 * k) * ncols + c] = at(P1, k);
+    coef[(int64_t)(2 * k + 1) * ncols + c] = at(P2, k);
+  }
+  nu_out[c] = nu;
+  e_out[c] = e;
+}
+
+void launch_dgs_step(int j, int m, bool fin, int ncols, const double2* P1, const double2* P2, const double* beta2,
+                     double2* Hraw, double2* H, double* cs, double2* sn, double2* g, double2* hprov, double2* coef,
+                     double* nu, double2* e, int32_t* kdim, int32_t* act, double* resid, const double* bnorm,
+                     double tol, hipStream_t st) {
+  k_dgs_step<<<(unsigned)ceil_div(ncols, 64), 64, 0, st>>>(j, m, fin ? 1 : 0, ncols, P1, P2, beta2, Hraw, H, cs, sn,
+                                                          g, hprov, coef, nu, e, kdim, act, resid, bnorm, tol);
+  MW_LAUNCH_CHECK();
+}
+
+// Residual estimate the next step would give, from the provisional column j
+// (its second-pass correction is of the order of the rounding error): the
+// column rotated by the rotations so far and a trial rotation.  done[c] = 1
+// when the estimate reaches tol |b| or the Krylov space is exhausted, so that
+// the next step can finish column j without applying the operator.
+__global__ void k_dgs_trial(int j, int m, int ncols, const double2* __restrict__ hprov, const double* __restrict__ beta2,
+                            const double* __restrict__ cs, const double2* __restrict__ sn,
+                            const double2* __restrict__ g, const int32_t* __restrict__ act,
+                            const double* __restrict__ bnorm, double tol, int32_t* __restrict__ done) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  if (!act[c]) { done[c] = 1; return; }
+  double2 x = hprov[c], nx = make_double2(0.0, 0.0);
+  for (int i = 0; i < j; ++i) {
+    nx = hprov[(int64_t)(i + 1) * ncols + c];
+    double ci = cs[(int64_t)i * ncols + c];
+    double2 si = sn[(int64_t)i * ncols + c];
+    x = csub(cscale(nx, ci), cmulc(x, si));   // the lower entry after rotation i
+  }
+  const double hn = sqrt(beta2[c]);
+  const double rho = hypot(hypot(x.x, x.y), hn);
+  const double2 gj = g[(int64_t)j * ncols + c];
+  const double res = rho > 0.0 ? hypot(gj.x, gj.y) * hn / rho : 0.0;
+  done[c] = (!(res > tol * bnorm[c]) || !(hn > 0.0)) ? 1 : 0;
+}
+
+void launch_dgs_trial(int j, int m, int ncols, const double2* hprov, const double* beta2, const double* cs,
+                      const double2* sn, const double2* g, const int32_t* act, const double* bnorm, double tol,
+                      int32_t* done, hipStream_t st) {
+  k_dgs_trial<<<(unsigned)ceil_div(ncols, 64), 64, 0, st>>>(j, m, ncols, hprov, beta2, cs, sn, g, act, bnorm, tol,
+                                                           done);
+  MW_LAUNCH_CHECK();
+}
+
+// Vector part of step j: v_j = (y - sum_k V_k a_k) / nu in place of y (slot
+// j), and the next candidate u = (T - sum_k V_k b_k - v_j e) / nu into slot
+// j+1, with |u|^2 chunk partials; coef holds (a_k, b_k) interleaved.  The
+// coefficients sit in LDS when 2j <= CGS_HK.
+__global__ void __launch_bounds__(256) k_dgs_update(double2* __restrict__ V, int64_t vstride, int j,
+                                                    const double2* __restrict__ coef, const double* __restrict__ nu,
+                                                    const double2* __restrict__ e, const double2* __restrict__ T,
+                                                    int64_t n, int64_t ld, int ncols, const int32_t* __restrict__ act,
                                                     double* __restrict__ norm_part) {
   __shared__ double red[4][64];
-  extern __shared__ double2 hs[];   // [kcount][64] when kcount <= CGS_HK
-  int chunk = blockIdx.x;
-  int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
-  int c = blockIdx.y * 64 + cl;
-  int64_t r0 = (int64_t)chunk * RCHUNK, r1 = min(n, r0 + RCHUNK);
-  const bool in_lds = kcount <= CGS_HK;
+  extern __shared__ double2 cf[];   // [2j][64] when 2j <= CGS_HK
+  const int chunk = blockIdx.x;
+  const int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  const int c = blockIdx.y * 64 + cl;
+  const int64_t r0 = (int64_t)chunk * RCHUNK, r1 = min(n, r0 + RCHUNK);
+  const bool in_lds = 2 * j <= CGS_HK;
   if (in_lds) {
-    for (int k = rl; k < kcount; k += 4) hs[k * 64 + cl] = c < ncols ? h[(int64_t)k * ncols + c] : make_double2(0.0, 0.0);
+    for (int k = rl; k < 2 * j; k += 4) cf[k * 64 + cl] = c < ncols ? coef[(int64_t)k * ncols + c] : make_double2(0.0, 0.0);
     __syncthreads();
   }
   double acc = 0.0;
   if (c < ncols && act[c]) {
-    for (int64_t r = r0 + rl; r < r1; r += 4) {
-      double2 x = w[r * ld + c];
-      for (int k = 0; k < kcount; ++k) {
-        double2 v = V[(int64_t)k * vstride + r * ld + c];
-        double2 hk = in_lds ? hs[k * 64 + cl] : h[(int64_t)k * ncols + c];
-        x.x -= v.x * hk.x - v.y * hk.y;
-        x.y -= v.x * hk.y + v.y * hk.x;
-      }
-      w[r * ld + c] = x;
-      acc += x.x * x.x + x.y * x.y;
-    }
-  }
-  if (norm_part) {
-    red[rl][cl] = acc;
-    __syncthreads();
-    if (rl == 0 && c < ncols)
-      norm_part[(int64_t)chunk * ncols + c] = ((red[0][cl] + red[1][cl]) + red[2][cl]) + red[3][cl];
-  }
-}
-
-void launch_cgs_update(const double2* V, int64_t vstride, int kcount, const double2* h, double2* w, int64_t n,
-                       int64_t ld, int ncols, const int32_t* act, double* norm_part, hipStream_t st) {
-  dim3 g((unsigned)reduce_chunks(n), (unsigned)ceil_div(ncols, 64));
-  kt_begin(KF_CGS_UPDATE, st);
-  size_t lds = kcount <= CGS_HK ? (size_t)kcount * 64 * sizeof(double2) : 0;
-  k_cgs_update<<<g, 256, lds, st>>>(V, vstride, kcount, h, w, n, ld, ncols, act, norm_part);
-  MW_LAUNCH_CHECK();
-  if (kt_enabled()) kt_end(KF_CGS_UPDATE, st, 8.0 * kcount * n * ncols, (kcount + 2.0) * n * ncols * 16);
-}
-
-// Second Gram-Schmidt sweep fused with the first update:
-//   w' = w - sum_k V_k h1_k   and   part[chunk][k][c] = sum_rows conj(V_k) w'
-// for k < kcount <= KMAX; every row is finished before its products are
-// accumulated, so one pass over V replaces two.  Per-thread accumulators are
-// indexed by unrolled constants (registers, no scratch).
-template <int KMAX>
-__global__ void __launch_bounds__(256) k_cgs_update_dots(const double2* __restrict__ V, int64_t vstride, int kcount,
-                                                         const double2* __restrict__ h, double2* __restrict__ w,
-                                                         int64_t n, int64_t ld, int ncols,
-                                                         const int32_t* __restrict__ act, double2* __restrict__ part) {
-  __shared__ double2 red[4][64];
-  __shared__ double2 hs[KMAX][64];
-  int chunk = blockIdx.x;
-  int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
-  int c = blockIdx.y * 64 + cl;
-  int64_t r0 = (int64_t)chunk * RCHUNK, r1 = min(n, r0 + RCHUNK);
-  for (int k = rl; k < KMAX; k += 4)
-    hs[k][cl] = (c < ncols && k < kcount) ? h[(int64_t)k * ncols + c] : make_double2(0.0, 0.0);
-  __syncthreads();
-  double2 acc[KMAX];
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k) acc[k] = make_double2(0.0, 0.0);
-  const bool live = c < ncols && act[c];
-  if (live) {
+    const double inu = nu[c];
+    const double2 ec = e[c];
+    double2* Vj = V + (int64_t)j * vstride;
+    double2* Vn = V + (int64_t)(j + 1) * vstride;
     for (int64_t r = r0 + rl; r < r1; r += 4) {
       const int64_t o = r * ld + c;
-      double2 x = w[o];
-#pragma unroll
-      for (int k = 0; k < KMAX; ++k)
-        if (k < kcount) {
-          double2 v = V[(int64_t)k * vstride + o];
-          double2 hk = hs[k][cl];
-          x.x -= v.x * hk.x - v.y * hk.y;
-          x.y -= v.x * hk.y + v.y * hk.x;
-        }
-      w[o] = x;
-#pragma unroll
-      for (int k = 0; k < KMAX; ++k)
-        if (k < kcount) {
-          double2 v = V[(int64_t)k * vstride + o];
-          acc[k].x += v.x * x.x + v.y * x.y;
-          acc[k].y += v.x * x.y - v.y * x.x;
-        }
+      double2 y = Vj[o], u = T[o];
+      for (int k = 0; k < j; ++k) {
+        const double2 v = V[(int64_t)k * vstride + o];
+        const double2 ak = in_lds ? cf[(2 * k) * 64 + cl] : coef[(int64_t)(2 * k) * ncols + c];
+        const double2 bk = in_lds ? cf[(2 * k + 1) * 64 + cl] : coef[(int64_t)(2 * k + 1) * ncols + c];
+        y.x -= v.x * ak.x - v.y * ak.y;
+        y.y -= v.x * ak.y + v.y * ak.x;
+        u.x -= v.x * bk.x - v.y * bk.y;
+        u.y -= v.x * bk.y + v.y * bk.x;
+      }
+      y = make_double2(y.x / inu, y.y / inu);
+      u.x -= y.x * ec.x - y.y * ec.y;
+      u.y -= y.x * ec.y + y.y * ec.x;
+      u = make_double2(u.x / inu, u.y / inu);
+      Vj[o] = y;
+      Vn[o] = u;
+      acc += u.x * u.x + u.y * u.y;
     }
   }
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
-    if (k < kcount) {
-      red[rl][cl] = acc[k];
-      __syncthreads();
-      if (rl == 0 && c < ncols)
-        part[((int64_t)chunk * kcount + k) * ncols + c] =
-            cadd(cadd(cadd(red[0][cl], red[1][cl]), red[2][cl]), red[3][cl]);
-      __syncthreads();
-    }
-  }
+  red[rl][cl] = acc;
+  __syncthreads();
+  if (rl == 0 && c < ncols)
+    norm_part[(int64_t)chunk * ncols + c] = ((red[0][cl] + red[1][cl]) + red[2][cl]) + red[3][cl];
 }
 
-bool launch_cgs_update_dots(const double2* V, int64_t vstride, int kcount, const double2* h, double2* w, int64_t n,
-                            int64_t ld, int ncols, const int32_t* act, double2* part, hipStream_t st) {
+void launch_dgs_update(double2* V, int64_t vstride, int j, const double2* coef, const double* nu, const double2* e,
+                       const double2* T, int64_t n, int64_t ld, int ncols, const int32_t* act, double* norm_part,
+                       hipStream_t st) {
   dim3 g((unsigned)reduce_chunks(n), (unsigned)ceil_div(ncols, 64));
-  // the per-thread dot accumulators stay in registers (occupancy 5) only up
-  // to 8 basis vectors; beyond that the two separate sweeps are faster
-  if (kcount > 8) return false;
+  size_t lds = 2 * j <= CGS_HK ? (size_t)(2 * j) * 64 * sizeof(double2) : 0;
   kt_begin(KF_CGS_UPDATE, st);
-  k_cgs_update_dots<8><<<g, 256, 0, st>>>(V, vstride, kcount, h, w, n, ld, ncols, act, part);
+  k_dgs_update<<<g, 256, lds, st>>>(V, vstride, j, coef, nu, e, T, n, ld, ncols, act, norm_part);
   MW_LAUNCH_CHECK();
-  if (kt_enabled()) kt_end(KF_CGS_UPDATE, st, 16.0 * kcount * n * ncols, (kcount + 2.0) * n * ncols * 16);
-  return true;
+  if (kt_enabled()) kt_end(KF_CGS_UPDATE, st, 16.0 * j * n * ncols, (j + 4.0) * n * ncols * 16);
 }
 
 // w[:, c] /= sqrt(nrm2[c]) for active columns with a nonzero norm
@@ -463,64 +566,6 @@ void launch_scale_cols(double2* w, int64_t n, int64_t ld, int ncols, const doubl
 }
 
 // ---------------------------------------------------------------- K7
-// Column j of the Hessenberg matrix of every active column: h = h1 + h2
-// (the two Gram-Schmidt passes), h_{j+1,j} = ||w||; previous Givens
-// rotations, a new one, the residual estimate |g_{j+1}|, and deactivation
-// when it reaches tol * ||b|| or the Krylov space is exhausted.
-// H[i][jj][c] at (i*m + jj)*ncols + c, g[i][c] at i*ncols + c.
-__global__ void k_givens(int j, int m, int ncols, const double2* __restrict__ h1, const double2* __restrict__ h2,
-                         const double* __restrict__ hn2, double2* __restrict__ H, double* __restrict__ cs,
-                         double2* __restrict__ sn, double2* __restrict__ g, int32_t* __restrict__ kdim,
-                         int32_t* __restrict__ act, double* __restrict__ resid, const double* __restrict__ bnorm,
-                         double tol) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncols || !act[c]) return;
-  for (int i = 0; i <= j; ++i) H[((int64_t)i * m + j) * ncols + c] = cadd(h1[(int64_t)i * ncols + c], h2[(int64_t)i * ncols + c]);
-  double hn = sqrt(hn2[c]);
-  for (int i = 0; i < j; ++i) {
-    double ci = cs[(int64_t)i * ncols + c];
-    double2 si = sn[(int64_t)i * ncols + c];
-    double2 a = H[((int64_t)i * m + j) * ncols + c];
-    double2 b = H[((int64_t)(i + 1) * m + j) * ncols + c];
-    double2 t = cadd(cscale(a, ci), cmul(si, b));
-    double2 u = csub(cscale(b, ci), cmulc(a, si));   // -conj(s) a + c b
-    H[((int64_t)i * m + j) * ncols + c] = t;
-    H[((int64_t)(i + 1) * m + j) * ncols + c] = u;
-  }
-  double2 a = H[((int64_t)j * m + j) * ncols + c];
-  double aa = hypot(a.x, a.y);
-  double rho = hypot(aa, hn);
-  double ci;
-  double2 si, r;
-  if (rho == 0.0) { ci = 1.0; si = make_double2(0.0, 0.0); r = make_double2(0.0, 0.0); }
-  else if (aa == 0.0) { ci = 0.0; si = make_double2(1.0, 0.0); r = make_double2(hn, 0.0); }
-  else {
-    double2 ph = make_double2(a.x / aa, a.y / aa);
-    ci = aa / rho;
-    si = cscale(ph, hn / rho);
-    r = cscale(ph, rho);
-  }
-  cs[(int64_t)j * ncols + c] = ci;
-  sn[(int64_t)j * ncols + c] = si;
-  H[((int64_t)j * m + j) * ncols + c] = r;
-  double2 gj = g[(int64_t)j * ncols + c];
-  double2 gj1 = make_double2(-(si.x * gj.x + si.y * gj.y), -(si.x * gj.y - si.y * gj.x));   // -conj(s) g_j
-  g[(int64_t)(j + 1) * ncols + c] = gj1;
-  g[(int64_t)j * ncols + c] = cscale(gj, ci);
-  kdim[c] = j + 1;
-  double res = hypot(gj1.x, gj1.y);
-  resid[c] = res;
-  if (!(res > tol * bnorm[c]) || !(hn > 0.0)) act[c] = 0;
-}
-
-void launch_givens(int j, int m, int ncols, const double2* h1, const double2* h2, const double* hn2, double2* H,
-                   double* cs, double2* sn, double2* g, int32_t* kdim, int32_t* act, double* resid,
-                   const double* bnorm, double tol, hipStream_t st) {
-  k_givens<<<(unsigned)ceil_div(ncols, 64), 64, 0, st>>>(j, m, ncols, h1, h2, hn2, H, cs, sn, g, kdim, act, resid,
-                                                        bnorm, tol);
-  MW_LAUNCH_CHECK();
-}
-
 // y = R^-1 g on the Krylov dimension of each column (back substitution)
 __global__ void k_backsolve(int m, int ncols, const double2* __restrict__ H, const double2* __restrict__ g,
                             const int32_t* __restrict__ kdim, double2* __restrict__ y) {
