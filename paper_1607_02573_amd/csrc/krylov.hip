@@ -274,7 +274,7 @@ void launch_sum_chunks_c(const double2* part, int64_t nchunk, int64_t width, dou
 // basis vectors of one row chunk and 64 columns, so w1 and w2 are read once
 // per KG vectors; every (k, c) sum runs over the chunk's rows in the same
 // order whatever KG and the other columns are.
-constexpr int DOTS_KG = 8;
+constexpr int DOTS_KG = 6;
 constexpr int CGS_HK = 32;   // coefficients held in LDS up to this many (complex) per column
 __global__ void __launch_bounds__(256) k_dots_partial(const double2* __restrict__ V, int64_t vstride, int kcount,
                                                       const double2* __restrict__ w1, const double2* __restrict__ w2,
@@ -508,25 +508,43 @@ __global__ void __launch_bounds__(256) k_dgs_update(double2* __restrict__ V, int
     const double2 ec = e[c];
     double2* Vj = V + (int64_t)j * vstride;
     double2* Vn = V + (int64_t)(j + 1) * vstride;
-    for (int64_t r = r0 + rl; r < r1; r += 4) {
-      const int64_t o = r * ld + c;
-      double2 y = Vj[o], u = T[o];
+    // two rows per pass (r and r + 4), sharing each coefficient load
+    for (int64_t r = r0 + rl; r < r1; r += 8) {
+      const bool two = r + 4 < r1;
+      const int64_t o0 = r * ld + c, o1 = (r + 4) * ld + c;
+      double2 y0 = Vj[o0], u0 = T[o0];
+      double2 y1 = two ? Vj[o1] : make_double2(0.0, 0.0), u1 = two ? T[o1] : make_double2(0.0, 0.0);
       for (int k = 0; k < j; ++k) {
-        const double2 v = V[(int64_t)k * vstride + o];
+        const double2* Vk = V + (int64_t)k * vstride;
+        const double2 v0 = Vk[o0];
+        const double2 v1 = two ? Vk[o1] : make_double2(0.0, 0.0);
         const double2 ak = in_lds ? cf[(2 * k) * 64 + cl] : coef[(int64_t)(2 * k) * ncols + c];
         const double2 bk = in_lds ? cf[(2 * k + 1) * 64 + cl] : coef[(int64_t)(2 * k + 1) * ncols + c];
-        y.x -= v.x * ak.x - v.y * ak.y;
-        y.y -= v.x * ak.y + v.y * ak.x;
-        u.x -= v.x * bk.x - v.y * bk.y;
-        u.y -= v.x * bk.y + v.y * bk.x;
+        y0.x -= v0.x * ak.x - v0.y * ak.y;
+        y0.y -= v0.x * ak.y + v0.y * ak.x;
+        u0.x -= v0.x * bk.x - v0.y * bk.y;
+        u0.y -= v0.x * bk.y + v0.y * bk.x;
+        y1.x -= v1.x * ak.x - v1.y * ak.y;
+        y1.y -= v1.x * ak.y + v1.y * ak.x;
+        u1.x -= v1.x * bk.x - v1.y * bk.y;
+        u1.y -= v1.x * bk.y + v1.y * bk.x;
       }
-      y = make_double2(y.x / inu, y.y / inu);
-      u.x -= y.x * ec.x - y.y * ec.y;
-      u.y -= y.x * ec.y + y.y * ec.x;
-      u = make_double2(u.x / inu, u.y / inu);
-      Vj[o] = y;
-      Vn[o] = u;
-      acc += u.x * u.x + u.y * u.y;
+      y0 = make_double2(y0.x / inu, y0.y / inu);
+      u0.x -= y0.x * ec.x - y0.y * ec.y;
+      u0.y -= y0.x * ec.y + y0.y * ec.x;
+      u0 = make_double2(u0.x / inu, u0.y / inu);
+      Vj[o0] = y0;
+      Vn[o0] = u0;
+      acc += u0.x * u0.x + u0.y * u0.y;
+      if (two) {
+        y1 = make_double2(y1.x / inu, y1.y / inu);
+        u1.x -= y1.x * ec.x - y1.y * ec.y;
+        u1.y -= y1.x * ec.y + y1.y * ec.x;
+        u1 = make_double2(u1.x / inu, u1.y / inu);
+        Vj[o1] = y1;
+        Vn[o1] = u1;
+        acc += u1.x * u1.x + u1.y * u1.y;
+      }
     }
   }
   red[rl][cl] = acc;
