@@ -42,8 +42,8 @@ MFMA_FAMILIES = ("trsm_gemm", "lu_gemm")
 # known size (--copy-probe-mib).  Valid only for the kernel source it was
 # taken on: a different hash of that file reports null.
 PMC_TRAFFIC = {"family": "trsm_gemm", "source": "paper_1607_02573_amd/csrc/dense.hip",
-               "sha256": "c44be9c28cf66aef9a1e3222e599c7ca3d1e89effeb065882068e6495a606032",
-               "bytes_per_launch": 1.7819e9}   # FETCH 1.5215e9 + WRITE 2.604e8 (pmc_trsm_gemm_chamber10_mixed)
+               "sha256": "f80cc64a6259f42437fa3df56be9ad11227ee2e9e7b221d270ea4b51233fe5be",
+               "bytes_per_launch": 1.7817e9}   # FETCH 1.5213e9 + WRITE 2.604e8 (pmc_trsm_gemm_chamber10_mixed)
 
 
 def measured_traffic(family: str):
