@@ -112,6 +112,71 @@ __global__ void __launch_bounds__(256) k_spmm_w(int64_t n, const int64_t* __rest
   }
 }
 
+// Half-wave form: 32 lanes per row (two rows per wave), each lane on CPL
+// columns c = lane + 32 q; the row's nonzeros are loaded 32 at a time and
+// broadcast within the half-wave.  No idle lanes for 32 * CPL columns.
+template <int CPL>
+__global__ void __launch_bounds__(256) k_spmm_h(int64_t n, const int64_t* __restrict__ row_ptr,
+                                                const int32_t* __restrict__ col, const double2* __restrict__ val,
+                                                const double2* __restrict__ X, int64_t ldx, double2* __restrict__ Y,
+                                                int64_t ldy, int ncols, const double2* __restrict__ Bs, int64_t ldb) {
+  const int64_t G = gridDim.x;
+  const int64_t blk = (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  const int64_t r = (blk * blockDim.x + threadIdx.x) >> 5;
+  const int lane = threadIdx.x & 31;
+  const bool live = r < n;
+  const int64_t b = live ? row_ptr[r] : 0, e = live ? row_ptr[r + 1] : 0;
+  double2 acc[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) acc[q] = make_double2(0.0, 0.0);
+  // both half-waves run the same number of passes (shuffles need every lane)
+  const int64_t len = e - b;
+  const int64_t len_o = __shfl_xor(len, 32);
+  const int64_t len_max = len > len_o ? len : len_o;
+  for (int64_t kb = 0; kb < len_max; kb += 32) {
+    const int cnt = (int)min((int64_t)32, len - kb);
+    int mycol = 0;
+    double2 myval = make_double2(0.0, 0.0);
+    if (lane < cnt) {
+      mycol = col[b + kb + lane];
+      myval = val[b + kb + lane];
+    }
+    const int cnt_max = (int)min((int64_t)32, len_max - kb);
+#pragma unroll 4
+    for (int t = 0; t < cnt_max; ++t) {
+      const int64_t cc = __shfl(mycol, t, 32);
+      double2 a;
+      a.x = __shfl(myval.x, t, 32);
+      a.y = __shfl(myval.y, t, 32);
+      if (t < cnt) {
+        const double2* xr = X + cc * ldx;
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+          const int c = lane + 32 * q;
+          if (c < ncols) {
+            double2 x = xr[c];
+            acc[q].x += a.x * x.x - a.y * x.y;
+            acc[q].y += a.x * x.y + a.y * x.x;
+          }
+        }
+      }
+    }
+  }
+  if (!live) return;
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const int c = lane + 32 * q;
+    if (c < ncols) {
+      double2 o = acc[q];
+      if (Bs) {
+        double2 bb = Bs[r * ldb + c];
+        o = make_double2(bb.x - o.x, bb.y - o.y);
+      }
+      Y[r * ldy + c] = o;
+    }
+  }
+}
+
 void launch_spmm(const DeviceMesh& m, const double2* val, const double2* X, int64_t ldx, double2* Y, int64_t ldy,
                  int ncols, const double2* Bsub, int64_t ldb, hipStream_t st) {
   int64_t n = m.n;
@@ -130,6 +195,9 @@ void launch_spmm(const DeviceMesh& m, const double2* val, const double2* X, int6
   else if (ncols <= 32) MW_SPMM(32);
   else if (ncols <= 64) MW_SPMM_W(1);
   else if (ncols <= 128) MW_SPMM_W(2);
+  else if (ncols <= 160)
+    k_spmm_h<5><<<(unsigned)round_up(ceil_div(n * 32, 256), 8), 256, 0, st>>>(n, m.row_ptr, m.col, val, X, ldx, Y,
+                                                                              ldy, ncols, Bsub, ldb);
   else MW_SPMM_W(3);
 #undef MW_SPMM
 #undef MW_SPMM_W
