@@ -77,3 +77,25 @@ def test_refused_inputs(cube):
     assert e.value.code == binding.MW_EINVAL
     with pytest.raises(ValueError):
         P.solve(P.rhs_dipoles(w.dipoles).to(torch.complex64))   # wrong dtype never reaches the library
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("nc", [1, 33, 65, 129, 160, 161])
+def test_solve_column_counts_against_oracle_residual(nc, prec):
+    """Every SpMM and triangular-solve tile variant (chosen by the column
+    count) gives solutions whose residual, measured with the oracle's own
+    matrix and sources, meets the tolerance."""
+    from paper_1607_02573_amd import solver
+    ctx = solver.Context(0)
+    w = mi.configs.small_chamber(0.25e9, n_per_ring=8, n_sub=8)
+    fp = fem.build(w.mesh, w.eps, w.k0, w.beta_imp, w.ports)
+    P = solver.problem_from_workload(ctx, w)
+    P.factor(w.part, w.n_sub, 1, prec)
+    rng = np.random.default_rng(nc)
+    Bo = fem.rhs_ports(fp, w.ports, w.tx) @ (rng.normal(size=(len(w.tx), nc)) + 1j * rng.normal(size=(len(w.tx), nc)))
+    X, info = P.solve(torch.from_numpy(np.ascontiguousarray(Bo)).cuda(), tol=1e-9)
+    res = np.linalg.norm(Bo - fp.A @ X.cpu().numpy(), axis=0) / np.linalg.norm(Bo, axis=0)
+    assert (info.relres <= 1e-9).all()
+    assert (res <= 1.5e-9).all(), res.max()
+    P.close()
+    ctx.close()
