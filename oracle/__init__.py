@@ -10,6 +10,7 @@ Modules:
   fem      -- edge-element assembly, sources, port projections (Section 2, 4)
   dd       -- overlapping decomposition, partition of unity, ORAS (Section 3)
   gmres    -- right-preconditioned pseudo-block GMRES(m) with CGS2 (Section 6)
+              and block GMRES(m) (the block Krylov method of Section 7)
   inverse  -- S-matrix, misfit, adjoint gradient, Woodbury finite differences
               (Sections 4-5)
 """
