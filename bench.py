@@ -35,6 +35,8 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"hbm_GBs": 8000.0, "fp32_TFLOPs": 157.3, "fp64_TFLOPs": 78.6}
 MFMA_FAMILIES = ("trsm_gemm", "lu_gemm")
+# block Gram-Schmidt of block GMRES: complex FP64 products on the matrix cores
+FP64_MFMA_FAMILIES = ("bgs_dots", "bgs_update")
 
 # HBM bytes per launch of the dominant kernel family, from two rocprofv3
 # --pmc passes (FETCH_SIZE, then WRITE_SIZE) over this benchmark at its
@@ -72,7 +74,7 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_steps(P, w, eps_dev, prec, nsteps, tol, restart, maxit, tx, rx):
+def run_steps(P, w, eps_dev, prec, nsteps, tol, restart, maxit, tx, rx, block=0):
     import torch
     stats = []
     for _ in range(nsteps):
@@ -81,7 +83,7 @@ def run_steps(P, w, eps_dev, prec, nsteps, tol, restart, maxit, tx, rx):
         P.factor(w.part, w.n_sub, 1, prec)          # B_i fill + batched LU
         t1 = time.perf_counter()
         Bm = P.rhs_ports(tx) if w.dipoles is None else P.rhs_dipoles(w.dipoles)
-        X, info = P.solve(Bm, tol=tol, restart=restart, maxit=maxit, raise_noconv=False)
+        X, info = P.solve(Bm, tol=tol, restart=restart, maxit=maxit, raise_noconv=False, block=block)
         S = P.s_matrix(X, rx) if w.dipoles is None and len(rx) else None
         torch.cuda.synchronize()
         t2 = time.perf_counter()
@@ -101,8 +103,9 @@ def family_table(fam: dict, mfma_peak_tflops: float, wall_s: float):
     out, roof_s = {}, 0.0
     for k, v in fam.items():
         s = max(v["ms"], 1e-9) * 1e-3
-        dense = k in MFMA_FAMILIES or k in ("trsm_leaf", "lu_panel", "lu_other")
-        t_flop = v["flops"] / ((mfma_peak_tflops if dense else PEAK["fp64_TFLOPs"]) * 1e12)
+        dense = k in MFMA_FAMILIES or k in ("trsm_leaf", "lu_panel", "lu_other") or k in FP64_MFMA_FAMILIES
+        peak = PEAK["fp64_TFLOPs"] if (k in FP64_MFMA_FAMILIES or not dense) else mfma_peak_tflops
+        t_flop = v["flops"] / (peak * 1e12)
         t_byte = v["bytes"] / (PEAK["hbm_GBs"] * 1e9)
         t_roof, bound = (t_flop, "mfma" if dense else "alu") if t_flop >= t_byte else (t_byte, "hbm")
         roof_s += t_roof
@@ -215,6 +218,8 @@ def main():
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--maxit", type=int, default=600)
     ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--block", type=int, default=0, choices=(0, 32),
+                    help="0: pseudo-block GMRES; 32: block GMRES with blocks of 32 right-hand sides")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain elementwise copy (torch.neg) of this many MiB, the known-size "
@@ -271,13 +276,14 @@ def main():
     # ---------------- mixed precision (the measured configuration)
     if args.warmup:
         log(f"[bench] warmup x{args.warmup}")
-        run_steps(P, w, eps_dev, "c64", args.warmup, tol, args.restart, args.maxit, tx, rx)
+        run_steps(P, w, eps_dev, "c64", args.warmup, tol, args.restart, args.maxit, tx, rx, args.block)
     binding.timer_enable(True)
     binding.timer_reset()
     log(f"[bench] timed mixed steps x{args.steps}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st, (Xm, Sm) = run_steps(P, w, eps_dev, "c64", args.steps, tol, args.restart, args.maxit, tx, rx)
+    st, (Xm, Sm) = run_steps(P, w, eps_dev, "c64", args.steps, tol, args.restart, args.maxit, tx, rx,
+                             args.block)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     fam = binding.timer_read()
@@ -320,7 +326,8 @@ def main():
         binding.timer_reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st64, (X64, S64) = run_steps(P, w, eps_dev, "c128", args.fp64_steps, tol, args.restart, args.maxit, tx, rx)
+        st64, (X64, S64) = run_steps(P, w, eps_dev, "c128", args.fp64_steps, tol, args.restart, args.maxit, tx, rx,
+                                     args.block)
         torch.cuda.synchronize()
         T64 = time.perf_counter() - t0
         fam64 = binding.timer_read()
@@ -352,8 +359,10 @@ def main():
         "dtype": "c64 factors/TRSM (FP32 MFMA) + f64 GMRES",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: n={P.n} unknowns, {w.mesh.nt} tets, {nrhs} port RHS, "
-                               f"{w.n_sub} subdomains overlap 1, GMRES({args.restart}), tol {tol:g}, mixed precision",
-                   "nrhs": nrhs, "n_sub": w.n_sub, "n": P.n, "restart": args.restart, "tol": tol},
+                               f"{w.n_sub} subdomains overlap 1, "
+                               f"{'block ' if args.block else ''}GMRES({args.restart}), tol {tol:g}, mixed precision",
+                   "nrhs": nrhs, "n_sub": w.n_sub, "n": P.n, "restart": args.restart, "tol": tol,
+                   "gmres": f"block GMRES, blocks of {args.block}" if args.block else "pseudo-block GMRES"},
         "solve_rhs_per_s": solve_rate,
         "setup_s": st[-1]["t_setup"],
         "iters_mean": float(it_mixed.mean()),

@@ -101,6 +101,10 @@ typedef struct {
   int32_t restart;   /* GMRES restart length m (>= 1) */
   int32_t maxit;     /* max total iterations per column */
   int32_t use_x0;    /* 1: X holds the initial guess on entry; 0: x0 = 0 */
+  int32_t block;     /* 0: pseudo-block GMRES (each column its own Krylov space);
+                        32: block GMRES, the columns grouped 32 at a time into
+                        blocks that share one block Krylov space (Section 7:
+                        block methods; Saad, Section 6.12).  Batches take 0. */
 } mw_solve_opts;
 
 typedef struct {
@@ -298,6 +302,21 @@ mw_status mw_host_topology(const mw_mesh *mesh, int64_t *n, int64_t *nnz, int64_
 mw_status mw_host_decomposition(const mw_mesh *mesh, const int32_t *tet_part, int32_t n_sub,
                                 int32_t overlap, int32_t *n_loc, int64_t *n_faces, int32_t *sub_dof,
                                 double *D);
+/* Block least squares of block GMRES (blocks of 32 columns; Saad, Iterative
+ * Methods for Sparse Linear Systems, Section 6.12), as the solver runs it on
+ * the host: S0 (32 x 32, upper triangular) the starting block's factor,
+ * width <= 32 the block's real columns (later ones are padding); H
+ * ((steps+1)*32 x steps*32, row-major, leading dimension steps*32) a block
+ * upper Hessenberg matrix whose sub-diagonal blocks are upper triangular.
+ * Adds the block columns one at a time; resid [steps x 32] (NULL to skip)
+ * gets the least-squares residual norm of every right-hand side after each
+ * step, Y [steps*32 x 32] (NULL to skip) the final solution of
+ * min ||E_1 S0 - H Y||.  Also, for G (32 x 32 Hermitian) given in place of
+ * H with steps = 0: resid[0] gets the number of pivots of its Cholesky
+ * factor that are <= thr (relative to the largest diagonal entry) and Y its
+ * Cholesky factor R (G = R^H R, upper triangular). */
+mw_status mw_host_block_lstsq(int32_t steps, int32_t width, const mw_complex *S0, const mw_complex *H,
+                              double thr, double *resid, mw_complex *Y);
 const char *mw_host_last_error(void);
 
 /* ---- kernel timing (measurement) --------------------------------------- */

@@ -113,7 +113,7 @@ def gmres(A, B: np.ndarray, prec, tol: float = 1e-8, restart: int = 30, maxit: i
 
 
 def block_gmres(A, B: np.ndarray, prec, tol: float = 1e-8, restart: int = 30, maxit: int = 1000,
-                p: int = 32, delta: float = 1e-10):
+                p: int = 32, delta: float = 1e-7):
     """Solve A X = B by restarted block GMRES(m) with blocks of p columns.
 
     The block Krylov method the paper's conclusion names as a way to share one
@@ -144,7 +144,9 @@ def block_gmres(A, B: np.ndarray, prec, tol: float = 1e-8, restart: int = 30, ma
     basis vector) and the block's cycle ends after it.  A block whose
     starting residual block is rank deficient in the same sense leaves block
     mode: those columns are finished by ordinary GMRES (gmres above) from the
-    current iterate.
+    current iterate.  delta = 1e-7 sits above the square root of the FP64
+    unit roundoff, the smallest relative pivot a Cholesky-based QR (the GPU
+    solver's) still resolves, so both sides see the same breakdowns.
 
     Returns X and per-column (iterations, true relative residual).
     """

@@ -46,7 +46,8 @@ class mw_port(C.Structure):
 
 
 class mw_solve_opts(C.Structure):
-    _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("maxit", C.c_int32), ("use_x0", C.c_int32)]
+    _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("maxit", C.c_int32), ("use_x0", C.c_int32),
+                ("block", C.c_int32)]
 
 
 class mw_solve_info(C.Structure):
@@ -104,6 +105,7 @@ _SIGS = {
     "mw_batch_destroy": [_P],
     "mw_host_topology": [C.POINTER(mw_mesh), _P, _P, _P, _P, _P, _P],
     "mw_host_decomposition": [C.POINTER(mw_mesh), _P, _I, _I, _P, _P, _P, _P],
+    "mw_host_block_lstsq": [_I, _I, _P, _P, C.c_double, _P, _P],
 }
 EXPORTED = list(_SIGS) + ["mw_last_error", "mw_host_last_error", "mw_timer_families", "mw_timer_name",
                           "mw_timer_enable", "mw_timer_reset"]
@@ -215,3 +217,28 @@ def timer_read() -> dict:
         check(L.mw_timer_read(f, C.addressof(n), C.addressof(ms), C.addressof(fl), C.addressof(by)))
         out[L.mw_timer_name(f).decode()] = {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
     return out
+
+
+def host_block_lstsq(S0: np.ndarray, H: np.ndarray, width: int = 32):
+    """Run the library's host least-squares update of block GMRES over the
+    block columns of H ((steps+1)*32 x steps*32); returns the per-step
+    residual norms [steps, 32] and the final Y [steps*32, 32]."""
+    L = lib()
+    steps = H.shape[1] // 32
+    S0 = np.ascontiguousarray(S0, dtype=np.complex128)
+    H = np.ascontiguousarray(H, dtype=np.complex128)
+    res = np.zeros((steps, 32))
+    Y = np.zeros((steps * 32, 32), dtype=np.complex128)
+    check(L.mw_host_block_lstsq(steps, width, ptr(S0), ptr(H), 0.0, ptr(res), ptr(Y)), True)
+    return res, Y
+
+
+def host_block_cholesky(G: np.ndarray, thr: float):
+    """The library's Cholesky factor of a 32 x 32 block Gram matrix and its
+    count of pivots <= thr relative to the largest diagonal entry."""
+    L = lib()
+    G = np.ascontiguousarray(G, dtype=np.complex128)
+    nd = np.zeros(1)
+    R = np.zeros((32, 32), dtype=np.complex128)
+    check(L.mw_host_block_lstsq(0, 32, None, ptr(G), float(thr), ptr(nd), ptr(R)), True)
+    return R, int(nd[0])

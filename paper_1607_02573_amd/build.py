@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libmw.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.cpp", "hostcheck.cpp", "ktimer.cpp", "topology.cpp", "decomp.cpp", "assemble.hip", "dense.hip", "krylov.hip"]
+SOURCES = ["api.cpp", "hostcheck.cpp", "ktimer.cpp", "topology.cpp", "decomp.cpp", "assemble.hip", "dense.hip", "krylov.hip", "block.hip", "blockls.cpp"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-x", "hip",
          # packed FP32 instructions are disabled for all device code

@@ -15,7 +15,9 @@
 #include <memory>
 #include <numeric>
 
+#include "blockls.hpp"
 #include "kernels.hpp"
+#include "parallel.hpp"
 
 using namespace mw;
 
@@ -85,11 +87,11 @@ struct Work {
 // Device workspaces of one pseudo-block GMRES driver (mw_solve, or one
 // batch), grown on demand.
 struct GmresWork {
-  Work V, X, B, Z, Y, H, Hr, cs, sn, g, y, h1, h2, hp, cf, nu, ee, part, npart, vec, ints, tmp;
+  Work V, X, B, Z, Y, H, Hr, cs, sn, g, y, h1, h2, hp, cf, nu, ee, part, npart, vec, ints, tmp, w_idx;
   hipStream_t st = nullptr;   // the stream this driver's work runs on
-  std::array<Work*, 22> all() {
+  std::array<Work*, 23> all() {
     return {&V, &X, &B, &Z, &Y, &H, &Hr, &cs, &sn, &g, &y, &h1, &h2, &hp, &cf, &nu, &ee, &part, &npart, &vec, &ints,
-            &tmp};
+            &tmp, &w_idx};
   }
   void release() {
     for (Work* w : all()) w->b.release();
@@ -540,6 +542,387 @@ ChunkResult gmres_chunk(mw_problem* p, GmresWork& W, const double2* Bsrc, int64_
   return res;
 }
 
+// ---------------------------------------------------------------- block GMRES
+// Breakdown threshold of the block Cholesky QR: a pivot of the new block's
+// factor below this fraction of the largest column norm of A M^-1 V_j (or of
+// the starting residual block) counts as rank deficiency.  A Cholesky-based
+// QR in FP64 resolves relative pivots down to about the square root of the
+// unit roundoff, so the threshold sits above it.
+constexpr double BLOCK_DELTA = 1e-7;
+// Above this ||R||_F ||R^-1||_F the Cholesky QR of a block is repeated on its
+// result (CholQR2), which restores orthogonality to the unit roundoff.
+constexpr double BLOCK_COND2 = 2e3;
+
+// device bytes of the block Gram-Schmidt reduction partials for nb blocks
+int64_t block_part_bytes(int64_t n, int nb, int m) {
+  int64_t best = 0;
+  for (int ktot = 1; ktot <= m + 1; ++ktot) {
+    int64_t rows, nch;
+    bdots_chunks(n, nb, ktot, &rows, &nch);
+    best = std::max<int64_t>(best, nch * nb * ktot);
+  }
+  return best * 1024 * 16;
+}
+
+double frob(const zc* A, int q) {
+  double s = 0.0;
+  for (int e = 0; e < q * q; ++e) s += std::norm(A[e]);
+  return std::sqrt(s);
+}
+
+// C = A B (q x q, row-major)
+void matmul(const zc* A, const zc* B, int q, zc* C) {
+  for (int i = 0; i < q; ++i)
+    for (int l = 0; l < q; ++l) {
+      zc s = 0.0;
+      for (int k = 0; k < q; ++k) s += A[i * q + k] * B[k * q + l];
+      C[i * q + l] = s;
+    }
+}
+
+// One cycle of block GMRES(m) right-preconditioned with ORAS on nca columns
+// (leading dimension nca) grouped in blocks of BW: block b is columns
+// [BW b, min(BW (b+1), nca)).  On entry V_0 (the start of W.V) holds the true
+// residuals.  Per block: the starting block is factored by Cholesky QR
+// (R0 = V_0 S0); step j applies the operator to V_j, projects the image on
+// V_0..V_j twice (block classical Gram-Schmidt, k_bdots / k_bupdate: dots,
+// update, dots with the Gram matrix of the projected image, then the second
+// update fused with the scaling by R^-1), where R, the Cholesky factor of
+// the projected image's Gram matrix, comes from G1 - P2^H P2 (Pythagoras);
+// an ill-conditioned R gets a second Cholesky QR pass.  The host appends the
+// block column to the least-squares problem and stops the block when every
+// one of its columns' estimates reaches atol, after maxsteps[b] steps, or at
+// a rank-deficient R (that step still counts: only R^H R enters the least
+// squares).  Then U = M^-1 V Y.  steps[b] = steps of block b; 0 for a block
+// whose starting residuals are rank deficient (U = 0 there).
+void block_cycle(mw_problem* p, GmresWork& W, int nca, int m, const std::vector<double>& atol,
+                 const std::vector<int>& maxsteps, double2* U, std::vector<int>& steps) {
+  mw_ctx* c = p->ctx;
+  hipStream_t st = W.st;
+  const int64_t n = p->T.n();
+  const int64_t ld = nca;
+  const int64_t vstride = n * ld;
+  const int nb = (int)ceil_div(nca, BW);
+  double2* V = (double2*)W.V.get(c, (int64_t)(m + 1) * vstride * 16);
+  double2* T = (double2*)W.tmp.get(c, vstride * 16);
+  double2* part = (double2*)W.part.get(c, block_part_bytes(n, nb, m));
+  double2* dP1 = (double2*)W.h1.get(c, (int64_t)nb * (m + 1) * 1024 * 16);
+  double2* dP2 = (double2*)W.h2.get(c, (int64_t)nb * (m + 2) * 1024 * 16);
+  double2* dR = (double2*)W.cf.get(c, (int64_t)nb * 1024 * 16);
+  double2* dY = (double2*)W.y.get(c, (int64_t)nb * m * 1024 * 16);
+  int32_t* dflag = (int32_t*)W.ints.get(c, (int64_t)3 * nb * 4);
+  int32_t* d_dots = dflag;          // 1: block active (dots, first update)
+  int32_t* d_upd = dflag + nb;      // 0: skip, 1: compute, 2: write zeros
+  int32_t* d_kv = dflag + 2 * nb;   // steps per block (final combination)
+  std::vector<int> width(nb);
+  for (int b = 0; b < nb; ++b) width[b] = std::min(BW, nca - BW * b);
+  steps.assign(nb, 0);
+  std::vector<BlockLS> ls(nb);
+  std::vector<char> active(nb, 0);
+  std::vector<int32_t> f_dots(nb), f_upd(nb), f_kv(nb);
+  std::vector<zc> hP1, hP2, hG((size_t)nb * 1024), hR((size_t)nb * 1024);
+  std::vector<zc> R1((size_t)nb * 1024), R2((size_t)nb * 1024);
+  int64_t nch = 0;
+  auto upload_flags = [&](const std::vector<int32_t>& f, int32_t* d) {
+    MW_HIP(hipMemcpyAsync(d, f.data(), nb * 4, hipMemcpyHostToDevice, st));
+  };
+  auto set_identity = [&](zc* A) {
+    for (int e = 0; e < 1024; ++e) A[e] = (e % 33 == 0) ? 1.0 : 0.0;
+  };
+  // Gram matrices (host, nb x 32 x 32) of the blocks of X flagged in f_dots
+  auto gram = [&](const double2* X) {
+    upload_flags(f_dots, d_dots);
+    launch_bdots(V, vstride, 0, X, X, n, ld, nca, nb, d_dots, part, &nch, st);
+    launch_sum_chunks_c(part, nch, (int64_t)nb * 1024, dP2, st);
+    MW_HIP(hipMemcpyAsync(hG.data(), dP2, (size_t)nb * 1024 * 16, hipMemcpyDeviceToHost, st));
+    MW_HIP(hipStreamSynchronize(st));
+  };
+  // X[:, block b] <- X[:, block b] hR_b for the blocks flagged in f_upd (in place)
+  auto scale = [&](double2* X) {
+    upload_flags(f_upd, d_upd);
+    MW_HIP(hipMemcpyAsync(dR, hR.data(), (size_t)nb * 1024 * 16, hipMemcpyHostToDevice, st));
+    launch_bupdate(V, vstride, 0, nullptr, 0, dR, 0, dR, X, X, n, ld, nca, nb, d_upd, st);
+  };
+  // Cholesky of the Gram matrix of block b (padding columns: identity);
+  // returns the number of deficient pivots relative to scale2
+  auto chol = [&](const zc* Gb, int b, double scale2, zc* R) {
+    std::vector<zc> G(Gb, Gb + 1024);
+    for (int q = 0; q < BW; ++q)
+      for (int l = 0; l < BW; ++l)
+        if (q >= width[b] || l >= width[b]) G[q * BW + l] = (q == l) ? 1.0 : 0.0;
+    return chol_upper(G.data(), BW, BLOCK_DELTA * BLOCK_DELTA * scale2, R);
+  };
+  // second Cholesky QR pass over X for the blocks flagged in f_dots: R_b <- R2 R_b
+  auto cholqr2 = [&](double2* X, std::vector<zc>& R) {
+    gram(X);
+    for (int b = 0; b < nb; ++b) {
+      f_upd[b] = 0;
+      if (!f_dots[b]) continue;
+      zc* r2 = &R2[(size_t)b * 1024];
+      if (chol(&hG[(size_t)b * 1024], b, 1.0, r2) > 0) set_identity(r2);
+      tri_inv_upper(r2, BW, &hR[(size_t)b * 1024]);
+      std::vector<zc> t(1024);
+      matmul(r2, &R[(size_t)b * 1024], BW, t.data());
+      std::copy(t.begin(), t.end(), R.begin() + (size_t)b * 1024);
+      f_upd[b] = 1;
+    }
+    scale(X);
+  };
+
+  // starting block: Gram matrix of the residuals, Cholesky, V_0 = R0 S0^-1
+  for (int b = 0; b < nb; ++b) f_dots[b] = 1;
+  gram(V);
+  int nact = 0;
+  bool again = false;
+  for (int b = 0; b < nb; ++b) {
+    const zc* Gb = &hG[(size_t)b * 1024];
+    double s2 = 0.0;
+    for (int q = 0; q < width[b]; ++q) s2 = std::max(s2, Gb[q * BW + q].real());
+    zc* r1 = &R1[(size_t)b * 1024];
+    f_dots[b] = 0;
+    f_upd[b] = 2;
+    set_identity(&hR[(size_t)b * 1024]);
+    if (!(s2 > 0.0) || chol(Gb, b, s2, r1) > 0) continue;
+    tri_inv_upper(r1, BW, &hR[(size_t)b * 1024]);
+    active[b] = 1;
+    f_upd[b] = 1;
+    ++nact;
+    if (frob(r1, BW) * frob(&hR[(size_t)b * 1024], BW) > BLOCK_COND2) { f_dots[b] = 1; again = true; }
+  }
+  scale(V);
+  if (again) cholqr2(V, R1);
+  for (int b = 0; b < nb; ++b)
+    if (active[b]) ls[b].start(m, &R1[(size_t)b * 1024], width[b]);
+  if (nact == 0) return;
+
+  for (int j = 0; j < m && nact > 0; ++j) {
+    double2* Vj = V + (int64_t)j * vstride;
+    double2* Vn = V + (int64_t)(j + 1) * vstride;
+    const int kv = j + 1;
+    for (int b = 0; b < nb; ++b) f_dots[b] = active[b] ? 1 : 0;
+    upload_flags(f_dots, d_dots);
+    apply_prec(p, W, Vj, U, nca, ld);
+    launch_spmm(p->dm, p->val.as<double2>(), U, ld, T, ld, nca, nullptr, 0, st);
+    // first pass: P1 = V^H T, T -= V P1
+    launch_bdots(V, vstride, kv, nullptr, T, n, ld, nca, nb, d_dots, part, &nch, st);
+    launch_sum_chunks_c(part, nch, (int64_t)nb * kv * 1024, dP1, st);
+    launch_bupdate(V, vstride, kv, nullptr, kv, dP1, kv, nullptr, T, T, n, ld, nca, nb, d_dots, st);
+    // second pass: [P2; G1] = [V T]^H T
+    launch_bdots(V, vstride, kv, T, T, n, ld, nca, nb, d_dots, part, &nch, st);
+    launch_sum_chunks_c(part, nch, (int64_t)nb * (kv + 1) * 1024, dP2, st);
+    hP1.resize((size_t)nb * kv * 1024);
+    hP2.resize((size_t)nb * (kv + 1) * 1024);
+    MW_HIP(hipMemcpyAsync(hP1.data(), dP1, hP1.size() * 16, hipMemcpyDeviceToHost, st));
+    MW_HIP(hipMemcpyAsync(hP2.data(), dP2, hP2.size() * 16, hipMemcpyDeviceToHost, st));
+    MW_HIP(hipStreamSynchronize(st));
+    // R of every active block; deficient ones end their cycle at this step
+    std::vector<int> ndef(nb, 0);
+    std::vector<char> cond2(nb, 0);
+    parallel_items(nb, [&](int, int64_t bi) {
+      const int b = (int)bi;
+      if (!active[b]) return;
+      const zc* P1 = hP1.data() + (size_t)b * kv * 1024;
+      const zc* P2 = hP2.data() + (size_t)b * (kv + 1) * 1024;
+      const zc* G1 = P2 + (size_t)kv * 1024;
+      // squared column norms of A M^-1 V_j: ||P1 e_c||^2 + ||T e_c||^2
+      double s2 = 0.0;
+      for (int q = 0; q < width[b]; ++q) {
+        double s = G1[q * BW + q].real();
+        for (int r = 0; r < kv * BW; ++r) s += std::norm(P1[(size_t)r * BW + q]);
+        s2 = std::max(s2, s);
+      }
+      std::vector<zc> G(1024);
+      for (int q = 0; q < BW; ++q)
+        for (int l = 0; l < BW; ++l) {
+          zc s = G1[q * BW + l];
+          for (int r = 0; r < kv * BW; ++r) s -= std::conj(P2[(size_t)r * BW + q]) * P2[(size_t)r * BW + l];
+          G[q * BW + l] = s;
+        }
+      zc* r1 = &R1[(size_t)b * 1024];
+      ndef[b] = chol(G.data(), b, s2, r1);
+      if (ndef[b] == 0) {
+        tri_inv_upper(r1, BW, &hR[(size_t)b * 1024]);
+        cond2[b] = frob(r1, BW) * frob(&hR[(size_t)b * 1024], BW) > BLOCK_COND2;
+      }
+    });
+    bool need2 = false;
+    for (int b = 0; b < nb; ++b) need2 |= cond2[b] != 0;
+    if (need2) {
+      // an ill-conditioned factor: form V_{j+1} now and repeat its Cholesky QR
+      for (int b = 0; b < nb; ++b) {
+        f_upd[b] = (active[b] && ndef[b] == 0) ? 1 : 0;
+        f_dots[b] = cond2[b];
+      }
+      upload_flags(f_upd, d_upd);
+      MW_HIP(hipMemcpyAsync(dR, hR.data(), (size_t)nb * 1024 * 16, hipMemcpyHostToDevice, st));
+      launch_bupdate(V, vstride, kv, nullptr, kv, dP2, kv + 1, dR, T, Vn, n, ld, nca, nb, d_upd, st);
+      cholqr2(Vn, R1);
+    }
+    // append block column j and test convergence
+    std::vector<char> finished(nb, 0);
+    parallel_items(nb, [&](int, int64_t bi) {
+      const int b = (int)bi;
+      if (!active[b]) return;
+      const zc* P1 = hP1.data() + (size_t)b * kv * 1024;
+      const zc* P2 = hP2.data() + (size_t)b * (kv + 1) * 1024;
+      std::vector<zc> Hc((size_t)kv * 1024);
+      for (size_t e = 0; e < Hc.size(); ++e) Hc[e] = P1[e] + P2[e];
+      ls[b].add(Hc.data(), &R1[(size_t)b * 1024]);
+      steps[b] = kv;
+      bool done = ndef[b] > 0 || kv >= maxsteps[b];
+      if (!done) {
+        done = true;
+        for (int q = 0; q < width[b]; ++q)
+          if (!(ls[b].resid(q) <= atol[(size_t)b * BW + q])) done = false;
+      }
+      finished[b] = done;
+    });
+    for (int b = 0; b < nb; ++b)
+      if (active[b] && finished[b]) { active[b] = 0; --nact; }
+    if (nact == 0 || j + 1 == m) break;
+    if (!need2) {
+      // V_{j+1} = (T - V P2) R^-1 for the blocks that go on, zero for the others
+      for (int b = 0; b < nb; ++b) f_upd[b] = active[b] ? 1 : 2;
+      upload_flags(f_upd, d_upd);
+      MW_HIP(hipMemcpyAsync(dR, hR.data(), (size_t)nb * 1024 * 16, hipMemcpyHostToDevice, st));
+      launch_bupdate(V, vstride, kv, nullptr, kv, dP2, kv + 1, dR, T, Vn, n, ld, nca, nb, d_upd, st);
+    } else {
+      for (int b = 0; b < nb; ++b) f_upd[b] = active[b] ? 0 : 2;
+      upload_flags(f_upd, d_upd);
+      launch_bupdate(V, vstride, 0, nullptr, 0, dR, 0, nullptr, nullptr, Vn, n, ld, nca, nb, d_upd, st);
+    }
+  }
+  // U = M^-1 V Y
+  int kmax = 0;
+  std::vector<zc> Y((size_t)nb * m * 1024, zc(0.0));
+  parallel_items(nb, [&](int, int64_t bi) {
+    const int b = (int)bi;
+    if (steps[b] == 0) return;
+    zc* Yb = &Y[(size_t)b * m * 1024];
+    ls[b].solve(Yb);
+    for (int64_t e = 0; e < (int64_t)steps[b] * 1024; ++e) Yb[e] = -Yb[e];
+  });
+  for (int b = 0; b < nb; ++b) {
+    f_kv[b] = steps[b];
+    f_upd[b] = steps[b] > 0 ? 1 : 2;
+    kmax = std::max(kmax, steps[b]);
+  }
+  upload_flags(f_kv, d_kv);
+  upload_flags(f_upd, d_upd);
+  MW_HIP(hipMemcpyAsync(dY, Y.data(), Y.size() * 16, hipMemcpyHostToDevice, st));
+  launch_bupdate(V, vstride, 0, d_kv, kmax, dY, m, nullptr, nullptr, T, n, ld, nca, nb, d_upd, st);
+  apply_prec(p, W, T, U, nca, ld);
+  // the host vectors read by the asynchronous uploads must outlive them
+  MW_HIP(hipStreamSynchronize(st));
+}
+
+// Block GMRES(m) to convergence on nc columns (one memory chunk of
+// mw_solve): each restart recomputes the true residuals, regroups the
+// columns still above tol (in column order) into blocks of BW and runs a
+// block cycle on them.  Columns whose starting block is rank deficient are
+// finished by the pseudo-block solver from the current iterate.
+ChunkResult block_chunk(mw_problem* p, GmresWork& W, const double2* Bsrc, int64_t ldb_src, double2* Xdst,
+                        int64_t ldx_dst, int nc, const mw_solve_opts& o, int32_t* iters_out, double* relres_out) {
+  mw_ctx* c = p->ctx;
+  hipStream_t st = W.st;
+  const int64_t n = p->T.n();
+  const int64_t ld = nc;
+  const int64_t vstride = n * ld;
+  const int m = o.restart;
+  double2* X = (double2*)W.X.get(c, vstride * 16);
+  double2* B = (double2*)W.B.get(c, vstride * 16);
+  double2* Z = (double2*)W.Z.get(c, vstride * 16);
+  double* vec = (double*)W.vec.get(c, (int64_t)4 * nc * 8);
+  double* rn2 = vec + nc;
+  int32_t* didx = (int32_t*)W.w_idx.get(c, (int64_t)nc * 4);
+
+  launch_copy_cols(Bsrc, ldb_src, B, ld, n, nc, st);
+  if (o.use_x0) launch_copy_cols(Xdst, ldx_dst, X, ld, n, nc, st);
+  else launch_zero(X, vstride, st);
+  std::vector<double> hb(nc), hr, hb2(nc);
+  colnorm2(p, W, B, ld, nc, rn2);
+  MW_HIP(hipMemcpyAsync(hb2.data(), rn2, nc * 8, hipMemcpyDeviceToHost, st));
+  MW_HIP(hipStreamSynchronize(st));
+  for (int k = 0; k < nc; ++k) hb[k] = std::sqrt(hb2[k]);
+
+  ChunkResult res;
+  std::vector<int32_t> iters(nc, 0);
+  std::vector<double> relres(nc, 0.0);
+  std::vector<char> single(nc, 0);
+  for (;;) {
+    true_residual(p, W, B, X, Z, nc, rn2, hr);
+    std::vector<int32_t> act;
+    for (int k = 0; k < nc; ++k) {
+      double r = std::sqrt(hr[k]);
+      if (!std::isfinite(r)) res.numeric = true;
+      relres[k] = hb[k] > 0 ? r / hb[k] : 0.0;
+      if (column_continues(hb[k], relres[k], iters[k], r, o) && !single[k]) act.push_back(k);
+    }
+    if (res.numeric || act.empty()) break;
+    res.cycles++;
+    const int nca = (int)act.size();
+    const int nb = (int)ceil_div(nca, BW);
+    std::vector<double> atol((size_t)nb * BW, 0.0);
+    std::vector<int> maxsteps(nb, m);
+    for (int q = 0; q < nca; ++q) {
+      atol[q] = o.tol * hb[act[q]];
+      maxsteps[q / BW] = std::min(maxsteps[q / BW], o.maxit - iters[act[q]]);
+    }
+    MW_HIP(hipMemcpyAsync(didx, act.data(), nca * 4, hipMemcpyHostToDevice, st));
+    double2* V = (double2*)W.V.get(c, (int64_t)(m + 1) * n * nca * 16);
+    launch_gather_cols(Z, ld, didx, V, nca, n, nca, st);
+    std::vector<int> steps;
+    block_cycle(p, W, nca, m, atol, maxsteps, Z, steps);
+    // X[:, act] += U
+    double2* T = (double2*)W.tmp.get(c, vstride * 16);
+    launch_gather_cols(X, ld, didx, T, nca, n, nca, st);
+    launch_axpy_cols(T, Z, n, nca, nca, st);
+    launch_scatter_cols(T, nca, didx, X, ld, n, nca, st);
+    for (int q = 0; q < nca; ++q) {
+      const int s = steps[q / BW];
+      if (s == 0) single[act[q]] = 1;
+      iters[act[q]] += s;
+    }
+  }
+  launch_copy_cols(X, ld, Xdst, ldx_dst, n, nc, st);
+  MW_HIP(hipStreamSynchronize(st));
+  // columns left to the pseudo-block solver
+  std::vector<int32_t> rest;
+  int rest_max_it = 0;
+  for (int k = 0; k < nc; ++k)
+    if (single[k] && !res.numeric && column_continues(hb[k], relres[k], iters[k], relres[k] * hb[k], o)) {
+      rest.push_back(k);
+      rest_max_it = std::max(rest_max_it, iters[k]);
+    }
+  if (!rest.empty()) {
+    const int ns = (int)rest.size();
+    DevBuf Bs = dalloc(c, n * ns * 16), Xs = dalloc(c, n * ns * 16), ix = dalloc(c, (int64_t)ns * 4);
+    MW_HIP(hipMemcpyAsync(ix.p, rest.data(), ns * 4, hipMemcpyHostToDevice, st));
+    launch_gather_cols(Bsrc, ldb_src, ix.as<int32_t>(), Bs.as<double2>(), ns, n, ns, st);
+    launch_gather_cols(Xdst, ldx_dst, ix.as<int32_t>(), Xs.as<double2>(), ns, n, ns, st);
+    mw_solve_opts o2 = o;
+    o2.use_x0 = 1;
+    o2.maxit = std::max(1, o.maxit - rest_max_it);
+    std::vector<int32_t> it2(ns);
+    std::vector<double> rr2(ns);
+    ChunkResult r2 = gmres_chunk(p, W, Bs.as<double2>(), ns, Xs.as<double2>(), ns, ns, o2, it2.data(), rr2.data());
+    launch_scatter_cols(Xs.as<double2>(), ns, ix.as<int32_t>(), Xdst, ldx_dst, n, ns, st);
+    MW_HIP(hipStreamSynchronize(st));
+    res.numeric |= r2.numeric;
+    res.cycles += r2.cycles;
+    for (int q = 0; q < ns; ++q) {
+      iters[rest[q]] += it2[q];
+      relres[rest[q]] = rr2[q];
+    }
+  }
+  for (int k = 0; k < nc; ++k) {
+    if (iters_out) iters_out[k] = iters[k];
+    if (relres_out) relres_out[k] = relres[k];
+    res.max_iters = std::max(res.max_iters, iters[k]);
+  }
+  return res;
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -809,11 +1192,14 @@ mw_status mw_apply_preconditioner(mw_problem* p, int32_t nrhs, const void* V, vo
   });
 }
 
-static int solve_chunk_cols(mw_problem* p, int nrhs, int m) {
+static int solve_chunk_cols(mw_problem* p, int nrhs, int m, bool block) {
   mw_ctx* c = p->ctx;
   int64_t per = gmres_bytes_per_col(p, m);
   int64_t held = p->ws.held();
   int64_t avail = c->budget - c->used.load() + held;
+  // block mode: reduction partials of the block Gram-Schmidt, bounded by
+  // about 4096 32x32 products per sweep plus one per block and basis vector
+  if (block) avail -= block_part_bytes(p->T.n(), (int)ceil_div(nrhs, BW), m) + (64 << 20);
   int64_t cols = avail / std::max<int64_t>(per, 1);
   // when the columns must be split, use multiples of 32 (the width granule of
   // the triangular-solve tiles) so that no tile runs half empty
@@ -825,15 +1211,16 @@ mw_status mw_solve(mw_problem* p, int32_t nrhs, const void* B, void* X, const mw
   return guard([&] {
     check_prob(p);
     MW_CHECK(nrhs >= 0 && (nrhs == 0 || (B && X)), MW_EINVAL, "NULL argument");
-    mw_solve_opts op{1e-8, 30, 1000, 0};
+    mw_solve_opts op{1e-8, 30, 1000, 0, 0};
     if (o) op = *o;
     MW_CHECK(op.restart >= 1 && op.maxit >= 1 && op.tol > 0, MW_EINVAL, "invalid solve options");
+    MW_CHECK(op.block == 0 || op.block == BW, MW_EINVAL, "block must be 0 (pseudo-block) or 32 (block GMRES)");
     MW_CHECK(p->factors_valid, MW_EINVAL, "no valid subdomain factors: call mw_factor_subdomains");
     if (info) { info->max_iters = 0; info->cycles = 0; info->chunks = 0; info->t_solve = 0; }
     if (nrhs == 0) return;
     DeviceGuard dg(p->ctx->device);
     double t0 = now_s();
-    int cols = solve_chunk_cols(p, nrhs, op.restart);
+    int cols = solve_chunk_cols(p, nrhs, op.restart, op.block != 0);
     MW_CHECK(cols >= 1, MW_ENOMEM, "HBM budget leaves no room for the Krylov basis of one column");
     bool numeric = false, noconv = false;
     int chunks = 0;
@@ -843,7 +1230,10 @@ mw_status mw_solve(mw_problem* p, int32_t nrhs, const void* B, void* X, const mw
       std::vector<double> rr(nc);
       p->ws.st = p->stream;
       ChunkResult r =
-          gmres_chunk(p, p->ws, (const double2*)B + c0, nrhs, (double2*)X + c0, nrhs, nc, op, it.data(), rr.data());
+          op.block ? block_chunk(p, p->ws, (const double2*)B + c0, nrhs, (double2*)X + c0, nrhs, nc, op, it.data(),
+                                 rr.data())
+                   : gmres_chunk(p, p->ws, (const double2*)B + c0, nrhs, (double2*)X + c0, nrhs, nc, op, it.data(),
+                                 rr.data());
       chunks++;
       numeric |= r.numeric;
       for (int k = 0; k < nc; ++k) {
@@ -1066,10 +1456,11 @@ mw_status mw_batch_create(mw_problem* p, int32_t max_cols, const mw_solve_opts* 
   return guard([&] {
     check_prob(p);
     MW_CHECK(out != nullptr && max_cols >= 1, MW_EINVAL, "out is NULL or max_cols < 1");
-    mw_solve_opts op{1e-8, 30, 1000, 0};
+    mw_solve_opts op{1e-8, 30, 1000, 0, 0};
     if (o) op = *o;
     MW_CHECK(op.restart >= 1 && op.maxit >= 1 && op.tol > 0, MW_EINVAL, "invalid solve options");
     MW_CHECK(!op.use_x0, MW_EINVAL, "batched columns start from x0 = 0");
+    MW_CHECK(op.block == 0, MW_EINVAL, "batches run the pseudo-block solver (block must be 0)");
     DeviceGuard dg(p->ctx->device);
     auto b = std::make_unique<mw_batch>();
     b->p = p;

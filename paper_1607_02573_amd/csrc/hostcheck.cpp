@@ -4,6 +4,7 @@
 #include <cstring>
 #include <numeric>
 
+#include "blockls.hpp"
 #include "common.hpp"
 
 using namespace mw;
@@ -62,6 +63,38 @@ mw_status mw_host_decomposition(const mw_mesh* mesh, const int32_t* tet_part, in
         ++w;
       }
     }
+  });
+}
+
+mw_status mw_host_block_lstsq(int32_t steps, int32_t width, const mw_complex* S0, const mw_complex* H, double thr,
+                              double* resid, mw_complex* Y) {
+  return hguard([&] {
+    MW_CHECK(steps >= 0 && width >= 1 && width <= BW && H, MW_EINVAL, "invalid block least-squares arguments");
+    const zc* Hz = reinterpret_cast<const zc*>(H);
+    if (steps == 0) {
+      double dmax = 0.0;
+      for (int c = 0; c < BW; ++c) dmax = std::max(dmax, Hz[c * BW + c].real());
+      std::vector<zc> R(BW * BW);
+      int nd = chol_upper(Hz, BW, thr * thr * dmax, R.data());
+      if (resid) resid[0] = nd;
+      if (Y) std::copy(R.begin(), R.end(), reinterpret_cast<zc*>(Y));
+      return;
+    }
+    MW_CHECK(S0 != nullptr, MW_EINVAL, "NULL argument");
+    const int64_t ldh = (int64_t)steps * BW;
+    BlockLS ls;
+    ls.start(steps, reinterpret_cast<const zc*>(S0), width);
+    std::vector<zc> Hc((size_t)(steps + 1) * BW * BW), R(BW * BW);
+    for (int j = 0; j < steps; ++j) {
+      for (int64_t r = 0; r < (int64_t)(j + 1) * BW; ++r)
+        for (int t = 0; t < BW; ++t) Hc[r * BW + t] = Hz[r * ldh + (int64_t)j * BW + t];
+      for (int r = 0; r < BW; ++r)
+        for (int t = 0; t < BW; ++t) R[r * BW + t] = Hz[((int64_t)(j + 1) * BW + r) * ldh + (int64_t)j * BW + t];
+      ls.add(Hc.data(), R.data());
+      if (resid)
+        for (int c = 0; c < BW; ++c) resid[(int64_t)j * BW + c] = ls.resid(c);
+    }
+    if (Y) ls.solve(reinterpret_cast<zc*>(Y));
   });
 }
 

@@ -7,7 +7,7 @@ namespace mw {
 
 // kernel families timed by ktimer.cpp
 enum KFamily { KF_TRSM_GEMM, KF_TRSM_LEAF, KF_LU_GEMM, KF_LU_PANEL, KF_LU_OTHER, KF_SPMM, KF_CGS_DOTS,
-               KF_CGS_UPDATE, KF_RESTRICT, KF_PROLONG, KF_VECTOR, KF_COUNT };
+               KF_CGS_UPDATE, KF_RESTRICT, KF_PROLONG, KF_VECTOR, KF_BGS_DOTS, KF_BGS_UPDATE, KF_COUNT };
 bool kt_enabled();
 void kt_begin(int family, hipStream_t st);
 void kt_end(int family, hipStream_t st, double flops, double bytes);
@@ -163,6 +163,15 @@ void launch_gather_cols(const double2* src, int64_t lds, const int32_t* idx, dou
 void launch_scatter_cols(const double2* src, int64_t lds, const int32_t* idx, double2* dst, int64_t ldd, int64_t n,
                          int ncols, hipStream_t st);
 void launch_zero_bytes(void* p, int64_t bytes, hipStream_t st);
+
+// block Gram-Schmidt of block GMRES (block.hip): blocks of 32 columns
+void bdots_chunks(int64_t n, int nb, int ktot, int64_t* rows_per_ch, int64_t* nch);
+void launch_bdots(const double2* V, int64_t vstride, int kv, const double2* E, const double2* Wr, int64_t n,
+                  int64_t ld, int ncols, int nb, const int32_t* blk, double2* part, int64_t* nch_out,
+                  hipStream_t st);
+void launch_bupdate(const double2* V, int64_t vstride, int kv, const int32_t* kvb, int kv_max, const double2* P,
+                    int pk_stride, const double2* Rinv, const double2* Win, double2* Out, int64_t n, int64_t ld,
+                    int ncols, int nb, const int32_t* blk, hipStream_t st);
 void launch_misfit(const double2* S, const double2* Sm, int64_t count, double2* gS, double* J, hipStream_t st);
 
 }  // namespace mw

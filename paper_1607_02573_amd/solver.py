@@ -26,8 +26,9 @@ class SolveInfo:
     t_solve: float
 
 
-def _opts(tol, restart, maxit, use_x0):
-    return B.mw_solve_opts(tol=float(tol), restart=int(restart), maxit=int(maxit), use_x0=int(use_x0))
+def _opts(tol, restart, maxit, use_x0, block=0):
+    return B.mw_solve_opts(tol=float(tol), restart=int(restart), maxit=int(maxit), use_x0=int(use_x0),
+                           block=int(block))
 
 
 def _dev_tensor(t: torch.Tensor, dtype, device, name):
@@ -167,7 +168,10 @@ class Problem:
 
     # ------------------------------------------------------------------ solve
     def solve(self, Bm: torch.Tensor, tol=1e-8, restart=30, maxit=1000, x0: torch.Tensor | None = None,
-              raise_noconv: bool = True):
+              raise_noconv: bool = True, block: int = 0):
+        """GMRES solve of A X = Bm; block = 32 groups the columns into blocks
+        of 32 sharing one block Krylov space, block = 0 keeps one Krylov space
+        per column (pseudo-block)."""
         _dev_tensor(Bm, torch.complex128, self.ctx.device, "B")
         nrhs = Bm.shape[1]
         if x0 is not None:
@@ -180,7 +184,7 @@ class Problem:
         it = np.zeros(nrhs, dtype=np.int32)
         rr = np.zeros(nrhs)
         info = B.mw_solve_info(iters=ptr(it) if nrhs else None, relres=ptr(rr) if nrhs else None)
-        o = _opts(tol, restart, maxit, x0 is not None)
+        o = _opts(tol, restart, maxit, x0 is not None, block)
         code = lib().mw_solve(self.h, nrhs, ptr(Bm), ptr(X), C.byref(o), C.byref(info))
         if code != B.MW_OK and not (code == B.MW_ENOCONV and not raise_noconv):
             check(code)
@@ -194,25 +198,26 @@ class Problem:
         check(lib().mw_s_matrix(self.h, rx.size, ptr(rx), U.shape[1], ptr(U), ptr(S)))
         return S
 
-    def adjoint_gradient(self, U: torch.Tensor, gS: torch.Tensor, tx, rx, tol=1e-8, restart=30, maxit=1000):
+    def adjoint_gradient(self, U: torch.Tensor, gS: torch.Tensor, tx, rx, tol=1e-8, restart=30, maxit=1000,
+                         block: int = 0):
         tx = np.ascontiguousarray(tx, dtype=np.int32)
         rx = np.ascontiguousarray(rx, dtype=np.int32)
         _dev_tensor(U, torch.complex128, self.ctx.device, "U")
         _dev_tensor(gS, torch.complex128, self.ctx.device, "gS")
         g = torch.empty(self.nt, dtype=torch.complex128, device=self.ctx.device)
-        o = _opts(tol, restart, maxit, 0)
+        o = _opts(tol, restart, maxit, 0, block)
         check(lib().mw_adjoint_gradient(self.h, tx.size, ptr(tx), rx.size, ptr(rx), ptr(U), ptr(gS), ptr(g),
                                         C.byref(o), None))
         return g
 
-    def misfit_gradient(self, tx, rx, S_meas: torch.Tensor, tol=1e-8, restart=30, maxit=1000):
+    def misfit_gradient(self, tx, rx, S_meas: torch.Tensor, tol=1e-8, restart=30, maxit=1000, block: int = 0):
         tx = np.ascontiguousarray(tx, dtype=np.int32)
         rx = np.ascontiguousarray(rx, dtype=np.int32)
         _dev_tensor(S_meas, torch.complex128, self.ctx.device, "S_meas")
         S = torch.empty((rx.size, tx.size), dtype=torch.complex128, device=self.ctx.device)
         g = torch.empty(self.nt, dtype=torch.complex128, device=self.ctx.device)
         J = C.c_double()
-        o = _opts(tol, restart, maxit, 0)
+        o = _opts(tol, restart, maxit, 0, block)
         check(lib().mw_misfit_gradient(self.h, tx.size, ptr(tx), rx.size, ptr(rx), ptr(S_meas), C.addressof(J),
                                        ptr(S), ptr(g), C.byref(o)))
         return J.value, S, g

@@ -124,3 +124,71 @@ def test_library_missing_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(binding, "_lib", None)
     with pytest.raises(binding.MwLibraryMissing):
         binding.lib()
+
+
+def _block_hessenberg(rng, steps, width=32):
+    """Random block upper Hessenberg matrix with upper-triangular
+    sub-diagonal blocks; columns and rows beyond `width` in every block are
+    padding (identity on the sub-diagonal, zero elsewhere) as the solver
+    builds them."""
+    q = 32
+    H = np.zeros(((steps + 1) * q, steps * q), dtype=np.complex128)
+    for j in range(steps):
+        for i in range(j + 1):
+            blk = rng.normal(size=(q, q)) + 1j * rng.normal(size=(q, q))
+            blk[width:, :] = 0
+            blk[:, width:] = 0
+            H[i * q:(i + 1) * q, j * q:(j + 1) * q] = blk
+        R = np.triu(rng.normal(size=(q, q)) + 1j * rng.normal(size=(q, q))) + 4 * np.eye(q)
+        R[width:, :] = 0
+        R[:, width:] = 0
+        R[np.arange(width, q), np.arange(width, q)] = 1
+        H[(j + 1) * q:(j + 2) * q, j * q:(j + 1) * q] = R
+    S0 = np.triu(rng.normal(size=(q, q)) + 1j * rng.normal(size=(q, q)))
+    S0[width:, :] = 0
+    S0[:, width:] = 0
+    S0[np.arange(width, q), np.arange(width, q)] = 1
+    return S0, H
+
+
+@pytest.mark.parametrize("width", [32, 7])
+def test_host_block_least_squares_matches_lstsq(L, width):
+    """The library's incremental Householder least squares of block GMRES
+    equals a dense least-squares solve after every block column."""
+    from paper_1607_02573_amd import binding
+    rng = np.random.default_rng(width)
+    steps = 4
+    S0, H = _block_hessenberg(rng, steps, width)
+    res, Y = binding.host_block_lstsq(S0, H, width)
+    q = 32
+    E = np.zeros(((steps + 1) * q, q), dtype=np.complex128)
+    E[:q] = S0
+    E[:, width:] = 0
+    for j in range(steps):
+        Hj = H[:(j + 2) * q, :(j + 1) * q]
+        Yj = np.linalg.lstsq(Hj, E[:(j + 2) * q], rcond=None)[0]
+        want = np.linalg.norm(E[:(j + 2) * q] - Hj @ Yj, axis=0)
+        np.testing.assert_allclose(res[j, :width], want[:width], rtol=1e-9, atol=1e-12 * np.abs(E).max())
+    np.testing.assert_allclose(Y[:, :width], Yj[:, :width], rtol=1e-9, atol=1e-10 * np.abs(Yj).max())
+
+
+def test_host_block_cholesky(L):
+    """Cholesky factor R^H R = G, and rank deficiency counted."""
+    from paper_1607_02573_amd import binding
+    rng = np.random.default_rng(3)
+    W = rng.normal(size=(200, 32)) + 1j * rng.normal(size=(200, 32))
+    G = W.conj().T @ W
+    R, nd = binding.host_block_cholesky(G, 1e-10)
+    assert nd == 0
+    np.testing.assert_allclose(np.triu(R), R)
+    np.testing.assert_allclose(R.conj().T @ R, G, rtol=1e-12, atol=1e-12 * np.abs(G).max())
+    # a column dependent up to 1e-9 (below the 1e-7 threshold, near the
+    # square root of the unit roundoff that a Gram-based factor resolves)
+    # counts as deficient; one 1e-5 away does not
+    W2 = W.copy()
+    W2[:, 5] = W[:, 2] + 1e-9 * np.linalg.norm(W[:, 2]) * W[:, 9] / np.linalg.norm(W[:, 9])
+    _, nd = binding.host_block_cholesky(W2.conj().T @ W2, 1e-7)
+    assert nd == 1
+    W2[:, 5] = W[:, 2] + 1e-5 * np.linalg.norm(W[:, 2]) * W[:, 9] / np.linalg.norm(W[:, 9])
+    _, nd = binding.host_block_cholesky(W2.conj().T @ W2, 1e-7)
+    assert nd == 0
