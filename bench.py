@@ -69,6 +69,8 @@ def make_workload(name: str):
         return mi.configs.chamber10()
     if name == "chamber05":
         return mi.configs.chamber05()
+    if name == "inversion05":
+        return mi.configs.inversion05()
     if name == "cube8":
         return mi.configs.cube8()
     raise SystemExit(f"unknown workload {name}")
@@ -207,6 +209,58 @@ def serve_main(args):
     ctx.close()
 
 
+def invert_main(args):
+    """The outer inversion loop (L-BFGS on the normalised, regularised misfit
+    over a vertex permittivity) on the workload: synthetic data from the
+    per-tetrahedron phantom with a 1 cm inclusion, S_empty from the
+    homogeneous gel, start from the gel; prints one JSON line."""
+    import torch
+
+    import mw_inputs as mi
+    from paper_1607_02573_amd import inversion, solver
+    w = make_workload(args.workload)
+    tx = w.tx if args.nrhs == 0 else w.tx[: args.nrhs]
+    rx = w.rx
+    eps_true = w.extra.get("eps_true") if w.extra else None
+    if eps_true is None:
+        eps_true = mi.fields.add_inclusion(w.mesh, w.eps)
+    total = torch.cuda.mem_get_info()[1]
+    ctx = solver.Context(0, budget_bytes=int(total - (24 << 30)))
+    P = solver.problem_from_workload(ctx, w)
+
+    def s_of(eps_t):
+        P.update_eps(torch.from_numpy(np.ascontiguousarray(eps_t)).cuda())
+        P.factor(w.part, w.n_sub, 1, "c64")
+        U, _ = P.solve(P.rhs_ports(tx), tol=1e-10, restart=args.restart, maxit=args.maxit)
+        S = P.s_matrix(U, rx).cpu().numpy()
+        del U
+        return S
+
+    log(f"[invert] {w.name}: data at the phantom with inclusion, S_empty at the homogeneous gel")
+    gel = 44 - 20j    # the matching medium that fills the empty chamber
+    S_mes = s_of(eps_true)
+    S_empty = s_of(np.full(w.mesh.nt, gel))
+    inv = inversion.Inversion(P, w.mesh.xyz, w.mesh.tet, w.part, w.n_sub, tx, rx, S_mes, S_empty, args.alpha,
+                              precision="c64", tol=args.tol, restart=args.restart, block=args.block)
+    e0 = np.full(w.mesh.xyz.shape[0], gel)
+    log(f"[invert] L-BFGS x{args.invert} from the gel")
+    torch.cuda.synchronize()
+    h = inv.run(e0, iters=args.invert, step0=args.step0)
+    line = {
+        "metric": "inversion: seconds per L-BFGS evaluation (factor + forward + adjoint solves), mixed precision",
+        "value": h.seconds / h.evaluations, "unit": "s", "higher_is_better": False, "n_gpus": 1,
+        "iterations": len(h.J) - 1, "evaluations": h.evaluations, "J": h.J, "seconds": h.seconds,
+        "rhs_solves_per_s": h.solve_columns / h.seconds,
+        "dtype": "c64 factors/TRSM (FP32 MFMA) + f64 GMRES", "data": "synthetic",
+        "config": {"workload": f"{w.name}: {P.n} unknowns, {len(tx)} ports, {w.n_sub} subdomains; vertex "
+                               f"permittivity ({w.mesh.xyz.shape[0]} vertices), defJ2 misfit, alpha {args.alpha:g}",
+                   "tol": args.tol, "restart": args.restart, "gmres": "block" if args.block else "pseudo-block"},
+    }
+    print(json.dumps(line), flush=True)
+    P.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +283,11 @@ def main():
                          "its latency line instead of the batch benchmark")
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--serve-rate", type=float, default=4.0)
+    ap.add_argument("--invert", type=int, default=0,
+                    help="run this many L-BFGS iterations of the outer inversion loop on the workload and print "
+                         "its line instead of the batch benchmark")
+    ap.add_argument("--alpha", type=float, default=1e-4, help="Tikhonov weight of the inversion loop")
+    ap.add_argument("--step0", type=float, default=0.5, help="largest vertex change of the first L-BFGS step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this library solves all subdomains "
@@ -243,6 +302,9 @@ def main():
     binding.lib()   # fails loudly if the HIP library is not built
     if args.serve:
         serve_main(args)
+        return
+    if args.invert:
+        invert_main(args)
         return
     if args.copy_probe_mib:
         src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
