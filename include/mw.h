@@ -60,6 +60,11 @@ typedef enum {
 } mw_status;
 
 typedef enum { MW_C128 = 0, MW_C64 = 1 } mw_precision;
+/* Subdomain factorisation: LU with partial pivoting, or L D L^T without
+ * interchanges for the complex-symmetric B_i (about half the work); AUTO takes
+ * L D L^T when every tetrahedron is lossy (Im eps_r < 0), which makes the
+ * imaginary part of every B_i positive definite, so no pivot can vanish. */
+typedef enum { MW_FACTOR_AUTO = 0, MW_FACTOR_LU = 1, MW_FACTOR_LDLT = 2 } mw_factorization;
 
 #define MW_TAG_PEC (-1)
 #define MW_TAG_IMPEDANCE 0
@@ -127,6 +132,7 @@ typedef struct {
   int32_t precision;
   int64_t factor_bytes;
   double t_assemble, t_decompose, t_factor; /* seconds of the last calls */
+  int32_t factorization; /* of the valid factors: MW_FACTOR_LU or MW_FACTOR_LDLT; 0 if none */
 } mw_problem_info;
 
 /* ---- context -------------------------------------------------------- */
@@ -177,11 +183,16 @@ mw_status mw_rhs_dipoles(mw_problem *p, int32_t np, const double *xyz, const dou
  * >= 1 layers of vertex-adjacent tetrahedra.  Builds R_i, the partition of
  * unity D_i (P1 chi_i at edge midpoints), the local matrices B_i with
  * impedance transmission conditions i k (E x n).(v x n) on the interfaces,
- * k = k0 sqrt(Re eps_r) of the owning tetrahedron, and factors every B_i by
- * dense LU with partial pivoting in `prec` (MW_C64: complex FP32 factors
- * and triangular solves; MW_C128: complex FP64). */
+ * k = k0 sqrt(Re eps_r) of the owning tetrahedron, and factors every B_i
+ * densely in `prec` (MW_C64: complex FP32 factors and triangular solves;
+ * MW_C128: complex FP64) by the factorisation mw_set_factorization selects
+ * (section 6 of the paper factors the B_i by a symmetric L D L^T). */
 mw_status mw_factor_subdomains(mw_problem *p, int32_t n_sub, int32_t overlap,
                                mw_precision prec, const int32_t *tet_part);
+/* kind: an mw_factorization value, used by the next mw_factor_subdomains
+ * (default MW_FACTOR_AUTO).  MW_FACTOR_LDLT on matrices whose pivots can
+ * vanish may end in MW_ESINGULAR. */
+mw_status mw_set_factorization(mw_problem *p, int32_t kind);
 /* Z = M^-1 V for nrhs columns (device n x nrhs). */
 mw_status mw_apply_preconditioner(mw_problem *p, int32_t nrhs, const void *V, void *Z);
 

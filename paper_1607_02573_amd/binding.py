@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libmw.so")
 
 MW_OK, MW_EINVAL, MW_ENOMEM, MW_ESINGULAR, MW_ENOCONV, MW_ENUMERIC, MW_EDEVICE = 0, -1, -2, -3, -4, -5, -6
 MW_C128, MW_C64 = 0, 1
+MW_FACTOR_AUTO, MW_FACTOR_LU, MW_FACTOR_LDLT = 0, 1, 2
 STATUS_NAMES = {0: "MW_OK", -1: "MW_EINVAL", -2: "MW_ENOMEM", -3: "MW_ESINGULAR", -4: "MW_ENOCONV",
                 -5: "MW_ENUMERIC", -6: "MW_EDEVICE"}
 
@@ -59,7 +60,7 @@ class mw_problem_info(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("n_edges", C.c_int64), ("nt", C.c_int32),
                 ("nports", C.c_int32), ("n_sub", C.c_int32), ("sum_ni", C.c_int64), ("max_ni", C.c_int32),
                 ("precision", C.c_int32), ("factor_bytes", C.c_int64), ("t_assemble", C.c_double),
-                ("t_decompose", C.c_double), ("t_factor", C.c_double)]
+                ("t_decompose", C.c_double), ("t_factor", C.c_double), ("factorization", C.c_int32)]
 
 
 class mw_batch_info(C.Structure):
@@ -106,6 +107,7 @@ _SIGS = {
     "mw_host_topology": [C.POINTER(mw_mesh), _P, _P, _P, _P, _P, _P],
     "mw_host_decomposition": [C.POINTER(mw_mesh), _P, _I, _I, _P, _P, _P, _P],
     "mw_host_block_lstsq": [_I, _I, _P, _P, C.c_double, _P, _P],
+    "mw_set_factorization": [_P, _I],
 }
 EXPORTED = list(_SIGS) + ["mw_last_error", "mw_host_last_error", "mw_timer_families", "mw_timer_name",
                           "mw_timer_enable", "mw_timer_reset"]

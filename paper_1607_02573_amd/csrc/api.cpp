@@ -129,6 +129,8 @@ struct mw_problem {
   DeviceDecomp dd;
   DevBuf F;
   int prec = -1;
+  int factor_kind = MW_FACTOR_AUTO;   // requested
+  int factorization = 0;              // used by the current factors (MW_FACTOR_LU / MW_FACTOR_LDLT)
   bool factors_valid = false;
   // workspaces of mw_solve / mw_apply_preconditioner, and of small index lists
   GmresWork ws;
@@ -1017,6 +1019,15 @@ mw_status mw_assemble(mw_ctx* ctx, const mw_mesh* mesh, const mw_complex* eps_r,
   });
 }
 
+mw_status mw_set_factorization(mw_problem* p, int32_t kind) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(kind == MW_FACTOR_AUTO || kind == MW_FACTOR_LU || kind == MW_FACTOR_LDLT, MW_EINVAL,
+             "unknown factorisation kind");
+    p->factor_kind = kind;
+  });
+}
+
 mw_status mw_update_eps(mw_problem* p, const void* eps_dev) {
   return guard([&] {
     check_prob(p);
@@ -1047,6 +1058,7 @@ mw_status mw_problem_get_info(mw_problem* p, mw_problem_info* info) {
       info->max_ni = *std::max_element(p->D.n_loc.begin(), p->D.n_loc.end());
     }
     info->precision = p->prec;
+    info->factorization = p->factors_valid ? p->factorization : 0;
     info->factor_bytes = (int64_t)p->F.bytes;
     info->t_assemble = p->t_assemble;
     info->t_decompose = p->t_decompose;
@@ -1161,13 +1173,23 @@ mw_status mw_factor_subdomains(mw_problem* p, int32_t n_sub, int32_t overlap, mw
     }
     p->prec = prec;
     hipStream_t st = p->stream;
+    bool sym = p->factor_kind == MW_FACTOR_LDLT;
+    if (p->factor_kind == MW_FACTOR_AUTO) {
+      double* dmax = (double*)p->w_small.get(c, 8);
+      double hmax = 0.0;
+      launch_max_imag(p->eps.as<double2>(), p->T.nt, dmax, st);
+      MW_HIP(hipMemcpyAsync(&hmax, dmax, 8, hipMemcpyDeviceToHost, st));
+      psync(p);
+      sym = hmax < 0.0;
+    }
+    p->factorization = sym ? MW_FACTOR_LDLT : MW_FACTOR_LU;
     launch_zero_bytes(p->dd.info, (int64_t)p->dd.nsub * 4, st);
     if (prec == MW_C64) {
       launch_fill_local<float2>(p->dm, p->dd, p->E.as<double2>(), p->eps.as<double2>(), p->k0, p->F.as<float2>(), st);
-      lu_factor_batched<float2>(p->dd, p->F.as<float2>(), st);
+      lu_factor_batched<float2>(p->dd, p->F.as<float2>(), st, sym);
     } else {
       launch_fill_local<double2>(p->dm, p->dd, p->E.as<double2>(), p->eps.as<double2>(), p->k0, p->F.as<double2>(), st);
-      lu_factor_batched<double2>(p->dd, p->F.as<double2>(), st);
+      lu_factor_batched<double2>(p->dd, p->F.as<double2>(), st, sym);
     }
     std::vector<int32_t> info(p->dd.nsub);
     MW_HIP(hipMemcpyAsync(info.data(), p->dd.info, info.size() * 4, hipMemcpyDeviceToHost, st));

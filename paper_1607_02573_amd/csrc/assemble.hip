@@ -502,4 +502,25 @@ void launch_gradient(const DeviceMesh& m, const double2* U, const double2* F, in
   MW_LAUNCH_CHECK();
 }
 
+// out[0] = max_t Im eps_t (one workgroup, fixed order): every B_i has a
+// positive definite imaginary part when it is negative (lossy media with the
+// e^{+i omega t} convention), which selects the symmetric factorisation.
+__global__ void __launch_bounds__(1024) k_max_imag(const double2* __restrict__ eps, int64_t nt,
+                                                   double* __restrict__ out) {
+  __shared__ double red[1024];
+  double m = -INFINITY;
+  for (int64_t t = threadIdx.x; t < nt; t += 1024) m = fmax(m, eps[t].y);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+void launch_max_imag(const double2* eps, int64_t nt, double* out, hipStream_t st) {
+  k_max_imag<<<1, 1024, 0, st>>>(eps, nt, out);
+  MW_LAUNCH_CHECK();
+}
+
 }  // namespace mw

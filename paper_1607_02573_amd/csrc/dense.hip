@@ -143,7 +143,8 @@ __device__ inline void gemm_tile(const typename cplx<R>::t* __restrict__ A, int6
 
 // LU-internal update of subdomain blockIdx.y:
 // F[r0:np, c0:min(c1,np)] -= F[r0:np, k0:k1] * F[k0:k1, c0:min(c1,np)]
-template <class R>
+// LOWER: only tiles on or below the diagonal (r0 == c0; symmetric factorisation)
+template <class R, bool LOWER = false>
 __global__ void __launch_bounds__(256) k_gemm_lu(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
                                                  const int32_t* __restrict__ n_pad, int r0, int k0, int k1,
                                                  int c0, int c1) {
@@ -156,6 +157,7 @@ __global__ void __launch_bounds__(256) k_gemm_lu(typename cplx<R>::t* F, const i
   int tiles_n = (N + TB - 1) / TB;
   int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
   if (tm * TB >= M) return;
+  if (LOWER && r0 + tm * TB + TB <= c0 + tn * TB) return;
   C* Fi = F + fac_off[i];
   gemm_tile<R, false>(Fi + (int64_t)r0 * np + k0, np, Fi + (int64_t)k0 * np + c0, np,
                       Fi + (int64_t)r0 * np + c0, np, M, N, k1 - k0, tm, tn);
@@ -484,7 +486,7 @@ __global__ void __launch_bounds__(256) k_leaf_x(const typename cplx<R>::t* F, co
 template <class R, int WC, bool G3>
 struct LuwTile { static constexpr int TM = 64; };
 
-template <class R, int WC, bool G3>
+template <class R, int WC, bool G3, bool LOWER = false>
 __global__ void __launch_bounds__(256, G3 ? 2 : 1) k_gemm_luw(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
                                                   const int32_t* __restrict__ n_pad, int r0, int r1, int k0, int k1,
                                                   int c0, int c1, int tiles_m, int tiles_n, int nsub) {
@@ -503,6 +505,7 @@ __global__ void __launch_bounds__(256, G3 ? 2 : 1) k_gemm_luw(typename cplx<R>::
   if (M <= 0 || N <= 0 || k1 > np) return;
   C* Fi = F + fac_off[i];
   const int row = r0 + tm * TM, col = c0 + tn * 32 * WC;
+  if (LOWER && row + TM <= col) return;   // strictly above the diagonal: not needed
   if constexpr (G3)
     gemm3m<R, WC, 2>(Fi + (int64_t)row * np + k0, np, Fi + (int64_t)k0 * np + col, np, Fi + (int64_t)row * np + col,
                   np, M, min(N, 32 * WC), k1 - k0);
@@ -511,15 +514,15 @@ __global__ void __launch_bounds__(256, G3 ? 2 : 1) k_gemm_luw(typename cplx<R>::
                      Fi + (int64_t)row * np + col, np, M, min(N, 32 * WC), k1 - k0);
 }
 
-template <class R, int WC, bool G3 = false>
+template <class R, int WC, bool G3 = false, bool LOWER = false>
 static void launch_gemm_lu(const DeviceDecomp& d, typename cplx<R>::t* F, int r0, int r1, int k0, int k1, int c0,
                            int c1, int maxp, hipStream_t st) {
   int tiles_m = (int)ceil_div(std::min(r1, maxp) - r0, LuwTile<R, WC, G3>::TM);
   int tiles_n = (int)ceil_div(std::min(c1, maxp) - c0, 32 * WC);
   if (tiles_m <= 0 || tiles_n <= 0 || k1 <= k0) return;
   int64_t G = round_up((int64_t)d.nsub * tiles_m * tiles_n, 8);
-  k_gemm_luw<R, WC, G3><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, r0, r1, k0, k1, c0, c1, tiles_m,
-                                                     tiles_n, d.nsub);
+  k_gemm_luw<R, WC, G3, LOWER><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, r0, r1, k0, k1, c0, c1,
+                                                            tiles_m, tiles_n, d.nsub);
   MW_LAUNCH_CHECK();
 }
 
@@ -557,7 +560,8 @@ __global__ void __launch_bounds__(256) k_amax(const typename cplx<R>::t* __restr
 // One workgroup per subdomain: factor columns [c, c+W0) of rows [c, np),
 // row interchanges across the 64-wide panel [k, k+NB), then the unit-lower
 // solve of rows [c, c+W0) for the panel columns [c+W0, k+NB).
-template <class R>
+// NOPIV: no interchanges (the diagonal entry is the pivot; symmetric factorisation).
+template <class R, bool NOPIV = false>
 __global__ void __launch_bounds__(256) k_lu_panel(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
                                                   const int32_t* __restrict__ n_pad,
                                                   const int64_t* __restrict__ loc_off, int32_t* ipiv,
@@ -575,20 +579,26 @@ __global__ void __launch_bounds__(256) k_lu_panel(typename cplx<R>::t* F, const 
   for (int j = 0; j < W0; ++j) {
     int col = c + j;
     Piv best{-1.0, 0x7fffffff};
-    for (int r = col + tid; r < np; r += 256) {
-      C v = Fi[(int64_t)r * np + col];
-      double a = fabs((double)v.x) + fabs((double)v.y);
-      if (a > best.v) { best.v = a; best.idx = r; }
+    if (NOPIV) {
+      C v = Fi[(int64_t)col * np + col];
+      best.v = fabs((double)v.x) + fabs((double)v.y);
+      best.idx = col;
+    } else {
+      for (int r = col + tid; r < np; r += 256) {
+        C v = Fi[(int64_t)r * np + col];
+        double a = fabs((double)v.x) + fabs((double)v.y);
+        if (a > best.v) { best.v = a; best.idx = r; }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        Piv o;
+        o.v = __shfl_xor(best.v, off);
+        o.idx = __shfl_xor(best.idx, off);
+        best = piv_max(best, o);
+      }
+      if (lane == 0) red[wave] = best;
+      __syncthreads();
+      best = piv_max(piv_max(red[0], red[1]), piv_max(red[2], red[3]));
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      Piv o;
-      o.v = __shfl_xor(best.v, off);
-      o.idx = __shfl_xor(best.idx, off);
-      best = piv_max(best, o);
-    }
-    if (lane == 0) red[wave] = best;
-    __syncthreads();
-    best = piv_max(piv_max(red[0], red[1]), piv_max(red[2], red[3]));
     int p = best.idx;
     // a pivot below rtol * max|B_i| marks B_i numerically singular; an exact
     // zero (or NaN) column is skipped without division
@@ -648,28 +658,35 @@ struct PanelRegArgs {
   double thr;        // rtol * max|B_i|
 };
 
-template <int J, int RPT>
+template <int J, int RPT, bool NOPIV>
 __device__ __forceinline__ void panel_reg_col(float2 (&v)[RPT][W0], const PanelRegArgs& g) {
   const int col = g.c + J, tid = g.tid;
   Piv best{-1.0, 0x7fffffff};
+  if (NOPIV) {
+    // the diagonal entry (row col: thread J, slot 0) is the pivot
+    if (tid == J) g.red[0] = Piv{fabs((double)v[0][J].x) + fabs((double)v[0][J].y), col};
+    __syncthreads();
+    best = g.red[0];
+  } else {
 #pragma unroll
-  for (int s = 0; s < RPT; ++s) {
-    const int row = g.c + tid + 1024 * s;
-    if (row >= col && row < g.np) {
-      const double a = fabs((double)v[s][J].x) + fabs((double)v[s][J].y);
-      if (a > best.v) { best.v = a; best.idx = row; }
+    for (int s = 0; s < RPT; ++s) {
+      const int row = g.c + tid + 1024 * s;
+      if (row >= col && row < g.np) {
+        const double a = fabs((double)v[s][J].x) + fabs((double)v[s][J].y);
+        if (a > best.v) { best.v = a; best.idx = row; }
+      }
     }
+    for (int off = 32; off > 0; off >>= 1) {
+      Piv o;
+      o.v = __shfl_xor(best.v, off);
+      o.idx = __shfl_xor(best.idx, off);
+      best = piv_max(best, o);
+    }
+    if ((tid & 63) == 0) g.red[tid >> 6] = best;
+    __syncthreads();
+    best = g.red[0];
+    for (int w = 1; w < 16; ++w) best = piv_max(best, g.red[w]);
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    Piv o;
-    o.v = __shfl_xor(best.v, off);
-    o.idx = __shfl_xor(best.idx, off);
-    best = piv_max(best, o);
-  }
-  if ((tid & 63) == 0) g.red[tid >> 6] = best;
-  __syncthreads();
-  best = g.red[0];
-  for (int w = 1; w < 16; ++w) best = piv_max(best, g.red[w]);
   int p = best.idx;
   const bool zero = !(best.v > 0.0);
   const bool tiny = !(best.v > g.thr);
@@ -728,7 +745,7 @@ __device__ __forceinline__ void panel_reg_col(float2 (&v)[RPT][W0], const PanelR
   __syncthreads();
 }
 
-template <int RPT>
+template <int RPT, bool NOPIV = false>
 __global__ void __launch_bounds__(1024) k_lu_panel_reg(float2* F, const int64_t* __restrict__ fac_off,
                                                        const int32_t* __restrict__ n_pad,
                                                        const int64_t* __restrict__ loc_off, int32_t* ipiv,
@@ -749,14 +766,14 @@ __global__ void __launch_bounds__(1024) k_lu_panel_reg(float2* F, const int64_t*
 #pragma unroll
     for (int q = 0; q < W0; ++q) v[s][q] = row < np ? g.Fi[(int64_t)row * np + c + q] : make_float2(0.f, 0.f);
   }
-  panel_reg_col<0, RPT>(v, g);
-  panel_reg_col<1, RPT>(v, g);
-  panel_reg_col<2, RPT>(v, g);
-  panel_reg_col<3, RPT>(v, g);
-  panel_reg_col<4, RPT>(v, g);
-  panel_reg_col<5, RPT>(v, g);
-  panel_reg_col<6, RPT>(v, g);
-  panel_reg_col<7, RPT>(v, g);
+  panel_reg_col<0, RPT, NOPIV>(v, g);
+  panel_reg_col<1, RPT, NOPIV>(v, g);
+  panel_reg_col<2, RPT, NOPIV>(v, g);
+  panel_reg_col<3, RPT, NOPIV>(v, g);
+  panel_reg_col<4, RPT, NOPIV>(v, g);
+  panel_reg_col<5, RPT, NOPIV>(v, g);
+  panel_reg_col<6, RPT, NOPIV>(v, g);
+  panel_reg_col<7, RPT, NOPIV>(v, g);
 #pragma unroll
   for (int s = 0; s < RPT; ++s) {
     const int row = c + g.tid + 1024 * s;
@@ -908,6 +925,35 @@ __global__ void __launch_bounds__(256) k_trsm_panel(typename cplx<R>::t* F, cons
   trsm_leaf<R, false>(Fi + (int64_t)k * np + k, np, Fi + (int64_t)k * np, np, cb, min(np, cb + PANEL_COLS), tri);
 }
 
+// Symmetric factorisation (B_i = L D L^T, B_i complex symmetric, no
+// interchanges): the rows [k, k+NB) of U = D L^T right of the panel are the
+// scaled transpose of the panel's L columns, U[r][j] = U[r][r] L[j][r] for
+// j >= k+NB, so they are written from the panel instead of being solved for
+// (and the trailing updates never need the part above the diagonal).  One
+// workgroup per 64 columns j, the 64 x 64 tile transposed through LDS.
+template <class R>
+__global__ void __launch_bounds__(256) k_sym_row(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
+                                                 const int32_t* __restrict__ n_pad, int k) {
+  using C = typename cplx<R>::t;
+  const int i = blockIdx.y;
+  const int np = n_pad[i];
+  const int jb = k + NB + blockIdx.x * NB;
+  if (jb >= np) return;
+  C* Fi = F + fac_off[i];
+  __shared__ C T[NB][NB + 1];
+  __shared__ C dg[NB];
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int jj = e / NB, rr = e % NB;
+    T[jj][rr] = Fi[(int64_t)(jb + jj) * np + k + rr];
+  }
+  if (threadIdx.x < NB) dg[threadIdx.x] = Fi[(int64_t)(k + threadIdx.x) * np + k + threadIdx.x];
+  __syncthreads();
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int rr = e / NB, jj = e % NB;
+    Fi[(int64_t)(k + rr) * np + jb + jj] = cmul(dg[rr], T[jj][rr]);
+  }
+}
+
 // Every 64 x 64 diagonal block of a factored B_i is replaced by the inverses of
 // its two triangles: L_bb^-1 (unit lower, strict part stored) and U_bb^-1
 // (upper with diagonal) share the block, so the leaf triangular solves become
@@ -970,7 +1016,7 @@ static void kt_account(const DeviceDecomp& d, int fam, hipStream_t st, F&& per_s
 static inline double clampd(double v) { return v > 0 ? v : 0; }
 
 template <class C>
-void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st) {
+void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st, bool sym) {
   using R = typename RealOf<C>::t;
   MW_CHECK(d.max_pad <= 8192, MW_EINVAL, "subdomain too large for the dense factorisation (n_i > 8192)");
   const int maxp = d.max_pad;
@@ -982,6 +1028,10 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st) {
   // NB2 columns; the rows of a panel beyond the outer block receive the
   // block's earlier panels just before their triangular solve; the trailing
   // matrix is updated once per outer block with K = NB2.
+  // sym (B_i complex symmetric with a definite imaginary part): L D L^T
+  // without interchanges in the same storage; the U rows of each panel come
+  // from its L columns (k_sym_row) and the updates skip the tiles above the
+  // diagonal, about half the work of LU.
   constexpr int WCL = sizeof(R) == 4 ? 5 : 2;
   for (int K0 = 0; K0 < maxp; K0 += NB2) {
     const int Kend = std::min(K0 + NB2, maxp);
@@ -990,12 +1040,22 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st) {
         kt_begin(KF_LU_PANEL, st);
         if constexpr (sizeof(R) == 4) {
           if (maxp - c <= 4096) {
-            k_lu_panel_reg<4><<<d.nsub, 1024, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, d.amax,
-                                                      rtol, c, k);
+            if (sym)
+              k_lu_panel_reg<4, true><<<d.nsub, 1024, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info,
+                                                              d.amax, rtol, c, k);
+            else
+              k_lu_panel_reg<4><<<d.nsub, 1024, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, d.amax,
+                                                        rtol, c, k);
+          } else if (sym) {
+            k_lu_panel<R, true><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, d.amax,
+                                                        rtol, c, k);
           } else {
             k_lu_panel<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, d.amax, rtol, c,
                                                   k);
           }
+        } else if (sym) {
+          k_lu_panel<R, true><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, d.amax, rtol,
+                                                      c, k);
         } else {
           k_lu_panel<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, d.amax, rtol, c, k);
         }
@@ -1016,6 +1076,34 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st) {
           }, (int)sizeof(C));
         }
       }
+      const int c0 = k + NB;
+      if (sym) {
+        // no interchanges; the U rows from the L columns; the tiles of the
+        // block below the diagonal
+        if (c0 >= maxp) continue;
+        kt_begin(KF_LU_OTHER, st);
+        k_sym_row<R><<<dim3((unsigned)ceil_div(maxp - c0, NB), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, k);
+        MW_LAUNCH_CHECK();
+        kt_account(d, KF_LU_OTHER, st, [&](int n, double& f, double& b) {
+          double N = clampd(n - c0);
+          f = 6.0 * NB * N;
+          b = 2.0 * NB * N;
+        }, (int)sizeof(C));
+        if (c0 < Kend) {
+          kt_begin(KF_LU_GEMM, st);
+          int M = maxp - c0, N = Kend - c0;
+          unsigned tiles = (unsigned)(ceil_div(M, TB) * ceil_div(N, TB));
+          k_gemm_lu<R, true><<<dim3(tiles, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, c0, k, k + NB, c0, Kend);
+          MW_LAUNCH_CHECK();
+          kt_account(d, KF_LU_GEMM, st, [&](int n, double& f, double& b) {
+            double M2 = clampd(n - c0), N2 = clampd(std::min(Kend, n) - c0), K = clampd(std::min(k + NB, n) - k);
+            double lower = N2 * M2 - N2 * (N2 - 1) / 2;
+            f = 8.0 * lower * K;
+            b = M2 * K + K * N2 + 2 * lower;
+          }, (int)sizeof(C));
+        }
+        continue;
+      }
       int ncol = maxp;  // upper bound of columns outside the panel
       kt_begin(KF_LU_OTHER, st);
       k_laswp<R><<<dim3((unsigned)ceil_div(ncol, 256), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off,
@@ -1023,7 +1111,6 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st) {
       MW_LAUNCH_CHECK();
       kt_account(d, KF_LU_OTHER, st, [&](int n, double& f, double& b) { f = 0; b = n > k ? 2.0 * NB * n : 0; },
                  (int)sizeof(C));
-      const int c0 = k + NB;
       if (c0 >= maxp) continue;
       if (k > K0 && Kend < maxp) {
         // rows [k, k+NB) beyond the outer block: the block's panels [K0, k)
@@ -1061,11 +1148,13 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st) {
     if (Kend < maxp) {
       // trailing matrix: rows and columns [Kend, np), K = [K0, Kend)
       kt_begin(KF_LU_GEMM, st);
-      launch_gemm_lu<R, WCL, true>(d, F, Kend, maxp, K0, Kend, Kend, maxp, maxp, st);
+      if (sym) launch_gemm_lu<R, WCL, true, true>(d, F, Kend, maxp, K0, Kend, Kend, maxp, maxp, st);
+      else launch_gemm_lu<R, WCL, true>(d, F, Kend, maxp, K0, Kend, Kend, maxp, maxp, st);
       kt_account(d, KF_LU_GEMM, st, [&](int n, double& f, double& b) {
         double M2 = clampd(n - Kend), K = clampd(std::min(Kend, n) - K0);
-        f = 8.0 * M2 * M2 * K;
-        b = M2 * K + K * M2 + 2 * M2 * M2;
+        double C2 = sym ? M2 * (M2 + 1) / 2 : M2 * M2;   // entries updated
+        f = 8.0 * C2 * K;
+        b = M2 * K + K * M2 + 2 * C2;
       }, (int)sizeof(C));
     }
   }
@@ -1215,8 +1304,8 @@ void lu_solve_batched(const DeviceDecomp& d, const C* F, C* Y, int ncols, int64_
   bwd_rec<R>(d, F, Y, ncols, ld, 0, nblk, st);
 }
 
-template void lu_factor_batched<float2>(const DeviceDecomp&, float2*, hipStream_t);
-template void lu_factor_batched<double2>(const DeviceDecomp&, double2*, hipStream_t);
+template void lu_factor_batched<float2>(const DeviceDecomp&, float2*, hipStream_t, bool);
+template void lu_factor_batched<double2>(const DeviceDecomp&, double2*, hipStream_t, bool);
 template void lu_solve_batched<float2>(const DeviceDecomp&, const float2*, float2*, int, int64_t, hipStream_t);
 template void lu_solve_batched<double2>(const DeviceDecomp&, const double2*, double2*, int, int64_t, hipStream_t);
 

@@ -106,11 +106,14 @@ void launch_adjoint_rhs(const DevicePorts& P, int nrx, const int32_t* rx_dev, in
 void launch_gradient(const DeviceMesh& m, const double2* U, const double2* F, int64_t ld, int ncol, double k0,
                      double2* grad, hipStream_t st);
 
+void launch_max_imag(const double2* eps, int64_t nt, double* out, hipStream_t st);
+
 // ---- dense subdomain algebra (dense.hip)
-// Factor every B_i in place: P_i B_i = L_i U_i (partial pivoting, unit L),
-// then build the pivoted restriction index.  C = float2 or double2.
+// Factor every B_i in place: P_i B_i = L_i U_i (partial pivoting, unit L), or
+// with sym B_i = L_i U_i, U_i = D_i L_i^T (no interchanges), then build the
+// pivoted restriction index.  C = float2 or double2.
 template <class C>
-void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st);
+void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st, bool sym);
 // Y_i = U_i^-1 L_i^-1 Y_i in place on the local multi-vector (rows
 // loc_off[i] .. +n_pad[i], ncols columns, leading dimension ld).
 template <class C>

@@ -140,6 +140,11 @@ class Problem:
         return nu[: self.nports]
 
     # ------------------------------------------------------------------ preconditioner
+    def set_factorization(self, kind: str):
+        """'auto' (L D L^T when every tetrahedron is lossy, else LU), 'lu' or 'ldlt'."""
+        k = {"auto": B.MW_FACTOR_AUTO, "lu": B.MW_FACTOR_LU, "ldlt": B.MW_FACTOR_LDLT}[kind]
+        check(lib().mw_set_factorization(self.h, k))
+
     def factor(self, part, n_sub: int, overlap: int = 1, precision: str = "c128"):
         part = np.ascontiguousarray(part, dtype=np.int32)
         prec = {"c128": B.MW_C128, "c64": B.MW_C64}[precision]
