@@ -44,8 +44,8 @@ FP64_MFMA_FAMILIES = ("bgs_dots", "bgs_update")
 # known size (--copy-probe-mib).  Valid only for the kernel source it was
 # taken on: a different hash of that file reports null.
 PMC_TRAFFIC = {"family": "trsm_gemm", "source": "paper_1607_02573_amd/csrc/dense.hip",
-               "sha256": "f80cc64a6259f42437fa3df56be9ad11227ee2e9e7b221d270ea4b51233fe5be",
-               "bytes_per_launch": 1.7817e9}   # FETCH 1.5213e9 + WRITE 2.604e8 (pmc_trsm_gemm_chamber10_mixed)
+               "sha256": "65806afbf1943c6cb90f7f99c91df4b8156b3ca4086d80a997f46ead8426482a",
+               "bytes_per_launch": 1.7819e9}   # FETCH 1.5216e9 + WRITE 2.604e8 (pmc_trsm_gemm_chamber10_mixed)
 
 
 def measured_traffic(family: str):
@@ -241,7 +241,8 @@ def invert_main(args):
     S_mes = s_of(eps_true)
     S_empty = s_of(np.full(w.mesh.nt, gel))
     inv = inversion.Inversion(P, w.mesh.xyz, w.mesh.tet, w.part, w.n_sub, tx, rx, S_mes, S_empty, args.alpha,
-                              precision="c64", tol=args.tol, restart=args.restart, block=args.block)
+                              precision="c64", tol=args.tol, restart=args.restart, block=args.block,
+                              recycle=not args.no_recycle)
     e0 = np.full(w.mesh.xyz.shape[0], gel)
     log(f"[invert] L-BFGS x{args.invert} from the gel")
     torch.cuda.synchronize()
@@ -251,6 +252,7 @@ def invert_main(args):
         "value": h.seconds / h.evaluations, "unit": "s", "higher_is_better": False, "n_gpus": 1,
         "iterations": len(h.J) - 1, "evaluations": h.evaluations, "J": h.J, "seconds": h.seconds,
         "rhs_solves_per_s": h.solve_columns / h.seconds,
+        "gmres_iters_per_evaluation": h.iters, "recycle": inv.recycle,
         "dtype": "c64 factors/TRSM (FP32 MFMA) + f64 GMRES", "data": "synthetic",
         "config": {"workload": f"{w.name}: {P.n} unknowns, {len(tx)} ports, {w.n_sub} subdomains; vertex "
                                f"permittivity ({w.mesh.xyz.shape[0]} vertices), defJ2 misfit, alpha {args.alpha:g}",
@@ -288,6 +290,8 @@ def main():
                          "its line instead of the batch benchmark")
     ap.add_argument("--alpha", type=float, default=1e-4, help="Tikhonov weight of the inversion loop")
     ap.add_argument("--step0", type=float, default=0.5, help="largest vertex change of the first L-BFGS step")
+    ap.add_argument("--no-recycle", action="store_true",
+                    help="inversion loop: start every solve from zero instead of the previous fields")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this library solves all subdomains "

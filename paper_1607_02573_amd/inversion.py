@@ -14,7 +14,12 @@ Every evaluation of J and its gradient runs on the device through the C ABI:
 the permittivity update and subdomain factorisation (mw_update_eps,
 mw_factor_subdomains), the forward solves of all transmitting ports and the
 S-matrix (mw_solve, mw_s_matrix), and one adjoint solve with the same factors
-plus the per-tetrahedron gradient (mw_adjoint_gradient).  The optimiser's
+plus the per-tetrahedron gradient (mw_adjoint_rhs, mw_solve, mw_gradient).
+With `recycle`, the forward and adjoint fields of the previous evaluation are
+the initial guesses of the next one (the permittivity moves little between
+evaluations, so GMRES starts from a small residual; the stopping test stays
+relative to ||b||) -- the simplest form of the Krylov-information reuse
+across inversion iterations that the paper's conclusion proposes.  The optimiser's
 vector algebra, the vertex/tetrahedron maps and the Tikhonov product (one
 sparse product over the vertices) run on the host, between evaluations.
 """
@@ -61,12 +66,13 @@ class History:
     evaluations: int = 0
     seconds: float = 0.0
     solve_columns: int = 0                       # forward + adjoint right-hand sides solved
+    iters: list = field(default_factory=list)    # (forward, adjoint) mean GMRES iterations per evaluation
 
 
 class Inversion:
     def __init__(self, problem, xyz, tet, part, n_sub: int, tx, rx, S_mes: np.ndarray, S_empty: np.ndarray,
                  alpha: float, precision: str = "c64", tol: float = 1e-8, restart: int = 30, block: int = 0,
-                 overlap: int = 1):
+                 overlap: int = 1, recycle: bool = True):
         self.P = problem
         self.tet = np.ascontiguousarray(tet)
         self.nv = xyz.shape[0]
@@ -82,6 +88,8 @@ class Inversion:
         self.avg = vertex_average_matrix(self.tet, self.nv)
         self.K1 = p1_stiffness(np.asarray(xyz, dtype=np.float64), self.tet)
         self.dev = problem.ctx.device
+        self.recycle = recycle
+        self._U = self._F = None
         self.history = History()
 
     def objective(self, eps_v: np.ndarray):
@@ -90,13 +98,18 @@ class Inversion:
         eps_t = torch.from_numpy(np.ascontiguousarray(self.avg @ eps_v)).to(self.dev)
         P.update_eps(eps_t)
         P.factor(self.part, self.n_sub, self.overlap, self.precision)
-        U, info = P.solve(P.rhs_ports(self.tx), tol=self.tol, restart=self.restart, block=self.block)
+        U, info = P.solve(P.rhs_ports(self.tx), tol=self.tol, restart=self.restart, block=self.block,
+                          x0=self._U if self.recycle else None)
         S = P.s_matrix(U, self.rx).cpu().numpy()
         r = S - self.S_mes
         J_data = 0.5 * float(np.sum(self.weight * np.abs(r) ** 2))
         gS = torch.from_numpy(np.ascontiguousarray(self.weight * r)).to(self.dev)
-        g_t = P.adjoint_gradient(U, gS, self.tx, self.rx, tol=self.tol, restart=self.restart,
-                                 block=self.block).cpu().numpy()
+        F, info_a = P.solve(P.adjoint_rhs(gS, self.rx), tol=self.tol, restart=self.restart, block=self.block,
+                            x0=self._F if self.recycle else None)
+        g_t = P.gradient(U, F).cpu().numpy()
+        if self.recycle:
+            self._U, self._F = U, F
+        self.history.iters.append((float(info.iters.mean()), float(info_a.iters.mean())))
         kr, ki = self.K1 @ eps_v.real, self.K1 @ eps_v.imag
         J = J_data + 0.5 * self.alpha * float(eps_v.real @ kr + eps_v.imag @ ki)
         g = self.avg.T @ g_t + self.alpha * (kr + 1j * ki)

@@ -36,15 +36,19 @@ def setup():
     return w, ports, S_mes, S_empty, e_gel, es, Js, nev
 
 
+@pytest.mark.parametrize("recycle", [False, True])
 @pytest.mark.parametrize("prec,tol,rtol", [("c128", 1e-11, 1e-7), ("c64", 1e-10, 1e-6)])
-def test_lbfgs_on_gpu_matches_oracle(setup, prec, tol, rtol):
+def test_lbfgs_on_gpu_matches_oracle(setup, prec, tol, rtol, recycle):
     from paper_1607_02573_amd import inversion, solver
     w, ports, S_mes, S_empty, e_gel, es, Js, nev = setup
     ctx = solver.Context(0)
     Pg = solver.problem_from_workload(ctx, w)
     inv = inversion.Inversion(Pg, w.mesh.xyz, w.mesh.tet, w.part, w.n_sub, ports, ports, S_mes, S_empty, 1e-4,
-                              precision=prec, tol=tol)
+                              precision=prec, tol=tol, recycle=recycle)
     h = inv.run(e_gel, iters=3, step0=0.5)
+    if recycle:
+        # later evaluations start from the previous fields: fewer iterations
+        assert sum(f + a for f, a in h.iters[1:]) < sum(f + a for f, a in h.iters[:1]) * (len(h.iters) - 1)
     assert h.evaluations == nev
     assert len(h.J) == len(Js) == 4
     np.testing.assert_allclose(h.J, Js, rtol=rtol)
