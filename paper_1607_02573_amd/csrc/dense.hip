@@ -925,6 +925,104 @@ __global__ void __launch_bounds__(256) k_trsm_panel(typename cplx<R>::t* F, cons
   trsm_leaf<R, false>(Fi + (int64_t)k * np + k, np, Fi + (int64_t)k * np, np, cb, min(np, cb + PANEL_COLS), tri);
 }
 
+// Symmetric factorisation, panel [k, k+NB) without interchanges: with no
+// pivot search the panel is a diagonal block and an independent triangular
+// solve per row block.  k_sym_diag (one workgroup per subdomain) factors the
+// 64 x 64 diagonal block A_kk = L_kk U_kk in LDS (the singular-pivot test of
+// the LU panels), writes both triangles back, sets the identity interchanges,
+// and leaves U_kk^-1 in the block right of it (rows [k, k+NB), columns
+// [k+NB, k+2NB): the future U row, overwritten afterwards by k_sym_row).
+template <class R>
+__global__ void __launch_bounds__(256) k_sym_diag(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
+                                                  const int32_t* __restrict__ n_pad,
+                                                  const int64_t* __restrict__ loc_off, int32_t* ipiv,
+                                                  int32_t* info, const double* __restrict__ amax, double rtol,
+                                                  int k) {
+  using C = typename cplx<R>::t;
+  const int i = blockIdx.x;
+  const int np = n_pad[i];
+  if (k >= np) return;
+  C* Fi = F + fac_off[i];
+  __shared__ C T[NB][NB + 1];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < NB * NB; e += 256) T[e / NB][e % NB] = Fi[(int64_t)(k + e / NB) * np + k + e % NB];
+  __syncthreads();
+  const double thr = rtol * amax[i];
+  for (int j = 0; j < NB; ++j) {
+    const C pv = T[j][j];
+    const double a = fabs((double)pv.x) + fabs((double)pv.y);
+    const bool zero = !(a > 0.0);
+    if (tid == 0 && !(a > thr) && bad == 0) bad = k + j + 1;
+    const C inv = zero ? cmk<C>(0, 0) : cinv(pv);
+    // column j of L below the pivot (each thread its own rows), then the
+    // rank-1 update of the trailing block
+    for (int r = j + 1 + tid; r < NB; r += 256) T[r][j] = cmul(T[r][j], inv);
+    __syncthreads();
+    const int m = NB - 1 - j;
+    for (int e = tid; e < m * m; e += 256) {
+      const int r = j + 1 + e / m, c = j + 1 + e % m;
+      T[r][c] = csub(T[r][c], cmul(T[r][j], T[j][c]));
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < NB * NB; e += 256) Fi[(int64_t)(k + e / NB) * np + k + e % NB] = T[e / NB][e % NB];
+  if (tid < NB) ipiv[loc_off[i] + k + tid] = k + tid;
+  if (tid == 0 && bad && info[i] == 0) info[i] = bad;
+  if (k + 2 * NB > np) return;
+  __syncthreads();
+  // U_kk^-1 (upper triangular), one column per thread, by back substitution
+  __shared__ C X[NB][NB + 1];
+  if (tid < NB) {
+    const int c = tid;
+    for (int r = NB - 1; r >= 0; --r) {
+      C v = cmk<C>(0, 0);
+      if (r <= c) {
+        v = cmk<C>(r == c ? 1 : 0, 0);
+        for (int l = r + 1; l <= c; ++l) v = csub(v, cmul(T[r][l], X[l][c]));
+        const C d = T[r][r];
+        v = (fabs((double)d.x) + fabs((double)d.y) > 0.0) ? cmul(v, cinv(d)) : cmk<C>(0, 0);
+      }
+      X[r][c] = v;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < NB * NB; e += 256) Fi[(int64_t)(k + e / NB) * np + k + NB + e % NB] = X[e / NB][e % NB];
+}
+
+// L_rk = A_rk U_kk^-1 for one 64-row block r of the panel below the diagonal
+// block (U_kk^-1 read from where k_sym_diag left it).
+template <class R>
+__global__ void __launch_bounds__(256) k_sym_cols(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
+                                                  const int32_t* __restrict__ n_pad, int k) {
+  using C = typename cplx<R>::t;
+  const int i = blockIdx.y;
+  const int np = n_pad[i];
+  const int rb = k + NB + blockIdx.x * NB;
+  if (rb >= np) return;
+  C* Fi = F + fac_off[i];
+  __shared__ C A[NB][NB + 1];
+  __shared__ C U[NB][NB + 1];
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    A[e / NB][e % NB] = Fi[(int64_t)(rb + e / NB) * np + k + e % NB];
+    U[e / NB][e % NB] = Fi[(int64_t)(k + e / NB) * np + k + NB + e % NB];
+  }
+  __syncthreads();
+  const int r = threadIdx.x >> 2, cg = threadIdx.x & 3;
+  C acc[NB / 4];
+#pragma unroll
+  for (int u = 0; u < NB / 4; ++u) acc[u] = cmk<C>(0, 0);
+#pragma unroll 4
+  for (int l = 0; l < NB; ++l) {
+    const C a = A[r][l];
+#pragma unroll
+    for (int u = 0; u < NB / 4; ++u) acc[u] = cadd(acc[u], cmul(a, U[l][cg + 4 * u]));
+  }
+#pragma unroll
+  for (int u = 0; u < NB / 4; ++u) Fi[(int64_t)(rb + r) * np + k + cg + 4 * u] = acc[u];
+}
+
 // Symmetric factorisation (B_i = L D L^T, B_i complex symmetric, no
 // interchanges): the rows [k, k+NB) of U = D L^T right of the panel are the
 // scaled transpose of the panel's L columns, U[r][j] = U[r][r] L[j][r] for
@@ -1036,7 +1134,22 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st, bool sym) {
   for (int K0 = 0; K0 < maxp; K0 += NB2) {
     const int Kend = std::min(K0 + NB2, maxp);
     for (int k = K0; k < Kend; k += NB) {
-      for (int c = k; c < k + NB; c += W0) {
+      if (sym) {
+        kt_begin(KF_LU_PANEL, st);
+        k_sym_diag<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, d.amax, rtol, k);
+        MW_LAUNCH_CHECK();
+        if (k + NB < maxp) {
+          k_sym_cols<R><<<dim3((unsigned)ceil_div(maxp - k - NB, NB), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad,
+                                                                                             k);
+          MW_LAUNCH_CHECK();
+        }
+        kt_account(d, KF_LU_PANEL, st, [&](int n, double& f, double& b) {
+          double rows = clampd(n - k - NB);
+          f = n > k ? 8.0 * (NB * NB * NB / 3.0 + rows * NB * NB / 2.0) : 0;
+          b = n > k ? 2.0 * (NB + rows) * NB : 0;
+        }, (int)sizeof(C));
+      }
+      for (int c = k; c < k + NB && !sym; c += W0) {
         kt_begin(KF_LU_PANEL, st);
         if constexpr (sizeof(R) == 4) {
           if (maxp - c <= 4096) {
