@@ -79,3 +79,11 @@ def test_automatic_choice():
     assert P.info().factorization == 1
     P.close()
     ctx.close()
+
+
+def test_refused_factorisation_kind(chamber):
+    from paper_1607_02573_amd import binding
+    w, fp, P = chamber
+    with pytest.raises(binding.MwError) as e:
+        binding.check(binding.lib().mw_set_factorization(P.h, 7))
+    assert e.value.code == binding.MW_EINVAL

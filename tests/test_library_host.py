@@ -116,6 +116,14 @@ def test_host_error_paths(L):
     with pytest.raises(binding.MwError) as e:
         binding.host_decomposition(m.xyz, m.tet, m.bface, m.btag, part, 2, 1)   # part 1 empty
     assert e.value.code == binding.MW_EINVAL
+    # block least squares: width outside [1, 32], or no S0 with steps > 0
+    H = np.zeros((64, 32), dtype=np.complex128)
+    with pytest.raises(binding.MwError) as e:
+        binding.host_block_lstsq(np.eye(32), H, width=33)
+    assert e.value.code == binding.MW_EINVAL
+    with pytest.raises(binding.MwError) as e:
+        binding.check(L.mw_host_block_lstsq(1, 32, None, binding.ptr(H), 0.0, None, None), True)
+    assert e.value.code == binding.MW_EINVAL
 
 
 def test_library_missing_fails_loudly(tmp_path, monkeypatch):
