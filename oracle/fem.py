@@ -28,6 +28,7 @@ the 2-D Whitney functions built from the surface gradients of the face.
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass
 
 import numpy as np
@@ -108,6 +109,38 @@ def element_matrices(xyz: np.ndarray, tet: np.ndarray):
                           - mm[pb, qc] * gg[:, pa, qd] + mm[pb, qd] * gg[:, pa, qc])
     M *= vol[:, None, None]
     return K, M
+
+
+def cubic_bary_weights() -> np.ndarray:
+    """W3[v, x, y] = int_T l_v l_x l_y / vol: 3! prod(m_i!) / 6! over the
+    multiplicities m_i of the indices (1/120 all different, 1/60 two equal,
+    1/20 all equal)."""
+    W = np.zeros((4, 4, 4))
+    for v in range(4):
+        for x in range(4):
+            for y in range(4):
+                m = np.bincount([v, x, y], minlength=4)
+                W[v, x, y] = 6.0 * np.prod([math.factorial(int(k)) for k in m]) / 720.0
+    return W
+
+
+def element_mass_p1(xyz: np.ndarray, tet: np.ndarray) -> np.ndarray:
+    """M1[t, v] = int_t l_v N_p . N_q (6 x 6 per vertex v): the mass matrix of a
+    coefficient that is linear on the tetrahedron, sum_v kappa_v M1[t, v]
+    (Section 6 discretises kappa with P1 elements).  Sum over v = M_t."""
+    _, g, vol = tet_geometry(xyz, tet)
+    a, b = TET_EDGES[:, 0], TET_EDGES[:, 1]
+    gg = np.einsum("tik,tjk->tij", g, g)
+    W = cubic_bary_weights()
+    M1 = np.zeros((tet.shape[0], 4, 6, 6))
+    for v in range(4):
+        for p in range(6):
+            pa, pb = a[p], b[p]
+            for q in range(6):
+                qc, qd = a[q], b[q]
+                M1[:, v, p, q] = (W[v, pa, qc] * gg[:, pb, qd] - W[v, pa, qd] * gg[:, pb, qc]
+                                  - W[v, pb, qc] * gg[:, pa, qd] + W[v, pb, qd] * gg[:, pa, qc])
+    return M1 * vol[:, None, None, None]
 
 
 def face_geometry(xyz: np.ndarray, faces: np.ndarray):
@@ -220,6 +253,20 @@ def with_eps(fp: FEProblem, eps) -> FEProblem:
     A = assemble_matrix(fp.tet, fp.t2e, fp.K, fp.M, eps, fp.k0, fp.bf2e, fp.bf_beta, fp.MF,
                         fp.dof, fp.n)
     return FEProblem(**{**fp.__dict__, "eps": eps, "A": A})
+
+
+def with_eps_vertex(fp: FEProblem, eps_v, M1: np.ndarray | None = None) -> FEProblem:
+    """The operator with eps_r linear on every tetrahedron, given at the
+    vertices: sum_t K_t - k0^2 sum_v eps_v M1[t, v] + boundary terms.  The
+    problem's eps becomes the tetrahedron means (used by the transmission
+    wavenumber of the preconditioner)."""
+    eps_v = np.asarray(eps_v, dtype=np.complex128)
+    if M1 is None:
+        M1 = element_mass_p1(fp.xyz, fp.tet)
+    Meps = np.einsum("tv,tvpq->tpq", eps_v[fp.tet], M1)
+    A = assemble_matrix(fp.tet, fp.t2e, fp.K, Meps, np.ones(fp.tet.shape[0], dtype=np.complex128), fp.k0,
+                        fp.bf2e, fp.bf_beta, fp.MF, fp.dof, fp.n)
+    return FEProblem(**{**fp.__dict__, "eps": eps_v[fp.tet].mean(axis=1), "A": A})
 
 
 # ---------------------------------------------------------------- sources

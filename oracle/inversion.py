@@ -4,9 +4,10 @@ TEST INFRASTRUCTURE ONLY (see oracle/fem.py).
 
   * Unknown: the relative permittivity at the mesh vertices (P1), as the
     paper's kappa = k0^2 eps_r is discretised with P1 elements in its
-    reconstructions (Section 6).  The Maxwell operator uses on every
-    tetrahedron the mean of its four vertex values (one-point quadrature of
-    the coefficient in the mass term).
+    reconstructions (Section 6).  The Maxwell operator takes either, on every
+    tetrahedron, the mean of its four vertex values (one-point quadrature of
+    the coefficient in the mass term), or with `p1` the linear coefficient
+    integrated exactly: sum_v eps_v int_t l_v N_p . N_q (fem.element_mass_p1).
   * Misfit, equation (defJ2): each pair (i, j) normalised by the empty-chamber
     coefficient, plus a Tikhonov term on the gradient of the parameter,
         J = 1/2 sum_ij |S_ij - Smes_ij|^2 / |Sempty_ij|^2
@@ -17,7 +18,8 @@ TEST INFRASTRUCTURE ONLY (see oracle/fem.py).
   * Gradient (dJ/dRe + i dJ/dIm at each vertex): the adjoint gradient per
     tetrahedron of the data term (Section 5, the adjoint problem (pbadj) with
     data weighted by 1/|Sempty_ij|^2), mapped to the vertices by the transpose
-    of the averaging, plus alpha K1 e.
+    of the averaging, plus alpha K1 e; with `p1`, vertex v collects
+    conj(k0^2 sum_j f_j|_t^T M1[t, v] u_j|_t) over its tetrahedra.
   * Optimiser: L-BFGS, the two-loop recursion (Nocedal and Wright, Numerical
     Optimization, 2nd ed., Algorithms 7.4 and 7.5) on x = [Re e; Im e] with
     memory `mem`, H0 = (s^T y / y^T y) I from the latest pair, and a
@@ -59,8 +61,9 @@ def stiffness_p1(xyz: np.ndarray, tet: np.ndarray) -> sp.csr_matrix:
 class Objective:
     """J (equation defJ2) and its vertex gradient, every solve by sparse LU."""
 
-    def __init__(self, fp: fem.FEProblem, ports, tx, rx, Smes, Sempty, alpha: float):
+    def __init__(self, fp: fem.FEProblem, ports, tx, rx, Smes, Sempty, alpha: float, p1: bool = False):
         self.fp, self.ports = fp, ports
+        self.M1 = fem.element_mass_p1(fp.xyz, fp.tet) if p1 else None
         self.tx, self.rx = np.asarray(tx), np.asarray(rx)
         self.Smes = Smes
         self.w = 1.0 / np.abs(Sempty) ** 2
@@ -71,18 +74,32 @@ class Objective:
         self.evals = 0
 
     def __call__(self, ev: np.ndarray):
-        fp = fem.with_eps(self.fp, vertex_mean(self.fp.tet, ev))
+        nv = self.fp.xyz.shape[0]
+        if self.M1 is not None:
+            fp = fem.with_eps_vertex(self.fp, ev, self.M1)
+        else:
+            fp = fem.with_eps(self.fp, vertex_mean(self.fp.tet, ev))
         lu = spla.splu(fp.A.tocsc())
         U = lu.solve(self.B)
         S = inverse.s_matrix(self.P, self.nu, U, self.rx)
         r = S - self.Smes
         Jd = 0.5 * float(np.sum(self.w * np.abs(r) ** 2))
         # adjoint with the weighted residual: d(Jd) = Re sum conj(w r) dS
-        _, _, gt = inverse.adjoint_gradient(fp, lu, self.P, self.nu, U, self.tx, self.rx,
-                                            S - self.w * r)
+        if self.M1 is not None:
+            Lam = (self.P[:, self.rx] / self.nu[self.rx][None, :]) @ (self.w * r)
+            F = lu.solve(Lam)
+            ut, ft = inverse.local_values(fp, U), inverse.local_values(fp, F)
+            G = (fp.k0 ** 2) * np.einsum("tpj,tvpq,tqj->tv", ft, self.M1, ut)
+            gd = np.zeros(nv, dtype=np.complex128)
+            np.add.at(gd, self.fp.tet.ravel(), G.ravel())
+            gd = np.conj(gd)
+        else:
+            _, _, gt = inverse.adjoint_gradient(fp, lu, self.P, self.nu, U, self.tx, self.rx,
+                                                S - self.w * r)
+            gd = vertex_mean_adjoint(self.fp.tet, nv, gt)
         Kr, Ki = self.K1 @ ev.real, self.K1 @ ev.imag
         Jr = 0.5 * self.alpha * float(ev.real @ Kr + ev.imag @ Ki)
-        g = vertex_mean_adjoint(self.fp.tet, self.fp.xyz.shape[0], gt) + self.alpha * (Kr + 1j * Ki)
+        g = gd + self.alpha * (Kr + 1j * Ki)
         self.evals += 1
         return Jd + Jr, g, S
 

@@ -55,6 +55,33 @@ def test_mass_matrix_matches_quadrature():
         np.testing.assert_allclose(M[0], Mq, rtol=1e-12, atol=1e-12 * np.abs(Mq).max())
 
 
+def test_p1_coefficient_mass_matches_cubic_quadrature():
+    """int_t l_v N_p . N_q (degree 3) by the 5-point degree-3 rule with
+    independently built Whitney functions; and sum_v over the four vertex
+    matrices gives the plain mass matrix (the l_v sum to one)."""
+    for _ in range(5):
+        P = random_tet()
+        vol = abs(np.linalg.det(np.c_[np.ones(4), P])) / 6
+        Mq = np.zeros((4, 6, 6))
+        for lam, wq in zip(TET_Q3_PTS, TET_Q3_W):
+            N = whitney_at(P, lam)
+            for v in range(4):
+                Mq[v] += vol * wq * lam[v] * (N @ N.T)
+        M1 = fem.element_mass_p1(P, np.array([[0, 1, 2, 3]]))[0]
+        np.testing.assert_allclose(M1, Mq, rtol=1e-11, atol=1e-12 * np.abs(Mq).max())
+        _, M = fem.element_matrices(P, np.array([[0, 1, 2, 3]]))
+        np.testing.assert_allclose(M1.sum(axis=0), M[0], rtol=1e-13, atol=1e-14 * np.abs(M).max())
+
+
+def test_p1_operator_with_constant_field_is_the_p0_operator():
+    w = mi.configs.cube(2)
+    fp = fem.build(w.mesh, w.eps, w.k0, w.beta_imp, w.ports)
+    c = 2.5 - 0.7j
+    A1 = fem.with_eps_vertex(fp, np.full(fp.nv, c)).A
+    A0 = fem.with_eps(fp, np.full(fp.tet.shape[0], c)).A
+    assert abs(A1 - A0).max() <= 1e-13 * abs(A0).max()
+
+
 def test_curl_matrix_matches_numerical_curl():
     for _ in range(5):
         P = random_tet()

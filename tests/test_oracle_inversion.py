@@ -45,7 +45,7 @@ def test_p1_stiffness_exact_on_linear_fields(small):
     assert abs(e @ (K1 @ e) - (c @ c) * vol.sum()) <= 1e-10 * (c @ c) * vol.sum()
 
 
-def _objective(w, fp, alpha, seed=5):
+def _objective(w, fp, alpha, seed=5, p1=False):
     """Data from a perturbed vertex permittivity; the empty chamber is the
     homogeneous gel; returns the objective and the true vertex field."""
     nv = fp.xyz.shape[0]
@@ -59,17 +59,17 @@ def _objective(w, fp, alpha, seed=5):
     B = fem.rhs_ports(fp, w.ports, w.tx)
 
     def S_of(ev):
-        f = fem.with_eps(fp, inversion.vertex_mean(fp.tet, ev))
+        f = fem.with_eps_vertex(fp, ev) if p1 else fem.with_eps(fp, inversion.vertex_mean(fp.tet, ev))
         import scipy.sparse.linalg as spla
         return inverse.s_matrix(P, nu, spla.splu(f.A.tocsc()).solve(B), w.rx)
 
-    return inversion.Objective(fp, w.ports, w.tx, w.rx, S_of(e_true), S_of(e_gel), alpha), e_gel, e_true
+    return inversion.Objective(fp, w.ports, w.tx, w.rx, S_of(e_true), S_of(e_gel), alpha, p1=p1), e_gel, e_true
 
 
-@pytest.mark.parametrize("alpha", [0.0, 1e-3])
-def test_objective_gradient_matches_finite_differences(small, alpha):
+@pytest.mark.parametrize("alpha,p1", [(0.0, False), (1e-3, False), (0.0, True), (1e-3, True)])
+def test_objective_gradient_matches_finite_differences(small, alpha, p1):
     w, fp = small
-    obj, e_gel, _ = _objective(w, fp, alpha)
+    obj, e_gel, _ = _objective(w, fp, alpha, p1=p1)
     J, g, _ = obj(e_gel)
     nv = fp.xyz.shape[0]
     for k in range(3):
@@ -82,10 +82,11 @@ def test_objective_gradient_matches_finite_differences(small, alpha):
         assert abs(an - fd) <= 1e-5 * abs(fd), (k, an, fd)
 
 
-def test_true_parameter_is_a_minimiser(small):
+@pytest.mark.parametrize("p1", [False, True])
+def test_true_parameter_is_a_minimiser(small, p1):
     """Without regularisation J = 0 and grad J = 0 at the parameter that made the data."""
     w, fp = small
-    obj, _, e_true = _objective(w, fp, 0.0)
+    obj, _, e_true = _objective(w, fp, 0.0, p1=p1)
     J, g, _ = obj(e_true)
     J0, g0, _ = obj(np.full(fp.xyz.shape[0], 44 - 20j))
     assert J <= 1e-20 * J0
