@@ -242,7 +242,7 @@ def invert_main(args):
     S_empty = s_of(np.full(w.mesh.nt, gel))
     inv = inversion.Inversion(P, w.mesh.xyz, w.mesh.tet, w.part, w.n_sub, tx, rx, S_mes, S_empty, args.alpha,
                               precision="c64", tol=args.tol, restart=args.restart, block=args.block,
-                              recycle=not args.no_recycle)
+                              recycle=not args.no_recycle, p1=args.p1)
     e0 = np.full(w.mesh.xyz.shape[0], gel)
     log(f"[invert] L-BFGS x{args.invert} from the gel")
     torch.cuda.synchronize()
@@ -255,7 +255,9 @@ def invert_main(args):
         "gmres_iters_per_evaluation": h.iters, "recycle": inv.recycle,
         "dtype": "c64 factors/TRSM (FP32 MFMA) + f64 GMRES", "data": "synthetic",
         "config": {"workload": f"{w.name}: {P.n} unknowns, {len(tx)} ports, {w.n_sub} subdomains; vertex "
-                               f"permittivity ({w.mesh.xyz.shape[0]} vertices), defJ2 misfit, alpha {args.alpha:g}",
+                               f"permittivity ({w.mesh.xyz.shape[0]} vertices, "
+                               f"{'exact P1 mass term' if args.p1 else 'tetrahedron means'}), defJ2 misfit, "
+                               f"alpha {args.alpha:g}",
                    "tol": args.tol, "restart": args.restart, "gmres": "block" if args.block else "pseudo-block"},
     }
     print(json.dumps(line), flush=True)
@@ -292,6 +294,9 @@ def main():
     ap.add_argument("--step0", type=float, default=0.5, help="largest vertex change of the first L-BFGS step")
     ap.add_argument("--no-recycle", action="store_true",
                     help="inversion loop: start every solve from zero instead of the previous fields")
+    ap.add_argument("--p1", action="store_true",
+                    help="inversion loop: the permittivity linear on every tetrahedron, integrated exactly "
+                         "(instead of the tetrahedron mean of the vertex values)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this library solves all subdomains "

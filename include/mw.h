@@ -157,6 +157,14 @@ mw_status mw_assemble(mw_ctx *ctx, const mw_mesh *mesh, const mw_complex *eps_r,
 /* Replaces eps (device [nt] complex) and re-assembles A.  Factors become
  * stale: call mw_factor_subdomains again before mw_solve. */
 mw_status mw_update_eps(mw_problem *p, const void *eps_dev);
+/* eps_r linear on every tetrahedron (Section 6 discretises kappa = k0^2 eps_r
+ * with P1 elements): eps_vertex_dev (device [nv] complex) the values at the
+ * mesh vertices; the mass term of tetrahedron t becomes
+ * sum_v eps_v int_t l_v N_p . N_q (exact), and the tetrahedron means stand for
+ * eps_t wherever a per-tetrahedron value is read (the transmission wavenumber,
+ * the choice of factorisation).  Re-assembles A; factors become stale.  A
+ * later mw_update_eps returns to one value per tetrahedron. */
+mw_status mw_update_eps_vertex(mw_problem *p, const void *eps_vertex_dev);
 mw_status mw_problem_get_info(mw_problem *p, mw_problem_info *info);
 /* host [n]: edge id of every unknown; host [n_edges*2]: edge end vertices. */
 mw_status mw_dof_edges(mw_problem *p, int32_t *edge_of_dof, int32_t *edge_vertices);
@@ -238,6 +246,10 @@ mw_status mw_misfit_gradient(mw_problem *p, int32_t ntx, const int32_t *tx, int3
 mw_status mw_adjoint_rhs(mw_problem *p, int32_t nrx, const int32_t *rx, int32_t ntx, const void *gS,
                          void *Lambda);
 mw_status mw_gradient(mw_problem *p, int32_t ntx, const void *U, const void *F, void *grad_eps);
+/* With eps_r given at the vertices: grad_vertex (device [nv]) =
+ * dL/dRe eps_v + i dL/dIm eps_v = conj(k0^2 sum_t sum_j f_j^T (int_t l_v N_p . N_q) u_j)
+ * from the forward fields U and adjoint fields F (device n x ntx each). */
+mw_status mw_gradient_vertex(mw_problem *p, int32_t ntx, const void *U, const void *F, void *grad_vertex);
 mw_status mw_misfit(mw_problem *p, int64_t count, const void *S_sim, const void *S_meas, void *gS,
                     double *J);
 

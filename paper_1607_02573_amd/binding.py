@@ -108,6 +108,8 @@ _SIGS = {
     "mw_host_decomposition": [C.POINTER(mw_mesh), _P, _I, _I, _P, _P, _P, _P],
     "mw_host_block_lstsq": [_I, _I, _P, _P, C.c_double, _P, _P],
     "mw_set_factorization": [_P, _I],
+    "mw_update_eps_vertex": [_P, _P],
+    "mw_gradient_vertex": [_P, _I, _P, _P, _P],
 }
 EXPORTED = list(_SIGS) + ["mw_last_error", "mw_host_last_error", "mw_timer_families", "mw_timer_name",
                           "mw_timer_enable", "mw_timer_reset"]

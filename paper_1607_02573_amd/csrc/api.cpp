@@ -114,6 +114,10 @@ struct mw_problem {
   // mesh and operator
   DevBuf xyz, tet, t2e, dof, bface, bf2e, fbeta, row_ptr, col, rt_ptr, rt, rf_ptr, rf;
   DevBuf eps, E, val;
+  // eps_r linear on every tetrahedron (mw_update_eps_vertex): vertex values,
+  // and the (t*4 + slot) entries of every vertex for the vertex gradient
+  bool eps_p1 = false;
+  DevBuf eps_v, vt_ptr, vt;
   DeviceMesh dm;
   // ports
   DevBuf port_dev, port_ptr, ent_dof, ent_port, ent_ptr, ent_fq, pf_ptr, pf, pval, nu;
@@ -238,7 +242,11 @@ void setup_ports(mw_problem* p) {
 }
 
 void assemble_values(mw_problem* p) {
-  launch_element_matrices(p->dm, p->eps.as<double2>(), p->k0, p->E.as<double2>(), p->stream);
+  if (p->eps_p1)
+    launch_element_matrices_p1(p->dm, p->eps_v.as<double2>(), p->k0, p->E.as<double2>(), p->eps.as<double2>(),
+                               p->stream);
+  else
+    launch_element_matrices(p->dm, p->eps.as<double2>(), p->k0, p->E.as<double2>(), p->stream);
   launch_gather_csr(p->dm, p->E.as<double2>(), p->val.as<double2>(), p->stream);
 }
 
@@ -1035,10 +1043,51 @@ mw_status mw_update_eps(mw_problem* p, const void* eps_dev) {
     DeviceGuard dg(p->ctx->device);
     double t0 = now_s();
     MW_HIP(hipMemcpyAsync(p->eps.p, eps_dev, (size_t)p->T.nt * 16, hipMemcpyDeviceToDevice, p->stream));
+    p->eps_p1 = false;
     assemble_values(p);
     p->factors_valid = false;
     psync(p);
     p->t_assemble = now_s() - t0;
+  });
+}
+
+mw_status mw_update_eps_vertex(mw_problem* p, const void* eps_vertex_dev) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(eps_vertex_dev != nullptr, MW_EINVAL, "eps is NULL");
+    DeviceGuard dg(p->ctx->device);
+    double t0 = now_s();
+    if (p->eps_v.p == nullptr) p->eps_v = dalloc(p->ctx, (int64_t)p->T.nv * 16);
+    MW_HIP(hipMemcpyAsync(p->eps_v.p, eps_vertex_dev, (size_t)p->T.nv * 16, hipMemcpyDeviceToDevice, p->stream));
+    p->eps_p1 = true;
+    assemble_values(p);
+    p->factors_valid = false;
+    psync(p);
+    p->t_assemble = now_s() - t0;
+  });
+}
+
+mw_status mw_gradient_vertex(mw_problem* p, int32_t ntx, const void* U, const void* F, void* grad_vertex) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(ntx >= 1 && U && F && grad_vertex, MW_EINVAL, "NULL argument");
+    DeviceGuard dg(p->ctx->device);
+    const int64_t nt = p->T.nt, nv = p->T.nv;
+    if (p->vt.p == nullptr) {
+      // (t*4 + slot) entries of every vertex, ascending t
+      std::vector<int64_t> ptr(nv + 1, 0);
+      for (int64_t e = 0; e < nt * 4; ++e) ptr[p->T.tet[e] + 1]++;
+      for (int64_t v = 0; v < nv; ++v) ptr[v + 1] += ptr[v];
+      std::vector<int32_t> lst(nt * 4);
+      std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+      for (int64_t e = 0; e < nt * 4; ++e) lst[fill[p->T.tet[e]]++] = (int32_t)e;
+      p->vt_ptr = upload(p->ctx, p->stream, ptr);
+      p->vt = upload(p->ctx, p->stream, lst);
+    }
+    DevBuf G = dalloc(p->ctx, nt * 4 * 16);
+    launch_gradient_p1(p->dm, (const double2*)U, (const double2*)F, ntx, ntx, p->k0, p->vt_ptr.as<int64_t>(),
+                       p->vt.as<int32_t>(), G.as<double2>(), (double2*)grad_vertex, p->stream);
+    psync(p);
   });
 }
 

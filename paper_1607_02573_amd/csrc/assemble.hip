@@ -85,6 +85,61 @@ __global__ void k_element_matrices(const double* __restrict__ xyz, const int32_t
     }
 }
 
+// int_t l_v l_x l_y / vol (Section 6 discretises kappa with P1 elements):
+// 1/120 for three different indices, 1/60 when exactly two agree, 1/20 when
+// all three agree.
+__device__ inline double w3(int v, int x, int y) {
+  const int same = (v == x) + (v == y) + (x == y);
+  return same == 0 ? 1.0 / 120.0 : (same == 1 ? 1.0 / 60.0 : 1.0 / 20.0);
+}
+
+// mass entry of a coefficient linear on the tetrahedron with vertex values
+// ev[4]: sum_v ev[v] int l_v N_p . N_q = vol [W_ac g_b.g_d - W_ad g_b.g_c
+// - W_bc g_a.g_d + W_bd g_a.g_c], W_xy = sum_v ev[v] w3(v, x, y)
+__device__ inline double2 mass_entry_p1(const V3* g, int p, int q, double vol, const double2 ev[4]) {
+  const int a = c_tedge[p][0], b = c_tedge[p][1], c = c_tedge[q][0], d = c_tedge[q][1];
+  auto W = [&](int x, int y) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int v = 0; v < 4; ++v) s = cadd(s, cscale(ev[v], w3(v, x, y)));
+    return s;
+  };
+  const double2 wac = W(a, c), wad = W(a, d), wbc = W(b, c), wbd = W(b, d);
+  const double gbd = vdot(g[b], g[d]), gbc = vdot(g[b], g[c]), gad = vdot(g[a], g[d]), gac = vdot(g[a], g[c]);
+  return make_double2(vol * (wac.x * gbd - wad.x * gbc - wbc.x * gad + wbd.x * gac),
+                      vol * (wac.y * gbd - wad.y * gbc - wbc.y * gad + wbd.y * gac));
+}
+
+// E_t with eps_r linear on the tetrahedron (vertex values eps_v), and the
+// tetrahedron mean of eps_v (the coefficient the preconditioner's
+// transmission wavenumber and the factorisation choice read)
+__global__ void k_element_matrices_p1(const double* __restrict__ xyz, const int32_t* __restrict__ tet,
+                                      const double2* __restrict__ eps_v, double k0sq, int64_t nt,
+                                      double2* __restrict__ E, double2* __restrict__ eps_t) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  V3 g[4];
+  double vol = tet_grads(xyz, tet, t, g);
+  double2 ev[4];
+  for (int v = 0; v < 4; ++v) ev[v] = eps_v[tet[t * 4 + v]];
+  V3 cu[6];
+  for (int p = 0; p < 6; ++p) cu[p] = vmul(vcross(g[c_tedge[p][0]], g[c_tedge[p][1]]), 2.0);
+  double2* out = E + t * 21;
+  for (int p = 0; p < 6; ++p)
+    for (int q = p; q < 6; ++q) {
+      double k = vol * vdot(cu[p], cu[q]);
+      double2 m = mass_entry_p1(g, p, q, vol, ev);
+      out[sym21(p, q)] = make_double2(k - k0sq * m.x, -k0sq * m.y);
+    }
+  eps_t[t] = make_double2(0.25 * (ev[0].x + ev[1].x + ev[2].x + ev[3].x),
+                          0.25 * (ev[0].y + ev[1].y + ev[2].y + ev[3].y));
+}
+
+void launch_element_matrices_p1(const DeviceMesh& m, const double2* eps_v, double k0, double2* E, double2* eps_t,
+                                hipStream_t st) {
+  k_element_matrices_p1<<<(unsigned)ceil_div(m.nt, 256), 256, 0, st>>>(m.xyz, m.tet, eps_v, k0 * k0, m.nt, E, eps_t);
+  MW_LAUNCH_CHECK();
+}
+
 // row p of i*beta*M_F for the triangle (a,b,c) (ascending)
 __device__ inline void face_row(const double* xyz, int32_t a, int32_t b, int32_t c, double2 beta,
                                 int p, double2 out[3]) {
@@ -499,6 +554,61 @@ void launch_gradient(const DeviceMesh& m, const double2* U, const double2* F, in
                      double2* grad, hipStream_t st) {
   k_gradient<<<(unsigned)ceil_div(m.nt, 128), 128, 0, st>>>(m.xyz, m.tet, m.t2e, m.dof, m.nt, U, F, ld, ncol,
                                                              k0 * k0, grad);
+  MW_LAUNCH_CHECK();
+}
+
+// Vertex gradient for eps_r linear on every tetrahedron: G[t][v] =
+// conj(k0^2 sum_j f_j|_t^T M1_v u_j|_t), M1_v = int l_v N_p . N_q, then
+// grad[v] = sum of G over the (t, slot) pairs of vertex v in a fixed order
+// (k_vertex_sum, one thread per vertex).
+__global__ void k_gradient_p1(const double* __restrict__ xyz, const int32_t* __restrict__ tet,
+                              const int32_t* __restrict__ t2e, const int32_t* __restrict__ dof, int64_t nt,
+                              const double2* __restrict__ U, const double2* __restrict__ F, int64_t ld, int ncol,
+                              double k0sq, double2* __restrict__ G) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  V3 g[4];
+  double vol = tet_grads(xyz, tet, t, g);
+  int32_t d[6];
+  for (int p = 0; p < 6; ++p) d[p] = dof[t2e[t * 6 + p]];
+  for (int v = 0; v < 4; ++v) {
+    double2 ev[4];
+    for (int u = 0; u < 4; ++u) ev[u] = make_double2(u == v ? 1.0 : 0.0, 0.0);
+    double M[21];
+    for (int p = 0; p < 6; ++p)
+      for (int q = p; q < 6; ++q) M[sym21(p, q)] = mass_entry_p1(g, p, q, vol, ev).x;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int j = 0; j < ncol; ++j) {
+      double2 uu[6], ff[6];
+      for (int p = 0; p < 6; ++p) {
+        uu[p] = d[p] >= 0 ? U[(int64_t)d[p] * ld + j] : make_double2(0.0, 0.0);
+        ff[p] = d[p] >= 0 ? F[(int64_t)d[p] * ld + j] : make_double2(0.0, 0.0);
+      }
+      for (int p = 0; p < 6; ++p) {
+        double2 mu = make_double2(0.0, 0.0);
+        for (int q = 0; q < 6; ++q) mu = cadd(mu, cscale(uu[q], M[sym21(p, q)]));
+        acc = cadd(acc, cmul(ff[p], mu));
+      }
+    }
+    G[t * 4 + v] = make_double2(k0sq * acc.x, -k0sq * acc.y);
+  }
+}
+
+__global__ void k_vertex_sum(int64_t nv, const int64_t* __restrict__ vt_ptr, const int32_t* __restrict__ vt,
+                             const double2* __restrict__ G, double2* __restrict__ grad) {
+  int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  double2 s = make_double2(0.0, 0.0);
+  for (int64_t k = vt_ptr[v]; k < vt_ptr[v + 1]; ++k) s = cadd(s, G[vt[k]]);
+  grad[v] = s;
+}
+
+void launch_gradient_p1(const DeviceMesh& m, const double2* U, const double2* F, int64_t ld, int ncol, double k0,
+                        const int64_t* vt_ptr, const int32_t* vt, double2* G, double2* grad, hipStream_t st) {
+  k_gradient_p1<<<(unsigned)ceil_div(m.nt, 128), 128, 0, st>>>(m.xyz, m.tet, m.t2e, m.dof, m.nt, U, F, ld, ncol,
+                                                                k0 * k0, G);
+  MW_LAUNCH_CHECK();
+  k_vertex_sum<<<(unsigned)ceil_div(m.nv, 256), 256, 0, st>>>(m.nv, vt_ptr, vt, G, grad);
   MW_LAUNCH_CHECK();
 }
 

@@ -107,6 +107,12 @@ void launch_gradient(const DeviceMesh& m, const double2* U, const double2* F, in
                      double2* grad, hipStream_t st);
 
 void launch_max_imag(const double2* eps, int64_t nt, double* out, hipStream_t st);
+// eps_r linear on every tetrahedron (vertex values): element matrices and tet means;
+// vertex gradient (G: nt x 4 scratch; vt_ptr/vt: (t*4 + slot) entries of each vertex)
+void launch_element_matrices_p1(const DeviceMesh& m, const double2* eps_v, double k0, double2* E, double2* eps_t,
+                                hipStream_t st);
+void launch_gradient_p1(const DeviceMesh& m, const double2* U, const double2* F, int64_t ld, int ncol, double k0,
+                        const int64_t* vt_ptr, const int32_t* vt, double2* G, double2* grad, hipStream_t st);
 
 // ---- dense subdomain algebra (dense.hip)
 // Factor every B_i in place: P_i B_i = L_i U_i (partial pivoting, unit L), or

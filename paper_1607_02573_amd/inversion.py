@@ -1,7 +1,9 @@
 """Outer inversion loop on the GPU solver (Section 5 of the paper).
 
 The unknown is the relative permittivity at the mesh vertices; the Maxwell
-operator takes on each tetrahedron the mean of its four vertex values.  The
+operator takes on each tetrahedron the mean of its four vertex values, or with
+`p1` the linear coefficient integrated exactly in the mass term
+(mw_update_eps_vertex, gradient by mw_gradient_vertex).  The
 misfit is equation (defJ2): every pair (i, j) divided by |S_ij^empty|^2 (the
 S-matrix of the chamber filled with the matching medium only), plus a
 Tikhonov term alpha/2 int |grad eps_r|^2, exact for the piecewise-linear field
@@ -72,7 +74,7 @@ class History:
 class Inversion:
     def __init__(self, problem, xyz, tet, part, n_sub: int, tx, rx, S_mes: np.ndarray, S_empty: np.ndarray,
                  alpha: float, precision: str = "c64", tol: float = 1e-8, restart: int = 30, block: int = 0,
-                 overlap: int = 1, recycle: bool = True):
+                 overlap: int = 1, recycle: bool = True, p1: bool = False):
         self.P = problem
         self.tet = np.ascontiguousarray(tet)
         self.nv = xyz.shape[0]
@@ -89,14 +91,17 @@ class Inversion:
         self.K1 = p1_stiffness(np.asarray(xyz, dtype=np.float64), self.tet)
         self.dev = problem.ctx.device
         self.recycle = recycle
+        self.p1 = p1
         self._U = self._F = None
         self.history = History()
 
     def objective(self, eps_v: np.ndarray):
         """J and dJ/dRe eps_v + i dJ/dIm eps_v at the vertex field eps_v."""
         P = self.P
-        eps_t = torch.from_numpy(np.ascontiguousarray(self.avg @ eps_v)).to(self.dev)
-        P.update_eps(eps_t)
+        if self.p1:
+            P.update_eps_vertex(torch.from_numpy(np.ascontiguousarray(eps_v, dtype=np.complex128)).to(self.dev))
+        else:
+            P.update_eps(torch.from_numpy(np.ascontiguousarray(self.avg @ eps_v)).to(self.dev))
         P.factor(self.part, self.n_sub, self.overlap, self.precision)
         U, info = P.solve(P.rhs_ports(self.tx), tol=self.tol, restart=self.restart, block=self.block,
                           x0=self._U if self.recycle else None)
@@ -106,13 +111,14 @@ class Inversion:
         gS = torch.from_numpy(np.ascontiguousarray(self.weight * r)).to(self.dev)
         F, info_a = P.solve(P.adjoint_rhs(gS, self.rx), tol=self.tol, restart=self.restart, block=self.block,
                             x0=self._F if self.recycle else None)
-        g_t = P.gradient(U, F).cpu().numpy()
+        g_d = (P.gradient_vertex(U, F).cpu().numpy() if self.p1
+               else self.avg.T @ P.gradient(U, F).cpu().numpy())
         if self.recycle:
             self._U, self._F = U, F
         self.history.iters.append((float(info.iters.mean()), float(info_a.iters.mean())))
         kr, ki = self.K1 @ eps_v.real, self.K1 @ eps_v.imag
         J = J_data + 0.5 * self.alpha * float(eps_v.real @ kr + eps_v.imag @ ki)
-        g = self.avg.T @ g_t + self.alpha * (kr + 1j * ki)
+        g = g_d + self.alpha * (kr + 1j * ki)
         self.history.evaluations += 1
         self.history.solve_columns += 2 * len(self.tx)
         return J, g

@@ -68,6 +68,7 @@ class Problem:
         self.ctx = ctx
         L = lib()
         m, self._mesh_keep = B.make_mesh(xyz, tet, bface, btag)
+        self.nv = int(m.nv)
         eps = np.ascontiguousarray(np.asarray(eps, dtype=np.complex128))
         assert eps.shape == (m.nt,)
         nports = len(ports)
@@ -118,6 +119,13 @@ class Problem:
     def update_eps(self, eps: torch.Tensor):
         _dev_tensor(eps, torch.complex128, self.ctx.device, "eps")
         check(lib().mw_update_eps(self.h, ptr(eps)))
+
+    def update_eps_vertex(self, eps_v: torch.Tensor):
+        """eps_r linear on every tetrahedron, given at the mesh vertices."""
+        _dev_tensor(eps_v, torch.complex128, self.ctx.device, "eps_v")
+        if eps_v.numel() != self.nv:
+            raise ValueError(f"eps_v must have {self.nv} entries (one per vertex)")
+        check(lib().mw_update_eps_vertex(self.h, ptr(eps_v)))
 
     def rhs_ports(self, tx) -> torch.Tensor:
         tx = np.ascontiguousarray(tx, dtype=np.int32)
@@ -241,6 +249,15 @@ class Problem:
         assert U.shape == F.shape
         g = torch.empty(self.nt, dtype=torch.complex128, device=self.ctx.device)
         check(lib().mw_gradient(self.h, U.shape[1], ptr(U), ptr(F), ptr(g)))
+        return g
+
+    def gradient_vertex(self, U: torch.Tensor, F: torch.Tensor) -> torch.Tensor:
+        """Vertex gradient (dL/dRe + i dL/dIm of eps_v) with eps_r given at the vertices."""
+        _dev_tensor(U, torch.complex128, self.ctx.device, "U")
+        _dev_tensor(F, torch.complex128, self.ctx.device, "F")
+        assert U.shape == F.shape
+        g = torch.empty(self.nv, dtype=torch.complex128, device=self.ctx.device)
+        check(lib().mw_gradient_vertex(self.h, U.shape[1], ptr(U), ptr(F), ptr(g)))
         return g
 
     def misfit(self, S: torch.Tensor, S_meas: torch.Tensor):
