@@ -360,17 +360,35 @@ __global__ void __launch_bounds__(256) k_dots_partial(const double2* __restrict_
   for (int q = 0; q < DOTS_KG; ++q) acc1[q] = acc2[q] = make_double2(0.0, 0.0);
   if (c < ncols && act[c]) {
     const double2* Vb = V + (int64_t)kb * vstride;
-    for (int64_t r = r0 + rl; r < r1; r += 4) {
-      const double2 x = w1[r * ld + c];
-      const double2 y = w2 ? w2[r * ld + c] : make_double2(0.0, 0.0);
+    // two rows per pass (r and r + 4): twice the loads in flight; each
+    // (k, column) sum still runs over the chunk's rows in ascending order
+    for (int64_t r = r0 + rl; r < r1; r += 8) {
+      const bool two = r + 4 < r1;
+      const int64_t o0 = r * ld + c, o1 = (r + 4) * ld + c;
+      const double2 x0 = w1[o0];
+      const double2 y0 = w2 ? w2[o0] : make_double2(0.0, 0.0);
+      const double2 x1 = two ? w1[o1] : make_double2(0.0, 0.0);
+      const double2 y1 = (two && w2) ? w2[o1] : make_double2(0.0, 0.0);
+      double2 v0[DOTS_KG], v1[DOTS_KG];
+#pragma unroll
+      for (int q = 0; q < DOTS_KG; ++q) {
+        const bool ok = kb + q < kcount;
+        v0[q] = ok ? Vb[(int64_t)q * vstride + o0] : make_double2(0.0, 0.0);
+        v1[q] = (ok && two) ? Vb[(int64_t)q * vstride + o1] : make_double2(0.0, 0.0);
+      }
 #pragma unroll
       for (int q = 0; q < DOTS_KG; ++q)
         if (kb + q < kcount) {
-          const double2 v = Vb[(int64_t)q * vstride + r * ld + c];
-          acc1[q].x += v.x * x.x + v.y * x.y;
-          acc1[q].y += v.x * x.y - v.y * x.x;
-          acc2[q].x += v.x * y.x + v.y * y.y;
-          acc2[q].y += v.x * y.y - v.y * y.x;
+          acc1[q].x += v0[q].x * x0.x + v0[q].y * x0.y;
+          acc1[q].y += v0[q].x * x0.y - v0[q].y * x0.x;
+          acc2[q].x += v0[q].x * y0.x + v0[q].y * y0.y;
+          acc2[q].y += v0[q].x * y0.y - v0[q].y * y0.x;
+          if (two) {
+            acc1[q].x += v1[q].x * x1.x + v1[q].y * x1.y;
+            acc1[q].y += v1[q].x * x1.y - v1[q].y * x1.x;
+            acc2[q].x += v1[q].x * y1.x + v1[q].y * y1.y;
+            acc2[q].y += v1[q].x * y1.y - v1[q].y * y1.x;
+          }
         }
     }
   }
@@ -582,6 +600,7 @@ __global__ void __launch_bounds__(256) k_dgs_update(double2* __restrict__ V, int
       const int64_t o0 = r * ld + c, o1 = (r + 4) * ld + c;
       double2 y0 = Vj[o0], u0 = T[o0];
       double2 y1 = two ? Vj[o1] : make_double2(0.0, 0.0), u1 = two ? T[o1] : make_double2(0.0, 0.0);
+#pragma unroll 4
       for (int k = 0; k < j; ++k) {
         const double2* Vk = V + (int64_t)k * vstride;
         const double2 v0 = Vk[o0];
