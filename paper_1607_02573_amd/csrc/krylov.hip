@@ -594,43 +594,45 @@ __global__ void __launch_bounds__(256) k_dgs_update(double2* __restrict__ V, int
     const double2 ec = e[c];
     double2* Vj = V + (int64_t)j * vstride;
     double2* Vn = V + (int64_t)(j + 1) * vstride;
-    // two rows per pass (r and r + 4), sharing each coefficient load
-    for (int64_t r = r0 + rl; r < r1; r += 8) {
-      const bool two = r + 4 < r1;
-      const int64_t o0 = r * ld + c, o1 = (r + 4) * ld + c;
-      double2 y0 = Vj[o0], u0 = T[o0];
-      double2 y1 = two ? Vj[o1] : make_double2(0.0, 0.0), u1 = two ? T[o1] : make_double2(0.0, 0.0);
-#pragma unroll 4
+    // RP rows per pass (r, r + 4, ...), sharing each coefficient load; the
+    // norm is summed over the rows in ascending order
+    constexpr int RP = 4;
+    for (int64_t r = r0 + rl; r < r1; r += 4 * RP) {
+      int64_t o[RP];
+      bool live[RP];
+      double2 y[RP], u[RP];
+#pragma unroll
+      for (int q = 0; q < RP; ++q) {
+        live[q] = r + 4 * q < r1;
+        o[q] = (r + 4 * q) * ld + c;
+        y[q] = live[q] ? Vj[o[q]] : make_double2(0.0, 0.0);
+        u[q] = live[q] ? T[o[q]] : make_double2(0.0, 0.0);
+      }
+#pragma unroll 2
       for (int k = 0; k < j; ++k) {
         const double2* Vk = V + (int64_t)k * vstride;
-        const double2 v0 = Vk[o0];
-        const double2 v1 = two ? Vk[o1] : make_double2(0.0, 0.0);
         const double2 ak = in_lds ? cf[(2 * k) * 64 + cl] : coef[(int64_t)(2 * k) * ncols + c];
         const double2 bk = in_lds ? cf[(2 * k + 1) * 64 + cl] : coef[(int64_t)(2 * k + 1) * ncols + c];
-        y0.x -= v0.x * ak.x - v0.y * ak.y;
-        y0.y -= v0.x * ak.y + v0.y * ak.x;
-        u0.x -= v0.x * bk.x - v0.y * bk.y;
-        u0.y -= v0.x * bk.y + v0.y * bk.x;
-        y1.x -= v1.x * ak.x - v1.y * ak.y;
-        y1.y -= v1.x * ak.y + v1.y * ak.x;
-        u1.x -= v1.x * bk.x - v1.y * bk.y;
-        u1.y -= v1.x * bk.y + v1.y * bk.x;
+#pragma unroll
+        for (int q = 0; q < RP; ++q) {
+          const double2 v = live[q] ? Vk[o[q]] : make_double2(0.0, 0.0);
+          y[q].x -= v.x * ak.x - v.y * ak.y;
+          y[q].y -= v.x * ak.y + v.y * ak.x;
+          u[q].x -= v.x * bk.x - v.y * bk.y;
+          u[q].y -= v.x * bk.y + v.y * bk.x;
+        }
       }
-      y0 = make_double2(y0.x / inu, y0.y / inu);
-      u0.x -= y0.x * ec.x - y0.y * ec.y;
-      u0.y -= y0.x * ec.y + y0.y * ec.x;
-      u0 = make_double2(u0.x / inu, u0.y / inu);
-      Vj[o0] = y0;
-      Vn[o0] = u0;
-      acc += u0.x * u0.x + u0.y * u0.y;
-      if (two) {
-        y1 = make_double2(y1.x / inu, y1.y / inu);
-        u1.x -= y1.x * ec.x - y1.y * ec.y;
-        u1.y -= y1.x * ec.y + y1.y * ec.x;
-        u1 = make_double2(u1.x / inu, u1.y / inu);
-        Vj[o1] = y1;
-        Vn[o1] = u1;
-        acc += u1.x * u1.x + u1.y * u1.y;
+#pragma unroll
+      for (int q = 0; q < RP; ++q) {
+        if (!live[q]) continue;
+        double2 yy = make_double2(y[q].x / inu, y[q].y / inu);
+        double2 uu = u[q];
+        uu.x -= yy.x * ec.x - yy.y * ec.y;
+        uu.y -= yy.x * ec.y + yy.y * ec.x;
+        uu = make_double2(uu.x / inu, uu.y / inu);
+        Vj[o[q]] = yy;
+        Vn[o[q]] = uu;
+        acc += uu.x * uu.x + uu.y * uu.y;
       }
     }
   }
