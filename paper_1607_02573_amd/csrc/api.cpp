@@ -112,7 +112,7 @@ struct mw_problem {
   mw_complex beta_imp{0, 0};
   std::vector<mw_port> ports;
   // mesh and operator
-  DevBuf xyz, tet, t2e, dof, bface, bf2e, fbeta, row_ptr, col, rt_ptr, rt, rf_ptr, rf;
+  DevBuf xyz, tet, t2e, dof, bface, bf2e, fbeta, row_ptr, col, rt_ptr, rt, rf_ptr, rf, rorder;
   DevBuf eps, E, val;
   // eps_r linear on every tetrahedron (mw_update_eps_vertex): vertex values,
   // and the (t*4 + slot) entries of every vertex for the vertex gradient
@@ -128,8 +128,9 @@ struct mw_problem {
   Decomposition D;
   DevBuf d_fac_off, d_loc_off, d_n_loc, d_n_pad, d_lt_off, d_lt_tet, d_lt_loc, d_lf_off, d_lf_vert, d_lf_owner,
       d_lf_kind, d_lf_loc, d_rtl_ptr, d_rtl, d_rfl_ptr, d_rfl, d_sub_dof, d_D, d_cp_ptr, d_cp_row, d_ipiv, d_ridx,
-      d_info, d_amax, d_row_lo;
+      d_info, d_amax, d_row_lo, d_env;
   std::vector<int32_t> h_row_lo;
+  std::vector<int2> h_env;
   DeviceDecomp dd;
   DevBuf F;
   int prec = -1;
@@ -241,6 +242,38 @@ void setup_ports(mw_problem* p) {
   launch_port_setup(p->dm, P, p->stream);
 }
 
+// Rows of A sorted by the Z-order (Morton) code of their edge midpoints,
+// 10 bits per axis over the mesh's bounding box: consecutive rows of this
+// order couple nearby unknowns, so the wide SpMM's reads of x rows stay in L2.
+std::vector<int32_t> zorder_rows(const Topology& T) {
+  const int64_t n = T.n();
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int32_t v = 0; v < T.nv; ++v)
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], T.xyz[3 * v + a]);
+      hi[a] = std::max(hi[a], T.xyz[3 * v + a]);
+    }
+  std::vector<std::pair<uint32_t, int32_t>> key(n);
+  for (int64_t d = 0; d < n; ++d) {
+    const int64_t e = T.free_edge[d];
+    const int64_t va = T.edges[2 * e], vb = T.edges[2 * e + 1];
+    uint32_t q[3];
+    for (int a = 0; a < 3; ++a) {
+      const double x = 0.5 * (T.xyz[3 * va + a] + T.xyz[3 * vb + a]);
+      const double t = hi[a] > lo[a] ? (x - lo[a]) / (hi[a] - lo[a]) : 0.0;
+      q[a] = (uint32_t)std::min(1023.0, std::max(0.0, t * 1023.0));
+    }
+    uint32_t code = 0;
+    for (int b = 0; b < 10; ++b)
+      for (int a = 0; a < 3; ++a) code |= ((q[a] >> b) & 1u) << (3 * b + a);
+    key[d] = {code, (int32_t)d};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int32_t> order(n);
+  for (int64_t d = 0; d < n; ++d) order[d] = key[d].second;
+  return order;
+}
+
 void assemble_values(mw_problem* p) {
   if (p->eps_p1)
     launch_element_matrices_p1(p->dm, p->eps_v.as<double2>(), p->k0, p->E.as<double2>(), p->eps.as<double2>(),
@@ -317,6 +350,11 @@ void upload_decomp(mw_problem* p) {
   d.h_n_loc = p->D.n_loc.data();
   d.row_lo = p->d_row_lo.as<int32_t>();
   d.h_row_lo = p->h_row_lo.data();
+  d.env_stride = d.max_pad / 32;
+  p->h_env.assign((size_t)d.nsub * d.env_stride, make_int2(0, 0));
+  p->d_env = dalloc(c, (int64_t)p->h_env.size() * 8);
+  d.env = p->d_env.as<int2>();
+  d.h_env = p->h_env.data();
 }
 
 // Z = M^-1 V (n x nc, leading dimension ld), local workspace W.Y
@@ -1004,6 +1042,7 @@ mw_status mw_assemble(mw_ctx* ctx, const mw_mesh* mesh, const mw_complex* eps_r,
     p->bf2e = upload(ctx, p->stream, T.bf2e);
     p->fbeta = upload(ctx, p->stream, fb);
     p->row_ptr = upload(ctx, p->stream, T.row_ptr);
+    p->rorder = upload(ctx, p->stream, zorder_rows(T));
     p->col = upload(ctx, p->stream, T.col);
     p->rt_ptr = upload(ctx, p->stream, T.rt_ptr);
     p->rt = upload(ctx, p->stream, T.rt);
@@ -1019,6 +1058,7 @@ mw_status mw_assemble(mw_ctx* ctx, const mw_mesh* mesh, const mw_complex* eps_r,
     m.fbeta = p->fbeta.as<double2>(); m.row_ptr = p->row_ptr.as<int64_t>(); m.col = p->col.as<int32_t>();
     m.rt_ptr = p->rt_ptr.as<int64_t>(); m.rt = p->rt.as<int32_t>(); m.rf_ptr = p->rf_ptr.as<int64_t>();
     m.rf = p->rf.as<int32_t>();
+    m.rorder = p->rorder.as<int32_t>();
     assemble_values(p.get());
     setup_ports(p.get());
     psync(p.get());
@@ -1242,6 +1282,7 @@ mw_status mw_factor_subdomains(mw_problem* p, int32_t n_sub, int32_t overlap, mw
     }
     std::vector<int32_t> info(p->dd.nsub);
     MW_HIP(hipMemcpyAsync(info.data(), p->dd.info, info.size() * 4, hipMemcpyDeviceToHost, st));
+    MW_HIP(hipMemcpyAsync(p->h_env.data(), p->dd.env, p->h_env.size() * 8, hipMemcpyDeviceToHost, st));
     psync(p);
     p->t_factor = now_s() - t1;
     for (int i = 0; i < p->dd.nsub; ++i)

@@ -38,6 +38,74 @@ struct SubTmp {
 struct Scratch {
   std::vector<int32_t> node0, node, tet, edge, eloc;
 };
+
+// Breadth-first levels of the component of `start` (level[] = -1 for unseen
+// vertices on entry); returns the vertices in visiting order and sets `depth`.
+std::vector<int32_t> bfs_levels(int32_t start, const std::vector<int32_t>& ptr, const std::vector<int32_t>& adj,
+                                std::vector<int32_t>& level, int32_t& depth) {
+  std::vector<int32_t> seq{start};
+  level[start] = 0;
+  depth = 0;
+  for (size_t h = 0; h < seq.size(); ++h) {
+    const int32_t u = seq[h];
+    for (int32_t q = ptr[u]; q < ptr[u + 1]; ++q)
+      if (level[adj[q]] < 0) {
+        level[adj[q]] = level[u] + 1;
+        depth = std::max(depth, level[u] + 1);
+        seq.push_back(adj[q]);
+      }
+  }
+  return seq;
+}
+
+// Reverse Cuthill-McKee order of a symmetric graph (Cuthill & McKee 1969,
+// reversed as in George & Liu, Computer Solution of Large Sparse Positive
+// Definite Systems, 1981): per connected component, a pseudo-peripheral start
+// (repeated breadth-first search from a vertex of least degree in the last
+// level while the depth grows), then a breadth-first order that visits each
+// vertex's unnumbered neighbours by increasing degree (ties: lower index); the
+// whole sequence reversed.  Keeps the nonzeros of every row close to the
+// diagonal, and factorisation without interchanges fills only that envelope.
+std::vector<int32_t> rcm_order(int32_t n, const std::vector<int32_t>& ptr, const std::vector<int32_t>& adj) {
+  auto deg = [&](int32_t v) { return ptr[v + 1] - ptr[v]; };
+  std::vector<int32_t> order, level(n, -1), mark(n, 0);
+  order.reserve(n);
+  for (int32_t seed = 0; seed < n; ++seed) {
+    if (mark[seed]) continue;
+    int32_t start = seed, depth = 0;
+    std::vector<int32_t> comp = bfs_levels(start, ptr, adj, level, depth);
+    for (int round = 0; round < 8; ++round) {
+      int32_t best = -1;
+      for (int32_t v : comp)
+        if (level[v] == depth && (best < 0 || deg(v) < deg(best) || (deg(v) == deg(best) && v < best))) best = v;
+      for (int32_t v : comp) level[v] = -1;
+      int32_t d2 = 0;
+      std::vector<int32_t> c2 = bfs_levels(best, ptr, adj, level, d2);
+      comp.swap(c2);               // same vertex set, levels now from `best`
+      if (d2 <= depth) break;
+      start = best;
+      depth = d2;
+    }
+    for (int32_t v : comp) level[v] = -1;
+    // Cuthill-McKee sweep of the component
+    const size_t first = order.size();
+    order.push_back(start);
+    mark[start] = 1;
+    std::vector<int32_t> nbr;
+    for (size_t h = first; h < order.size(); ++h) {
+      const int32_t u = order[h];
+      nbr.clear();
+      for (int32_t q = ptr[u]; q < ptr[u + 1]; ++q)
+        if (!mark[adj[q]]) { mark[adj[q]] = 1; nbr.push_back(adj[q]); }
+      std::sort(nbr.begin(), nbr.end(), [&](int32_t a, int32_t b) {
+        return deg(a) != deg(b) ? deg(a) < deg(b) : a < b;
+      });
+      order.insert(order.end(), nbr.begin(), nbr.end());
+    }
+  }
+  std::reverse(order.begin(), order.end());
+  return order;
+}
 }  // namespace
 
 void build_decomposition(const Topology& T, const int32_t* part, int32_t nsub, int32_t delta,
@@ -160,9 +228,12 @@ void build_decomposition(const Topology& T, const int32_t* part, int32_t nsub, i
       }
     std::sort(o.edges.begin(), o.edges.end());
     const int32_t ni = (int32_t)o.edges.size();
-    // weights, then the local numbering: unknowns with D = 0 first (they are
-    // discarded after the local solve, so the backward substitution can stop
-    // at the first block holding a weighted unknown), each group ascending
+    // weights, then the local numbering: reverse Cuthill-McKee on the graph
+    // of B_i (two unknowns coupled when they share a tetrahedron), so that
+    // the dense factors are banded and the triangular solves skip the zero
+    // tiles outside the envelope; n_lead counts the leading unknowns with
+    // D = 0 (discarded after the local solve: the backward substitution
+    // stops at the first block holding a weighted unknown)
     std::vector<double> Dg(ni);
     for (int32_t l = 0; l < ni; ++l) {
       int64_t e = o.edges[l];
@@ -172,11 +243,31 @@ void build_decomposition(const Topology& T, const int32_t* part, int32_t nsub, i
       Dg[l] = 0.5 * (ca + cb);
     }
     {
-      std::vector<int32_t> ord(ni);
+      for (int32_t l = 0; l < ni; ++l) s.eloc[o.edges[l]] = l;
+      std::vector<int64_t> pairs;
+      for (int32_t t : o.tets) {
+        int32_t loc[6];
+        int m = 0;
+        for (int p = 0; p < 6; ++p) {
+          int32_t e = T.t2e[(size_t)t * 6 + p];
+          if (!T.pec[e]) loc[m++] = s.eloc[e];
+        }
+        for (int a = 0; a < m; ++a)
+          for (int b = 0; b < m; ++b)
+            if (a != b) pairs.push_back((int64_t)loc[a] * ni + loc[b]);
+      }
+      std::sort(pairs.begin(), pairs.end());
+      pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+      std::vector<int32_t> gptr(ni + 1, 0), gadj(pairs.size());
+      for (size_t q = 0; q < pairs.size(); ++q) {
+        gptr[pairs[q] / ni + 1]++;
+        gadj[q] = (int32_t)(pairs[q] % ni);
+      }
+      for (int32_t l = 0; l < ni; ++l) gptr[l + 1] += gptr[l];
+      std::vector<int32_t> ord = rcm_order(ni, gptr, gadj);
       int32_t z = 0;
-      for (int32_t l = 0; l < ni; ++l) if (Dg[l] == 0.0) ord[z++] = l;
+      while (z < ni && Dg[ord[z]] == 0.0) ++z;
       o.n_lead = z;
-      for (int32_t l = 0; l < ni; ++l) if (Dg[l] != 0.0) ord[z++] = l;
       std::vector<int32_t> e2(ni);
       o.D.resize(ni);
       for (int32_t l = 0; l < ni; ++l) { e2[l] = o.edges[ord[l]]; o.D[l] = Dg[ord[l]]; }

@@ -430,7 +430,8 @@ __global__ void __launch_bounds__(256, (sizeof(R) == 8 && WC >= 2) ? 2 : RB) k_g
                                                 const int64_t* __restrict__ loc_off, typename cplx<R>::t* Y,
                                                 int64_t ld, int ncols, int r0, int r1, int k0, int k1,
                                                 int tiles_m, int tiles_n, int nsub,
-                                                const int32_t* __restrict__ row_lo) {
+                                                const int32_t* __restrict__ row_lo,
+                                                const int2* __restrict__ env, int env_stride) {
   using C = typename cplx<R>::t;
   const int per_sub = tiles_m * tiles_n;
   const int G = gridDim.x;
@@ -441,17 +442,29 @@ __global__ void __launch_bounds__(256, (sizeof(R) == 8 && WC >= 2) ? 2 : RB) k_g
   const int tm = t / tiles_n, tn = t % tiles_n;
   const int np = n_pad[i];
   const int M = min(r1, np) - r0 - tm * XTile<R, RB>::TM;
-  const int K = min(k1, np) - k0;
-  if (M <= 0 || K <= 0) return;
+  if (M <= 0) return;
   constexpr int TM = XTile<R, RB>::TM;
+  const int row = r0 + tm * TM;
+  if (row_lo && row + TM <= row_lo[i]) return;   // rows discarded by the weights
+  // inner dimension clipped to the envelope of the tile's rows (row < np,
+  // both multiples of TM, so the tile's 32-row groups exist)
+  int kb = k0, ke = min(k1, np);
+  if (env) {
+#pragma unroll
+    for (int q = 0; q < TM / 32; ++q) {
+      const int2 e = env[(int64_t)i * env_stride + row / 32 + q];
+      kb = q == 0 ? max(k0, e.x) : min(kb, max(k0, e.x));
+      ke = q == 0 ? min(ke, e.y) : max(ke, min(min(k1, np), e.y));
+    }
+  }
+  const int K = ke - kb;
+  if (K <= 0) return;
   const int TN = WC * 32;
   const int N = min(ncols - tn * TN, TN);
   const C* Fi = F + fac_off[i];
   C* Yi = Y + loc_off[i] * ld;
-  const int row = r0 + tm * TM;
-  if (row_lo && row + TM <= row_lo[i]) return;   // rows discarded by the weights
   // FP32: 32*RB-row tiles; FP64: 64-row tiles (two row blocks per wave)
-  gemm3m<R, WC, sizeof(R) == 4 ? RB : 2, FULL>(Fi + (int64_t)row * np + k0, np, Yi + (int64_t)k0 * ld + tn * TN, ld,
+  gemm3m<R, WC, sizeof(R) == 4 ? RB : 2, FULL>(Fi + (int64_t)row * np + kb, np, Yi + (int64_t)kb * ld + tn * TN, ld,
                                                Yi + (int64_t)row * ld + tn * TN, ld, M, N, K);
 }
 
@@ -1093,6 +1106,85 @@ __global__ void __launch_bounds__(256) k_build_perm(const int32_t* __restrict__ 
   for (int l = threadIdx.x; l < np; l += blockDim.x) ridx[o + l] = sub_dof[o + perm[l]];
 }
 
+// Envelope of the factors: one workgroup per (subdomain, 32-row group g).
+// Rows [32g, 32g+32) lie in the diagonal block b = g/2 (columns
+// [64b, 64b+64), which holds the inverted diagonal factors and is excluded).
+// Every wave takes 8 rows; for each it finds the first nonzero column of L
+// left of the block, scanning 64 columns per step from column 0 and
+// stopping at the first step with a nonzero (or at the bound already found),
+// and the last nonzero column of U right of the block, scanning from the last
+// column leftwards in the same way.  Entries
+// outside the envelope stay exactly zero through a factorisation without
+// interchanges, so skipping them changes no result; with interchanges the
+// scan still sees every nonzero.
+template <class C>
+__global__ void __launch_bounds__(256) k_envelope(const C* __restrict__ F, const int64_t* __restrict__ fac_off,
+                                                  const int32_t* __restrict__ n_pad, int stride,
+                                                  int2* __restrict__ env) {
+  const int i = blockIdx.x / stride, g = blockIdx.x % stride;
+  const int np = n_pad[i];
+  const int b0 = (g / 2) * 64, b1 = b0 + 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int lo = b0, hi = b1;
+  if (32 * g < np) {
+    const C* Fi = F + fac_off[i];
+    for (int q = 0; q < 8; ++q) {
+      const C* row = Fi + (int64_t)(32 * g + 8 * wave + q) * np;
+      for (int c0 = 0; c0 < lo; c0 += 64) {
+        const C v = row[c0 + lane];
+        const unsigned long long m = __ballot(v.x != 0 || v.y != 0);
+        if (m) {
+          lo = min(lo, c0 + (int)__builtin_ctzll(m));
+          break;
+        }
+      }
+      for (int c0 = np - 64; c0 + 64 > hi; c0 -= 64) {
+        const C v = row[c0 + lane];
+        const unsigned long long m = __ballot(v.x != 0 || v.y != 0);
+        if (m) {
+          hi = max(hi, c0 + 64 - (int)__builtin_clzll(m));
+          break;
+        }
+      }
+    }
+  }
+  __shared__ int slo[4], shi[4];
+  if (lane == 0) {
+    slo[wave] = lo;
+    shi[wave] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) {
+      lo = min(lo, slo[w]);
+      hi = max(hi, shi[w]);
+    }
+    env[blockIdx.x] = make_int2(lo & ~7, (hi + 7) & ~7);
+  }
+}
+
+// Factor entries and clipped inner dimension of the envelope-restricted
+// update Y[r0:r1] -= F[r0:r1, k0:k1] Y[k0:k1] of subdomain i (n unknowns),
+// 32-row groups at a time: the algorithmic work of one launch.
+static void env_work(const DeviceDecomp& d, int i, int n, int r0, int r1, int k0, int k1, double& fac,
+                     double& kspan) {
+  fac = 0;
+  int kmin = k1, kmax = k0;
+  r1 = std::min(r1, n);
+  k1 = std::min(k1, n);
+  for (int g = r0 / 32; 32 * g < r1; ++g) {
+    const int2 e = d.h_env[(size_t)i * d.env_stride + g];
+    const int rows = std::min(32 * g + 32, r1) - std::max(32 * g, r0);
+    const int kb = std::max(k0, e.x), ke = std::min(k1, e.y);
+    if (rows > 0 && ke > kb) {
+      fac += (double)rows * (ke - kb);
+      kmin = std::min(kmin, kb);
+      kmax = std::max(kmax, ke);
+    }
+  }
+  kspan = kmax > kmin ? kmax - kmin : 0;
+}
+
 template <class C> struct RealOf;
 template <> struct RealOf<float2> { using t = float; };
 template <> struct RealOf<double2> { using t = double; };
@@ -1281,6 +1373,9 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st, bool sym) {
   }, (int)sizeof(C));
   k_build_perm<<<d.nsub, 256, 0, st>>>(d.n_pad, d.loc_off, d.ipiv, d.sub_dof, d.ridx);
   MW_LAUNCH_CHECK();
+  k_envelope<C><<<(unsigned)((int64_t)d.nsub * d.env_stride), 256, 0, st>>>(F, d.fac_off, d.n_pad, d.env_stride,
+                                                                            d.env);
+  MW_LAUNCH_CHECK();
 }
 
 // Tile width (columns) for a multi-vector of ncols columns: the narrowest of
@@ -1302,7 +1397,7 @@ static void launch_gemm_x_wc(const DeviceDecomp& d, const typename cplx<R>::t* F
   int tiles_n = (int)ceil_div(ncols, WC * 32);
   int64_t G = round_up((int64_t)d.nsub * tiles_m * tiles_n, 8);
   k_gemm_x<R, WC, RB, FULL><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, Y, ld, ncols, r0, r1, k0, k1,
-                                                   tiles_m, tiles_n, d.nsub, row_lo);
+                                                   tiles_m, tiles_n, d.nsub, row_lo, d.env, d.env_stride);
   MW_LAUNCH_CHECK();
 }
 // FP32 updates with a long inner dimension take 64-row tiles (two row blocks
@@ -1367,11 +1462,15 @@ static void fwd_rec(const DeviceDecomp& d, const typename cplx<R>::t* F, typenam
   kt_begin(KF_TRSM_GEMM, st);
   launch_gemm_x<R>(d, F, Y, ld, ncols, mid * NB, b1 * NB, b0 * NB, mid * NB, nullptr, st);
   MW_LAUNCH_CHECK();
-  kt_account(d, KF_TRSM_GEMM, st, [&](int n, double& f, double& b) {
-    double Mi = clampd(std::min(b1 * NB, n) - mid * NB), Ki = clampd(std::min(mid * NB, n) - b0 * NB);
-    f = 8.0 * Mi * Ki * ncols;
-    b = Mi * Ki + Ki * ncols + 2 * Mi * ncols;
-  }, esz);
+  {
+    int sub = 0;
+    kt_account(d, KF_TRSM_GEMM, st, [&](int n, double& f, double& b) {
+      double Mi = clampd(std::min(b1 * NB, n) - mid * NB), fac, kspan;
+      env_work(d, sub++, n, mid * NB, b1 * NB, b0 * NB, mid * NB, fac, kspan);
+      f = 8.0 * fac * ncols;
+      b = fac + kspan * ncols + (fac > 0 ? 2 * Mi * ncols : 0.0);
+    }, esz);
+  }
   fwd_rec<R>(d, F, Y, ncols, ld, mid, b1, st);
 }
 
@@ -1400,10 +1499,12 @@ static void bwd_rec(const DeviceDecomp& d, const typename cplx<R>::t* F, typenam
   {
     int sub = 0;
     kt_account(d, KF_TRSM_GEMM, st, [&](int n, double& f, double& b) {
-      const int lo = d.h_row_lo[sub++];
-      double Mi = clampd(std::min(mid * NB, n) - std::max(b0 * NB, lo)), Ki = clampd(std::min(b1 * NB, n) - mid * NB);
-      f = 8.0 * Mi * Ki * ncols;
-      b = Mi * Ki + Ki * ncols + 2 * Mi * ncols;
+      const int i = sub++;
+      const int lo = std::max(b0 * NB, d.h_row_lo[i]);
+      double Mi = clampd(std::min(mid * NB, n) - lo), fac = 0, kspan = 0;
+      if (Mi > 0) env_work(d, i, n, lo, mid * NB, mid * NB, b1 * NB, fac, kspan);
+      f = 8.0 * fac * ncols;
+      b = fac + kspan * ncols + (fac > 0 ? 2 * Mi * ncols : 0.0);
     }, esz);
   }
   bwd_rec<R>(d, F, Y, ncols, ld, b0, mid, st);

@@ -24,6 +24,7 @@ struct DeviceMesh {
   const double2* fbeta = nullptr;   // i*beta coefficient source per boundary face (beta)
   const int64_t* row_ptr = nullptr;
   const int32_t* col = nullptr;
+  const int32_t* rorder = nullptr;   // rows of A in Z-order of their edge midpoints (SpMM locality)
   const int64_t* rt_ptr = nullptr;
   const int32_t* rt = nullptr;
   const int64_t* rf_ptr = nullptr;
@@ -85,6 +86,14 @@ struct DeviceDecomp {
   const int32_t* h_n_loc = nullptr;  // host copy of n_loc (launch accounting)
   const int32_t* row_lo = nullptr;   // [nsub] first row (multiple of 64) the backward solve must produce
   const int32_t* h_row_lo = nullptr; // host copy
+  // envelope of the factors per 32-row group g of every subdomain (entry
+  // i * env_stride + g, env_stride = max_pad / 32), written by the
+  // factorisation: x = first column left of the group's 64-wide diagonal
+  // block holding a nonzero of L (rounded down to 8), y = one past the last
+  // column right of it holding a nonzero of U (rounded up to 8)
+  int2* env = nullptr;
+  const int2* h_env = nullptr;       // host copy (launch accounting)
+  int env_stride = 0;
 };
 
 // ---- assembly (assemble.hip)

@@ -119,12 +119,14 @@ template <int CPL>
 __global__ void __launch_bounds__(256) k_spmm_h(int64_t n, const int64_t* __restrict__ row_ptr,
                                                 const int32_t* __restrict__ col, const double2* __restrict__ val,
                                                 const double2* __restrict__ X, int64_t ldx, double2* __restrict__ Y,
-                                                int64_t ldy, int ncols, const double2* __restrict__ Bs, int64_t ldb) {
+                                                int64_t ldy, int ncols, const double2* __restrict__ Bs, int64_t ldb,
+                                                const int32_t* __restrict__ rorder) {
   const int64_t G = gridDim.x;
   const int64_t blk = (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
-  const int64_t r = (blk * blockDim.x + threadIdx.x) >> 5;
+  const int64_t rr = (blk * blockDim.x + threadIdx.x) >> 5;
   const int lane = threadIdx.x & 31;
-  const bool live = r < n;
+  const bool live = rr < n;
+  const int64_t r = (live && rorder) ? rorder[rr] : rr;
   const int64_t b = live ? row_ptr[r] : 0, e = live ? row_ptr[r + 1] : 0;
   double2 acc[CPL];
 #pragma unroll
@@ -197,7 +199,7 @@ void launch_spmm(const DeviceMesh& m, const double2* val, const double2* X, int6
   else if (ncols <= 128) MW_SPMM_W(2);
   else if (ncols <= 160)
     k_spmm_h<5><<<(unsigned)round_up(ceil_div(n * 32, 256), 8), 256, 0, st>>>(n, m.row_ptr, m.col, val, X, ldx, Y,
-                                                                              ldy, ncols, Bsub, ldb);
+                                                                              ldy, ncols, Bsub, ldb, m.rorder);
   else MW_SPMM_W(3);
 #undef MW_SPMM
 #undef MW_SPMM_W
