@@ -145,6 +145,10 @@ struct Decomposition {
   std::vector<int32_t> n_loc;       // [nsub] n_i
   std::vector<int32_t> n_pad;       // [nsub] n_i rounded up to the block size
   std::vector<int32_t> n_lead;      // [nsub] leading local unknowns with D = 0
+  // [nsub * fenv_stride] per 32-row group of B_i: first column of its rows'
+  // envelope (symmetric pattern: also the first row of its columns' envelope)
+  std::vector<int32_t> fenv;
+  int32_t fenv_stride = 0;
   std::vector<int64_t> loc_off;     // [nsub+1] row offset of subdomain i in local vectors
   std::vector<int64_t> fac_off;     // [nsub+1] element offset of subdomain i's dense matrix
   std::vector<int32_t> sub_dof;     // [sum n_pad] global dof of each local row (-1 padding);

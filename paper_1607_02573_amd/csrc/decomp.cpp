@@ -30,6 +30,7 @@ static const int kFaceEdge[4][3] = {{0, 1, 3}, {0, 2, 4}, {1, 2, 5}, {3, 4, 5}};
 namespace {
 struct SubTmp {
   int32_t n_lead = 0;
+  std::vector<int32_t> fgrp;   // per 32-row group: first column of the rows' envelope
   std::vector<int32_t> tets, edges, lt_loc, lf_vert, lf_owner, lf_kind, lf_loc;
   std::vector<double> D;
   std::vector<int64_t> rtl_ptr, rfl_ptr;
@@ -268,6 +269,21 @@ void build_decomposition(const Topology& T, const int32_t* part, int32_t nsub, i
       int32_t z = 0;
       while (z < ni && Dg[ord[z]] == 0.0) ++z;
       o.n_lead = z;
+      // envelope of B_i in the new order: first coupled column of every row
+      // (the pattern is symmetric, so this also bounds every column from
+      // above); factorisation without interchanges fills only inside it
+      {
+        std::vector<int32_t> inv(ni);
+        for (int32_t k = 0; k < ni; ++k) inv[ord[k]] = k;
+        const int32_t npad0 = (int32_t)round_up(std::max(ni, 1), block);
+        o.fgrp.assign(npad0 / 32, 0);
+        for (int32_t g = 0; g < npad0 / 32; ++g) o.fgrp[g] = 32 * g;
+        for (int32_t k = 0; k < ni; ++k) {
+          int32_t f = k;
+          for (int32_t q = gptr[ord[k]]; q < gptr[ord[k] + 1]; ++q) f = std::min(f, inv[gadj[q]]);
+          o.fgrp[k / 32] = std::min(o.fgrp[k / 32], f);
+        }
+      }
       std::vector<int32_t> e2(ni);
       o.D.resize(ni);
       for (int32_t l = 0; l < ni; ++l) { e2[l] = o.edges[ord[l]]; o.D[l] = Dg[ord[l]]; }
@@ -325,6 +341,14 @@ void build_decomposition(const Topology& T, const int32_t* part, int32_t nsub, i
   D = Decomposition();
   D.nsub = nsub; D.delta = delta;
   D.n_loc.resize(nsub); D.n_pad.resize(nsub); D.n_lead.resize(nsub);
+  {
+    size_t mg = 1;
+    for (int32_t i = 0; i < nsub; ++i) mg = std::max(mg, sub[i].fgrp.size());
+    D.fenv_stride = (int32_t)mg;
+    D.fenv.assign((size_t)nsub * mg, 0);
+    for (int32_t i = 0; i < nsub; ++i)
+      std::copy(sub[i].fgrp.begin(), sub[i].fgrp.end(), D.fenv.begin() + (size_t)i * mg);
+  }
   D.loc_off.assign(nsub + 1, 0); D.fac_off.assign(nsub + 1, 0);
   D.lt_off.assign(nsub + 1, 0); D.lf_off.assign(nsub + 1, 0);
   for (int32_t i = 0; i < nsub; ++i) {

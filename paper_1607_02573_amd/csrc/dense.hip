@@ -147,7 +147,8 @@ __device__ inline void gemm_tile(const typename cplx<R>::t* __restrict__ A, int6
 template <class R, bool LOWER = false>
 __global__ void __launch_bounds__(256) k_gemm_lu(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
                                                  const int32_t* __restrict__ n_pad, int r0, int k0, int k1,
-                                                 int c0, int c1) {
+                                                 int c0, int c1, const int32_t* __restrict__ fenv = nullptr,
+                                                 int fstride = 0) {
   using C = typename cplx<R>::t;
   int i = blockIdx.y;
   int np = n_pad[i];
@@ -158,6 +159,13 @@ __global__ void __launch_bounds__(256) k_gemm_lu(typename cplx<R>::t* F, const i
   int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
   if (tm * TB >= M) return;
   if (LOWER && r0 + tm * TB + TB <= c0 + tn * TB) return;
+  if (fenv) {
+    // no interchanges: L[r, k] and U[k, c] vanish for k below the envelope
+    // start of row r and of column c (64-row/column tiles lie inside np)
+    const int32_t* fe = fenv + (int64_t)i * fstride;
+    const int gr = (r0 + tm * TB) / 32, gc = (c0 + tn * TB) / 32;
+    if (max(min(fe[gr], fe[gr + 1]), min(fe[gc], fe[gc + 1])) >= k1) return;
+  }
   C* Fi = F + fac_off[i];
   gemm_tile<R, false>(Fi + (int64_t)r0 * np + k0, np, Fi + (int64_t)k0 * np + c0, np,
                       Fi + (int64_t)r0 * np + c0, np, M, N, k1 - k0, tm, tn);
@@ -502,7 +510,8 @@ struct LuwTile { static constexpr int TM = 64; };
 template <class R, int WC, bool G3, bool LOWER = false>
 __global__ void __launch_bounds__(256, G3 ? 2 : 1) k_gemm_luw(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
                                                   const int32_t* __restrict__ n_pad, int r0, int r1, int k0, int k1,
-                                                  int c0, int c1, int tiles_m, int tiles_n, int nsub) {
+                                                  int c0, int c1, int tiles_m, int tiles_n, int nsub,
+                                                  const int32_t* __restrict__ fenv, int fstride) {
   using C = typename cplx<R>::t;
   const int per_sub = tiles_m * tiles_n;
   const int G = gridDim.x;
@@ -519,12 +528,24 @@ __global__ void __launch_bounds__(256, G3 ? 2 : 1) k_gemm_luw(typename cplx<R>::
   C* Fi = F + fac_off[i];
   const int row = r0 + tm * TM, col = c0 + tn * 32 * WC;
   if (LOWER && row + TM <= col) return;   // strictly above the diagonal: not needed
+  int kb = k0;
+  if (fenv) {
+    // no interchanges: the products L[r, k] U[k, c] of the tile vanish for k
+    // below max(first envelope column of its rows, of its columns)
+    const int32_t* fe = fenv + (int64_t)i * fstride;
+    int fr = fe[row / 32], fc = fe[col / 32];
+#pragma unroll
+    for (int q = 1; q < TM / 32; ++q) fr = min(fr, fe[row / 32 + q]);
+    for (int q = 1; q < WC && col + 32 * q < min(c1, np); ++q) fc = min(fc, fe[col / 32 + q]);
+    kb = max(k0, max(fr, fc) & ~7);
+    if (kb >= k1) return;
+  }
   if constexpr (G3)
-    gemm3m<R, WC, 2>(Fi + (int64_t)row * np + k0, np, Fi + (int64_t)k0 * np + col, np, Fi + (int64_t)row * np + col,
-                  np, M, min(N, 32 * WC), k1 - k0);
+    gemm3m<R, WC, 2>(Fi + (int64_t)row * np + kb, np, Fi + (int64_t)kb * np + col, np, Fi + (int64_t)row * np + col,
+                  np, M, min(N, 32 * WC), k1 - kb);
   else
-    gemm_wide<R, WC>(Fi + (int64_t)row * np + k0, np, Fi + (int64_t)k0 * np + col, np,
-                     Fi + (int64_t)row * np + col, np, M, min(N, 32 * WC), k1 - k0);
+    gemm_wide<R, WC>(Fi + (int64_t)row * np + kb, np, Fi + (int64_t)kb * np + col, np,
+                     Fi + (int64_t)row * np + col, np, M, min(N, 32 * WC), k1 - kb);
 }
 
 template <class R, int WC, bool G3 = false, bool LOWER = false>
@@ -534,8 +555,10 @@ static void launch_gemm_lu(const DeviceDecomp& d, typename cplx<R>::t* F, int r0
   int tiles_n = (int)ceil_div(std::min(c1, maxp) - c0, 32 * WC);
   if (tiles_m <= 0 || tiles_n <= 0 || k1 <= k0) return;
   int64_t G = round_up((int64_t)d.nsub * tiles_m * tiles_n, 8);
+  // envelope clipping only for the factorisation without interchanges
   k_gemm_luw<R, WC, G3, LOWER><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, r0, r1, k0, k1, c0, c1,
-                                                            tiles_m, tiles_n, d.nsub);
+                                                            tiles_m, tiles_n, d.nsub, LOWER ? d.fenv : nullptr,
+                                                            d.fenv_stride);
   MW_LAUNCH_CHECK();
 }
 
@@ -1185,6 +1208,37 @@ static void env_work(const DeviceDecomp& d, int i, int n, int r0, int r1, int k0
   kspan = kmax > kmin ? kmax - kmin : 0;
 }
 
+// Algorithmic work of the lower-triangle update
+// F[r, c] -= sum_{k in [k0, k1)} L[r, k] U[k, c], r >= r0, c in [c0, c1), c <= r,
+// of subdomain i (n unknowns) inside the envelope, 32 x 32 blocks at a time:
+// rows and columns with a nonzero product, entries updated, and complex
+// multiply-adds.
+static void fenv_work(const DeviceDecomp& d, int i, int n, int r0, int k0, int k1, int c0, int c1, double& rows,
+                      double& cols, double& entries, double& macs) {
+  rows = cols = entries = macs = 0;
+  const int32_t* fe = d.h_fenv + (size_t)i * d.fenv_stride;
+  c1 = std::min(c1, n);
+  k1 = std::min(k1, n);
+  if (k1 <= k0) return;
+  for (int g = r0 / 32; 32 * g < n; ++g) {
+    const int rg = std::min(32 * g + 32, n) - std::max(32 * g, r0);
+    if (rg <= 0 || fe[g] >= k1) continue;
+    bool any = false;
+    for (int h = c0 / 32; 32 * h < c1 && h <= g; ++h) {
+      const int ch = std::min(32 * h + 32, c1) - std::max(32 * h, c0);
+      const int kb = std::max(k0, std::max(fe[g], fe[h]));
+      if (ch <= 0 || kb >= k1) continue;
+      const double e = h < g ? (double)rg * ch : (double)rg * (rg + 1) / 2;
+      entries += e;
+      macs += e * (k1 - kb);
+      any = true;
+    }
+    if (any) rows += rg;
+  }
+  for (int h = c0 / 32; 32 * h < c1; ++h)
+    if (fe[h] < k1) cols += std::min(32 * h + 32, c1) - std::max(32 * h, c0);
+}
+
 template <class C> struct RealOf;
 template <> struct RealOf<float2> { using t = float; };
 template <> struct RealOf<double2> { using t = double; };
@@ -1298,13 +1352,15 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st, bool sym) {
           kt_begin(KF_LU_GEMM, st);
           int M = maxp - c0, N = Kend - c0;
           unsigned tiles = (unsigned)(ceil_div(M, TB) * ceil_div(N, TB));
-          k_gemm_lu<R, true><<<dim3(tiles, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, c0, k, k + NB, c0, Kend);
+          k_gemm_lu<R, true><<<dim3(tiles, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, c0, k, k + NB, c0, Kend,
+                                                                  d.fenv, d.fenv_stride);
           MW_LAUNCH_CHECK();
+          int sub = 0;
           kt_account(d, KF_LU_GEMM, st, [&](int n, double& f, double& b) {
-            double M2 = clampd(n - c0), N2 = clampd(std::min(Kend, n) - c0), K = clampd(std::min(k + NB, n) - k);
-            double lower = N2 * M2 - N2 * (N2 - 1) / 2;
-            f = 8.0 * lower * K;
-            b = M2 * K + K * N2 + 2 * lower;
+            double M2, N2, entries, kk;
+            fenv_work(d, sub++, n, c0, k, k + NB, c0, Kend, M2, N2, entries, kk);
+            f = 8.0 * kk;
+            b = M2 * NB + NB * N2 + 2 * entries;
           }, (int)sizeof(C));
         }
         continue;
@@ -1355,11 +1411,18 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st, bool sym) {
       kt_begin(KF_LU_GEMM, st);
       if (sym) launch_gemm_lu<R, WCL, true, true>(d, F, Kend, maxp, K0, Kend, Kend, maxp, maxp, st);
       else launch_gemm_lu<R, WCL, true>(d, F, Kend, maxp, K0, Kend, Kend, maxp, maxp, st);
+      int sub = 0;
       kt_account(d, KF_LU_GEMM, st, [&](int n, double& f, double& b) {
         double M2 = clampd(n - Kend), K = clampd(std::min(Kend, n) - K0);
-        double C2 = sym ? M2 * (M2 + 1) / 2 : M2 * M2;   // entries updated
-        f = 8.0 * C2 * K;
-        b = M2 * K + K * M2 + 2 * C2;
+        if (sym) {
+          double R2, C2, entries, kk;
+          fenv_work(d, sub++, n, Kend, K0, Kend, Kend, maxp, R2, C2, entries, kk);
+          f = 8.0 * kk;
+          b = R2 * K + K * C2 + 2 * entries;
+        } else {
+          f = 8.0 * M2 * M2 * K;
+          b = M2 * K + K * M2 + 2 * M2 * M2;
+        }
       }, (int)sizeof(C));
     }
   }

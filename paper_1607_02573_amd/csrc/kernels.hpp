@@ -91,6 +91,9 @@ struct DeviceDecomp {
   // factorisation: x = first column left of the group's 64-wide diagonal
   // block holding a nonzero of L (rounded down to 8), y = one past the last
   // column right of it holding a nonzero of U (rounded up to 8)
+  const int32_t* fenv = nullptr;     // [nsub * fenv_stride] structural envelope of B_i per 32-row group
+  const int32_t* h_fenv = nullptr;   // host copy
+  int fenv_stride = 0;
   int2* env = nullptr;
   const int2* h_env = nullptr;       // host copy (launch accounting)
   int env_stride = 0;
