@@ -1031,12 +1031,16 @@ __global__ void __launch_bounds__(256) k_sym_diag(typename cplx<R>::t* F, const 
 // block (U_kk^-1 read from where k_sym_diag left it).
 template <class R>
 __global__ void __launch_bounds__(256) k_sym_cols(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
-                                                  const int32_t* __restrict__ n_pad, int k) {
+                                                  const int32_t* __restrict__ n_pad, int k,
+                                                  const int32_t* __restrict__ fenv, int fstride) {
   using C = typename cplx<R>::t;
   const int i = blockIdx.y;
   const int np = n_pad[i];
   const int rb = k + NB + blockIdx.x * NB;
   if (rb >= np) return;
+  // rows whose envelope starts right of the panel: A_rk = 0, L_rk stays 0
+  const int32_t* fe = fenv + (int64_t)i * fstride;
+  if (min(fe[rb / 32], fe[rb / 32 + 1]) >= k + NB) return;
   C* Fi = F + fac_off[i];
   __shared__ C A[NB][NB + 1];
   __shared__ C U[NB][NB + 1];
@@ -1067,12 +1071,17 @@ __global__ void __launch_bounds__(256) k_sym_cols(typename cplx<R>::t* F, const 
 // workgroup per 64 columns j, the 64 x 64 tile transposed through LDS.
 template <class R>
 __global__ void __launch_bounds__(256) k_sym_row(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
-                                                 const int32_t* __restrict__ n_pad, int k) {
+                                                 const int32_t* __restrict__ n_pad, int k,
+                                                 const int32_t* __restrict__ fenv, int fstride) {
   using C = typename cplx<R>::t;
   const int i = blockIdx.y;
   const int np = n_pad[i];
   const int jb = k + NB + blockIdx.x * NB;
   if (jb >= np) return;
+  // columns whose envelope starts below the panel: their U entries are, and
+  // stay, zero; the first block always runs (it holds U_kk^-1 until now)
+  const int32_t* fe = fenv + (int64_t)i * fstride;
+  if (jb > k + NB && min(fe[jb / 32], fe[jb / 32 + 1]) >= k + NB) return;
   C* Fi = F + fac_off[i];
   __shared__ C T[NB][NB + 1];
   __shared__ C dg[NB];
@@ -1239,6 +1248,18 @@ static void fenv_work(const DeviceDecomp& d, int i, int n, int r0, int k0, int k
     if (fe[h] < k1) cols += std::min(32 * h + 32, c1) - std::max(32 * h, c0);
 }
 
+// Rows in 64-row blocks from r0 on whose envelope starts left of kend (the
+// blocks the symmetric panel kernels process; with `first`, the block at r0
+// always counts).
+static double fenv_rows(const DeviceDecomp& d, int i, int n, int r0, int kend, bool first) {
+  const int32_t* fe = d.h_fenv + (size_t)i * d.fenv_stride;
+  double rows = 0;
+  for (int rb = r0; rb < n; rb += 64)
+    if ((first && rb == r0) || std::min(fe[rb / 32], rb + 32 < n ? fe[rb / 32 + 1] : fe[rb / 32]) < kend)
+      rows += std::min(64, n - rb);
+  return rows;
+}
+
 template <class C> struct RealOf;
 template <> struct RealOf<float2> { using t = float; };
 template <> struct RealOf<double2> { using t = double; };
@@ -1286,11 +1307,13 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st, bool sym) {
         MW_LAUNCH_CHECK();
         if (k + NB < maxp) {
           k_sym_cols<R><<<dim3((unsigned)ceil_div(maxp - k - NB, NB), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad,
-                                                                                             k);
+                                                                                             k, d.fenv,
+                                                                                             d.fenv_stride);
           MW_LAUNCH_CHECK();
         }
+        int sub = 0;
         kt_account(d, KF_LU_PANEL, st, [&](int n, double& f, double& b) {
-          double rows = clampd(n - k - NB);
+          double rows = fenv_rows(d, sub++, n, k + NB, k + NB, false);
           f = n > k ? 8.0 * (NB * NB * NB / 3.0 + rows * NB * NB / 2.0) : 0;
           b = n > k ? 2.0 * (NB + rows) * NB : 0;
         }, (int)sizeof(C));
@@ -1341,13 +1364,17 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st, bool sym) {
         // block below the diagonal
         if (c0 >= maxp) continue;
         kt_begin(KF_LU_OTHER, st);
-        k_sym_row<R><<<dim3((unsigned)ceil_div(maxp - c0, NB), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, k);
+        k_sym_row<R><<<dim3((unsigned)ceil_div(maxp - c0, NB), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, k,
+                                                                                        d.fenv, d.fenv_stride);
         MW_LAUNCH_CHECK();
-        kt_account(d, KF_LU_OTHER, st, [&](int n, double& f, double& b) {
-          double N = clampd(n - c0);
-          f = 6.0 * NB * N;
-          b = 2.0 * NB * N;
-        }, (int)sizeof(C));
+        {
+          int sub = 0;
+          kt_account(d, KF_LU_OTHER, st, [&](int n, double& f, double& b) {
+            double N = fenv_rows(d, sub++, n, c0, k + NB, true);
+            f = 6.0 * NB * N;
+            b = 2.0 * NB * N;
+          }, (int)sizeof(C));
+        }
         if (c0 < Kend) {
           kt_begin(KF_LU_GEMM, st);
           int M = maxp - c0, N = Kend - c0;
