@@ -424,8 +424,8 @@ __device__ __attribute__((always_inline)) inline void gemm3m(const typename cplx
       }
 }
 
-// rows per tile of the triangular-solve updates: 32*RB (3M, FP32) or 64 (4M, FP64)
-template <class R, int RB = 1> struct XTile { static constexpr int TM = sizeof(R) == 4 ? 32 * RB : 64; };
+// rows per tile of the triangular-solve updates (3M form)
+template <class R, int RB = 1> struct XTile { static constexpr int TM = 32 * RB; };
 
 // Triangular-solve update on the local multi-vector of every subdomain:
 // Y[r0:min(r1,np)] -= F[r0:min(r1,np), k0:min(k1,np)] * Y[k0:min(k1,np)].
@@ -471,9 +471,8 @@ __global__ void __launch_bounds__(256, (sizeof(R) == 8 && WC >= 2) ? 2 : RB) k_g
   const int N = min(ncols - tn * TN, TN);
   const C* Fi = F + fac_off[i];
   C* Yi = Y + loc_off[i] * ld;
-  // FP32: 32*RB-row tiles; FP64: 64-row tiles (two row blocks per wave)
-  gemm3m<R, WC, sizeof(R) == 4 ? RB : 2, FULL>(Fi + (int64_t)row * np + kb, np, Yi + (int64_t)kb * ld + tn * TN, ld,
-                                               Yi + (int64_t)row * ld + tn * TN, ld, M, N, K);
+  gemm3m<R, WC, RB, FULL>(Fi + (int64_t)row * np + kb, np, Yi + (int64_t)kb * ld + tn * TN, ld,
+                          Yi + (int64_t)row * ld + tn * TN, ld, M, N, K);
 }
 
 // Leaf of the blocked triangular solves: Y[r0:r0+64] = T^-1 Y[r0:r0+64] with the
@@ -1195,12 +1194,14 @@ __global__ void __launch_bounds__(256) k_envelope(const C* __restrict__ F, const
   }
 }
 
-// Factor entries and clipped inner dimension of the envelope-restricted
-// update Y[r0:r1] -= F[r0:r1, k0:k1] Y[k0:k1] of subdomain i (n unknowns),
-// 32-row groups at a time: the algorithmic work of one launch.
+// Factor entries, clipped inner dimension and rows with work of the
+// envelope-restricted update Y[r0:r1] -= F[r0:r1, k0:k1] Y[k0:k1] of
+// subdomain i (n unknowns), 32-row groups at a time: the algorithmic work of
+// one launch.
 static void env_work(const DeviceDecomp& d, int i, int n, int r0, int r1, int k0, int k1, double& fac,
-                     double& kspan) {
+                     double& kspan, double& rows_work) {
   fac = 0;
+  rows_work = 0;
   int kmin = k1, kmax = k0;
   r1 = std::min(r1, n);
   k1 = std::min(k1, n);
@@ -1210,6 +1211,7 @@ static void env_work(const DeviceDecomp& d, int i, int n, int r0, int r1, int k0
     const int kb = std::max(k0, e.x), ke = std::min(k1, e.y);
     if (rows > 0 && ke > kb) {
       fac += (double)rows * (ke - kb);
+      rows_work += rows;
       kmin = std::min(kmin, kb);
       kmax = std::max(kmax, ke);
     }
@@ -1490,9 +1492,9 @@ static void launch_gemm_x_wc(const DeviceDecomp& d, const typename cplx<R>::t* F
                                                    tiles_m, tiles_n, d.nsub, row_lo, d.env, d.env_stride);
   MW_LAUNCH_CHECK();
 }
-// FP32 updates with a long inner dimension take 64-row tiles (two row blocks
-// per wave: half the B reads per product, lower occupancy).
-constexpr int RB2_MIN_K = 256;
+// The updates take 32-row tiles: clipped to the banded envelope their inner
+// dimension is a few hundred at most, where more and smaller tiles balance
+// better than 64-row tiles with half the B reads per product.
 template <class R>
 static void launch_gemm_x(const DeviceDecomp& d, const typename cplx<R>::t* F, typename cplx<R>::t* Y, int64_t ld,
                           int ncols, int r0, int r1, int k0, int k1, const int32_t* row_lo, hipStream_t st) {
@@ -1502,10 +1504,10 @@ static void launch_gemm_x(const DeviceDecomp& d, const typename cplx<R>::t* F, t
     case 3: launch_gemm_x_wc<R, sizeof(R) == 4 ? 3 : 2>(d, F, Y, ld, ncols, r0, r1, k0, k1, row_lo, st); break;
     case 4: launch_gemm_x_wc<R, sizeof(R) == 4 ? 4 : 2>(d, F, Y, ld, ncols, r0, r1, k0, k1, row_lo, st); break;
     default:
-      // full tiles: every row and K range is a multiple of 64, so only the
-      // column count decides
-      if (sizeof(R) == 4 && k1 - k0 >= RB2_MIN_K && ncols % 160 == 0)
-        launch_gemm_x_wc<R, sizeof(R) == 4 ? 5 : 2, 2, true>(d, F, Y, ld, ncols, r0, r1, k0, k1, row_lo, st);
+      // full column tiles: rows and K ranges are multiples of 32 and 8, so
+      // only the column count decides between the unchecked and checked forms
+      if (sizeof(R) == 4 && ncols % 160 == 0)
+        launch_gemm_x_wc<R, 5, 1, true>(d, F, Y, ld, ncols, r0, r1, k0, k1, row_lo, st);
       else
         launch_gemm_x_wc<R, sizeof(R) == 4 ? 5 : 2>(d, F, Y, ld, ncols, r0, r1, k0, k1, row_lo, st);
       break;
@@ -1555,10 +1557,10 @@ static void fwd_rec(const DeviceDecomp& d, const typename cplx<R>::t* F, typenam
   {
     int sub = 0;
     kt_account(d, KF_TRSM_GEMM, st, [&](int n, double& f, double& b) {
-      double Mi = clampd(std::min(b1 * NB, n) - mid * NB), fac, kspan;
-      env_work(d, sub++, n, mid * NB, b1 * NB, b0 * NB, mid * NB, fac, kspan);
+      double fac, kspan, rows;
+      env_work(d, sub++, n, mid * NB, b1 * NB, b0 * NB, mid * NB, fac, kspan, rows);
       f = 8.0 * fac * ncols;
-      b = fac + kspan * ncols + (fac > 0 ? 2 * Mi * ncols : 0.0);
+      b = fac + kspan * ncols + 2 * rows * ncols;
     }, esz);
   }
   fwd_rec<R>(d, F, Y, ncols, ld, mid, b1, st);
@@ -1591,10 +1593,10 @@ static void bwd_rec(const DeviceDecomp& d, const typename cplx<R>::t* F, typenam
     kt_account(d, KF_TRSM_GEMM, st, [&](int n, double& f, double& b) {
       const int i = sub++;
       const int lo = std::max(b0 * NB, d.h_row_lo[i]);
-      double Mi = clampd(std::min(mid * NB, n) - lo), fac = 0, kspan = 0;
-      if (Mi > 0) env_work(d, i, n, lo, mid * NB, mid * NB, b1 * NB, fac, kspan);
+      double fac = 0, kspan = 0, rows = 0;
+      if (std::min(mid * NB, n) > lo) env_work(d, i, n, lo, mid * NB, mid * NB, b1 * NB, fac, kspan, rows);
       f = 8.0 * fac * ncols;
-      b = fac + kspan * ncols + (fac > 0 ? 2 * Mi * ncols : 0.0);
+      b = fac + kspan * ncols + 2 * rows * ncols;
     }, esz);
   }
   bwd_rec<R>(d, F, Y, ncols, ld, b0, mid, st);
