@@ -1522,16 +1522,13 @@ static void launch_leaf_x_wc(const DeviceDecomp& d, const typename cplx<R>::t* F
                                                      d.nsub, row_lo);
   MW_LAUNCH_CHECK();
 }
+// The leaves take 32-column tiles whatever the width: one 64 x 64 block per
+// subdomain is too little work per launch, and more, narrower workgroups
+// (the inverted block re-read from L2 by each) hide the load latency better.
 template <class R, int AMODE>
 static void launch_leaf_x(const DeviceDecomp& d, const typename cplx<R>::t* F, typename cplx<R>::t* Y, int64_t ld,
                           int ncols, int r0, const int32_t* row_lo, hipStream_t st) {
-  switch (pick_wc<R>(ncols)) {
-    case 1: launch_leaf_x_wc<R, 1, AMODE>(d, F, Y, ld, ncols, r0, row_lo, st); break;
-    case 2: launch_leaf_x_wc<R, 2, AMODE>(d, F, Y, ld, ncols, r0, row_lo, st); break;
-    case 3: launch_leaf_x_wc<R, sizeof(R) == 4 ? 3 : 2, AMODE>(d, F, Y, ld, ncols, r0, row_lo, st); break;
-    case 4: launch_leaf_x_wc<R, sizeof(R) == 4 ? 4 : 2, AMODE>(d, F, Y, ld, ncols, r0, row_lo, st); break;
-    default: launch_leaf_x_wc<R, sizeof(R) == 4 ? 5 : 2, AMODE>(d, F, Y, ld, ncols, r0, row_lo, st); break;
-  }
+  launch_leaf_x_wc<R, 1, AMODE>(d, F, Y, ld, ncols, r0, row_lo, st);
 }
 
 template <class R>
