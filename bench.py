@@ -44,8 +44,8 @@ FP64_MFMA_FAMILIES = ("bgs_dots", "bgs_update")
 # known size (--copy-probe-mib).  Valid only for the kernel source it was
 # taken on: a different hash of that file reports null.
 PMC_TRAFFIC = {"family": "trsm_gemm", "source": "paper_1607_02573_amd/csrc/dense.hip",
-               "sha256": "e9faaf835674e0c020a86bfaf4ae4181b4020fd52deea3cad9cf4e159bcdc5d3",
-               "bytes_per_launch": 1.7818e9}   # FETCH 1.5214e9 + WRITE 2.604e8 (pmc_trsm_gemm_chamber10_mixed)
+               "sha256": "0e41d19a023623cfc9b020898b2266957a1657c790d1343d5dbf887665c9fbe8",
+               "bytes_per_launch": 7.773e8}   # FETCH 5.718e8 + WRITE 2.055e8 (pmc_trsm_gemm_chamber10_mixed)
 
 
 def measured_traffic(family: str):
