@@ -94,6 +94,31 @@ def test_host_decomposition_matches_oracle(L, which, nsub):
     np.testing.assert_allclose(tot, 1.0, atol=1e-15)
 
 
+def test_factorisation_fills_only_the_envelope(L):
+    """The triangular solves and the L D L^T updates skip every product
+    outside the envelope of B_i in the library's local order: elimination
+    without interchanges (numpy, row by row) leaves L[r, c] = 0 for c left of
+    the first coupled column of row r and U[r, c] = 0 above that of column c,
+    exactly (George & Liu's envelope theorem)."""
+    from paper_1607_02573_amd import binding
+    w = mi.configs.cube8()
+    m = w.mesh
+    part = mi.partition.rcb(m, 8)
+    dec = binding.host_decomposition(m.xyz, m.tet, m.bface, m.btag, part, 8, 1)
+    fp = fem.build(m, w.eps, w.k0, w.beta_imp, w.ports)
+    s = dd.decompose(fp, part, 1, factor=False)[0]
+    pos = np.searchsorted(s.gdof, dec["sub_dof"][0])
+    F = s.B.tocsr()[pos][:, pos].toarray()
+    n = F.shape[0]
+    first = np.array([min(np.nonzero(F[r])[0].min(), r) for r in range(n)])
+    for k in range(n - 1):
+        F[k + 1:, k] /= F[k, k]
+        F[k + 1:, k + 1:] -= np.outer(F[k + 1:, k], F[k, k + 1:])
+    outside = np.arange(n)[None, :] < first[:, None]       # (r, c) left of row r's envelope
+    assert not F[outside].any() and not F.T[outside].any()
+    assert outside.sum() > 0.5 * n * (n - 1) / 2            # most of the triangle lies outside
+
+
 def test_host_decomposition_overlap_two(L):
     from paper_1607_02573_amd import binding
     w = mi.configs.cube(4, n_sub=4)
