@@ -128,7 +128,7 @@ struct mw_problem {
   Decomposition D;
   DevBuf d_fac_off, d_loc_off, d_n_loc, d_n_pad, d_lt_off, d_lt_tet, d_lt_loc, d_lf_off, d_lf_vert, d_lf_owner,
       d_lf_kind, d_lf_loc, d_rtl_ptr, d_rtl, d_rfl_ptr, d_rfl, d_sub_dof, d_D, d_cp_ptr, d_cp_row, d_ipiv, d_ridx,
-      d_info, d_amax, d_row_lo, d_env, d_fenv;
+      d_info, d_amax, d_row_lo, d_env, d_fenv, d_fenvh;
   std::vector<int32_t> h_row_lo;
   std::vector<int2> h_env;
   DeviceDecomp dd;
@@ -352,9 +352,12 @@ void upload_decomp(mw_problem* p) {
   d.h_row_lo = p->h_row_lo.data();
   p->d_fenv = upload(c, p->stream, D.fenv);
   d.fenv = p->d_fenv.as<int32_t>();
+  p->d_fenvh = upload(c, p->stream, D.fenv_hi);
+  d.fenv_hi = p->d_fenvh.as<int32_t>();
   d.h_fenv = p->D.fenv.data();
   d.fenv_stride = D.fenv_stride;
   d.env_stride = d.max_pad / 32;
+  MW_CHECK(d.fenv_stride == d.env_stride, MW_EINVAL, "envelope tables of unequal strides");
   p->h_env.assign((size_t)d.nsub * d.env_stride, make_int2(0, 0));
   p->d_env = dalloc(c, (int64_t)p->h_env.size() * 8);
   d.env = p->d_env.as<int2>();

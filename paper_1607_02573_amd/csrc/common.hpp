@@ -148,6 +148,8 @@ struct Decomposition {
   // [nsub * fenv_stride] per 32-row group of B_i: first column of its rows'
   // envelope (symmetric pattern: also the first row of its columns' envelope)
   std::vector<int32_t> fenv;
+  // same layout: one past the last column whose envelope reaches the group's rows
+  std::vector<int32_t> fenv_hi;
   int32_t fenv_stride = 0;
   std::vector<int64_t> loc_off;     // [nsub+1] row offset of subdomain i in local vectors
   std::vector<int64_t> fac_off;     // [nsub+1] element offset of subdomain i's dense matrix

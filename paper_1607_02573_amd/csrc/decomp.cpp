@@ -31,6 +31,7 @@ namespace {
 struct SubTmp {
   int32_t n_lead = 0;
   std::vector<int32_t> fgrp;   // per 32-row group: first column of the rows' envelope
+  std::vector<int32_t> hgrp;   // per 32-row group: one past the last column whose envelope reaches it
   std::vector<int32_t> tets, edges, lt_loc, lf_vert, lf_owner, lf_kind, lf_loc;
   std::vector<double> D;
   std::vector<int64_t> rtl_ptr, rfl_ptr;
@@ -278,10 +279,19 @@ void build_decomposition(const Topology& T, const int32_t* part, int32_t nsub, i
         const int32_t npad0 = (int32_t)round_up(std::max(ni, 1), block);
         o.fgrp.assign(npad0 / 32, 0);
         for (int32_t g = 0; g < npad0 / 32; ++g) o.fgrp[g] = 32 * g;
+        // hgrp[g]: columns c with first(c) <= 32g + 31 end before it
+        o.hgrp.assign(npad0 / 32, 0);
+        std::vector<int32_t> best(npad0 / 32, -1);
         for (int32_t k = 0; k < ni; ++k) {
           int32_t f = k;
           for (int32_t q = gptr[ord[k]]; q < gptr[ord[k] + 1]; ++q) f = std::min(f, inv[gadj[q]]);
           o.fgrp[k / 32] = std::min(o.fgrp[k / 32], f);
+          best[f / 32] = std::max(best[f / 32], k);
+        }
+        int32_t run = -1;
+        for (int32_t g = 0; g < npad0 / 32; ++g) {
+          run = std::max(run, best[g]);
+          o.hgrp[g] = std::max(32 * g + 32, run + 1);
         }
       }
       std::vector<int32_t> e2(ni);
@@ -346,8 +356,11 @@ void build_decomposition(const Topology& T, const int32_t* part, int32_t nsub, i
     for (int32_t i = 0; i < nsub; ++i) mg = std::max(mg, sub[i].fgrp.size());
     D.fenv_stride = (int32_t)mg;
     D.fenv.assign((size_t)nsub * mg, 0);
-    for (int32_t i = 0; i < nsub; ++i)
+    D.fenv_hi.assign((size_t)nsub * mg, 0);
+    for (int32_t i = 0; i < nsub; ++i) {
       std::copy(sub[i].fgrp.begin(), sub[i].fgrp.end(), D.fenv.begin() + (size_t)i * mg);
+      std::copy(sub[i].hgrp.begin(), sub[i].hgrp.end(), D.fenv_hi.begin() + (size_t)i * mg);
+    }
   }
   D.loc_off.assign(nsub + 1, 0); D.fac_off.assign(nsub + 1, 0);
   D.lt_off.assign(nsub + 1, 0); D.lf_off.assign(nsub + 1, 0);

@@ -570,18 +570,23 @@ __device__ inline Piv piv_max(Piv a, Piv b) {
 
 // largest |re|+|im| of every B_i (scale of the singular-pivot test)
 template <class R>
+// (only the envelope of B_i is read: every entry outside it is zero)
 __global__ void __launch_bounds__(256) k_amax(const typename cplx<R>::t* __restrict__ F,
                                               const int64_t* __restrict__ fac_off, const int32_t* __restrict__ n_pad,
-                                              double* __restrict__ amax) {
+                                              const int32_t* __restrict__ fenv, const int32_t* __restrict__ fenv_hi,
+                                              int fstride, double* __restrict__ amax) {
   __shared__ double red[4];
   int i = blockIdx.x;
-  int64_t tot = (int64_t)n_pad[i] * n_pad[i];
+  const int np = n_pad[i];
   const auto* Fi = F + fac_off[i];
   double m = 0.0;
-  for (int64_t k = threadIdx.x; k < tot; k += 256) {
-    auto v = Fi[k];
-    double a = fabs((double)v.x) + fabs((double)v.y);
-    m = a > m ? a : m;
+  for (int g = 0; 32 * g < np; ++g) {
+    const int c0 = fenv[(int64_t)i * fstride + g], w = min(fenv_hi[(int64_t)i * fstride + g], np) - c0;
+    for (int k = threadIdx.x; k < 32 * w; k += 256) {
+      auto v = Fi[(int64_t)(32 * g + k / w) * np + c0 + k % w];
+      double a = fabs((double)v.x) + fabs((double)v.y);
+      m = a > m ? a : m;
+    }
   }
   for (int off = 32; off > 0; off >>= 1) {
     double o = __shfl_xor(m, off);
@@ -1151,7 +1156,8 @@ __global__ void __launch_bounds__(256) k_build_perm(const int32_t* __restrict__ 
 template <class C>
 __global__ void __launch_bounds__(256) k_envelope(const C* __restrict__ F, const int64_t* __restrict__ fac_off,
                                                   const int32_t* __restrict__ n_pad, int stride,
-                                                  int2* __restrict__ env) {
+                                                  const int32_t* __restrict__ fenv,
+                                                  const int32_t* __restrict__ fenv_hi, int2* __restrict__ env) {
   const int i = blockIdx.x / stride, g = blockIdx.x % stride;
   const int np = n_pad[i];
   const int b0 = (g / 2) * 64, b1 = b0 + 64;
@@ -1159,9 +1165,13 @@ __global__ void __launch_bounds__(256) k_envelope(const C* __restrict__ F, const
   int lo = b0, hi = b1;
   if (32 * g < np) {
     const C* Fi = F + fac_off[i];
+    // without interchanges nothing lies outside the structural envelope of
+    // B_i, so the scans may start at its 64-column steps (else at the edges)
+    const int l0 = fenv ? min(b0, fenv[blockIdx.x] & ~63) : 0;
+    const int u0 = fenv_hi ? max(b1, min(np, (fenv_hi[blockIdx.x] + 63) & ~63)) : np;
     for (int q = 0; q < 8; ++q) {
       const C* row = Fi + (int64_t)(32 * g + 8 * wave + q) * np;
-      for (int c0 = 0; c0 < lo; c0 += 64) {
+      for (int c0 = l0; c0 < lo; c0 += 64) {
         const C v = row[c0 + lane];
         const unsigned long long m = __ballot(v.x != 0 || v.y != 0);
         if (m) {
@@ -1169,7 +1179,7 @@ __global__ void __launch_bounds__(256) k_envelope(const C* __restrict__ F, const
           break;
         }
       }
-      for (int c0 = np - 64; c0 + 64 > hi; c0 -= 64) {
+      for (int c0 = u0 - 64; c0 + 64 > hi; c0 -= 64) {
         const C v = row[c0 + lane];
         const unsigned long long m = __ballot(v.x != 0 || v.y != 0);
         if (m) {
@@ -1287,7 +1297,7 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st, bool sym) {
   using R = typename RealOf<C>::t;
   MW_CHECK(d.max_pad <= 8192, MW_EINVAL, "subdomain too large for the dense factorisation (n_i > 8192)");
   const int maxp = d.max_pad;
-  k_amax<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.amax);
+  k_amax<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.fenv, d.fenv_hi, d.fenv_stride, d.amax);
   MW_LAUNCH_CHECK();
   const double rtol = sizeof(R) == 4 ? 1e-6 : 1e-14;
   // Right-looking blocked LU in two levels: 64-column panels (8-column
@@ -1465,8 +1475,8 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st, bool sym) {
   }, (int)sizeof(C));
   k_build_perm<<<d.nsub, 256, 0, st>>>(d.n_pad, d.loc_off, d.ipiv, d.sub_dof, d.ridx);
   MW_LAUNCH_CHECK();
-  k_envelope<C><<<(unsigned)((int64_t)d.nsub * d.env_stride), 256, 0, st>>>(F, d.fac_off, d.n_pad, d.env_stride,
-                                                                            d.env);
+  k_envelope<C><<<(unsigned)((int64_t)d.nsub * d.env_stride), 256, 0, st>>>(
+      F, d.fac_off, d.n_pad, d.env_stride, sym ? d.fenv : nullptr, sym ? d.fenv_hi : nullptr, d.env);
   MW_LAUNCH_CHECK();
 }
 

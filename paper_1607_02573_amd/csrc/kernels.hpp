@@ -93,6 +93,7 @@ struct DeviceDecomp {
   // column right of it holding a nonzero of U (rounded up to 8)
   const int32_t* fenv = nullptr;     // [nsub * fenv_stride] structural envelope of B_i per 32-row group
   const int32_t* h_fenv = nullptr;   // host copy
+  const int32_t* fenv_hi = nullptr;  // [nsub * fenv_stride] one past the last column of B_i reaching the group
   int fenv_stride = 0;
   int2* env = nullptr;
   const int2* h_env = nullptr;       // host copy (launch accounting)
