@@ -154,7 +154,7 @@ struct Decomposition {
   std::vector<int64_t> loc_off;     // [nsub+1] row offset of subdomain i in local vectors
   std::vector<int64_t> fac_off;     // [nsub+1] element offset of subdomain i's dense matrix
   std::vector<int32_t> sub_dof;     // [sum n_pad] global dof of each local row (-1 padding);
-                                    // zero-weight unknowns first, each group ascending
+                                    // reverse Cuthill-McKee order within each subdomain
   std::vector<double> D;            // [sum n_pad] partition-of-unity weight (0 padding)
   // prolongation: copies of every global dof (CSR over dofs, deterministic order)
   std::vector<int64_t> cp_ptr;      // [n+1]

@@ -3,8 +3,8 @@
 //  * T_i^delta: T_i^{delta-1} plus every tetrahedron sharing a vertex with it
 //    ("adjacent" read as vertex adjacency: the only reading under which the
 //    support of the P1 function chi~_i stays inside T_i^delta);
-//  * R_i: restriction to the non-PEC edges of T_i^delta; locally numbered with
-//    the zero-weight unknowns first (ascending), then the others (ascending);
+//  * R_i: restriction to the non-PEC edges of T_i^delta; locally numbered in
+//    reverse Cuthill-McKee order of the graph of B_i (banded dense factors);
 //  * partition of unity, equations (algebPartUnity) and (chi):
 //    chi~_i = 1 on the nodes of T_i^0, 0 on the other nodes of T_i^delta,
 //    chi_i = chi~_i / sum_j chi~_j, and D_i[e] is chi_i at the midpoint of e
