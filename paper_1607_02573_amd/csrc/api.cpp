@@ -137,6 +137,9 @@ struct mw_problem {
   int factor_kind = MW_FACTOR_AUTO;   // requested
   int factorization = 0;              // used by the current factors (MW_FACTOR_LU / MW_FACTOR_LDLT)
   bool factors_valid = false;
+  // F holds zeros outside the band of every 32-row group (true after a
+  // factorisation without interchanges; a refill then clears the band only)
+  bool band_clean = false;
   // workspaces of mw_solve / mw_apply_preconditioner, and of small index lists
   GmresWork ws;
   Work w_small;
@@ -1266,6 +1269,7 @@ mw_status mw_factor_subdomains(mw_problem* p, int32_t n_sub, int32_t overlap, mw
       // solve workspaces are re-created on demand; give their memory to the factors
       p->ws.release();
       p->F = dalloc(c, need);
+      p->band_clean = false;
     }
     p->prec = prec;
     hipStream_t st = p->stream;
@@ -1281,12 +1285,15 @@ mw_status mw_factor_subdomains(mw_problem* p, int32_t n_sub, int32_t overlap, mw
     p->factorization = sym ? MW_FACTOR_LDLT : MW_FACTOR_LU;
     launch_zero_bytes(p->dd.info, (int64_t)p->dd.nsub * 4, st);
     if (prec == MW_C64) {
-      launch_fill_local<float2>(p->dm, p->dd, p->E.as<double2>(), p->eps.as<double2>(), p->k0, p->F.as<float2>(), st);
+      launch_fill_local<float2>(p->dm, p->dd, p->E.as<double2>(), p->eps.as<double2>(), p->k0, p->F.as<float2>(), st,
+                                p->band_clean);
       lu_factor_batched<float2>(p->dd, p->F.as<float2>(), st, sym);
     } else {
-      launch_fill_local<double2>(p->dm, p->dd, p->E.as<double2>(), p->eps.as<double2>(), p->k0, p->F.as<double2>(), st);
+      launch_fill_local<double2>(p->dm, p->dd, p->E.as<double2>(), p->eps.as<double2>(), p->k0, p->F.as<double2>(), st,
+                                 p->band_clean);
       lu_factor_batched<double2>(p->dd, p->F.as<double2>(), st, sym);
     }
+    p->band_clean = sym;
     std::vector<int32_t> info(p->dd.nsub);
     MW_HIP(hipMemcpyAsync(info.data(), p->dd.info, info.size() * 4, hipMemcpyDeviceToHost, st));
     MW_HIP(hipMemcpyAsync(p->h_env.data(), p->dd.env, p->h_env.size() * 8, hipMemcpyDeviceToHost, st));

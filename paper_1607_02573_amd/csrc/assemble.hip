@@ -234,6 +234,32 @@ __global__ void k_fill_identity(C* __restrict__ F, const int64_t* __restrict__ f
   }
 }
 
+// Same result where F already holds zeros outside the band that a
+// factorisation without interchanges writes: per 32-row group the columns
+// from its envelope start (or its 64 x 64 diagonal block, if earlier) to one
+// past the last column reaching it (or the block's end), zeroed, with ones on
+// the padding diagonal.
+template <class C>
+__global__ void k_fill_band(C* __restrict__ F, const int64_t* __restrict__ fac_off,
+                            const int32_t* __restrict__ n_loc, const int32_t* __restrict__ n_pad,
+                            const int32_t* __restrict__ fenv, const int32_t* __restrict__ fenv_hi, int stride) {
+  const int i = blockIdx.y, g = blockIdx.x;
+  const int np = n_pad[i];
+  if (32 * g >= np) return;
+  const int b0 = (g / 2) * 64;
+  const int lo = min(fenv[(int64_t)i * stride + g], b0);
+  const int hi = min(np, max(fenv_hi[(int64_t)i * stride + g], b0 + 64));
+  const int w = hi - lo, nl = n_loc[i];
+  C* Fi = F + fac_off[i];
+  for (int k = threadIdx.x; k < 32 * w; k += blockDim.x) {
+    const int r = 32 * g + k / w, c = lo + k % w;
+    C z;
+    z.x = (r == c && r >= nl) ? 1 : 0;
+    z.y = 0;
+    Fi[(int64_t)r * np + c] = z;
+  }
+}
+
 template <class C>
 __global__ void k_fill_local(C* __restrict__ F, const int64_t* __restrict__ fac_off,
                              const int64_t* __restrict__ loc_off, const int32_t* __restrict__ n_loc,
@@ -292,9 +318,14 @@ __global__ void k_fill_local(C* __restrict__ F, const int64_t* __restrict__ fac_
 
 template <class C>
 void launch_fill_local(const DeviceMesh& m, const DeviceDecomp& d, const double2* E, const double2* eps,
-                       double k0, C* F, hipStream_t st) {
-  dim3 g1(1024, d.nsub);
-  k_fill_identity<C><<<g1, 256, 0, st>>>(F, d.fac_off, d.n_loc, d.n_pad);
+                       double k0, C* F, hipStream_t st, bool band_only) {
+  if (band_only) {
+    k_fill_band<C><<<dim3((unsigned)d.fenv_stride, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_loc, d.n_pad, d.fenv,
+                                                                        d.fenv_hi, d.fenv_stride);
+  } else {
+    dim3 g1(1024, d.nsub);
+    k_fill_identity<C><<<g1, 256, 0, st>>>(F, d.fac_off, d.n_loc, d.n_pad);
+  }
   MW_LAUNCH_CHECK();
   dim3 g2((unsigned)ceil_div(d.max_pad, 128), d.nsub);
   k_fill_local<C><<<g2, 128, 0, st>>>(F, d.fac_off, d.loc_off, d.n_loc, d.n_pad, d.lt_off, d.lt_tet,
@@ -303,9 +334,9 @@ void launch_fill_local(const DeviceMesh& m, const DeviceDecomp& d, const double2
   MW_LAUNCH_CHECK();
 }
 template void launch_fill_local<float2>(const DeviceMesh&, const DeviceDecomp&, const double2*,
-                                        const double2*, double, float2*, hipStream_t);
+                                        const double2*, double, float2*, hipStream_t, bool);
 template void launch_fill_local<double2>(const DeviceMesh&, const DeviceDecomp&, const double2*,
-                                         const double2*, double, double2*, hipStream_t);
+                                         const double2*, double, double2*, hipStream_t, bool);
 
 // ---------------------------------------------------------------- ports
 // Port projections p_k[e] = int_{Gamma_k} E0_k . N_e with the edge-midpoint

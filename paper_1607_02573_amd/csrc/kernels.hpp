@@ -105,7 +105,8 @@ void launch_element_matrices(const DeviceMesh& m, const double2* eps, double k0,
 void launch_gather_csr(const DeviceMesh& m, const double2* E, double2* val, hipStream_t st);
 template <class C>
 void launch_fill_local(const DeviceMesh& m, const DeviceDecomp& d, const double2* E, const double2* eps,
-                       double k0, C* F, hipStream_t st);
+                       double k0, C* F, hipStream_t st,
+                       bool band_only = false);
 void launch_port_setup(const DeviceMesh& m, const DevicePorts& P, hipStream_t st);
 void launch_rhs_ports(const DevicePorts& P, int ntx, const int32_t* tx_dev, double2* B, int64_t ldb,
                       hipStream_t st);
