@@ -87,3 +87,26 @@ def test_refused_factorisation_kind(chamber):
     with pytest.raises(binding.MwError) as e:
         binding.check(binding.lib().mw_set_factorization(P.h, 7))
     assert e.value.code == binding.MW_EINVAL
+
+
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-12), ("c64", 2e-5)])
+def test_refactoring_after_new_permittivity_and_kind(chamber, prec, tol):
+    """A refill after a factorisation without interchanges clears only the
+    band of every B_i (the rest is still zero); after LU with interchanges it
+    clears everything.  Factor a sequence of permittivities and kinds and
+    check every preconditioner against the oracle's for that permittivity."""
+    w, fp, P = chamber
+    rng = np.random.default_rng(12)
+    V = rng.normal(size=(fp.n, 8)) + 1j * rng.normal(size=(fp.n, 8))
+    Vg = torch.from_numpy(V).cuda()
+    for step, kind in enumerate(("ldlt", "ldlt", "lu", "ldlt", "ldlt")):
+        eps = w.eps * (1.0 + 0.05 * step)
+        P.update_eps(torch.from_numpy(np.ascontiguousarray(eps)).cuda())
+        P.set_factorization(kind)
+        P.factor(w.part, w.n_sub, 1, prec)
+        Zo = dd.oras_apply(dd.decompose(fem.with_eps(fp, eps), w.part, 1), V)
+        Z = P.apply_preconditioner(Vg).cpu().numpy()
+        err = np.linalg.norm(Z - Zo) / np.linalg.norm(Zo)
+        assert err <= tol, (step, kind, err)
+    P.update_eps(torch.from_numpy(np.ascontiguousarray(w.eps)).cuda())
+    P.set_factorization("auto")
