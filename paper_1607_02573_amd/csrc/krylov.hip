@@ -267,12 +267,43 @@ __global__ void k_prolong(int64_t n, const int64_t* __restrict__ cp_ptr, const i
   Z[g * ldz + c] = acc;
 }
 
+// the same for an even number of columns, two adjacent columns per thread
+// (each column summed exactly as above)
+template <class C>
+__global__ void k_prolong2(int64_t n, const int64_t* __restrict__ cp_ptr, const int64_t* __restrict__ cp_row,
+                           const double* __restrict__ D, const C* __restrict__ Y, int64_t ldy, int npairs,
+                           double2* __restrict__ Z, int64_t ldz) {
+  int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t g = id / npairs;
+  int c = 2 * (int)(id % npairs);
+  if (g >= n) return;
+  double2 a0 = make_double2(0.0, 0.0), a1 = make_double2(0.0, 0.0);
+  for (int64_t k = cp_ptr[g]; k < cp_ptr[g + 1]; ++k) {
+    int64_t r = cp_row[k];
+    C y0 = Y[r * ldy + c], y1 = Y[r * ldy + c + 1];
+    double w = D[r];
+    a0.x += w * (double)y0.x;
+    a0.y += w * (double)y0.y;
+    a1.x += w * (double)y1.x;
+    a1.y += w * (double)y1.y;
+  }
+  Z[g * ldz + c] = a0;
+  Z[g * ldz + c + 1] = a1;
+}
+
 template <class C>
 void launch_prolong(const DeviceDecomp& d, int64_t n, const C* Y, int64_t ldy, int ncols, double2* Z, int64_t ldz,
                     hipStream_t st) {
-  int64_t tot = n * ncols;
+  if (n <= 0 || ncols <= 0) return;
   kt_begin(KF_PROLONG, st);
-  k_prolong<C><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(n, d.cp_ptr, d.cp_row, d.D, Y, ldy, ncols, Z, ldz);
+  if (ncols % 2 == 0) {
+    int64_t tot = n * (ncols / 2);
+    k_prolong2<C><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(n, d.cp_ptr, d.cp_row, d.D, Y, ldy, ncols / 2, Z,
+                                                                ldz);
+  } else {
+    int64_t tot = n * ncols;
+    k_prolong<C><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(n, d.cp_ptr, d.cp_row, d.D, Y, ldy, ncols, Z, ldz);
+  }
   MW_LAUNCH_CHECK();
   if (kt_enabled()) {
     double sl = 0;
