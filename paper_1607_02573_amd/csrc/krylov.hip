@@ -232,12 +232,38 @@ __global__ void k_restrict(int64_t nloc, const int32_t* __restrict__ ridx, const
   Y[l * ldy + c] = y;
 }
 
+// the same for an even number of columns, two adjacent columns per thread
+template <class C>
+__global__ void k_restrict2(int64_t nloc, const int32_t* __restrict__ ridx, const double2* __restrict__ V,
+                            int64_t ldv, int npairs, C* __restrict__ Y, int64_t ldy) {
+  int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t l = id / npairs;
+  int c = 2 * (int)(id % npairs);
+  if (l >= nloc) return;
+  int32_t g = ridx[l];
+  C y0, y1;
+  y0.x = 0; y0.y = 0; y1.x = 0; y1.y = 0;
+  if (g >= 0) {
+    double2 v0 = V[(int64_t)g * ldv + c], v1 = V[(int64_t)g * ldv + c + 1];
+    y0.x = v0.x; y0.y = v0.y;
+    y1.x = v1.x; y1.y = v1.y;
+  }
+  Y[l * ldy + c] = y0;
+  Y[l * ldy + c + 1] = y1;
+}
+
 template <class C>
 void launch_restrict(const DeviceDecomp& d, const double2* V, int64_t ldv, int ncols, C* Y, int64_t ldy,
                      hipStream_t st) {
-  int64_t tot = d.sum_pad * ncols;
+  if (d.sum_pad <= 0 || ncols <= 0) return;
   kt_begin(KF_RESTRICT, st);
-  k_restrict<C><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(d.sum_pad, d.ridx, V, ldv, ncols, Y, ldy);
+  if (ncols % 2 == 0) {
+    int64_t tot = d.sum_pad * (ncols / 2);
+    k_restrict2<C><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(d.sum_pad, d.ridx, V, ldv, ncols / 2, Y, ldy);
+  } else {
+    int64_t tot = d.sum_pad * ncols;
+    k_restrict<C><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(d.sum_pad, d.ridx, V, ldv, ncols, Y, ldy);
+  }
   MW_LAUNCH_CHECK();
   if (kt_enabled()) {
     double sl = 0;
