@@ -249,31 +249,41 @@ def test_port_reciprocity_and_projection():
     S = np.conj(P.T @ U) / nu[:, None]
     W = nu[:, None] * S
     assert np.abs(W - W.T).max() < 1e-10 * np.abs(W).max()
-    # nu_k approximates the exact integral of cos^2 over the aperture faces
-    # (staircase faces, so only to a loose tolerance)
-    # and every port vector is supported on the edges of its own faces
+    # every port vector is supported on the edges of its own faces (the
+    # values of p_k and nu_k are pinned on a flat aperture below)
     for k in range(len(w.ports)):
         e = set(fp.dof[fp.bf2e[fp.btag == k + 1].ravel()]) - {-1}
         assert set(np.nonzero(P[:, k])[0]) <= e
 
 
-def _plane_wave_error(n, k0=2 * np.pi, eps=1 - 0.1j):
+def _plane_wave_error(n, k0=2 * np.pi, eps=1 - 0.1j, d=(1.0, 2.0, 2.0), p=(2.0, -1.0, 0.0), pec_z=False):
+    """L2 and curl errors of the discrete solution for the plane wave
+    E = p exp(-i k d.x) on the cube with N = n cells per side.  Every face
+    carries the exact impedance data g = (curl E) x n + i k E_t, except with
+    pec_z the faces z = 0 and z = 1, which are metallic (E x n = 0 there
+    requires p parallel to z: the TEM wave between two parallel plates)."""
     m = mi.mesh.cube_mesh(n)
     k = k0 * np.sqrt(eps)
-    d = np.array([1.0, 2.0, 2.0]) / 3.0
-    p = np.array([2.0, -1.0, 0.0]) / np.sqrt(5.0)
+    d = np.asarray(d, dtype=float) / np.linalg.norm(d)
+    p = np.asarray(p, dtype=float) / np.linalg.norm(p)
+    if pec_z:
+        zf = m.xyz[m.bface][:, :, 2]
+        on_plate = (np.abs(zf).max(axis=1) < 1e-12) | (np.abs(zf - 1.0).max(axis=1) < 1e-12)
+        m.btag = np.where(on_plate, fem.TAG_PEC, m.btag).astype(np.int32)
     fp = fem.build(m, np.full(m.nt, eps), k0, k, [])
 
     def E(x):
         return p * np.exp(-1j * k * (x @ d))[..., None]
 
-    # boundary data g = (curl E) x n + i k E_t on every face (outward normals)
+    # boundary data g = (curl E) x n + i k E_t on every non-PEC face (outward normals)
     s, area, nrm = fem.face_geometry(fp.xyz, fp.bface)
     cen = fp.xyz[fp.bface].mean(axis=1)
     out = np.sign(((cen - 0.5) * nrm).sum(axis=1))
     nrm = nrm * out[:, None]
     b = np.zeros(fp.n, dtype=complex)
     for f in range(fp.bface.shape[0]):
+        if fp.btag[f] == fem.TAG_PEC:
+            continue
         X = fp.xyz[fp.bface[f]]
         nn = nrm[f]
         for mu, wq in zip(TRI_Q4, TRI_Q4_W):
@@ -281,12 +291,16 @@ def _plane_wave_error(n, k0=2 * np.pi, eps=1 - 0.1j):
             Ex = E(x)
             g = 1j * k * (Ex - nn * (nn @ Ex) - (d @ nn) * Ex + (Ex @ nn) * d)
             for q, (a, bb) in enumerate(fem.TRI_EDGES):
-                Nq = mu[a] * s[f, bb] - mu[bb] * s[f, a]
-                b[fp.dof[fp.bf2e[f, q]]] += area[f] * wq * (g @ Nq)
+                dof = fp.dof[fp.bf2e[f, q]]
+                if dof >= 0:
+                    Nq = mu[a] * s[f, bb] - mu[bb] * s[f, a]
+                    b[dof] += area[f] * wq * (g @ Nq)
     u = spla.splu(fp.A.tocsc()).solve(b)
-    # L2 and curl errors by a degree-3 rule on every tetrahedron
+    # L2 and curl errors by a degree-3 rule on every tetrahedron; eliminated
+    # (PEC) edges carry a zero circulation
     c0, gr, vol = fem.tet_geometry(fp.xyz, fp.tet)
-    ut = u[fp.dof[fp.t2e]]
+    dt = fp.dof[fp.t2e]
+    ut = np.where(dt >= 0, u[np.maximum(dt, 0)], 0.0)
     e2 = c2 = 0.0
     a, bb = fem.TET_EDGES[:, 0], fem.TET_EDGES[:, 1]
     curlN = 2 * np.cross(gr[:, a, :], gr[:, bb, :])
@@ -310,3 +324,97 @@ def test_plane_wave_first_order_convergence():
     rates = np.log2(e[:-1] / e[1:])
     assert (rates[-1] >= 0.9).all(), (e, rates)
     assert e[-1, 0] < 0.15 and e[-1, 1] < 0.8 * 2 * np.pi
+
+
+def test_parallel_plate_wave_with_pec_walls_converges():
+    """E = z exp(-i k x) between metallic plates z = 0 and z = 1 (equation
+    (eqmetal): E x n = 0 holds there exactly), exact impedance data on the
+    four other faces: with the PEC edges eliminated the discrete solution
+    converges at O(h) in L2 and in the curl.  Treating the plates as natural
+    (curl E x n = 0) or impedance faces, or eliminating the wrong edges,
+    leaves an O(1) error."""
+    e = np.array([_plane_wave_error(n, d=(1.0, 0.0, 0.0), p=(0.0, 0.0, 1.0), pec_z=True) for n in (4, 8)])
+    rates = np.log2(e[0] / e[1])
+    assert (rates >= 0.9).all(), (e, rates)
+    assert e[1, 0] < 0.25 and e[1, 1] < 0.25 * 2 * np.pi
+
+
+def _flat_port(n):
+    """Box [2, 3] x [-0.5, 0.5] x [0, 1] with n^3 cells; the face x = 3 is
+    the aperture of one port (arc coordinate s = 3 atan2(y, x), width 1,
+    polarisation with a normal component), every other face impedance (no
+    PEC edge is eliminated, so every edge of the aperture is an unknown)."""
+    m = mi.mesh.cube_mesh(n)
+    m.xyz = m.xyz + np.array([2.0, -0.5, 0.0])
+    xf = m.xyz[m.bface][:, :, 0]
+    m.btag = np.where(np.abs(xf - 3.0).max(axis=1) < 1e-12, 1, fem.TAG_IMPEDANCE).astype(np.int32)
+    pt = mi.mesh.PortSpec(theta=0.0, z=0.5, width=1.0, height=1.0, radius=3.0, beta=5.0 - 0.5j,
+                          pol=(0.5, 0.6, 0.8))
+    fp = fem.build(m, np.full(m.nt, 1 - 0.1j), 3.0, 3.0, [pt])
+    return fp, pt
+
+
+def test_port_projection_and_norm_against_exact_integrals():
+    """Section 4, equation (sij): p_k[e] = int E0 . N_e and
+    nu_k = int |E0_t|^2 over the aperture.  Whitney functions reproduce
+    every field c(x) = a + b x x of the lowest-order edge-element space
+    exactly from its circulations int_e c . t (= c(midpoint) . t_e, the
+    integrand being linear), so sum_e (int_e c . t) p_k[e] = int_Gamma E0 . c_t;
+    on the flat aperture x = 3 this and nu_k are integrals of
+    cos(pi s / width) times polynomials, computed here by adaptive
+    quadrature.  The edge-midpoint rule is exact for quadratics, so the
+    discrepancies must fall at least as h^2 under refinement."""
+    from scipy.integrate import dblquad, quad
+
+    prof = lambda y: np.cos(np.pi * 3.0 * np.arctan2(y, 3.0))   # noqa: E731
+    I2 = quad(lambda y: prof(y) ** 2, -0.5, 0.5, epsabs=1e-14, epsrel=1e-14)[0]
+    pol = np.array([0.5, 0.6, 0.8])
+    pol_t = pol * np.array([0.0, 1.0, 1.0])                    # tangential part on x = 3
+    fields = [(np.array([0.3, -1.2, 0.7]), np.zeros(3)), (np.array([1.0, 0.0, 0.0]), np.zeros(3)),
+              (np.array([-0.4, 0.9, 1.1]), np.array([0.5, -0.8, 1.3])),
+              (np.zeros(3), np.array([-1.1, 0.4, 0.6]))]
+    exact = []
+    for a, b in fields:
+        f = lambda z, y: prof(y) * (pol_t @ (a + np.cross(b, [3.0, y, z])))   # noqa: E731
+        exact.append(dblquad(f, -0.5, 0.5, 0.0, 1.0, epsabs=1e-13, epsrel=1e-13)[0])
+    exact = np.array(exact)
+    errs_p, errs_nu = [], []
+    for n in (4, 8, 16):
+        fp, pt = _flat_port(n)
+        P, nu = fem.port_vectors(fp, [pt])
+        xa, xb = fp.xyz[fp.edges[fp.free, 0]], fp.xyz[fp.edges[fp.free, 1]]
+        mid, t = 0.5 * (xa + xb), xb - xa
+        lhs = np.array([((a + np.cross(b, mid)) * t).sum(axis=1) @ P[:, 0] for a, b in fields])
+        errs_p.append(np.abs(lhs - exact).max() / np.abs(exact).max())
+        errs_nu.append(abs(nu[0] - I2 * (pol_t @ pol_t)) / (I2 * (pol_t @ pol_t)))
+    errs_p, errs_nu = np.array(errs_p), np.array(errs_nu)
+    assert errs_p[-1] < 1e-3 and errs_nu[-1] < 1e-3, (errs_p, errs_nu)
+    # entry by entry on the coarsest mesh: the same edge-midpoint rule applied
+    # to the tangential traces of the 3-D Whitney functions of the
+    # tetrahedron owning each aperture face (barycentric gradients from a
+    # 4 x 4 solve, not fem's surface gradients)
+    fp, pt = _flat_port(4)
+    P, _ = fem.port_vectors(fp, [pt])
+    own = fem.face_owner(fp.tet, fp.bface)
+    pref = np.zeros(fp.n)
+    for f in np.nonzero(fp.btag == 1)[0]:
+        tv = fp.tet[own[f]]
+        X = fp.xyz[tv]
+        fv = fp.bface[f]
+        nrm = np.cross(fp.xyz[fv[1]] - fp.xyz[fv[0]], fp.xyz[fv[2]] - fp.xyz[fv[0]])
+        area = 0.5 * np.linalg.norm(nrm)
+        nrm /= 2 * area
+        for u, v in ((0, 1), (0, 2), (1, 2)):
+            lam = np.zeros(4)
+            lam[np.searchsorted(tv, fv[u])] = lam[np.searchsorted(tv, fv[v])] = 0.5
+            x = lam @ X
+            e0 = fem.port_mode(pt, x)
+            e0t = e0 - (e0 @ nrm) * nrm
+            N = whitney_at(X, lam)
+            for q, (a, b) in enumerate(fem.TET_EDGES):
+                if tv[a] in fv and tv[b] in fv:
+                    e = fem.edge_ids(fp.edges, fp.nv, np.array([tv[a]]), np.array([tv[b]]))[0]
+                    pref[fp.dof[e]] += area / 3.0 * (e0t @ N[q])
+    assert np.abs(P[:, 0] - pref).max() <= 1e-13 * np.abs(pref).max()
+    assert (np.log2(errs_p[:-1] / errs_p[1:]) >= 1.9).all(), errs_p
+    assert (np.log2(errs_nu[:-1] / errs_nu[1:]) >= 1.9).all(), errs_nu
