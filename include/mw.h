@@ -55,7 +55,8 @@ typedef enum {
   MW_ENOMEM = -2,     /* request exceeds the context's HBM budget; nothing allocated */
   MW_ESINGULAR = -3,  /* zero pivot in a subdomain factorisation (message names it) */
   MW_ENOCONV = -4,    /* GMRES reached maxit; X holds the last iterate, info filled */
-  MW_ENUMERIC = -5,   /* NaN or Inf in a residual */
+  MW_ENUMERIC = -5,   /* NaN or Inf in a GMRES residual (e.g. from the right-hand
+                         side) or in a subdomain matrix (from the permittivity) */
   MW_EDEVICE = -6     /* HIP runtime error (message holds its string) */
 } mw_status;
 
@@ -133,6 +134,10 @@ typedef struct {
   int64_t factor_bytes;
   double t_assemble, t_decompose, t_factor; /* seconds of the last calls */
   int32_t factorization; /* of the valid factors: MW_FACTOR_LU or MW_FACTOR_LDLT; 0 if none */
+  int64_t state;         /* changes with every call that changes the operator or the factors
+                            (mw_update_eps, mw_update_eps_vertex, mw_factor_subdomains,
+                            mw_release_factors): solves made at equal states used the same
+                            A(eps) and the same factors */
 } mw_problem_info;
 
 /* ---- context -------------------------------------------------------- */
@@ -187,7 +192,10 @@ mw_status mw_rhs_dipoles(mw_problem *p, int32_t np, const double *xyz, const dou
 
 /* ---- preconditioner (Section 3) -------------------------------------- */
 /* tet_part: host [nt] subdomain of every tetrahedron, values in [0, n_sub)
- * (the non-overlapping partition T_i; every part non-empty).  overlap: delta
+ * (the non-overlapping partition T_i; every part non-empty), or NULL for the
+ * library's own partition: recursive coordinate bisection of the tetrahedron
+ * centroids into parts of floor(nt / n_sub) or one more tetrahedra
+ * (mw_host_partition returns it; 1 <= n_sub <= nt).  overlap: delta
  * >= 1 layers of vertex-adjacent tetrahedra.  Builds R_i, the partition of
  * unity D_i (P1 chi_i at edge midpoints), the local matrices B_i with
  * impedance transmission conditions i k (E x n).(v x n) on the interfaces,
@@ -338,6 +346,14 @@ mw_status mw_host_decomposition(const mw_mesh *mesh, const int32_t *tet_part, in
  * H with steps = 0: resid[0] gets the number of pivots of its Cholesky
  * factor that are <= thr (relative to the largest diagonal entry) and Y its
  * Cholesky factor R (G = R^H R, upper triangular). */
+/* The partition mw_factor_subdomains takes when tet_part is NULL: tet_part
+ * (host [nt], caller-owned) gets the part of every tetrahedron.  Section 3
+ * starts from a non-overlapping partition of the mesh into n_sub subdomains;
+ * here it is recursive coordinate bisection of the centroids: split across
+ * the axis of largest extent, the lower floor(count * floor(np/2) / np) by
+ * (coordinate, tetrahedron id) to the first half of the np parts.  MW_EINVAL
+ * unless 1 <= n_sub <= nt. */
+mw_status mw_host_partition(const mw_mesh *mesh, int32_t n_sub, int32_t *tet_part);
 mw_status mw_host_block_lstsq(int32_t steps, int32_t width, const mw_complex *S0, const mw_complex *H,
                               double thr, double *resid, mw_complex *Y);
 const char *mw_host_last_error(void);

@@ -60,7 +60,8 @@ class mw_problem_info(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("n_edges", C.c_int64), ("nt", C.c_int32),
                 ("nports", C.c_int32), ("n_sub", C.c_int32), ("sum_ni", C.c_int64), ("max_ni", C.c_int32),
                 ("precision", C.c_int32), ("factor_bytes", C.c_int64), ("t_assemble", C.c_double),
-                ("t_decompose", C.c_double), ("t_factor", C.c_double), ("factorization", C.c_int32)]
+                ("t_decompose", C.c_double), ("t_factor", C.c_double), ("factorization", C.c_int32),
+                ("state", C.c_int64)]
 
 
 class mw_batch_info(C.Structure):
@@ -107,6 +108,7 @@ _SIGS = {
     "mw_host_topology": [C.POINTER(mw_mesh), _P, _P, _P, _P, _P, _P],
     "mw_host_decomposition": [C.POINTER(mw_mesh), _P, _I, _I, _P, _P, _P, _P],
     "mw_host_block_lstsq": [_I, _I, _P, _P, C.c_double, _P, _P],
+    "mw_host_partition": [C.POINTER(mw_mesh), _I, _P],
     "mw_set_factorization": [_P, _I],
     "mw_update_eps_vertex": [_P, _P],
     "mw_gradient_vertex": [_P, _I, _P, _P, _P],
@@ -202,6 +204,15 @@ def host_decomposition(xyz, tet, bface, btag, part, n_sub: int, overlap: int = 1
     off = np.r_[0, np.cumsum(n_loc)]
     return {"n_loc": n_loc, "n_faces": nf, "sub_dof": [sub_dof[off[i]:off[i + 1]] for i in range(n_sub)],
             "D": [D[off[i]:off[i + 1]] for i in range(n_sub)]}
+
+
+def host_partition(xyz, tet, bface, btag, n_sub: int) -> np.ndarray:
+    """The library's own partition (tet_part = NULL): int32 [nt]."""
+    m, keep = make_mesh(xyz, tet, bface, btag)
+    part = np.empty(m.nt, dtype=np.int32)
+    check(lib().mw_host_partition(C.byref(m), int(n_sub), ptr(part)), host=True)
+    del keep
+    return part
 
 
 def timer_enable(on: bool = True):

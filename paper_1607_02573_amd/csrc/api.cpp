@@ -145,6 +145,12 @@ struct mw_problem {
   Work w_small;
   hipStream_t stream = nullptr;    // every launch and copy of this problem
   int live_batches = 0;
+  // bumped by every call that changes the operator or the factors (eps,
+  // factorisation, release), so that callers can tell whether the factors
+  // still belong to the permittivity they solved with
+  int64_t state = 0;
+  // the internal partition (tet_part == NULL) of the last decomposition
+  std::vector<int32_t> own_part;
   double t_assemble = 0, t_decompose = 0, t_factor = 0;
 };
 
@@ -288,6 +294,7 @@ void assemble_values(mw_problem* p) {
 
 uint64_t hash_part(const int32_t* part, int32_t nt, int32_t nsub, int32_t delta) {
   uint64_t h = 1469598103934665603ull ^ (uint64_t)nsub * 1099511628211ull ^ ((uint64_t)delta << 32);
+  if (part == nullptr) return h ^ 0x9e3779b97f4a7c15ull;   // the internal partition of nsub parts
   for (int32_t t = 0; t < nt; ++t) h = (h ^ (uint64_t)(uint32_t)part[t]) * 1099511628211ull;
   return h;
 }
@@ -1092,6 +1099,7 @@ mw_status mw_update_eps(mw_problem* p, const void* eps_dev) {
     MW_CHECK(eps_dev != nullptr, MW_EINVAL, "eps is NULL");
     DeviceGuard dg(p->ctx->device);
     double t0 = now_s();
+    p->state++;
     MW_HIP(hipMemcpyAsync(p->eps.p, eps_dev, (size_t)p->T.nt * 16, hipMemcpyDeviceToDevice, p->stream));
     p->eps_p1 = false;
     assemble_values(p);
@@ -1107,6 +1115,7 @@ mw_status mw_update_eps_vertex(mw_problem* p, const void* eps_vertex_dev) {
     MW_CHECK(eps_vertex_dev != nullptr, MW_EINVAL, "eps is NULL");
     DeviceGuard dg(p->ctx->device);
     double t0 = now_s();
+    p->state++;
     if (p->eps_v.p == nullptr) p->eps_v = dalloc(p->ctx, (int64_t)p->T.nv * 16);
     MW_HIP(hipMemcpyAsync(p->eps_v.p, eps_vertex_dev, (size_t)p->T.nv * 16, hipMemcpyDeviceToDevice, p->stream));
     p->eps_p1 = true;
@@ -1162,6 +1171,7 @@ mw_status mw_problem_get_info(mw_problem* p, mw_problem_info* info) {
     info->t_assemble = p->t_assemble;
     info->t_decompose = p->t_decompose;
     info->t_factor = p->t_factor;
+    info->state = p->state;
   });
 }
 
@@ -1243,17 +1253,22 @@ mw_status mw_factor_subdomains(mw_problem* p, int32_t n_sub, int32_t overlap, mw
   return guard([&] {
     check_prob(p);
     MW_CHECK(prec == MW_C64 || prec == MW_C128, MW_EINVAL, "precision must be MW_C64 or MW_C128");
-    MW_CHECK(tet_part != nullptr, MW_EINVAL, "tet_part is NULL");
     mw_ctx* c = p->ctx;
     DeviceGuard dg(c->device);
     double t0 = now_s();
+    p->state++;
     uint64_t key = hash_part(tet_part, p->T.nt, n_sub, overlap);
     if (!p->has_dec || key != p->dec_key) {
       p->has_dec = false;
       p->factors_valid = false;
       p->F.release();
+      const int32_t* part = tet_part;
+      if (part == nullptr) {
+        partition_rcb(p->T, n_sub, p->own_part);
+        part = p->own_part.data();
+      }
       Decomposition D;
-      build_decomposition(p->T, tet_part, n_sub, overlap, 64, D);
+      build_decomposition(p->T, part, n_sub, overlap, 64, D);
       p->D = std::move(D);
       upload_decomp(p);
       p->has_dec = true;
@@ -1283,6 +1298,7 @@ mw_status mw_factor_subdomains(mw_problem* p, int32_t n_sub, int32_t overlap, mw
       sym = hmax < 0.0;
     }
     p->factorization = sym ? MW_FACTOR_LDLT : MW_FACTOR_LU;
+    p->factors_valid = false;
     launch_zero_bytes(p->dd.info, (int64_t)p->dd.nsub * 4, st);
     if (prec == MW_C64) {
       launch_fill_local<float2>(p->dm, p->dd, p->E.as<double2>(), p->eps.as<double2>(), p->k0, p->F.as<float2>(), st,
@@ -1293,15 +1309,24 @@ mw_status mw_factor_subdomains(mw_problem* p, int32_t n_sub, int32_t overlap, mw
                                  p->band_clean);
       lu_factor_batched<double2>(p->dd, p->F.as<double2>(), st, sym);
     }
-    p->band_clean = sym;
+    // the fill may have been band-only; what lies outside the band is known
+    // to be zero again only after a factorisation without interchanges that
+    // met no small pivot (a failed one can leave overflowed values anywhere)
+    p->band_clean = false;
     std::vector<int32_t> info(p->dd.nsub);
+    std::vector<double> amax(p->dd.nsub);
     MW_HIP(hipMemcpyAsync(info.data(), p->dd.info, info.size() * 4, hipMemcpyDeviceToHost, st));
+    MW_HIP(hipMemcpyAsync(amax.data(), p->dd.amax, amax.size() * 8, hipMemcpyDeviceToHost, st));
     MW_HIP(hipMemcpyAsync(p->h_env.data(), p->dd.env, p->h_env.size() * 8, hipMemcpyDeviceToHost, st));
     psync(p);
     p->t_factor = now_s() - t1;
     for (int i = 0; i < p->dd.nsub; ++i)
+      MW_CHECK(std::isfinite(amax[i]), MW_ENUMERIC,
+               "NaN or Inf in the local matrix of subdomain " + std::to_string(i) + " (non-finite permittivity?)");
+    for (int i = 0; i < p->dd.nsub; ++i)
       MW_CHECK(info[i] == 0, MW_ESINGULAR,
                "(near-)zero pivot in subdomain " + std::to_string(i) + " at column " + std::to_string(info[i] - 1));
+    p->band_clean = sym;
     p->factors_valid = true;
   });
 }
@@ -1509,6 +1534,7 @@ mw_status mw_release_factors(mw_problem* p) {
     check_prob(p);
     DeviceGuard dg(p->ctx->device);
     psync(p);
+    p->state++;
     p->F.release();
     p->ws.release();
     p->factors_valid = false;
@@ -1519,7 +1545,7 @@ mw_status mw_factor_bytes(mw_problem* p, int32_t n_sub, int32_t overlap, mw_prec
                           int64_t* bytes) {
   return guard([&] {
     check_prob(p);
-    MW_CHECK(bytes && tet_part, MW_EINVAL, "NULL argument");
+    MW_CHECK(bytes != nullptr, MW_EINVAL, "NULL argument");
     MW_CHECK(prec == MW_C64 || prec == MW_C128, MW_EINVAL, "precision must be MW_C64 or MW_C128");
     int64_t esz = prec == MW_C64 ? 8 : 16;
     uint64_t key = hash_part(tet_part, p->T.nt, n_sub, overlap);

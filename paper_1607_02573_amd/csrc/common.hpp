@@ -182,4 +182,8 @@ struct Decomposition {
 void build_decomposition(const Topology& T, const int32_t* tet_part, int32_t nsub, int32_t delta,
                          int32_t block, Decomposition& D);
 
+// Internal non-overlapping partition: recursive coordinate bisection of the
+// tetrahedron centroids into nsub parts of floor(nt/nsub) or one more.
+void partition_rcb(const Topology& T, int32_t nsub, std::vector<int32_t>& part);
+
 }  // namespace mw

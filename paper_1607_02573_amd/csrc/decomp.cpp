@@ -424,4 +424,56 @@ void build_decomposition(const Topology& T, const int32_t* part, int32_t nsub, i
   }
 }
 
+// Non-overlapping partition T_i of the tetrahedra (Section 3 starts from one;
+// the paper takes it from a graph partitioner) by recursive coordinate
+// bisection of the tetrahedron centroids: the current set is split across
+// the axis of largest centroid extent (ties: lowest axis) so that the lower
+// side holds floor(count * nl / np) tetrahedra for nl = floor(np / 2) of its
+// np parts, ordered by (coordinate, tetrahedron id); each side is split
+// again until one part is left.  Every part then holds floor(nt / nsub) or
+// one more tetrahedron; only the mesh geometry decides, so any tetrahedral
+// mesh can be split.
+void partition_rcb(const Topology& T, int32_t nsub, std::vector<int32_t>& part) {
+  const int32_t nt = T.nt;
+  MW_CHECK(nsub >= 1 && nsub <= nt, MW_EINVAL, "n_sub must lie in [1, number of tetrahedra]");
+  std::vector<double> cen((size_t)nt * 3);
+  for (int32_t t = 0; t < nt; ++t)
+    for (int a = 0; a < 3; ++a) {
+      double s = 0.0;
+      for (int k = 0; k < 4; ++k) s += T.xyz[3 * (size_t)T.tet[4 * (size_t)t + k] + a];
+      cen[3 * (size_t)t + a] = 0.25 * s;
+    }
+  std::vector<int32_t> ids(nt);
+  for (int32_t t = 0; t < nt; ++t) ids[t] = t;
+  part.assign(nt, 0);
+  struct Range { int64_t lo, hi; int32_t p0, np; };
+  std::vector<Range> todo{{0, nt, 0, nsub}};
+  while (!todo.empty()) {
+    Range r = todo.back();
+    todo.pop_back();
+    if (r.np == 1) {
+      for (int64_t k = r.lo; k < r.hi; ++k) part[ids[k]] = r.p0;
+      continue;
+    }
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t k = r.lo; k < r.hi; ++k)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], cen[3 * (size_t)ids[k] + a]);
+        hi[a] = std::max(hi[a], cen[3 * (size_t)ids[k] + a]);
+      }
+    int ax = 0;
+    for (int a = 1; a < 3; ++a)
+      if (hi[a] - lo[a] > hi[ax] - lo[ax]) ax = a;
+    const int32_t nl = r.np / 2;
+    const int64_t cut = r.lo + (r.hi - r.lo) * nl / r.np;
+    auto less = [&](int32_t a, int32_t b) {
+      const double xa = cen[3 * (size_t)a + ax], xb = cen[3 * (size_t)b + ax];
+      return xa < xb || (xa == xb && a < b);
+    };
+    if (cut > r.lo && cut < r.hi) std::nth_element(ids.begin() + r.lo, ids.begin() + cut, ids.begin() + r.hi, less);
+    todo.push_back({cut, r.hi, r.p0 + nl, r.np - nl});
+    todo.push_back({r.lo, cut, r.p0, nl});
+  }
+}
+
 }  // namespace mw

@@ -568,7 +568,8 @@ __device__ inline Piv piv_max(Piv a, Piv b) {
   return a;
 }
 
-// largest |re|+|im| of every B_i (scale of the singular-pivot test)
+// largest |re|+|im| of every B_i (scale of the singular-pivot test; NaN or
+// Inf when B_i holds a non-finite entry)
 template <class R>
 // (only the envelope of B_i is read: every entry outside it is zero)
 __global__ void __launch_bounds__(256) k_amax(const typename cplx<R>::t* __restrict__ F,
@@ -585,16 +586,20 @@ __global__ void __launch_bounds__(256) k_amax(const typename cplx<R>::t* __restr
     for (int k = threadIdx.x; k < 32 * w; k += 256) {
       auto v = Fi[(int64_t)(32 * g + k / w) * np + c0 + k % w];
       double a = fabs((double)v.x) + fabs((double)v.y);
-      m = a > m ? a : m;
+      m = (a > m || a != a) ? a : m;   // a NaN entry makes the maximum NaN
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
     double o = __shfl_xor(m, off);
-    m = o > m ? o : m;
+    m = (o > m || o != o) ? o : m;
   }
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
-  if (threadIdx.x == 0) amax[i] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < 4; ++w) r = (red[w] > r || red[w] != red[w]) ? red[w] : r;
+    amax[i] = r;
+  }
 }
 
 // One workgroup per subdomain: factor columns [c, c+W0) of rows [c, np),

@@ -66,6 +66,17 @@ mw_status mw_host_decomposition(const mw_mesh* mesh, const int32_t* tet_part, in
   });
 }
 
+mw_status mw_host_partition(const mw_mesh* mesh, int32_t n_sub, int32_t* tet_part) {
+  return hguard([&] {
+    MW_CHECK(mesh && tet_part, MW_EINVAL, "NULL argument");
+    Topology T;
+    build_topology(*mesh, T);
+    std::vector<int32_t> part;
+    partition_rcb(T, n_sub, part);
+    std::copy(part.begin(), part.end(), tet_part);
+  });
+}
+
 mw_status mw_host_block_lstsq(int32_t steps, int32_t width, const mw_complex* S0, const mw_complex* H, double thr,
                               double* resid, mw_complex* Y) {
   return hguard([&] {

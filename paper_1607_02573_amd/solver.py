@@ -154,17 +154,29 @@ class Problem:
         check(lib().mw_set_factorization(self.h, k))
 
     def factor(self, part, n_sub: int, overlap: int = 1, precision: str = "c128"):
-        part = np.ascontiguousarray(part, dtype=np.int32)
+        """Fill and factor the B_i; part = None takes the library's own
+        partition (recursive coordinate bisection of the centroids)."""
         prec = {"c128": B.MW_C128, "c64": B.MW_C64}[precision]
+        if part is None:
+            check(lib().mw_factor_subdomains(self.h, int(n_sub), int(overlap), prec, None))
+            return
+        part = np.ascontiguousarray(part, dtype=np.int32)
         check(lib().mw_factor_subdomains(self.h, int(n_sub), int(overlap), prec, ptr(part)))
 
     def factor_bytes(self, part, n_sub: int, overlap: int = 1, precision: str = "c64") -> int:
         """Device bytes of the factors of this partition (decomposition built once before)."""
-        part = np.ascontiguousarray(part, dtype=np.int32)
         prec = {"c128": B.MW_C128, "c64": B.MW_C64}[precision]
         out = C.c_int64()
+        if part is None:
+            check(lib().mw_factor_bytes(self.h, int(n_sub), int(overlap), prec, None, C.addressof(out)))
+            return out.value
+        part = np.ascontiguousarray(part, dtype=np.int32)
         check(lib().mw_factor_bytes(self.h, int(n_sub), int(overlap), prec, ptr(part), C.addressof(out)))
         return out.value
+
+    def state(self) -> int:
+        """Counter that changes whenever the operator or the factors change."""
+        return int(self.info().state)
 
     def release_factors(self):
         check(lib().mw_release_factors(self.h))

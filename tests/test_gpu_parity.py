@@ -261,7 +261,9 @@ def test_preconditioner_column_counts(chamber_small, prec, tol):
         V = rng.normal(size=(P.n, nc)) + 1j * rng.normal(size=(P.n, nc))
         Zg = P.apply_preconditioner(torch.from_numpy(V).cuda()).cpu().numpy()
         Zo = dd.oras_apply(subs, V)
-        assert _rel(Zg, Zo) <= tol, nc
+        # per column
+        err = np.linalg.norm(Zg - Zo, axis=0) / np.linalg.norm(Zo, axis=0)
+        assert err.max() <= tol, (nc, err.max())
         # each column is independent of the others (bitwise)
         Z1 = P.apply_preconditioner(torch.from_numpy(np.ascontiguousarray(V[:, :1])).cuda()).cpu().numpy()
         assert np.array_equal(Z1[:, 0], Zg[:, 0]), nc

@@ -236,3 +236,36 @@ def test_host_block_cholesky(L):
     W2[:, 5] = W[:, 2] + 1e-5 * np.linalg.norm(W[:, 2]) * W[:, 9] / np.linalg.norm(W[:, 9])
     _, nd = binding.host_block_cholesky(W2.conj().T @ W2, 1e-7)
     assert nd == 0
+
+
+@pytest.mark.parametrize("which,nsub", [("cube8", 8), ("cube8", 7), ("small_chamber", 13)])
+def test_internal_partition_is_balanced_and_decomposes_like_the_oracle(L, which, nsub):
+    """tet_part = NULL: the library's recursive coordinate bisection of the
+    centroids.  Every part holds floor(nt/nsub) or one more tetrahedron, the
+    parts are geometrically compact (each part's centroid bounding box is far
+    smaller than the mesh's), a shuffled vertex order inside the tetrahedra
+    gives the same parts, and the overlapping decomposition built on it
+    equals the oracle's on the same partition."""
+    from paper_1607_02573_amd import binding
+    w = mi.configs.cube8() if which == "cube8" else mi.configs.small_chamber(0.25e9, n_per_ring=8)
+    m = w.mesh
+    part = binding.host_partition(m.xyz, m.tet, m.bface, m.btag, nsub)
+    cnt = np.bincount(part, minlength=nsub)
+    assert part.min() == 0 and part.max() == nsub - 1
+    assert set(cnt.tolist()) <= {m.nt // nsub, m.nt // nsub + 1}
+    cen = m.xyz[m.tet].mean(axis=1)
+    vol_all = np.prod(cen.max(axis=0) - cen.min(axis=0))
+    for i in range(nsub):
+        c = cen[part == i]
+        assert np.prod(c.max(axis=0) - c.min(axis=0)) < 2.5 * vol_all / nsub
+    rng = np.random.default_rng(3)
+    tet_sh = np.array([rng.permutation(t) for t in m.tet])
+    assert np.array_equal(binding.host_partition(m.xyz, tet_sh, m.bface, m.btag, nsub), part)
+    dec = binding.host_decomposition(m.xyz, m.tet, m.bface, m.btag, part, nsub, 1)
+    fp = fem.build(m, w.eps, w.k0, w.beta_imp, w.ports)
+    for i, s in enumerate(dd.decompose(fp, part, 1, factor=False)):
+        o = np.argsort(dec["sub_dof"][i], kind="stable")
+        assert np.array_equal(dec["sub_dof"][i][o], s.gdof)
+        np.testing.assert_allclose(dec["D"][i][o], s.D, rtol=0, atol=1e-15)
+    with pytest.raises(Exception):
+        binding.host_partition(m.xyz, m.tet, m.bface, m.btag, m.nt + 1)
