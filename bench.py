@@ -116,53 +116,106 @@ def family_table(fam: dict, mfma_peak_tflops: float, wall_s: float):
     return out, {"roofline_s": roof_s, "wall_s": wall_s, "frac": roof_s / wall_s if wall_s > 0 else None}
 
 
-def cpu_baseline(w, iters_mean: float, nrhs: int, budget_s: float):
-    """The oracle (FP64 numpy/scipy, sparse direct subdomain solves), single
-    thread, on a bounded sample of the same workload, scaled to RHS/s:
-    full assembly + ports, S sampled subdomains built and factored, one
-    preconditioner application and one GMRES iteration's Gram-Schmidt and
-    SpMV on one right-hand side; per-RHS time = (assembly + all factors)/nrhs
-    + iters * (ORAS apply + SpMV + CGS2 at the mean Krylov index)."""
-    from threadpoolctl import threadpool_limits
+def host_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
 
-    from oracle import dd, fem
-    with threadpool_limits(1):
+
+def cpu_baseline(w, tx, tol: float, restart: int, ncols: int = 2):
+    """The oracle (plain FP64 numpy/scipy, SuperLU subdomain factors) timed on
+    this host's cores, on the same workload: re-assembly of A for the
+    permittivity and the port sources of all columns, then every subdomain
+    built and factored on a process pool of all cores (oracle/pool.py), then
+    its pseudo-block ORAS-GMRES on `ncols` of the port columns to the same
+    tolerance.  Columns are independent in pseudo-block GMRES, so the whole
+    job's time is t_assembly + t_factor + (nrhs / ncols) * t_solve.  Runs
+    before the GPU is touched (the pool forks).  Returns the baseline record
+    and the oracle's problem (matrix and sources), which the per-result
+    error check reuses."""
+    from oracle import fem, gmres, pool
+    nproc = host_cores()
+    nrhs = len(tx)
+    t0 = time.perf_counter()
+    fp = fem.build(w.mesh, w.eps, w.k0, w.beta_imp, w.ports)
+    t_build = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    fp = fem.with_eps(fp, w.eps)
+    B = fem.rhs_ports(fp, w.ports, tx) if w.dipoles is None else fem.rhs_dipoles(fp, w.dipoles)
+    t_asm = time.perf_counter() - t0
+    cols = np.unique(np.linspace(0, nrhs - 1, ncols).round().astype(int))
+    with pool.PooledORAS(fp, w.part, w.overlap, nproc=nproc, max_cols=len(cols)) as M:
+        t_fac = M.t_setup
         t0 = time.perf_counter()
-        fp = fem.build(w.mesh, w.eps, w.k0, w.beta_imp, w.ports)
-        b = fem.rhs_ports(fp, w.ports, w.tx[:1]) if w.dipoles is None else fem.rhs_dipoles(fp, w.dipoles[:1])
-        t_asm = time.perf_counter() - t0
-        nsub = w.n_sub
-        nsamp = max(1, min(nsub, 8 if nsub > 64 else nsub))
-        subset = np.unique(np.linspace(0, nsub - 1, nsamp).astype(int))
-        t0 = time.perf_counter()
-        subs = dd.decompose(fp, w.part, 1, factor=True, subset=list(subset))
-        t_fac = (time.perf_counter() - t0) * nsub / len(subset)
-        x = b[:, :1]
-        t0 = time.perf_counter()
-        z = np.zeros_like(x)
-        for s in subs:
-            z[s.gdof] += s.D[:, None] * s.lu.solve(np.ascontiguousarray(x[s.gdof]))
-        t_prec = (time.perf_counter() - t0) * nsub / len(subset)
-        t0 = time.perf_counter()
-        for _ in range(3):
-            y = fp.A @ x
-        t_spmv = (time.perf_counter() - t0) / 3
-        jbar = 15
-        V = np.ones((jbar + 1, fp.n, 1), dtype=np.complex128)
-        t0 = time.perf_counter()
-        for _ in range(2):
-            h = np.einsum("knc,nc->kc", V.conj(), y)
-            y = y - np.einsum("knc,kc->nc", V, h)
-        t_cgs = time.perf_counter() - t0
-        del y, z
-    per_rhs = (t_asm + t_fac) / nrhs + iters_mean * (t_prec + t_spmv + t_cgs)
-    return {"value": 1.0 / per_rhs, "unit": "RHS/s", "cores": 1, "kind": "oracle",
-            "host_cpus": os.cpu_count(),
-            "sample": (f"oracle on {w.name}: full FP64 assembly + port source ({t_asm:.1f} s), "
-                       f"{len(subset)} of {nsub} subdomains built + SuperLU-factored (scaled x{nsub / len(subset):.0f}: "
-                       f"{t_fac:.1f} s), one ORAS apply ({t_prec:.2f} s scaled), SpMV ({t_spmv:.3f} s) and CGS2 at "
-                       f"j=15 ({t_cgs:.2f} s) on 1 RHS; per-RHS time = (assembly+factors)/{nrhs} + "
-                       f"{iters_mean:.1f} iterations x (apply+SpMV+CGS2); single thread")}
+        _, it, rr = gmres.gmres(fp.A, B[:, cols], M.apply, tol=tol, restart=restart)
+        t_solve = time.perf_counter() - t0
+    total = t_asm + t_fac + (nrhs / len(cols)) * t_solve
+    rec = {"value": nrhs / total, "unit": "RHS/s", "cores": nproc, "kind": "oracle",
+           "host_cpus": os.cpu_count(),
+           "sample": (f"oracle on {w.name} ({fp.n} unknowns) on {nproc} host cores, measured: re-assembly of A "
+                      f"and the {nrhs} sources {t_asm:.1f} s; all {w.n_sub} subdomains built and SuperLU-factored "
+                      f"on a {nproc}-process pool {t_fac:.1f} s; pseudo-block ORAS-GMRES of columns "
+                      f"{cols.tolist()} to {tol:g}: {t_solve:.1f} s, iterations {it.tolist()}, relres max "
+                      f"{rr.max():.1e}; RHS/s = {nrhs} / (assembly + factor + {nrhs}/{len(cols)} x solve) "
+                      f"(columns are independent); topology {t_build:.1f} s not counted")}
+    return rec, fp, B
+
+
+def oracle_errors(w, fp, B, X, tx, label: str):
+    """Error of GPU fields X (device, n x nrhs, columns = ports tx) against
+    the oracle: the relative residual ||b - A x|| / ||b|| with the oracle's
+    own matrix and sources on 16 evenly spaced columns, and, where stored
+    oracle fields exist for this workload (tests/golden, written by the
+    oracle's ORAS-GMRES at 1e-10), the field error on their ports."""
+    import torch
+    nrhs = X.shape[1]
+    cols = np.unique(np.linspace(0, nrhs - 1, min(16, nrhs)).round().astype(int))
+    Xc = X[:, cols].cpu().numpy()
+    res = np.linalg.norm(B[:, cols] - fp.A @ Xc, axis=0) / np.linalg.norm(B[:, cols], axis=0)
+    out = {"relres_oracle_A_max": float(res.max()), "relres_columns": len(cols)}
+    path = os.path.join(ROOT, "tests", "golden", f"{w.name}_oracle.npz")
+    if os.path.exists(path) and w.dipoles is None:
+        z = np.load(path)
+        pos = {int(t): k for k, t in enumerate(tx)}
+        if int(z["fingerprint"][0]) == fp.n and all(int(t) in pos for t in z["tx"]):
+            c = [pos[int(t)] for t in z["tx"]]
+            Xs = X[torch.from_numpy(z["idx"]).to(X.device)][:, c].cpu().numpy()
+            e_s = np.linalg.norm(Xs - z["U_sample"], axis=0) / np.linalg.norm(z["U_sample"], axis=0)
+            e_n = np.abs(torch.linalg.norm(X[:, c], dim=0).cpu().numpy() - z["norms"]) / z["norms"]
+            out["fields_vs_oracle"] = {"ports": [int(t) for t in z["tx"]], "oracle_tol": float(z["tol"]),
+                                       "sample_relL2_max": float(e_s.max()), "norm_rel_max": float(e_n.max()),
+                                       "sample_size": int(z["idx"].size)}
+    log(f"[bench] {label} vs oracle: relres (oracle A) max {out['relres_oracle_A_max']:.2e}"
+        + (f", fields {out['fields_vs_oracle']['sample_relL2_max']:.2e}" if "fields_vs_oracle" in out else ""))
+    return out
+
+
+def serving_leg(args, freqs, n_req: int, rate: float):
+    """Continuous-batching service over a menu of chamber problems (seeded
+    Poisson arrivals of solve and gradient requests); returns the summary."""
+    import torch
+
+    import mw_inputs as mi
+    from paper_1607_02573_amd import serve, solver
+    menu = mi.serving.serving_menu(freqs=freqs)
+    reqs = mi.serving.serving_requests(n_req=n_req, rate=rate, n_meshes=len(menu))
+    total = torch.cuda.mem_get_info()[1]
+    ctx = solver.Context(0, budget_bytes=int(total - (8 << 30)))
+    srv = serve.Server(ctx, menu, tol=args.tol, restart=args.restart, maxit=args.maxit, log=log,
+                       budget_bytes=int(total - (20 << 30)))
+    t0 = time.perf_counter()
+    out = srv.run(reqs)
+    t_wall = time.perf_counter() - t0
+    summ = serve.summarize(out, t_wall)
+    summ["evictions"] = srv.evictions
+    summ["setup_s"] = srv.t_setup
+    summ["factorisations"] = {f"{menu[k[0]].name}/v{k[1]}": sl.factorisations for k, sl in srv.slots.items()}
+    summ["budget_bytes"] = srv.adm.budget
+    summ["menu"] = [f"{e.name}: {e.n_edges} edges, {e.workload.n_sub} subdomains" for e in menu]
+    srv.close()
+    ctx.close()
+    return summ
 
 
 def serve_main(args):
@@ -286,6 +339,10 @@ def main():
                     help="serve the seeded request stream over the 4-mesh x 2-permittivity chamber menu and print "
                          "its latency line instead of the batch benchmark")
     ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-short", type=int, default=40,
+                    help="requests of the short serving leg of the default line (0: none)")
+    ap.add_argument("--cpu-cols", type=int, default=2,
+                    help="port columns the oracle baseline solves (the rest scaled by column count)")
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--invert", type=int, default=0,
                     help="run this many L-BFGS iterations of the outer inversion loop on the workload and print "
@@ -302,6 +359,21 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this library solves all subdomains "
               "of a problem on a single MI355X and has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
+
+    # the oracle baseline forks a process pool: it runs before the GPU is touched
+    w = None
+    cpu = fp_oracle = B_oracle = None
+    if not (args.serve or args.invert):
+        log(f"[bench] generating workload {args.workload}")
+        w = make_workload(args.workload)
+        tx = w.tx if w.dipoles is None else np.arange(w.nrhs)
+        if args.nrhs and w.dipoles is None:
+            tx = w.tx[: args.nrhs]
+        tol = args.tol if args.workload != "cube8" else w.tol
+        if not args.no_cpu:
+            log(f"[bench] cpu_baseline: the oracle on {host_cores()} host cores")
+            cpu, fp_oracle, B_oracle = cpu_baseline(w, tx, tol, args.restart, args.cpu_cols)
+            log(f"[bench] cpu_baseline: {cpu['value']:.4f} RHS/s ({cpu['sample']})")
 
     import torch
 
@@ -323,14 +395,8 @@ def main():
         log(f"[bench] copy probe: {args.copy_probe_mib} MiB read, {args.copy_probe_mib} MiB written")
         del src, dst
 
-    log(f"[bench] generating workload {args.workload}")
-    w = make_workload(args.workload)
-    tx = w.tx if w.dipoles is None else np.arange(w.nrhs)
-    if args.nrhs and w.dipoles is None:
-        tx = w.tx[: args.nrhs]
     rx = w.rx if w.rx is not None else np.zeros(0, dtype=np.int32)
     nrhs = len(tx) if w.dipoles is None else w.nrhs
-    tol = args.tol if args.workload != "cube8" else w.tol
 
     total = torch.cuda.mem_get_info()[1]
     ctx = solver.Context(0, budget_bytes=int(total - (24 << 30)))
@@ -382,6 +448,10 @@ def main():
     roof["avg_launch_us"] = d["ms"] * 1e3 / d["launches"]
     kernel_table, solve_roof = family_table(famt, PEAK["fp32_TFLOPs"], T)
 
+    err_mixed = err_fp64 = None
+    if fp_oracle is not None:
+        err_mixed = oracle_errors(w, fp_oracle, B_oracle, Xm, tx, "mixed")
+
     # ---------------- FP64 path, same workload
     fp64 = None
     if args.fp64_steps > 0 and args.workload != "cube8":
@@ -405,17 +475,43 @@ def main():
         binding.timer_enable(False)
         ok64 = int(sum((s["relres"] <= tol).sum() for s in st64))
         it64 = np.concatenate([s["iters"] for s in st64])
+        if fp_oracle is not None:
+            err_fp64 = oracle_errors(w, fp_oracle, B_oracle, X64, tx, "FP64")
         x64 = X64[:, : Xm_host.shape[1]].cpu()
         dx = (torch.linalg.norm(Xm_host - x64, dim=0) / torch.linalg.norm(x64, dim=0)).max().item()
         dS = ((Sm_host - S64.cpu()).abs().max() / S64.cpu().abs().max()).item() if Sm_host is not None else None
         fp64 = {"value": ok64 / T64, "ms_per_step": 1e3 * T64 / args.fp64_steps, "iters_mean": float(it64.mean()),
                 "chunks": st64[-1]["chunks"], "solve_rhs_per_s": sum(len(s["relres"]) for s in st64)
                 / sum(s["t_solve"] for s in st64), "setup_s": st64[-1]["t_setup"],
-                "mixed_vs_fp64_field_relL2_max": dx, "mixed_vs_fp64_S_rel_max": dS,
+                "mixed_vs_fp64_field_relL2_max": dx, "mixed_vs_fp64_S_rel_max": dS, "error_vs_oracle": err_fp64,
                 "kernels": family_table({k: v for k, v in fam64.items() if v["launches"] > 0},
                                         PEAK["fp64_TFLOPs"], T64)[0]}
         log(f"[bench] FP64: {T64 / args.fp64_steps:.2f} s/step, {fp64['value']:.2f} RHS/s; mixed-vs-fp64 field {dx:.2e}")
+        del X64, S64
+    else:
+        del Xm, Sm
 
+    del fp_oracle, B_oracle, eps_dev
+    P.close()
+    ctx.close()
+    torch.cuda.empty_cache()
+    latency = None
+    if args.serve_short > 0:
+        log(f"[bench] serving leg: {args.serve_short} requests at {args.serve_rate}/s on the 0.3125 and 0.5 GHz "
+            "chambers")
+        summ = serving_leg(args, (0.3125e9, 0.5e9), args.serve_short, args.serve_rate)
+        log(f"[bench] serving: p50 {summ['p50_s']:.2f} s, p99 {summ['p99_s']:.2f} s, {summ['rhs_per_s']:.1f} "
+            f"columns/s, failed {summ['failed']}")
+        latency = {"p50_s": summ["p50_s"], "p99_s": summ["p99_s"], "mean_s": summ["mean_s"],
+                   "by_kind": summ["by_kind"], "requests": summ["requests"], "failed": summ["failed"],
+                   "rhs_columns": summ["rhs_columns"], "rhs_per_s": summ["rhs_per_s"],
+                   "makespan_s": summ["makespan_s"], "max_relres": summ["max_relres"],
+                   "evictions": summ["evictions"], "factorisations": summ["factorisations"],
+                   "config": {"workload": "continuous-batching service, chamber menu " + "; ".join(summ["menu"]) +
+                              f"; 2 permittivity versions each; seeded Poisson arrivals at {args.serve_rate}/s, "
+                              f"{args.serve_short} requests, 75 % solves (1-160 columns) / 25 % gradients (1-32)",
+                              "precision": "c64 factors + f64 GMRES", "tol": args.tol,
+                              "budget_bytes": summ["budget_bytes"]}}
     out = {
         "metric": "RHS solves/s at rel-res 1e-8, mixed vs FP64 ORAS-GMRES; p50/p99 latency",
         "value": value,
@@ -439,19 +535,17 @@ def main():
         "iters_mean": float(it_mixed.mean()),
         "iters_max": int(it_mixed.max()),
         "converged": ok,
+        "error_vs_oracle": err_mixed,
+        "latency": latency,
         "fp64": fp64,
         "speedup_mixed_vs_fp64": (value / fp64["value"]) if fp64 else None,
         "roofline": roof,
         "kernels": kernel_table,
         "whole_run_roofline": solve_roof,
     }
-    if not args.no_cpu:
-        log("[bench] cpu_baseline (oracle sample)")
-        it_ref = fp64["iters_mean"] if fp64 else float(it_mixed.mean())
-        out["cpu_baseline"] = cpu_baseline(w, it_ref, nrhs, 20.0)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
-    P.close()
-    ctx.close()
 
 
 if __name__ == "__main__":

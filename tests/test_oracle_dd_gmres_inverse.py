@@ -184,3 +184,19 @@ def test_local_matrices_have_positive_definite_imaginary_part(cube4):
             piv.append(abs(A[k, k]))
             A[k + 1:, k + 1:] -= np.outer(A[k + 1:, k], A[k, k + 1:]) / A[k, k]
         assert min(piv) > 1e-6 * np.abs(Bd).max()
+
+
+def test_pooled_oras_equals_serial_sum(cube4):
+    """The process-pool form of the preconditioner (one share of the
+    subdomains per worker, partial sums added in worker order) equals the
+    serial sum over subdomains to rounding, for more columns than one pass
+    takes."""
+    from oracle import pool
+    w, fp = cube4
+    part = mi.partition.rcb(w.mesh, 7)
+    subs = dd.decompose(fp, part, 1)
+    V = RNG.normal(size=(fp.n, 5)) + 1j * RNG.normal(size=(fp.n, 5))
+    Zs = dd.oras_apply(subs, V)
+    with pool.PooledORAS(fp, part, 1, nproc=3, max_cols=2) as M:
+        Zp = M.apply(V)
+    np.testing.assert_allclose(Zp, Zs, rtol=0, atol=1e-13 * np.abs(Zs).max())
