@@ -55,16 +55,24 @@ def _all_faces(tet: np.ndarray):
     return f, own
 
 
-def decompose(fp: fem.FEProblem, part: np.ndarray, delta: int = 1, factor: bool = True, subset=None):
-    """All subdomains, or only those listed in ``subset``."""
+def node_counts(tet: np.ndarray, part: np.ndarray, nv: int) -> np.ndarray:
+    """Number of subdomains whose T_j^0 holds each node: the denominator of
+    equation (chi)."""
+    cnt = np.zeros(nv)
+    for i in range(int(part.max()) + 1):
+        nodes = np.zeros(nv, dtype=bool)
+        nodes[tet[part == i].ravel()] = True
+        cnt += nodes
+    return cnt
+
+
+def decompose(fp: fem.FEProblem, part: np.ndarray, delta: int = 1, factor: bool = True, subset=None, cnt=None):
+    """All subdomains, or only those listed in ``subset`` (cnt: node_counts,
+    if already known)."""
     nsub = int(part.max()) + 1
     nv = fp.nv
-    # number of subdomains whose T_j^0 holds each node: denominator of (chi)
-    cnt = np.zeros(nv)
-    for i in range(nsub):
-        nodes = np.zeros(nv, dtype=bool)
-        nodes[fp.tet[part == i].ravel()] = True
-        cnt += nodes
+    if cnt is None:
+        cnt = node_counts(fp.tet, part, nv)
     # boundary-face lookup: key -> (beta, face index)
     key_b = _face_keys(fp.bface, nv)
     order_b = np.argsort(key_b)

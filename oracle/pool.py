@@ -32,7 +32,15 @@ def _worker(fp, part, delta, share, n, max_cols, vbuf, zbuf, slot, conn):
     from threadpoolctl import threadpool_limits
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        subs = dd.decompose(fp, part, delta, factor=True, subset=list(share)) if len(share) else []
+        # built a few at a time, keeping only what the apply needs (R_i, D_i
+        # and the factors), so that the workers' memory stays near the
+        # factors' own size
+        subs = []
+        cnt = dd.node_counts(fp.tet, part, fp.nv)
+        for k in range(0, len(share), 32):
+            for s in dd.decompose(fp, part, delta, factor=True, subset=list(share[k:k + 32]), cnt=cnt):
+                s.B = s.tets = None
+                subs.append(s)
         lu_bytes = sum(16 * (s.lu.L.nnz + s.lu.U.nnz) for s in subs)
         conn.send(("ready", time.perf_counter() - t0, lu_bytes))
         V_all = np.frombuffer(vbuf, dtype=np.complex128)
