@@ -212,6 +212,20 @@ mw_status mw_set_factorization(mw_problem *p, int32_t kind);
 /* Z = M^-1 V for nrhs columns (device n x nrhs). */
 mw_status mw_apply_preconditioner(mw_problem *p, int32_t nrhs, const void *V, void *Z);
 
+/* Same result as mw_apply_preconditioner (the same kernels, bit for bit),
+ * for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The local
+ * vectors live in a fixed buffer of MW_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every device it runs on until the process ends; the call makes no
+ * allocation of its own (the factors come from mw_factor_subdomains).
+ * Requires sum_i n_pad_i * nrhs * (8 for MW_C64, 16 for MW_C128) <=
+ * MW_NOALLOC_SCRATCH_BYTES (n_pad_i: n_i rounded up to 64), else MW_EINVAL
+ * with the sizes in the message.  Every call on a device shares that
+ * device's buffer: calls that overlap in time on one device (other host
+ * threads, other streams) race and must be serialised by the caller. */
+#define MW_NOALLOC_SCRATCH_BYTES (64ll << 20)
+mw_status mw_apply_preconditioner_noalloc(mw_problem *p, int32_t nrhs, const void *V, void *Z);
+
 /* ---- solve ----------------------------------------------------------- */
 /* X = A^-1 B for nrhs columns (device n x nrhs each) by ORAS right-
  * preconditioned pseudo-block GMRES(m): each column keeps its own Krylov

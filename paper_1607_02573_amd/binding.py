@@ -56,6 +56,9 @@ class mw_solve_info(C.Structure):
                 ("chunks", C.c_int32), ("t_solve", C.c_double)]
 
 
+NOALLOC_SCRATCH_BYTES = 64 << 20   # MW_NOALLOC_SCRATCH_BYTES
+
+
 class mw_problem_info(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("n_edges", C.c_int64), ("nt", C.c_int32),
                 ("nports", C.c_int32), ("n_sub", C.c_int32), ("sum_ni", C.c_int64), ("max_ni", C.c_int32),
@@ -86,6 +89,7 @@ _SIGS = {
     "mw_rhs_dipoles": [_P, _I, _P, _P, _P],
     "mw_factor_subdomains": [_P, _I, _I, C.c_int, _P],
     "mw_apply_preconditioner": [_P, _I, _P, _P],
+    "mw_apply_preconditioner_noalloc": [_P, _I, _P, _P],
     "mw_solve": [_P, _I, _P, _P, C.POINTER(mw_solve_opts), C.POINTER(mw_solve_info)],
     "mw_s_matrix": [_P, _I, _P, _I, _P, _P],
     "mw_port_norms": [_P, _P],

@@ -13,6 +13,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <numeric>
 
 #include "blockls.hpp"
@@ -22,6 +23,36 @@
 using namespace mw;
 
 static thread_local std::string g_last_error;
+
+// Fixed device buffer of mw_apply_preconditioner_noalloc: the local vectors
+// R_i v of every subdomain live here instead of in an allocated workspace.
+// Each device that loads the library holds one copy until the process ends;
+// host code reaches it only through the address hipGetSymbolAddress returns
+// for the current device (the array's name is a host-side stand-in).
+static __device__ __align__(256) char scratch[MW_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch`; looked up once per
+// device (at mw_create), with that device current.
+void* scratch_for_device(int device, bool lookup) {
+  MW_CHECK(device >= 0 && device < kMaxDevices, MW_EINVAL, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device] == nullptr && lookup) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) {
+      (void)hipGetLastError();
+      fail(MW_EDEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
+}  // namespace
 
 struct mw_ctx {
   int device = 0;
@@ -1004,6 +1035,7 @@ mw_status mw_create(mw_ctx** out, int device, int64_t hbm_budget_bytes) {
     DeviceGuard dg(device);
     size_t fr = 0, tot = 0;
     MW_HIP(hipMemGetInfo(&fr, &tot));
+    (void)scratch_for_device(device, true);
     auto* c = new mw_ctx();
     c->device = device;
     c->budget = hbm_budget_bytes > 0 ? hbm_budget_bytes : (int64_t)(0.95 * (double)tot);
@@ -1339,6 +1371,40 @@ mw_status mw_apply_preconditioner(mw_problem* p, int32_t nrhs, const void* V, vo
     DeviceGuard dg(p->ctx->device);
     p->ws.st = p->stream;
     apply_prec(p, p->ws, (const double2*)V, (double2*)Z, nrhs, nrhs);
+    psync(p);
+  });
+}
+
+mw_status mw_apply_preconditioner_noalloc(mw_problem* p, int32_t nrhs, const void* V, void* Z) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(nrhs >= 0 && (nrhs == 0 || (V && Z)), MW_EINVAL, "NULL argument");
+    MW_CHECK(p->factors_valid, MW_EINVAL, "no valid subdomain factors: call mw_factor_subdomains");
+    if (nrhs == 0) return;
+    const int64_t esz = p->prec == MW_C64 ? 8 : 16;
+    const int64_t need = p->dd.sum_pad * (int64_t)nrhs * esz;
+    MW_CHECK(need <= (int64_t)MW_NOALLOC_SCRATCH_BYTES, MW_EINVAL,
+             "mw_apply_preconditioner_noalloc: the local vectors need " + std::to_string(need) +
+                 " bytes, more than the fixed buffer's " + std::to_string((int64_t)MW_NOALLOC_SCRATCH_BYTES) +
+                 " (sum of padded local sizes " + std::to_string(p->dd.sum_pad) + " x " + std::to_string(nrhs) +
+                 " columns x " + std::to_string(esz) + " bytes); use fewer columns or mw_apply_preconditioner");
+    DeviceGuard dg(p->ctx->device);
+    void* Y = scratch_for_device(p->ctx->device, false);
+    MW_CHECK(Y != nullptr, MW_EDEVICE, "the fixed buffer of this device was not set up (mw_create)");
+    const int64_t n = p->T.n();
+    const double2* Vd = (const double2*)V;
+    double2* Zd = (double2*)Z;
+    // the restriction writes every local row (zeros on the padding), so the
+    // buffer needs no clearing between calls
+    if (p->prec == MW_C64) {
+      launch_restrict<float2>(p->dd, Vd, nrhs, nrhs, (float2*)Y, nrhs, p->stream);
+      lu_solve_batched<float2>(p->dd, p->F.as<float2>(), (float2*)Y, nrhs, nrhs, p->stream);
+      launch_prolong<float2>(p->dd, n, (const float2*)Y, nrhs, nrhs, Zd, nrhs, p->stream);
+    } else {
+      launch_restrict<double2>(p->dd, Vd, nrhs, nrhs, (double2*)Y, nrhs, p->stream);
+      lu_solve_batched<double2>(p->dd, p->F.as<double2>(), (double2*)Y, nrhs, nrhs, p->stream);
+      launch_prolong<double2>(p->dd, n, (const double2*)Y, nrhs, nrhs, Zd, nrhs, p->stream);
+    }
     psync(p);
   });
 }

@@ -191,6 +191,16 @@ class Problem:
         check(lib().mw_apply_preconditioner(self.h, V.shape[1], ptr(V), ptr(Z)))
         return Z
 
+    def apply_preconditioner_noalloc(self, V: torch.Tensor, Z: torch.Tensor) -> torch.Tensor:
+        """Z = M^-1 V into the caller's Z, through the entry point that
+        allocates nothing (local vectors in the library's fixed buffer)."""
+        _dev_tensor(V, torch.complex128, self.ctx.device, "V")
+        _dev_tensor(Z, torch.complex128, self.ctx.device, "Z")
+        if Z.shape != V.shape:
+            raise ValueError("Z must have the shape of V")
+        check(lib().mw_apply_preconditioner_noalloc(self.h, V.shape[1], ptr(V), ptr(Z)))
+        return Z
+
     # ------------------------------------------------------------------ solve
     def solve(self, Bm: torch.Tensor, tol=1e-8, restart=30, maxit=1000, x0: torch.Tensor | None = None,
               raise_noconv: bool = True, block: int = 0):
