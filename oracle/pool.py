@@ -41,7 +41,7 @@ def _worker(fp, part, delta, share, n, max_cols, vbuf, zbuf, slot, conn):
             for s in dd.decompose(fp, part, delta, factor=True, subset=list(share[k:k + 32]), cnt=cnt):
                 s.B = s.tets = None
                 subs.append(s)
-        lu_bytes = sum(16 * (s.lu.L.nnz + s.lu.U.nnz) for s in subs)
+        lu_bytes = sum(16 * s.lu.nnz for s in subs)   # (s.lu.L would copy the factors)
         conn.send(("ready", time.perf_counter() - t0, lu_bytes))
         V_all = np.frombuffer(vbuf, dtype=np.complex128)
         Z_all = np.frombuffer(zbuf, dtype=np.complex128).reshape(-1, n * max_cols)

@@ -65,8 +65,8 @@ def _csr(P):
 
 
 # run first: the 1 GHz fixtures below hold most of the device memory until the
-# end of the module
-@pytest.fixture(scope="module")
+# end of the module, so the 0.5 GHz problems are released before them
+@pytest.fixture(scope="class")
 def inversion05():
     from paper_1607_02573_amd import solver
     print("[fullsize] 0.5 GHz inversion step: problem and stored oracle results", flush=True)
@@ -80,55 +80,56 @@ def inversion05():
     torch.cuda.empty_cache()
 
 
-def test_inversion05_gradient_matches_oracle(inversion05):
-    """The GPU misfit, S and adjoint gradient (FP64 factors, every solve at
-    1e-11) against the oracle's, with the oracle's 'measured' S, on the 20
-    seeded tetrahedra entry by entry."""
-    w, P, z = inversion05
-    P.update_eps(torch.from_numpy(w.eps).cuda())
-    P.factor(w.part, w.n_sub, 1, "c128")
-    J, S, g = P.misfit_gradient(w.tx, w.rx, torch.from_numpy(z["S_meas"]).cuda(), tol=1e-11)
-    gf = g.cpu().numpy()[z["fd_tets"]]
-    go = z["grad_fd"]
-    err = np.abs(gf - go) / np.abs(go)
-    print(f"[fullsize] J {J:.9e} vs oracle {float(z['J']):.9e}; gradient on 20 tets: max relative error "
-          f"{err.max():.2e}", flush=True)
-    assert abs(J - float(z["J"])) <= 1e-6 * float(z["J"])
-    So = z["S"]
-    assert np.abs(S.cpu().numpy() - So).max() <= 1e-6 * np.abs(So).max()
-    assert err.max() <= 1e-6
-
-
-def test_inversion05_gradient_directional_difference(inversion05):
-    w, P, z = inversion05
-    print("[fullsize] 0.5 GHz inversion step: forward + adjoint on 32 ports", flush=True)
-    dev = torch.device("cuda")
-    eps_true = torch.from_numpy(w.extra["eps_true"]).to(dev)
-    P.update_eps(eps_true)
-    P.factor(w.part, w.n_sub, 1, "c128")
-    U, _ = P.solve(P.rhs_ports(w.tx), tol=1e-11)
-    S_meas = P.s_matrix(U, w.rx)
-    eps0 = torch.from_numpy(w.eps).to(dev)
-    P.update_eps(eps0)
-    P.factor(w.part, w.n_sub, 1, "c128")
-    J, S, g = P.misfit_gradient(w.tx, w.rx, S_meas, tol=1e-11)
-    assert J > 0
-    rng = np.random.default_rng(7)
-    d = np.zeros(w.mesh.nt, dtype=np.complex128)
-    d[w.extra["fd_tets"]] = rng.normal(size=20) + 1j * rng.normal(size=20)
-    d *= 1e-4 * np.abs(w.eps).max() / np.abs(d).max()
-    dd = torch.from_numpy(d).to(dev)
-
-    def J_at(e):
-        P.update_eps(e)
+class TestInversion05:
+    def test_inversion05_gradient_matches_oracle(self, inversion05):
+        """The GPU misfit, S and adjoint gradient (FP64 factors, every solve at
+        1e-11) against the oracle's, with the oracle's 'measured' S, on the 20
+        seeded tetrahedra entry by entry."""
+        w, P, z = inversion05
+        P.update_eps(torch.from_numpy(w.eps).cuda())
         P.factor(w.part, w.n_sub, 1, "c128")
-        Ue, _ = P.solve(P.rhs_ports(w.tx), tol=1e-11)
-        return 0.5 * float((P.s_matrix(Ue, w.rx) - S_meas).abs().pow(2).sum())
+        J, S, g = P.misfit_gradient(w.tx, w.rx, torch.from_numpy(z["S_meas"]).cuda(), tol=1e-11)
+        gf = g.cpu().numpy()[z["fd_tets"]]
+        go = z["grad_fd"]
+        err = np.abs(gf - go) / np.abs(go)
+        print(f"[fullsize] J {J:.9e} vs oracle {float(z['J']):.9e}; gradient on 20 tets: max relative error "
+              f"{err.max():.2e}", flush=True)
+        assert abs(J - float(z["J"])) <= 1e-6 * float(z["J"])
+        So = z["S"]
+        assert np.abs(S.cpu().numpy() - So).max() <= 1e-6 * np.abs(So).max()
+        assert err.max() <= 1e-6
 
-    fd = (J_at(eps0 + dd) - J_at(eps0 - dd)) / 2
-    lin = float(torch.sum(torch.conj(g) * dd).real)
-    print(f"[fullsize] directional derivative: adjoint {lin:.6e}, central difference {fd:.6e}", flush=True)
-    assert abs(lin - fd) <= 1e-5 * abs(fd)
+
+    def test_inversion05_gradient_directional_difference(self, inversion05):
+        w, P, z = inversion05
+        print("[fullsize] 0.5 GHz inversion step: forward + adjoint on 32 ports", flush=True)
+        dev = torch.device("cuda")
+        eps_true = torch.from_numpy(w.extra["eps_true"]).to(dev)
+        P.update_eps(eps_true)
+        P.factor(w.part, w.n_sub, 1, "c128")
+        U, _ = P.solve(P.rhs_ports(w.tx), tol=1e-11)
+        S_meas = P.s_matrix(U, w.rx)
+        eps0 = torch.from_numpy(w.eps).to(dev)
+        P.update_eps(eps0)
+        P.factor(w.part, w.n_sub, 1, "c128")
+        J, S, g = P.misfit_gradient(w.tx, w.rx, S_meas, tol=1e-11)
+        assert J > 0
+        rng = np.random.default_rng(7)
+        d = np.zeros(w.mesh.nt, dtype=np.complex128)
+        d[w.extra["fd_tets"]] = rng.normal(size=20) + 1j * rng.normal(size=20)
+        d *= 1e-4 * np.abs(w.eps).max() / np.abs(d).max()
+        dd = torch.from_numpy(d).to(dev)
+
+        def J_at(e):
+            P.update_eps(e)
+            P.factor(w.part, w.n_sub, 1, "c128")
+            Ue, _ = P.solve(P.rhs_ports(w.tx), tol=1e-11)
+            return 0.5 * float((P.s_matrix(Ue, w.rx) - S_meas).abs().pow(2).sum())
+
+        fd = (J_at(eps0 + dd) - J_at(eps0 - dd)) / 2
+        lin = float(torch.sum(torch.conj(g) * dd).real)
+        print(f"[fullsize] directional derivative: adjoint {lin:.6e}, central difference {fd:.6e}", flush=True)
+        assert abs(lin - fd) <= 1e-5 * abs(fd)
 
 
 @pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64", 1e-8)])
