@@ -314,6 +314,7 @@ def invert_main(args):
                    "tol": args.tol, "restart": args.restart, "gmres": "block" if args.block else "pseudo-block"},
     }
     print(json.dumps(line), flush=True)
+    inv.close()
     P.close()
     ctx.close()
 

@@ -66,6 +66,8 @@ typedef enum { MW_C128 = 0, MW_C64 = 1 } mw_precision;
  * L D L^T when every tetrahedron is lossy (Im eps_r < 0), which makes the
  * imaginary part of every B_i positive definite, so no pivot can vanish. */
 typedef enum { MW_FACTOR_AUTO = 0, MW_FACTOR_LU = 1, MW_FACTOR_LDLT = 2 } mw_factorization;
+/* Coarse space of the two-level preconditioner (mw_set_coarse_space). */
+typedef enum { MW_COARSE_NONE = 0, MW_COARSE_CONST = 1 } mw_coarse_space;
 
 #define MW_TAG_PEC (-1)
 #define MW_TAG_IMPEDANCE 0
@@ -138,6 +140,7 @@ typedef struct {
                             (mw_update_eps, mw_update_eps_vertex, mw_factor_subdomains,
                             mw_release_factors): solves made at equal states used the same
                             A(eps) and the same factors */
+  int32_t coarse_size;   /* unknowns of the coarse problem of the valid factors (0: one-level) */
 } mw_problem_info;
 
 /* ---- context -------------------------------------------------------- */
@@ -205,6 +208,20 @@ mw_status mw_rhs_dipoles(mw_problem *p, int32_t np, const double *xyz, const dou
  * (section 6 of the paper factors the B_i by a symmetric L D L^T). */
 mw_status mw_factor_subdomains(mw_problem *p, int32_t n_sub, int32_t overlap,
                                mw_precision prec, const int32_t *tet_part);
+/* Two-level preconditioner (the paper's conclusion, Section 7, names a coarse
+ * space as the remedy for iteration counts that grow with the number of
+ * subdomains, Section 6.1, Table tabscaling).  kind MW_COARSE_CONST: every
+ * subdomain i contributes the D_i-weighted edge interpolants of the three
+ * constant fields, Z_i = R_i^T D_i Phi_i with Phi_i[l, a] = (x_hi - x_lo)[a]
+ * of the edge of local unknown l; E = Z^T A Z (3 n_sub unknowns, at most
+ * 8192) is assembled on the device and factored like the B_i, in the same
+ * precision and factorisation; the preconditioner becomes
+ *     M2^-1 v = M^-1 (v - A q) + q,   q = Z E^-1 Z^T v
+ * (deflated form: M2^-1 A is the identity on span Z).  Every solve, batch and
+ * mw_apply_preconditioner then uses it; mw_apply_preconditioner_noalloc
+ * refuses it (MW_EINVAL).  Takes effect at the next mw_factor_subdomains
+ * (the factors are invalid until then).  MW_COARSE_NONE (default): one-level. */
+mw_status mw_set_coarse_space(mw_problem *p, int32_t kind);
 /* kind: an mw_factorization value, used by the next mw_factor_subdomains
  * (default MW_FACTOR_AUTO).  MW_FACTOR_LDLT on matrices whose pivots can
  * vanish may end in MW_ESINGULAR. */
@@ -274,6 +291,81 @@ mw_status mw_gradient(mw_problem *p, int32_t ntx, const void *U, const void *F, 
 mw_status mw_gradient_vertex(mw_problem *p, int32_t ntx, const void *U, const void *F, void *grad_vertex);
 mw_status mw_misfit(mw_problem *p, int64_t count, const void *S_sim, const void *S_meas, void *gS,
                     double *J);
+/* The normalised misfit of Section 5, equation (defJ2): gS = W (S_sim - S_meas)
+ * and J = 1/2 sum W |S_sim - S_meas|^2 over count entries, W (device double
+ * [count], e.g. 1 / |S_empty|^2) or NULL for weights 1 (= mw_misfit). */
+mw_status mw_misfit_weighted(mw_problem *p, int64_t count, const void *S_sim, const void *S_meas, const double *W,
+                             void *gS, double *J);
+
+/* ---- outer inversion loop (Section 5) ---------------------------------- */
+/* Limited-memory BFGS (Section 5 names L-BFGS; Nocedal and Wright, Numerical
+ * Optimization, 2nd ed., Algorithms 7.4 and 7.5): two-loop recursion over the
+ * last `mem` pairs (s, y) with s^T y > 1e-12 |s| |y|, H0 = (s^T y / y^T y) I
+ * from the latest pair, backtracking line search on the Armijo condition
+ * J(x + t d) <= J(x) + c1 t g^T d (t halved, at most max_backtrack tries);
+ * the first step is scaled so that it moves the largest entry by step0. */
+typedef struct {
+  int32_t mem;
+  double step0;
+  double c1;
+  int32_t max_backtrack;
+} mw_lbfgs_opts;
+/* objective: J(x) and its gradient g (both host, n doubles); MW_OK or an error */
+typedef mw_status (*mw_objective_fn)(void *user, const double *x, double *J, double *g);
+/* Host routine: `iters` accepted steps from x (host [n], overwritten by the
+ * last accepted iterate; fewer steps if a line search fails).  J_hist (host
+ * [iters+1]) and x_hist (host [(iters+1) * n]) receive the accepted values
+ * (either may be NULL); accepted / evaluations the counts (may be NULL). */
+mw_status mw_lbfgs(int64_t n, double *x, int32_t iters, const mw_lbfgs_opts *o, mw_objective_fn f, void *user,
+                   double *J_hist, double *x_hist, int32_t *accepted, int32_t *evaluations);
+
+/* The inversion of Section 5 over a relative permittivity e given at the mesh
+ * vertices (Section 6 takes kappa = k0^2 eps_r in P1).  One evaluation at e:
+ * A(e) with the tetrahedron means of e (p1 = 0) or e integrated exactly in
+ * the mass term (p1 = 1, mw_update_eps_vertex); the subdomain factors; the
+ * forward solves of the ports tx and S (equation (sij)); the misfit of
+ * equation (defJ2), J_d = 1/2 sum_ij |S_ij - S_meas,ij|^2 / |S_empty,ij|^2;
+ * one adjoint solve with the weighted residual (problem (pbadj)); the
+ * gradient per tetrahedron mapped to the vertices by the transpose of the
+ * averaging (p1: the exact vertex form); plus the Tikhonov term
+ * (alpha/2) int |grad e|^2, exact for P1 through the P1 stiffness matrix K1
+ * (alpha/2 Re(e^H K1 e), gradient alpha K1 e).  The gradient is
+ * dJ/dRe e + i dJ/dIm e.  recycle = 1: every evaluation's forward and adjoint
+ * solves start from the previous evaluation's fields. */
+typedef struct {
+  double alpha;
+  int32_t p1;
+  int32_t recycle;
+  int32_t n_sub;
+  int32_t overlap;
+  int32_t precision;     /* mw_precision of the subdomain factors */
+  mw_solve_opts solve;   /* tol, restart, maxit, block of every solve (use_x0 ignored) */
+} mw_inversion_opts;
+typedef struct {
+  int32_t evaluations;
+  int64_t solve_columns;  /* forward + adjoint right-hand sides solved */
+  double seconds;         /* inside evaluations */
+} mw_inversion_info;
+typedef struct mw_inversion mw_inversion;
+/* mesh: the problem's mesh (host; nv, xyz and tet are read); tet_part: host
+ * [nt] partition or NULL (the library's own); S_meas, S_empty: device
+ * nrx x ntx complex (copied); tx, rx host port lists.  MW_EINVAL if S_empty
+ * has a zero entry. */
+mw_status mw_inversion_create(mw_problem *p, const mw_mesh *mesh, const int32_t *tet_part,
+                              const mw_inversion_opts *o, int32_t ntx, const int32_t *tx, int32_t nrx,
+                              const int32_t *rx, const void *S_meas, const void *S_empty, mw_inversion **out);
+/* J (host) and grad (device [nv] complex) at eps_v (device [nv] complex). */
+mw_status mw_inversion_objective(mw_inversion *inv, const void *eps_v, double *J, void *grad);
+/* mw_lbfgs over x = [Re e; Im e] from eps_v (device [nv], overwritten by the
+ * last accepted iterate); J_hist host [iters+1], eps_hist host
+ * [(iters+1) x nv] complex (either may be NULL). */
+mw_status mw_inversion_run(mw_inversion *inv, const mw_lbfgs_opts *lo, int32_t iters, void *eps_v, double *J_hist,
+                           void *eps_hist, int32_t *accepted, int32_t *evaluations);
+/* Mean GMRES iterations of the forward and adjoint solves of the first cap
+ * evaluations (host [cap] each, either may be NULL), and the totals. */
+mw_status mw_inversion_get_info(mw_inversion *inv, int32_t cap, double *iters_forward, double *iters_adjoint,
+                                mw_inversion_info *info);
+mw_status mw_inversion_destroy(mw_inversion *inv);
 
 /* ---- serving: memory, streams, factor cache, continuous batching ------ */
 /* Budget and bytes currently held by the context (either pointer may be NULL). */

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libmw.so")
 MW_OK, MW_EINVAL, MW_ENOMEM, MW_ESINGULAR, MW_ENOCONV, MW_ENUMERIC, MW_EDEVICE = 0, -1, -2, -3, -4, -5, -6
 MW_C128, MW_C64 = 0, 1
 MW_FACTOR_AUTO, MW_FACTOR_LU, MW_FACTOR_LDLT = 0, 1, 2
+MW_COARSE_NONE, MW_COARSE_CONST = 0, 1
 STATUS_NAMES = {0: "MW_OK", -1: "MW_EINVAL", -2: "MW_ENOMEM", -3: "MW_ESINGULAR", -4: "MW_ENOCONV",
                 -5: "MW_ENUMERIC", -6: "MW_EDEVICE"}
 
@@ -64,7 +65,25 @@ class mw_problem_info(C.Structure):
                 ("nports", C.c_int32), ("n_sub", C.c_int32), ("sum_ni", C.c_int64), ("max_ni", C.c_int32),
                 ("precision", C.c_int32), ("factor_bytes", C.c_int64), ("t_assemble", C.c_double),
                 ("t_decompose", C.c_double), ("t_factor", C.c_double), ("factorization", C.c_int32),
-                ("state", C.c_int64)]
+                ("state", C.c_int64), ("coarse_size", C.c_int32)]
+
+
+class mw_lbfgs_opts(C.Structure):
+    _fields_ = [("mem", C.c_int32), ("step0", C.c_double), ("c1", C.c_double), ("max_backtrack", C.c_int32)]
+
+
+class mw_inversion_opts(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("p1", C.c_int32), ("recycle", C.c_int32), ("n_sub", C.c_int32),
+                ("overlap", C.c_int32), ("precision", C.c_int32), ("solve", mw_solve_opts)]
+
+
+class mw_inversion_info(C.Structure):
+    _fields_ = [("evaluations", C.c_int32), ("solve_columns", C.c_int64), ("seconds", C.c_double)]
+
+
+# mw_objective_fn: (user, x, J, g) -> mw_status
+OBJECTIVE_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                           C.POINTER(C.c_double))
 
 
 class mw_batch_info(C.Structure):
@@ -116,6 +135,15 @@ _SIGS = {
     "mw_set_factorization": [_P, _I],
     "mw_update_eps_vertex": [_P, _P],
     "mw_gradient_vertex": [_P, _I, _P, _P, _P],
+    "mw_set_coarse_space": [_P, _I],
+    "mw_misfit_weighted": [_P, C.c_int64, _P, _P, _P, _P, _P],
+    "mw_lbfgs": [C.c_int64, _P, _I, C.POINTER(mw_lbfgs_opts), OBJECTIVE_FN, _P, _P, _P, _P, _P],
+    "mw_inversion_create": [_P, C.POINTER(mw_mesh), _P, C.POINTER(mw_inversion_opts), _I, _P, _I, _P, _P, _P,
+                            C.POINTER(_P)],
+    "mw_inversion_objective": [_P, _P, _P, _P],
+    "mw_inversion_run": [_P, C.POINTER(mw_lbfgs_opts), _I, _P, _P, _P, _P, _P],
+    "mw_inversion_get_info": [_P, _I, _P, _P, C.POINTER(mw_inversion_info)],
+    "mw_inversion_destroy": [_P],
 }
 EXPORTED = list(_SIGS) + ["mw_last_error", "mw_host_last_error", "mw_timer_families", "mw_timer_name",
                           "mw_timer_enable", "mw_timer_reset"]
@@ -217,6 +245,39 @@ def host_partition(xyz, tet, bface, btag, n_sub: int) -> np.ndarray:
     check(lib().mw_host_partition(C.byref(m), int(n_sub), ptr(part)), host=True)
     del keep
     return part
+
+
+def lbfgs(fun, x0: np.ndarray, iters: int, mem: int = 5, step0: float = 0.5, c1: float = 1e-4,
+          max_backtrack: int = 20):
+    """The library's host L-BFGS (mw_lbfgs) on a Python objective
+    fun(x) -> (J, g) over real vectors; returns the last accepted x, the
+    accepted J values and iterates, and the number of evaluations."""
+    x = np.ascontiguousarray(x0, dtype=np.float64).copy()
+    n = x.size
+    err = []
+
+    def cb(user, xp, Jp, gp):
+        try:
+            xv = np.ctypeslib.as_array(xp, shape=(n,)).copy()
+            J, g = fun(xv)
+            Jp[0] = float(J)
+            np.ctypeslib.as_array(gp, shape=(n,))[:] = np.asarray(g, dtype=np.float64)
+            return MW_OK
+        except Exception as e:  # pragma: no cover - surfaced below
+            err.append(e)
+            return MW_EINVAL
+
+    f = OBJECTIVE_FN(cb)
+    Jh = np.zeros(iters + 1)
+    Xh = np.zeros((iters + 1, n))
+    acc, nev = C.c_int32(), C.c_int32()
+    o = mw_lbfgs_opts(mem=mem, step0=step0, c1=c1, max_backtrack=max_backtrack)
+    code = lib().mw_lbfgs(n, ptr(x), iters, C.byref(o), f, None, ptr(Jh), ptr(Xh), C.addressof(acc),
+                          C.addressof(nev))
+    if err:
+        raise err[0]
+    check(code)
+    return x, Jh[: acc.value + 1], Xh[: acc.value + 1], nev.value
 
 
 def timer_enable(on: bool = True):

@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libmw.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.cpp", "hostcheck.cpp", "ktimer.cpp", "topology.cpp", "decomp.cpp", "assemble.hip", "dense.hip", "krylov.hip", "block.hip", "blockls.cpp"]
+SOURCES = ["api.cpp", "hostcheck.cpp", "ktimer.cpp", "topology.cpp", "decomp.cpp", "assemble.hip", "dense.hip", "krylov.hip",
+           "block.hip", "blockls.cpp", "coarse.hip", "invert.hip"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-x", "hip",
          # packed FP32 instructions are disabled for all device code

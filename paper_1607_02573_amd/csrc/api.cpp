@@ -17,7 +17,7 @@
 #include <numeric>
 
 #include "blockls.hpp"
-#include "kernels.hpp"
+#include "internal.hpp"
 #include "parallel.hpp"
 
 using namespace mw;
@@ -67,15 +67,6 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-struct DeviceGuard {
-  int prev = 0;
-  explicit DeviceGuard(int dev) {
-    MW_HIP(hipGetDevice(&prev));
-    if (prev != dev) MW_HIP(hipSetDevice(dev));
-  }
-  ~DeviceGuard() { (void)hipSetDevice(prev); }
-};
-
 DevBuf dalloc(mw_ctx* c, int64_t bytes) {
   DevBuf b;
   if (bytes <= 0) return b;
@@ -119,10 +110,11 @@ struct Work {
 // batch), grown on demand.
 struct GmresWork {
   Work V, X, B, Z, Y, H, Hr, cs, sn, g, y, h1, h2, hp, cf, nu, ee, part, npart, vec, ints, tmp, w_idx;
+  Work cq, cw, cy;            // two-level: Q v, v - A Q v, coarse vector
   hipStream_t st = nullptr;   // the stream this driver's work runs on
-  std::array<Work*, 23> all() {
+  std::array<Work*, 26> all() {
     return {&V, &X, &B, &Z, &Y, &H, &Hr, &cs, &sn, &g, &y, &h1, &h2, &hp, &cf, &nu, &ee, &part, &npart, &vec, &ints,
-            &tmp, &w_idx};
+            &tmp, &w_idx, &cq, &cw, &cy};
   }
   void release() {
     for (Work* w : all()) w->b.release();
@@ -176,12 +168,24 @@ struct mw_problem {
   Work w_small;
   hipStream_t stream = nullptr;    // every launch and copy of this problem
   int live_batches = 0;
+  int live_users = 0;                // inversions driving this problem
   // bumped by every call that changes the operator or the factors (eps,
   // factorisation, release), so that callers can tell whether the factors
   // still belong to the permittivity they solved with
   int64_t state = 0;
   // the internal partition (tet_part == NULL) of the last decomposition
   std::vector<int32_t> own_part;
+  // two-level preconditioner (mw_set_coarse_space): coarse space of the three
+  // constant fields per subdomain, its structures for the current
+  // decomposition, and the factors of E = Z^T A Z
+  int coarse_kind = MW_COARSE_NONE;
+  bool coarse_built = false, coarse_active = false;
+  DevBuf c_tvec, c_row_sub, c_nb_ptr, c_nb, c_fac_off, c_loc_off, c_n_loc, c_n_pad, c_sub_dof, c_ipiv, c_ridx,
+      c_info, c_amax, c_row_lo, c_fenv, c_fenvh, c_env, Fc;
+  std::vector<int32_t> ch_n_loc, ch_row_lo, ch_fenv;
+  std::vector<int2> ch_env;
+  DeviceCoarse cz;
+  DeviceDecomp cdd;
   double t_assemble = 0, t_decompose = 0, t_factor = 0;
 };
 
@@ -204,6 +208,38 @@ mw_status guard(const std::function<void()>& f) {
 }
 
 void check_prob(mw_problem* p) { MW_CHECK(p != nullptr && p->ctx != nullptr, MW_EINVAL, "problem is NULL"); }
+
+}  // namespace
+
+namespace mw {
+mw_status guarded(const std::function<void()>& f) { return guard(f); }
+hipStream_t problem_stream(mw_problem* p) {
+  check_prob(p);
+  return p->stream;
+}
+int problem_device(mw_problem* p) {
+  check_prob(p);
+  return p->ctx->device;
+}
+DevBuf problem_alloc(mw_problem* p, int64_t bytes) {
+  check_prob(p);
+  return dalloc(p->ctx, bytes);
+}
+void problem_retain(mw_problem* p) {
+  check_prob(p);
+  p->live_users++;
+}
+void problem_release(mw_problem* p) {
+  if (p) p->live_users--;
+}
+DevBuf problem_upload(mw_problem* p, const void* host, int64_t bytes) {
+  DevBuf b = problem_alloc(p, bytes);
+  if (bytes > 0) MW_HIP(hipMemcpyAsync(b.p, host, (size_t)bytes, hipMemcpyHostToDevice, p->stream));
+  return b;
+}
+}  // namespace mw
+
+namespace {
 
 void psync(mw_problem* p) { MW_HIP(hipStreamSynchronize(p->stream)); }
 
@@ -406,9 +442,8 @@ void upload_decomp(mw_problem* p) {
 }
 
 // Z = M^-1 V (n x nc, leading dimension ld), local workspace W.Y
-void apply_prec(mw_problem* p, GmresWork& W, const double2* V, double2* Z, int nc, int64_t ld) {
+void one_level(mw_problem* p, GmresWork& W, const double2* V, double2* Z, int nc, int64_t ld) {
   mw_ctx* c = p->ctx;
-  MW_CHECK(p->factors_valid, MW_EINVAL, "no valid subdomain factors: call mw_factor_subdomains");
   int64_t n = p->T.n();
   if (p->prec == MW_C64) {
     float2* Y = (float2*)W.Y.get(c, p->dd.sum_pad * nc * 8);
@@ -421,6 +456,161 @@ void apply_prec(mw_problem* p, GmresWork& W, const double2* V, double2* Z, int n
     lu_solve_batched<double2>(p->dd, p->F.as<double2>(), Y, nc, nc, W.st);
     launch_prolong<double2>(p->dd, n, Y, nc, nc, Z, ld, W.st);
   }
+}
+
+// two-level: q = Z E^-1 Z^T v, then Z = M^-1 (v - A q) + q
+template <class C>
+void two_level(mw_problem* p, GmresWork& W, const double2* V, double2* Z, int nc, int64_t ld) {
+  mw_ctx* c = p->ctx;
+  const int64_t n = p->T.n();
+  const int ncp = p->cdd.max_pad;
+  C* Yc = (C*)W.cy.get(c, (int64_t)ncp * nc * (int64_t)sizeof(C));
+  double2* q = (double2*)W.cq.get(c, n * ld * 16);
+  double2* w = (double2*)W.cw.get(c, n * ld * 16);
+  launch_coarse_restrict<C>(p->dd, p->cz, V, ld, nc, Yc, nc, ncp, W.st);
+  lu_solve_batched<C>(p->cdd, p->Fc.as<C>(), Yc, nc, nc, W.st);
+  launch_coarse_prolong<C>(p->dd, p->cz, n, Yc, nc, nc, q, ld, W.st);
+  launch_spmm(p->dm, p->val.as<double2>(), q, ld, w, ld, nc, V, ld, W.st);
+  one_level(p, W, w, Z, nc, ld);
+  launch_axpy_cols(Z, q, n, ld, nc, W.st);
+}
+
+// Z = M^-1 V (one- or two-level) for nc columns of leading dimension ld
+void apply_prec(mw_problem* p, GmresWork& W, const double2* V, double2* Z, int nc, int64_t ld) {
+  MW_CHECK(p->factors_valid, MW_EINVAL, "no valid subdomain factors: call mw_factor_subdomains");
+  if (!p->coarse_active) {
+    one_level(p, W, V, Z, nc, ld);
+  } else if (p->prec == MW_C64) {
+    two_level<float2>(p, W, V, Z, nc, ld);
+  } else {
+    two_level<double2>(p, W, V, Z, nc, ld);
+  }
+}
+
+// Structures of the coarse space for the current decomposition: edge vector
+// of every unknown, subdomain of every local row, and per subdomain i the
+// ascending list of subdomains j with E[(i,.),(j,.)] structurally nonzero (a
+// row of i with D_i > 0 coupled by A to a row of j with D_j > 0)
+void build_coarse(mw_problem* p) {
+  mw_ctx* c = p->ctx;
+  const Topology& T = p->T;
+  const Decomposition& D = p->D;
+  const int32_t nsub = D.nsub;
+  const int64_t n = T.n();
+  const int nc = 3 * nsub, ncp = (int)round_up(nc, 64);
+  MW_CHECK(ncp <= 8192, MW_EINVAL,
+           "coarse space of " + std::to_string(nc) + " unknowns exceeds the dense coarse factor's 8192 (n_sub <= 2730)");
+  std::vector<double> tvec(3 * n);
+  for (int64_t g = 0; g < n; ++g) {
+    const int64_t e = T.free_edge[g];
+    const int64_t va = T.edges[2 * e], vb = T.edges[2 * e + 1];
+    for (int a = 0; a < 3; ++a) tvec[3 * g + a] = T.xyz[3 * vb + a] - T.xyz[3 * va + a];
+  }
+  std::vector<int32_t> row_sub(D.sum_pad());
+  for (int32_t i = 0; i < nsub; ++i)
+    for (int64_t r = D.loc_off[i]; r < D.loc_off[i + 1]; ++r) row_sub[r] = i;
+  std::vector<std::vector<int32_t>> nbl(nsub);
+  parallel_for(nsub, [&](int64_t i) {
+    std::vector<int32_t> js;
+    for (int64_t r = D.loc_off[i]; r < D.loc_off[i] + D.n_pad[i]; ++r) {
+      const int32_t g = D.sub_dof[r];
+      if (g < 0 || D.D[r] == 0.0) continue;
+      for (int64_t k = T.row_ptr[g]; k < T.row_ptr[g + 1]; ++k) {
+        const int32_t h = T.col[k];
+        for (int64_t q = D.cp_ptr[h]; q < D.cp_ptr[h + 1]; ++q) js.push_back(row_sub[D.cp_row[q]]);
+      }
+      if (js.size() > (1u << 16)) {
+        std::sort(js.begin(), js.end());
+        js.erase(std::unique(js.begin(), js.end()), js.end());
+      }
+    }
+    std::sort(js.begin(), js.end());
+    js.erase(std::unique(js.begin(), js.end()), js.end());
+    nbl[i] = std::move(js);
+  });
+  std::vector<int64_t> nb_ptr(nsub + 1, 0);
+  int max_nb = 0;
+  for (int32_t i = 0; i < nsub; ++i) {
+    nb_ptr[i + 1] = nb_ptr[i] + (int64_t)nbl[i].size();
+    max_nb = std::max(max_nb, (int)nbl[i].size());
+  }
+  MW_CHECK(max_nb <= kCoarseMaxNb, MW_EINVAL,
+           "a subdomain couples to " + std::to_string(max_nb) + " others in the coarse matrix (at most " +
+               std::to_string(kCoarseMaxNb) + ")");
+  std::vector<int32_t> nb(nb_ptr[nsub]);
+  for (int32_t i = 0; i < nsub; ++i) std::copy(nbl[i].begin(), nbl[i].end(), nb.begin() + nb_ptr[i]);
+  hipStream_t st = p->stream;
+  p->c_tvec = upload(c, st, tvec);
+  p->c_row_sub = upload(c, st, row_sub);
+  p->c_nb_ptr = upload(c, st, nb_ptr);
+  p->c_nb = upload(c, st, nb);
+  DeviceCoarse& z = p->cz;
+  z.nsub = nsub;
+  z.max_nb = max_nb;
+  z.tvec = p->c_tvec.as<double>();
+  z.row_sub = p->c_row_sub.as<int32_t>();
+  z.nb_ptr = p->c_nb_ptr.as<int64_t>();
+  z.nb = p->c_nb.as<int32_t>();
+  // the coarse matrix as a single dense "subdomain" of the batched
+  // factorisation: no structural envelope assumed (every column may be
+  // nonzero), all rows needed by the backward solve
+  std::vector<int64_t> fac_off{0, (int64_t)ncp * ncp}, loc_off{0, ncp};
+  p->ch_n_loc = {nc};
+  std::vector<int32_t> n_pad{ncp}, sub_dof(ncp, -1);
+  for (int k = 0; k < nc; ++k) sub_dof[k] = k;
+  p->ch_row_lo = {0};
+  const int stride = ncp / 32;
+  p->ch_fenv.assign(stride, 0);
+  std::vector<int32_t> fenv_hi(stride, ncp);
+  p->ch_env.assign(stride, make_int2(0, 0));
+  p->c_fac_off = upload(c, st, fac_off);
+  p->c_loc_off = upload(c, st, loc_off);
+  p->c_n_loc = upload(c, st, p->ch_n_loc);
+  p->c_n_pad = upload(c, st, n_pad);
+  p->c_sub_dof = upload(c, st, sub_dof);
+  p->c_ipiv = dalloc(c, (int64_t)ncp * 4);
+  p->c_ridx = dalloc(c, (int64_t)ncp * 4);
+  p->c_info = dalloc(c, 8);
+  p->c_amax = dalloc(c, 8);
+  p->c_row_lo = upload(c, st, p->ch_row_lo);
+  p->c_fenv = upload(c, st, p->ch_fenv);
+  p->c_fenvh = upload(c, st, fenv_hi);
+  p->c_env = dalloc(c, (int64_t)stride * 8);
+  DeviceDecomp& d = p->cdd;
+  d = DeviceDecomp{};
+  d.nsub = 1;
+  d.max_pad = ncp;
+  d.sum_pad = ncp;
+  d.fac_off = p->c_fac_off.as<int64_t>();
+  d.loc_off = p->c_loc_off.as<int64_t>();
+  d.n_loc = p->c_n_loc.as<int32_t>();
+  d.n_pad = p->c_n_pad.as<int32_t>();
+  d.sub_dof = p->c_sub_dof.as<int32_t>();
+  d.ipiv = p->c_ipiv.as<int32_t>();
+  d.ridx = p->c_ridx.as<int32_t>();
+  d.info = p->c_info.as<int32_t>();
+  d.amax = p->c_amax.as<double>();
+  d.h_n_loc = p->ch_n_loc.data();
+  d.row_lo = p->c_row_lo.as<int32_t>();
+  d.h_row_lo = p->ch_row_lo.data();
+  d.fenv = p->c_fenv.as<int32_t>();
+  d.h_fenv = p->ch_fenv.data();
+  d.fenv_hi = p->c_fenvh.as<int32_t>();
+  d.fenv_stride = stride;
+  d.env = p->c_env.as<int2>();
+  d.h_env = p->ch_env.data();
+  d.env_stride = stride;
+  p->coarse_built = true;
+}
+
+// E = Z^T A Z assembled and factored (the subdomain factorisation's kind)
+template <class C>
+void factor_coarse(mw_problem* p, bool sym) {
+  hipStream_t st = p->stream;
+  const int ncp = p->cdd.max_pad;
+  launch_coarse_matrix<C>(p->dm, p->val.as<double2>(), p->dd, p->cz, p->Fc.as<C>(), ncp, st);
+  launch_zero_bytes(p->cdd.info, 4, st);
+  lu_factor_batched<C>(p->cdd, p->Fc.as<C>(), st, sym);
 }
 
 // column 2-norms squared of an n x nc block (device out), deterministic
@@ -437,6 +627,8 @@ void colnorm2(mw_problem* p, GmresWork& W, const double2* V, int64_t ld, int nc,
 int64_t gmres_bytes_per_col(mw_problem* p, int m) {
   int64_t esz = p->prec == MW_C64 ? 8 : 16;
   int64_t big = (int64_t)(m + 5) * p->T.n() * 16 + p->dd.sum_pad * esz + reduce_chunks(p->T.n()) * (2 * m + 3) * 16;
+  if (p->coarse_kind != MW_COARSE_NONE)   // two-level: Q v, v - A Q v, coarse vector
+    big += 2 * p->T.n() * 16 + (int64_t)round_up(3 * (int64_t)std::max(p->D.nsub, 1), 64) * esz;
   // Hessenberg (raw and rotated), rotations, g, y, dot sums, provisional
   // column, coefficients, norms, flags
   int64_t small = 2 * (int64_t)(m + 1) * m * 16 + (int64_t)m * 24 + 5 * (int64_t)(m + 1) * 16 + 2 * (int64_t)m * 16 +
@@ -1116,6 +1308,20 @@ mw_status mw_assemble(mw_ctx* ctx, const mw_mesh* mesh, const mw_complex* eps_r,
   });
 }
 
+mw_status mw_set_coarse_space(mw_problem* p, int32_t kind) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(kind == MW_COARSE_NONE || kind == MW_COARSE_CONST, MW_EINVAL, "unknown coarse space");
+    if (kind != p->coarse_kind) {
+      p->coarse_kind = kind;
+      p->coarse_active = false;
+      p->factors_valid = false;
+      p->state++;
+      if (kind == MW_COARSE_NONE) p->Fc.release();
+    }
+  });
+}
+
 mw_status mw_set_factorization(mw_problem* p, int32_t kind) {
   return guard([&] {
     check_prob(p);
@@ -1204,6 +1410,7 @@ mw_status mw_problem_get_info(mw_problem* p, mw_problem_info* info) {
     info->t_decompose = p->t_decompose;
     info->t_factor = p->t_factor;
     info->state = p->state;
+    info->coarse_size = p->coarse_active ? 3 * p->D.nsub : 0;
   });
 }
 
@@ -1232,6 +1439,7 @@ mw_status mw_destroy_problem(mw_problem* p) {
   return guard([&] {
     if (!p) return;
     MW_CHECK(p->live_batches == 0, MW_EINVAL, "destroy the problem's batches first");
+    MW_CHECK(p->live_users == 0, MW_EINVAL, "destroy the inversions driving the problem first");
     if (p->ctx) { DeviceGuard dg(p->ctx->device); (void)hipStreamSynchronize(p->stream); delete p; }
     else delete p;
   });
@@ -1302,6 +1510,8 @@ mw_status mw_factor_subdomains(mw_problem* p, int32_t n_sub, int32_t overlap, mw
       Decomposition D;
       build_decomposition(p->T, part, n_sub, overlap, 64, D);
       p->D = std::move(D);
+      p->coarse_built = p->coarse_active = false;
+      p->Fc.release();
       upload_decomp(p);
       p->has_dec = true;
       p->dec_key = key;
@@ -1359,6 +1569,26 @@ mw_status mw_factor_subdomains(mw_problem* p, int32_t n_sub, int32_t overlap, mw
       MW_CHECK(info[i] == 0, MW_ESINGULAR,
                "(near-)zero pivot in subdomain " + std::to_string(i) + " at column " + std::to_string(info[i] - 1));
     p->band_clean = sym;
+    p->coarse_active = false;
+    if (p->coarse_kind != MW_COARSE_NONE) {
+      if (!p->coarse_built) build_coarse(p);
+      const int64_t fcb = (int64_t)p->cdd.max_pad * p->cdd.max_pad * esz;
+      if ((int64_t)p->Fc.bytes != fcb) {
+        p->Fc.release();
+        p->Fc = dalloc(c, fcb);
+      }
+      if (prec == MW_C64) factor_coarse<float2>(p, sym);
+      else factor_coarse<double2>(p, sym);
+      int32_t cinfo = 0;
+      double camax = 0.0;
+      MW_HIP(hipMemcpyAsync(&cinfo, p->cdd.info, 4, hipMemcpyDeviceToHost, st));
+      MW_HIP(hipMemcpyAsync(&camax, p->cdd.amax, 8, hipMemcpyDeviceToHost, st));
+      MW_HIP(hipMemcpyAsync(p->ch_env.data(), p->cdd.env, p->ch_env.size() * 8, hipMemcpyDeviceToHost, st));
+      psync(p);
+      MW_CHECK(std::isfinite(camax), MW_ENUMERIC, "NaN or Inf in the coarse matrix");
+      MW_CHECK(cinfo == 0, MW_ESINGULAR, "(near-)zero pivot in the coarse matrix at column " + std::to_string(cinfo - 1));
+      p->coarse_active = true;
+    }
     p->factors_valid = true;
   });
 }
@@ -1380,6 +1610,9 @@ mw_status mw_apply_preconditioner_noalloc(mw_problem* p, int32_t nrhs, const voi
     check_prob(p);
     MW_CHECK(nrhs >= 0 && (nrhs == 0 || (V && Z)), MW_EINVAL, "NULL argument");
     MW_CHECK(p->factors_valid, MW_EINVAL, "no valid subdomain factors: call mw_factor_subdomains");
+    MW_CHECK(!p->coarse_active, MW_EINVAL,
+             "mw_apply_preconditioner_noalloc applies the one-level preconditioner only: the two-level one needs "
+             "workspace beyond the fixed buffer (use mw_apply_preconditioner)");
     if (nrhs == 0) return;
     const int64_t esz = p->prec == MW_C64 ? 8 : 16;
     const int64_t need = p->dd.sum_pad * (int64_t)nrhs * esz;
@@ -1519,12 +1752,17 @@ mw_status mw_gradient(mw_problem* p, int32_t ntx, const void* U, const void* F, 
 }
 
 mw_status mw_misfit(mw_problem* p, int64_t count, const void* S_sim, const void* S_meas, void* gS, double* J) {
+  return mw_misfit_weighted(p, count, S_sim, S_meas, nullptr, gS, J);
+}
+
+mw_status mw_misfit_weighted(mw_problem* p, int64_t count, const void* S_sim, const void* S_meas, const double* W,
+                             void* gS, double* J) {
   return guard([&] {
     check_prob(p);
     MW_CHECK(count >= 1 && S_sim && S_meas && gS && J, MW_EINVAL, "NULL argument");
     DeviceGuard dg(p->ctx->device);
     double* dJ = (double*)p->w_small.get(p->ctx, 16);
-    launch_misfit((const double2*)S_sim, (const double2*)S_meas, count, (double2*)gS, dJ, p->stream);
+    launch_misfit((const double2*)S_sim, (const double2*)S_meas, W, count, (double2*)gS, dJ, p->stream);
     MW_HIP(hipMemcpyAsync(J, dJ, 8, hipMemcpyDeviceToHost, p->stream));
     psync(p);
   });
@@ -1602,8 +1840,10 @@ mw_status mw_release_factors(mw_problem* p) {
     psync(p);
     p->state++;
     p->F.release();
+    p->Fc.release();
     p->ws.release();
     p->factors_valid = false;
+    p->coarse_active = false;
   });
 }
 

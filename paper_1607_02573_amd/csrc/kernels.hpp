@@ -7,7 +7,7 @@ namespace mw {
 
 // kernel families timed by ktimer.cpp
 enum KFamily { KF_TRSM_GEMM, KF_TRSM_LEAF, KF_LU_GEMM, KF_LU_PANEL, KF_LU_OTHER, KF_SPMM, KF_CGS_DOTS,
-               KF_CGS_UPDATE, KF_RESTRICT, KF_PROLONG, KF_VECTOR, KF_BGS_DOTS, KF_BGS_UPDATE, KF_COUNT };
+               KF_CGS_UPDATE, KF_RESTRICT, KF_PROLONG, KF_VECTOR, KF_BGS_DOTS, KF_BGS_UPDATE, KF_COARSE, KF_COUNT };
 bool kt_enabled();
 void kt_begin(int family, hipStream_t st);
 void kt_end(int family, hipStream_t st, double flops, double bytes);
@@ -98,6 +98,18 @@ struct DeviceDecomp {
   int2* env = nullptr;
   const int2* h_env = nullptr;       // host copy (launch accounting)
   int env_stride = 0;
+};
+
+// Coarse space of the two-level preconditioner (coarse.hip): three coarse
+// unknowns per subdomain (the weighted interpolants of the constant fields).
+constexpr int kCoarseMaxNb = 256;   // most neighbours a subdomain may have in E
+struct DeviceCoarse {
+  int nsub = 0;
+  int max_nb = 0;                      // longest neighbour list
+  const double* tvec = nullptr;        // [n*3] edge vector x_hi - x_lo of every unknown
+  const int32_t* row_sub = nullptr;    // [sum_pad] subdomain of every local row
+  const int64_t* nb_ptr = nullptr;     // [nsub+1] neighbour lists of E's block rows
+  const int32_t* nb = nullptr;         // ascending subdomain ids, the subdomain itself included
 };
 
 // ---- assembly (assemble.hip)
@@ -195,6 +207,20 @@ void launch_bdots(const double2* V, int64_t vstride, int kv, const double2* E, c
 void launch_bupdate(const double2* V, int64_t vstride, int kv, const int32_t* kvb, int kv_max, const double2* P,
                     int pk_stride, const double2* Rinv, const double2* Win, double2* Out, int64_t n, int64_t ld,
                     int ncols, int nb, const int32_t* blk, hipStream_t st);
-void launch_misfit(const double2* S, const double2* Sm, int64_t count, double2* gS, double* J, hipStream_t st);
+// gS = W (S - Sm), J = 1/2 sum W |S - Sm|^2 (W = NULL: weights 1)
+void launch_misfit(const double2* S, const double2* Sm, const double* W, int64_t count, double2* gS, double* J,
+                   hipStream_t st);
+
+// two-level ORAS (coarse.hip): E = Z^T A Z into F (ldf x ldf, identity on the
+// padding), Y = Z^T V (rows 3 nsub .. ldf zero), Q = Z Y
+template <class C>
+void launch_coarse_matrix(const DeviceMesh& m, const double2* val, const DeviceDecomp& d, const DeviceCoarse& cz,
+                          C* F, int ldf, hipStream_t st);
+template <class C>
+void launch_coarse_restrict(const DeviceDecomp& d, const DeviceCoarse& cz, const double2* V, int64_t ldv, int ncols,
+                            C* Y, int64_t ldy, int ldf, hipStream_t st);
+template <class C>
+void launch_coarse_prolong(const DeviceDecomp& d, const DeviceCoarse& cz, int64_t n, const C* Y, int64_t ldy,
+                           int ncols, double2* Q, int64_t ldq, hipStream_t st);
 
 }  // namespace mw

@@ -859,13 +859,15 @@ void launch_zero(double2* p, int64_t count, hipStream_t st) { launch_zero_bytes(
 
 // gS = S - Smes and J = 1/2 sum |gS|^2 (one workgroup, fixed summation order)
 __global__ void __launch_bounds__(256) k_misfit(const double2* __restrict__ S, const double2* __restrict__ Sm,
-                                                int64_t count, double2* __restrict__ gS, double* __restrict__ J) {
+                                                const double* __restrict__ W, int64_t count,
+                                                double2* __restrict__ gS, double* __restrict__ J) {
   __shared__ double red[256];
   double acc = 0.0;
   for (int64_t k = threadIdx.x; k < count; k += 256) {
     double2 d = csub(S[k], Sm[k]);
-    gS[k] = d;
-    acc += d.x * d.x + d.y * d.y;
+    const double w = W ? W[k] : 1.0;
+    gS[k] = make_double2(w * d.x, w * d.y);
+    acc += w * (d.x * d.x + d.y * d.y);
   }
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -875,8 +877,9 @@ __global__ void __launch_bounds__(256) k_misfit(const double2* __restrict__ S, c
   }
   if (threadIdx.x == 0) J[0] = 0.5 * red[0];
 }
-void launch_misfit(const double2* S, const double2* Sm, int64_t count, double2* gS, double* J, hipStream_t st) {
-  k_misfit<<<1, 256, 0, st>>>(S, Sm, count, gS, J);
+void launch_misfit(const double2* S, const double2* Sm, const double* W, int64_t count, double2* gS, double* J,
+                   hipStream_t st) {
+  k_misfit<<<1, 256, 0, st>>>(S, Sm, W, count, gS, J);
   MW_LAUNCH_CHECK();
 }
 

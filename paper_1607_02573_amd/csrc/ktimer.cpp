@@ -13,7 +13,7 @@ namespace mw {
 namespace {
 const char* kNames[KF_COUNT] = {"trsm_gemm", "trsm_leaf", "lu_gemm", "lu_panel", "lu_other", "spmm",
                                 "cgs_dots", "cgs_update", "restrict", "prolong", "vector", "bgs_dots",
-                                "bgs_update"};
+                                "bgs_update", "coarse"};
 struct Fam {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
   double flops = 0, bytes = 0;

@@ -148,6 +148,12 @@ class Problem:
         return nu[: self.nports]
 
     # ------------------------------------------------------------------ preconditioner
+    def set_coarse_space(self, kind: str):
+        """'none' (one-level ORAS) or 'const' (two-level: three weighted
+        constant fields per subdomain); takes effect at the next factor()."""
+        k = {"none": B.MW_COARSE_NONE, "const": B.MW_COARSE_CONST}[kind]
+        check(lib().mw_set_coarse_space(self.h, k))
+
     def set_factorization(self, kind: str):
         """'auto' (L D L^T when every tetrahedron is lossy, else LU), 'lu' or 'ldlt'."""
         k = {"auto": B.MW_FACTOR_AUTO, "lu": B.MW_FACTOR_LU, "ldlt": B.MW_FACTOR_LDLT}[kind]
@@ -282,13 +288,18 @@ class Problem:
         check(lib().mw_gradient_vertex(self.h, U.shape[1], ptr(U), ptr(F), ptr(g)))
         return g
 
-    def misfit(self, S: torch.Tensor, S_meas: torch.Tensor):
+    def misfit(self, S: torch.Tensor, S_meas: torch.Tensor, weights: torch.Tensor | None = None):
+        """J = 1/2 sum w |S - S_meas|^2 and gS = w (S - S_meas) (w = 1 if None)."""
         _dev_tensor(S, torch.complex128, self.ctx.device, "S")
         _dev_tensor(S_meas, torch.complex128, self.ctx.device, "S_meas")
         assert S.shape == S_meas.shape
+        if weights is not None:
+            _dev_tensor(weights, torch.float64, self.ctx.device, "weights")
+            assert weights.shape == S.shape
         gS = torch.empty_like(S)
         J = C.c_double()
-        check(lib().mw_misfit(self.h, S.numel(), ptr(S), ptr(S_meas), ptr(gS), C.addressof(J)))
+        check(lib().mw_misfit_weighted(self.h, S.numel(), ptr(S), ptr(S_meas),
+                                       None if weights is None else ptr(weights), ptr(gS), C.addressof(J)))
         return J.value, gS
 
 

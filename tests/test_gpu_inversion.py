@@ -55,6 +55,7 @@ def test_lbfgs_on_gpu_matches_oracle(setup, prec, tol, rtol, recycle):
     for eg, eo in zip(h.eps, es):
         assert np.linalg.norm(eg - eo) <= rtol * np.linalg.norm(eo)
     assert h.J[-1] < 0.5 * h.J[0]
+    inv.close()
     Pg.close()
     ctx.close()
 
@@ -69,6 +70,7 @@ def test_block_mode_inversion_matches(setup):
                               precision="c128", tol=1e-11, block=32)
     h = inv.run(e_gel, iters=3, step0=0.5)
     np.testing.assert_allclose(h.J, Js, rtol=1e-7)
+    inv.close()
     Pg.close()
     ctx.close()
 
@@ -117,6 +119,7 @@ def test_vertex_permittivity_operator_and_gradient_match_oracle(setup_p1):
     Jg, g_g = inv.objective(e_gel)
     assert abs(Jg - J) <= 1e-9 * abs(J)
     assert np.abs(g_g - g_o).max() <= 1e-7 * np.abs(g_o).max()
+    inv.close()
     Pg.close()
     ctx.close()
 
@@ -133,5 +136,6 @@ def test_lbfgs_with_vertex_permittivity_matches_oracle(setup_p1):
     np.testing.assert_allclose(h.J, Js, rtol=1e-7)
     for eg, eo in zip(h.eps, es):
         assert np.linalg.norm(eg - eo) <= 1e-7 * np.linalg.norm(eo)
+    inv.close()
     Pg.close()
     ctx.close()

@@ -1,50 +1,50 @@
-"""CPU checks of the GPU inversion driver's host side: its vertex averaging and
-P1 stiffness equal the oracle's, and its L-BFGS takes the oracle's steps on a
-quadratic (no device needed)."""
+"""CPU checks of the library's host side of the inversion loop: its L-BFGS
+(mw_lbfgs, driven through a Python objective) takes the oracle's steps on a
+quadratic and minimises it; bad options are refused (no device needed)."""
 import numpy as np
+import pytest
 
-import mw_inputs as mi
-from oracle import fem, inversion as oinv
-
-
-def test_vertex_maps_and_stiffness_equal_oracle():
-    from paper_1607_02573_amd import inversion
-    w = mi.configs.small_chamber(0.15e9, n_per_ring=8)
-    fp = fem.build(w.mesh, w.eps, w.k0, w.beta_imp, w.ports)
-    nv = w.mesh.xyz.shape[0]
-    rng = np.random.default_rng(1)
-    ev = rng.normal(size=nv) + 1j * rng.normal(size=nv)
-    A = inversion.vertex_average_matrix(w.mesh.tet, nv)
-    np.testing.assert_allclose(A @ ev, oinv.vertex_mean(w.mesh.tet, ev), rtol=1e-14)
-    K = inversion.p1_stiffness(w.mesh.xyz, w.mesh.tet)
-    Ko = oinv.stiffness_p1(fp.xyz, fp.tet)
-    assert abs(K - Ko).max() <= 1e-12 * abs(Ko).max()
+from oracle import inversion as oinv
 
 
-def test_lbfgs_steps_equal_oracle_on_a_quadratic():
-    from paper_1607_02573_amd import inversion
-    n = 9
-    rng = np.random.default_rng(2)
+def _quadratic(n, seed):
+    rng = np.random.default_rng(seed)
     M = rng.normal(size=(2 * n, 2 * n))
     Q = M @ M.T + 0.5 * np.eye(2 * n)
     b = rng.normal(size=2 * n)
+    return Q, b
 
-    def fun(e):
+
+def test_lbfgs_steps_equal_oracle_on_a_quadratic():
+    from paper_1607_02573_amd import binding
+    n = 9
+    Q, b = _quadratic(n, 2)
+
+    def real_fun(x):
+        return 0.5 * x @ Q @ x - b @ x, Q @ x - b
+
+    def cplx_fun(e):
         x = np.concatenate([e.real, e.imag])
-        g = Q @ x - b
-        return 0.5 * x @ Q @ x - b @ x, g[:n] + 1j * g[n:]
+        J, g = real_fun(x)
+        return J, g[:n] + 1j * g[n:], None
 
-    class Quad(inversion.Inversion):
-        def __init__(self):
-            self.nv = n
-            self.history = inversion.History()
+    x, Jh, Xh, nev = binding.lbfgs(real_fun, np.zeros(2 * n), iters=25, mem=4, step0=0.3)
+    es, Js, nev_o = oinv.lbfgs(cplx_fun, np.zeros(n, dtype=complex), iters=25, mem=4, step0=0.3)
+    assert nev == nev_o
+    np.testing.assert_allclose(Jh, Js, rtol=1e-10, atol=1e-12 * abs(Js[0]))
+    xo = np.concatenate([es[-1].real, es[-1].imag])
+    assert np.abs(x - xo).max() <= 1e-9 * np.abs(xo).max()
+    for k in range(len(es)):
+        np.testing.assert_allclose(Xh[k], np.concatenate([es[k].real, es[k].imag]), rtol=1e-9, atol=1e-12)
+    # J decreases at every accepted step, towards the minimiser of the quadratic
+    assert (np.diff(Jh) < 0).all()
+    xs = np.linalg.solve(Q, b)
+    assert np.linalg.norm(x - xs) <= 1e-2 * np.linalg.norm(xs)
 
-        def objective(self, e):
-            self.history.evaluations += 1
-            return fun(e)
 
-    h = Quad().run(np.zeros(n, dtype=complex), iters=25, mem=4, step0=0.3)
-    es, Js, nev = oinv.lbfgs(lambda e: (*fun(e), None), np.zeros(n, dtype=complex), iters=25, mem=4, step0=0.3)
-    assert h.evaluations == nev
-    np.testing.assert_allclose(h.J, Js, rtol=1e-10, atol=1e-12 * abs(Js[0]))
-    assert np.abs(h.eps[-1] - es[-1]).max() <= 1e-9 * np.abs(es[-1]).max()
+def test_lbfgs_refuses_bad_options_and_reports_objective_errors():
+    from paper_1607_02573_amd import binding
+    with pytest.raises(binding.MwError):
+        binding.lbfgs(lambda x: (float(x @ x), 2 * x), np.ones(3), iters=2, mem=0)
+    with pytest.raises(ZeroDivisionError):
+        binding.lbfgs(lambda x: (1 / 0, x), np.ones(3), iters=2)
