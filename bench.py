@@ -342,6 +342,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--serve-short", type=int, default=40,
                     help="requests of the short serving leg of the default line (0: none)")
+    ap.add_argument("--two-level-steps", type=int, default=2,
+                    help="timed mixed steps with the two-level preconditioner beside the one-level line (0: none)")
     ap.add_argument("--cpu-cols", type=int, default=2,
                     help="port columns the oracle baseline solves (the rest scaled by column count)")
     ap.add_argument("--serve-rate", type=float, default=4.0)
@@ -453,8 +455,49 @@ def main():
     if fp_oracle is not None:
         err_mixed = oracle_errors(w, fp_oracle, B_oracle, Xm, tx, "mixed")
 
+    # ---------------- two-level preconditioner (coarse space), same mixed step
+    two_level = None
+    if args.two_level_steps > 0 and args.block == 0:
+        del Xm, Sm
+        Xm = Sm = None
+        torch.cuda.empty_cache()
+        P.set_coarse_space("const")
+        log(f"[bench] two-level: warm-up step, then {args.two_level_steps} timed mixed steps")
+        run_steps(P, w, eps_dev, "c64", 1, tol, args.restart, args.maxit, tx, rx)
+        binding.timer_enable(True)
+        binding.timer_reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st2, (X2, S2) = run_steps(P, w, eps_dev, "c64", args.two_level_steps, tol, args.restart, args.maxit, tx, rx)
+        torch.cuda.synchronize()
+        T2 = time.perf_counter() - t0
+        fam2 = binding.timer_read()
+        binding.timer_enable(False)
+        ok2 = int(sum((s["relres"] <= tol).sum() for s in st2))
+        it2 = np.concatenate([s["iters"] for s in st2])
+        two_level = {"value": ok2 / T2, "unit": "RHS/s", "ms_per_step": 1e3 * T2 / args.two_level_steps,
+                     "steps": args.two_level_steps, "iters_mean": float(it2.mean()), "iters_max": int(it2.max()),
+                     "converged": ok2, "coarse_size": int(P.info().coarse_size),
+                     "solve_rhs_per_s": sum(len(s["relres"]) for s in st2) / sum(s["t_solve"] for s in st2),
+                     "setup_s": st2[-1]["t_setup"], "chunks": st2[-1]["chunks"],
+                     "coarse_ms_per_step": fam2["coarse"]["ms"] / args.two_level_steps,
+                     "one_level": {"value": value, "iters_mean": float(it_mixed.mean()),
+                                   "ms_per_step": 1e3 * T / args.steps},
+                     "coarse_space": "three partition-of-unity-weighted constant fields per subdomain, "
+                                     "deflated correction M^-1 (v - A q) + q, q = Z E^-1 Z^T v",
+                     "error_vs_oracle": oracle_errors(w, fp_oracle, B_oracle, X2, tx, "two-level")
+                     if fp_oracle is not None else None}
+        log(f"[bench] two-level: {T2 / args.two_level_steps:.2f} s/step, {two_level['value']:.2f} RHS/s, iters "
+            f"{it2.min()}-{it2.max()} (one-level {it_mixed.min()}-{it_mixed.max()})")
+        del X2, S2
+        P.set_coarse_space("none")
+        P.factor(w.part, w.n_sub, 1, "c64")
+
     # ---------------- FP64 path, same workload
     fp64 = None
+    if Xm is None and args.fp64_steps > 0 and args.workload != "cube8":
+        # the mixed fields for the comparison below: the last mixed step again
+        _, (Xm, Sm) = run_steps(P, w, eps_dev, "c64", 1, tol, args.restart, args.maxit, tx, rx, args.block)
     if args.fp64_steps > 0 and args.workload != "cube8":
         Xm_host = Xm[:, : min(8, Xm.shape[1])].cpu()
         Sm_host = Sm.cpu() if Sm is not None else None
@@ -537,6 +580,7 @@ def main():
         "iters_max": int(it_mixed.max()),
         "converged": ok,
         "error_vs_oracle": err_mixed,
+        "two_level": two_level,
         "latency": latency,
         "fp64": fp64,
         "speedup_mixed_vs_fp64": (value / fp64["value"]) if fp64 else None,

@@ -110,7 +110,7 @@ struct Work {
 // batch), grown on demand.
 struct GmresWork {
   Work V, X, B, Z, Y, H, Hr, cs, sn, g, y, h1, h2, hp, cf, nu, ee, part, npart, vec, ints, tmp, w_idx;
-  Work cq, cw, cy;            // two-level: Q v, v - A Q v, coarse vector
+  Work cq, cw, cy;            // two-level: Q v, (spare), coarse vector
   hipStream_t st = nullptr;   // the stream this driver's work runs on
   std::array<Work*, 26> all() {
     return {&V, &X, &B, &Z, &Y, &H, &Hr, &cs, &sn, &g, &y, &h1, &h2, &hp, &cf, &nu, &ee, &part, &npart, &vec, &ints,
@@ -398,6 +398,7 @@ void upload_decomp(mw_problem* p) {
   p->d_row_lo = upload(c, p->stream, p->h_row_lo);
   DeviceDecomp& d = p->dd;
   d.nsub = D.nsub;
+  d.n_glob = p->T.n();
   d.max_pad = *std::max_element(D.n_pad.begin(), D.n_pad.end());
   d.sum_pad = D.sum_pad();
   d.fac_off = p->d_fac_off.as<int64_t>();
@@ -458,7 +459,9 @@ void one_level(mw_problem* p, GmresWork& W, const double2* V, double2* Z, int nc
   }
 }
 
-// two-level: q = Z E^-1 Z^T v, then Z = M^-1 (v - A q) + q
+// two-level: q = Z E^-1 Z^T v, then Z = M^-1 (v - A q) + q; v - A q is
+// formed in Z itself (the one-level restriction reads all of it before the
+// prolongation overwrites it)
 template <class C>
 void two_level(mw_problem* p, GmresWork& W, const double2* V, double2* Z, int nc, int64_t ld) {
   mw_ctx* c = p->ctx;
@@ -466,12 +469,11 @@ void two_level(mw_problem* p, GmresWork& W, const double2* V, double2* Z, int nc
   const int ncp = p->cdd.max_pad;
   C* Yc = (C*)W.cy.get(c, (int64_t)ncp * nc * (int64_t)sizeof(C));
   double2* q = (double2*)W.cq.get(c, n * ld * 16);
-  double2* w = (double2*)W.cw.get(c, n * ld * 16);
   launch_coarse_restrict<C>(p->dd, p->cz, V, ld, nc, Yc, nc, ncp, W.st);
   lu_solve_batched<C>(p->cdd, p->Fc.as<C>(), Yc, nc, nc, W.st);
   launch_coarse_prolong<C>(p->dd, p->cz, n, Yc, nc, nc, q, ld, W.st);
-  launch_spmm(p->dm, p->val.as<double2>(), q, ld, w, ld, nc, V, ld, W.st);
-  one_level(p, W, w, Z, nc, ld);
+  launch_spmm(p->dm, p->val.as<double2>(), q, ld, Z, ld, nc, V, ld, W.st);
+  one_level(p, W, Z, Z, nc, ld);
   launch_axpy_cols(Z, q, n, ld, nc, W.st);
 }
 
@@ -627,8 +629,8 @@ void colnorm2(mw_problem* p, GmresWork& W, const double2* V, int64_t ld, int nc,
 int64_t gmres_bytes_per_col(mw_problem* p, int m) {
   int64_t esz = p->prec == MW_C64 ? 8 : 16;
   int64_t big = (int64_t)(m + 5) * p->T.n() * 16 + p->dd.sum_pad * esz + reduce_chunks(p->T.n()) * (2 * m + 3) * 16;
-  if (p->coarse_kind != MW_COARSE_NONE)   // two-level: Q v, v - A Q v, coarse vector
-    big += 2 * p->T.n() * 16 + (int64_t)round_up(3 * (int64_t)std::max(p->D.nsub, 1), 64) * esz;
+  if (p->coarse_kind != MW_COARSE_NONE)   // two-level: Q v and the coarse vector
+    big += p->T.n() * 16 + (int64_t)round_up(3 * (int64_t)std::max(p->D.nsub, 1), 64) * esz;
   // Hessenberg (raw and rotated), rotations, g, y, dot sums, provisional
   // column, coefficients, norms, flags
   int64_t small = 2 * (int64_t)(m + 1) * m * 16 + (int64_t)m * 24 + 5 * (int64_t)(m + 1) * 16 + 2 * (int64_t)m * 16 +

@@ -57,6 +57,7 @@ struct DevicePorts {
 
 struct DeviceDecomp {
   int nsub = 0;
+  int64_t n_glob = 0;           // global unknowns (restriction traffic)
   int max_pad = 0;
   int64_t sum_pad = 0;
   const int64_t* fac_off = nullptr;

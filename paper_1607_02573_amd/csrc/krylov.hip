@@ -268,7 +268,10 @@ void launch_restrict(const DeviceDecomp& d, const double2* V, int64_t ldv, int n
   if (kt_enabled()) {
     double sl = 0;
     for (int i = 0; i < d.nsub; ++i) sl += d.h_n_loc[i];
-    kt_end(KF_RESTRICT, st, 0.0, sl * 4 + sl * ncols * (16.0 + sizeof(C)));
+    // algorithmic bytes: every global row read once (n x 16 per column; the
+    // copies of a row shared by several subdomains come from L2), the gather
+    // index, and every local row written
+    kt_end(KF_RESTRICT, st, 0.0, sl * 4 + (double)d.n_glob * ncols * 16.0 + sl * ncols * (double)sizeof(C));
   }
 }
 
