@@ -382,7 +382,10 @@ mw_status mw_problem_set_stream(mw_problem *p, void *stream);
  * rebuilt. */
 mw_status mw_release_factors(mw_problem *p);
 /* Bytes mw_factor_subdomains holds for the factors of this partition in
- * `prec` (the decomposition must have been built once). */
+ * `prec` (the decomposition must have been built once): banded storage when
+ * the next factorisation is L D L^T without interchanges (mw_set_factorization,
+ * or automatic with every tetrahedron lossy), dense n_pad^2 per subdomain for
+ * LU with interchanges. */
 mw_status mw_factor_bytes(mw_problem *p, int32_t n_sub, int32_t overlap, mw_precision prec,
                           const int32_t *tet_part, int64_t *bytes);
 
@@ -452,6 +455,16 @@ mw_status mw_host_decomposition(const mw_mesh *mesh, const int32_t *tet_part, in
  * H with steps = 0: resid[0] gets the number of pivots of its Cholesky
  * factor that are <= thr (relative to the largest diagonal entry) and Y its
  * Cholesky factor R (G = R^H R, upper triangular). */
+/* Storage of the subdomain factors for this decomposition, in complex
+ * elements over all subdomains: dense_elems = sum n_pad^2 (LU with
+ * interchanges), band_elems (L D L^T without interchanges: every 64-row
+ * block keeps the columns of its structural envelope, 64-aligned, and at
+ * least 64 columns past its diagonal block).  blk_lo / blk_hi (host
+ * [n_pad(sub)/64], either may be NULL): the stored column range
+ * [lo, hi) of every 64-row block of subdomain `sub`. */
+mw_status mw_host_factor_storage(const mw_mesh *mesh, const int32_t *tet_part, int32_t n_sub, int32_t overlap,
+                                 int32_t sub, int32_t *blk_lo, int32_t *blk_hi, int64_t *dense_elems,
+                                 int64_t *band_elems);
 /* The partition mw_factor_subdomains takes when tet_part is NULL: tet_part
  * (host [nt], caller-owned) gets the part of every tetrahedron.  Section 3
  * starts from a non-overlapping partition of the mesh into n_sub subdomains;

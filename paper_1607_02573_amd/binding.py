@@ -132,6 +132,7 @@ _SIGS = {
     "mw_host_decomposition": [C.POINTER(mw_mesh), _P, _I, _I, _P, _P, _P, _P],
     "mw_host_block_lstsq": [_I, _I, _P, _P, C.c_double, _P, _P],
     "mw_host_partition": [C.POINTER(mw_mesh), _I, _P],
+    "mw_host_factor_storage": [C.POINTER(mw_mesh), _P, _I, _I, _I, _P, _P, _P, _P],
     "mw_set_factorization": [_P, _I],
     "mw_update_eps_vertex": [_P, _P],
     "mw_gradient_vertex": [_P, _I, _P, _P, _P],
@@ -278,6 +279,21 @@ def lbfgs(fun, x0: np.ndarray, iters: int, mem: int = 5, step0: float = 0.5, c1:
         raise err[0]
     check(code)
     return x, Jh[: acc.value + 1], Xh[: acc.value + 1], nev.value
+
+
+def host_factor_storage(xyz, tet, bface, btag, part, n_sub: int, overlap: int = 1, sub: int = 0):
+    """Factor storage of the decomposition: (dense elements, banded elements,
+    stored column range [lo, hi) of every 64-row block of subdomain `sub`)."""
+    m, keep = make_mesh(xyz, tet, bface, btag)
+    part = np.ascontiguousarray(part, dtype=np.int32)
+    dense, band = C.c_int64(), C.c_int64()
+    lo = np.zeros(8192 // 64, dtype=np.int32)
+    hi = np.zeros(8192 // 64, dtype=np.int32)
+    check(lib().mw_host_factor_storage(C.byref(m), ptr(part), int(n_sub), int(overlap), int(sub), ptr(lo), ptr(hi),
+                                       C.addressof(dense), C.addressof(band)), host=True)
+    del keep
+    nb = int((hi > 0).sum())
+    return dense.value, band.value, lo[:nb], hi[:nb]
 
 
 def timer_enable(on: bool = True):

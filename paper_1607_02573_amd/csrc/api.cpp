@@ -160,9 +160,9 @@ struct mw_problem {
   int factor_kind = MW_FACTOR_AUTO;   // requested
   int factorization = 0;              // used by the current factors (MW_FACTOR_LU / MW_FACTOR_LDLT)
   bool factors_valid = false;
-  // F holds zeros outside the band of every 32-row group (true after a
-  // factorisation without interchanges; a refill then clears the band only)
-  bool band_clean = false;
+  // factor storage of F: banded (L D L^T, no interchanges) or dense (LU)
+  bool banded = false;
+  DevBuf d_boff_dense, d_blo_dense, d_bw_dense, d_boff_band, d_blo_band, d_bw_band, d_fac_off_band;
   // workspaces of mw_solve / mw_apply_preconditioner, and of small index lists
   GmresWork ws;
   Work w_small;
@@ -181,7 +181,7 @@ struct mw_problem {
   int coarse_kind = MW_COARSE_NONE;
   bool coarse_built = false, coarse_active = false;
   DevBuf c_tvec, c_row_sub, c_nb_ptr, c_nb, c_fac_off, c_loc_off, c_n_loc, c_n_pad, c_sub_dof, c_ipiv, c_ridx,
-      c_info, c_amax, c_row_lo, c_fenv, c_fenvh, c_env, Fc;
+      c_info, c_amax, c_row_lo, c_fenv, c_fenvh, c_env, c_boff, c_blo, c_bw, Fc;
   std::vector<int32_t> ch_n_loc, ch_row_lo, ch_fenv;
   std::vector<int2> ch_env;
   DeviceCoarse cz;
@@ -370,6 +370,13 @@ void upload_decomp(mw_problem* p) {
   mw_ctx* c = p->ctx;
   const Decomposition& D = p->D;
   p->d_fac_off = upload(c, p->stream, D.fac_off);
+  p->d_fac_off_band = upload(c, p->stream, D.fac_off_band);
+  p->d_boff_dense = upload(c, p->stream, D.boff_dense);
+  p->d_blo_dense = upload(c, p->stream, D.blo_dense);
+  p->d_bw_dense = upload(c, p->stream, D.bw_dense);
+  p->d_boff_band = upload(c, p->stream, D.boff_band);
+  p->d_blo_band = upload(c, p->stream, D.blo_band);
+  p->d_bw_band = upload(c, p->stream, D.bw_band);
   p->d_loc_off = upload(c, p->stream, D.loc_off);
   p->d_n_loc = upload(c, p->stream, D.n_loc);
   p->d_n_pad = upload(c, p->stream, D.n_pad);
@@ -402,6 +409,10 @@ void upload_decomp(mw_problem* p) {
   d.max_pad = *std::max_element(D.n_pad.begin(), D.n_pad.end());
   d.sum_pad = D.sum_pad();
   d.fac_off = p->d_fac_off.as<int64_t>();
+  d.boff = p->d_boff_dense.as<int64_t>();
+  d.blo = p->d_blo_dense.as<int32_t>();
+  d.bw = p->d_bw_dense.as<int32_t>();
+  d.bstride = D.bstride;
   d.loc_off = p->d_loc_off.as<int64_t>();
   d.n_loc = p->d_n_loc.as<int32_t>();
   d.n_pad = p->d_n_pad.as<int32_t>();
@@ -475,6 +486,36 @@ void two_level(mw_problem* p, GmresWork& W, const double2* V, double2* Z, int nc
   launch_spmm(p->dm, p->val.as<double2>(), q, ld, Z, ld, nc, V, ld, W.st);
   one_level(p, W, Z, Z, nc, ld);
   launch_axpy_cols(Z, q, n, ld, nc, W.st);
+}
+
+// Factorisation the next mw_factor_subdomains uses: L D L^T without
+// interchanges when requested, or (automatic) when every tetrahedron is lossy
+bool choose_sym(mw_problem* p) {
+  if (p->factor_kind != MW_FACTOR_AUTO) return p->factor_kind == MW_FACTOR_LDLT;
+  double* dmax = (double*)p->w_small.get(p->ctx, 8);
+  double hmax = 0.0;
+  launch_max_imag(p->eps.as<double2>(), p->T.nt, dmax, p->stream);
+  MW_HIP(hipMemcpyAsync(&hmax, dmax, 8, hipMemcpyDeviceToHost, p->stream));
+  MW_HIP(hipStreamSynchronize(p->stream));
+  return hmax < 0.0;
+}
+
+// factor storage: banded for the factorisation without interchanges, dense
+// for LU with interchanges; elements of the whole batch
+int64_t factor_elems(const Decomposition& D, bool banded) {
+  // (one dense 64-row block of slack after the banded storage: no kernel
+  // reads outside its rows' stored columns, and none could leave the buffer)
+  int32_t mp = 0;
+  for (int32_t np : D.n_pad) mp = std::max(mp, np);
+  return banded ? D.fac_off_band.back() + (int64_t)64 * mp : D.fac_off.back();
+}
+void set_layout(mw_problem* p, bool banded) {
+  DeviceDecomp& d = p->dd;
+  p->banded = banded;
+  d.fac_off = (banded ? p->d_fac_off_band : p->d_fac_off).as<int64_t>();
+  d.boff = (banded ? p->d_boff_band : p->d_boff_dense).as<int64_t>();
+  d.blo = (banded ? p->d_blo_band : p->d_blo_dense).as<int32_t>();
+  d.bw = (banded ? p->d_bw_band : p->d_bw_dense).as<int32_t>();
 }
 
 // Z = M^-1 V (one- or two-level) for nc columns of leading dimension ld
@@ -602,6 +643,17 @@ void build_coarse(mw_problem* p) {
   d.env = p->c_env.as<int2>();
   d.h_env = p->ch_env.data();
   d.env_stride = stride;
+  // dense storage of the coarse matrix
+  std::vector<int64_t> boff(ncp / 64);
+  std::vector<int32_t> blo(ncp / 64, 0), bw(ncp / 64, ncp);
+  for (int b = 0; b < ncp / 64; ++b) boff[b] = (int64_t)64 * b * ncp;
+  p->c_boff = upload(c, st, boff);
+  p->c_blo = upload(c, st, blo);
+  p->c_bw = upload(c, st, bw);
+  d.boff = p->c_boff.as<int64_t>();
+  d.blo = p->c_blo.as<int32_t>();
+  d.bw = p->c_bw.as<int32_t>();
+  d.bstride = ncp / 64;
   p->coarse_built = true;
 }
 
@@ -1520,43 +1572,28 @@ mw_status mw_factor_subdomains(mw_problem* p, int32_t n_sub, int32_t overlap, mw
     }
     double t1 = now_s();
     p->t_decompose = t1 - t0;
+    hipStream_t st = p->stream;
+    const bool sym = choose_sym(p);
     int64_t esz = prec == MW_C64 ? 8 : 16;
-    int64_t need = p->D.fac_off.back() * esz;
+    int64_t need = factor_elems(p->D, sym) * esz;
+    p->factors_valid = false;
     if ((int64_t)p->F.bytes != need) {
       p->F.release();
-      p->factors_valid = false;
       // solve workspaces are re-created on demand; give their memory to the factors
       p->ws.release();
       p->F = dalloc(c, need);
-      p->band_clean = false;
     }
+    set_layout(p, sym);
     p->prec = prec;
-    hipStream_t st = p->stream;
-    bool sym = p->factor_kind == MW_FACTOR_LDLT;
-    if (p->factor_kind == MW_FACTOR_AUTO) {
-      double* dmax = (double*)p->w_small.get(c, 8);
-      double hmax = 0.0;
-      launch_max_imag(p->eps.as<double2>(), p->T.nt, dmax, st);
-      MW_HIP(hipMemcpyAsync(&hmax, dmax, 8, hipMemcpyDeviceToHost, st));
-      psync(p);
-      sym = hmax < 0.0;
-    }
     p->factorization = sym ? MW_FACTOR_LDLT : MW_FACTOR_LU;
-    p->factors_valid = false;
     launch_zero_bytes(p->dd.info, (int64_t)p->dd.nsub * 4, st);
     if (prec == MW_C64) {
-      launch_fill_local<float2>(p->dm, p->dd, p->E.as<double2>(), p->eps.as<double2>(), p->k0, p->F.as<float2>(), st,
-                                p->band_clean);
+      launch_fill_local<float2>(p->dm, p->dd, p->E.as<double2>(), p->eps.as<double2>(), p->k0, p->F.as<float2>(), st);
       lu_factor_batched<float2>(p->dd, p->F.as<float2>(), st, sym);
     } else {
-      launch_fill_local<double2>(p->dm, p->dd, p->E.as<double2>(), p->eps.as<double2>(), p->k0, p->F.as<double2>(), st,
-                                 p->band_clean);
+      launch_fill_local<double2>(p->dm, p->dd, p->E.as<double2>(), p->eps.as<double2>(), p->k0, p->F.as<double2>(), st);
       lu_factor_batched<double2>(p->dd, p->F.as<double2>(), st, sym);
     }
-    // the fill may have been band-only; what lies outside the band is known
-    // to be zero again only after a factorisation without interchanges that
-    // met no small pivot (a failed one can leave overflowed values anywhere)
-    p->band_clean = false;
     std::vector<int32_t> info(p->dd.nsub);
     std::vector<double> amax(p->dd.nsub);
     MW_HIP(hipMemcpyAsync(info.data(), p->dd.info, info.size() * 4, hipMemcpyDeviceToHost, st));
@@ -1570,7 +1607,6 @@ mw_status mw_factor_subdomains(mw_problem* p, int32_t n_sub, int32_t overlap, mw
     for (int i = 0; i < p->dd.nsub; ++i)
       MW_CHECK(info[i] == 0, MW_ESINGULAR,
                "(near-)zero pivot in subdomain " + std::to_string(i) + " at column " + std::to_string(info[i] - 1));
-    p->band_clean = sym;
     p->coarse_active = false;
     if (p->coarse_kind != MW_COARSE_NONE) {
       if (!p->coarse_built) build_coarse(p);
@@ -1859,7 +1895,8 @@ mw_status mw_factor_bytes(mw_problem* p, int32_t n_sub, int32_t overlap, mw_prec
     uint64_t key = hash_part(tet_part, p->T.nt, n_sub, overlap);
     MW_CHECK(p->has_dec && key == p->dec_key, MW_EINVAL,
              "no decomposition for this partition yet: call mw_factor_subdomains once");
-    *bytes = p->D.fac_off.back() * esz;
+    DeviceGuard dg(p->ctx->device);
+    *bytes = factor_elems(p->D, choose_sym(p)) * esz;
   });
 }
 

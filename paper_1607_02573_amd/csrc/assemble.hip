@@ -213,50 +213,34 @@ void launch_gather_csr(const DeviceMesh& m, const double2* E, double2* val, hipS
 }
 
 // ---------------------------------------------------------------- K8
-// Dense local matrices B_i (row-major n_pad x n_pad, zero + identity on the
-// padding diagonal), then the volume, boundary and transmission terms, one
-// thread per local row.
+// Local matrices B_i in the factor storage (every stored entry zero, ones on
+// the padding diagonal), then the volume, boundary and transmission terms,
+// one thread per local row.
 template <class C>
-__global__ void k_fill_identity(C* __restrict__ F, const int64_t* __restrict__ fac_off,
-                                const int32_t* __restrict__ n_loc, const int32_t* __restrict__ n_pad) {
-  int i = blockIdx.y;
-  int64_t np = n_pad[i];
-  int64_t total = np * np;
+__global__ void k_fill_zero(C* __restrict__ F, const int64_t* __restrict__ fac_off) {
+  const int i = blockIdx.y;
+  const int64_t total = fac_off[i + 1] - fac_off[i];
   C* Fi = F + fac_off[i];
-  int nl = n_loc[i];
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < total;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    int64_t r = k / np, c = k - r * np;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.x * blockDim.x) {
     C z;
-    z.x = (r == c && r >= nl) ? 1 : 0;
+    z.x = 0;
     z.y = 0;
     Fi[k] = z;
   }
 }
 
-// Same result where F already holds zeros outside the band that a
-// factorisation without interchanges writes: per 32-row group the columns
-// from its envelope start (or its 64 x 64 diagonal block, if earlier) to one
-// past the last column reaching it (or the block's end), zeroed, with ones on
-// the padding diagonal.
 template <class C>
-__global__ void k_fill_band(C* __restrict__ F, const int64_t* __restrict__ fac_off,
-                            const int32_t* __restrict__ n_loc, const int32_t* __restrict__ n_pad,
-                            const int32_t* __restrict__ fenv, const int32_t* __restrict__ fenv_hi, int stride) {
-  const int i = blockIdx.y, g = blockIdx.x;
-  const int np = n_pad[i];
-  if (32 * g >= np) return;
-  const int b0 = (g / 2) * 64;
-  const int lo = min(fenv[(int64_t)i * stride + g], b0);
-  const int hi = min(np, max(fenv_hi[(int64_t)i * stride + g], b0 + 64));
-  const int w = hi - lo, nl = n_loc[i];
+__global__ void k_fill_pad_diag(C* __restrict__ F, const int64_t* __restrict__ fac_off,
+                                const int32_t* __restrict__ n_loc, const int32_t* __restrict__ n_pad,
+                                const int64_t* __restrict__ boff, const int32_t* __restrict__ blo,
+                                const int32_t* __restrict__ bw, int bstride) {
+  const int i = blockIdx.x;
   C* Fi = F + fac_off[i];
-  for (int k = threadIdx.x; k < 32 * w; k += blockDim.x) {
-    const int r = 32 * g + k / w, c = lo + k % w;
-    C z;
-    z.x = (r == c && r >= nl) ? 1 : 0;
-    z.y = 0;
-    Fi[(int64_t)r * np + c] = z;
+  for (int r = n_loc[i] + (int)threadIdx.x; r < n_pad[i]; r += blockDim.x) {
+    C one;
+    one.x = 1;
+    one.y = 0;
+    frow(Fi, boff + (int64_t)i * bstride, blo + (int64_t)i * bstride, bw + (int64_t)i * bstride, r)[r] = one;
   }
 }
 
@@ -271,12 +255,13 @@ __global__ void k_fill_local(C* __restrict__ F, const int64_t* __restrict__ fac_
                              const int32_t* __restrict__ rtl, const int64_t* __restrict__ rfl_ptr,
                              const int32_t* __restrict__ rfl, const double2* __restrict__ E,
                              const double2* __restrict__ fbeta, const double2* __restrict__ eps,
-                             const double* __restrict__ xyz, double k0) {
+                             const double* __restrict__ xyz, double k0, const int64_t* __restrict__ boff,
+                             const int32_t* __restrict__ blo, const int32_t* __restrict__ bw, int bstride) {
   int i = blockIdx.y;
   int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= n_loc[i]) return;
-  int64_t np = n_pad[i];
-  C* row = F + fac_off[i] + (int64_t)l * np;
+  // every entry of row l lies in its structural envelope, stored
+  C* row = frow(F + fac_off[i], boff + (int64_t)i * bstride, blo + (int64_t)i * bstride, bw + (int64_t)i * bstride, l);
   int64_t r = loc_off[i] + l;
   const int32_t* tl = lt_loc + lt_off[i] * 6;
   const int32_t* tt = lt_tet + lt_off[i];
@@ -318,25 +303,22 @@ __global__ void k_fill_local(C* __restrict__ F, const int64_t* __restrict__ fac_
 
 template <class C>
 void launch_fill_local(const DeviceMesh& m, const DeviceDecomp& d, const double2* E, const double2* eps,
-                       double k0, C* F, hipStream_t st, bool band_only) {
-  if (band_only) {
-    k_fill_band<C><<<dim3((unsigned)d.fenv_stride, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_loc, d.n_pad, d.fenv,
-                                                                        d.fenv_hi, d.fenv_stride);
-  } else {
-    dim3 g1(1024, d.nsub);
-    k_fill_identity<C><<<g1, 256, 0, st>>>(F, d.fac_off, d.n_loc, d.n_pad);
-  }
+                       double k0, C* F, hipStream_t st) {
+  k_fill_zero<C><<<dim3(1024, d.nsub), 256, 0, st>>>(F, d.fac_off);
+  MW_LAUNCH_CHECK();
+  k_fill_pad_diag<C><<<d.nsub, 64, 0, st>>>(F, d.fac_off, d.n_loc, d.n_pad, d.boff, d.blo, d.bw, d.bstride);
   MW_LAUNCH_CHECK();
   dim3 g2((unsigned)ceil_div(d.max_pad, 128), d.nsub);
   k_fill_local<C><<<g2, 128, 0, st>>>(F, d.fac_off, d.loc_off, d.n_loc, d.n_pad, d.lt_off, d.lt_tet,
                                       d.lt_loc, d.lf_off, d.lf_vert, d.lf_owner, d.lf_kind, d.lf_loc,
-                                      d.rtl_ptr, d.rtl, d.rfl_ptr, d.rfl, E, m.fbeta, eps, m.xyz, k0);
+                                      d.rtl_ptr, d.rtl, d.rfl_ptr, d.rfl, E, m.fbeta, eps, m.xyz, k0, d.boff, d.blo,
+                                      d.bw, d.bstride);
   MW_LAUNCH_CHECK();
 }
 template void launch_fill_local<float2>(const DeviceMesh&, const DeviceDecomp&, const double2*,
-                                        const double2*, double, float2*, hipStream_t, bool);
+                                        const double2*, double, float2*, hipStream_t);
 template void launch_fill_local<double2>(const DeviceMesh&, const DeviceDecomp&, const double2*,
-                                         const double2*, double, double2*, hipStream_t, bool);
+                                         const double2*, double, double2*, hipStream_t);
 
 // ---------------------------------------------------------------- ports
 // Port projections p_k[e] = int_{Gamma_k} E0_k . N_e with the edge-midpoint

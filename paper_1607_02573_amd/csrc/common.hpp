@@ -153,6 +153,14 @@ struct Decomposition {
   int32_t fenv_stride = 0;
   std::vector<int64_t> loc_off;     // [nsub+1] row offset of subdomain i in local vectors
   std::vector<int64_t> fac_off;     // [nsub+1] element offset of subdomain i's dense matrix
+  // factor storage per 64-row block k (entry i * bstride + k): offset of the
+  // block's first row within the subdomain's storage, first stored column,
+  // row width; dense (all n_pad columns) and banded (the block's structural
+  // envelope, 64-aligned, reaching at least 64 columns past its diagonal
+  // block; what a factorisation without interchanges fills)
+  int32_t bstride = 0;
+  std::vector<int64_t> boff_dense, boff_band, fac_off_band;
+  std::vector<int32_t> blo_dense, blo_band, bw_dense, bw_band;
   std::vector<int32_t> sub_dof;     // [sum n_pad] global dof of each local row (-1 padding);
                                     // reverse Cuthill-McKee order within each subdomain
   std::vector<double> D;            // [sum n_pad] partition-of-unity weight (0 padding)

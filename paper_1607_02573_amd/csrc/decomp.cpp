@@ -373,6 +373,38 @@ void build_decomposition(const Topology& T, const int32_t* part, int32_t nsub, i
     D.lt_off[i + 1] = D.lt_off[i] + (int64_t)sub[i].tets.size();
     D.lf_off[i + 1] = D.lf_off[i] + (int64_t)sub[i].lf_owner.size();
   }
+  // factor storage tables (64-row blocks; block size and n_pad are multiples of 64)
+  {
+    int32_t mp = 0;
+    for (int32_t i = 0; i < nsub; ++i) mp = std::max(mp, D.n_pad[i]);
+    D.bstride = std::max(1, mp / 64);
+    const size_t tot = (size_t)nsub * D.bstride;
+    D.boff_dense.assign(tot, 0); D.boff_band.assign(tot, 0);
+    D.blo_dense.assign(tot, 0); D.blo_band.assign(tot, 0);
+    D.bw_dense.assign(tot, 0); D.bw_band.assign(tot, 0);
+    D.fac_off_band.assign(nsub + 1, 0);
+    for (int32_t i = 0; i < nsub; ++i) {
+      const int32_t np = D.n_pad[i];
+      const int32_t* fe = D.fenv.data() + (size_t)i * D.fenv_stride;
+      const int32_t* fh = D.fenv_hi.data() + (size_t)i * D.fenv_stride;
+      int64_t off = 0;
+      for (int32_t b = 0; b < np / 64; ++b) {
+        const size_t e = (size_t)i * D.bstride + b;
+        D.boff_dense[e] = (int64_t)64 * b * np;
+        D.blo_dense[e] = 0;
+        D.bw_dense[e] = np;
+        int32_t lo = std::min(std::min(fe[2 * b], fe[2 * b + 1]) & ~63, 64 * b);
+        int32_t hi = (int32_t)round_up(std::max(fh[2 * b], fh[2 * b + 1]), 64);
+        hi = std::max(hi, std::min(np, 64 * b + 128));
+        hi = std::min(std::max(hi, 64 * b + 64), np);
+        D.blo_band[e] = lo;
+        D.bw_band[e] = hi - lo;
+        D.boff_band[e] = off;
+        off += (int64_t)64 * (hi - lo);
+      }
+      D.fac_off_band[i + 1] = D.fac_off_band[i] + off;
+    }
+  }
   const int64_t sp = D.loc_off[nsub];
   D.sub_dof.assign(sp, -1);
   D.D.assign(sp, 0.0);

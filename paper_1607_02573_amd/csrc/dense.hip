@@ -3,9 +3,16 @@
 // each B_i factored once; applying B_i^-1 to many vectors is one forward
 // elimination and one backward substitution).
 //
-// Layout: B_i is row-major n_pad x n_pad (n_pad a multiple of 64) at
-// F + fac_off[i]; every kernel is batched over the subdomains (grid.y or
-// grid.x = subdomain) and skips the parts beyond each subdomain's size.
+// Layout: B_i is row-major with n_pad rows (n_pad a multiple of 64) at
+// F + fac_off[i], each 64-row block storing the columns [blo, blo + bw) of
+// its rows (block tables of DeviceDecomp; frow() gives a row's base): all
+// n_pad columns for LU with interchanges, the structural envelope of the
+// block's rows (aligned to 64, plus room for U_kk^-1 beside the diagonal
+// block) for L D L^T without interchanges.  The LU kernels that pivot
+// (k_lu_panel*, k_laswp, k_trsm_panel, k_gemm_luw without LOWER) address
+// dense rows of n_pad; every other kernel goes through the block tables.
+// Every kernel is batched over the subdomains (grid.y or grid.x =
+// subdomain) and skips the parts beyond each subdomain's size.
 //
 // LU (right-looking, LAPACK-style row interchanges on the whole row):
 //   for each 64-wide panel k:
@@ -144,11 +151,12 @@ __device__ inline void gemm_tile(const typename cplx<R>::t* __restrict__ A, int6
 // LU-internal update of subdomain blockIdx.y:
 // F[r0:np, c0:min(c1,np)] -= F[r0:np, k0:k1] * F[k0:k1, c0:min(c1,np)]
 // LOWER: only tiles on or below the diagonal (r0 == c0; symmetric factorisation)
+// (k0 a multiple of 64 and k1 - k0 <= 64: the K rows lie in one 64-row block)
 template <class R, bool LOWER = false>
 __global__ void __launch_bounds__(256) k_gemm_lu(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
                                                  const int32_t* __restrict__ n_pad, int r0, int k0, int k1,
-                                                 int c0, int c1, const int32_t* __restrict__ fenv = nullptr,
-                                                 int fstride = 0) {
+                                                 int c0, int c1, const int64_t* __restrict__ boff, const int32_t* __restrict__ blo, const int32_t* __restrict__ bw, int bstride,
+                                                 const int32_t* __restrict__ fenv = nullptr, int fstride = 0) {
   using C = typename cplx<R>::t;
   int i = blockIdx.y;
   int np = n_pad[i];
@@ -167,8 +175,13 @@ __global__ void __launch_bounds__(256) k_gemm_lu(typename cplx<R>::t* F, const i
     if (max(min(fe[gr], fe[gr + 1]), min(fe[gc], fe[gc + 1])) >= k1) return;
   }
   C* Fi = F + fac_off[i];
-  gemm_tile<R, false>(Fi + (int64_t)r0 * np + k0, np, Fi + (int64_t)k0 * np + c0, np,
-                      Fi + (int64_t)r0 * np + c0, np, M, N, k1 - k0, tm, tn);
+  const int64_t* bo = boff + (int64_t)i * bstride;
+  const int32_t* bl = blo + (int64_t)i * bstride;
+  const int32_t* bwi = bw + (int64_t)i * bstride;
+  const int row = r0 + tm * TB, col = c0 + tn * TB;
+  C* Ar = frow(Fi, bo, bl, bwi, row);
+  gemm_tile<R, false>(Ar + k0, bwi[row >> 6], frow(Fi, bo, bl, bwi, k0) + col, bwi[k0 >> 6], Ar + col,
+                      bwi[row >> 6], M - tm * TB, N - tn * TB, k1 - k0, 0, 0);
 }
 
 // Wide tile for the triangular-solve updates: C[64 x 32*WC] -= A[64 x K] B[K x 32*WC]
@@ -305,11 +318,31 @@ __device__ __attribute__((always_inline)) inline void gemm_wide(const typename c
 // the B reads per product at the cost of occupancy (long K pays for it).
 // FULL: M, N, K are known to be multiples of the tile (no bounds tests).
 constexpr int G3K = 8;
-template <class R, int WC, int RB = 1, bool FULL = false>
+// Rows of B taken from banded factor storage: B row k (0-based) is factor row
+// r0 + k, columns c0 + c; entries outside the stored columns of their block
+// read as zero.
+template <class C>
+struct BandRows {
+  const C* Fi = nullptr;
+  const int64_t* boff = nullptr;
+  const int32_t* blo = nullptr;
+  const int32_t* bw = nullptr;
+  int r0 = 0, c0 = 0;
+  __device__ inline C at(int k, int c) const {
+    const int r = r0 + k, b = r >> 6, gc = c0 + c, lo = blo[b];
+    C v;
+    v.x = 0;
+    v.y = 0;
+    if (gc >= lo && gc < lo + bw[b]) v = Fi[boff[b] + (int64_t)(r & 63) * bw[b] + gc - lo];
+    return v;
+  }
+};
+template <class R, int WC, int RB = 1, bool FULL = false, bool BBAND = false>
 __device__ __attribute__((always_inline)) inline void gemm3m(const typename cplx<R>::t* __restrict__ A, int64_t lda,
                                                              const typename cplx<R>::t* B, int64_t ldb,
                                                              typename cplx<R>::t* Cm, int64_t ldc, int M, int N,
-                                                             int K) {
+                                                             int K,
+                                                             BandRows<typename cplx<R>::t> bb = {}) {
   using C = typename cplx<R>::t;
   using acc_t = typename Mf<R>::acc;
   constexpr int TM = 32 * RB, TN = 32 * WC;
@@ -349,7 +382,10 @@ __device__ __attribute__((always_inline)) inline void gemm3m(const typename cplx
       C v;
       v.x = 0;
       v.y = 0;
-      if (idx < G3K * TN && (FULL || (k0 + r < K && c < N))) v = B[(int64_t)(k0 + r) * ldb + c];
+      if (idx < G3K * TN && (FULL || (k0 + r < K && c < N))) {
+        if constexpr (BBAND) v = bb.at(k0 + r, c);
+        else v = B[(int64_t)(k0 + r) * ldb + c];
+      }
       rb[e] = v;
     }
   };
@@ -439,7 +475,7 @@ __global__ void __launch_bounds__(256, (sizeof(R) == 8 && WC >= 2) ? 2 : RB) k_g
                                                 int64_t ld, int ncols, int r0, int r1, int k0, int k1,
                                                 int tiles_m, int tiles_n, int nsub,
                                                 const int32_t* __restrict__ row_lo,
-                                                const int2* __restrict__ env, int env_stride) {
+                                                const int2* __restrict__ env, int env_stride, const int64_t* __restrict__ boff, const int32_t* __restrict__ blo, const int32_t* __restrict__ bw, int bstride) {
   using C = typename cplx<R>::t;
   const int per_sub = tiles_m * tiles_n;
   const int G = gridDim.x;
@@ -470,8 +506,13 @@ __global__ void __launch_bounds__(256, (sizeof(R) == 8 && WC >= 2) ? 2 : RB) k_g
   const int TN = WC * 32;
   const int N = min(ncols - tn * TN, TN);
   const C* Fi = F + fac_off[i];
+  const int64_t* bo = boff + (int64_t)i * bstride;
+  const int32_t* bl = blo + (int64_t)i * bstride;
+  const int32_t* bwi = bw + (int64_t)i * bstride;
   C* Yi = Y + loc_off[i] * ld;
-  gemm3m<R, WC, RB, FULL>(Fi + (int64_t)row * np + kb, np, Yi + (int64_t)kb * ld + tn * TN, ld,
+  // the tile's rows lie in one 64-row block; the clipped inner range lies in
+  // the stored columns of that block
+  gemm3m<R, WC, RB, FULL>(frow(Fi, bo, bl, bwi, row) + kb, bwi[row >> 6], Yi + (int64_t)kb * ld + tn * TN, ld,
                           Yi + (int64_t)row * ld + tn * TN, ld, M, N, K);
 }
 
@@ -482,7 +523,7 @@ __global__ void __launch_bounds__(256) k_leaf_x(const typename cplx<R>::t* F, co
                                                 const int32_t* __restrict__ n_pad,
                                                 const int64_t* __restrict__ loc_off, typename cplx<R>::t* Y,
                                                 int64_t ld, int ncols, int r0, int tiles_n, int nsub,
-                                                const int32_t* __restrict__ row_lo) {
+                                                const int32_t* __restrict__ row_lo, const int64_t* __restrict__ boff, const int32_t* __restrict__ blo, const int32_t* __restrict__ bw, int bstride) {
   using C = typename cplx<R>::t;
   const int G = gridDim.x;
   const int logical = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
@@ -493,9 +534,13 @@ __global__ void __launch_bounds__(256) k_leaf_x(const typename cplx<R>::t* F, co
   if (r0 >= np || (row_lo && r0 < row_lo[i])) return;
   const int TN = WC * 32;
   const int N = min(ncols - tn * TN, TN);
-  const C* blk = F + fac_off[i] + (int64_t)r0 * np + r0;
+  const C* Fi = F + fac_off[i];
+  const int64_t* bo = boff + (int64_t)i * bstride;
+  const int32_t* bl = blo + (int64_t)i * bstride;
+  const int32_t* bwi = bw + (int64_t)i * bstride;
+  const C* blk = frow(Fi, bo, bl, bwi, r0) + r0;
   C* Yb = Y + (loc_off[i] + r0) * ld + tn * TN;
-  gemm_wide<R, WC, AMODE, true>(blk, np, Yb, ld, Yb, ld, NB, N, NB);
+  gemm_wide<R, WC, AMODE, true>(blk, bwi[r0 >> 6], Yb, ld, Yb, ld, NB, N, NB);
 }
 
 // LU update with wide tiles:
@@ -510,7 +555,7 @@ template <class R, int WC, bool G3, bool LOWER = false>
 __global__ void __launch_bounds__(256, G3 ? 2 : 1) k_gemm_luw(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
                                                   const int32_t* __restrict__ n_pad, int r0, int r1, int k0, int k1,
                                                   int c0, int c1, int tiles_m, int tiles_n, int nsub,
-                                                  const int32_t* __restrict__ fenv, int fstride) {
+                                                  const int32_t* __restrict__ fenv, int fstride, const int64_t* __restrict__ boff, const int32_t* __restrict__ blo, const int32_t* __restrict__ bw, int bstride) {
   using C = typename cplx<R>::t;
   const int per_sub = tiles_m * tiles_n;
   const int G = gridDim.x;
@@ -539,12 +584,34 @@ __global__ void __launch_bounds__(256, G3 ? 2 : 1) k_gemm_luw(typename cplx<R>::
     kb = max(k0, max(fr, fc) & ~7);
     if (kb >= k1) return;
   }
-  if constexpr (G3)
+  if constexpr (LOWER && G3) {
+    // factorisation without interchanges, banded storage: the tile's rows
+    // lie in one 64-row block whose stored columns hold [kb, k1); the K rows
+    // (U part) span several blocks and are read through the block tables;
+    // columns of the tile beyond the rows' stored range receive no update
+    // (U[k, c] = 0 there for every k of the range)
+  const int64_t* bo = boff + (int64_t)i * bstride;
+  const int32_t* bl = blo + (int64_t)i * bstride;
+  const int32_t* bwi = bw + (int64_t)i * bstride;
+    C* Ar = frow(Fi, bo, bl, bwi, row);
+    const int ncol = min(min(N, 32 * WC), bl[row >> 6] + bwi[row >> 6] - col);
+    if (ncol <= 0) return;
+    BandRows<C> bb;
+    bb.Fi = Fi;
+    bb.boff = bo;
+    bb.blo = bl;
+    bb.bw = bwi;
+    bb.r0 = kb;
+    bb.c0 = col;
+    gemm3m<R, WC, 2, false, true>(Ar + kb, bwi[row >> 6], nullptr, 0, Ar + col, bwi[row >> 6], M, ncol, k1 - kb, bb);
+  } else if constexpr (G3) {
     gemm3m<R, WC, 2>(Fi + (int64_t)row * np + kb, np, Fi + (int64_t)kb * np + col, np, Fi + (int64_t)row * np + col,
                   np, M, min(N, 32 * WC), k1 - kb);
-  else
+  } else {
+    static_assert(!LOWER, "the factorisation without interchanges uses the three-product tiles");
     gemm_wide<R, WC>(Fi + (int64_t)row * np + kb, np, Fi + (int64_t)kb * np + col, np,
                      Fi + (int64_t)row * np + col, np, M, min(N, 32 * WC), k1 - kb);
+  }
 }
 
 template <class R, int WC, bool G3 = false, bool LOWER = false>
@@ -557,7 +624,7 @@ static void launch_gemm_lu(const DeviceDecomp& d, typename cplx<R>::t* F, int r0
   // envelope clipping only for the factorisation without interchanges
   k_gemm_luw<R, WC, G3, LOWER><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, r0, r1, k0, k1, c0, c1,
                                                             tiles_m, tiles_n, d.nsub, LOWER ? d.fenv : nullptr,
-                                                            d.fenv_stride);
+                                                            d.fenv_stride, d.boff, d.blo, d.bw, d.bstride);
   MW_LAUNCH_CHECK();
 }
 
@@ -575,16 +642,19 @@ template <class R>
 __global__ void __launch_bounds__(256) k_amax(const typename cplx<R>::t* __restrict__ F,
                                               const int64_t* __restrict__ fac_off, const int32_t* __restrict__ n_pad,
                                               const int32_t* __restrict__ fenv, const int32_t* __restrict__ fenv_hi,
-                                              int fstride, double* __restrict__ amax) {
+                                              int fstride, double* __restrict__ amax, const int64_t* __restrict__ boff, const int32_t* __restrict__ blo, const int32_t* __restrict__ bw, int bstride) {
   __shared__ double red[4];
   int i = blockIdx.x;
   const int np = n_pad[i];
   const auto* Fi = F + fac_off[i];
+  const int64_t* bo = boff + (int64_t)i * bstride;
+  const int32_t* bl = blo + (int64_t)i * bstride;
+  const int32_t* bwi = bw + (int64_t)i * bstride;
   double m = 0.0;
   for (int g = 0; 32 * g < np; ++g) {
     const int c0 = fenv[(int64_t)i * fstride + g], w = min(fenv_hi[(int64_t)i * fstride + g], np) - c0;
     for (int k = threadIdx.x; k < 32 * w; k += 256) {
-      auto v = Fi[(int64_t)(32 * g + k / w) * np + c0 + k % w];
+      auto v = frow(Fi, bo, bl, bwi, 32 * g + k / w)[c0 + k % w];
       double a = fabs((double)v.x) + fabs((double)v.y);
       m = (a > m || a != a) ? a : m;   // a NaN entry makes the maximum NaN
     }
@@ -982,17 +1052,20 @@ __global__ void __launch_bounds__(256) k_sym_diag(typename cplx<R>::t* F, const 
                                                   const int32_t* __restrict__ n_pad,
                                                   const int64_t* __restrict__ loc_off, int32_t* ipiv,
                                                   int32_t* info, const double* __restrict__ amax, double rtol,
-                                                  int k) {
+                                                  int k, const int64_t* __restrict__ boff, const int32_t* __restrict__ blo, const int32_t* __restrict__ bw, int bstride) {
   using C = typename cplx<R>::t;
   const int i = blockIdx.x;
   const int np = n_pad[i];
   if (k >= np) return;
   C* Fi = F + fac_off[i];
+  const int64_t* bo = boff + (int64_t)i * bstride;
+  const int32_t* bl = blo + (int64_t)i * bstride;
+  const int32_t* bwi = bw + (int64_t)i * bstride;
   __shared__ C T[NB][NB + 1];
   __shared__ int bad;
   const int tid = threadIdx.x;
   if (tid == 0) bad = 0;
-  for (int e = tid; e < NB * NB; e += 256) T[e / NB][e % NB] = Fi[(int64_t)(k + e / NB) * np + k + e % NB];
+  for (int e = tid; e < NB * NB; e += 256) T[e / NB][e % NB] = frow(Fi, bo, bl, bwi, k + e / NB)[k + e % NB];
   __syncthreads();
   const double thr = rtol * amax[i];
   for (int j = 0; j < NB; ++j) {
@@ -1012,7 +1085,7 @@ __global__ void __launch_bounds__(256) k_sym_diag(typename cplx<R>::t* F, const 
     }
     __syncthreads();
   }
-  for (int e = tid; e < NB * NB; e += 256) Fi[(int64_t)(k + e / NB) * np + k + e % NB] = T[e / NB][e % NB];
+  for (int e = tid; e < NB * NB; e += 256) frow(Fi, bo, bl, bwi, k + e / NB)[k + e % NB] = T[e / NB][e % NB];
   if (tid < NB) ipiv[loc_off[i] + k + tid] = k + tid;
   if (tid == 0 && bad && info[i] == 0) info[i] = bad;
   if (k + 2 * NB > np) return;
@@ -1033,7 +1106,8 @@ __global__ void __launch_bounds__(256) k_sym_diag(typename cplx<R>::t* F, const 
     }
   }
   __syncthreads();
-  for (int e = tid; e < NB * NB; e += 256) Fi[(int64_t)(k + e / NB) * np + k + NB + e % NB] = X[e / NB][e % NB];
+  // (the stored columns of every block reach at least 64 past its diagonal block)
+  for (int e = tid; e < NB * NB; e += 256) frow(Fi, bo, bl, bwi, k + e / NB)[k + NB + e % NB] = X[e / NB][e % NB];
 }
 
 // L_rk = A_rk U_kk^-1 for one 64-row block r of the panel below the diagonal
@@ -1041,7 +1115,7 @@ __global__ void __launch_bounds__(256) k_sym_diag(typename cplx<R>::t* F, const 
 template <class R>
 __global__ void __launch_bounds__(256) k_sym_cols(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
                                                   const int32_t* __restrict__ n_pad, int k,
-                                                  const int32_t* __restrict__ fenv, int fstride) {
+                                                  const int32_t* __restrict__ fenv, int fstride, const int64_t* __restrict__ boff, const int32_t* __restrict__ blo, const int32_t* __restrict__ bw, int bstride) {
   using C = typename cplx<R>::t;
   const int i = blockIdx.y;
   const int np = n_pad[i];
@@ -1051,11 +1125,16 @@ __global__ void __launch_bounds__(256) k_sym_cols(typename cplx<R>::t* F, const 
   const int32_t* fe = fenv + (int64_t)i * fstride;
   if (min(fe[rb / 32], fe[rb / 32 + 1]) >= k + NB) return;
   C* Fi = F + fac_off[i];
+  const int64_t* bo = boff + (int64_t)i * bstride;
+  const int32_t* bl = blo + (int64_t)i * bstride;
+  const int32_t* bwi = bw + (int64_t)i * bstride;
   __shared__ C A[NB][NB + 1];
   __shared__ C U[NB][NB + 1];
+  // (the row block's envelope starts left of k + NB, so its stored columns
+  // begin at or before k)
   for (int e = threadIdx.x; e < NB * NB; e += 256) {
-    A[e / NB][e % NB] = Fi[(int64_t)(rb + e / NB) * np + k + e % NB];
-    U[e / NB][e % NB] = Fi[(int64_t)(k + e / NB) * np + k + NB + e % NB];
+    A[e / NB][e % NB] = frow(Fi, bo, bl, bwi, rb + e / NB)[k + e % NB];
+    U[e / NB][e % NB] = frow(Fi, bo, bl, bwi, k + e / NB)[k + NB + e % NB];
   }
   __syncthreads();
   const int r = threadIdx.x >> 2, cg = threadIdx.x & 3;
@@ -1068,8 +1147,9 @@ __global__ void __launch_bounds__(256) k_sym_cols(typename cplx<R>::t* F, const 
 #pragma unroll
     for (int u = 0; u < NB / 4; ++u) acc[u] = cadd(acc[u], cmul(a, U[l][cg + 4 * u]));
   }
+  C* out = frow(Fi, bo, bl, bwi, rb + r) + k + cg;
 #pragma unroll
-  for (int u = 0; u < NB / 4; ++u) Fi[(int64_t)(rb + r) * np + k + cg + 4 * u] = acc[u];
+  for (int u = 0; u < NB / 4; ++u) out[4 * u] = acc[u];
 }
 
 // Symmetric factorisation (B_i = L D L^T, B_i complex symmetric, no
@@ -1081,7 +1161,7 @@ __global__ void __launch_bounds__(256) k_sym_cols(typename cplx<R>::t* F, const 
 template <class R>
 __global__ void __launch_bounds__(256) k_sym_row(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
                                                  const int32_t* __restrict__ n_pad, int k,
-                                                 const int32_t* __restrict__ fenv, int fstride) {
+                                                 const int32_t* __restrict__ fenv, int fstride, const int64_t* __restrict__ boff, const int32_t* __restrict__ blo, const int32_t* __restrict__ bw, int bstride) {
   using C = typename cplx<R>::t;
   const int i = blockIdx.y;
   const int np = n_pad[i];
@@ -1092,17 +1172,25 @@ __global__ void __launch_bounds__(256) k_sym_row(typename cplx<R>::t* F, const i
   const int32_t* fe = fenv + (int64_t)i * fstride;
   if (jb > k + NB && min(fe[jb / 32], fe[jb / 32 + 1]) >= k + NB) return;
   C* Fi = F + fac_off[i];
+  const int64_t* bo = boff + (int64_t)i * bstride;
+  const int32_t* bl = blo + (int64_t)i * bstride;
+  const int32_t* bwi = bw + (int64_t)i * bstride;
   __shared__ C T[NB][NB + 1];
   __shared__ C dg[NB];
+  // L[jb + jj, k + rr]: zero left of the stored columns of block jb (the
+  // first block runs whatever its envelope); U rows k.. are written where
+  // stored (beyond, the scaled zeros are not kept)
+  const int jbk = jb >> 6, lo_j = bl[jbk];
   for (int e = threadIdx.x; e < NB * NB; e += 256) {
     const int jj = e / NB, rr = e % NB;
-    T[jj][rr] = Fi[(int64_t)(jb + jj) * np + k + rr];
+    T[jj][rr] = k + rr >= lo_j ? frow(Fi, bo, bl, bwi, jb + jj)[k + rr] : cmk<C>(0, 0);
   }
-  if (threadIdx.x < NB) dg[threadIdx.x] = Fi[(int64_t)(k + threadIdx.x) * np + k + threadIdx.x];
+  if (threadIdx.x < NB) dg[threadIdx.x] = frow(Fi, bo, bl, bwi, k + threadIdx.x)[k + threadIdx.x];
   __syncthreads();
+  const int kk = k >> 6, hi_k = bl[kk] + bwi[kk];
   for (int e = threadIdx.x; e < NB * NB; e += 256) {
     const int rr = e / NB, jj = e % NB;
-    Fi[(int64_t)(k + rr) * np + jb + jj] = cmul(dg[rr], T[jj][rr]);
+    if (jb + jj < hi_k) frow(Fi, bo, bl, bwi, k + rr)[jb + jj] = cmul(dg[rr], T[jj][rr]);
   }
 }
 
@@ -1113,15 +1201,20 @@ __global__ void __launch_bounds__(256) k_sym_row(typename cplx<R>::t* F, const i
 // overwritten; the L_bb^-1 writes touch only the strict lower part.
 template <class R>
 __global__ void __launch_bounds__(256) k_invert_diag(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
-                                                     const int32_t* __restrict__ n_pad) {
+                                                     const int32_t* __restrict__ n_pad, const int64_t* __restrict__ boff, const int32_t* __restrict__ blo, const int32_t* __restrict__ bw, int bstride) {
   int b = blockIdx.x, i = blockIdx.y;
   int np = n_pad[i];
   if (b * NB >= np) return;
-  auto* blk = F + fac_off[i] + (int64_t)b * NB * np + b * NB;
+  auto* Fi = F + fac_off[i];
+  const int64_t* bo = boff + (int64_t)i * bstride;
+  const int32_t* bl = blo + (int64_t)i * bstride;
+  const int32_t* bwi = bw + (int64_t)i * bstride;
+  auto* blk = frow(Fi, bo, bl, bwi, b * NB) + b * NB;
+  const int ldb = bwi[b];
   __shared__ typename cplx<R>::t tri[BAND_TOTAL];
-  trsm_leaf<R, false, true, 1>(blk, np, blk, np, 0, NB, tri);
+  trsm_leaf<R, false, true, 1>(blk, ldb, blk, ldb, 0, NB, tri);
   __syncthreads();
-  trsm_leaf<R, true, true, 2>(blk, np, blk, np, 0, NB, tri);
+  trsm_leaf<R, true, true, 2>(blk, ldb, blk, ldb, 0, NB, tri);
 }
 
 // restriction gather index with the row interchanges folded in:
@@ -1162,7 +1255,8 @@ template <class C>
 __global__ void __launch_bounds__(256) k_envelope(const C* __restrict__ F, const int64_t* __restrict__ fac_off,
                                                   const int32_t* __restrict__ n_pad, int stride,
                                                   const int32_t* __restrict__ fenv,
-                                                  const int32_t* __restrict__ fenv_hi, int2* __restrict__ env) {
+                                                  const int32_t* __restrict__ fenv_hi, int2* __restrict__ env,
+                                                  const int64_t* __restrict__ boff, const int32_t* __restrict__ blo, const int32_t* __restrict__ bw, int bstride) {
   const int i = blockIdx.x / stride, g = blockIdx.x % stride;
   const int np = n_pad[i];
   const int b0 = (g / 2) * 64, b1 = b0 + 64;
@@ -1170,12 +1264,15 @@ __global__ void __launch_bounds__(256) k_envelope(const C* __restrict__ F, const
   int lo = b0, hi = b1;
   if (32 * g < np) {
     const C* Fi = F + fac_off[i];
+    const int64_t* bo = boff + (int64_t)i * bstride;
+    const int32_t* bl = blo + (int64_t)i * bstride;
+    const int32_t* bwi = bw + (int64_t)i * bstride;
     // without interchanges nothing lies outside the structural envelope of
     // B_i, so the scans may start at its 64-column steps (else at the edges)
     const int l0 = fenv ? min(b0, fenv[blockIdx.x] & ~63) : 0;
     const int u0 = fenv_hi ? max(b1, min(np, (fenv_hi[blockIdx.x] + 63) & ~63)) : np;
     for (int q = 0; q < 8; ++q) {
-      const C* row = Fi + (int64_t)(32 * g + 8 * wave + q) * np;
+      const C* row = frow(Fi, bo, bl, bwi, 32 * g + 8 * wave + q);
       for (int c0 = l0; c0 < lo; c0 += 64) {
         const C v = row[c0 + lane];
         const unsigned long long m = __ballot(v.x != 0 || v.y != 0);
@@ -1301,8 +1398,9 @@ template <class C>
 void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st, bool sym) {
   using R = typename RealOf<C>::t;
   MW_CHECK(d.max_pad <= 8192, MW_EINVAL, "subdomain too large for the dense factorisation (n_i > 8192)");
+  MW_CHECK(d.boff && d.blo && d.bw && d.bstride >= d.max_pad / 64, MW_EINVAL, "factor storage tables missing");
   const int maxp = d.max_pad;
-  k_amax<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.fenv, d.fenv_hi, d.fenv_stride, d.amax);
+  k_amax<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.fenv, d.fenv_hi, d.fenv_stride, d.amax, d.boff, d.blo, d.bw, d.bstride);
   MW_LAUNCH_CHECK();
   const double rtol = sizeof(R) == 4 ? 1e-6 : 1e-14;
   // Right-looking blocked LU in two levels: 64-column panels (8-column
@@ -1320,12 +1418,13 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st, bool sym) {
     for (int k = K0; k < Kend; k += NB) {
       if (sym) {
         kt_begin(KF_LU_PANEL, st);
-        k_sym_diag<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, d.amax, rtol, k);
+        k_sym_diag<R><<<d.nsub, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, d.ipiv, d.info, d.amax, rtol, k,
+                                              d.boff, d.blo, d.bw, d.bstride);
         MW_LAUNCH_CHECK();
         if (k + NB < maxp) {
           k_sym_cols<R><<<dim3((unsigned)ceil_div(maxp - k - NB, NB), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad,
                                                                                              k, d.fenv,
-                                                                                             d.fenv_stride);
+                                                                                             d.fenv_stride, d.boff, d.blo, d.bw, d.bstride);
           MW_LAUNCH_CHECK();
         }
         int sub = 0;
@@ -1382,7 +1481,8 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st, bool sym) {
         if (c0 >= maxp) continue;
         kt_begin(KF_LU_OTHER, st);
         k_sym_row<R><<<dim3((unsigned)ceil_div(maxp - c0, NB), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, k,
-                                                                                        d.fenv, d.fenv_stride);
+                                                                                        d.fenv, d.fenv_stride,
+                                                                                        d.boff, d.blo, d.bw, d.bstride);
         MW_LAUNCH_CHECK();
         {
           int sub = 0;
@@ -1397,7 +1497,7 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st, bool sym) {
           int M = maxp - c0, N = Kend - c0;
           unsigned tiles = (unsigned)(ceil_div(M, TB) * ceil_div(N, TB));
           k_gemm_lu<R, true><<<dim3(tiles, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, c0, k, k + NB, c0, Kend,
-                                                                  d.fenv, d.fenv_stride);
+                                                                  d.boff, d.blo, d.bw, d.bstride, d.fenv, d.fenv_stride);
           MW_LAUNCH_CHECK();
           int sub = 0;
           kt_account(d, KF_LU_GEMM, st, [&](int n, double& f, double& b) {
@@ -1441,7 +1541,7 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st, bool sym) {
         kt_begin(KF_LU_GEMM, st);
         int M = maxp - c0, N = Kend - c0;
         unsigned tiles = (unsigned)(ceil_div(M, TB) * ceil_div(N, TB));
-        k_gemm_lu<R><<<dim3(tiles, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, c0, k, k + NB, c0, Kend);
+        k_gemm_lu<R><<<dim3(tiles, d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, c0, k, k + NB, c0, Kend, d.boff, d.blo, d.bw, d.bstride);
         MW_LAUNCH_CHECK();
         kt_account(d, KF_LU_GEMM, st, [&](int n, double& f, double& b) {
           double M2 = clampd(n - c0), N2 = clampd(std::min(Kend, n) - c0), K = clampd(std::min(k + NB, n) - k);
@@ -1471,7 +1571,7 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st, bool sym) {
     }
   }
   kt_begin(KF_LU_OTHER, st);
-  k_invert_diag<R><<<dim3((unsigned)(maxp / NB), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad);
+  k_invert_diag<R><<<dim3((unsigned)(maxp / NB), d.nsub), 256, 0, st>>>(F, d.fac_off, d.n_pad, d.boff, d.blo, d.bw, d.bstride);
   MW_LAUNCH_CHECK();
   kt_account(d, KF_LU_OTHER, st, [&](int n, double& f, double& b) {
     double nb = std::ceil(n / (double)NB);
@@ -1481,7 +1581,7 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st, bool sym) {
   k_build_perm<<<d.nsub, 256, 0, st>>>(d.n_pad, d.loc_off, d.ipiv, d.sub_dof, d.ridx);
   MW_LAUNCH_CHECK();
   k_envelope<C><<<(unsigned)((int64_t)d.nsub * d.env_stride), 256, 0, st>>>(
-      F, d.fac_off, d.n_pad, d.env_stride, sym ? d.fenv : nullptr, sym ? d.fenv_hi : nullptr, d.env);
+      F, d.fac_off, d.n_pad, d.env_stride, sym ? d.fenv : nullptr, sym ? d.fenv_hi : nullptr, d.env, d.boff, d.blo, d.bw, d.bstride);
   MW_LAUNCH_CHECK();
 }
 
@@ -1504,7 +1604,7 @@ static void launch_gemm_x_wc(const DeviceDecomp& d, const typename cplx<R>::t* F
   int tiles_n = (int)ceil_div(ncols, WC * 32);
   int64_t G = round_up((int64_t)d.nsub * tiles_m * tiles_n, 8);
   k_gemm_x<R, WC, RB, FULL><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, Y, ld, ncols, r0, r1, k0, k1,
-                                                   tiles_m, tiles_n, d.nsub, row_lo, d.env, d.env_stride);
+                                                   tiles_m, tiles_n, d.nsub, row_lo, d.env, d.env_stride, d.boff, d.blo, d.bw, d.bstride);
   MW_LAUNCH_CHECK();
 }
 // The updates take 32-row tiles: clipped to the banded envelope their inner
@@ -1534,7 +1634,7 @@ static void launch_leaf_x_wc(const DeviceDecomp& d, const typename cplx<R>::t* F
   int tiles_n = (int)ceil_div(ncols, WC * 32);
   int64_t G = round_up((int64_t)d.nsub * tiles_n, 8);
   k_leaf_x<R, WC, AMODE><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, Y, ld, ncols, r0, tiles_n,
-                                                     d.nsub, row_lo);
+                                                     d.nsub, row_lo, d.boff, d.blo, d.bw, d.bstride);
   MW_LAUNCH_CHECK();
 }
 // The leaves take 32-column tiles whatever the width: one 64 x 64 block per

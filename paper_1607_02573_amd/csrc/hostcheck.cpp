@@ -66,6 +66,26 @@ mw_status mw_host_decomposition(const mw_mesh* mesh, const int32_t* tet_part, in
   });
 }
 
+mw_status mw_host_factor_storage(const mw_mesh* mesh, const int32_t* tet_part, int32_t n_sub, int32_t overlap,
+                                 int32_t sub, int32_t* blk_lo, int32_t* blk_hi, int64_t* dense_elems,
+                                 int64_t* band_elems) {
+  return hguard([&] {
+    MW_CHECK(mesh && tet_part, MW_EINVAL, "NULL argument");
+    Topology T;
+    build_topology(*mesh, T);
+    Decomposition Dc;
+    build_decomposition(T, tet_part, n_sub, overlap, 64, Dc);
+    MW_CHECK(sub >= 0 && sub < n_sub, MW_EINVAL, "subdomain out of range");
+    if (dense_elems) *dense_elems = Dc.fac_off.back();
+    if (band_elems) *band_elems = Dc.fac_off_band.back();
+    for (int32_t b = 0; b < Dc.n_pad[sub] / 64; ++b) {
+      const size_t e = (size_t)sub * Dc.bstride + b;
+      if (blk_lo) blk_lo[b] = Dc.blo_band[e];
+      if (blk_hi) blk_hi[b] = Dc.blo_band[e] + Dc.bw_band[e];
+    }
+  });
+}
+
 mw_status mw_host_partition(const mw_mesh* mesh, int32_t n_sub, int32_t* tet_part) {
   return hguard([&] {
     MW_CHECK(mesh && tet_part, MW_EINVAL, "NULL argument");

@@ -99,7 +99,26 @@ struct DeviceDecomp {
   int2* env = nullptr;
   const int2* h_env = nullptr;       // host copy (launch accounting)
   int env_stride = 0;
+  // storage of the factors, per 64-row block k of subdomain i (entry
+  // i * bstride + k): element offset of the block's first row within the
+  // subdomain's storage, first stored column, row width.  Element (r, c) is
+  // at F + fac_off[i] + boff + (r mod 64) * bw + c - blo; only columns
+  // [blo, blo + bw) exist.  Dense storage: boff = 64 k n_pad, blo = 0,
+  // bw = n_pad (LU with interchanges); banded storage holds each block's
+  // structural envelope (L D L^T without interchanges fills nothing outside).
+  const int64_t* boff = nullptr;
+  const int32_t* blo = nullptr;
+  const int32_t* bw = nullptr;
+  int bstride = 0;
 };
+
+// Row r of a subdomain's factors: P such that P[c] is element (r, c) (the
+// block tables of that subdomain).
+template <class T>
+__device__ inline T* frow(T* Fi, const int64_t* boff, const int32_t* blo, const int32_t* bw, int r) {
+  const int k = r >> 6;
+  return Fi + boff[k] + (int64_t)(r & 63) * bw[k] - blo[k];
+}
 
 // Coarse space of the two-level preconditioner (coarse.hip): three coarse
 // unknowns per subdomain (the weighted interpolants of the constant fields).
@@ -118,8 +137,7 @@ void launch_element_matrices(const DeviceMesh& m, const double2* eps, double k0,
 void launch_gather_csr(const DeviceMesh& m, const double2* E, double2* val, hipStream_t st);
 template <class C>
 void launch_fill_local(const DeviceMesh& m, const DeviceDecomp& d, const double2* E, const double2* eps,
-                       double k0, C* F, hipStream_t st,
-                       bool band_only = false);
+                       double k0, C* F, hipStream_t st);
 void launch_port_setup(const DeviceMesh& m, const DevicePorts& P, hipStream_t st);
 void launch_rhs_ports(const DevicePorts& P, int ntx, const int32_t* tx_dev, double2* B, int64_t ldb,
                       hipStream_t st);

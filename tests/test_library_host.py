@@ -269,3 +269,40 @@ def test_internal_partition_is_balanced_and_decomposes_like_the_oracle(L, which,
         np.testing.assert_allclose(dec["D"][i][o], s.D, rtol=0, atol=1e-15)
     with pytest.raises(Exception):
         binding.host_partition(m.xyz, m.tet, m.bface, m.btag, m.nt + 1)
+
+
+def test_banded_factor_storage_holds_the_elimination(L):
+    """The banded factor storage (factorisation without interchanges): every
+    64-row block stores a column range that contains every nonzero that
+    elimination without interchanges (numpy, in the library's local order)
+    produces in its rows, at least 64 columns past its diagonal block, and
+    the whole storage is far smaller than dense."""
+    from paper_1607_02573_amd import binding
+    w = mi.configs.cube8()
+    m = w.mesh
+    fp = fem.build(m, w.eps, w.k0, w.beta_imp, w.ports)
+    dec = binding.host_decomposition(m.xyz, m.tet, m.bface, m.btag, w.part, 8, 1)
+    subs = dd.decompose(fp, w.part, 1, factor=False)
+    for sub in (0, 5):
+        dense, band, lo, hi = binding.host_factor_storage(m.xyz, m.tet, m.bface, m.btag, w.part, 8, 1, sub)
+        s = subs[sub]
+        pos = np.searchsorted(s.gdof, dec["sub_dof"][sub])
+        F = s.B.tocsr()[pos][:, pos].toarray()
+        n = F.shape[0]
+        for k in range(n - 1):
+            F[k + 1:, k] /= F[k, k]
+            F[k + 1:, k + 1:] -= np.outer(F[k + 1:, k], F[k, k + 1:])
+        npad = 64 * len(lo)
+        assert npad >= n and len(lo) == (n + 63) // 64
+        for b in range(len(lo)):
+            rows = F[64 * b:64 * b + 64]
+            nzc = np.nonzero(rows.any(axis=0))[0]
+            assert lo[b] % 64 == 0 and hi[b] % 64 == 0 or hi[b] == npad
+            assert lo[b] <= 64 * b and hi[b] >= min(npad, 64 * b + 128)
+            assert nzc.min() >= lo[b] and nzc.max() < hi[b]
+    assert band < 0.75 * dense
+    # on the larger chamber subdomains the band is a small part of dense storage
+    ws = mi.configs.small_chamber(0.25e9, n_per_ring=8, n_sub=8)
+    ms = ws.mesh
+    dense, band, _, _ = binding.host_factor_storage(ms.xyz, ms.tet, ms.bface, ms.btag, ws.part, 8, 1, 0)
+    assert band < 0.4 * dense
