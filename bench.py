@@ -503,8 +503,8 @@ def main():
         Sm_host = Sm.cpu() if Sm is not None else None
         del Xm, Sm
         torch.cuda.empty_cache()
-        log("[bench] FP64 warm-up factorisation (allocates the complex-FP64 factors)")
-        P.factor(w.part, w.n_sub, 1, "c128")
+        log("[bench] FP64 warm-up step (allocates the complex-FP64 factors and the solve workspace)")
+        run_steps(P, w, eps_dev, "c128", 1, tol, args.restart, args.maxit, tx, rx, args.block)
         torch.cuda.synchronize()
         log(f"[bench] FP64 steps x{args.fp64_steps}")
         binding.timer_enable(True)

@@ -328,12 +328,24 @@ struct BandRows {
   const int32_t* blo = nullptr;
   const int32_t* bw = nullptr;
   int r0 = 0, c0 = 0;
-  __device__ inline C at(int k, int c) const {
-    const int r = r0 + k, b = r >> 6, gc = c0 + c, lo = blo[b];
+  // the rows [k, k + 8) of one K stage (r0 + k a multiple of 8) lie in one
+  // 64-row block: its base (element (row, c) at base[(row - r0 - k) * w + c0
+  // + c]) and stored column range, once per stage
+  struct Stage {
+    const C* base;
+    int lo, w;
+  };
+  __device__ inline Stage stage(int k) const {
+    const int r = r0 + k, b = r >> 6;
+    const int lo = blo[b], w = bw[b];
+    return {Fi + boff[b] + (int64_t)(r & 63) * w - lo, lo, w};
+  }
+  __device__ inline C at(const Stage& s, int kk, int c) const {
+    const int gc = c0 + c;
     C v;
     v.x = 0;
     v.y = 0;
-    if (gc >= lo && gc < lo + bw[b]) v = Fi[boff[b] + (int64_t)(r & 63) * bw[b] + gc - lo];
+    if (gc >= s.lo && gc < s.lo + s.w) v = s.base[(int64_t)kk * s.w + gc];
     return v;
   }
 };
@@ -375,6 +387,8 @@ __device__ __attribute__((always_inline)) inline void gemm3m(const typename cplx
       if (FULL || (r < M && k0 + kc < K)) v = A[(int64_t)r * lda + k0 + kc];
       ra[e] = v;
     }
+    typename BandRows<C>::Stage bs{};
+    if constexpr (BBAND) bs = bb.stage(k0);
 #pragma unroll
     for (int e = 0; e < BREG; ++e) {
       int idx = tid + e * 256;
@@ -383,7 +397,7 @@ __device__ __attribute__((always_inline)) inline void gemm3m(const typename cplx
       v.x = 0;
       v.y = 0;
       if (idx < G3K * TN && (FULL || (k0 + r < K && c < N))) {
-        if constexpr (BBAND) v = bb.at(k0 + r, c);
+        if constexpr (BBAND) v = bb.at(bs, r, c);
         else v = B[(int64_t)(k0 + r) * ldb + c];
       }
       rb[e] = v;
@@ -653,8 +667,10 @@ __global__ void __launch_bounds__(256) k_amax(const typename cplx<R>::t* __restr
   double m = 0.0;
   for (int g = 0; 32 * g < np; ++g) {
     const int c0 = fenv[(int64_t)i * fstride + g], w = min(fenv_hi[(int64_t)i * fstride + g], np) - c0;
+    const auto* Pg = frow(Fi, bo, bl, bwi, 32 * g) + c0;   // the group's 32 rows: one block
+    const int64_t ldg = bwi[g >> 1];
     for (int k = threadIdx.x; k < 32 * w; k += 256) {
-      auto v = frow(Fi, bo, bl, bwi, 32 * g + k / w)[c0 + k % w];
+      auto v = Pg[(k / w) * ldg + k % w];
       double a = fabs((double)v.x) + fabs((double)v.y);
       m = (a > m || a != a) ? a : m;   // a NaN entry makes the maximum NaN
     }
@@ -1065,7 +1081,9 @@ __global__ void __launch_bounds__(256) k_sym_diag(typename cplx<R>::t* F, const 
   __shared__ int bad;
   const int tid = threadIdx.x;
   if (tid == 0) bad = 0;
-  for (int e = tid; e < NB * NB; e += 256) T[e / NB][e % NB] = frow(Fi, bo, bl, bwi, k + e / NB)[k + e % NB];
+  C* Pk = frow(Fi, bo, bl, bwi, k) + k;   // rows k .. k+63: one block, row stride bwi[k / 64]
+  const int64_t ldk = bwi[k >> 6];
+  for (int e = tid; e < NB * NB; e += 256) T[e / NB][e % NB] = Pk[(e / NB) * ldk + e % NB];
   __syncthreads();
   const double thr = rtol * amax[i];
   for (int j = 0; j < NB; ++j) {
@@ -1085,7 +1103,7 @@ __global__ void __launch_bounds__(256) k_sym_diag(typename cplx<R>::t* F, const 
     }
     __syncthreads();
   }
-  for (int e = tid; e < NB * NB; e += 256) frow(Fi, bo, bl, bwi, k + e / NB)[k + e % NB] = T[e / NB][e % NB];
+  for (int e = tid; e < NB * NB; e += 256) Pk[(e / NB) * ldk + e % NB] = T[e / NB][e % NB];
   if (tid < NB) ipiv[loc_off[i] + k + tid] = k + tid;
   if (tid == 0 && bad && info[i] == 0) info[i] = bad;
   if (k + 2 * NB > np) return;
@@ -1107,7 +1125,7 @@ __global__ void __launch_bounds__(256) k_sym_diag(typename cplx<R>::t* F, const 
   }
   __syncthreads();
   // (the stored columns of every block reach at least 64 past its diagonal block)
-  for (int e = tid; e < NB * NB; e += 256) frow(Fi, bo, bl, bwi, k + e / NB)[k + NB + e % NB] = X[e / NB][e % NB];
+  for (int e = tid; e < NB * NB; e += 256) Pk[(e / NB) * ldk + NB + e % NB] = X[e / NB][e % NB];
 }
 
 // L_rk = A_rk U_kk^-1 for one 64-row block r of the panel below the diagonal
@@ -1132,9 +1150,12 @@ __global__ void __launch_bounds__(256) k_sym_cols(typename cplx<R>::t* F, const 
   __shared__ C U[NB][NB + 1];
   // (the row block's envelope starts left of k + NB, so its stored columns
   // begin at or before k)
+  C* Pr = frow(Fi, bo, bl, bwi, rb) + k;
+  const C* Pk = frow(Fi, bo, bl, bwi, k) + k + NB;
+  const int64_t ldr = bwi[rb >> 6], ldk = bwi[k >> 6];
   for (int e = threadIdx.x; e < NB * NB; e += 256) {
-    A[e / NB][e % NB] = frow(Fi, bo, bl, bwi, rb + e / NB)[k + e % NB];
-    U[e / NB][e % NB] = frow(Fi, bo, bl, bwi, k + e / NB)[k + NB + e % NB];
+    A[e / NB][e % NB] = Pr[(e / NB) * ldr + e % NB];
+    U[e / NB][e % NB] = Pk[(e / NB) * ldk + e % NB];
   }
   __syncthreads();
   const int r = threadIdx.x >> 2, cg = threadIdx.x & 3;
@@ -1147,7 +1168,7 @@ __global__ void __launch_bounds__(256) k_sym_cols(typename cplx<R>::t* F, const 
 #pragma unroll
     for (int u = 0; u < NB / 4; ++u) acc[u] = cadd(acc[u], cmul(a, U[l][cg + 4 * u]));
   }
-  C* out = frow(Fi, bo, bl, bwi, rb + r) + k + cg;
+  C* out = Pr + r * ldr + cg;
 #pragma unroll
   for (int u = 0; u < NB / 4; ++u) out[4 * u] = acc[u];
 }
@@ -1181,16 +1202,20 @@ __global__ void __launch_bounds__(256) k_sym_row(typename cplx<R>::t* F, const i
   // first block runs whatever its envelope); U rows k.. are written where
   // stored (beyond, the scaled zeros are not kept)
   const int jbk = jb >> 6, lo_j = bl[jbk];
+  const C* Pj = frow(Fi, bo, bl, bwi, jb);
+  const int64_t ldj = bwi[jbk];
   for (int e = threadIdx.x; e < NB * NB; e += 256) {
     const int jj = e / NB, rr = e % NB;
-    T[jj][rr] = k + rr >= lo_j ? frow(Fi, bo, bl, bwi, jb + jj)[k + rr] : cmk<C>(0, 0);
+    T[jj][rr] = k + rr >= lo_j ? Pj[jj * ldj + k + rr] : cmk<C>(0, 0);
   }
-  if (threadIdx.x < NB) dg[threadIdx.x] = frow(Fi, bo, bl, bwi, k + threadIdx.x)[k + threadIdx.x];
-  __syncthreads();
+  C* Pk = frow(Fi, bo, bl, bwi, k);
   const int kk = k >> 6, hi_k = bl[kk] + bwi[kk];
+  const int64_t ldk = bwi[kk];
+  if (threadIdx.x < NB) dg[threadIdx.x] = Pk[threadIdx.x * ldk + k + threadIdx.x];
+  __syncthreads();
   for (int e = threadIdx.x; e < NB * NB; e += 256) {
     const int rr = e / NB, jj = e % NB;
-    if (jb + jj < hi_k) frow(Fi, bo, bl, bwi, k + rr)[jb + jj] = cmul(dg[rr], T[jj][rr]);
+    if (jb + jj < hi_k) Pk[rr * ldk + jb + jj] = cmul(dg[rr], T[jj][rr]);
   }
 }
 
