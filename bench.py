@@ -295,7 +295,7 @@ def invert_main(args):
     S_empty = s_of(np.full(w.mesh.nt, gel))
     inv = inversion.Inversion(P, w.mesh.xyz, w.mesh.tet, w.part, w.n_sub, tx, rx, S_mes, S_empty, args.alpha,
                               precision="c64", tol=args.tol, restart=args.restart, block=args.block,
-                              recycle=not args.no_recycle, p1=args.p1)
+                              recycle=args.recycle, p1=args.p1)
     e0 = np.full(w.mesh.xyz.shape[0], gel)
     log(f"[invert] L-BFGS x{args.invert} from the gel")
     torch.cuda.synchronize()
@@ -352,8 +352,9 @@ def main():
                          "its line instead of the batch benchmark")
     ap.add_argument("--alpha", type=float, default=1e-4, help="Tikhonov weight of the inversion loop")
     ap.add_argument("--step0", type=float, default=0.5, help="largest vertex change of the first L-BFGS step")
-    ap.add_argument("--no-recycle", action="store_true",
-                    help="inversion loop: start every solve from zero instead of the previous fields")
+    ap.add_argument("--recycle", choices=("none", "warm", "project"), default="warm",
+                    help="inversion loop: start every solve from zero, from its own previous field, or from the "
+                         "least-squares combination of all previous fields")
     ap.add_argument("--p1", action="store_true",
                     help="inversion loop: the permittivity linear on every tetrahedron, integrated exactly "
                          "(instead of the tetrahedron mean of the vertex values)")

@@ -330,8 +330,13 @@ mw_status mw_lbfgs(int64_t n, double *x, int32_t iters, const mw_lbfgs_opts *o, 
  * averaging (p1: the exact vertex form); plus the Tikhonov term
  * (alpha/2) int |grad e|^2, exact for P1 through the P1 stiffness matrix K1
  * (alpha/2 Re(e^H K1 e), gradient alpha K1 e).  The gradient is
- * dJ/dRe e + i dJ/dIm e.  recycle = 1: every evaluation's forward and adjoint
- * solves start from the previous evaluation's fields. */
+ * dJ/dRe e + i dJ/dIm e.  Reuse of the previous evaluation's Krylov
+ * solutions across iterations (Section 7 names the recycling of Krylov
+ * information): recycle = 1, every column of the forward and adjoint solves
+ * starts from its own previous field; recycle = 2, all columns start from the
+ * best combination of all previous fields, X0 = U Y with Y minimising
+ * ||B - A U Y||_F (its normal equations solved on the host; never a larger
+ * starting residual than recycle = 1). */
 typedef struct {
   double alpha;
   int32_t p1;

@@ -225,6 +225,10 @@ DevBuf problem_alloc(mw_problem* p, int64_t bytes) {
   check_prob(p);
   return dalloc(p->ctx, bytes);
 }
+void problem_spmm(mw_problem* p, const double2* X, double2* Y, int nc, int64_t ld, const double2* Bsub) {
+  check_prob(p);
+  launch_spmm(p->dm, p->val.as<double2>(), X, ld, Y, ld, nc, Bsub, ld, p->stream);
+}
 void problem_retain(mw_problem* p) {
   check_prob(p);
   p->live_users++;

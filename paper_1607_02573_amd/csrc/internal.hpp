@@ -29,6 +29,8 @@ int problem_device(mw_problem* p);
 // device memory counted against the problem's context budget (MW_ENOMEM beyond it)
 DevBuf problem_alloc(mw_problem* p, int64_t bytes);
 DevBuf problem_upload(mw_problem* p, const void* host, int64_t bytes);
+// Y = A X (Bsub NULL) or Y = Bsub - A X for nc columns (leading dimensions ld), on the problem's stream
+void problem_spmm(mw_problem* p, const double2* X, double2* Y, int nc, int64_t ld, const double2* Bsub);
 // objects that drive a problem (an inversion) register themselves, so that
 // mw_destroy_problem refuses while they exist
 void problem_retain(mw_problem* p);

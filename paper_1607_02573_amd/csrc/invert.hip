@@ -14,8 +14,13 @@
 //       the P1 stiffness matrix K1 (applied to Re e and Im e): alpha/2
 //       Re(e^H K1 e) and its gradient alpha K1 e.
 // J = J_d + Tikhonov; gradient in the convention dJ/dRe e + i dJ/dIm e.
-// With recycle, the forward and adjoint solves start from the previous
-// evaluation's fields.  The optimiser (mw_lbfgs) is the two-loop recursion
+// Reuse of the previous evaluation's Krylov solutions (the paper's conclusion,
+// Section 7, proposes recycling Krylov information across the inversion's
+// iterations): recycle = 1 starts every column from its own previous field;
+// recycle = 2 starts all columns from the best combination of all previous
+// fields, X0 = U Y with Y minimising ||B - A U Y||_F column by column (normal
+// equations (AU)^H (AU) Y = (AU)^H B, solved by Cholesky on the host), which
+// is never worse than recycle = 1 (Y = I is one choice).  The optimiser (mw_lbfgs) is the two-loop recursion
 // of limited-memory BFGS (Nocedal and Wright, Numerical Optimization, 2nd
 // ed., Algorithms 7.4 and 7.5) with a backtracking Armijo line search; it
 // runs on the host over x = [Re e; Im e], the objective on the device.
@@ -141,6 +146,44 @@ __global__ void k_weights(int64_t count, const double2* __restrict__ Se, double*
   w[i] = 1.0 / a;
 }
 
+constexpr int GCHUNK = 2048;   // rows per partial sum of the Gram products
+
+// part[chunk][i][j] = sum over the chunk's rows r of conj(X[r][i]) Y[r][j]
+// (i < p, j < q): one workgroup per (row chunk, 16 x 16 output tile), every
+// sum over the chunk's rows in row order
+__global__ void __launch_bounds__(256) k_xhy_partial(const double2* __restrict__ X, int p,
+                                                     const double2* __restrict__ Y, int q, int64_t n,
+                                                     int tiles_q, double2* __restrict__ part) {
+  const int64_t ch = blockIdx.x;
+  const int ti = blockIdx.y / tiles_q, tj = blockIdx.y % tiles_q;
+  const int i = 16 * ti + (threadIdx.x >> 4), j = 16 * tj + (threadIdx.x & 15);
+  const int64_t r0 = ch * GCHUNK, r1 = min(n, r0 + GCHUNK);
+  double re = 0.0, im = 0.0;
+  if (i < p && j < q)
+    for (int64_t r = r0; r < r1; ++r) {
+      const double2 x = X[r * p + i], y = Y[r * q + j];
+      re += x.x * y.x + x.y * y.y;
+      im += x.x * y.y - x.y * y.x;
+    }
+  if (i < p && j < q) part[ch * (int64_t)p * q + (int64_t)i * q + j] = make_double2(re, im);
+}
+
+// Z[r][c] = sum_k U[r][k] Yc[k][c] (n x p times p x p)
+__global__ void k_times_small(const double2* __restrict__ U, const double2* __restrict__ Yc, int p, int64_t n,
+                              double2* __restrict__ Z) {
+  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t r = id / p;
+  const int c = (int)(id % p);
+  if (r >= n) return;
+  double re = 0.0, im = 0.0;
+  for (int k = 0; k < p; ++k) {
+    const double2 u = U[r * p + k], y = Yc[(int64_t)k * p + c];
+    re += u.x * y.x - u.y * y.y;
+    im += u.x * y.y + u.y * y.x;
+  }
+  Z[r * p + c] = make_double2(re, im);
+}
+
 void status_check(mw_status s) {
   if (s != MW_OK) fail(s, mw_last_error());
 }
@@ -161,6 +204,7 @@ struct mw_inversion {
   std::vector<int32_t> tx, rx, part;
   bool own_part = false;
   DevBuf tet, Ke, vt_ptr, vt, S_meas, w, S, gS, eps_t, ev, gt, gv, ky, q, red, B, U, F, Lam;
+  DevBuf AU, X0, gpart, gram;   // recycle = 2: A U, the projected start, Gram partials and sums
   bool have_prev = false;
   // per evaluation: mean GMRES iterations of the forward and adjoint solves
   std::vector<double> it_fwd, it_adj;
@@ -169,6 +213,84 @@ struct mw_inversion {
 };
 
 namespace {
+
+// recycle = 2: X (the previous solution of A X = B's predecessor) is replaced
+// by X Y with Y minimising ||B - A X Y||_F: the Gram matrices (AX)^H (AX) and
+// (AX)^H B on the device, the p x p Cholesky solve on the host (a relative
+// shift of 1e-13 on the diagonal keeps it defined when two previous fields
+// are nearly parallel; any Y is a valid start)
+void project_start(mw_inversion* I, double2* X, const double2* B) {
+  mw_problem* p = I->p;
+  hipStream_t st = problem_stream(p);
+  const int pc = I->ntx;
+  const int64_t n = I->n;
+  problem_spmm(p, X, I->AU.as<double2>(), pc, pc, nullptr);
+  const int64_t nch = ceil_div(n, GCHUNK);
+  const int tq = (int)ceil_div(pc, 16);
+  double2* part = I->gpart.as<double2>();
+  double2* G = I->gram.as<double2>();
+  const int64_t pp = (int64_t)pc * pc;
+  k_xhy_partial<<<dim3((unsigned)nch, (unsigned)(tq * tq)), 256, 0, st>>>(I->AU.as<double2>(), pc,
+                                                                         I->AU.as<double2>(), pc, n, tq, part);
+  MW_LAUNCH_CHECK();
+  launch_sum_chunks_c(part, nch, pp, G, st);
+  k_xhy_partial<<<dim3((unsigned)nch, (unsigned)(tq * tq)), 256, 0, st>>>(I->AU.as<double2>(), pc, B, pc, n, tq,
+                                                                         part);
+  MW_LAUNCH_CHECK();
+  launch_sum_chunks_c(part, nch, pp, G + pp, st);
+  std::vector<double2> h(2 * pp);
+  MW_HIP(hipMemcpyAsync(h.data(), G, 2 * pp * 16, hipMemcpyDeviceToHost, st));
+  MW_HIP(hipStreamSynchronize(st));
+  // Cholesky G = L L^H (lower, row-major), then L L^H Y = R column by column
+  std::vector<double> Lr(pp, 0.0), Li(pp, 0.0);
+  double dmax = 0.0;
+  for (int k = 0; k < pc; ++k) dmax = std::max(dmax, h[(int64_t)k * pc + k].x);
+  const double shift = 1e-13 * dmax;
+  for (int j = 0; j < pc; ++j) {
+    double d = h[(int64_t)j * pc + j].x + shift;
+    for (int k = 0; k < j; ++k) d -= Lr[j * pc + k] * Lr[j * pc + k] + Li[j * pc + k] * Li[j * pc + k];
+    if (!(d > 0.0)) return;   // not positive definite in floating point: keep the current start
+    const double l = std::sqrt(d);
+    Lr[j * pc + j] = l;
+    for (int r = j + 1; r < pc; ++r) {
+      // L[r][j] = (G[r][j] - sum_k L[r][k] conj(L[j][k])) / L[j][j]
+      double sr = h[(int64_t)r * pc + j].x, si = h[(int64_t)r * pc + j].y;
+      for (int k = 0; k < j; ++k) {
+        sr -= Lr[r * pc + k] * Lr[j * pc + k] + Li[r * pc + k] * Li[j * pc + k];
+        si -= Li[r * pc + k] * Lr[j * pc + k] - Lr[r * pc + k] * Li[j * pc + k];
+      }
+      Lr[r * pc + j] = sr / l;
+      Li[r * pc + j] = si / l;
+    }
+  }
+  std::vector<double2> Y(pp);
+  for (int c = 0; c < pc; ++c) {
+    std::vector<double> zr(pc), zi(pc);
+    for (int r = 0; r < pc; ++r) {   // L z = R[:, c]
+      double sr = h[pp + (int64_t)r * pc + c].x, si = h[pp + (int64_t)r * pc + c].y;
+      for (int k = 0; k < r; ++k) {
+        sr -= Lr[r * pc + k] * zr[k] - Li[r * pc + k] * zi[k];
+        si -= Lr[r * pc + k] * zi[k] + Li[r * pc + k] * zr[k];
+      }
+      zr[r] = sr / Lr[r * pc + r];
+      zi[r] = si / Lr[r * pc + r];
+    }
+    for (int r = pc - 1; r >= 0; --r) {   // L^H y = z
+      double sr = zr[r], si = zi[r];
+      for (int k = r + 1; k < pc; ++k) {   // conj(L[k][r]) y_k
+        const double ar = Lr[k * pc + r], ai = -Li[k * pc + r];
+        sr -= ar * Y[(int64_t)k * pc + c].x - ai * Y[(int64_t)k * pc + c].y;
+        si -= ar * Y[(int64_t)k * pc + c].y + ai * Y[(int64_t)k * pc + c].x;
+      }
+      Y[(int64_t)r * pc + c] = make_double2(sr / Lr[r * pc + r], si / Lr[r * pc + r]);
+    }
+  }
+  MW_HIP(hipMemcpyAsync(G, Y.data(), pp * 16, hipMemcpyHostToDevice, st));
+  k_times_small<<<(unsigned)ceil_div(n * pc, 256), 256, 0, st>>>(X, G, pc, n, I->X0.as<double2>());
+  MW_LAUNCH_CHECK();
+  MW_HIP(hipMemcpyAsync(X, I->X0.p, n * pc * 16, hipMemcpyDeviceToDevice, st));
+  MW_HIP(hipStreamSynchronize(st));
+}
 
 // J and gradient (device [nv]) at the vertex field ev (device [nv])
 double evaluate(mw_inversion* I, const double2* ev, double2* gv) {
@@ -188,6 +310,7 @@ double evaluate(mw_inversion* I, const double2* ev, double2* gv) {
   status_check(mw_rhs_ports(p, I->ntx, I->tx.data(), I->B.p));
   mw_solve_opts so = I->o.solve;
   so.use_x0 = (I->o.recycle && I->have_prev) ? 1 : 0;
+  if (I->o.recycle == 2 && I->have_prev) project_start(I, I->U.as<double2>(), I->B.as<double2>());
   std::vector<int32_t> its(I->ntx);
   mw_solve_info info{};
   info.iters = its.data();
@@ -197,6 +320,7 @@ double evaluate(mw_inversion* I, const double2* ev, double2* gv) {
   double Jd = 0.0;
   status_check(mw_misfit_weighted(p, (int64_t)I->nrx * I->ntx, I->S.p, I->S_meas.p, I->w.as<double>(), I->gS.p, &Jd));
   status_check(mw_adjoint_rhs(p, I->nrx, I->rx.data(), I->ntx, I->gS.p, I->Lam.p));
+  if (I->o.recycle == 2 && I->have_prev) project_start(I, I->F.as<double2>(), I->Lam.as<double2>());
   status_check(mw_solve(p, I->ntx, I->Lam.p, I->F.p, &so, &info));
   I->it_adj.push_back(std::accumulate(its.begin(), its.end(), 0.0) / std::max(1, I->ntx));
   I->have_prev = true;
@@ -346,6 +470,7 @@ mw_status mw_inversion_create(mw_problem* p, const mw_mesh* mesh, const int32_t*
     MW_CHECK(ntx >= 1 && nrx >= 1, MW_EINVAL, "need at least one transmitting and one receiving port");
     MW_CHECK(o->precision == MW_C64 || o->precision == MW_C128, MW_EINVAL, "precision must be MW_C64 or MW_C128");
     MW_CHECK(o->n_sub >= 1 && o->overlap >= 1, MW_EINVAL, "n_sub and overlap must be >= 1");
+    MW_CHECK(o->recycle >= 0 && o->recycle <= 2, MW_EINVAL, "recycle must be 0, 1 or 2");
     mw_problem_info pi{};
     status_check(mw_problem_get_info(p, &pi));
     MW_CHECK(mesh->nt == pi.nt, MW_EINVAL, "mesh does not match the problem (number of tetrahedra)");
@@ -411,6 +536,12 @@ mw_status mw_inversion_create(mw_problem* p, const mw_mesh* mesh, const int32_t*
     I->U = problem_alloc(p, n * ntx * 16);
     I->F = problem_alloc(p, n * ntx * 16);
     I->Lam = problem_alloc(p, n * ntx * 16);
+    if (o->recycle == 2) {
+      I->AU = problem_alloc(p, n * ntx * 16);
+      I->X0 = problem_alloc(p, n * ntx * 16);
+      I->gpart = problem_alloc(p, ceil_div(n, GCHUNK) * (int64_t)ntx * ntx * 16);
+      I->gram = problem_alloc(p, 2 * (int64_t)ntx * ntx * 16);
+    }
     MW_HIP(hipStreamSynchronize(st));
     problem_retain(p);
     *out = I.release();

@@ -32,15 +32,23 @@ class History:
 class Inversion:
     """L-BFGS over the vertex permittivity on the library's device objective.
 
+    recycle: how each evaluation's solves reuse the previous evaluation's
+    fields: 'none' (zero start), 'warm' (each column from its own previous
+    field) or 'project' (all columns from the least-squares combination of
+    all previous fields).
+
     part: the non-overlapping partition (int32 [nt]) or None for the
     library's own; S_mes, S_empty: nrx x ntx complex (host or device)."""
 
     def __init__(self, problem, xyz, tet, part, n_sub: int, tx, rx, S_mes, S_empty, alpha: float,
                  precision: str = "c64", tol: float = 1e-8, restart: int = 30, block: int = 0, overlap: int = 1,
-                 recycle: bool = True, p1: bool = False, maxit: int = 1000):
+                 recycle="warm", p1: bool = False, maxit: int = 1000):
         self.P = problem
         self.nv = int(np.asarray(xyz).shape[0])
-        self.recycle, self.p1 = recycle, p1
+        modes = {"none": 0, "warm": 1, "project": 2, False: 0, True: 1, 0: 0, 1: 1, 2: 2}
+        if recycle not in modes:
+            raise ValueError("recycle must be 'none', 'warm' or 'project'")
+        self.recycle, self.p1 = ("none", "warm", "project")[modes[recycle]], p1
         dev = problem.ctx.device
         self._mesh, self._keep = B.make_mesh(xyz, tet, np.zeros((0, 3), np.int32), np.zeros(0, np.int32))
         self._tx = np.ascontiguousarray(tx, dtype=np.int32)
@@ -49,7 +57,7 @@ class Inversion:
         Sm = torch.as_tensor(np.asarray(S_mes, dtype=np.complex128)).to(dev).contiguous()
         Se = torch.as_tensor(np.asarray(S_empty, dtype=np.complex128)).to(dev).contiguous()
         assert Sm.shape == Se.shape == (self._rx.size, self._tx.size)
-        o = B.mw_inversion_opts(alpha=float(alpha), p1=int(p1), recycle=int(recycle), n_sub=int(n_sub),
+        o = B.mw_inversion_opts(alpha=float(alpha), p1=int(p1), recycle=modes[recycle], n_sub=int(n_sub),
                                 overlap=int(overlap), precision={"c128": B.MW_C128, "c64": B.MW_C64}[precision],
                                 solve=B.mw_solve_opts(tol=float(tol), restart=int(restart), maxit=int(maxit),
                                                       use_x0=0, block=int(block)))

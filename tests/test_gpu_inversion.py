@@ -36,7 +36,7 @@ def setup():
     return w, ports, S_mes, S_empty, e_gel, es, Js, nev
 
 
-@pytest.mark.parametrize("recycle", [False, True])
+@pytest.mark.parametrize("recycle", ["none", "warm", "project"])
 @pytest.mark.parametrize("prec,tol,rtol", [("c128", 1e-11, 1e-7), ("c64", 1e-10, 1e-6)])
 def test_lbfgs_on_gpu_matches_oracle(setup, prec, tol, rtol, recycle):
     from paper_1607_02573_amd import inversion, solver
@@ -46,7 +46,7 @@ def test_lbfgs_on_gpu_matches_oracle(setup, prec, tol, rtol, recycle):
     inv = inversion.Inversion(Pg, w.mesh.xyz, w.mesh.tet, w.part, w.n_sub, ports, ports, S_mes, S_empty, 1e-4,
                               precision=prec, tol=tol, recycle=recycle)
     h = inv.run(e_gel, iters=3, step0=0.5)
-    if recycle:
+    if recycle != "none":
         # later evaluations start from the previous fields: fewer iterations
         assert sum(f + a for f, a in h.iters[1:]) < sum(f + a for f, a in h.iters[:1]) * (len(h.iters) - 1)
     assert h.evaluations == nev
@@ -56,6 +56,30 @@ def test_lbfgs_on_gpu_matches_oracle(setup, prec, tol, rtol, recycle):
         assert np.linalg.norm(eg - eo) <= rtol * np.linalg.norm(eo)
     assert h.J[-1] < 0.5 * h.J[0]
     inv.close()
+    Pg.close()
+    ctx.close()
+
+
+def test_projected_start_needs_no_more_iterations(setup):
+    """The projected start X0 = U Y (Y the least-squares combination of all
+    previous fields) has a starting residual no larger than the warm start's
+    (Y = I is one of the choices), column by column: over the same accepted
+    iterates, its GMRES iteration total is at most the warm start's (2 %
+    slack: a smaller starting residual need not save an iteration in every
+    column, since GMRES stops at a tolerance relative to ||b||)."""
+    from paper_1607_02573_amd import inversion, solver
+    w, ports, S_mes, S_empty, e_gel, es, Js, nev = setup
+    ctx = solver.Context(0)
+    Pg = solver.problem_from_workload(ctx, w)
+    tot = {}
+    for mode in ("warm", "project"):
+        inv = inversion.Inversion(Pg, w.mesh.xyz, w.mesh.tet, w.part, w.n_sub, ports, ports, S_mes, S_empty, 1e-4,
+                                  precision="c128", tol=1e-11, recycle=mode)
+        h = inv.run(e_gel, iters=3, step0=0.5)
+        np.testing.assert_allclose(h.J, Js, rtol=1e-7)
+        tot[mode] = sum(f + a for f, a in h.iters[1:])
+        inv.close()
+    assert tot["project"] <= 1.02 * tot["warm"], tot
     Pg.close()
     ctx.close()
 
