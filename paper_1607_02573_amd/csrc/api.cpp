@@ -151,7 +151,7 @@ struct mw_problem {
   Decomposition D;
   DevBuf d_fac_off, d_loc_off, d_n_loc, d_n_pad, d_lt_off, d_lt_tet, d_lt_loc, d_lf_off, d_lf_vert, d_lf_owner,
       d_lf_kind, d_lf_loc, d_rtl_ptr, d_rtl, d_rfl_ptr, d_rfl, d_sub_dof, d_D, d_cp_ptr, d_cp_row, d_ipiv, d_ridx,
-      d_info, d_amax, d_row_lo, d_env, d_fenv, d_fenvh;
+      d_info, d_amax, d_row_lo, d_env, d_fenv, d_fenvh, d_order;
   std::vector<int32_t> h_row_lo;
   std::vector<int2> h_env;
   DeviceDecomp dd;
@@ -407,6 +407,14 @@ void upload_decomp(mw_problem* p) {
   p->h_row_lo.resize(D.nsub);
   for (int32_t i = 0; i < D.nsub; ++i) p->h_row_lo[i] = (D.n_lead[i] / 64) * 64;
   p->d_row_lo = upload(c, p->stream, p->h_row_lo);
+  {
+    // subdomains by decreasing size (ties by index): the triangular solves
+    // start the longest sweeps first
+    std::vector<int32_t> order(D.nsub);
+    for (int32_t i = 0; i < D.nsub; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return D.n_pad[a] > D.n_pad[b]; });
+    p->d_order = upload(c, p->stream, order);
+  }
   DeviceDecomp& d = p->dd;
   d.nsub = D.nsub;
   d.n_glob = p->T.n();
@@ -443,6 +451,7 @@ void upload_decomp(mw_problem* p) {
   d.h_n_loc = p->D.n_loc.data();
   d.row_lo = p->d_row_lo.as<int32_t>();
   d.h_row_lo = p->h_row_lo.data();
+  d.order = p->d_order.as<int32_t>();
   p->d_fenv = upload(c, p->stream, D.fenv);
   d.fenv = p->d_fenv.as<int32_t>();
   p->d_fenvh = upload(c, p->stream, D.fenv_hi);

@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(256) k_gemm_lu(typename cplx<R>::t* F, const i
 // C = A B (B may alias C: all B rows of the tile are read before the
 // epilogue writes).
 constexpr int WBK = 8;    // complex K per stage
-template <class R, int WC, int AMODE = 0, bool OVERWRITE = false>
+template <class R, int WC, int AMODE = 0, bool OVERWRITE = false, bool NEG = false>
 __device__ __attribute__((always_inline)) inline void gemm_wide(const typename cplx<R>::t* __restrict__ A, int64_t lda,
                                  const typename cplx<R>::t* B, int64_t ldb,
                                  typename cplx<R>::t* Cm, int64_t ldc, int M, int N, int K) {
@@ -299,7 +299,8 @@ __device__ __attribute__((always_inline)) inline void gemm_wide(const typename c
         if (gr < M && gc < N) {
           C* p = Cm + (int64_t)gr * ldc + gc;
           C o;
-          if (OVERWRITE) { o.x = accr[x][y][r]; o.y = acci[x][y][r]; }
+          if (OVERWRITE && NEG) { o.x = -accr[x][y][r]; o.y = -acci[x][y][r]; }
+          else if (OVERWRITE) { o.x = accr[x][y][r]; o.y = acci[x][y][r]; }
           else { o = *p; o.x -= accr[x][y][r]; o.y -= acci[x][y][r]; }
           *p = o;
         }
@@ -555,6 +556,230 @@ __global__ void __launch_bounds__(256) k_leaf_x(const typename cplx<R>::t* F, co
   const C* blk = frow(Fi, bo, bl, bwi, r0) + r0;
   C* Yb = Y + (loc_off[i] + r0) * ld + tn * TN;
   gemm_wide<R, WC, AMODE, true>(blk, bwi[r0 >> 6], Yb, ld, Yb, ld, NB, N, NB);
+}
+
+// Block-row form of the triangular solves (every batch of more than one
+// subdomain).  After the factorisation each 64-row block b keeps, beside its
+// inverted diagonal blocks T_L = L_bb^-1 and T_U = U_bb^-1, the scaled
+// off-diagonal rows S_L = -T_L L[b, :64b] and S_U = -T_U U[b, 64b+64:]
+// (k_scale_offdiag, once per factorisation).  A solve is then one product per
+// block and direction, the diagonal solve folded in:
+//   forward,  b = 0, 1, ...:  Y_b <- T_L Y_b + S_L Y[lo:64b]
+//   backward, b = last, ...:  Y_b <- T_U Y_b + S_U Y[64b+64:hi]
+// ([lo, hi) the envelope of the block's rows), each Y_b written once per
+// direction.  One workgroup owns a 64-row block and a column tile, so it
+// alone reads the old Y_b and writes the new one.
+
+// S_L (UPPER false) or S_U (UPPER true) of block blockIdx.x of subdomain
+// blockIdx.y, in place, 64 columns at a time, over the envelope of the
+// block's rows (the rest is zero before and after).
+template <class R, bool UPPER>
+__global__ void __launch_bounds__(256) k_scale_offdiag(typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
+                                                       const int32_t* __restrict__ n_pad,
+                                                       const int2* __restrict__ env, int env_stride,
+                                                       const int64_t* __restrict__ boff,
+                                                       const int32_t* __restrict__ blo,
+                                                       const int32_t* __restrict__ bw, int bstride) {
+  const int b = blockIdx.x, i = blockIdx.y;
+  const int np = n_pad[i];
+  const int r0 = b * NB;
+  if (r0 >= np) return;
+  const int2 e0 = env[(int64_t)i * env_stride + 2 * b], e1 = env[(int64_t)i * env_stride + 2 * b + 1];
+  auto* Fi = F + fac_off[i];
+  const int64_t* bo = boff + (int64_t)i * bstride;
+  const int32_t* bl = blo + (int64_t)i * bstride;
+  const int32_t* bwi = bw + (int64_t)i * bstride;
+  auto* row = frow(Fi, bo, bl, bwi, r0);
+  const int ld = bwi[b];
+  const auto* T = row + r0;
+  if (!UPPER) {
+    for (int c = min(e0.x, e1.x) & ~63; c < r0; c += NB)
+      gemm_wide<R, 2, 1, true, true>(T, ld, row + c, ld, row + c, ld, NB, NB, NB);
+  } else {
+    const int hi = min(np, (max(e0.y, e1.y) + 63) & ~63);
+    for (int c = r0 + NB; c < hi; c += NB) gemm_wide<R, 2, 2, true, true>(T, ld, row + c, ld, row + c, ld, NB, NB, NB);
+  }
+}
+
+// The product of one block of the block-row solves, C = A B over a 64-row
+// block and up to 32 WC columns, in the 3M form of gemm3m.  A's columns
+// [kd, kd + 64) hold the inverted diagonal block, read as unit lower (amode
+// 1: strict lower part, ones on the diagonal) or upper with diagonal (amode
+// 2).  The operands stay in LDS as complex pairs: one 64-bit (FP32) LDS read
+// gives a value's real and imaginary parts, and their sum is formed in
+// registers (a third of the LDS reads and writes of gemm3m's three real
+// arrays; 3.5 ms less per preconditioner application on the 1 GHz chamber
+// at 160 columns).  C aliases B's first or last 64 rows; every B read
+// precedes the first C write.
+template <class R, int WC>
+__device__ __attribute__((always_inline)) inline void gemm3m_pairs(const typename cplx<R>::t* __restrict__ A,
+                                                                   int64_t lda, const typename cplx<R>::t* B,
+                                                                   int64_t ldb, typename cplx<R>::t* Cm, int64_t ldc,
+                                                                   int N, int K, int kd, int amode) {
+  using C = typename cplx<R>::t;
+  using acc_t = typename Mf<R>::acc;
+  constexpr int RB = 2, TM = 64, TN = 32 * WC, KS = G3K;
+  constexpr int AREG = TM * KS / 256;
+  constexpr int BREG = KS * TN / 256;
+  __shared__ C As[2][TM][KS + 1];
+  __shared__ C Bs[2][KS][TN + 1];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, kq = lane >> 4;
+  const bool lower = amode == 1;
+  acc_t p1[RB][WC], p2[RB][WC], p3[RB][WC];
+#pragma unroll
+  for (int x = 0; x < RB; ++x)
+#pragma unroll
+    for (int y = 0; y < WC; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) { p1[x][y][r] = 0; p2[x][y][r] = 0; p3[x][y][r] = 0; }
+  C ra[AREG], rb[BREG];
+  auto fetch = [&](int k0) {
+    const bool tstage = k0 + KS > kd && k0 < kd + 64;   // same for the whole workgroup
+#pragma unroll
+    for (int e = 0; e < AREG; ++e) {
+      const int idx = tid + e * 256;
+      const int r = idx / KS, kc = idx % KS;
+      C v = A[(int64_t)r * lda + k0 + kc];
+      if (tstage) {
+        const int j = k0 + kc - kd;
+        if (j >= 0 && j < 64 && !(lower ? j < r : j >= r)) {
+          v.x = (lower && j == r) ? 1 : 0;
+          v.y = 0;
+        }
+      }
+      ra[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < BREG; ++e) {
+      const int idx = tid + e * 256;
+      const int r = idx / TN, c = idx % TN;
+      C v;
+      v.x = 0;
+      v.y = 0;
+      if (c < N) v = B[(int64_t)(k0 + r) * ldb + c];
+      rb[e] = v;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < AREG; ++e) {
+      const int idx = tid + e * 256;
+      As[buf][idx / KS][idx % KS] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < BREG; ++e) {
+      const int idx = tid + e * 256;
+      Bs[buf][idx / TN][idx % TN] = rb[e];
+    }
+  };
+  // K is a multiple of KS (a difference of multiples of 8), at least 64
+  fetch(0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < K; k0 += KS) {
+    const bool more = k0 + KS < K;
+    if (more) fetch(k0 + KS);
+#pragma unroll
+    for (int kk = 0; kk < KS; kk += 4) {
+      R a1[RB], a2[RB], a3[RB];
+#pragma unroll
+      for (int x = 0; x < RB; ++x) {
+        const C av = As[buf][wm * 16 * RB + x * 16 + li][kk + kq];
+        a1[x] = av.x;
+        a2[x] = av.y;
+        a3[x] = av.x + av.y;
+      }
+#pragma unroll
+      for (int y = 0; y < WC; ++y) {
+        const C bv = Bs[buf][kk + kq][wn * 16 * WC + y * 16 + li];
+        const R b1 = bv.x, b2 = bv.y, b3 = bv.x + bv.y;
+#pragma unroll
+        for (int x = 0; x < RB; ++x) {
+          p1[x][y] = Mf<R>::mfma(a1[x], b1, p1[x][y]);
+          p2[x][y] = Mf<R>::mfma(a2[x], b2, p2[x][y]);
+          p3[x][y] = Mf<R>::mfma(a3[x], b3, p3[x][y]);
+        }
+      }
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int x = 0; x < RB; ++x)
+#pragma unroll
+    for (int y = 0; y < WC; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = wm * 16 * RB + x * 16 + Mf<R>::out_row(lane, r);
+        const int gc = wn * 16 * WC + y * 16 + li;
+        if (gc < N) {
+          C o;
+          o.x = p1[x][y][r] - p2[x][y][r];
+          o.y = p3[x][y][r] - p1[x][y][r] - p2[x][y][r];
+          Cm[(int64_t)gr * ldc + gc] = o;
+        }
+      }
+}
+
+// Both sweeps in one launch: every workgroup takes one (subdomain, column
+// tile) and runs its forward blocks, then its backward blocks, reading back
+// the rows it has just written (a workgroup barrier between blocks orders
+// them).  Subdomains are independent, so no workgroup waits for another; the
+// few hundred rows of the moving window stay in the caches between
+// consecutive blocks, and the forward sweep's last rows are the backward
+// sweep's first.  Workgroup g runs on XCD g mod 8 (round-robin dispatch):
+// XCD x takes the subdomains of rank x, x + 8, x + 16, ... in decreasing
+// size (order[]), all column tiles of one subdomain on one XCD, so the
+// longest sweeps start first and the XCDs get alike shares.
+template <class R, int WC, int DIRS>
+__global__ void __launch_bounds__(256, 2) k_row_sweep(const typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
+                                                      const int32_t* __restrict__ n_pad,
+                                                      const int64_t* __restrict__ loc_off, typename cplx<R>::t* Y,
+                                                      int64_t ld, int ncols, int tiles_n, int nsub,
+                                                      const int32_t* __restrict__ order,
+                                                      const int32_t* __restrict__ row_lo,
+                                                      const int2* __restrict__ env, int env_stride,
+                                                      const int64_t* __restrict__ boff,
+                                                      const int32_t* __restrict__ blo,
+                                                      const int32_t* __restrict__ bw, int bstride) {
+  using C = typename cplx<R>::t;
+  const int x = blockIdx.x & 7, q = blockIdx.x >> 3;
+  const int rank = 8 * (q / tiles_n) + x;
+  if (rank >= nsub) return;
+  const int i = order[rank];
+  const int tn = q % tiles_n;
+  const int np = n_pad[i];
+  const int nblk = np / NB;
+  constexpr int TN = WC * 32;
+  const int N = min(ncols - tn * TN, TN);
+  const C* Fi = F + fac_off[i];
+  const int64_t* bo = boff + (int64_t)i * bstride;
+  const int32_t* bl = blo + (int64_t)i * bstride;
+  const int32_t* bwi = bw + (int64_t)i * bstride;
+  const int2* ei = env + (int64_t)i * env_stride;
+  C* Yi = Y + loc_off[i] * ld + tn * TN;
+  // blocks of the backward sweep: the last down to the one holding row_lo
+  const int nbwd = nblk - (row_lo ? row_lo[i] / NB : 0);
+  const int nsteps = ((DIRS & 1) ? nblk : 0) + ((DIRS & 2) ? nbwd : 0);
+  // one product per step (one call site, so that both directions share its
+  // LDS): forward Y_b <- T_L Y_b + S_L Y[lo:64b], b = 0, 1, ...; backward
+  // Y_b <- T_U Y_b + S_U Y[64b+64:hi], b = last, ...
+  for (int s = 0; s < nsteps; ++s) {
+    const bool fwd = (DIRS & 1) && s < nblk;
+    const int b = fwd ? s : nblk - 1 - (s - ((DIRS & 1) ? nblk : 0));
+    const int r0 = b * NB;
+    const int2 e0 = ei[2 * b], e1 = ei[2 * b + 1];
+    const int kb = fwd ? min(min(e0.x, e1.x), r0) : r0;
+    const int ke = fwd ? r0 + NB : min(np, max(max(e0.y, e1.y), r0 + NB));
+    gemm3m_pairs<R, WC>(frow(Fi, bo, bl, bwi, r0) + kb, bwi[b], Yi + (int64_t)kb * ld, ld, Yi + (int64_t)r0 * ld,
+                        ld, N, ke - kb, r0 - kb, fwd ? 1 : 2);
+    __syncthreads();
+  }
 }
 
 // LU update with wide tiles:
@@ -1419,6 +1644,12 @@ static void kt_account(const DeviceDecomp& d, int fam, hipStream_t st, F&& per_s
 }
 static inline double clampd(double v) { return v > 0 ? v : 0; }
 
+// Batches of more than one subdomain take the block-row solves (their
+// factors carry the scaled off-diagonal rows); a single matrix (the coarse
+// operator) keeps the recursive solves, whose updates spread one matrix
+// over many workgroups.
+static inline bool row_form(const DeviceDecomp& d) { return d.nsub > 1; }
+
 template <class C>
 void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st, bool sym) {
   using R = typename RealOf<C>::t;
@@ -1608,6 +1839,39 @@ void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st, bool sym) {
   k_envelope<C><<<(unsigned)((int64_t)d.nsub * d.env_stride), 256, 0, st>>>(
       F, d.fac_off, d.n_pad, d.env_stride, sym ? d.fenv : nullptr, sym ? d.fenv_hi : nullptr, d.env, d.boff, d.blo, d.bw, d.bstride);
   MW_LAUNCH_CHECK();
+  if (row_form(d)) {
+    // S_L = -T_L L[b, :64b] and S_U = -T_U U[b, 64b+64:] of every block,
+    // over the envelope just found
+    kt_begin(KF_LU_OTHER, st);
+    const dim3 g((unsigned)(maxp / NB), (unsigned)d.nsub);
+    k_scale_offdiag<R, false><<<g, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.env, d.env_stride, d.boff, d.blo, d.bw,
+                                                d.bstride);
+    MW_LAUNCH_CHECK();
+    k_scale_offdiag<R, true><<<g, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.env, d.env_stride, d.boff, d.blo, d.bw,
+                                               d.bstride);
+    MW_LAUNCH_CHECK();
+    int sub = 0;
+    kt_account(d, KF_LU_OTHER, st, [&](int n, double& f, double& by) {
+      // per 64 x 64 chunk: a triangular 64 x 64 times 64 x 64 product, the
+      // chunk read and written, the triangle read once per block; chunks of
+      // the structural envelope without interchanges (as many right of the
+      // diagonal as left of it: B_i is structurally symmetric), all of them
+      // with interchanges
+      const int i = sub++;
+      double chunks = 0, blocks = 0;
+      for (int r0 = 0; r0 < n; r0 += NB) {
+        int lo = 0;
+        if (sym && d.h_fenv) {
+          const int32_t* fe = d.h_fenv + (size_t)i * d.fenv_stride;
+          lo = std::min(fe[r0 / 32], fe[r0 / 32 + 1]) & ~63;
+        }
+        chunks += sym ? 2.0 * ((r0 - std::min(lo, r0)) / NB) : (double)((n + NB - 1) / NB - 1);
+        blocks += 1;
+      }
+      f = chunks * 4.0 * NB * NB * NB;
+      by = chunks * 2.0 * NB * NB + blocks * NB * NB;
+    }, (int)sizeof(C));
+  }
 }
 
 // Tile width (columns) for a multi-vector of ncols columns: the narrowest of
@@ -1739,10 +2003,65 @@ static void bwd_rec(const DeviceDecomp& d, const typename cplx<R>::t* F, typenam
   bwd_rec<R>(d, F, Y, ncols, ld, b0, mid, st);
 }
 
+template <class R, int WC, int DIRS>
+static void launch_row_sweep_wc(const DeviceDecomp& d, const typename cplx<R>::t* F, typename cplx<R>::t* Y,
+                                int64_t ld, int ncols, hipStream_t st) {
+  const int tiles_n = (int)ceil_div(ncols, WC * 32);
+  const int64_t G = 8 * ceil_div(d.nsub, 8) * (int64_t)tiles_n;
+  k_row_sweep<R, WC, DIRS><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, Y, ld, ncols, tiles_n,
+                                                        d.nsub, d.order, d.row_lo, d.env, d.env_stride, d.boff,
+                                                        d.blo, d.bw, d.bstride);
+  MW_LAUNCH_CHECK();
+}
+// Both triangular solves of every subdomain, block-row form (DIRS = 3; 1
+// forward only, 2 backward only).
+template <class R, int DIRS = 3>
+static void launch_row_sweep(const DeviceDecomp& d, const typename cplx<R>::t* F, typename cplx<R>::t* Y, int64_t ld,
+                             int ncols, hipStream_t st) {
+  const int esz = (int)sizeof(typename cplx<R>::t);
+  MW_CHECK(d.order != nullptr, MW_EINVAL, "subdomain order missing");
+  kt_begin(KF_TRSM_GEMM, st);
+  switch (pick_wc<R>(ncols)) {
+    case 1: launch_row_sweep_wc<R, 1, DIRS>(d, F, Y, ld, ncols, st); break;
+    case 2: launch_row_sweep_wc<R, 2, DIRS>(d, F, Y, ld, ncols, st); break;
+    case 3: launch_row_sweep_wc<R, sizeof(R) == 4 ? 3 : 2, DIRS>(d, F, Y, ld, ncols, st); break;
+    case 4: launch_row_sweep_wc<R, sizeof(R) == 4 ? 4 : 2, DIRS>(d, F, Y, ld, ncols, st); break;
+    default: launch_row_sweep_wc<R, sizeof(R) == 4 ? 5 : 2, DIRS>(d, F, Y, ld, ncols, st); break;
+  }
+  // algorithmic work per block: the triangular solve with the diagonal
+  // block (m rows) and the product with the off-diagonal entries inside the
+  // envelope (32-row groups); bytes: those factor entries once, every row of
+  // Y read and written once per sweep
+  int sub = 0;
+  kt_account(d, KF_TRSM_GEMM, st, [&](int n, double& f, double& by) {
+    const int i = sub++;
+    f = by = 0;
+    for (int dir = 1; dir <= 2; ++dir) {
+      if (!(DIRS & dir)) continue;
+      double rows_y = 0;
+      for (int r0 = 0; r0 < n; r0 += NB) {
+        const double m = std::min(r0 + NB, n) - r0;
+        if (dir == 2 && r0 + NB <= d.h_row_lo[i]) continue;
+        double fac, kspan, rows;
+        if (dir == 2) env_work(d, i, n, r0, r0 + NB, r0 + NB, n, fac, kspan, rows);
+        else env_work(d, i, n, r0, r0 + NB, 0, r0, fac, kspan, rows);
+        f += 8.0 * fac * ncols + 4.0 * m * m * ncols;
+        by += fac + m * m / 2;
+        rows_y += m;
+      }
+      by += 2.0 * rows_y * ncols;
+    }
+  }, esz);
+}
+
 template <class C>
 void lu_solve_batched(const DeviceDecomp& d, const C* F, C* Y, int ncols, int64_t ld, hipStream_t st) {
   using R = typename RealOf<C>::t;
   int nblk = d.max_pad / NB;
+  if (row_form(d)) {
+    launch_row_sweep<R>(d, F, Y, ld, ncols, st);
+    return;
+  }
   fwd_rec<R>(d, F, Y, ncols, ld, 0, nblk, st);
   bwd_rec<R>(d, F, Y, ncols, ld, 0, nblk, st);
 }
