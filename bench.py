@@ -44,8 +44,8 @@ FP64_MFMA_FAMILIES = ("bgs_dots", "bgs_update")
 # known size (--copy-probe-mib).  Valid only for the kernel source it was
 # taken on: a different hash of that file reports null.
 PMC_TRAFFIC = {"family": "trsm_gemm", "source": "paper_1607_02573_amd/csrc/dense.hip",
-               "sha256": "c87a4c5a861dec68fb75730d56acb663c79bdd0f8a12aec041c8bb6f7f2c00e7",
-               "bytes_per_launch": 7.774e8}   # FETCH 5.719e8 + WRITE 2.055e8 (pmc_trsm_gemm_chamber10_mixed)
+               "sha256": "ffc8e21b0c89a99fcebb9b751b980d35008a214de339184b882165bd447c6645",
+               "bytes_per_launch": 9.145e10}   # FETCH 7.903e10 + WRITE 1.242e10 (pmc_row_sweep_chamber10_mixed)
 
 
 def measured_traffic(family: str):

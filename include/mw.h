@@ -442,8 +442,9 @@ mw_status mw_host_topology(const mw_mesh *mesh, int64_t *n, int64_t *nnz, int64_
  * sizes, n_faces [n_sub] faces carrying a boundary or transmission term
  * (NULL to skip), and concatenated over subdomains (NULL to skip): sub_dof
  * [sum n_loc] global unknown of each local one (R_i), D [sum n_loc] the
- * partition-of-unity weights.  Within a subdomain the unknowns with D = 0
- * come first (ascending global number), then the others (ascending). */
+ * partition-of-unity weights.  Within a subdomain the unknowns are in the
+ * order of the local matrix and its factors: reverse Cuthill-McKee on the
+ * graph of B_i (two unknowns coupled when they share a tetrahedron). */
 mw_status mw_host_decomposition(const mw_mesh *mesh, const int32_t *tet_part, int32_t n_sub,
                                 int32_t overlap, int32_t *n_loc, int64_t *n_faces, int32_t *sub_dof,
                                 double *D);
