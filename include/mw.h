@@ -66,6 +66,8 @@ typedef enum { MW_C128 = 0, MW_C64 = 1 } mw_precision;
  * L D L^T when every tetrahedron is lossy (Im eps_r < 0), which makes the
  * imaginary part of every B_i positive definite, so no pivot can vanish. */
 typedef enum { MW_FACTOR_AUTO = 0, MW_FACTOR_LU = 1, MW_FACTOR_LDLT = 2 } mw_factorization;
+/* Form of the subdomain triangular solves (mw_set_solve_form). */
+typedef enum { MW_SOLVE_AUTO = 0, MW_SOLVE_RECURSIVE = 1, MW_SOLVE_ROWS = 2 } mw_solve_form;
 /* Coarse space of the two-level preconditioner (mw_set_coarse_space). */
 typedef enum { MW_COARSE_NONE = 0, MW_COARSE_CONST = 1 } mw_coarse_space;
 
@@ -226,6 +228,18 @@ mw_status mw_set_coarse_space(mw_problem *p, int32_t kind);
  * (default MW_FACTOR_AUTO).  MW_FACTOR_LDLT on matrices whose pivots can
  * vanish may end in MW_ESINGULAR. */
 mw_status mw_set_factorization(mw_problem *p, int32_t kind);
+/* How the factors are applied, B_i^-1 = U_i^-1 L_i^-1 (the subdomain solves
+ * of equation (ORAS), Section 3).  MW_SOLVE_ROWS: after factoring, every
+ * 64-row block keeps its off-diagonal rows multiplied by its inverted
+ * diagonal block, and each subdomain's forward and backward sweeps run as
+ * one product per block inside one workgroup per (subdomain, column tile),
+ * all subdomains in one launch; MW_SOLVE_RECURSIVE: recursive blocked
+ * triangular solves whose products spread every subdomain over many
+ * workgroups.  MW_SOLVE_AUTO (default): ROWS when n_sub >= 512 (enough
+ * independent sweeps to fill the device), else RECURSIVE.  Both give the same
+ * operator; results differ by rounding only.  Takes effect at the next
+ * mw_factor_subdomains.  MW_EINVAL for an unknown form. */
+mw_status mw_set_solve_form(mw_problem *p, int32_t form);
 /* Z = M^-1 V for nrhs columns (device n x nrhs). */
 mw_status mw_apply_preconditioner(mw_problem *p, int32_t nrhs, const void *V, void *Z);
 

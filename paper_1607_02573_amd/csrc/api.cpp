@@ -158,6 +158,7 @@ struct mw_problem {
   DevBuf F;
   int prec = -1;
   int factor_kind = MW_FACTOR_AUTO;   // requested
+  int solve_form = MW_SOLVE_AUTO;      // requested (mw_set_solve_form)
   int factorization = 0;              // used by the current factors (MW_FACTOR_LU / MW_FACTOR_LDLT)
   bool factors_valid = false;
   // factor storage of F: banded (L D L^T, no interchanges) or dense (LU)
@@ -1398,6 +1399,15 @@ mw_status mw_set_factorization(mw_problem* p, int32_t kind) {
   });
 }
 
+mw_status mw_set_solve_form(mw_problem* p, int32_t form) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(form == MW_SOLVE_AUTO || form == MW_SOLVE_RECURSIVE || form == MW_SOLVE_ROWS, MW_EINVAL,
+             "unknown solve form");
+    p->solve_form = form;
+  });
+}
+
 mw_status mw_update_eps(mw_problem* p, const void* eps_dev) {
   return guard([&] {
     check_prob(p);
@@ -1599,6 +1609,7 @@ mw_status mw_factor_subdomains(mw_problem* p, int32_t n_sub, int32_t overlap, mw
     set_layout(p, sym);
     p->prec = prec;
     p->factorization = sym ? MW_FACTOR_LDLT : MW_FACTOR_LU;
+    p->dd.rows = p->solve_form == MW_SOLVE_ROWS || (p->solve_form == MW_SOLVE_AUTO && p->dd.nsub >= 512);
     launch_zero_bytes(p->dd.info, (int64_t)p->dd.nsub * 4, st);
     if (prec == MW_C64) {
       launch_fill_local<float2>(p->dm, p->dd, p->E.as<double2>(), p->eps.as<double2>(), p->k0, p->F.as<float2>(), st);

@@ -1644,11 +1644,11 @@ static void kt_account(const DeviceDecomp& d, int fam, hipStream_t st, F&& per_s
 }
 static inline double clampd(double v) { return v > 0 ? v : 0; }
 
-// Batches of more than one subdomain take the block-row solves (their
-// factors carry the scaled off-diagonal rows); a single matrix (the coarse
-// operator) keeps the recursive solves, whose updates spread one matrix
-// over many workgroups.
-static inline bool row_form(const DeviceDecomp& d) { return d.nsub > 1; }
+// Block-row solves when the decomposition asks for them (its factors then
+// carry the scaled off-diagonal rows), else the recursive solves, whose
+// updates spread each matrix over many workgroups (few subdomains, the
+// single coarse matrix).
+static inline bool row_form(const DeviceDecomp& d) { return d.rows; }
 
 template <class C>
 void lu_factor_batched(const DeviceDecomp& d, C* F, hipStream_t st, bool sym) {

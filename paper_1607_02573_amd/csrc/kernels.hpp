@@ -88,6 +88,7 @@ struct DeviceDecomp {
   const int32_t* row_lo = nullptr;   // [nsub] first row (multiple of 64) the backward solve must produce
   const int32_t* h_row_lo = nullptr; // host copy
   const int32_t* order = nullptr;    // [nsub] subdomains by decreasing n_pad (block-row solves)
+  bool rows = false;                 // factors in block-row form (scaled off-diagonal rows)
   // envelope of the factors per 32-row group g of every subdomain (entry
   // i * env_stride + g, env_stride = max_pad / 32), written by the
   // factorisation: x = first column left of the group's 64-wide diagonal

@@ -159,6 +159,12 @@ class Problem:
         k = {"auto": B.MW_FACTOR_AUTO, "lu": B.MW_FACTOR_LU, "ldlt": B.MW_FACTOR_LDLT}[kind]
         check(lib().mw_set_factorization(self.h, k))
 
+    def set_solve_form(self, form: str):
+        """'auto' (block rows for 512 subdomains or more), 'recursive' or 'rows';
+        used by the next factor()."""
+        f = {"auto": B.MW_SOLVE_AUTO, "recursive": B.MW_SOLVE_RECURSIVE, "rows": B.MW_SOLVE_ROWS}[form]
+        check(lib().mw_set_solve_form(self.h, f))
+
     def factor(self, part, n_sub: int, overlap: int = 1, precision: str = "c128"):
         """Fill and factor the B_i; part = None takes the library's own
         partition (recursive coordinate bisection of the centroids)."""

@@ -26,11 +26,14 @@ def chamber():
     ctx.close()
 
 
+@pytest.mark.parametrize("form", ["recursive", "rows"])
 @pytest.mark.parametrize("prec,tol", [("c128", 1e-12), ("c64", 2e-5)])
-def test_ldlt_and_lu_give_the_same_preconditioner(chamber, prec, tol):
-    """M^-1 V with either factorisation equals the oracle's ORAS apply
-    (sparse LU of every B_i) to the factor precision."""
+def test_ldlt_and_lu_give_the_same_preconditioner(chamber, prec, tol, form):
+    """M^-1 V with either factorisation, and either form of the triangular
+    solves, equals the oracle's ORAS apply (sparse LU of every B_i) to the
+    factor precision."""
     w, fp, P = chamber
+    P.set_solve_form(form)
     subs = dd.decompose(fp, w.part, 1)
     rng = np.random.default_rng(11)
     V = rng.normal(size=(fp.n, 40)) + 1j * rng.normal(size=(fp.n, 40))
@@ -45,6 +48,7 @@ def test_ldlt_and_lu_give_the_same_preconditioner(chamber, prec, tol):
         err = np.linalg.norm(out[kind] - Zo) / np.linalg.norm(Zo)
         assert err <= tol, (kind, err)
     P.set_factorization("auto")
+    P.set_solve_form("auto")
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])

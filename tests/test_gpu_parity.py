@@ -87,11 +87,26 @@ def test_port_rhs_and_norms(chamber_small):
     assert np.abs(Bg - Bo).max() <= 1e-13 * np.abs(Bo).max()
 
 
+@pytest.fixture(params=["recursive", "rows"])
+def form(request):
+    """Both forms of the subdomain triangular solves (the automatic choice
+    takes the recursive one at these sizes); back to automatic afterwards."""
+    return request.param
+
+
+def _factor(P, w, prec, form):
+    P.set_solve_form(form)
+    try:
+        P.factor(w.part, w.n_sub, 1, prec)
+    finally:
+        P.set_solve_form("auto")
+
+
 @pytest.mark.parametrize("prec,tol", [("c128", 1e-11), ("c64", 1e-5)])
 @pytest.mark.parametrize("which", ["cube", "chamber_small"])
-def test_preconditioner_matches_oracle(which, prec, tol, request):
+def test_preconditioner_matches_oracle(which, prec, tol, form, request):
     w, fp, P = request.getfixturevalue(which)
-    P.factor(w.part, w.n_sub, 1, prec)
+    _factor(P, w, prec, form)
     subs = dd.decompose(fp, w.part, 1)
     rng = np.random.default_rng(11)
     V = rng.normal(size=(P.n, 5)) + 1j * rng.normal(size=(P.n, 5))
@@ -101,9 +116,9 @@ def test_preconditioner_matches_oracle(which, prec, tol, request):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-def test_cube_solve_matches_direct(cube, prec):
+def test_cube_solve_matches_direct(cube, prec, form):
     w, fp, P = cube
-    P.factor(w.part, w.n_sub, 1, prec)
+    _factor(P, w, prec, form)
     Bo = fem.rhs_dipoles(fp, w.dipoles)
     X, info = P.solve(torch.from_numpy(Bo).cuda(), tol=1e-10, restart=30)
     U = spla.splu(fp.A.tocsc()).solve(Bo)
@@ -118,9 +133,9 @@ def test_cube_solve_matches_direct(cube, prec):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-def test_chamber_solve_and_s_matrix(chamber_small, prec):
+def test_chamber_solve_and_s_matrix(chamber_small, prec, form):
     w, fp, P = chamber_small
-    P.factor(w.part, w.n_sub, 1, prec)
+    _factor(P, w, prec, form)
     Bg = P.rhs_ports(w.tx)
     X, info = P.solve(Bg, tol=1e-10, restart=30)
     lu = spla.splu(fp.A.tocsc())
@@ -251,10 +266,10 @@ def test_error_paths(ctx):
 
 
 @pytest.mark.parametrize("prec,tol", [("c128", 1e-11), ("c64", 1e-5)])
-def test_preconditioner_column_counts(chamber_small, prec, tol):
+def test_preconditioner_column_counts(chamber_small, prec, tol, form):
     """Every tile width of the batched triangular solves (1 .. >160 columns)."""
     w, fp, P = chamber_small
-    P.factor(w.part, w.n_sub, 1, prec)
+    _factor(P, w, prec, form)
     subs = dd.decompose(fp, w.part, 1)
     rng = np.random.default_rng(5)
     for nc in (1, 3, 33, 65, 97, 130, 170):
