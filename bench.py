@@ -59,6 +59,9 @@ def measured_traffic(family: str):
     return t["bytes_per_launch"]
 
 
+MIXED_DTYPE = "c64 factors/TRSM (FP32 MFMA), c64 Krylov basis, f64 GMRES arithmetic and residuals"
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -251,7 +254,7 @@ def serve_main(args):
         "rhs_columns": summ["rhs_columns"], "rhs_per_s": summ["rhs_per_s"], "makespan_s": t_wall,
         "failed": summ["failed"], "max_relres": summ["max_relres"],
         "factorisations": facts, "evictions": srv.evictions, "setup_s": srv.t_setup,
-        "dtype": "c64 factors/TRSM (FP32 MFMA) + f64 GMRES", "data": "synthetic",
+        "dtype": MIXED_DTYPE, "data": "synthetic",
         "config": {"workload": "chamber serving menu: 0.3125/0.5/0.75/1 GHz meshes x 2 permittivity versions, "
                                "160 ports, ceil(edges/1000) subdomains; Poisson arrivals",
                    "requests": len(reqs), "rate_per_s": args.serve_rate, "tol": args.tol,
@@ -306,7 +309,7 @@ def invert_main(args):
         "iterations": len(h.J) - 1, "evaluations": h.evaluations, "J": h.J, "seconds": h.seconds,
         "rhs_solves_per_s": h.solve_columns / h.seconds,
         "gmres_iters_per_evaluation": h.iters, "recycle": inv.recycle,
-        "dtype": "c64 factors/TRSM (FP32 MFMA) + f64 GMRES", "data": "synthetic",
+        "dtype": MIXED_DTYPE, "data": "synthetic",
         "config": {"workload": f"{w.name}: {P.n} unknowns, {len(tx)} ports, {w.n_sub} subdomains; vertex "
                                f"permittivity ({w.mesh.xyz.shape[0]} vertices, "
                                f"{'exact P1 mass term' if args.p1 else 'tetrahedron means'}), defJ2 misfit, "
@@ -333,6 +336,8 @@ def main():
     ap.add_argument("--block", type=int, default=0, choices=(0, 32),
                     help="0: pseudo-block GMRES; 32: block GMRES with blocks of 32 right-hand sides")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--basis", choices=("auto", "fp64"), default="auto",
+                    help="Krylov basis of the mixed-precision solves: complex FP32 (auto) or complex FP64")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain elementwise copy (torch.neg) of this many MiB, the known-size "
                          "kernel that calibrates rocprofv3's FETCH_SIZE / WRITE_SIZE counters")
@@ -410,6 +415,7 @@ def main():
     t_topo = time.perf_counter() - t0
     eps_dev = torch.from_numpy(np.ascontiguousarray(w.eps)).cuda()
     log(f"[bench] n={P.n} nnz={P.nnz} topology+assembly {t_topo:.2f} s; first factorisation (decomposition)")
+    P.set_krylov_basis(args.basis)
     P.factor(w.part, w.n_sub, 1, "c64")
     inf = P.info()
     log(f"[bench] decomposition {inf.t_decompose:.2f} s, n_sub={inf.n_sub}, sum n_i={inf.sum_ni}, max n_i={inf.max_ni}")
@@ -568,7 +574,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 factors/TRSM (FP32 MFMA) + f64 GMRES",
+        "dtype": MIXED_DTYPE if args.basis == "auto" else MIXED_DTYPE.replace("c64 Krylov", "f64 Krylov"),
         "data": "synthetic",
         "config": {"workload": f"{w.name}: n={P.n} unknowns, {w.mesh.nt} tets, {nrhs} port RHS, "
                                f"{w.n_sub} subdomains overlap 1, "

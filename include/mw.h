@@ -68,6 +68,8 @@ typedef enum { MW_C128 = 0, MW_C64 = 1 } mw_precision;
 typedef enum { MW_FACTOR_AUTO = 0, MW_FACTOR_LU = 1, MW_FACTOR_LDLT = 2 } mw_factorization;
 /* Form of the subdomain triangular solves (mw_set_solve_form). */
 typedef enum { MW_SOLVE_AUTO = 0, MW_SOLVE_RECURSIVE = 1, MW_SOLVE_ROWS = 2 } mw_solve_form;
+/* Precision of the GMRES Krylov basis (mw_set_krylov_basis). */
+typedef enum { MW_BASIS_AUTO = 0, MW_BASIS_FP64 = 1 } mw_krylov_basis;
 /* Coarse space of the two-level preconditioner (mw_set_coarse_space). */
 typedef enum { MW_COARSE_NONE = 0, MW_COARSE_CONST = 1 } mw_coarse_space;
 
@@ -240,6 +242,18 @@ mw_status mw_set_factorization(mw_problem *p, int32_t kind);
  * operator; results differ by rounding only.  Takes effect at the next
  * mw_factor_subdomains.  MW_EINVAL for an unknown form. */
 mw_status mw_set_solve_form(mw_problem *p, int32_t form);
+/* Storage of the Arnoldi basis of pseudo-block GMRES (Section 6; mixed
+ * precision is not in the paper).  MW_BASIS_AUTO (default): complex FP32
+ * when the subdomain factors are FP32, complex FP64 otherwise;
+ * MW_BASIS_FP64: always complex FP64.  Every product, dot product, the
+ * Hessenberg matrix, the iterate and the true residual stay FP64; an FP32
+ * basis only rounds the stored vectors (relative 6e-8), which perturbs the
+ * Arnoldi relation of a restart cycle by about that much of the cycle's
+ * starting residual, while the stopping test is always taken on the true
+ * FP64 residual at the restart.  It halves the bytes of Gram-Schmidt.  Block
+ * GMRES keeps an FP64 basis.  Takes effect at the next solve.  MW_EINVAL for
+ * an unknown kind. */
+mw_status mw_set_krylov_basis(mw_problem *p, int32_t kind);
 /* Z = M^-1 V for nrhs columns (device n x nrhs). */
 mw_status mw_apply_preconditioner(mw_problem *p, int32_t nrhs, const void *V, void *Z);
 

@@ -19,6 +19,7 @@ MW_OK, MW_EINVAL, MW_ENOMEM, MW_ESINGULAR, MW_ENOCONV, MW_ENUMERIC, MW_EDEVICE =
 MW_C128, MW_C64 = 0, 1
 MW_FACTOR_AUTO, MW_FACTOR_LU, MW_FACTOR_LDLT = 0, 1, 2
 MW_SOLVE_AUTO, MW_SOLVE_RECURSIVE, MW_SOLVE_ROWS = 0, 1, 2
+MW_BASIS_AUTO, MW_BASIS_FP64 = 0, 1
 MW_COARSE_NONE, MW_COARSE_CONST = 0, 1
 STATUS_NAMES = {0: "MW_OK", -1: "MW_EINVAL", -2: "MW_ENOMEM", -3: "MW_ESINGULAR", -4: "MW_ENOCONV",
                 -5: "MW_ENUMERIC", -6: "MW_EDEVICE"}
@@ -136,6 +137,7 @@ _SIGS = {
     "mw_host_factor_storage": [C.POINTER(mw_mesh), _P, _I, _I, _I, _P, _P, _P, _P],
     "mw_set_factorization": [_P, _I],
     "mw_set_solve_form": [_P, _I],
+    "mw_set_krylov_basis": [_P, _I],
     "mw_update_eps_vertex": [_P, _P],
     "mw_gradient_vertex": [_P, _I, _P, _P, _P],
     "mw_set_coarse_space": [_P, _I],

@@ -13,6 +13,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <type_traits>
 #include <mutex>
 #include <numeric>
 
@@ -110,7 +111,7 @@ struct Work {
 // batch), grown on demand.
 struct GmresWork {
   Work V, X, B, Z, Y, H, Hr, cs, sn, g, y, h1, h2, hp, cf, nu, ee, part, npart, vec, ints, tmp, w_idx;
-  Work cq, cw, cy;            // two-level: Q v, (spare), coarse vector
+  Work cq, cw, cy;            // two-level: Q v, FP64 copy of an FP32 basis vector, coarse vector
   hipStream_t st = nullptr;   // the stream this driver's work runs on
   std::array<Work*, 26> all() {
     return {&V, &X, &B, &Z, &Y, &H, &Hr, &cs, &sn, &g, &y, &h1, &h2, &hp, &cf, &nu, &ee, &part, &npart, &vec, &ints,
@@ -159,6 +160,7 @@ struct mw_problem {
   int prec = -1;
   int factor_kind = MW_FACTOR_AUTO;   // requested
   int solve_form = MW_SOLVE_AUTO;      // requested (mw_set_solve_form)
+  int basis = MW_BASIS_AUTO;           // Krylov basis precision (mw_set_krylov_basis)
   int factorization = 0;              // used by the current factors (MW_FACTOR_LU / MW_FACTOR_LDLT)
   bool factors_valid = false;
   // factor storage of F: banded (L D L^T, no interchanges) or dense (LU)
@@ -468,19 +470,24 @@ void upload_decomp(mw_problem* p) {
 }
 
 // Z = M^-1 V (n x nc, leading dimension ld), local workspace W.Y
-void one_level(mw_problem* p, GmresWork& W, const double2* V, double2* Z, int nc, int64_t ld) {
+// V complex FP64, or complex FP32 (a basis vector of the mixed-precision
+// GMRES, with FP32 factors only)
+template <class VT>
+void one_level(mw_problem* p, GmresWork& W, const VT* V, double2* Z, int nc, int64_t ld) {
   mw_ctx* c = p->ctx;
   int64_t n = p->T.n();
   if (p->prec == MW_C64) {
     float2* Y = (float2*)W.Y.get(c, p->dd.sum_pad * nc * 8);
-    launch_restrict<float2>(p->dd, V, ld, nc, Y, nc, W.st);
+    launch_restrict<float2, VT>(p->dd, V, ld, nc, Y, nc, W.st);
     lu_solve_batched<float2>(p->dd, p->F.as<float2>(), Y, nc, nc, W.st);
     launch_prolong<float2>(p->dd, n, Y, nc, nc, Z, ld, W.st);
-  } else {
+  } else if constexpr (std::is_same<VT, double2>::value) {
     double2* Y = (double2*)W.Y.get(c, p->dd.sum_pad * nc * 16);
     launch_restrict<double2>(p->dd, V, ld, nc, Y, nc, W.st);
     lu_solve_batched<double2>(p->dd, p->F.as<double2>(), Y, nc, nc, W.st);
     launch_prolong<double2>(p->dd, n, Y, nc, nc, Z, ld, W.st);
+  } else {
+    MW_CHECK(false, MW_EINVAL, "an FP32 Krylov basis needs FP32 subdomain factors");
   }
 }
 
@@ -498,7 +505,7 @@ void two_level(mw_problem* p, GmresWork& W, const double2* V, double2* Z, int nc
   lu_solve_batched<C>(p->cdd, p->Fc.as<C>(), Yc, nc, nc, W.st);
   launch_coarse_prolong<C>(p->dd, p->cz, n, Yc, nc, nc, q, ld, W.st);
   launch_spmm(p->dm, p->val.as<double2>(), q, ld, Z, ld, nc, V, ld, W.st);
-  one_level(p, W, Z, Z, nc, ld);
+  one_level<double2>(p, W, Z, Z, nc, ld);
   launch_axpy_cols(Z, q, n, ld, nc, W.st);
 }
 
@@ -536,12 +543,24 @@ void set_layout(mw_problem* p, bool banded) {
 void apply_prec(mw_problem* p, GmresWork& W, const double2* V, double2* Z, int nc, int64_t ld) {
   MW_CHECK(p->factors_valid, MW_EINVAL, "no valid subdomain factors: call mw_factor_subdomains");
   if (!p->coarse_active) {
-    one_level(p, W, V, Z, nc, ld);
+    one_level<double2>(p, W, V, Z, nc, ld);
   } else if (p->prec == MW_C64) {
     two_level<float2>(p, W, V, Z, nc, ld);
   } else {
     two_level<double2>(p, W, V, Z, nc, ld);
   }
+}
+// the same for an FP32 basis vector: the one-level restriction reads it
+// directly; the two-level correction works on an FP64 copy
+void apply_prec(mw_problem* p, GmresWork& W, const float2* V, double2* Z, int nc, int64_t ld) {
+  MW_CHECK(p->factors_valid, MW_EINVAL, "no valid subdomain factors: call mw_factor_subdomains");
+  if (!p->coarse_active) {
+    one_level<float2>(p, W, V, Z, nc, ld);
+    return;
+  }
+  double2* Vd = (double2*)W.cw.get(p->ctx, p->T.n() * ld * 16);
+  launch_widen(V, Vd, p->T.n() * ld, W.st);
+  apply_prec(p, W, (const double2*)Vd, Z, nc, ld);
 }
 
 // Structures of the coarse space for the current decomposition: edge vector
@@ -690,13 +709,19 @@ void colnorm2(mw_problem* p, GmresWork& W, const double2* V, int64_t ld, int nc,
   launch_sum_chunks(part, nch, nc, out, W.st);
 }
 
+// whether GMRES keeps its Krylov basis in complex FP32: with FP32 factors,
+// unless an FP64 basis was asked for
+bool basis_fp32(mw_problem* p) { return p->prec == MW_C64 && p->basis == MW_BASIS_AUTO; }
+
 // device bytes one more right-hand side column costs a GMRES(m) driver:
 // basis (m+1), X, B, Z, update, local vectors, reduction partials
-int64_t gmres_bytes_per_col(mw_problem* p, int m) {
+int64_t gmres_bytes_per_col(mw_problem* p, int m, bool block) {
   int64_t esz = p->prec == MW_C64 ? 8 : 16;
-  int64_t big = (int64_t)(m + 5) * p->T.n() * 16 + p->dd.sum_pad * esz + reduce_chunks(p->T.n()) * (2 * m + 3) * 16;
-  if (p->coarse_kind != MW_COARSE_NONE)   // two-level: Q v and the coarse vector
-    big += p->T.n() * 16 + (int64_t)round_up(3 * (int64_t)std::max(p->D.nsub, 1), 64) * esz;
+  const int64_t bsz = (!block && basis_fp32(p)) ? 8 : 16;   // block GMRES keeps an FP64 basis
+  int64_t big = (int64_t)(m + 1) * p->T.n() * bsz + 4 * p->T.n() * 16 + p->dd.sum_pad * esz +
+                reduce_chunks(p->T.n()) * (2 * m + 3) * 16;
+  if (p->coarse_kind != MW_COARSE_NONE)   // two-level: Q v, the coarse vector, an FP64 copy of an FP32 basis vector
+    big += p->T.n() * 16 * (bsz == 8 ? 2 : 1) + (int64_t)round_up(3 * (int64_t)std::max(p->D.nsub, 1), 64) * esz;
   // Hessenberg (raw and rotated), rotations, g, y, dot sums, provisional
   // column, coefficients, norms, flags
   int64_t small = 2 * (int64_t)(m + 1) * m * 16 + (int64_t)m * 24 + 5 * (int64_t)(m + 1) * 16 + 2 * (int64_t)m * 16 +
@@ -728,6 +753,7 @@ void true_residual(mw_problem* p, GmresWork& W, const double2* B, const double2*
 // tol (relative to ||b||) or its iteration count reaches maxit; the cycle
 // ends when every column has stopped or after m steps, then x += M^-1 V y.
 // iters[k] counts the Arnoldi steps of column k.
+template <class BT>
 void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, const mw_solve_opts& o, double* vec,
                  const std::vector<double>& rnorm, std::vector<int32_t>& hact, std::vector<int32_t>& iters) {
   mw_ctx* c = p->ctx;
@@ -736,7 +762,7 @@ void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, co
   const int m = o.restart;
   const int64_t ld = nc;
   const int64_t vstride = n * ld;
-  double2* V = (double2*)W.V.get(c, (int64_t)(m + 1) * vstride * 16);
+  BT* V = (BT*)W.V.get(c, (int64_t)(m + 1) * vstride * (int64_t)sizeof(BT));
   double2* T = (double2*)W.tmp.get(c, vstride * 16);
   double2* H = (double2*)W.H.get(c, (int64_t)(m + 1) * m * nc * 16);
   double2* Hraw = (double2*)W.Hr.get(c, (int64_t)(m + 1) * m * nc * 16);
@@ -782,7 +808,7 @@ void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, co
   // operator, the column already finished.
   bool finish_only = false;
   for (int j = 0; j <= m; ++j) {
-    double2* Vj = V + (int64_t)j * vstride;
+    BT* Vj = V + (int64_t)j * vstride;
     bool more = j < m && !finish_only;   // step m only finishes column m-1
     for (int pass = 0; pass < 2; ++pass) {
       if (more) {
@@ -886,7 +912,8 @@ ChunkResult gmres_chunk(mw_problem* p, GmresWork& W, const double2* Bsrc, int64_
     }
     if (res.numeric || nact == 0) break;
     res.cycles++;
-    gmres_cycle(p, W, X, Z, nc, o, vec, rnorm, hact, iters);
+    if (basis_fp32(p)) gmres_cycle<float2>(p, W, X, Z, nc, o, vec, rnorm, hact, iters);
+    else gmres_cycle<double2>(p, W, X, Z, nc, o, vec, rnorm, hact, iters);
   }
   launch_copy_cols(X, ld, Xdst, ldx_dst, n, nc, st);
   MW_HIP(hipStreamSynchronize(st));
@@ -1399,6 +1426,14 @@ mw_status mw_set_factorization(mw_problem* p, int32_t kind) {
   });
 }
 
+mw_status mw_set_krylov_basis(mw_problem* p, int32_t kind) {
+  return guard([&] {
+    check_prob(p);
+    MW_CHECK(kind == MW_BASIS_AUTO || kind == MW_BASIS_FP64, MW_EINVAL, "unknown Krylov basis kind");
+    p->basis = kind;
+  });
+}
+
 mw_status mw_set_solve_form(mw_problem* p, int32_t form) {
   return guard([&] {
     check_prob(p);
@@ -1706,7 +1741,7 @@ mw_status mw_apply_preconditioner_noalloc(mw_problem* p, int32_t nrhs, const voi
 
 static int solve_chunk_cols(mw_problem* p, int nrhs, int m, bool block) {
   mw_ctx* c = p->ctx;
-  int64_t per = gmres_bytes_per_col(p, m);
+  int64_t per = gmres_bytes_per_col(p, m, block);
   int64_t held = p->ws.held();
   int64_t avail = c->budget - c->used.load() + held;
   // block mode: reduction partials of the block Gram-Schmidt, bounded by
@@ -2085,7 +2120,8 @@ mw_status mw_batch_cycle(mw_batch* b, int32_t* n_active, int32_t* n_finished) {
       rnorm[k] = r;
       hact[k] = column_continues(hb[k], relres[k], iters[k], r, b->o) ? 1 : 0;
     }
-    gmres_cycle(p, W, X, Z, na, b->o, vec, rnorm, hact, iters);
+    if (basis_fp32(p)) gmres_cycle<float2>(p, W, X, Z, na, b->o, vec, rnorm, hact, iters);
+    else gmres_cycle<double2>(p, W, X, Z, na, b->o, vec, rnorm, hact, iters);
     b->cycles++;
     // restart point: the true residual decides which columns leave
     true_residual(p, W, Bc, X, Z, na, vec + na, hr);
@@ -2169,7 +2205,7 @@ mw_status mw_batch_get_info(mw_batch* b, mw_batch_info* info) {
     info->cycles = b->cycles;
     info->slot_bytes = (int64_t)(b->Bs.bytes + b->Xs.bytes + b->idx.bytes);
     info->work_bytes = b->W.held();
-    info->bytes_per_col = gmres_bytes_per_col(b->p, b->o.restart);
+    info->bytes_per_col = gmres_bytes_per_col(b->p, b->o.restart, false);
   });
 }
 

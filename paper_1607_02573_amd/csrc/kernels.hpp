@@ -175,8 +175,8 @@ void lu_solve_batched(const DeviceDecomp& d, const C* F, C* Y, int ncols, int64_
 // ---- Krylov and vector kernels (krylov.hip)
 void launch_spmm(const DeviceMesh& m, const double2* val, const double2* X, int64_t ldx, double2* Y,
                  int64_t ldy, int ncols, const double2* Bsub, int64_t ldb, hipStream_t st);
-template <class C>
-void launch_restrict(const DeviceDecomp& d, const double2* V, int64_t ldv, int ncols, C* Y, int64_t ldy,
+template <class C, class VT = double2>
+void launch_restrict(const DeviceDecomp& d, const VT* V, int64_t ldv, int ncols, C* Y, int64_t ldy,
                      hipStream_t st);
 template <class C>
 void launch_prolong(const DeviceDecomp& d, int64_t n, const C* Y, int64_t ldy, int ncols, double2* Z,
@@ -185,7 +185,8 @@ void launch_prolong(const DeviceDecomp& d, int64_t n, const C* Y, int64_t ldy, i
 int64_t reduce_chunks(int64_t n);
 void launch_colnorm2_partial(const double2* V, int64_t n, int64_t ld, int ncols, double* part, hipStream_t st);
 void launch_sum_chunks(const double* part, int64_t nchunk, int64_t width, double* out, hipStream_t st);
-void launch_dots_partial(const double2* V, int64_t vstride, int kcount, const double2* w1, const double2* w2,
+template <class B>
+void launch_dots_partial(const B* V, int64_t vstride, int kcount, const B* w1, const double2* w2,
                          int64_t n, int64_t ld, int ncols, const int32_t* act, double2* part1, double2* part2,
                          hipStream_t st);
 void launch_sum_chunks_c(const double2* part, int64_t nchunk, int64_t width, double2* out, hipStream_t st);
@@ -196,17 +197,23 @@ void launch_dgs_step(int j, int m, bool fin, int ncols, const double2* P1, const
 void launch_dgs_trial(int j, int m, int ncols, const double2* hprov, const double* beta2, const double* cs,
                       const double2* sn, const double2* g, const int32_t* act, const double* bnorm, double tol,
                       int32_t* done, hipStream_t st);
-void launch_dgs_update(double2* V, int64_t vstride, int j, const double2* coef, const double* nu, const double2* e,
+template <class B>
+void launch_dgs_update(B* V, int64_t vstride, int j, const double2* coef, const double* nu, const double2* e,
                        const double2* T, int64_t n, int64_t ld, int ncols, const int32_t* act, double* norm_part,
                        hipStream_t st);
-void launch_scale_cols(double2* w, int64_t n, int64_t ld, int ncols, const double* nrm, const int32_t* act,
+template <class B>
+void launch_scale_cols(B* w, int64_t n, int64_t ld, int ncols, const double* nrm, const int32_t* act,
                        hipStream_t st);
 void launch_backsolve(int m, int ncols, const double2* H, const double2* g, const int32_t* kdim, double2* y,
                       hipStream_t st);
-void launch_combine(const double2* V, int64_t vstride, int m, const double2* y, const int32_t* kdim,
+template <class B>
+void launch_combine(const B* V, int64_t vstride, int m, const double2* y, const int32_t* kdim,
                     double2* u, int64_t n, int64_t ld, int ncols, hipStream_t st);
 void launch_axpy_cols(double2* x, const double2* z, int64_t n, int64_t ld, int ncols, hipStream_t st);
-void launch_start_cycle(const double2* r, double2* v0, int64_t n, int64_t ld, int ncols, const double* rn2,
+// dst[i] = src[i] widened to complex FP64
+void launch_widen(const float2* src, double2* dst, int64_t count, hipStream_t st);
+template <class B>
+void launch_start_cycle(const double2* r, B* v0, int64_t n, int64_t ld, int ncols, const double* rn2,
                         const int32_t* act, hipStream_t st);
 void launch_copy_cols(const double2* src, int64_t lds, double2* dst, int64_t ldd, int64_t n, int ncols,
                       hipStream_t st);

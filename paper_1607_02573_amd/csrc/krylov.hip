@@ -215,8 +215,8 @@ void launch_spmm(const DeviceMesh& m, const double2* val, const double2* X, int6
 
 // ---------------------------------------------------------------- K4 / K5
 // restriction: Y[l][c] = V[ridx[l]][c] (cast), zero on padding rows
-template <class C>
-__global__ void k_restrict(int64_t nloc, const int32_t* __restrict__ ridx, const double2* __restrict__ V,
+template <class C, class VT>
+__global__ void k_restrict(int64_t nloc, const int32_t* __restrict__ ridx, const VT* __restrict__ V,
                            int64_t ldv, int ncols, C* __restrict__ Y, int64_t ldy) {
   int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t l = id / ncols;
@@ -226,15 +226,15 @@ __global__ void k_restrict(int64_t nloc, const int32_t* __restrict__ ridx, const
   C y;
   y.x = 0; y.y = 0;
   if (g >= 0) {
-    double2 v = V[(int64_t)g * ldv + c];
+    VT v = V[(int64_t)g * ldv + c];
     y.x = v.x; y.y = v.y;
   }
   Y[l * ldy + c] = y;
 }
 
 // the same for an even number of columns, two adjacent columns per thread
-template <class C>
-__global__ void k_restrict2(int64_t nloc, const int32_t* __restrict__ ridx, const double2* __restrict__ V,
+template <class C, class VT>
+__global__ void k_restrict2(int64_t nloc, const int32_t* __restrict__ ridx, const VT* __restrict__ V,
                             int64_t ldv, int npairs, C* __restrict__ Y, int64_t ldy) {
   int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t l = id / npairs;
@@ -244,7 +244,7 @@ __global__ void k_restrict2(int64_t nloc, const int32_t* __restrict__ ridx, cons
   C y0, y1;
   y0.x = 0; y0.y = 0; y1.x = 0; y1.y = 0;
   if (g >= 0) {
-    double2 v0 = V[(int64_t)g * ldv + c], v1 = V[(int64_t)g * ldv + c + 1];
+    VT v0 = V[(int64_t)g * ldv + c], v1 = V[(int64_t)g * ldv + c + 1];
     y0.x = v0.x; y0.y = v0.y;
     y1.x = v1.x; y1.y = v1.y;
   }
@@ -252,17 +252,17 @@ __global__ void k_restrict2(int64_t nloc, const int32_t* __restrict__ ridx, cons
   Y[l * ldy + c + 1] = y1;
 }
 
-template <class C>
-void launch_restrict(const DeviceDecomp& d, const double2* V, int64_t ldv, int ncols, C* Y, int64_t ldy,
+template <class C, class VT>
+void launch_restrict(const DeviceDecomp& d, const VT* V, int64_t ldv, int ncols, C* Y, int64_t ldy,
                      hipStream_t st) {
   if (d.sum_pad <= 0 || ncols <= 0) return;
   kt_begin(KF_RESTRICT, st);
   if (ncols % 2 == 0) {
     int64_t tot = d.sum_pad * (ncols / 2);
-    k_restrict2<C><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(d.sum_pad, d.ridx, V, ldv, ncols / 2, Y, ldy);
+    k_restrict2<C, VT><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(d.sum_pad, d.ridx, V, ldv, ncols / 2, Y, ldy);
   } else {
     int64_t tot = d.sum_pad * ncols;
-    k_restrict<C><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(d.sum_pad, d.ridx, V, ldv, ncols, Y, ldy);
+    k_restrict<C, VT><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(d.sum_pad, d.ridx, V, ldv, ncols, Y, ldy);
   }
   MW_LAUNCH_CHECK();
   if (kt_enabled()) {
@@ -271,7 +271,8 @@ void launch_restrict(const DeviceDecomp& d, const double2* V, int64_t ldv, int n
     // algorithmic bytes: every global row read once (n x 16 per column; the
     // copies of a row shared by several subdomains come from L2), the gather
     // index, and every local row written
-    kt_end(KF_RESTRICT, st, 0.0, sl * 4 + (double)d.n_glob * ncols * 16.0 + sl * ncols * (double)sizeof(C));
+    kt_end(KF_RESTRICT, st, 0.0,
+           sl * 4 + (double)d.n_glob * ncols * (double)sizeof(VT) + sl * ncols * (double)sizeof(C));
   }
 }
 
@@ -341,10 +342,12 @@ void launch_prolong(const DeviceDecomp& d, int64_t n, const C* Y, int64_t ldy, i
   }
 }
 
-template void launch_restrict<float2>(const DeviceDecomp&, const double2*, int64_t, int, float2*, int64_t,
-                                      hipStream_t);
-template void launch_restrict<double2>(const DeviceDecomp&, const double2*, int64_t, int, double2*, int64_t,
-                                       hipStream_t);
+template void launch_restrict<float2, double2>(const DeviceDecomp&, const double2*, int64_t, int, float2*, int64_t,
+                                               hipStream_t);
+template void launch_restrict<float2, float2>(const DeviceDecomp&, const float2*, int64_t, int, float2*, int64_t,
+                                              hipStream_t);
+template void launch_restrict<double2, double2>(const DeviceDecomp&, const double2*, int64_t, int, double2*,
+                                                int64_t, hipStream_t);
 template void launch_prolong<float2>(const DeviceDecomp&, int64_t, const float2*, int64_t, int, double2*, int64_t,
                                      hipStream_t);
 template void launch_prolong<double2>(const DeviceDecomp&, int64_t, const double2*, int64_t, int, double2*,
@@ -402,6 +405,14 @@ void launch_sum_chunks_c(const double2* part, int64_t nchunk, int64_t width, dou
   MW_LAUNCH_CHECK();
 }
 
+// Krylov basis elements: complex FP64 (double2) or, with FP32 subdomain
+// factors, complex FP32 (float2); every product and sum below is FP64.
+__device__ inline double2 bload(const double2& v) { return v; }
+__device__ inline double2 bload(const float2& v) { return make_double2(v.x, v.y); }
+template <class B> __device__ inline B bstore(double2 v);
+template <> __device__ inline double2 bstore<double2>(double2 v) { return v; }
+template <> __device__ inline float2 bstore<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
+
 // ---------------------------------------------------------------- K6 (CGS2)
 // part1[chunk][k][c] = sum_{rows of chunk} conj(V_k[r][c]) w1[r][c] and, if
 // w2 is given, part2 likewise with w2, for k < kcount.  A workgroup takes KG
@@ -410,8 +421,9 @@ void launch_sum_chunks_c(const double2* part, int64_t nchunk, int64_t width, dou
 // order whatever KG and the other columns are.
 constexpr int DOTS_KG = 6;
 constexpr int CGS_HK = 32;   // coefficients held in LDS up to this many (complex) per column
-__global__ void __launch_bounds__(256) k_dots_partial(const double2* __restrict__ V, int64_t vstride, int kcount,
-                                                      const double2* __restrict__ w1, const double2* __restrict__ w2,
+template <class B>
+__global__ void __launch_bounds__(256) k_dots_partial(const B* __restrict__ V, int64_t vstride, int kcount,
+                                                      const B* __restrict__ w1, const double2* __restrict__ w2,
                                                       int64_t n, int64_t ld, int ncols,
                                                       const int32_t* __restrict__ act, double2* __restrict__ part1,
                                                       double2* __restrict__ part2) {
@@ -425,37 +437,37 @@ __global__ void __launch_bounds__(256) k_dots_partial(const double2* __restrict_
 #pragma unroll
   for (int q = 0; q < DOTS_KG; ++q) acc1[q] = acc2[q] = make_double2(0.0, 0.0);
   if (c < ncols && act[c]) {
-    const double2* Vb = V + (int64_t)kb * vstride;
-    // two rows per pass (r and r + 4): twice the loads in flight; each
-    // (k, column) sum still runs over the chunk's rows in ascending order
-    for (int64_t r = r0 + rl; r < r1; r += 8) {
-      const bool two = r + 4 < r1;
-      const int64_t o0 = r * ld + c, o1 = (r + 4) * ld + c;
-      const double2 x0 = w1[o0];
-      const double2 y0 = w2 ? w2[o0] : make_double2(0.0, 0.0);
-      const double2 x1 = two ? w1[o1] : make_double2(0.0, 0.0);
-      const double2 y1 = (two && w2) ? w2[o1] : make_double2(0.0, 0.0);
-      double2 v0[DOTS_KG], v1[DOTS_KG];
+    const B* Vb = V + (int64_t)kb * vstride;
+    // two rows per pass (r and r + 4): twice the loads in flight (four rows
+    // with an FP32 basis measured slower: 815 against 404 ms per step, the
+    // registers halve the occupancy); each (k, column) sum still runs over
+    // the chunk's rows in ascending order
+    constexpr int RPD = 2;
+    for (int64_t r = r0 + rl; r < r1; r += 4 * RPD) {
+      double2 x[RPD], y[RPD], v[RPD][DOTS_KG];
+      bool live[RPD];
 #pragma unroll
-      for (int q = 0; q < DOTS_KG; ++q) {
-        const bool ok = kb + q < kcount;
-        v0[q] = ok ? Vb[(int64_t)q * vstride + o0] : make_double2(0.0, 0.0);
-        v1[q] = (ok && two) ? Vb[(int64_t)q * vstride + o1] : make_double2(0.0, 0.0);
+      for (int h = 0; h < RPD; ++h) {
+        live[h] = r + 4 * h < r1;
+        const int64_t o = (r + 4 * h) * ld + c;
+        x[h] = live[h] ? bload(w1[o]) : make_double2(0.0, 0.0);
+        y[h] = (live[h] && w2) ? w2[o] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < DOTS_KG; ++q)
+          v[h][q] = (live[h] && kb + q < kcount) ? bload(Vb[(int64_t)q * vstride + o]) : make_double2(0.0, 0.0);
       }
 #pragma unroll
-      for (int q = 0; q < DOTS_KG; ++q)
-        if (kb + q < kcount) {
-          acc1[q].x += v0[q].x * x0.x + v0[q].y * x0.y;
-          acc1[q].y += v0[q].x * x0.y - v0[q].y * x0.x;
-          acc2[q].x += v0[q].x * y0.x + v0[q].y * y0.y;
-          acc2[q].y += v0[q].x * y0.y - v0[q].y * y0.x;
-          if (two) {
-            acc1[q].x += v1[q].x * x1.x + v1[q].y * x1.y;
-            acc1[q].y += v1[q].x * x1.y - v1[q].y * x1.x;
-            acc2[q].x += v1[q].x * y1.x + v1[q].y * y1.y;
-            acc2[q].y += v1[q].x * y1.y - v1[q].y * y1.x;
+      for (int h = 0; h < RPD; ++h) {
+        if (!live[h]) continue;
+#pragma unroll
+        for (int q = 0; q < DOTS_KG; ++q)
+          if (kb + q < kcount) {
+            acc1[q].x += v[h][q].x * x[h].x + v[h][q].y * x[h].y;
+            acc1[q].y += v[h][q].x * x[h].y - v[h][q].y * x[h].x;
+            acc2[q].x += v[h][q].x * y[h].x + v[h][q].y * y[h].y;
+            acc2[q].y += v[h][q].x * y[h].y - v[h][q].y * y[h].x;
           }
-        }
+      }
     }
   }
 #pragma unroll
@@ -479,16 +491,22 @@ __global__ void __launch_bounds__(256) k_dots_partial(const double2* __restrict_
   }
 }
 
-void launch_dots_partial(const double2* V, int64_t vstride, int kcount, const double2* w1, const double2* w2,
+template <class B>
+void launch_dots_partial(const B* V, int64_t vstride, int kcount, const B* w1, const double2* w2,
                          int64_t n, int64_t ld, int ncols, const int32_t* act, double2* part1, double2* part2,
                          hipStream_t st) {
   dim3 g((unsigned)ceil_div(kcount, DOTS_KG), (unsigned)reduce_chunks(n), (unsigned)ceil_div(ncols, 64));
   kt_begin(KF_CGS_DOTS, st);
-  k_dots_partial<<<g, 256, 0, st>>>(V, vstride, kcount, w1, w2, n, ld, ncols, act, part1, w2 ? part2 : nullptr);
+  k_dots_partial<B><<<g, 256, 0, st>>>(V, vstride, kcount, w1, w2, n, ld, ncols, act, part1, w2 ? part2 : nullptr);
   MW_LAUNCH_CHECK();
   if (kt_enabled())
-    kt_end(KF_CGS_DOTS, st, (w2 ? 16.0 : 8.0) * kcount * n * ncols, (kcount + (w2 ? 2.0 : 1.0)) * n * ncols * 16);
+    kt_end(KF_CGS_DOTS, st, (w2 ? 16.0 : 8.0) * kcount * n * ncols,
+           ((kcount + 1.0) * sizeof(B) + (w2 ? 16.0 : 0.0)) * n * ncols);
 }
+template void launch_dots_partial<double2>(const double2*, int64_t, int, const double2*, const double2*, int64_t,
+                                           int64_t, int, const int32_t*, double2*, double2*, hipStream_t);
+template void launch_dots_partial<float2>(const float2*, int64_t, int, const float2*, const double2*, int64_t,
+                                          int64_t, int, const int32_t*, double2*, double2*, hipStream_t);
 
 // ---------------------------------------------------------------- K6/K7 with delayed reorthogonalisation
 // Arnoldi step j of every active column, scalar part (one thread per column).
@@ -638,7 +656,8 @@ void launch_dgs_trial(int j, int m, int ncols, const double2* hprov, const doubl
 // j), and the next candidate u = (T - sum_k V_k b_k - v_j e) / nu into slot
 // j+1, with |u|^2 chunk partials; coef holds (a_k, b_k) interleaved.  The
 // coefficients sit in LDS when 2j <= CGS_HK.
-__global__ void __launch_bounds__(256) k_dgs_update(double2* __restrict__ V, int64_t vstride, int j,
+template <class B>
+__global__ void __launch_bounds__(256) k_dgs_update(B* __restrict__ V, int64_t vstride, int j,
                                                     const double2* __restrict__ coef, const double* __restrict__ nu,
                                                     const double2* __restrict__ e, const double2* __restrict__ T,
                                                     int64_t n, int64_t ld, int ncols, const int32_t* __restrict__ act,
@@ -658,10 +677,11 @@ __global__ void __launch_bounds__(256) k_dgs_update(double2* __restrict__ V, int
   if (c < ncols && act[c]) {
     const double inu = nu[c];
     const double2 ec = e[c];
-    double2* Vj = V + (int64_t)j * vstride;
-    double2* Vn = V + (int64_t)(j + 1) * vstride;
+    B* Vj = V + (int64_t)j * vstride;
+    B* Vn = V + (int64_t)(j + 1) * vstride;
     // RP rows per pass (r, r + 4, ...), sharing each coefficient load; the
-    // norm is summed over the rows in ascending order
+    // norm is summed over the rows in ascending order (eight rows with an
+    // FP32 basis measured slower: 620 against 482 ms per step)
     constexpr int RP = 4;
     for (int64_t r = r0 + rl; r < r1; r += 4 * RP) {
       int64_t o[RP];
@@ -671,17 +691,17 @@ __global__ void __launch_bounds__(256) k_dgs_update(double2* __restrict__ V, int
       for (int q = 0; q < RP; ++q) {
         live[q] = r + 4 * q < r1;
         o[q] = (r + 4 * q) * ld + c;
-        y[q] = live[q] ? Vj[o[q]] : make_double2(0.0, 0.0);
+        y[q] = live[q] ? bload(Vj[o[q]]) : make_double2(0.0, 0.0);
         u[q] = live[q] ? T[o[q]] : make_double2(0.0, 0.0);
       }
 #pragma unroll 2
       for (int k = 0; k < j; ++k) {
-        const double2* Vk = V + (int64_t)k * vstride;
+        const B* Vk = V + (int64_t)k * vstride;
         const double2 ak = in_lds ? cf[(2 * k) * 64 + cl] : coef[(int64_t)(2 * k) * ncols + c];
         const double2 bk = in_lds ? cf[(2 * k + 1) * 64 + cl] : coef[(int64_t)(2 * k + 1) * ncols + c];
 #pragma unroll
         for (int q = 0; q < RP; ++q) {
-          const double2 v = live[q] ? Vk[o[q]] : make_double2(0.0, 0.0);
+          const double2 v = live[q] ? bload(Vk[o[q]]) : make_double2(0.0, 0.0);
           y[q].x -= v.x * ak.x - v.y * ak.y;
           y[q].y -= v.x * ak.y + v.y * ak.x;
           u[q].x -= v.x * bk.x - v.y * bk.y;
@@ -696,9 +716,12 @@ __global__ void __launch_bounds__(256) k_dgs_update(double2* __restrict__ V, int
         uu.x -= yy.x * ec.x - yy.y * ec.y;
         uu.y -= yy.x * ec.y + yy.y * ec.x;
         uu = make_double2(uu.x / inu, uu.y / inu);
-        Vj[o[q]] = yy;
-        Vn[o[q]] = uu;
-        acc += uu.x * uu.x + uu.y * uu.y;
+        Vj[o[q]] = bstore<B>(yy);
+        const B us = bstore<B>(uu);
+        Vn[o[q]] = us;
+        // the norm of what is stored (the candidate the next step uses)
+        const double2 ur = bload(us);
+        acc += ur.x * ur.x + ur.y * ur.y;
       }
     }
   }
@@ -708,19 +731,26 @@ __global__ void __launch_bounds__(256) k_dgs_update(double2* __restrict__ V, int
     norm_part[(int64_t)chunk * ncols + c] = ((red[0][cl] + red[1][cl]) + red[2][cl]) + red[3][cl];
 }
 
-void launch_dgs_update(double2* V, int64_t vstride, int j, const double2* coef, const double* nu, const double2* e,
+template <class B>
+void launch_dgs_update(B* V, int64_t vstride, int j, const double2* coef, const double* nu, const double2* e,
                        const double2* T, int64_t n, int64_t ld, int ncols, const int32_t* act, double* norm_part,
                        hipStream_t st) {
   dim3 g((unsigned)reduce_chunks(n), (unsigned)ceil_div(ncols, 64));
   size_t lds = 2 * j <= CGS_HK ? (size_t)(2 * j) * 64 * sizeof(double2) : 0;
   kt_begin(KF_CGS_UPDATE, st);
-  k_dgs_update<<<g, 256, lds, st>>>(V, vstride, j, coef, nu, e, T, n, ld, ncols, act, norm_part);
+  k_dgs_update<B><<<g, 256, lds, st>>>(V, vstride, j, coef, nu, e, T, n, ld, ncols, act, norm_part);
   MW_LAUNCH_CHECK();
-  if (kt_enabled()) kt_end(KF_CGS_UPDATE, st, 16.0 * j * n * ncols, (j + 4.0) * n * ncols * 16);
+  // reads V_0..V_j and T, writes v_j and the next candidate
+  if (kt_enabled()) kt_end(KF_CGS_UPDATE, st, 16.0 * j * n * ncols, ((j + 3.0) * sizeof(B) + 16.0) * n * ncols);
 }
+template void launch_dgs_update<double2>(double2*, int64_t, int, const double2*, const double*, const double2*,
+                                         const double2*, int64_t, int64_t, int, const int32_t*, double*, hipStream_t);
+template void launch_dgs_update<float2>(float2*, int64_t, int, const double2*, const double*, const double2*,
+                                        const double2*, int64_t, int64_t, int, const int32_t*, double*, hipStream_t);
 
 // w[:, c] /= sqrt(nrm2[c]) for active columns with a nonzero norm
-__global__ void k_scale_cols(double2* __restrict__ w, int64_t n, int64_t ld, int ncols, const double* __restrict__ nrm2,
+template <class B>
+__global__ void k_scale_cols(B* __restrict__ w, int64_t n, int64_t ld, int ncols, const double* __restrict__ nrm2,
                              const int32_t* __restrict__ act) {
   int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t r = id / ncols;
@@ -728,15 +758,18 @@ __global__ void k_scale_cols(double2* __restrict__ w, int64_t n, int64_t ld, int
   if (r >= n || !act[c]) return;
   double s = sqrt(nrm2[c]);
   if (s > 0.0) {
-    double2 v = w[r * ld + c];
-    w[r * ld + c] = make_double2(v.x / s, v.y / s);
+    const double2 v = bload(w[r * ld + c]);
+    w[r * ld + c] = bstore<B>(make_double2(v.x / s, v.y / s));
   }
 }
-void launch_scale_cols(double2* w, int64_t n, int64_t ld, int ncols, const double* nrm, const int32_t* act,
+template <class B>
+void launch_scale_cols(B* w, int64_t n, int64_t ld, int ncols, const double* nrm, const int32_t* act,
                        hipStream_t st) {
-  k_scale_cols<<<(unsigned)ceil_div(n * ncols, 256), 256, 0, st>>>(w, n, ld, ncols, nrm, act);
+  k_scale_cols<B><<<(unsigned)ceil_div(n * ncols, 256), 256, 0, st>>>(w, n, ld, ncols, nrm, act);
   MW_LAUNCH_CHECK();
 }
+template void launch_scale_cols<double2>(double2*, int64_t, int64_t, int, const double*, const int32_t*, hipStream_t);
+template void launch_scale_cols<float2>(float2*, int64_t, int64_t, int, const double*, const int32_t*, hipStream_t);
 
 // ---------------------------------------------------------------- K7
 // y = R^-1 g on the Krylov dimension of each column (back substitution)
@@ -758,7 +791,8 @@ void launch_backsolve(int m, int ncols, const double2* H, const double2* g, cons
 }
 
 // u[r][c] = sum_{k < kdim[c]} V_k[r][c] y[k][c]
-__global__ void k_combine(const double2* __restrict__ V, int64_t vstride, const double2* __restrict__ y,
+template <class B>
+__global__ void k_combine(const B* __restrict__ V, int64_t vstride, const double2* __restrict__ y,
                           const int32_t* __restrict__ kdim, double2* __restrict__ u, int64_t n, int64_t ld,
                           int ncols) {
   int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -767,15 +801,21 @@ __global__ void k_combine(const double2* __restrict__ V, int64_t vstride, const 
   if (r >= n) return;
   double2 acc = make_double2(0.0, 0.0);
   int kk = kdim[c];
-  for (int k = 0; k < kk; ++k) acc = cadd(acc, cmul(V[(int64_t)k * vstride + r * ld + c], y[(int64_t)k * ncols + c]));
+  for (int k = 0; k < kk; ++k)
+    acc = cadd(acc, cmul(bload(V[(int64_t)k * vstride + r * ld + c]), y[(int64_t)k * ncols + c]));
   u[r * ld + c] = acc;
 }
-void launch_combine(const double2* V, int64_t vstride, int m, const double2* y, const int32_t* kdim, double2* u,
+template <class B>
+void launch_combine(const B* V, int64_t vstride, int m, const double2* y, const int32_t* kdim, double2* u,
                     int64_t n, int64_t ld, int ncols, hipStream_t st) {
   (void)m;
-  k_combine<<<(unsigned)ceil_div(n * ncols, 256), 256, 0, st>>>(V, vstride, y, kdim, u, n, ld, ncols);
+  k_combine<B><<<(unsigned)ceil_div(n * ncols, 256), 256, 0, st>>>(V, vstride, y, kdim, u, n, ld, ncols);
   MW_LAUNCH_CHECK();
 }
+template void launch_combine<double2>(const double2*, int64_t, int, const double2*, const int32_t*, double2*,
+                                      int64_t, int64_t, int, hipStream_t);
+template void launch_combine<float2>(const float2*, int64_t, int, const double2*, const int32_t*, double2*, int64_t,
+                                     int64_t, int, hipStream_t);
 
 __global__ void k_axpy_cols(double2* __restrict__ x, const double2* __restrict__ z, int64_t total) {
   int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -789,7 +829,8 @@ void launch_axpy_cols(double2* x, const double2* z, int64_t n, int64_t ld, int n
 }
 
 // v0 = r / ||r|| for active columns, 0 elsewhere
-__global__ void k_start_cycle(const double2* __restrict__ r, double2* __restrict__ v0, int64_t n, int64_t ld,
+template <class B>
+__global__ void k_start_cycle(const double2* __restrict__ r, B* __restrict__ v0, int64_t n, int64_t ld,
                               int ncols, const double* __restrict__ rn2, const int32_t* __restrict__ act) {
   int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t row = id / ncols;
@@ -801,11 +842,26 @@ __global__ void k_start_cycle(const double2* __restrict__ r, double2* __restrict
     double2 x = r[row * ld + c];
     v = make_double2(x.x / s, x.y / s);
   }
-  v0[row * ld + c] = v;
+  v0[row * ld + c] = bstore<B>(v);
 }
-void launch_start_cycle(const double2* r, double2* v0, int64_t n, int64_t ld, int ncols, const double* rn2,
+template <class B>
+void launch_start_cycle(const double2* r, B* v0, int64_t n, int64_t ld, int ncols, const double* rn2,
                         const int32_t* act, hipStream_t st) {
-  k_start_cycle<<<(unsigned)ceil_div(n * ncols, 256), 256, 0, st>>>(r, v0, n, ld, ncols, rn2, act);
+  k_start_cycle<B><<<(unsigned)ceil_div(n * ncols, 256), 256, 0, st>>>(r, v0, n, ld, ncols, rn2, act);
+  MW_LAUNCH_CHECK();
+}
+template void launch_start_cycle<double2>(const double2*, double2*, int64_t, int64_t, int, const double*,
+                                          const int32_t*, hipStream_t);
+template void launch_start_cycle<float2>(const double2*, float2*, int64_t, int64_t, int, const double*,
+                                         const int32_t*, hipStream_t);
+
+__global__ void k_widen(const float2* __restrict__ src, double2* __restrict__ dst, int64_t count) {
+  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (id < count) dst[id] = make_double2(src[id].x, src[id].y);
+}
+void launch_widen(const float2* src, double2* dst, int64_t count, hipStream_t st) {
+  if (count <= 0) return;
+  k_widen<<<(unsigned)ceil_div(count, 256), 256, 0, st>>>(src, dst, count);
   MW_LAUNCH_CHECK();
 }
 

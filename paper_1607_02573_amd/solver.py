@@ -165,6 +165,10 @@ class Problem:
         f = {"auto": B.MW_SOLVE_AUTO, "recursive": B.MW_SOLVE_RECURSIVE, "rows": B.MW_SOLVE_ROWS}[form]
         check(lib().mw_set_solve_form(self.h, f))
 
+    def set_krylov_basis(self, kind: str):
+        """'auto' (complex FP32 with FP32 factors) or 'fp64'; used by later solves."""
+        check(lib().mw_set_krylov_basis(self.h, {"auto": B.MW_BASIS_AUTO, "fp64": B.MW_BASIS_FP64}[kind]))
+
     def factor(self, part, n_sub: int, overlap: int = 1, precision: str = "c128"):
         """Fill and factor the B_i; part = None takes the library's own
         partition (recursive coordinate bisection of the centroids)."""
