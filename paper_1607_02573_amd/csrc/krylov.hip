@@ -438,34 +438,36 @@ __global__ void __launch_bounds__(256) k_dots_partial(const B* __restrict__ V, i
   for (int q = 0; q < DOTS_KG; ++q) acc1[q] = acc2[q] = make_double2(0.0, 0.0);
   if (c < ncols && act[c]) {
     const B* Vb = V + (int64_t)kb * vstride;
-    // two rows per pass (r and r + 4): twice the loads in flight (four rows
-    // with an FP32 basis measured slower: 815 against 404 ms per step, the
-    // registers halve the occupancy); each (k, column) sum still runs over
-    // the chunk's rows in ascending order
-    constexpr int RPD = 2;
+    // RPD rows per pass (r, r + 4, ...): four with an FP32 basis (its loads
+    // carry half the bytes; the raw values stay in registers until used),
+    // two otherwise; each (k, column) sum still runs over the chunk's rows
+    // in ascending order
+    constexpr int RPD = sizeof(B) == 8 ? 4 : 2;
     for (int64_t r = r0 + rl; r < r1; r += 4 * RPD) {
-      double2 x[RPD], y[RPD], v[RPD][DOTS_KG];
+      B x[RPD], v[RPD][DOTS_KG];
+      double2 y[RPD];
       bool live[RPD];
 #pragma unroll
       for (int h = 0; h < RPD; ++h) {
         live[h] = r + 4 * h < r1;
         const int64_t o = (r + 4 * h) * ld + c;
-        x[h] = live[h] ? bload(w1[o]) : make_double2(0.0, 0.0);
+        x[h] = live[h] ? w1[o] : B{};
         y[h] = (live[h] && w2) ? w2[o] : make_double2(0.0, 0.0);
 #pragma unroll
-        for (int q = 0; q < DOTS_KG; ++q)
-          v[h][q] = (live[h] && kb + q < kcount) ? bload(Vb[(int64_t)q * vstride + o]) : make_double2(0.0, 0.0);
+        for (int q = 0; q < DOTS_KG; ++q) v[h][q] = (live[h] && kb + q < kcount) ? Vb[(int64_t)q * vstride + o] : B{};
       }
 #pragma unroll
       for (int h = 0; h < RPD; ++h) {
         if (!live[h]) continue;
+        const double2 xh = bload(x[h]);
 #pragma unroll
         for (int q = 0; q < DOTS_KG; ++q)
           if (kb + q < kcount) {
-            acc1[q].x += v[h][q].x * x[h].x + v[h][q].y * x[h].y;
-            acc1[q].y += v[h][q].x * x[h].y - v[h][q].y * x[h].x;
-            acc2[q].x += v[h][q].x * y[h].x + v[h][q].y * y[h].y;
-            acc2[q].y += v[h][q].x * y[h].y - v[h][q].y * y[h].x;
+            const double2 vq = bload(v[h][q]);
+            acc1[q].x += vq.x * xh.x + vq.y * xh.y;
+            acc1[q].y += vq.x * xh.y - vq.y * xh.x;
+            acc2[q].x += vq.x * y[h].x + vq.y * y[h].y;
+            acc2[q].y += vq.x * y[h].y - vq.y * y[h].x;
           }
       }
     }
@@ -680,8 +682,9 @@ __global__ void __launch_bounds__(256) k_dgs_update(B* __restrict__ V, int64_t v
     B* Vj = V + (int64_t)j * vstride;
     B* Vn = V + (int64_t)(j + 1) * vstride;
     // RP rows per pass (r, r + 4, ...), sharing each coefficient load; the
-    // norm is summed over the rows in ascending order (eight rows with an
-    // FP32 basis measured slower: 620 against 482 ms per step)
+    // norm is summed over the rows in ascending order (with an FP32 basis,
+    // eight rows per pass or a four-way unroll over the basis measured
+    // slower: 573-620 against 482 ms per 1 GHz step)
     constexpr int RP = 4;
     for (int64_t r = r0 + rl; r < r1; r += 4 * RP) {
       int64_t o[RP];
@@ -694,14 +697,28 @@ __global__ void __launch_bounds__(256) k_dgs_update(B* __restrict__ V, int64_t v
         y[q] = live[q] ? bload(Vj[o[q]]) : make_double2(0.0, 0.0);
         u[q] = live[q] ? T[o[q]] : make_double2(0.0, 0.0);
       }
-#pragma unroll 2
+      // the raw values of basis vector k + 1 are loaded while vector k is
+      // applied (two vectors' loads in flight for a few registers; 331
+      // against 482 ms per 1 GHz step with an FP32 basis, against an
+      // unrolled loop that converted at the load)
+      B nxt[RP];
+#pragma unroll
+      for (int q = 0; q < RP; ++q) nxt[q] = (live[q] && j > 0) ? V[o[q]] : B{};
+#pragma unroll 1
       for (int k = 0; k < j; ++k) {
-        const B* Vk = V + (int64_t)k * vstride;
+        B cur[RP];
+#pragma unroll
+        for (int q = 0; q < RP; ++q) cur[q] = nxt[q];
+        if (k + 1 < j) {
+          const B* Vn1 = V + (int64_t)(k + 1) * vstride;
+#pragma unroll
+          for (int q = 0; q < RP; ++q) nxt[q] = live[q] ? Vn1[o[q]] : B{};
+        }
         const double2 ak = in_lds ? cf[(2 * k) * 64 + cl] : coef[(int64_t)(2 * k) * ncols + c];
         const double2 bk = in_lds ? cf[(2 * k + 1) * 64 + cl] : coef[(int64_t)(2 * k + 1) * ncols + c];
 #pragma unroll
         for (int q = 0; q < RP; ++q) {
-          const double2 v = live[q] ? bload(Vk[o[q]]) : make_double2(0.0, 0.0);
+          const double2 v = bload(cur[q]);
           y[q].x -= v.x * ak.x - v.y * ak.y;
           y[q].y -= v.x * ak.y + v.y * ak.x;
           u[q].x -= v.x * bk.x - v.y * bk.y;
