@@ -472,22 +472,22 @@ void upload_decomp(mw_problem* p) {
 // Z = M^-1 V (n x nc, leading dimension ld), local workspace W.Y
 // V complex FP64, or complex FP32 (a basis vector of the mixed-precision
 // GMRES, with FP32 factors only)
-template <class VT>
-void one_level(mw_problem* p, GmresWork& W, const VT* V, double2* Z, int nc, int64_t ld) {
+template <class VT, class ZT = double2>
+void one_level(mw_problem* p, GmresWork& W, const VT* V, ZT* Z, int nc, int64_t ld) {
   mw_ctx* c = p->ctx;
   int64_t n = p->T.n();
   if (p->prec == MW_C64) {
     float2* Y = (float2*)W.Y.get(c, p->dd.sum_pad * nc * 8);
     launch_restrict<float2, VT>(p->dd, V, ld, nc, Y, nc, W.st);
     lu_solve_batched<float2>(p->dd, p->F.as<float2>(), Y, nc, nc, W.st);
-    launch_prolong<float2>(p->dd, n, Y, nc, nc, Z, ld, W.st);
-  } else if constexpr (std::is_same<VT, double2>::value) {
+    launch_prolong<float2, ZT>(p->dd, n, Y, nc, nc, Z, ld, W.st);
+  } else if constexpr (std::is_same<VT, double2>::value && std::is_same<ZT, double2>::value) {
     double2* Y = (double2*)W.Y.get(c, p->dd.sum_pad * nc * 16);
     launch_restrict<double2>(p->dd, V, ld, nc, Y, nc, W.st);
     lu_solve_batched<double2>(p->dd, p->F.as<double2>(), Y, nc, nc, W.st);
     launch_prolong<double2>(p->dd, n, Y, nc, nc, Z, ld, W.st);
   } else {
-    MW_CHECK(false, MW_EINVAL, "an FP32 Krylov basis needs FP32 subdomain factors");
+    MW_CHECK(false, MW_EINVAL, "FP32 Krylov vectors need FP32 subdomain factors");
   }
 }
 
@@ -720,8 +720,9 @@ int64_t gmres_bytes_per_col(mw_problem* p, int m, bool block) {
   const int64_t bsz = (!block && basis_fp32(p)) ? 8 : 16;   // block GMRES keeps an FP64 basis
   int64_t big = (int64_t)(m + 1) * p->T.n() * bsz + 4 * p->T.n() * 16 + p->dd.sum_pad * esz +
                 reduce_chunks(p->T.n()) * (2 * m + 3) * 16;
-  if (p->coarse_kind != MW_COARSE_NONE)   // two-level: Q v, the coarse vector, an FP64 copy of an FP32 basis vector
-    big += p->T.n() * 16 * (bsz == 8 ? 2 : 1) + (int64_t)round_up(3 * (int64_t)std::max(p->D.nsub, 1), 64) * esz;
+  if (bsz == 8) big += p->T.n() * 16;   // FP32 basis: M^-1 v_j in FP32, or an FP64 copy of v_j (two-level)
+  if (p->coarse_kind != MW_COARSE_NONE)   // two-level: Q v and the coarse vector
+    big += p->T.n() * 16 + (int64_t)round_up(3 * (int64_t)std::max(p->D.nsub, 1), 64) * esz;
   // Hessenberg (raw and rotated), rotations, g, y, dot sums, provisional
   // column, coefficients, norms, flags
   int64_t small = 2 * (int64_t)(m + 1) * m * 16 + (int64_t)m * 24 + 5 * (int64_t)(m + 1) * 16 + 2 * (int64_t)m * 16 +
@@ -812,8 +813,18 @@ void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, co
     bool more = j < m && !finish_only;   // step m only finishes column m-1
     for (int pass = 0; pass < 2; ++pass) {
       if (more) {
-        apply_prec(p, W, Vj, Z, nc, ld);
-        launch_spmm(p->dm, p->val.as<double2>(), Z, ld, T, ld, nc, nullptr, 0, st);
+        if (std::is_same<BT, float2>::value && !p->coarse_active) {
+          // FP32 basis, one level: M^-1 v_j is rounded to FP32 as well (the
+          // product A M^-1 v_j is FP64 either way; the rounding perturbs the
+          // Arnoldi relation no more than the basis' own)
+          float2* Zf = (float2*)W.cw.get(c, vstride * 8);
+          MW_CHECK(p->factors_valid, MW_EINVAL, "no valid subdomain factors: call mw_factor_subdomains");
+          one_level<BT, float2>(p, W, Vj, Zf, nc, ld);
+          launch_spmm(p->dm, p->val.as<double2>(), (const float2*)Zf, ld, T, ld, nc, nullptr, 0, st);
+        } else {
+          apply_prec(p, W, Vj, Z, nc, ld);
+          launch_spmm(p->dm, p->val.as<double2>(), (const double2*)Z, ld, T, ld, nc, nullptr, 0, st);
+        }
       }
       launch_dots_partial(V, vstride, j + 1, Vj, more ? T : nullptr, n, ld, nc, act, part1, part2, st);
       launch_sum_chunks_c(part1, nch, (int64_t)(j + 1) * nc, P1, st);

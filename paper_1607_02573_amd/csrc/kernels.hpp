@@ -173,13 +173,16 @@ template <class C>
 void lu_solve_batched(const DeviceDecomp& d, const C* F, C* Y, int ncols, int64_t ld, hipStream_t st);
 
 // ---- Krylov and vector kernels (krylov.hip)
-void launch_spmm(const DeviceMesh& m, const double2* val, const double2* X, int64_t ldx, double2* Y,
+// X complex FP64 or complex FP32 (double2 / float2); products and sums FP64
+template <class XT>
+void launch_spmm(const DeviceMesh& m, const double2* val, const XT* X, int64_t ldx, double2* Y,
                  int64_t ldy, int ncols, const double2* Bsub, int64_t ldb, hipStream_t st);
 template <class C, class VT = double2>
 void launch_restrict(const DeviceDecomp& d, const VT* V, int64_t ldv, int ncols, C* Y, int64_t ldy,
                      hipStream_t st);
-template <class C>
-void launch_prolong(const DeviceDecomp& d, int64_t n, const C* Y, int64_t ldy, int ncols, double2* Z,
+// Z complex FP64, or complex FP32 (summed in FP64, then rounded)
+template <class C, class ZT = double2>
+void launch_prolong(const DeviceDecomp& d, int64_t n, const C* Y, int64_t ldy, int ncols, ZT* Z,
                     int64_t ldz, hipStream_t st);
 // column sums over rows in fixed-size row chunks, then in chunk order
 int64_t reduce_chunks(int64_t n);

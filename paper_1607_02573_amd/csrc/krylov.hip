@@ -13,13 +13,22 @@ constexpr int RCHUNK = 2048;   // rows per reduction chunk
 
 int64_t reduce_chunks(int64_t n) { return ceil_div(n, RCHUNK); }
 
+// Multi-vector elements: complex FP64 (double2) or complex FP32 (float2: the
+// Krylov basis and the preconditioned vectors of the mixed-precision GMRES);
+// every product and sum below is FP64.
+__device__ inline double2 bload(const double2& v) { return v; }
+__device__ inline double2 bload(const float2& v) { return make_double2(v.x, v.y); }
+template <class B> __device__ inline B bstore(double2 v);
+template <> __device__ inline double2 bstore<double2>(double2 v) { return v; }
+template <> __device__ inline float2 bstore<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
+
 // ---------------------------------------------------------------- K1 / K12
 // Y = A X  (Bsub == nullptr)  or  Y = Bsub - A X, CSR complex128.
 // TPR threads per row; each lane walks columns lane, lane+TPR, ...
-template <int TPR>
+template <int TPR, class XT>
 __global__ void __launch_bounds__(256) k_spmm(int64_t n, const int64_t* __restrict__ row_ptr,
                                               const int32_t* __restrict__ col, const double2* __restrict__ val,
-                                              const double2* __restrict__ X, int64_t ldx, double2* __restrict__ Y,
+                                              const XT* __restrict__ X, int64_t ldx, double2* __restrict__ Y,
                                               int64_t ldy, int ncols, const double2* __restrict__ Bs, int64_t ldb) {
   int64_t r = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / TPR;
   int lane = threadIdx.x % TPR;
@@ -31,7 +40,7 @@ __global__ void __launch_bounds__(256) k_spmm(int64_t n, const int64_t* __restri
     double2 acc = make_double2(0.0, 0.0);
     for (int64_t k = b; k < e; ++k) {
       double2 a = val[k];
-      double2 x = X[(int64_t)col[k] * ldx + c];
+      double2 x = bload(X[(int64_t)col[k] * ldx + c]);
       acc.x += a.x * x.x - a.y * x.y;
       acc.y += a.x * x.y + a.y * x.x;
     }
@@ -54,10 +63,10 @@ __device__ inline double bcast(double v, int t) {
   return __hiloint2double(hi, lo);
 }
 
-template <int CPL>
+template <int CPL, class XT>
 __global__ void __launch_bounds__(256) k_spmm_w(int64_t n, const int64_t* __restrict__ row_ptr,
                                                 const int32_t* __restrict__ col, const double2* __restrict__ val,
-                                                const double2* __restrict__ X, int64_t ldx, double2* __restrict__ Y,
+                                                const XT* __restrict__ X, int64_t ldx, double2* __restrict__ Y,
                                                 int64_t ldy, int ncols, const double2* __restrict__ Bs, int64_t ldb) {
   // workgroups are dealt to the 8 XCDs round-robin: remap so that each XCD
   // takes one contiguous eighth of the rows, whose X rows overlap in its L2
@@ -85,12 +94,12 @@ __global__ void __launch_bounds__(256) k_spmm_w(int64_t n, const int64_t* __rest
         double2 a;
         a.x = bcast(myval.x, t);
         a.y = bcast(myval.y, t);
-        const double2* xr = X + cc * ldx;
+        const XT* xr = X + cc * ldx;
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
           const int c = c0 + lane + 64 * q;
           if (c < ncols) {
-            double2 x = xr[c];
+            double2 x = bload(xr[c]);
             acc[q].x += a.x * x.x - a.y * x.y;
             acc[q].y += a.x * x.y + a.y * x.x;
           }
@@ -115,10 +124,10 @@ __global__ void __launch_bounds__(256) k_spmm_w(int64_t n, const int64_t* __rest
 // Half-wave form: 32 lanes per row (two rows per wave), each lane on CPL
 // columns c = lane + 32 q; the row's nonzeros are loaded 32 at a time and
 // broadcast within the half-wave.  No idle lanes for 32 * CPL columns.
-template <int CPL>
+template <int CPL, class XT>
 __global__ void __launch_bounds__(256) k_spmm_h(int64_t n, const int64_t* __restrict__ row_ptr,
                                                 const int32_t* __restrict__ col, const double2* __restrict__ val,
-                                                const double2* __restrict__ X, int64_t ldx, double2* __restrict__ Y,
+                                                const XT* __restrict__ X, int64_t ldx, double2* __restrict__ Y,
                                                 int64_t ldy, int ncols, const double2* __restrict__ Bs, int64_t ldb,
                                                 const int32_t* __restrict__ rorder) {
   const int64_t G = gridDim.x;
@@ -151,12 +160,12 @@ __global__ void __launch_bounds__(256) k_spmm_h(int64_t n, const int64_t* __rest
       a.x = __shfl(myval.x, t, 32);
       a.y = __shfl(myval.y, t, 32);
       if (t < cnt) {
-        const double2* xr = X + cc * ldx;
+        const XT* xr = X + cc * ldx;
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
           const int c = lane + 32 * q;
           if (c < ncols) {
-            double2 x = xr[c];
+            double2 x = bload(xr[c]);
             acc[q].x += a.x * x.x - a.y * x.y;
             acc[q].y += a.x * x.y + a.y * x.x;
           }
@@ -179,15 +188,16 @@ __global__ void __launch_bounds__(256) k_spmm_h(int64_t n, const int64_t* __rest
   }
 }
 
-void launch_spmm(const DeviceMesh& m, const double2* val, const double2* X, int64_t ldx, double2* Y, int64_t ldy,
+template <class XT>
+void launch_spmm(const DeviceMesh& m, const double2* val, const XT* X, int64_t ldx, double2* Y, int64_t ldy,
                  int ncols, const double2* Bsub, int64_t ldb, hipStream_t st) {
   int64_t n = m.n;
   kt_begin(KF_SPMM, st);
 #define MW_SPMM(T)                                                                                      \
-  k_spmm<T><<<(unsigned)ceil_div(n * T, 256), 256, 0, st>>>(n, m.row_ptr, m.col, val, X, ldx, Y, ldy, \
+  k_spmm<T, XT><<<(unsigned)ceil_div(n * T, 256), 256, 0, st>>>(n, m.row_ptr, m.col, val, X, ldx, Y, ldy, \
                                                             ncols, Bsub, ldb)
 #define MW_SPMM_W(Q)                                                                                  \
-  k_spmm_w<Q><<<(unsigned)round_up(ceil_div(n * 64, 256), 8), 256, 0, st>>>(n, m.row_ptr, m.col, val, X, \
+  k_spmm_w<Q, XT><<<(unsigned)round_up(ceil_div(n * 64, 256), 8), 256, 0, st>>>(n, m.row_ptr, m.col, val, X, \
                                                                            ldx, Y, ldy, ncols, Bsub, ldb)
   if (ncols <= 1) MW_SPMM(1);
   else if (ncols <= 2) MW_SPMM(2);
@@ -197,12 +207,12 @@ void launch_spmm(const DeviceMesh& m, const double2* val, const double2* X, int6
   else if (ncols <= 32)
     // half a wave per row, rows in Z order: 1.31 ms against 1.66 ms for one
     // thread group per row in natural order (32 columns, 1 GHz chamber)
-    k_spmm_h<1><<<(unsigned)round_up(ceil_div(n * 32, 256), 8), 256, 0, st>>>(n, m.row_ptr, m.col, val, X, ldx, Y,
+    k_spmm_h<1, XT><<<(unsigned)round_up(ceil_div(n * 32, 256), 8), 256, 0, st>>>(n, m.row_ptr, m.col, val, X, ldx, Y,
                                                                               ldy, ncols, Bsub, ldb, m.rorder);
   else if (ncols <= 64) MW_SPMM_W(1);
   else if (ncols <= 128) MW_SPMM_W(2);
   else if (ncols <= 160)
-    k_spmm_h<5><<<(unsigned)round_up(ceil_div(n * 32, 256), 8), 256, 0, st>>>(n, m.row_ptr, m.col, val, X, ldx, Y,
+    k_spmm_h<5, XT><<<(unsigned)round_up(ceil_div(n * 32, 256), 8), 256, 0, st>>>(n, m.row_ptr, m.col, val, X, ldx, Y,
                                                                               ldy, ncols, Bsub, ldb, m.rorder);
   else MW_SPMM_W(3);
 #undef MW_SPMM
@@ -210,8 +220,12 @@ void launch_spmm(const DeviceMesh& m, const double2* val, const double2* X, int6
   MW_LAUNCH_CHECK();
   if (kt_enabled())
     kt_end(KF_SPMM, st, 8.0 * m.nnz * ncols,
-           (double)m.nnz * 20 + (n + 1) * 8.0 + n * (double)ncols * 16 * (Bsub ? 3 : 2));
+           (double)m.nnz * 20 + (n + 1) * 8.0 + n * (double)ncols * (sizeof(XT) + 16.0 * (Bsub ? 2 : 1)));
 }
+template void launch_spmm<double2>(const DeviceMesh&, const double2*, const double2*, int64_t, double2*, int64_t, int,
+                                   const double2*, int64_t, hipStream_t);
+template void launch_spmm<float2>(const DeviceMesh&, const double2*, const float2*, int64_t, double2*, int64_t, int,
+                                  const double2*, int64_t, hipStream_t);
 
 // ---------------------------------------------------------------- K4 / K5
 // restriction: Y[l][c] = V[ridx[l]][c] (cast), zero on padding rows
@@ -278,10 +292,10 @@ void launch_restrict(const DeviceDecomp& d, const VT* V, int64_t ldv, int ncols,
 
 // weighted prolongation: Z[g][c] = sum over the copies of g of D * Y (FP64 sum,
 // ascending subdomain order)
-template <class C>
+template <class C, class ZT>
 __global__ void k_prolong(int64_t n, const int64_t* __restrict__ cp_ptr, const int64_t* __restrict__ cp_row,
                           const double* __restrict__ D, const C* __restrict__ Y, int64_t ldy, int ncols,
-                          double2* __restrict__ Z, int64_t ldz) {
+                          ZT* __restrict__ Z, int64_t ldz) {
   int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t g = id / ncols;
   int c = (int)(id % ncols);
@@ -294,15 +308,15 @@ __global__ void k_prolong(int64_t n, const int64_t* __restrict__ cp_ptr, const i
     acc.x += w * (double)y.x;
     acc.y += w * (double)y.y;
   }
-  Z[g * ldz + c] = acc;
+  Z[g * ldz + c] = bstore<ZT>(acc);
 }
 
 // the same for an even number of columns, two adjacent columns per thread
 // (each column summed exactly as above)
-template <class C>
+template <class C, class ZT>
 __global__ void k_prolong2(int64_t n, const int64_t* __restrict__ cp_ptr, const int64_t* __restrict__ cp_row,
                            const double* __restrict__ D, const C* __restrict__ Y, int64_t ldy, int npairs,
-                           double2* __restrict__ Z, int64_t ldz) {
+                           ZT* __restrict__ Z, int64_t ldz) {
   int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t g = id / npairs;
   int c = 2 * (int)(id % npairs);
@@ -317,28 +331,29 @@ __global__ void k_prolong2(int64_t n, const int64_t* __restrict__ cp_ptr, const 
     a1.x += w * (double)y1.x;
     a1.y += w * (double)y1.y;
   }
-  Z[g * ldz + c] = a0;
-  Z[g * ldz + c + 1] = a1;
+  Z[g * ldz + c] = bstore<ZT>(a0);
+  Z[g * ldz + c + 1] = bstore<ZT>(a1);
 }
 
-template <class C>
-void launch_prolong(const DeviceDecomp& d, int64_t n, const C* Y, int64_t ldy, int ncols, double2* Z, int64_t ldz,
+template <class C, class ZT>
+void launch_prolong(const DeviceDecomp& d, int64_t n, const C* Y, int64_t ldy, int ncols, ZT* Z, int64_t ldz,
                     hipStream_t st) {
   if (n <= 0 || ncols <= 0) return;
   kt_begin(KF_PROLONG, st);
   if (ncols % 2 == 0) {
     int64_t tot = n * (ncols / 2);
-    k_prolong2<C><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(n, d.cp_ptr, d.cp_row, d.D, Y, ldy, ncols / 2, Z,
+    k_prolong2<C, ZT><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(n, d.cp_ptr, d.cp_row, d.D, Y, ldy, ncols / 2, Z,
                                                                 ldz);
   } else {
     int64_t tot = n * ncols;
-    k_prolong<C><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(n, d.cp_ptr, d.cp_row, d.D, Y, ldy, ncols, Z, ldz);
+    k_prolong<C, ZT><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(n, d.cp_ptr, d.cp_row, d.D, Y, ldy, ncols, Z, ldz);
   }
   MW_LAUNCH_CHECK();
   if (kt_enabled()) {
     double sl = 0;
     for (int i = 0; i < d.nsub; ++i) sl += d.h_n_loc[i];
-    kt_end(KF_PROLONG, st, 4.0 * sl * ncols, sl * (16.0 + ncols * sizeof(C)) + (n + 1) * 8.0 + n * ncols * 16.0);
+    kt_end(KF_PROLONG, st, 4.0 * sl * ncols,
+           sl * (16.0 + ncols * sizeof(C)) + (n + 1) * 8.0 + n * ncols * (double)sizeof(ZT));
   }
 }
 
@@ -348,10 +363,12 @@ template void launch_restrict<float2, float2>(const DeviceDecomp&, const float2*
                                               hipStream_t);
 template void launch_restrict<double2, double2>(const DeviceDecomp&, const double2*, int64_t, int, double2*,
                                                 int64_t, hipStream_t);
-template void launch_prolong<float2>(const DeviceDecomp&, int64_t, const float2*, int64_t, int, double2*, int64_t,
-                                     hipStream_t);
-template void launch_prolong<double2>(const DeviceDecomp&, int64_t, const double2*, int64_t, int, double2*,
-                                      int64_t, hipStream_t);
+template void launch_prolong<float2, double2>(const DeviceDecomp&, int64_t, const float2*, int64_t, int, double2*,
+                                              int64_t, hipStream_t);
+template void launch_prolong<float2, float2>(const DeviceDecomp&, int64_t, const float2*, int64_t, int, float2*,
+                                             int64_t, hipStream_t);
+template void launch_prolong<double2, double2>(const DeviceDecomp&, int64_t, const double2*, int64_t, int, double2*,
+                                               int64_t, hipStream_t);
 
 // ---------------------------------------------------------------- reductions
 // Workgroup (chunk, column tile of 64): thread (column lane, row lane of 4)
@@ -404,14 +421,6 @@ void launch_sum_chunks_c(const double2* part, int64_t nchunk, int64_t width, dou
   k_sum_chunks_c<<<(unsigned)ceil_div(width, 128), 128, 0, st>>>(part, nchunk, width, out);
   MW_LAUNCH_CHECK();
 }
-
-// Krylov basis elements: complex FP64 (double2) or, with FP32 subdomain
-// factors, complex FP32 (float2); every product and sum below is FP64.
-__device__ inline double2 bload(const double2& v) { return v; }
-__device__ inline double2 bload(const float2& v) { return make_double2(v.x, v.y); }
-template <class B> __device__ inline B bstore(double2 v);
-template <> __device__ inline double2 bstore<double2>(double2 v) { return v; }
-template <> __device__ inline float2 bstore<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
 
 // ---------------------------------------------------------------- K6 (CGS2)
 // part1[chunk][k][c] = sum_{rows of chunk} conj(V_k[r][c]) w1[r][c] and, if
