@@ -137,6 +137,7 @@ struct mw_problem {
   std::vector<mw_port> ports;
   // mesh and operator
   DevBuf xyz, tet, t2e, dof, bface, bf2e, fbeta, row_ptr, col, rt_ptr, rt, rf_ptr, rf, rorder;
+  DevBuf sl_row, sl_off, sl_col, sl_idx, sl_val;   // sliced ELLPACK copy of A (products with few columns)
   DevBuf eps, E, val;
   // eps_r linear on every tetrahedron (mw_update_eps_vertex): vertex values,
   // and the (t*4 + slot) entries of every vertex for the vertex gradient
@@ -357,6 +358,48 @@ std::vector<int32_t> zorder_rows(const Topology& T) {
   return order;
 }
 
+// Sliced ELLPACK layout of A's pattern (slices of 64 rows; the rows in the
+// given order, sorted by decreasing length within windows of 512 so that a
+// slice's rows have alike lengths): lane row (-1 padding), slice offsets,
+// column of every slot (-1 padding) and its CSR position (-1 padding).
+struct SellLayout {
+  std::vector<int32_t> row, col, idx;
+  std::vector<int64_t> off;
+};
+SellLayout build_sell(const Topology& T, const std::vector<int32_t>& order) {
+  const int64_t n = T.n();
+  std::vector<int32_t> rows(order);
+  auto len = [&](int32_t r) { return T.row_ptr[r + 1] - T.row_ptr[r]; };
+  for (int64_t w0 = 0; w0 < n; w0 += 512)
+    std::stable_sort(rows.begin() + w0, rows.begin() + std::min<int64_t>(n, w0 + 512),
+                     [&](int32_t a, int32_t b) { return len(a) > len(b); });
+  const int64_t nsl = (n + 63) / 64;
+  SellLayout L;
+  L.row.assign(nsl * 64, -1);
+  L.off.assign(nsl + 1, 0);
+  for (int64_t s = 0; s < nsl; ++s) {
+    int64_t w = 0;
+    for (int64_t l = 0; l < 64 && s * 64 + l < n; ++l) {
+      L.row[s * 64 + l] = rows[s * 64 + l];
+      w = std::max<int64_t>(w, len(rows[s * 64 + l]));
+    }
+    L.off[s + 1] = L.off[s] + 64 * w;
+  }
+  L.col.assign(L.off[nsl], -1);
+  L.idx.assign(L.off[nsl], -1);
+  for (int64_t s = 0; s < nsl; ++s)
+    for (int64_t l = 0; l < 64; ++l) {
+      const int32_t r = L.row[s * 64 + l];
+      if (r < 0) continue;
+      for (int64_t k = 0; k < len(r); ++k) {
+        const int64_t pos = L.off[s] + 64 * k + l;
+        L.col[pos] = T.col[T.row_ptr[r] + k];
+        L.idx[pos] = (int32_t)(T.row_ptr[r] + k);
+      }
+    }
+  return L;
+}
+
 void assemble_values(mw_problem* p) {
   if (p->eps_p1)
     launch_element_matrices_p1(p->dm, p->eps_v.as<double2>(), p->k0, p->E.as<double2>(), p->eps.as<double2>(),
@@ -364,6 +407,9 @@ void assemble_values(mw_problem* p) {
   else
     launch_element_matrices(p->dm, p->eps.as<double2>(), p->k0, p->E.as<double2>(), p->stream);
   launch_gather_csr(p->dm, p->E.as<double2>(), p->val.as<double2>(), p->stream);
+  if (p->dm.sl_val)
+    launch_sell_values((int64_t)(p->sl_idx.bytes / 4), p->sl_idx.as<int32_t>(), p->val.as<double2>(),
+                       p->sl_val.as<double2>(), p->stream);
 }
 
 uint64_t hash_part(const int32_t* part, int32_t nt, int32_t nsub, int32_t delta) {
@@ -1389,7 +1435,16 @@ mw_status mw_assemble(mw_ctx* ctx, const mw_mesh* mesh, const mw_complex* eps_r,
     p->bf2e = upload(ctx, p->stream, T.bf2e);
     p->fbeta = upload(ctx, p->stream, fb);
     p->row_ptr = upload(ctx, p->stream, T.row_ptr);
-    p->rorder = upload(ctx, p->stream, zorder_rows(T));
+    const std::vector<int32_t> zrows = zorder_rows(T);
+    p->rorder = upload(ctx, p->stream, zrows);
+    {
+      const SellLayout L = build_sell(T, zrows);
+      p->sl_row = upload(ctx, p->stream, L.row);
+      p->sl_off = upload(ctx, p->stream, L.off);
+      p->sl_col = upload(ctx, p->stream, L.col);
+      p->sl_idx = upload(ctx, p->stream, L.idx);
+      p->sl_val = dalloc(ctx, (int64_t)L.col.size() * 16);
+    }
     p->col = upload(ctx, p->stream, T.col);
     p->rt_ptr = upload(ctx, p->stream, T.rt_ptr);
     p->rt = upload(ctx, p->stream, T.rt);
@@ -1406,6 +1461,12 @@ mw_status mw_assemble(mw_ctx* ctx, const mw_mesh* mesh, const mw_complex* eps_r,
     m.rt_ptr = p->rt_ptr.as<int64_t>(); m.rt = p->rt.as<int32_t>(); m.rf_ptr = p->rf_ptr.as<int64_t>();
     m.rf = p->rf.as<int32_t>();
     m.rorder = p->rorder.as<int32_t>();
+    m.sl_slots = (int64_t)(p->sl_row.bytes / 4);
+    m.sl_row = p->sl_row.as<int32_t>();
+    m.sl_off = p->sl_off.as<int64_t>();
+    m.sl_col = p->sl_col.as<int32_t>();
+    m.sl_val = p->sl_val.as<double2>();
+    m.csr_val = p->val.as<double2>();
     assemble_values(p.get());
     setup_ports(p.get());
     psync(p.get());

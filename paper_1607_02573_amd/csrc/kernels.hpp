@@ -25,6 +25,16 @@ struct DeviceMesh {
   const int64_t* row_ptr = nullptr;
   const int32_t* col = nullptr;
   const int32_t* rorder = nullptr;   // rows of A in Z-order of their edge midpoints (SpMM locality)
+  // A in sliced ELLPACK (SELL-64-512) for products with 1 or 2 columns: the
+  // rows in Z order, sorted by length within windows of 512, 64 per slice;
+  // slice s holds its rows' nonzeros column-major (entry k of the slice's
+  // lane l at sl_off[s] + 64 k + l), each row's in CSR order, padding col -1.
+  int64_t sl_slots = 0;                  // 64 x number of slices
+  const int32_t* sl_row = nullptr;       // [sl_slots] row of each lane (-1 padding)
+  const int64_t* sl_off = nullptr;       // [slices + 1]
+  const int32_t* sl_col = nullptr;       // [sl_off[slices]]
+  const double2* sl_val = nullptr;       // [sl_off[slices]] values, refreshed with val
+  const double2* csr_val = nullptr;      // the CSR values sl_val mirrors
   const int64_t* rt_ptr = nullptr;
   const int32_t* rt = nullptr;
   const int64_t* rf_ptr = nullptr;
@@ -173,6 +183,8 @@ template <class C>
 void lu_solve_batched(const DeviceDecomp& d, const C* F, C* Y, int ncols, int64_t ld, hipStream_t st);
 
 // ---- Krylov and vector kernels (krylov.hip)
+// values of the sliced ELLPACK copy of A: sl_val[p] = val[sl_idx[p]] (0 for padding)
+void launch_sell_values(int64_t total, const int32_t* sl_idx, const double2* val, double2* sl_val, hipStream_t st);
 // X complex FP64 or complex FP32 (double2 / float2); products and sums FP64
 template <class XT>
 void launch_spmm(const DeviceMesh& m, const double2* val, const XT* X, int64_t ldx, double2* Y,
