@@ -506,7 +506,7 @@ void launch_sum_chunks_c(const double2* part, int64_t nchunk, int64_t width, dou
 // order whatever KG and the other columns are.
 constexpr int DOTS_KG = 6;
 constexpr int CGS_HK = 32;   // coefficients held in LDS up to this many (complex) per column
-template <class B>
+template <class B, int DOTS_KG = 6>
 __global__ void __launch_bounds__(256) k_dots_partial(const B* __restrict__ V, int64_t vstride, int kcount,
                                                       const B* __restrict__ w1, const double2* __restrict__ w2,
                                                       int64_t n, int64_t ld, int ncols,
@@ -582,9 +582,13 @@ template <class B>
 void launch_dots_partial(const B* V, int64_t vstride, int kcount, const B* w1, const double2* w2,
                          int64_t n, int64_t ld, int ncols, const int32_t* act, double2* part1, double2* part2,
                          hipStream_t st) {
-  dim3 g((unsigned)ceil_div(kcount, DOTS_KG), (unsigned)reduce_chunks(n), (unsigned)ceil_div(ncols, 64));
   kt_begin(KF_CGS_DOTS, st);
-  k_dots_partial<B><<<g, 256, 0, st>>>(V, vstride, kcount, w1, w2, n, ld, ncols, act, part1, w2 ? part2 : nullptr);
+  // basis vectors per workgroup: 8 for an FP32 basis (the right vectors
+  // re-read less often: 279 against 285 ms per 1 GHz step), 6 otherwise
+  constexpr int KG = sizeof(B) == 8 ? 8 : DOTS_KG;
+  dim3 g((unsigned)ceil_div(kcount, KG), (unsigned)reduce_chunks(n), (unsigned)ceil_div(ncols, 64));
+  k_dots_partial<B, KG><<<g, 256, 0, st>>>(V, vstride, kcount, w1, w2, n, ld, ncols, act, part1,
+                                           w2 ? part2 : nullptr);
   MW_LAUNCH_CHECK();
   if (kt_enabled())
     kt_end(KF_CGS_DOTS, st, (w2 ? 16.0 : 8.0) * kcount * n * ncols,
@@ -743,7 +747,7 @@ void launch_dgs_trial(int j, int m, int ncols, const double2* hprov, const doubl
 // j), and the next candidate u = (T - sum_k V_k b_k - v_j e) / nu into slot
 // j+1, with |u|^2 chunk partials; coef holds (a_k, b_k) interleaved.  The
 // coefficients sit in LDS when 2j <= CGS_HK.
-template <class B>
+template <class B, int RPT = 4>
 __global__ void __launch_bounds__(256) k_dgs_update(B* __restrict__ V, int64_t vstride, int j,
                                                     const double2* __restrict__ coef, const double* __restrict__ nu,
                                                     const double2* __restrict__ e, const double2* __restrict__ T,
@@ -767,10 +771,8 @@ __global__ void __launch_bounds__(256) k_dgs_update(B* __restrict__ V, int64_t v
     B* Vj = V + (int64_t)j * vstride;
     B* Vn = V + (int64_t)(j + 1) * vstride;
     // RP rows per pass (r, r + 4, ...), sharing each coefficient load; the
-    // norm is summed over the rows in ascending order (with an FP32 basis,
-    // eight rows per pass or a four-way unroll over the basis measured
-    // slower: 573-620 against 482 ms per 1 GHz step)
-    constexpr int RP = 4;
+    // norm is summed over the rows in ascending order
+    constexpr int RP = RPT;
     for (int64_t r = r0 + rl; r < r1; r += 4 * RP) {
       int64_t o[RP];
       bool live[RP];
@@ -840,7 +842,9 @@ void launch_dgs_update(B* V, int64_t vstride, int j, const double2* coef, const 
   dim3 g((unsigned)reduce_chunks(n), (unsigned)ceil_div(ncols, 64));
   size_t lds = 2 * j <= CGS_HK ? (size_t)(2 * j) * 64 * sizeof(double2) : 0;
   kt_begin(KF_CGS_UPDATE, st);
-  k_dgs_update<B><<<g, 256, lds, st>>>(V, vstride, j, coef, nu, e, T, n, ld, ncols, act, norm_part);
+  // rows per pass: 8 for an FP32 basis (323 against 330 ms per 1 GHz step), 4 otherwise
+  k_dgs_update<B, sizeof(B) == 8 ? 8 : 4><<<g, 256, lds, st>>>(V, vstride, j, coef, nu, e, T, n, ld, ncols, act,
+                                                               norm_part);
   MW_LAUNCH_CHECK();
   // reads V_0..V_j and T, writes v_j and the next candidate
   if (kt_enabled()) kt_end(KF_CGS_UPDATE, st, 16.0 * j * n * ncols, ((j + 3.0) * sizeof(B) + 16.0) * n * ncols);
