@@ -683,8 +683,16 @@ __device__ __attribute__((always_inline)) inline void gemm3m_pairs(const typenam
   for (int k0 = 0; k0 < K; k0 += KS) {
     const bool more = k0 + KS < K;
     if (more) fetch(k0 + KS);
+    // the inverted diagonal block is triangular: the half of its columns
+    // on the far side of a wave's 32 rows is zero (unit lower: columns 32-63
+    // for rows 0-31; upper: columns 0-31 for rows 32-63), so that wave skips
+    // those stages' products and leaves the matrix units to the other
+    // workgroup on its SIMD
+    const bool zero_t = (lower && wm == 0 && k0 >= kd + 32 && k0 < kd + 64) ||
+                        (!lower && wm == 1 && k0 >= kd && k0 < kd + 32);
 #pragma unroll
     for (int kk = 0; kk < KS; kk += 4) {
+      if (zero_t) break;
       R a1[RB], a2[RB], a3[RB];
 #pragma unroll
       for (int x = 0; x < RB; ++x) {
