@@ -63,6 +63,19 @@ __device__ inline double bcast(double v, int t) {
   return __hiloint2double(hi, lo);
 }
 
+// acc += a x when ok (the same expression as every other product of A, so a
+// column's sum is bitwise the same in every form); a select, not a branch,
+// so that the loads feeding it are not moved under one
+__device__ inline void cmac_if(double2& acc, const double2& a, const double2& x, bool ok) {
+  const double rx = acc.x + (a.x * x.x - a.y * x.y);
+  const double ry = acc.y + (a.x * x.y + a.y * x.x);
+  acc.x = ok ? rx : acc.x;
+  acc.y = ok ? ry : acc.y;
+}
+
+// nonzeros per gather pass of the wide SpMM forms
+template <class XT> constexpr int SPMM_U = sizeof(XT) == 8 ? 4 : 2;
+
 template <int CPL, class XT>
 __global__ void __launch_bounds__(256) k_spmm_w(int64_t n, const int64_t* __restrict__ row_ptr,
                                                 const int32_t* __restrict__ col, const double2* __restrict__ val,
@@ -80,6 +93,11 @@ __global__ void __launch_bounds__(256) k_spmm_w(int64_t n, const int64_t* __rest
     double2 acc[CPL];
 #pragma unroll
     for (int q = 0; q < CPL; ++q) acc[q] = make_double2(0.0, 0.0);
+    // columns past ncols read column ncols - 1 and are never stored, so no
+    // load sits behind a per-column branch
+    int cq[CPL];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) cq[q] = min(c0 + lane + 64 * q, ncols - 1);
     for (int64_t kb = b; kb < e; kb += 64) {
       const int cnt = (int)min((int64_t)64, e - kb);
       int mycol = 0;
@@ -88,21 +106,30 @@ __global__ void __launch_bounds__(256) k_spmm_w(int64_t n, const int64_t* __rest
         mycol = col[kb + lane];
         myval = val[kb + lane];
       }
-#pragma unroll 4
-      for (int t = 0; t < cnt; ++t) {
-        const int64_t cc = __builtin_amdgcn_readlane(mycol, t);
-        double2 a;
-        a.x = bcast(myval.x, t);
-        a.y = bcast(myval.y, t);
-        const XT* xr = X + cc * ldx;
+      // SPMM_U nonzeros per pass: all their X rows are requested before the
+      // first product, so a wave keeps SPMM_U * CPL loads in flight; the
+      // passes past cnt read row mycol of a lane >= cnt (0) or of a lane
+      // wrapped round, which is in range, and add nothing
+      for (int t = 0; t < cnt; t += SPMM_U<XT>) {
+        int64_t cc[SPMM_U<XT>];
+        double2 a[SPMM_U<XT>];
 #pragma unroll
-        for (int q = 0; q < CPL; ++q) {
-          const int c = c0 + lane + 64 * q;
-          if (c < ncols) {
-            double2 x = bload(xr[c]);
-            acc[q].x += a.x * x.x - a.y * x.y;
-            acc[q].y += a.x * x.y + a.y * x.x;
-          }
+        for (int u = 0; u < SPMM_U<XT>; ++u) {
+          const int s = (t + u) & 63;
+          cc[u] = __builtin_amdgcn_readlane(mycol, s);
+          a[u].x = bcast(myval.x, s);
+          a[u].y = bcast(myval.y, s);
+        }
+        XT x[SPMM_U<XT>][CPL];
+#pragma unroll
+        for (int u = 0; u < SPMM_U<XT>; ++u)
+#pragma unroll
+          for (int q = 0; q < CPL; ++q) x[u][q] = X[cc[u] * ldx + cq[q]];
+#pragma unroll
+        for (int u = 0; u < SPMM_U<XT>; ++u) {
+          const bool ok = t + u < cnt;
+#pragma unroll
+          for (int q = 0; q < CPL; ++q) cmac_if(acc[q], a[u], bload(x[u][q]), ok);
         }
       }
     }
@@ -144,6 +171,9 @@ __global__ void __launch_bounds__(256) k_spmm_h(int64_t n, const int64_t* __rest
   const int64_t len = e - b;
   const int64_t len_o = __shfl_xor(len, 32);
   const int64_t len_max = len > len_o ? len : len_o;
+  int cq[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) cq[q] = min(lane + 32 * q, ncols - 1);
   for (int64_t kb = 0; kb < len_max; kb += 32) {
     const int cnt = (int)min((int64_t)32, len - kb);
     int mycol = 0;
@@ -153,23 +183,27 @@ __global__ void __launch_bounds__(256) k_spmm_h(int64_t n, const int64_t* __rest
       myval = val[b + kb + lane];
     }
     const int cnt_max = (int)min((int64_t)32, len_max - kb);
-#pragma unroll 4
-    for (int t = 0; t < cnt_max; ++t) {
-      const int64_t cc = __shfl(mycol, t, 32);
-      double2 a;
-      a.x = __shfl(myval.x, t, 32);
-      a.y = __shfl(myval.y, t, 32);
-      if (t < cnt) {
-        const XT* xr = X + cc * ldx;
+    // as in k_spmm_w: SPMM_U nonzeros' X rows requested before their products
+    for (int t = 0; t < cnt_max; t += SPMM_U<XT>) {
+      int64_t cc[SPMM_U<XT>];
+      double2 a[SPMM_U<XT>];
 #pragma unroll
-        for (int q = 0; q < CPL; ++q) {
-          const int c = lane + 32 * q;
-          if (c < ncols) {
-            double2 x = bload(xr[c]);
-            acc[q].x += a.x * x.x - a.y * x.y;
-            acc[q].y += a.x * x.y + a.y * x.x;
-          }
-        }
+      for (int u = 0; u < SPMM_U<XT>; ++u) {
+        const int s = (t + u) & 31;
+        cc[u] = __shfl(mycol, s, 32);
+        a[u].x = __shfl(myval.x, s, 32);
+        a[u].y = __shfl(myval.y, s, 32);
+      }
+      XT x[SPMM_U<XT>][CPL];
+#pragma unroll
+      for (int u = 0; u < SPMM_U<XT>; ++u)
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) x[u][q] = X[cc[u] * ldx + cq[q]];
+#pragma unroll
+      for (int u = 0; u < SPMM_U<XT>; ++u) {
+        const bool ok = t + u < cnt;
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) cmac_if(acc[q], a[u], bload(x[u][q]), ok);
       }
     }
   }
