@@ -635,14 +635,43 @@ __device__ __attribute__((always_inline)) inline void gemm3m_pairs(const typenam
     for (int y = 0; y < WC; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) { p1[x][y][r] = 0; p2[x][y][r] = 0; p3[x][y][r] = 0; }
-  C ra[AREG], rb[BREG];
-  auto fetch = [&](int k0) {
+  // Software pipeline: A (the factor rows, streamed from HBM) is requested
+  // two stages ahead into two alternating register sets, B (rows of Y,
+  // mostly in L2) one stage ahead.  Every load is unconditional (the
+  // requests past the last stage repeat its addresses; columns past N read
+  // column N - 1), and the diagonal block's masking and the zero columns are
+  // applied when the registers are written to LDS, so the only waits are at
+  // those writes.
+  C ra0[AREG], ra1[AREG], rb[BREG];
+  int aoff[AREG], boff[BREG];
+#pragma unroll
+  for (int e = 0; e < AREG; ++e) {
+    const int idx = tid + e * 256;
+    aoff[e] = (idx / KS) * (int)lda + idx % KS;
+  }
+#pragma unroll
+  for (int e = 0; e < BREG; ++e) {
+    const int idx = tid + e * 256;
+    boff[e] = (idx / TN) * (int)ldb + min(idx % TN, N - 1);
+  }
+  auto fetch_a = [&](int k0, C(&dst)[AREG]) {
+    const C* Ak = A + k0;
+#pragma unroll
+    for (int e = 0; e < AREG; ++e) dst[e] = Ak[aoff[e]];
+  };
+  auto fetch_b = [&](int k0) {
+    const C* Bk = B + (int64_t)k0 * ldb;
+#pragma unroll
+    for (int e = 0; e < BREG; ++e) rb[e] = Bk[boff[e]];
+  };
+  // LDS buffer buf <- stage k0 (A from src, B from rb)
+  auto store = [&](int buf, const C(&src)[AREG], int k0) {
     const bool tstage = k0 + KS > kd && k0 < kd + 64;   // same for the whole workgroup
 #pragma unroll
     for (int e = 0; e < AREG; ++e) {
       const int idx = tid + e * 256;
       const int r = idx / KS, kc = idx % KS;
-      C v = A[(int64_t)r * lda + k0 + kc];
+      C v = src[e];
       if (tstage) {
         const int j = k0 + kc - kd;
         if (j >= 0 && j < 64 && !(lower ? j < r : j >= r)) {
@@ -650,39 +679,26 @@ __device__ __attribute__((always_inline)) inline void gemm3m_pairs(const typenam
           v.y = 0;
         }
       }
-      ra[e] = v;
+      As[buf][r][kc] = v;
     }
 #pragma unroll
     for (int e = 0; e < BREG; ++e) {
       const int idx = tid + e * 256;
-      const int r = idx / TN, c = idx % TN;
-      C v;
-      v.x = 0;
-      v.y = 0;
-      if (c < N) v = B[(int64_t)(k0 + r) * ldb + c];
-      rb[e] = v;
+      C v = rb[e];
+      if (idx % TN >= N) {
+        v.x = 0;
+        v.y = 0;
+      }
+      Bs[buf][idx / TN][idx % TN] = v;
     }
   };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int e = 0; e < AREG; ++e) {
-      const int idx = tid + e * 256;
-      As[buf][idx / KS][idx % KS] = ra[e];
-    }
-#pragma unroll
-    for (int e = 0; e < BREG; ++e) {
-      const int idx = tid + e * 256;
-      Bs[buf][idx / TN][idx % TN] = rb[e];
-    }
-  };
-  // K is a multiple of KS (a difference of multiples of 8), at least 64
-  fetch(0);
-  store(0);
-  __syncthreads();
-  int buf = 0;
-  for (int k0 = 0; k0 < K; k0 += KS) {
-    const bool more = k0 + KS < K;
-    if (more) fetch(k0 + KS);
+  // stage k0 in LDS buffer buf: request B of the next stage and A of the
+  // one after (into a_next, whose stage is already in LDS), multiply, then
+  // write the next stage (A from a_stage) to the other buffer, which every
+  // wave finished reading before the previous barrier
+  auto step = [&](int k0, int buf, const C(&a_stage)[AREG], C(&a_next)[AREG]) {
+    fetch_b(min(k0 + KS, K - KS));
+    fetch_a(min(k0 + 2 * KS, K - KS), a_next);
     // the inverted diagonal block is triangular: the half of its columns
     // on the far side of a wave's 32 rows is zero (unit lower: columns 32-63
     // for rows 0-31; upper: columns 0-31 for rows 32-63), so that wave skips
@@ -692,7 +708,7 @@ __device__ __attribute__((always_inline)) inline void gemm3m_pairs(const typenam
                         (!lower && wm == 1 && k0 >= kd && k0 < kd + 32);
 #pragma unroll
     for (int kk = 0; kk < KS; kk += 4) {
-      if (zero_t) break;
+      if (zero_t || k0 >= K) break;
       R a1[RB], a2[RB], a3[RB];
 #pragma unroll
       for (int x = 0; x < RB; ++x) {
@@ -713,9 +729,21 @@ __device__ __attribute__((always_inline)) inline void gemm3m_pairs(const typenam
         }
       }
     }
-    if (more) store(buf ^ 1);
+    store(buf ^ 1, a_stage, k0 + KS);
     __syncthreads();
-    buf ^= 1;
+  };
+  // K is a multiple of KS (a difference of multiples of 8), at least 64
+  fetch_a(0, ra0);
+  fetch_b(0);
+  store(0, ra0, 0);
+  fetch_a(KS, ra1);
+  __syncthreads();
+  // stages in pairs, so that each register set keeps its role; with an odd
+  // number of stages the last pair's second stage lies past K and only
+  // loads (in range, clamped), writes LDS and waits
+  for (int k0 = 0; k0 < K; k0 += 2 * KS) {
+    step(k0, 0, ra1, ra0);
+    step(k0 + KS, 1, ra0, ra1);
   }
 #pragma unroll
   for (int x = 0; x < RB; ++x)
