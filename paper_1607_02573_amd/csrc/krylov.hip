@@ -539,7 +539,7 @@ void launch_sum_chunks_c(const double2* part, int64_t nchunk, int64_t width, dou
 // per KG vectors; every (k, c) sum runs over the chunk's rows in the same
 // order whatever KG and the other columns are.
 constexpr int DOTS_KG = 6;
-constexpr int CGS_HK = 32;   // coefficients held in LDS up to this many (complex) per column
+constexpr int CGS_HK = 64;   // coefficients held in LDS up to this many (complex) per column
 template <class B, int DOTS_KG = 6>
 __global__ void __launch_bounds__(256) k_dots_partial(const B* __restrict__ V, int64_t vstride, int kcount,
                                                       const B* __restrict__ w1, const double2* __restrict__ w2,
@@ -781,7 +781,7 @@ void launch_dgs_trial(int j, int m, int ncols, const double2* hprov, const doubl
 // j), and the next candidate u = (T - sum_k V_k b_k - v_j e) / nu into slot
 // j+1, with |u|^2 chunk partials; coef holds (a_k, b_k) interleaved.  The
 // coefficients sit in LDS when 2j <= CGS_HK.
-template <class B, int RPT = 4>
+template <class B, int RPT, bool CF_LDS>
 __global__ void __launch_bounds__(256) k_dgs_update(B* __restrict__ V, int64_t vstride, int j,
                                                     const double2* __restrict__ coef, const double* __restrict__ nu,
                                                     const double2* __restrict__ e, const double2* __restrict__ T,
@@ -793,8 +793,7 @@ __global__ void __launch_bounds__(256) k_dgs_update(B* __restrict__ V, int64_t v
   const int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
   const int c = blockIdx.y * 64 + cl;
   const int64_t r0 = (int64_t)chunk * RCHUNK, r1 = min(n, r0 + RCHUNK);
-  const bool in_lds = 2 * j <= CGS_HK;
-  if (in_lds) {
+  if (CF_LDS) {
     for (int k = rl; k < 2 * j; k += 4) cf[k * 64 + cl] = c < ncols ? coef[(int64_t)k * ncols + c] : make_double2(0.0, 0.0);
     __syncthreads();
   }
@@ -808,35 +807,46 @@ __global__ void __launch_bounds__(256) k_dgs_update(B* __restrict__ V, int64_t v
     // norm is summed over the rows in ascending order
     constexpr int RP = RPT;
     for (int64_t r = r0 + rl; r < r1; r += 4 * RP) {
+      // rows past the chunk read its last row (every load unconditional,
+      // so none waits behind a branch) and are neither stored nor summed
       int64_t o[RP];
       bool live[RP];
-      double2 y[RP], u[RP];
 #pragma unroll
       for (int q = 0; q < RP; ++q) {
         live[q] = r + 4 * q < r1;
-        o[q] = (r + 4 * q) * ld + c;
-        y[q] = live[q] ? bload(Vj[o[q]]) : make_double2(0.0, 0.0);
-        u[q] = live[q] ? T[o[q]] : make_double2(0.0, 0.0);
+        o[q] = (live[q] ? r + 4 * q : r1 - 1) * ld + c;
       }
-      // the raw values of basis vector k + 1 are loaded while vector k is
-      // applied (two vectors' loads in flight for a few registers; 331
-      // against 482 ms per 1 GHz step with an FP32 basis, against an
-      // unrolled loop that converted at the load)
-      B nxt[RP];
+      B yr[RP];
+      double2 u[RP];
 #pragma unroll
-      for (int q = 0; q < RP; ++q) nxt[q] = (live[q] && j > 0) ? V[o[q]] : B{};
-#pragma unroll 1
-      for (int k = 0; k < j; ++k) {
-        B cur[RP];
+      for (int q = 0; q < RP; ++q) {
+        yr[q] = Vj[o[q]];
+        u[q] = T[o[q]];
+      }
+      // basis vectors two ahead: n0 holds V_k for even k, n1 for odd k,
+      // each reloaded with V_{k+2} (clamped to V_{j-1}) right after its use,
+      // so that two vectors' loads are in flight while one is applied
+      const int jl = j > 0 ? j - 1 : 0;
+      B n0[RP], n1[RP];
 #pragma unroll
-        for (int q = 0; q < RP; ++q) cur[q] = nxt[q];
-        if (k + 1 < j) {
-          const B* Vn1 = V + (int64_t)(k + 1) * vstride;
+      for (int q = 0; q < RP; ++q) {
+        n0[q] = V[o[q]];
+        n1[q] = V[(int64_t)min(1, jl) * vstride + o[q]];
+      }
+      double2 y[RP];
 #pragma unroll
-          for (int q = 0; q < RP; ++q) nxt[q] = live[q] ? Vn1[o[q]] : B{};
+      for (int q = 0; q < RP; ++q) y[q] = bload(yr[q]);
+      auto apply = [&](int k, B(&cur)[RP]) {
+        // (LDS or global by template: a select between the two would make
+        // a flat load, which waits for every load in flight)
+        double2 ak, bk;
+        if constexpr (CF_LDS) {
+          ak = cf[(2 * k) * 64 + cl];
+          bk = cf[(2 * k + 1) * 64 + cl];
+        } else {
+          ak = coef[(int64_t)(2 * k) * ncols + c];
+          bk = coef[(int64_t)(2 * k + 1) * ncols + c];
         }
-        const double2 ak = in_lds ? cf[(2 * k) * 64 + cl] : coef[(int64_t)(2 * k) * ncols + c];
-        const double2 bk = in_lds ? cf[(2 * k + 1) * 64 + cl] : coef[(int64_t)(2 * k + 1) * ncols + c];
 #pragma unroll
         for (int q = 0; q < RP; ++q) {
           const double2 v = bload(cur[q]);
@@ -845,6 +855,14 @@ __global__ void __launch_bounds__(256) k_dgs_update(B* __restrict__ V, int64_t v
           u[q].x -= v.x * bk.x - v.y * bk.y;
           u[q].y -= v.x * bk.y + v.y * bk.x;
         }
+        const B* Vk2 = V + (int64_t)min(k + 2, jl) * vstride;
+#pragma unroll
+        for (int q = 0; q < RP; ++q) cur[q] = Vk2[o[q]];
+      };
+#pragma unroll 1
+      for (int k = 0; k < j; k += 2) {
+        apply(k, n0);
+        if (k + 1 < j) apply(k + 1, n1);
       }
 #pragma unroll
       for (int q = 0; q < RP; ++q) {
@@ -877,8 +895,12 @@ void launch_dgs_update(B* V, int64_t vstride, int j, const double2* coef, const 
   size_t lds = 2 * j <= CGS_HK ? (size_t)(2 * j) * 64 * sizeof(double2) : 0;
   kt_begin(KF_CGS_UPDATE, st);
   // rows per pass: 8 for an FP32 basis (323 against 330 ms per 1 GHz step), 4 otherwise
-  k_dgs_update<B, sizeof(B) == 8 ? 8 : 4><<<g, 256, lds, st>>>(V, vstride, j, coef, nu, e, T, n, ld, ncols, act,
-                                                               norm_part);
+  if (2 * j <= CGS_HK)
+    k_dgs_update<B, sizeof(B) == 8 ? 8 : 4, true><<<g, 256, lds, st>>>(V, vstride, j, coef, nu, e, T, n, ld, ncols,
+                                                                     act, norm_part);
+  else
+    k_dgs_update<B, sizeof(B) == 8 ? 8 : 4, false><<<g, 256, 0, st>>>(V, vstride, j, coef, nu, e, T, n, ld, ncols,
+                                                                    act, norm_part);
   MW_LAUNCH_CHECK();
   // reads V_0..V_j and T, writes v_j and the next candidate
   if (kt_enabled()) kt_end(KF_CGS_UPDATE, st, 16.0 * j * n * ncols, ((j + 3.0) * sizeof(B) + 16.0) * n * ncols);
