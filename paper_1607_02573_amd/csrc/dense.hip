@@ -611,21 +611,23 @@ __global__ void __launch_bounds__(256) k_scale_offdiag(typename cplx<R>::t* F, c
 // arrays; 3.5 ms less per preconditioner application on the 1 GHz chamber
 // at 160 columns).  C aliases B's first or last 64 rows; every B read
 // precedes the first C write.
-template <class R, int WC>
+template <class R, int WC, int WNW = 2>
 __device__ __attribute__((always_inline)) inline void gemm3m_pairs(const typename cplx<R>::t* __restrict__ A,
                                                                    int64_t lda, const typename cplx<R>::t* B,
                                                                    int64_t ldb, typename cplx<R>::t* Cm, int64_t ldc,
                                                                    int N, int K, int kd, int amode) {
   using C = typename cplx<R>::t;
   using acc_t = typename Mf<R>::acc;
-  constexpr int RB = 2, TM = 64, TN = 32 * WC, KS = G3K;
+  // WNW waves along N (2: 32-row, 16 WC-column wave tiles; 1: 16-row wave
+  // tiles over all TN = 16 WC columns)
+  constexpr int WMW = 4 / WNW, RB = 4 / WMW, TM = 64, TN = 16 * WC * WNW, KS = G3K;
   constexpr int AREG = TM * KS / 256;
-  constexpr int BREG = KS * TN / 256;
+  constexpr int BREG = (KS * TN + 255) / 256;
   __shared__ C As[2][TM][KS + 1];
   __shared__ C Bs[2][KS][TN + 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WNW, wn = wave % WNW;
   const int li = lane & 15, kq = lane >> 4;
   const bool lower = amode == 1;
   acc_t p1[RB][WC], p2[RB][WC], p3[RB][WC];
@@ -651,7 +653,7 @@ __device__ __attribute__((always_inline)) inline void gemm3m_pairs(const typenam
   }
 #pragma unroll
   for (int e = 0; e < BREG; ++e) {
-    const int idx = tid + e * 256;
+    const int idx = min(tid + e * 256, KS * TN - 1);
     boff[e] = (idx / TN) * (int)ldb + min(idx % TN, N - 1);
   }
   auto fetch_a = [&](int k0, C(&dst)[AREG]) {
@@ -684,6 +686,7 @@ __device__ __attribute__((always_inline)) inline void gemm3m_pairs(const typenam
 #pragma unroll
     for (int e = 0; e < BREG; ++e) {
       const int idx = tid + e * 256;
+      if ((KS * TN) % 256 != 0 && idx >= KS * TN) break;
       C v = rb[e];
       if (idx % TN >= N) {
         v.x = 0;
@@ -699,13 +702,14 @@ __device__ __attribute__((always_inline)) inline void gemm3m_pairs(const typenam
   auto step = [&](int k0, int buf, const C(&a_stage)[AREG], C(&a_next)[AREG]) {
     fetch_b(min(k0 + KS, K - KS));
     fetch_a(min(k0 + 2 * KS, K - KS), a_next);
-    // the inverted diagonal block is triangular: the half of its columns
-    // on the far side of a wave's 32 rows is zero (unit lower: columns 32-63
-    // for rows 0-31; upper: columns 0-31 for rows 32-63), so that wave skips
+    // the inverted diagonal block is triangular: its columns on the far
+    // side of a wave's rows are zero (unit lower: columns past the wave's
+    // last row; upper: columns before its first row), so the wave skips
     // those stages' products and leaves the matrix units to the other
-    // workgroup on its SIMD
-    const bool zero_t = (lower && wm == 0 && k0 >= kd + 32 && k0 < kd + 64) ||
-                        (!lower && wm == 1 && k0 >= kd && k0 < kd + 32);
+    // workgroups on its SIMD
+    constexpr int RW = 16 * RB;   // rows per wave
+    const bool zero_t = (lower && k0 >= kd + RW * (wm + 1) && k0 < kd + 64) ||
+                        (!lower && k0 >= kd && k0 + KS <= kd + RW * wm);
 #pragma unroll
     for (int kk = 0; kk < KS; kk += 4) {
       if (zero_t || k0 >= K) break;
@@ -772,7 +776,7 @@ __device__ __attribute__((always_inline)) inline void gemm3m_pairs(const typenam
 // XCD x takes the subdomains of rank x, x + 8, x + 16, ... in decreasing
 // size (order[]), all column tiles of one subdomain on one XCD, so the
 // longest sweeps start first and the XCDs get alike shares.
-template <class R, int WC, int DIRS>
+template <class R, int WC, int DIRS, int WNW = 2>
 __global__ void __launch_bounds__(256, 2) k_row_sweep(const typename cplx<R>::t* F, const int64_t* __restrict__ fac_off,
                                                       const int32_t* __restrict__ n_pad,
                                                       const int64_t* __restrict__ loc_off, typename cplx<R>::t* Y,
@@ -791,7 +795,7 @@ __global__ void __launch_bounds__(256, 2) k_row_sweep(const typename cplx<R>::t*
   const int tn = q % tiles_n;
   const int np = n_pad[i];
   const int nblk = np / NB;
-  constexpr int TN = WC * 32;
+  constexpr int TN = WC * 16 * WNW;
   const int N = min(ncols - tn * TN, TN);
   const C* Fi = F + fac_off[i];
   const int64_t* bo = boff + (int64_t)i * bstride;
@@ -812,7 +816,7 @@ __global__ void __launch_bounds__(256, 2) k_row_sweep(const typename cplx<R>::t*
     const int2 e0 = ei[2 * b], e1 = ei[2 * b + 1];
     const int kb = fwd ? min(min(e0.x, e1.x), r0) : r0;
     const int ke = fwd ? r0 + NB : min(np, max(max(e0.y, e1.y), r0 + NB));
-    gemm3m_pairs<R, WC>(frow(Fi, bo, bl, bwi, r0) + kb, bwi[b], Yi + (int64_t)kb * ld, ld, Yi + (int64_t)r0 * ld,
+    gemm3m_pairs<R, WC, WNW>(frow(Fi, bo, bl, bwi, r0) + kb, bwi[b], Yi + (int64_t)kb * ld, ld, Yi + (int64_t)r0 * ld,
                         ld, N, ke - kb, r0 - kb, fwd ? 1 : 2);
     __syncthreads();
   }
@@ -2039,12 +2043,12 @@ static void bwd_rec(const DeviceDecomp& d, const typename cplx<R>::t* F, typenam
   bwd_rec<R>(d, F, Y, ncols, ld, b0, mid, st);
 }
 
-template <class R, int WC, int DIRS>
+template <class R, int WC, int DIRS, int WNW = 2>
 static void launch_row_sweep_wc(const DeviceDecomp& d, const typename cplx<R>::t* F, typename cplx<R>::t* Y,
                                 int64_t ld, int ncols, hipStream_t st) {
-  const int tiles_n = (int)ceil_div(ncols, WC * 32);
+  const int tiles_n = (int)ceil_div(ncols, WC * 16 * WNW);
   const int64_t G = 8 * ceil_div(d.nsub, 8) * (int64_t)tiles_n;
-  k_row_sweep<R, WC, DIRS><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, Y, ld, ncols, tiles_n,
+  k_row_sweep<R, WC, DIRS, WNW><<<(unsigned)G, 256, 0, st>>>(F, d.fac_off, d.n_pad, d.loc_off, Y, ld, ncols, tiles_n,
                                                         d.nsub, d.order, d.row_lo, d.env, d.env_stride, d.boff,
                                                         d.blo, d.bw, d.bstride);
   MW_LAUNCH_CHECK();
@@ -2062,7 +2066,15 @@ static void launch_row_sweep(const DeviceDecomp& d, const typename cplx<R>::t* F
     case 2: launch_row_sweep_wc<R, 2, DIRS>(d, F, Y, ld, ncols, st); break;
     case 3: launch_row_sweep_wc<R, sizeof(R) == 4 ? 3 : 2, DIRS>(d, F, Y, ld, ncols, st); break;
     case 4: launch_row_sweep_wc<R, sizeof(R) == 4 ? 4 : 2, DIRS>(d, F, Y, ld, ncols, st); break;
-    default: launch_row_sweep_wc<R, sizeof(R) == 4 ? 5 : 2, DIRS>(d, F, Y, ld, ncols, st); break;
+    default:
+      // complex FP32, 129-160 columns: two 80-column tiles of four 16-row
+      // wave tiles (127 VGPRs, four workgroups per CU) rather than one
+      // 160-column tile of 32-row wave tiles (208 VGPRs, two per CU); the
+      // second tile's factor reads mostly hit the XCD's L2 (26.5 against
+      // 27.2 ms per application on the 1 GHz chamber)
+      if constexpr (sizeof(R) == 4) launch_row_sweep_wc<R, 5, DIRS, 1>(d, F, Y, ld, ncols, st);
+      else launch_row_sweep_wc<R, 2, DIRS>(d, F, Y, ld, ncols, st);
+      break;
   }
   // algorithmic work per block: the triangular solve with the diagonal
   // block (m rows) and the product with the off-diagonal entries inside the
