@@ -934,10 +934,15 @@ __global__ void __launch_bounds__(256) k_amax(const typename cplx<R>::t* __restr
     const int c0 = fenv[(int64_t)i * fstride + g], w = min(fenv_hi[(int64_t)i * fstride + g], np) - c0;
     const auto* Pg = frow(Fi, bo, bl, bwi, 32 * g) + c0;   // the group's 32 rows: one block
     const int64_t ldg = bwi[g >> 1];
-    for (int k = threadIdx.x; k < 32 * w; k += 256) {
-      auto v = Pg[(k / w) * ldg + k % w];
-      double a = fabs((double)v.x) + fabs((double)v.y);
-      m = (a > m || a != a) ? a : m;   // a NaN entry makes the maximum NaN
+    // wave rows rr, rr + 4, ..., lanes along the row (no index division)
+    for (int rr = threadIdx.x >> 6; rr < 32; rr += 4) {
+      const auto* pr = Pg + rr * ldg;
+#pragma unroll 4
+      for (int k = threadIdx.x & 63; k < w; k += 64) {
+        const auto v = pr[k];
+        const double a = fabs((double)v.x) + fabs((double)v.y);
+        m = (a > m || a != a) ? a : m;   // a NaN entry makes the maximum NaN
+      }
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
