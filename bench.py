@@ -44,8 +44,8 @@ FP64_MFMA_FAMILIES = ("bgs_dots", "bgs_update")
 # known size (--copy-probe-mib).  Valid only for the kernel source it was
 # taken on: a different hash of that file reports null.
 PMC_TRAFFIC = {"family": "trsm_gemm", "source": "paper_1607_02573_amd/csrc/dense.hip",
-               "sha256": "6ada1f2089db68f968a52ea533f2a2e88315adde3ed8b7a8889931dbc2fd56b9",
-               "bytes_per_launch": 9.145e10}   # FETCH 7.902e10 + WRITE 1.242e10 (pmc_row_sweep_chamber10_mixed)
+               "sha256": "bea924fae70f20f8c33e40644df2ef35a9e5f4525516ed97ffd74958c3d89e38",
+               "bytes_per_launch": 1.0437e11}   # FETCH 9.194e10 + WRITE 1.243e10 (pmc_row_sweep_chamber10_mixed)
 
 
 def measured_traffic(family: str):
