@@ -208,7 +208,7 @@ void launch_sum_chunks_c(const double2* part, int64_t nchunk, int64_t width, dou
 void launch_dgs_step(int j, int m, bool fin, int ncols, const double2* P1, const double2* P2, const double* beta2,
                      double2* Hraw, double2* H, double* cs, double2* sn, double2* g, double2* hprov, double2* coef,
                      double* nu, double2* e, int32_t* kdim, int32_t* act, double* resid, const double* bnorm,
-                     double tol, hipStream_t st);
+                     double tol, double2* Rc, hipStream_t st);
 void launch_dgs_trial(int j, int m, int ncols, const double2* hprov, const double* beta2, const double* cs,
                       const double2* sn, const double2* g, const int32_t* act, const double* bnorm, double tol,
                       int32_t* done, hipStream_t st);
@@ -221,6 +221,7 @@ void launch_scale_cols(B* w, int64_t n, int64_t ld, int ncols, const double* nrm
                        hipStream_t st);
 void launch_backsolve(int m, int ncols, const double2* H, const double2* g, const int32_t* kdim, double2* y,
                       hipStream_t st);
+void launch_candsolve(int m, int ncols, const double2* Rc, const int32_t* kdim, double2* y, hipStream_t st);
 template <class B>
 void launch_combine(const B* V, int64_t vstride, int m, const double2* y, const int32_t* kdim,
                     double2* u, int64_t n, int64_t ld, int ncols, hipStream_t st);

@@ -659,7 +659,8 @@ __global__ void k_dgs_step(int j, int m, int fin, int ncols, const double2* __re
                            double* __restrict__ cs, double2* __restrict__ sn, double2* __restrict__ g,
                            double2* __restrict__ hprov, double2* __restrict__ coef, double* __restrict__ nu_out,
                            double2* __restrict__ e_out, int32_t* __restrict__ kdim, int32_t* __restrict__ act,
-                           double* __restrict__ resid, const double* __restrict__ bnorm, double tol) {
+                           double* __restrict__ resid, const double* __restrict__ bnorm, double tol,
+                           double2* __restrict__ Rc) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncols || !act[c]) return;
   auto at = [&](const double2* X, int i) { return X[(int64_t)i * ncols + c]; };
@@ -732,14 +733,20 @@ __global__ void k_dgs_step(int j, int m, int fin, int ncols, const double2* __re
   }
   nu_out[c] = nu;
   e_out[c] = e;
+  if (Rc) {
+    // column j of the triangular factor relating the candidates to the basis:
+    // y_j = nu v_j + sum_k a_k v_k
+    for (int k = 0; k < j; ++k) Rc[((int64_t)k * m + j) * ncols + c] = at(P1, k);
+    Rc[((int64_t)j * m + j) * ncols + c] = make_double2(nu, 0.0);
+  }
 }
 
 void launch_dgs_step(int j, int m, bool fin, int ncols, const double2* P1, const double2* P2, const double* beta2,
                      double2* Hraw, double2* H, double* cs, double2* sn, double2* g, double2* hprov, double2* coef,
                      double* nu, double2* e, int32_t* kdim, int32_t* act, double* resid, const double* bnorm,
-                     double tol, hipStream_t st) {
+                     double tol, double2* Rc, hipStream_t st) {
   k_dgs_step<<<(unsigned)ceil_div(ncols, 64), 64, 0, st>>>(j, m, fin ? 1 : 0, ncols, P1, P2, beta2, Hraw, H, cs, sn,
-                                                          g, hprov, coef, nu, e, kdim, act, resid, bnorm, tol);
+                                                          g, hprov, coef, nu, e, kdim, act, resid, bnorm, tol, Rc);
   MW_LAUNCH_CHECK();
 }
 
@@ -949,6 +956,25 @@ __global__ void k_backsolve(int m, int ncols, const double2* __restrict__ H, con
 void launch_backsolve(int m, int ncols, const double2* H, const double2* g, const int32_t* kdim, double2* y,
                       hipStream_t st) {
   k_backsolve<<<(unsigned)ceil_div(ncols, 64), 64, 0, st>>>(m, ncols, H, g, kdim, y);
+  MW_LAUNCH_CHECK();
+}
+
+// y <- Rc^-1 y on the Krylov dimension of each column (Rc upper triangular,
+// m x m per column, as written by k_dgs_step): the coefficients of the
+// combination of the operator's inputs (the candidates) equal to V y
+__global__ void k_candsolve(int m, int ncols, const double2* __restrict__ Rc, const int32_t* __restrict__ kdim,
+                            double2* __restrict__ y) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  int kk = kdim[c];
+  for (int i = kk - 1; i >= 0; --i) {
+    double2 s = y[(int64_t)i * ncols + c];
+    for (int t = i + 1; t < kk; ++t) s = csub(s, cmul(Rc[((int64_t)i * m + t) * ncols + c], y[(int64_t)t * ncols + c]));
+    y[(int64_t)i * ncols + c] = cmul(s, cinv(Rc[((int64_t)i * m + i) * ncols + c]));
+  }
+}
+void launch_candsolve(int m, int ncols, const double2* Rc, const int32_t* kdim, double2* y, hipStream_t st) {
+  k_candsolve<<<(unsigned)ceil_div(ncols, 64), 64, 0, st>>>(m, ncols, Rc, kdim, y);
   MW_LAUNCH_CHECK();
 }
 
