@@ -112,11 +112,11 @@ struct Work {
 struct GmresWork {
   Work V, X, B, Z, Y, H, Hr, cs, sn, g, y, h1, h2, hp, cf, nu, ee, part, npart, vec, ints, tmp, w_idx;
   Work cq, cw, cy;            // two-level: Q v, FP64 copy of an FP32 basis vector, coarse vector
-  Work rc;                    // one level, FP32 basis: the candidates' triangular factor
+  Work zc, rc;                // FP32 basis: preconditioned candidates and their triangular factor
   hipStream_t st = nullptr;   // the stream this driver's work runs on
-  std::array<Work*, 27> all() {
+  std::array<Work*, 28> all() {
     return {&V, &X, &B, &Z, &Y, &H, &Hr, &cs, &sn, &g, &y, &h1, &h2, &hp, &cf, &nu, &ee, &part, &npart, &vec, &ints,
-            &tmp, &w_idx, &cq, &cw, &cy, &rc};
+            &tmp, &w_idx, &cq, &cw, &cy, &zc, &rc};
   }
   void release() {
     for (Work* w : all()) w->b.release();
@@ -767,9 +767,12 @@ int64_t gmres_bytes_per_col(mw_problem* p, int m, bool block) {
   const int64_t bsz = (!block && basis_fp32(p)) ? 8 : 16;   // block GMRES keeps an FP64 basis
   int64_t big = (int64_t)(m + 1) * p->T.n() * bsz + 4 * p->T.n() * 16 + p->dd.sum_pad * esz +
                 reduce_chunks(p->T.n()) * (2 * m + 3) * 16;
-  // FP32 basis: the m preconditioned candidates in FP32 (one level), or an
-  // FP64 copy of v_j (two-level)
-  if (bsz == 8) big += std::max((int64_t)m * 8, (int64_t)16) * p->T.n();
+  // FP32 basis: the m preconditioned candidates in FP32, and for the
+  // two-level preconditioner an FP64 copy of v_j
+  if (bsz == 8) {
+    big += (int64_t)m * 8 * p->T.n();
+    if (p->coarse_kind != MW_COARSE_NONE) big += p->T.n() * 16;
+  }
   if (p->coarse_kind != MW_COARSE_NONE)   // two-level: Q v and the coarse vector
     big += p->T.n() * 16 + (int64_t)round_up(3 * (int64_t)std::max(p->D.nsub, 1), 64) * esz;
   // Hessenberg (raw and rotated), rotations, g, y, dot sums, provisional
@@ -838,12 +841,12 @@ void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, co
   int32_t* act = ivec;
   int32_t* kdim = ivec + nc;
   int32_t* done = ivec + 2 * nc;
-  // FP32 basis, one level: the operator's inputs are kept (M^-1 of each
-  // candidate, FP32, as the SpMM reads it) with the triangular factor Rc
-  // relating the candidates to the basis, so that the cycle ends with
-  // x += Zc Rc^-1 y instead of one more preconditioner application
-  const bool keep_z = std::is_same<BT, float2>::value && !p->coarse_active;
-  float2* Zc = keep_z ? (float2*)W.cw.get(c, (int64_t)m * vstride * 8) : nullptr;
+  // FP32 basis: the operator's inputs are kept (M^-1 of each candidate,
+  // FP32, as the SpMM reads it) with the triangular factor Rc relating the
+  // candidates to the basis, so that the cycle ends with x += Zc Rc^-1 y
+  // instead of one more preconditioner application
+  const bool keep_z = std::is_same<BT, float2>::value;
+  float2* Zc = keep_z ? (float2*)W.zc.get(c, (int64_t)m * vstride * 8) : nullptr;
   double2* Rc = keep_z ? (double2*)W.rc.get(c, (int64_t)m * m * nc * 16) : nullptr;
   std::vector<double2> g0((size_t)nc);
   int nact = 0;
@@ -870,12 +873,17 @@ void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, co
     for (int pass = 0; pass < 2; ++pass) {
       if (more) {
         if (keep_z) {
-          // FP32 basis, one level: M^-1 v_j is rounded to FP32 as well (the
-          // product A M^-1 v_j is FP64 either way; the rounding perturbs the
-          // Arnoldi relation no more than the basis' own)
+          // FP32 basis: M^-1 v_j is rounded to FP32 as well (the product
+          // A M^-1 v_j is FP64 either way; the rounding perturbs the Arnoldi
+          // relation no more than the basis' own)
           float2* Zf = Zc + (int64_t)j * vstride;
           MW_CHECK(p->factors_valid, MW_EINVAL, "no valid subdomain factors: call mw_factor_subdomains");
-          one_level<BT, float2>(p, W, Vj, Zf, nc, ld);
+          if (!p->coarse_active) {
+            one_level<BT, float2>(p, W, Vj, Zf, nc, ld);
+          } else {
+            apply_prec(p, W, Vj, Z, nc, ld);
+            launch_narrow(Z, Zf, vstride, st);
+          }
           launch_spmm(p->dm, p->val.as<double2>(), (const float2*)Zf, ld, T, ld, nc, nullptr, 0, st);
         } else {
           apply_prec(p, W, Vj, Z, nc, ld);

@@ -228,6 +228,8 @@ void launch_combine(const B* V, int64_t vstride, int m, const double2* y, const 
 void launch_axpy_cols(double2* x, const double2* z, int64_t n, int64_t ld, int ncols, hipStream_t st);
 // dst[i] = src[i] widened to complex FP64
 void launch_widen(const float2* src, double2* dst, int64_t count, hipStream_t st);
+// dst[i] = src[i] rounded to complex FP32
+void launch_narrow(const double2* src, float2* dst, int64_t count, hipStream_t st);
 template <class B>
 void launch_start_cycle(const double2* r, B* v0, int64_t n, int64_t ld, int ncols, const double* rn2,
                         const int32_t* act, hipStream_t st);

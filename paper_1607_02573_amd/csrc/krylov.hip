@@ -1052,6 +1052,15 @@ void launch_widen(const float2* src, double2* dst, int64_t count, hipStream_t st
   k_widen<<<(unsigned)ceil_div(count, 256), 256, 0, st>>>(src, dst, count);
   MW_LAUNCH_CHECK();
 }
+__global__ void k_narrow(const double2* __restrict__ src, float2* __restrict__ dst, int64_t count) {
+  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (id < count) dst[id] = bstore<float2>(src[id]);
+}
+void launch_narrow(const double2* src, float2* dst, int64_t count, hipStream_t st) {
+  if (count <= 0) return;
+  k_narrow<<<(unsigned)ceil_div(count, 256), 256, 0, st>>>(src, dst, count);
+  MW_LAUNCH_CHECK();
+}
 
 __global__ void k_copy_cols(const double2* __restrict__ src, int64_t lds, double2* __restrict__ dst, int64_t ldd,
                             int64_t n, int ncols) {
