@@ -336,8 +336,9 @@ def main():
     ap.add_argument("--block", type=int, default=0, choices=(0, 32),
                     help="0: pseudo-block GMRES; 32: block GMRES with blocks of 32 right-hand sides")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--basis", choices=("auto", "fp64"), default="auto",
-                    help="Krylov basis of the mixed-precision solves: complex FP32 (auto) or complex FP64")
+    ap.add_argument("--basis", choices=("auto", "fp64", "fp32-lean"), default="auto",
+                    help="Krylov basis of the mixed-precision solves: complex FP32 with the preconditioned "
+                         "candidates kept (auto), complex FP32 without them (fp32-lean) or complex FP64")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain elementwise copy (torch.neg) of this many MiB, the known-size "
                          "kernel that calibrates rocprofv3's FETCH_SIZE / WRITE_SIZE counters")

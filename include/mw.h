@@ -69,7 +69,7 @@ typedef enum { MW_FACTOR_AUTO = 0, MW_FACTOR_LU = 1, MW_FACTOR_LDLT = 2 } mw_fac
 /* Form of the subdomain triangular solves (mw_set_solve_form). */
 typedef enum { MW_SOLVE_AUTO = 0, MW_SOLVE_RECURSIVE = 1, MW_SOLVE_ROWS = 2 } mw_solve_form;
 /* Precision of the GMRES Krylov basis (mw_set_krylov_basis). */
-typedef enum { MW_BASIS_AUTO = 0, MW_BASIS_FP64 = 1 } mw_krylov_basis;
+typedef enum { MW_BASIS_AUTO = 0, MW_BASIS_FP64 = 1, MW_BASIS_FP32_LEAN = 2 } mw_krylov_basis;
 /* Coarse space of the two-level preconditioner (mw_set_coarse_space). */
 typedef enum { MW_COARSE_NONE = 0, MW_COARSE_CONST = 1 } mw_coarse_space;
 
@@ -250,7 +250,15 @@ mw_status mw_set_solve_form(mw_problem *p, int32_t form);
  * basis only rounds the stored vectors (relative 6e-8), which perturbs the
  * Arnoldi relation of a restart cycle by about that much of the cycle's
  * starting residual, while the stopping test is always taken on the true
- * FP64 residual at the restart.  It halves the bytes of Gram-Schmidt.  Block
+ * FP64 residual at the restart.  It halves the bytes of Gram-Schmidt.  With
+ * the FP32 basis the operator's inputs M^-1 y_j (y_j the Arnoldi candidates)
+ * are rounded to FP32 and kept, so that a restart cycle ends with
+ * x += [M^-1 y_0 ...] R^-1 y (R relating the candidates to the basis)
+ * instead of one more preconditioner application: the update is consistent
+ * with the Arnoldi relation, which saves the iterations the next cycle
+ * would spend on the preconditioner's rounding.  MW_BASIS_FP32_LEAN: FP32
+ * basis without the kept inputs (m n 8 bytes less per column, one more
+ * preconditioner application per cycle), for memory-bound batching.  Block
  * GMRES keeps an FP64 basis.  Takes effect at the next solve.  MW_EINVAL for
  * an unknown kind. */
 mw_status mw_set_krylov_basis(mw_problem *p, int32_t kind);

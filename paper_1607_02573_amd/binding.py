@@ -19,7 +19,7 @@ MW_OK, MW_EINVAL, MW_ENOMEM, MW_ESINGULAR, MW_ENOCONV, MW_ENUMERIC, MW_EDEVICE =
 MW_C128, MW_C64 = 0, 1
 MW_FACTOR_AUTO, MW_FACTOR_LU, MW_FACTOR_LDLT = 0, 1, 2
 MW_SOLVE_AUTO, MW_SOLVE_RECURSIVE, MW_SOLVE_ROWS = 0, 1, 2
-MW_BASIS_AUTO, MW_BASIS_FP64 = 0, 1
+MW_BASIS_AUTO, MW_BASIS_FP64, MW_BASIS_FP32_LEAN = 0, 1, 2
 MW_COARSE_NONE, MW_COARSE_CONST = 0, 1
 STATUS_NAMES = {0: "MW_OK", -1: "MW_EINVAL", -2: "MW_ENOMEM", -3: "MW_ESINGULAR", -4: "MW_ENOCONV",
                 -5: "MW_ENUMERIC", -6: "MW_EDEVICE"}

@@ -758,7 +758,9 @@ void colnorm2(mw_problem* p, GmresWork& W, const double2* V, int64_t ld, int nc,
 
 // whether GMRES keeps its Krylov basis in complex FP32: with FP32 factors,
 // unless an FP64 basis was asked for
-bool basis_fp32(mw_problem* p) { return p->prec == MW_C64 && p->basis == MW_BASIS_AUTO; }
+bool basis_fp32(mw_problem* p) {
+  return p->prec == MW_C64 && (p->basis == MW_BASIS_AUTO || p->basis == MW_BASIS_FP32_LEAN);
+}
 
 // device bytes one more right-hand side column costs a GMRES(m) driver:
 // basis (m+1), X, B, Z, update, local vectors, reduction partials
@@ -767,10 +769,11 @@ int64_t gmres_bytes_per_col(mw_problem* p, int m, bool block) {
   const int64_t bsz = (!block && basis_fp32(p)) ? 8 : 16;   // block GMRES keeps an FP64 basis
   int64_t big = (int64_t)(m + 1) * p->T.n() * bsz + 4 * p->T.n() * 16 + p->dd.sum_pad * esz +
                 reduce_chunks(p->T.n()) * (2 * m + 3) * 16;
-  // FP32 basis: the m preconditioned candidates in FP32, and for the
-  // two-level preconditioner an FP64 copy of v_j
+  // FP32 basis: the m preconditioned candidates in FP32 (one, rewritten at
+  // every step, when lean), and for the two-level preconditioner an FP64
+  // copy of v_j
   if (bsz == 8) {
-    big += (int64_t)m * 8 * p->T.n();
+    big += (p->basis == MW_BASIS_FP32_LEAN ? 1 : (int64_t)m) * 8 * p->T.n();
     if (p->coarse_kind != MW_COARSE_NONE) big += p->T.n() * 16;
   }
   if (p->coarse_kind != MW_COARSE_NONE)   // two-level: Q v and the coarse vector
@@ -845,8 +848,13 @@ void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, co
   // FP32, as the SpMM reads it) with the triangular factor Rc relating the
   // candidates to the basis, so that the cycle ends with x += Zc Rc^-1 y
   // instead of one more preconditioner application
-  const bool keep_z = std::is_same<BT, float2>::value;
-  float2* Zc = keep_z ? (float2*)W.zc.get(c, (int64_t)m * vstride * 8) : nullptr;
+  const bool fp32_basis = std::is_same<BT, float2>::value;
+  const bool keep_z = fp32_basis && p->basis != MW_BASIS_FP32_LEAN;
+  // (lean, one level: one FP32 slot for M^-1 v_j, rewritten every step)
+  const bool one_slot = fp32_basis && !keep_z && !p->coarse_active;
+  float2* Zc = keep_z     ? (float2*)W.zc.get(c, (int64_t)m * vstride * 8)
+               : one_slot ? (float2*)W.zc.get(c, vstride * 8)
+                          : nullptr;
   double2* Rc = keep_z ? (double2*)W.rc.get(c, (int64_t)m * m * nc * 16) : nullptr;
   std::vector<double2> g0((size_t)nc);
   int nact = 0;
@@ -872,11 +880,11 @@ void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, co
     bool more = j < m && !finish_only;   // step m only finishes column m-1
     for (int pass = 0; pass < 2; ++pass) {
       if (more) {
-        if (keep_z) {
+        if (keep_z || one_slot) {
           // FP32 basis: M^-1 v_j is rounded to FP32 as well (the product
           // A M^-1 v_j is FP64 either way; the rounding perturbs the Arnoldi
           // relation no more than the basis' own)
-          float2* Zf = Zc + (int64_t)j * vstride;
+          float2* Zf = keep_z ? Zc + (int64_t)j * vstride : Zc;
           MW_CHECK(p->factors_valid, MW_EINVAL, "no valid subdomain factors: call mw_factor_subdomains");
           if (!p->coarse_active) {
             one_level<BT, float2>(p, W, Vj, Zf, nc, ld);
@@ -1525,7 +1533,8 @@ mw_status mw_set_factorization(mw_problem* p, int32_t kind) {
 mw_status mw_set_krylov_basis(mw_problem* p, int32_t kind) {
   return guard([&] {
     check_prob(p);
-    MW_CHECK(kind == MW_BASIS_AUTO || kind == MW_BASIS_FP64, MW_EINVAL, "unknown Krylov basis kind");
+    MW_CHECK(kind == MW_BASIS_AUTO || kind == MW_BASIS_FP64 || kind == MW_BASIS_FP32_LEAN, MW_EINVAL,
+             "unknown Krylov basis kind");
     p->basis = kind;
   });
 }

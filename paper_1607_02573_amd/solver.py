@@ -166,8 +166,11 @@ class Problem:
         check(lib().mw_set_solve_form(self.h, f))
 
     def set_krylov_basis(self, kind: str):
-        """'auto' (complex FP32 with FP32 factors) or 'fp64'; used by later solves."""
-        check(lib().mw_set_krylov_basis(self.h, {"auto": B.MW_BASIS_AUTO, "fp64": B.MW_BASIS_FP64}[kind]))
+        """'auto' (complex FP32 with FP32 factors, the preconditioned candidates
+        kept), 'fp32-lean' (FP32 without them: less memory per column) or
+        'fp64'; used by later solves."""
+        kinds = {"auto": B.MW_BASIS_AUTO, "fp64": B.MW_BASIS_FP64, "fp32-lean": B.MW_BASIS_FP32_LEAN}
+        check(lib().mw_set_krylov_basis(self.h, kinds[kind]))
 
     def factor(self, part, n_sub: int, overlap: int = 1, precision: str = "c128"):
         """Fill and factor the B_i; part = None takes the library's own

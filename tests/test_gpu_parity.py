@@ -286,23 +286,25 @@ def test_preconditioner_column_counts(chamber_small, prec, tol, form):
 
 def test_fp32_krylov_basis_reaches_the_same_solution(chamber_small):
     """Mixed precision keeps the Arnoldi basis in complex FP32 by default; the
-    stopping test stays on the true FP64 residual, so both bases reach the
+    stopping test stays on the true FP64 residual, so every basis kind (FP64,
+    FP32 with the preconditioned candidates kept, FP32 lean) reaches the
     tolerance and the same fields (within what the tolerance allows), with
     at most a few more iterations for the rounded basis."""
     w, fp, P = chamber_small
     P.factor(w.part, w.n_sub, 1, "c64")
     Bg = P.rhs_ports(w.tx)
     out = {}
-    for kind in ("fp64", "auto"):
+    for kind in ("fp64", "auto", "fp32-lean"):
         P.set_krylov_basis(kind)
         try:
             out[kind] = P.solve(Bg, tol=1e-10, restart=30)
         finally:
             P.set_krylov_basis("auto")
-    (X64, i64), (X32, i32) = out["fp64"], out["auto"]
-    assert (i64.relres <= 1e-10).all() and (i32.relres <= 1e-10).all()
+    (X64, i64), (X32, i32), (XL, iL) = out["fp64"], out["auto"], out["fp32-lean"]
+    assert (i64.relres <= 1e-10).all() and (i32.relres <= 1e-10).all() and (iL.relres <= 1e-10).all()
     U = spla.splu(fp.A.tocsc()).solve(fem.rhs_ports(fp, w.ports, w.tx))
-    for X in (X64, X32):
+    for X in (X64, X32, XL):
         err = np.linalg.norm(X.cpu().numpy() - U, axis=0) / np.linalg.norm(U, axis=0)
         assert (err <= 1e-6).all(), err.max()
     assert (i32.iters <= i64.iters + 3).all(), (i32.iters, i64.iters)
+    assert (iL.iters <= i64.iters + 3).all(), (iL.iters, i64.iters)
