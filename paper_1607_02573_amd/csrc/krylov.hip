@@ -22,6 +22,15 @@ template <class B> __device__ inline B bstore(double2 v);
 template <> __device__ inline double2 bstore<double2>(double2 v) { return v; }
 template <> __device__ inline float2 bstore<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
 
+// acc += a x as four fused multiply-adds, in this order: every form of the
+// product A X uses it, so a column's sums are bitwise the same in every form
+__device__ inline void cmac(double2& acc, const double2& a, const double2& x) {
+  acc.x = fma(a.x, x.x, acc.x);
+  acc.x = fma(-a.y, x.y, acc.x);
+  acc.y = fma(a.x, x.y, acc.y);
+  acc.y = fma(a.y, x.x, acc.y);
+}
+
 // ---------------------------------------------------------------- K1 / K12
 // Y = A X  (Bsub == nullptr)  or  Y = Bsub - A X, CSR complex128.
 // TPR threads per row; each lane walks columns lane, lane+TPR, ...
@@ -39,10 +48,7 @@ __global__ void __launch_bounds__(256) k_spmm(int64_t n, const int64_t* __restri
     if (c >= ncols) break;
     double2 acc = make_double2(0.0, 0.0);
     for (int64_t k = b; k < e; ++k) {
-      double2 a = val[k];
-      double2 x = bload(X[(int64_t)col[k] * ldx + c]);
-      acc.x += a.x * x.x - a.y * x.y;
-      acc.y += a.x * x.y + a.y * x.x;
+      cmac(acc, val[k], bload(X[(int64_t)col[k] * ldx + c]));
     }
     if (Bs) {
       double2 bb = Bs[r * ldb + c];
@@ -61,16 +67,6 @@ __device__ inline double bcast(double v, int t) {
   int lo = __builtin_amdgcn_readlane(__double2loint(v), t);
   int hi = __builtin_amdgcn_readlane(__double2hiint(v), t);
   return __hiloint2double(hi, lo);
-}
-
-// acc += a x when ok (the same expression as every other product of A, so a
-// column's sum is bitwise the same in every form); a select, not a branch,
-// so that the loads feeding it are not moved under one
-__device__ inline void cmac_if(double2& acc, const double2& a, const double2& x, bool ok) {
-  const double rx = acc.x + (a.x * x.x - a.y * x.y);
-  const double ry = acc.y + (a.x * x.y + a.y * x.x);
-  acc.x = ok ? rx : acc.x;
-  acc.y = ok ? ry : acc.y;
 }
 
 // nonzeros per gather pass of the wide SpMM forms
@@ -116,9 +112,10 @@ __global__ void __launch_bounds__(256) k_spmm_w(int64_t n, const int64_t* __rest
 #pragma unroll
         for (int u = 0; u < SPMM_U<XT>; ++u) {
           const int s = (t + u) & 63;
+          const bool ok = t + u < cnt;   // else a = 0, which adds exactly nothing to a finite sum
           cc[u] = __builtin_amdgcn_readlane(mycol, s);
-          a[u].x = bcast(myval.x, s);
-          a[u].y = bcast(myval.y, s);
+          a[u].x = ok ? bcast(myval.x, s) : 0.0;
+          a[u].y = ok ? bcast(myval.y, s) : 0.0;
         }
         XT x[SPMM_U<XT>][CPL];
 #pragma unroll
@@ -126,11 +123,9 @@ __global__ void __launch_bounds__(256) k_spmm_w(int64_t n, const int64_t* __rest
 #pragma unroll
           for (int q = 0; q < CPL; ++q) x[u][q] = X[cc[u] * ldx + cq[q]];
 #pragma unroll
-        for (int u = 0; u < SPMM_U<XT>; ++u) {
-          const bool ok = t + u < cnt;
+        for (int u = 0; u < SPMM_U<XT>; ++u)
 #pragma unroll
-          for (int q = 0; q < CPL; ++q) cmac_if(acc[q], a[u], bload(x[u][q]), ok);
-        }
+          for (int q = 0; q < CPL; ++q) cmac(acc[q], a[u], bload(x[u][q]));
       }
     }
 #pragma unroll
@@ -190,9 +185,11 @@ __global__ void __launch_bounds__(256) k_spmm_h(int64_t n, const int64_t* __rest
 #pragma unroll
       for (int u = 0; u < SPMM_U<XT>; ++u) {
         const int s = (t + u) & 31;
+        const bool ok = t + u < cnt;   // else a = 0, which adds exactly nothing to a finite sum
         cc[u] = __shfl(mycol, s, 32);
-        a[u].x = __shfl(myval.x, s, 32);
-        a[u].y = __shfl(myval.y, s, 32);
+        const double ax = __shfl(myval.x, s, 32), ay = __shfl(myval.y, s, 32);
+        a[u].x = ok ? ax : 0.0;
+        a[u].y = ok ? ay : 0.0;
       }
       XT x[SPMM_U<XT>][CPL];
 #pragma unroll
@@ -200,11 +197,9 @@ __global__ void __launch_bounds__(256) k_spmm_h(int64_t n, const int64_t* __rest
 #pragma unroll
         for (int q = 0; q < CPL; ++q) x[u][q] = X[cc[u] * ldx + cq[q]];
 #pragma unroll
-      for (int u = 0; u < SPMM_U<XT>; ++u) {
-        const bool ok = t + u < cnt;
+      for (int u = 0; u < SPMM_U<XT>; ++u)
 #pragma unroll
-        for (int q = 0; q < CPL; ++q) cmac_if(acc[q], a[u], bload(x[u][q]), ok);
-      }
+        for (int q = 0; q < CPL; ++q) cmac(acc[q], a[u], bload(x[u][q]));
     }
   }
   if (!live) return;
@@ -251,9 +246,7 @@ __global__ void __launch_bounds__(256) k_spmm_sell(int64_t nslots, const int32_t
 #pragma unroll
     for (int q = 0; q < NC; ++q)
       if (q < ncols) {
-        const double2 x = bload(xr[q]);
-        acc[q].x += a.x * x.x - a.y * x.y;
-        acc[q].y += a.x * x.y + a.y * x.x;
+        cmac(acc[q], a, bload(xr[q]));
       }
   }
 #pragma unroll
