@@ -113,10 +113,11 @@ struct GmresWork {
   Work V, X, B, Z, Y, H, Hr, cs, sn, g, y, h1, h2, hp, cf, nu, ee, part, npart, vec, ints, tmp, w_idx;
   Work cq, cw, cy;            // two-level: Q v, FP64 copy of an FP32 basis vector, coarse vector
   Work zc, rc;                // FP32 basis: preconditioned candidates and their triangular factor
+  Work csc;                   // FP32 basis: 1 / ||u|| of the unnormalised candidate, per column
   hipStream_t st = nullptr;   // the stream this driver's work runs on
-  std::array<Work*, 28> all() {
+  std::array<Work*, 29> all() {
     return {&V, &X, &B, &Z, &Y, &H, &Hr, &cs, &sn, &g, &y, &h1, &h2, &hp, &cf, &nu, &ee, &part, &npart, &vec, &ints,
-            &tmp, &w_idx, &cq, &cw, &cy, &zc, &rc};
+            &tmp, &w_idx, &cq, &cw, &cy, &zc, &rc, &csc};
   }
   void release() {
     for (Work* w : all()) w->b.release();
@@ -519,18 +520,20 @@ void upload_decomp(mw_problem* p) {
 // Z = M^-1 V (n x nc, leading dimension ld), local workspace W.Y
 // V complex FP64, or complex FP32 (a basis vector of the mixed-precision
 // GMRES, with FP32 factors only)
+// (vsc, optional: column c of V taken times vsc[c], a GMRES candidate stored
+// before its normalisation)
 template <class VT, class ZT = double2>
-void one_level(mw_problem* p, GmresWork& W, const VT* V, ZT* Z, int nc, int64_t ld) {
+void one_level(mw_problem* p, GmresWork& W, const VT* V, ZT* Z, int nc, int64_t ld, const double* vsc = nullptr) {
   mw_ctx* c = p->ctx;
   int64_t n = p->T.n();
   if (p->prec == MW_C64) {
     float2* Y = (float2*)W.Y.get(c, p->dd.sum_pad * nc * 8);
-    launch_restrict<float2, VT>(p->dd, V, ld, nc, Y, nc, W.st);
+    launch_restrict<float2, VT>(p->dd, V, ld, nc, Y, nc, W.st, vsc);
     lu_solve_batched<float2>(p->dd, p->F.as<float2>(), Y, nc, nc, W.st);
     launch_prolong<float2, ZT>(p->dd, n, Y, nc, nc, Z, ld, W.st);
   } else if constexpr (std::is_same<VT, double2>::value && std::is_same<ZT, double2>::value) {
     double2* Y = (double2*)W.Y.get(c, p->dd.sum_pad * nc * 16);
-    launch_restrict<double2>(p->dd, V, ld, nc, Y, nc, W.st);
+    launch_restrict<double2>(p->dd, V, ld, nc, Y, nc, W.st, vsc);
     lu_solve_batched<double2>(p->dd, p->F.as<double2>(), Y, nc, nc, W.st);
     launch_prolong<double2>(p->dd, n, Y, nc, nc, Z, ld, W.st);
   } else {
@@ -781,7 +784,7 @@ int64_t gmres_bytes_per_col(mw_problem* p, int m, bool block) {
   // Hessenberg (raw and rotated), rotations, g, y, dot sums, provisional
   // column, coefficients, norms, flags
   int64_t small = 2 * (int64_t)(m + 1) * m * 16 + (int64_t)m * 24 + 5 * (int64_t)(m + 1) * 16 + 2 * (int64_t)m * 16 +
-                  6 * 8 + 2 * 4 + (int64_t)m * m * 16;
+                  7 * 8 + 2 * 4 + (int64_t)m * m * 16;
   return big + small + 256;
 }
 
@@ -852,6 +855,13 @@ void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, co
   const bool keep_z = fp32_basis && p->basis != MW_BASIS_FP32_LEAN;
   // (lean, one level: one FP32 slot for M^-1 v_j, rewritten every step)
   const bool one_slot = fp32_basis && !keep_z && !p->coarse_active;
+  // FP32 basis, one level: the next candidate stays unnormalised in its
+  // slot; the three kernels that read it before the next update replaces
+  // it (restriction, dot products, update) take it times 1 / ||u||, from
+  // the update's partial sums (hn2), instead of a pass that rewrites it
+  const bool defer_norm = fp32_basis && !p->coarse_active;
+  double* csc_buf = defer_norm ? (double*)W.csc.get(c, (int64_t)nc * 8) : nullptr;
+  const double* cn2 = nullptr;   // csc_buf from step 1 on, while the candidate is unnormalised
   float2* Zc = keep_z     ? (float2*)W.zc.get(c, (int64_t)m * vstride * 8)
                : one_slot ? (float2*)W.zc.get(c, vstride * 8)
                           : nullptr;
@@ -887,7 +897,7 @@ void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, co
           float2* Zf = keep_z ? Zc + (int64_t)j * vstride : Zc;
           MW_CHECK(p->factors_valid, MW_EINVAL, "no valid subdomain factors: call mw_factor_subdomains");
           if (!p->coarse_active) {
-            one_level<BT, float2>(p, W, Vj, Zf, nc, ld);
+            one_level<BT, float2>(p, W, Vj, Zf, nc, ld, cn2);
           } else {
             apply_prec(p, W, Vj, Z, nc, ld);
             launch_narrow(Z, Zf, vstride, st);
@@ -898,7 +908,7 @@ void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, co
           launch_spmm(p->dm, p->val.as<double2>(), (const double2*)Z, ld, T, ld, nc, nullptr, 0, st);
         }
       }
-      launch_dots_partial(V, vstride, j + 1, Vj, more ? T : nullptr, n, ld, nc, act, part1, part2, st);
+      launch_dots_partial(V, vstride, j + 1, Vj, more ? T : nullptr, n, ld, nc, act, part1, part2, st, cn2);
       launch_sum_chunks_c(part1, nch, (int64_t)(j + 1) * nc, P1, st);
       if (more) launch_sum_chunks_c(part2, nch, (int64_t)(j + 1) * nc, P2, st);
       launch_dgs_step(j, m, pass == 0, nc, P1, more ? P2 : nullptr, hn2, Hraw, H, cs, sn, g, hprov, coef, nu, ee,
@@ -921,9 +931,14 @@ void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, co
       more = true;   // a column continues although its trial estimate said done
     }
     if (nact == 0 || j == m) break;
-    launch_dgs_update(V, vstride, j, coef, nu, ee, T, n, ld, nc, act, npart, st);
+    launch_dgs_update(V, vstride, j, coef, nu, ee, T, n, ld, nc, act, npart, st, cn2);
     launch_sum_chunks(npart, nch, nc, hn2, st);
-    launch_scale_cols(V + (int64_t)(j + 1) * vstride, n, ld, nc, hn2, act, st);
+    if (defer_norm) {
+      launch_inv_norms(nc, hn2, csc_buf, st);
+      cn2 = csc_buf;
+    } else {
+      launch_scale_cols(V + (int64_t)(j + 1) * vstride, n, ld, nc, hn2, act, st);
+    }
     finish_only = false;
     if (j + 1 < m) {
       launch_dgs_trial(j, m, nc, hprov, hn2, cs, sn, g, act, bnorm, o.tol, done, st);

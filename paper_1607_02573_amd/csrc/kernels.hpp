@@ -189,9 +189,12 @@ void launch_sell_values(int64_t total, const int32_t* sl_idx, const double2* val
 template <class XT>
 void launch_spmm(const DeviceMesh& m, const double2* val, const XT* X, int64_t ldx, double2* Y,
                  int64_t ldy, int ncols, const double2* Bsub, int64_t ldb, hipStream_t st);
+// vsc (optional, device, ncols): column c of V is taken times vsc[c]
 template <class C, class VT = double2>
 void launch_restrict(const DeviceDecomp& d, const VT* V, int64_t ldv, int ncols, C* Y, int64_t ldy,
-                     hipStream_t st);
+                     hipStream_t st, const double* vsc = nullptr);
+// vsc[c] = 1 / sqrt(n2[c]) where n2[c] > 0, else 1 (device, ncols each)
+void launch_inv_norms(int ncols, const double* n2, double* vsc, hipStream_t st);
 // Z complex FP64, or complex FP32 (summed in FP64, then rounded)
 template <class C, class ZT = double2>
 void launch_prolong(const DeviceDecomp& d, int64_t n, const C* Y, int64_t ldy, int ncols, ZT* Z,
@@ -200,10 +203,12 @@ void launch_prolong(const DeviceDecomp& d, int64_t n, const C* Y, int64_t ldy, i
 int64_t reduce_chunks(int64_t n);
 void launch_colnorm2_partial(const double2* V, int64_t n, int64_t ld, int ncols, double* part, hipStream_t st);
 void launch_sum_chunks(const double* part, int64_t nchunk, int64_t width, double* out, hipStream_t st);
+// w1sc (optional, device, ncols): w1 = V_{kcount-1} is a candidate stored
+// before its normalisation; both are taken times w1sc[c]
 template <class B>
 void launch_dots_partial(const B* V, int64_t vstride, int kcount, const B* w1, const double2* w2,
                          int64_t n, int64_t ld, int ncols, const int32_t* act, double2* part1, double2* part2,
-                         hipStream_t st);
+                         hipStream_t st, const double* w1sc = nullptr);
 void launch_sum_chunks_c(const double2* part, int64_t nchunk, int64_t width, double2* out, hipStream_t st);
 void launch_dgs_step(int j, int m, bool fin, int ncols, const double2* P1, const double2* P2, const double* beta2,
                      double2* Hraw, double2* H, double* cs, double2* sn, double2* g, double2* hprov, double2* coef,
@@ -212,10 +217,12 @@ void launch_dgs_step(int j, int m, bool fin, int ncols, const double2* P1, const
 void launch_dgs_trial(int j, int m, int ncols, const double2* hprov, const double* beta2, const double* cs,
                       const double2* sn, const double2* g, const int32_t* act, const double* bnorm, double tol,
                       int32_t* done, hipStream_t st);
+// vjsc (optional, device, ncols): V_j is a candidate stored before its
+// normalisation, taken times vjsc[c]
 template <class B>
 void launch_dgs_update(B* V, int64_t vstride, int j, const double2* coef, const double* nu, const double2* e,
                        const double2* T, int64_t n, int64_t ld, int ncols, const int32_t* act, double* norm_part,
-                       hipStream_t st);
+                       hipStream_t st, const double* vjsc = nullptr);
 template <class B>
 void launch_scale_cols(B* w, int64_t n, int64_t ld, int ncols, const double* nrm, const int32_t* act,
                        hipStream_t st);

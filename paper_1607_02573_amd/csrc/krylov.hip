@@ -332,9 +332,25 @@ template void launch_spmm<float2>(const DeviceMesh&, const double2*, const float
 
 // ---------------------------------------------------------------- K4 / K5
 // restriction: Y[l][c] = V[ridx[l]][c] (cast), zero on padding rows
+// Column c of V is taken times vsc[c] when vsc is given (a GMRES candidate
+// stored before its normalisation; vsc from k_inv_norms).
+__device__ inline double col_scale(const double* __restrict__ vsc, int c) { return vsc ? vsc[c] : 1.0; }
+
+// vsc[c] = 1 / sqrt(n2[c]) where n2[c] > 0, else 1
+__global__ void k_inv_norms(int ncols, const double* __restrict__ n2, double* __restrict__ vsc) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  const double s2 = n2[c];
+  vsc[c] = s2 > 0.0 ? 1.0 / sqrt(s2) : 1.0;
+}
+void launch_inv_norms(int ncols, const double* n2, double* vsc, hipStream_t st) {
+  k_inv_norms<<<(unsigned)ceil_div(ncols, 64), 64, 0, st>>>(ncols, n2, vsc);
+  MW_LAUNCH_CHECK();
+}
+
 template <class C, class VT>
 __global__ void k_restrict(int64_t nloc, const int32_t* __restrict__ ridx, const VT* __restrict__ V,
-                           int64_t ldv, int ncols, C* __restrict__ Y, int64_t ldy) {
+                           int64_t ldv, int ncols, C* __restrict__ Y, int64_t ldy, const double* __restrict__ vsc) {
   int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t l = id / ncols;
   int c = (int)(id % ncols);
@@ -344,7 +360,12 @@ __global__ void k_restrict(int64_t nloc, const int32_t* __restrict__ ridx, const
   y.x = 0; y.y = 0;
   if (g >= 0) {
     VT v = V[(int64_t)g * ldv + c];
-    y.x = v.x; y.y = v.y;
+    if (vsc) {
+      const double sc = col_scale(vsc, c);
+      y.x = (double)v.x * sc; y.y = (double)v.y * sc;
+    } else {
+      y.x = v.x; y.y = v.y;
+    }
   }
   Y[l * ldy + c] = y;
 }
@@ -352,7 +373,7 @@ __global__ void k_restrict(int64_t nloc, const int32_t* __restrict__ ridx, const
 // the same for an even number of columns, two adjacent columns per thread
 template <class C, class VT>
 __global__ void k_restrict2(int64_t nloc, const int32_t* __restrict__ ridx, const VT* __restrict__ V,
-                            int64_t ldv, int npairs, C* __restrict__ Y, int64_t ldy) {
+                            int64_t ldv, int npairs, C* __restrict__ Y, int64_t ldy, const double* __restrict__ vsc) {
   int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t l = id / npairs;
   int c = 2 * (int)(id % npairs);
@@ -362,8 +383,14 @@ __global__ void k_restrict2(int64_t nloc, const int32_t* __restrict__ ridx, cons
   y0.x = 0; y0.y = 0; y1.x = 0; y1.y = 0;
   if (g >= 0) {
     VT v0 = V[(int64_t)g * ldv + c], v1 = V[(int64_t)g * ldv + c + 1];
-    y0.x = v0.x; y0.y = v0.y;
-    y1.x = v1.x; y1.y = v1.y;
+    if (vsc) {
+      const double s0 = col_scale(vsc, c), s1 = col_scale(vsc, c + 1);
+      y0.x = (double)v0.x * s0; y0.y = (double)v0.y * s0;
+      y1.x = (double)v1.x * s1; y1.y = (double)v1.y * s1;
+    } else {
+      y0.x = v0.x; y0.y = v0.y;
+      y1.x = v1.x; y1.y = v1.y;
+    }
   }
   Y[l * ldy + c] = y0;
   Y[l * ldy + c + 1] = y1;
@@ -371,15 +398,16 @@ __global__ void k_restrict2(int64_t nloc, const int32_t* __restrict__ ridx, cons
 
 template <class C, class VT>
 void launch_restrict(const DeviceDecomp& d, const VT* V, int64_t ldv, int ncols, C* Y, int64_t ldy,
-                     hipStream_t st) {
+                     hipStream_t st, const double* vsc) {
   if (d.sum_pad <= 0 || ncols <= 0) return;
   kt_begin(KF_RESTRICT, st);
   if (ncols % 2 == 0) {
     int64_t tot = d.sum_pad * (ncols / 2);
-    k_restrict2<C, VT><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(d.sum_pad, d.ridx, V, ldv, ncols / 2, Y, ldy);
+    k_restrict2<C, VT><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(d.sum_pad, d.ridx, V, ldv, ncols / 2, Y, ldy,
+                                                                     vsc);
   } else {
     int64_t tot = d.sum_pad * ncols;
-    k_restrict<C, VT><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(d.sum_pad, d.ridx, V, ldv, ncols, Y, ldy);
+    k_restrict<C, VT><<<(unsigned)ceil_div(tot, 256), 256, 0, st>>>(d.sum_pad, d.ridx, V, ldv, ncols, Y, ldy, vsc);
   }
   MW_LAUNCH_CHECK();
   if (kt_enabled()) {
@@ -461,11 +489,11 @@ void launch_prolong(const DeviceDecomp& d, int64_t n, const C* Y, int64_t ldy, i
 }
 
 template void launch_restrict<float2, double2>(const DeviceDecomp&, const double2*, int64_t, int, float2*, int64_t,
-                                               hipStream_t);
+                                               hipStream_t, const double*);
 template void launch_restrict<float2, float2>(const DeviceDecomp&, const float2*, int64_t, int, float2*, int64_t,
-                                              hipStream_t);
+                                              hipStream_t, const double*);
 template void launch_restrict<double2, double2>(const DeviceDecomp&, const double2*, int64_t, int, double2*,
-                                                int64_t, hipStream_t);
+                                                int64_t, hipStream_t, const double*);
 template void launch_prolong<float2, double2>(const DeviceDecomp&, int64_t, const float2*, int64_t, int, double2*,
                                               int64_t, hipStream_t);
 template void launch_prolong<float2, float2>(const DeviceDecomp&, int64_t, const float2*, int64_t, int, float2*,
@@ -538,7 +566,7 @@ __global__ void __launch_bounds__(256) k_dots_partial(const B* __restrict__ V, i
                                                       const B* __restrict__ w1, const double2* __restrict__ w2,
                                                       int64_t n, int64_t ld, int ncols,
                                                       const int32_t* __restrict__ act, double2* __restrict__ part1,
-                                                      double2* __restrict__ part2) {
+                                                      double2* __restrict__ part2, const double* __restrict__ w1sc) {
   __shared__ double2 red[4][64];
   const int kb = blockIdx.x * DOTS_KG;
   const int chunk = blockIdx.y;
@@ -550,6 +578,7 @@ __global__ void __launch_bounds__(256) k_dots_partial(const B* __restrict__ V, i
   for (int q = 0; q < DOTS_KG; ++q) acc1[q] = acc2[q] = make_double2(0.0, 0.0);
   if (c < ncols && act[c]) {
     const B* Vb = V + (int64_t)kb * vstride;
+
     // RPD rows per pass (r, r + 4, ...): four with an FP32 basis (its loads
     // carry half the bytes; the raw values stay in registers until used),
     // two otherwise; each (k, column) sum still runs over the chunk's rows
@@ -584,6 +613,19 @@ __global__ void __launch_bounds__(256) k_dots_partial(const B* __restrict__ V, i
       }
     }
   }
+  if (w1sc && c < ncols) {
+    // w1 = V_{kcount-1} stored unnormalised: every sum with w1 taken times
+    // its factor, and the sums of V_{kcount-1} itself once more
+    const double sc = w1sc[c];
+#pragma unroll
+    for (int q = 0; q < DOTS_KG; ++q) {
+      const double s1 = kb + q == kcount - 1 ? sc * sc : sc, s2 = kb + q == kcount - 1 ? sc : 1.0;
+      acc1[q].x *= s1;
+      acc1[q].y *= s1;
+      acc2[q].x *= s2;
+      acc2[q].y *= s2;
+    }
+  }
 #pragma unroll
   for (int q = 0; q < DOTS_KG; ++q) {
     if (kb + q < kcount) {
@@ -608,23 +650,25 @@ __global__ void __launch_bounds__(256) k_dots_partial(const B* __restrict__ V, i
 template <class B>
 void launch_dots_partial(const B* V, int64_t vstride, int kcount, const B* w1, const double2* w2,
                          int64_t n, int64_t ld, int ncols, const int32_t* act, double2* part1, double2* part2,
-                         hipStream_t st) {
+                         hipStream_t st, const double* w1sc) {
   kt_begin(KF_CGS_DOTS, st);
   // basis vectors per workgroup: 8 for an FP32 basis (the right vectors
   // re-read less often: 279 against 285 ms per 1 GHz step), 6 otherwise
   constexpr int KG = sizeof(B) == 8 ? 8 : DOTS_KG;
   dim3 g((unsigned)ceil_div(kcount, KG), (unsigned)reduce_chunks(n), (unsigned)ceil_div(ncols, 64));
   k_dots_partial<B, KG><<<g, 256, 0, st>>>(V, vstride, kcount, w1, w2, n, ld, ncols, act, part1,
-                                           w2 ? part2 : nullptr);
+                                           w2 ? part2 : nullptr, w1sc);
   MW_LAUNCH_CHECK();
   if (kt_enabled())
     kt_end(KF_CGS_DOTS, st, (w2 ? 16.0 : 8.0) * kcount * n * ncols,
            ((kcount + 1.0) * sizeof(B) + (w2 ? 16.0 : 0.0)) * n * ncols);
 }
 template void launch_dots_partial<double2>(const double2*, int64_t, int, const double2*, const double2*, int64_t,
-                                           int64_t, int, const int32_t*, double2*, double2*, hipStream_t);
+                                           int64_t, int, const int32_t*, double2*, double2*, hipStream_t,
+                                           const double*);
 template void launch_dots_partial<float2>(const float2*, int64_t, int, const float2*, const double2*, int64_t,
-                                          int64_t, int, const int32_t*, double2*, double2*, hipStream_t);
+                                          int64_t, int, const int32_t*, double2*, double2*, hipStream_t,
+                                          const double*);
 
 // ---------------------------------------------------------------- K6/K7 with delayed reorthogonalisation
 // Arnoldi step j of every active column, scalar part (one thread per column).
@@ -786,7 +830,7 @@ __global__ void __launch_bounds__(256) k_dgs_update(B* __restrict__ V, int64_t v
                                                     const double2* __restrict__ coef, const double* __restrict__ nu,
                                                     const double2* __restrict__ e, const double2* __restrict__ T,
                                                     int64_t n, int64_t ld, int ncols, const int32_t* __restrict__ act,
-                                                    double* __restrict__ norm_part) {
+                                                    double* __restrict__ norm_part, const double* __restrict__ vjsc) {
   __shared__ double red[4][64];
   extern __shared__ double2 cf[];   // [2j][64] when 2j <= CGS_HK
   const int chunk = blockIdx.x;
@@ -801,6 +845,7 @@ __global__ void __launch_bounds__(256) k_dgs_update(B* __restrict__ V, int64_t v
   if (c < ncols && act[c]) {
     const double inu = nu[c];
     const double2 ec = e[c];
+    const double sc = col_scale(vjsc, c);   // v_j stored unnormalised when vjsc is given
     B* Vj = V + (int64_t)j * vstride;
     B* Vn = V + (int64_t)(j + 1) * vstride;
     // RP rows per pass (r, r + 4, ...), sharing each coefficient load; the
@@ -835,7 +880,11 @@ __global__ void __launch_bounds__(256) k_dgs_update(B* __restrict__ V, int64_t v
       }
       double2 y[RP];
 #pragma unroll
-      for (int q = 0; q < RP; ++q) y[q] = bload(yr[q]);
+      for (int q = 0; q < RP; ++q) {
+        y[q] = bload(yr[q]);
+        y[q].x *= sc;
+        y[q].y *= sc;
+      }
       auto apply = [&](int k, B(&cur)[RP]) {
         // (LDS or global by template: a select between the two would make
         // a flat load, which waits for every load in flight)
@@ -890,25 +939,27 @@ __global__ void __launch_bounds__(256) k_dgs_update(B* __restrict__ V, int64_t v
 template <class B>
 void launch_dgs_update(B* V, int64_t vstride, int j, const double2* coef, const double* nu, const double2* e,
                        const double2* T, int64_t n, int64_t ld, int ncols, const int32_t* act, double* norm_part,
-                       hipStream_t st) {
+                       hipStream_t st, const double* vjsc) {
   dim3 g((unsigned)reduce_chunks(n), (unsigned)ceil_div(ncols, 64));
   size_t lds = 2 * j <= CGS_HK ? (size_t)(2 * j) * 64 * sizeof(double2) : 0;
   kt_begin(KF_CGS_UPDATE, st);
   // rows per pass: 8 for an FP32 basis (323 against 330 ms per 1 GHz step), 4 otherwise
   if (2 * j <= CGS_HK)
     k_dgs_update<B, sizeof(B) == 8 ? 8 : 4, true><<<g, 256, lds, st>>>(V, vstride, j, coef, nu, e, T, n, ld, ncols,
-                                                                     act, norm_part);
+                                                                     act, norm_part, vjsc);
   else
     k_dgs_update<B, sizeof(B) == 8 ? 8 : 4, false><<<g, 256, 0, st>>>(V, vstride, j, coef, nu, e, T, n, ld, ncols,
-                                                                    act, norm_part);
+                                                                    act, norm_part, vjsc);
   MW_LAUNCH_CHECK();
   // reads V_0..V_j and T, writes v_j and the next candidate
   if (kt_enabled()) kt_end(KF_CGS_UPDATE, st, 16.0 * j * n * ncols, ((j + 3.0) * sizeof(B) + 16.0) * n * ncols);
 }
 template void launch_dgs_update<double2>(double2*, int64_t, int, const double2*, const double*, const double2*,
-                                         const double2*, int64_t, int64_t, int, const int32_t*, double*, hipStream_t);
+                                         const double2*, int64_t, int64_t, int, const int32_t*, double*, hipStream_t,
+                                         const double*);
 template void launch_dgs_update<float2>(float2*, int64_t, int, const double2*, const double*, const double2*,
-                                        const double2*, int64_t, int64_t, int, const int32_t*, double*, hipStream_t);
+                                        const double2*, int64_t, int64_t, int, const int32_t*, double*, hipStream_t,
+                                        const double*);
 
 // w[:, c] /= sqrt(nrm2[c]) for active columns with a nonzero norm
 template <class B>
