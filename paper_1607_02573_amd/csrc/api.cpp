@@ -861,7 +861,7 @@ void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, co
   // the update's partial sums (hn2), instead of a pass that rewrites it
   const bool defer_norm = fp32_basis && !p->coarse_active;
   double* csc_buf = defer_norm ? (double*)W.csc.get(c, (int64_t)nc * 8) : nullptr;
-  const double* cn2 = nullptr;   // csc_buf from step 1 on, while the candidate is unnormalised
+  const double* vj_scale = nullptr;   // 1 / ||u|| per column (csc_buf) from step 1 on: slot j unnormalised
   float2* Zc = keep_z     ? (float2*)W.zc.get(c, (int64_t)m * vstride * 8)
                : one_slot ? (float2*)W.zc.get(c, vstride * 8)
                           : nullptr;
@@ -897,7 +897,7 @@ void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, co
           float2* Zf = keep_z ? Zc + (int64_t)j * vstride : Zc;
           MW_CHECK(p->factors_valid, MW_EINVAL, "no valid subdomain factors: call mw_factor_subdomains");
           if (!p->coarse_active) {
-            one_level<BT, float2>(p, W, Vj, Zf, nc, ld, cn2);
+            one_level<BT, float2>(p, W, Vj, Zf, nc, ld, vj_scale);
           } else {
             apply_prec(p, W, Vj, Z, nc, ld);
             launch_narrow(Z, Zf, vstride, st);
@@ -908,7 +908,7 @@ void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, co
           launch_spmm(p->dm, p->val.as<double2>(), (const double2*)Z, ld, T, ld, nc, nullptr, 0, st);
         }
       }
-      launch_dots_partial(V, vstride, j + 1, Vj, more ? T : nullptr, n, ld, nc, act, part1, part2, st, cn2);
+      launch_dots_partial(V, vstride, j + 1, Vj, more ? T : nullptr, n, ld, nc, act, part1, part2, st, vj_scale);
       launch_sum_chunks_c(part1, nch, (int64_t)(j + 1) * nc, P1, st);
       if (more) launch_sum_chunks_c(part2, nch, (int64_t)(j + 1) * nc, P2, st);
       launch_dgs_step(j, m, pass == 0, nc, P1, more ? P2 : nullptr, hn2, Hraw, H, cs, sn, g, hprov, coef, nu, ee,
@@ -931,11 +931,11 @@ void gmres_cycle(mw_problem* p, GmresWork& W, double2* X, double2* Z, int nc, co
       more = true;   // a column continues although its trial estimate said done
     }
     if (nact == 0 || j == m) break;
-    launch_dgs_update(V, vstride, j, coef, nu, ee, T, n, ld, nc, act, npart, st, cn2);
+    launch_dgs_update(V, vstride, j, coef, nu, ee, T, n, ld, nc, act, npart, st, vj_scale);
     launch_sum_chunks(npart, nch, nc, hn2, st);
     if (defer_norm) {
       launch_inv_norms(nc, hn2, csc_buf, st);
-      cn2 = csc_buf;
+      vj_scale = csc_buf;
     } else {
       launch_scale_cols(V + (int64_t)(j + 1) * vstride, n, ld, nc, hn2, act, st);
     }
