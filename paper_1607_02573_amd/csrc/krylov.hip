@@ -331,12 +331,9 @@ template void launch_spmm<float2>(const DeviceMesh&, const double2*, const float
                                   const double2*, int64_t, hipStream_t);
 
 // ---------------------------------------------------------------- K4 / K5
-// restriction: Y[l][c] = V[ridx[l]][c] (cast), zero on padding rows
-// Column c of V is taken times vsc[c] when vsc is given (a GMRES candidate
-// stored before its normalisation; vsc from k_inv_norms).
-__device__ inline double col_scale(const double* __restrict__ vsc, int c) { return vsc ? vsc[c] : 1.0; }
-
-// vsc[c] = 1 / sqrt(n2[c]) where n2[c] > 0, else 1
+// Per-column factors of a GMRES candidate stored before its normalisation:
+// vsc[c] = 1 / sqrt(n2[c]) where n2[c] > 0, else 1 (the candidate's readers
+// take column c times vsc[c])
 __global__ void k_inv_norms(int ncols, const double* __restrict__ n2, double* __restrict__ vsc) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncols) return;
@@ -347,7 +344,10 @@ void launch_inv_norms(int ncols, const double* n2, double* vsc, hipStream_t st) 
   k_inv_norms<<<(unsigned)ceil_div(ncols, 64), 64, 0, st>>>(ncols, n2, vsc);
   MW_LAUNCH_CHECK();
 }
+__device__ inline double col_scale(const double* __restrict__ vsc, int c) { return vsc ? vsc[c] : 1.0; }
 
+// restriction: Y[l][c] = V[ridx[l]][c] (cast; times vsc[c] when vsc is
+// given), zero on padding rows
 template <class C, class VT>
 __global__ void k_restrict(int64_t nloc, const int32_t* __restrict__ ridx, const VT* __restrict__ V,
                            int64_t ldv, int ncols, C* __restrict__ Y, int64_t ldy, const double* __restrict__ vsc) {
@@ -578,7 +578,6 @@ __global__ void __launch_bounds__(256) k_dots_partial(const B* __restrict__ V, i
   for (int q = 0; q < DOTS_KG; ++q) acc1[q] = acc2[q] = make_double2(0.0, 0.0);
   if (c < ncols && act[c]) {
     const B* Vb = V + (int64_t)kb * vstride;
-
     // RPD rows per pass (r, r + 4, ...): four with an FP32 basis (its loads
     // carry half the bytes; the raw values stay in registers until used),
     // two otherwise; each (k, column) sum still runs over the chunk's rows
